@@ -1,0 +1,217 @@
+/*
+ * pj.h -- C ABI of the MI355X progressive polyhedral spatial join.
+ *
+ * Problem (3DPipe, arXiv 2604.19982, Section 3 opening and Section 2.1):
+ * objects are closed triangle meshes ("facets" are triangles); the distance
+ * of two objects is the minimum Euclidean distance between points of their
+ * surfaces.  For object sets R and S the library answers
+ *   - intersection:  all (r, s) whose surfaces meet (distance 0),
+ *   - within-tau:    all (r, s) with distance <= tau,
+ *   - k-NN:          for each r, the k objects of S closest to r.
+ * Each object carries a coarse-to-fine sequence of levels of detail (LoDs),
+ * the finest being the original mesh (Section 2.1, "Level of Detail").  The
+ * join filters candidate pairs by bounding boxes, then refines them LoD by
+ * LoD with the facet-level bounds of Eq. (1) and Eq. (2) until every pair
+ * is decided (Section 3.1, "Facet-Level Refinement").
+ *
+ * Conventions for every call:
+ *   - every function returns pj_status; nothing throws across the ABI;
+ *   - object ids are 0-based indices into R and S;
+ *   - all pointers passed in are HOST pointers unless stated otherwise; the
+ *     library copies what it keeps, so callers may free inputs on return;
+ *   - results are allocated by the library and released with pj_*_free;
+ *   - a context belongs to one host thread; mesh sets are immutable and may
+ *     be used by any context on the same device;
+ *   - on failure, pj_last_error(ctx) describes the cause.
+ */
+#ifndef PJ_H
+#define PJ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PJ_OK = 0,
+    PJ_ERR_INVALID_ARG = 1,   /* bad pointer, size, index, NaN/Inf coordinate, tau < 0, k < 1, ... */
+    PJ_ERR_OUT_OF_MEMORY = 2, /* device allocation failed or the memory cap cannot hold one tile */
+    PJ_ERR_DEVICE = 3,        /* a HIP runtime call failed (text in pj_last_error) */
+    PJ_ERR_UNSUPPORTED = 4,   /* valid request outside what this build implements */
+    PJ_ERR_INTERNAL = 5
+} pj_status;
+
+/* Arithmetic of the refinement. */
+typedef enum {
+    PJ_PREC_FP32_BAND = 0, /* FP32 bulk; pairs within the guard band of the decision are redone in FP64 */
+    PJ_PREC_FP64 = 1       /* FP64 for every facet pair */
+} pj_precision;
+
+/* How refinement work is scheduled. */
+typedef enum {
+    PJ_SCHED_BATCHED = 0, /* persistent load-balanced tile queue over all pairs of a LoD round */
+    PJ_SCHED_PLAIN = 1    /* one workgroup per (pair, LoD), one launch per LoD (the paper's Algorithm 4) */
+} pj_schedule;
+
+typedef struct {
+    int32_t device;          /* HIP device ordinal */
+    int32_t precision;       /* pj_precision */
+    int32_t schedule;        /* pj_schedule */
+    int32_t learned_skip;    /* 1: pick each pair's first LoD with the loaded LoD model (needs model_path) */
+    int32_t want_dist;       /* within/intersect: also return FP64 distances of result pairs */
+    int32_t use_graph;       /* 1: replay each LoD round's launches from a captured hipGraph */
+    int32_t tile_cull;       /* 1: skip facet tiles whose box gap proves they cannot matter */
+    int32_t tile_s;          /* streamed-side facets per tile (0: autotuned) */
+    int32_t waves_per_cu;    /* persistent grid size in waves per CU (0: autotuned) */
+    int32_t host_threads;    /* host threads for ingest (0: hardware concurrency) */
+    int64_t mem_cap_bytes;   /* device-memory budget for join work buffers (0: no cap) */
+    const char *model_path;  /* LoD model weights written by pj_train_lod_model (NULL: none) */
+    const char *log_path;    /* append per-pair resolution records here (NULL: no log) */
+    const char *autotune_path; /* autotuner cache file (NULL: none) */
+    void *stream;            /* hipStream_t to run on (NULL: the library creates one) */
+} pj_config;
+
+/* Fill *cfg with defaults: device 0, FP32 band, batched, tile culling on,
+ * graphs on, no learned skip, no cap, autotuned shapes. */
+void pj_config_default(pj_config *cfg);
+
+typedef struct pj_context pj_context;
+typedef struct pj_meshes pj_meshes;
+
+/* A set of objects (Section 2.1: polyhedra of triangle facets, each with a
+ * sequence of LoDs).  Object-major layout; caller-owned, copied on create. */
+typedef struct {
+    int32_t n_objects;          /* >= 0 */
+    int32_t n_lods;             /* L >= 1, the same for every object; LoD 0 coarsest, L-1 original */
+    int64_t n_verts;            /* rows of verts */
+    int64_t n_tris;             /* rows of tris */
+    const float *verts;         /* [n_verts][3] float32 xyz, all objects concatenated */
+    const int64_t *vert_begin;  /* [n_objects] first vertex row of each object */
+    const int32_t *vert_count;  /* [n_objects] */
+    const int32_t *tris;        /* [n_tris][3] vertex indices local to the object's vertex range */
+    const int64_t *tri_begin;   /* [n_objects * n_lods] first row of (object, LoD); ranges may alias */
+    const int32_t *tri_count;   /* [n_objects * n_lods] */
+    const int32_t *parent;      /* [n_tris] for rows of LoD l > 0: index of the parent triangle within the
+                                   same object's LoD l-1 list; ignored for LoD 0.  Required when n_lods > 1
+                                   and hd/ph are not given */
+    const float *hd;            /* optional [n_tris-aligned, per (object, LoD) range via hdph_begin]; NULL:
+                                   the library computes hd and ph from the parent maps */
+    const float *ph;
+    const int64_t *hdph_begin;  /* [n_objects * n_lods] start of each (object, LoD) in hd/ph, when given */
+} pj_mesh_desc;
+
+/* Create/destroy a context bound to cfg->device.  cfg NULL = defaults. */
+pj_status pj_context_create(const pj_config *cfg, pj_context **out);
+pj_status pj_context_destroy(pj_context *ctx);
+
+/* Validate and ingest one object set: copies it to the device and computes
+ * per-object MBBs and vertex anchors (Section 2.1, "Object and Voxel
+ * Centers"; anchors are always surface vertices) and per-facet hd/ph bounds
+ * (Section 2.1, "Facet-Level Hausdorff Bounds") rounded up to float32.
+ * Errors: INVALID_ARG for NaN/Inf coordinates, negative counts, indices out
+ * of range, parent indices outside the coarser LoD; OUT_OF_MEMORY; DEVICE. */
+pj_status pj_meshes_create(pj_context *ctx, const pj_mesh_desc *desc, pj_meshes **out);
+pj_status pj_meshes_destroy(pj_meshes *m);
+
+/* Result pairs, sorted by (r, s).  dist is NULL unless cfg.want_dist. */
+typedef struct {
+    int64_t n;
+    int32_t *r;
+    int32_t *s;
+    double *dist;
+} pj_pairs;
+
+/* k-NN result: row-major n_r x k; row r holds count[r] = min(k, |S|) ids of
+ * S ordered by (distance, id) and their FP64 distances. */
+typedef struct {
+    int32_t n_r, k;
+    int32_t *count;
+    int32_t *s;
+    double *dist;
+} pj_knn;
+
+/* within-tau join (Section 3, query (2)); tau >= 0 and finite.
+ * Meshes must have the same n_lods.  Empty R or S gives n = 0. */
+pj_status pj_join_within(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, double tau, pj_pairs *out);
+/* intersection join (Section 3, query (1)) == within(0): surfaces meet. */
+pj_status pj_join_intersect(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, pj_pairs *out);
+/* k-NN join (Section 3, query (3); pruning by Algorithm 6, corrected):
+ * k >= 1; k > |S| returns |S| entries per row. */
+pj_status pj_join_knn(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, int32_t k, pj_knn *out);
+
+void pj_pairs_free(pj_pairs *p);
+void pj_knn_free(pj_knn *p);
+
+/* Counters and timings of the last join on this context. */
+typedef struct {
+    double t_total_ms;          /* host wall time of the join call */
+    double t_filter_ms;         /* MBB filter (+ k-NN candidate generation) */
+    double t_refine_ms;         /* all LoD rounds incl. classification */
+    double t_band_ms;           /* FP64 guard-band recheck and distance finalisation */
+    double t_ingest_ms;         /* last pj_meshes_create on this context */
+    double refine_kernel_ms;    /* summed device time of the bulk refinement launches (HIP events) */
+    double band_kernel_ms;      /* summed device time of the FP64 pair kernel launches */
+    int64_t refine_launches;
+    int64_t candidates;         /* pairs passing the MBB filter */
+    int64_t confirmed_filter;   /* decided by the anchor upper bound alone */
+    int64_t facet_pairs;        /* facet pairs evaluated by the bulk refinement kernel */
+    int64_t facet_pairs_fp64;   /* facet pairs evaluated in FP64 (plain kernel, band, distances) */
+    int64_t tiles;              /* tiles issued to the bulk kernel */
+    int64_t tiles_culled;       /* streamed chunks skipped by the box-gap test */
+    int64_t band_pairs;         /* object pairs that needed the FP64 recheck */
+    int64_t resolved_at_lod[8]; /* pairs decided in each LoD round */
+    int64_t rounds;             /* LoD rounds executed */
+    int64_t peak_device_bytes;  /* high-water mark of join work buffers */
+} pj_stats;
+
+pj_status pj_get_stats(const pj_context *ctx, pj_stats *out);
+const char *pj_last_error(const pj_context *ctx);
+
+/* ------------------------------------------------------------------------
+ * Learned LoD skip.  The join, when cfg.log_path is set,
+ * appends one record per refined candidate pair: 16 float features and the
+ * LoD that decided it.  Training runs the network's forward, backward and
+ * Adam kernels on the GPU. */
+typedef struct {
+    int32_t epochs;
+    int32_t batch;
+    float lr;
+    uint64_t seed;
+} pj_train_opts;
+
+pj_status pj_train_lod_model(pj_context *ctx, const char *log_path, const char *model_out,
+                             const pj_train_opts *opts, float *final_loss);
+
+/* ------------------------------------------------------------------------
+ * Inspection entry points used by tests (all inputs and outputs are host
+ * arrays; they run the same device code as the join).
+ */
+/* Per-object MBB (lo xyz, hi xyz) and anchor (xyz), float32. */
+pj_status pj_meshes_boxes(const pj_meshes *m, float *mbb6, float *anchor3);
+/* Per-facet hd and ph of one (object, LoD), float32 (0 on the finest LoD). */
+pj_status pj_meshes_hdph(const pj_meshes *m, int32_t obj, int32_t lod, float *hd, float *ph);
+
+/* Distance of n triangle pairs (t1[n][9], t2[n][9] float32 corners).
+ * precision FP32_BAND: d = FP32 facet distance, hit = 1 where the FP32 test
+ * is sure the triangles cross; FP64: exact meet test and FP64 distance. */
+pj_status pj_facet_pairs(pj_context *ctx, const float *t1, const float *t2, int64_t n, int32_t precision,
+                         double *d, int8_t *hit);
+
+/* LoD bounds of n object pairs (r[i], s[i]) at one LoD (Eq. (1), Eq. (2)),
+ * with the given precision and schedule: lb, ub and the sure-meet flag. */
+pj_status pj_pair_bounds(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, int64_t n, const int32_t *r,
+                         const int32_t *s, int32_t lod, double *lb, double *ub, int8_t *hit);
+
+/* The LoD-skip network on n feature rows (x[n][16]) with the given
+ * parameters (FP32 master copies, layout W1[16][64] b1 W2[64][64] b2 W3[64][4]
+ * b3), weights rounded to BF16 as in inference.  logits[n][4]; if y is not
+ * NULL also the mean cross-entropy (loss) and FP32 gradients (grads, same
+ * layout as params). */
+pj_status pj_mlp_eval(pj_context *ctx, const float *params, const float *x, const int32_t *y, int64_t n,
+                      float *logits, float *loss, float *grads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PJ_H */

@@ -78,6 +78,9 @@ def lib():
         L.oracle_lod_bounds.argtypes = [sp, ctypes.c_int, sp, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, dp, dp]
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_tri_tri_batch.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_int]
+        L.oracle_tri_tri_batch.restype = None
         _lib = L
     return _lib
 
@@ -128,6 +131,18 @@ def tri_tri_dist(t1, t2) -> float:
     t2 = np.ascontiguousarray(t2, np.float32).reshape(9)
     fp = ctypes.POINTER(ctypes.c_float)
     return float(lib().oracle_tri_tri_dist(t1.ctypes.data_as(fp), t2.ctypes.data_as(fp), None))
+
+
+def tri_tri_batch(t1, t2, threads: int = 0):
+    """(d, hit) for many triangle pairs ([n, 9] or [n, 3, 3] float32 each)."""
+    t1 = np.ascontiguousarray(t1, np.float32).reshape(-1, 9)
+    t2 = np.ascontiguousarray(t2, np.float32).reshape(-1, 9)
+    n = len(t1)
+    d = np.empty(n, np.float64)
+    h = np.zeros(n, np.int8)
+    if n:
+        lib().oracle_tri_tri_batch(n, t1.ctypes.data, t2.ctypes.data, d.ctypes.data, h.ctypes.data, int(threads))
+    return d, h.astype(bool)
 
 
 def pt_tri(p, a, b, c) -> float:

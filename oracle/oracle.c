@@ -364,6 +364,16 @@ static void facet_boxes(const double *F, int n, double *box)
         }
 }
 
+static int cmp_bp(const void *x, const void *y)
+{
+    const double a = *(const double *)x, b = *(const double *)y;
+    if (a < b) return -1;
+    if (a > b) return 1;
+    const int64_t i = *(const int64_t *)((const char *)x + sizeof(double));
+    const int64_t j = *(const int64_t *)((const char *)y + sizeof(double));
+    return (i > j) - (i < j);
+}
+
 /* d(r,s) at the given LoDs: minimum over all facet pairs (Section 2.1).
  * mode 0 ("brute"): every facet pair.
  * mode 1 ("culled"): a facet pair whose boxes are at least the current best
@@ -383,26 +393,73 @@ double oracle_object_distance(const om_set *R, int r, int lod_r, const om_set *S
                 best = fmin(best, oracle_tri_tri_d15(FR + 9 * i, FS + 9 * j));
             }
     } else {
+        /* Facets are visited in blocks of OB consecutive facets; a block pair
+         * (and then a facet pair) whose boxes are at least the current best
+         * apart is skipped.  Block pairs are taken in ascending box-gap order
+         * so that small distances are found early.  Exact: a skipped pair's
+         * distance is not below its box gap. */
+        enum { OB = 32 };
         double *BR = (double *)malloc(sizeof(double) * 6 * (size_t)(nr > 0 ? nr : 1));
         double *BS = (double *)malloc(sizeof(double) * 6 * (size_t)(ns > 0 ? ns : 1));
         facet_boxes(FR, nr, BR);
         facet_boxes(FS, ns, BS);
-        double best2 = DBL_MAX;
-        for (int i = 0; i < nr && !h; i++) {
-            const double *bi = BR + 6 * i;
-            for (int j = 0; j < ns; j++) {
-                const double *bj = BS + 6 * j;
-                double g2 = 0.0;
-                for (int k = 0; k < 3; k++) {
-                    double g = fmax(0.0, fmax(bj[k] - bi[3 + k], bi[k] - bj[3 + k]));
-                    g2 += g * g;
+        int nbr = (nr + OB - 1) / OB, nbs = (ns + OB - 1) / OB;
+        double *KR = (double *)malloc(sizeof(double) * 6 * (size_t)(nbr > 0 ? nbr : 1));
+        double *KS = (double *)malloc(sizeof(double) * 6 * (size_t)(nbs > 0 ? nbs : 1));
+        for (int b = 0; b < nbr; b++)
+            for (int k = 0; k < 3; k++) {
+                KR[6 * b + k] = INFINITY;
+                KR[6 * b + 3 + k] = -INFINITY;
+                for (int i = b * OB; i < nr && i < (b + 1) * OB; i++) {
+                    KR[6 * b + k] = fmin(KR[6 * b + k], BR[6 * i + k]);
+                    KR[6 * b + 3 + k] = fmax(KR[6 * b + 3 + k], BR[6 * i + 3 + k]);
                 }
-                if (g2 >= best2) continue;
-                if (g2 == 0.0 && oracle_tri_tri_intersect_d(FR + 9 * i, FS + 9 * j)) { h = 1; best = 0.0; break; }
-                double d = oracle_tri_tri_d15(FR + 9 * i, FS + 9 * j);
-                if (d < best) { best = d; best2 = d * d; }
+            }
+        for (int b = 0; b < nbs; b++)
+            for (int k = 0; k < 3; k++) {
+                KS[6 * b + k] = INFINITY;
+                KS[6 * b + 3 + k] = -INFINITY;
+                for (int j = b * OB; j < ns && j < (b + 1) * OB; j++) {
+                    KS[6 * b + k] = fmin(KS[6 * b + k], BS[6 * j + k]);
+                    KS[6 * b + 3 + k] = fmax(KS[6 * b + 3 + k], BS[6 * j + 3 + k]);
+                }
+            }
+        int64_t nbp = (int64_t)nbr * nbs;
+        struct bp { double g2; int64_t id; } *order = (struct bp *)malloc(sizeof(struct bp) * (size_t)(nbp > 0 ? nbp : 1));
+        for (int64_t q = 0; q < nbp; q++) {
+            const double *a = KR + 6 * (q / nbs), *b = KS + 6 * (q % nbs);
+            double g2 = 0.0;
+            for (int k = 0; k < 3; k++) {
+                double g = fmax(0.0, fmax(b[k] - a[3 + k], a[k] - b[3 + k]));
+                g2 += g * g;
+            }
+            order[q].g2 = g2;
+            order[q].id = q;
+        }
+        qsort(order, (size_t)nbp, sizeof(struct bp), cmp_bp);
+        double best2 = DBL_MAX;
+        for (int64_t q = 0; q < nbp && !h; q++) {
+            if (order[q].g2 >= best2) break;
+            int b1 = (int)(order[q].id / nbs), b2 = (int)(order[q].id % nbs);
+            for (int i = b1 * OB; i < nr && i < (b1 + 1) * OB && !h; i++) {
+                const double *bi = BR + 6 * i;
+                for (int j = b2 * OB; j < ns && j < (b2 + 1) * OB; j++) {
+                    const double *bj = BS + 6 * j;
+                    double g2 = 0.0;
+                    for (int k = 0; k < 3; k++) {
+                        double g = fmax(0.0, fmax(bj[k] - bi[3 + k], bi[k] - bj[3 + k]));
+                        g2 += g * g;
+                    }
+                    if (g2 >= best2) continue;
+                    if (g2 == 0.0 && oracle_tri_tri_intersect_d(FR + 9 * i, FS + 9 * j)) { h = 1; best = 0.0; break; }
+                    double d = oracle_tri_tri_d15(FR + 9 * i, FS + 9 * j);
+                    if (d < best) { best = d; best2 = d * d; }
+                }
             }
         }
+        free(order);
+        free(KR);
+        free(KS);
         free(BR);
         free(BS);
     }
@@ -598,4 +655,18 @@ int oracle_num_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* Triangle distances and exact meet flags for n pairs (float32 corners). */
+void oracle_tri_tri_batch(int64_t n, const float *t1, const float *t2, double *d, int8_t *hit, int threads)
+{
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#pragma omp parallel for schedule(static)
+#endif
+    for (int64_t k = 0; k < n; k++) {
+        int h = 0;
+        d[k] = oracle_tri_tri_dist(t1 + 9 * k, t2 + 9 * k, &h);
+        hit[k] = (int8_t)h;
+    }
 }

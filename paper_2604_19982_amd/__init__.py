@@ -1,0 +1,289 @@
+"""Python binding of the MI355X progressive polyhedral spatial join library.
+
+Argument marshalling only: every step of the join runs in the HIP library
+``_lib/libpj.so`` behind the C ABI of ``include/pj.h``.  There is no CPU
+fallback; if the library is missing, importing a context raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libpj.so")
+
+PJ_OK = 0
+STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "UNSUPPORTED", 5: "INTERNAL"}
+PREC = {"fp32": 0, "fp32_band": 0, "fp64": 1}
+SCHED = {"batched": 0, "plain": 1}
+
+
+class PJError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("precision", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("learned_skip", ctypes.c_int32), ("want_dist", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("tile_cull", ctypes.c_int32), ("tile_s", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
+                ("host_threads", ctypes.c_int32), ("mem_cap_bytes", ctypes.c_int64),
+                ("model_path", ctypes.c_char_p), ("log_path", ctypes.c_char_p), ("autotune_path", ctypes.c_char_p),
+                ("stream", ctypes.c_void_p)]
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("n_objects", ctypes.c_int32), ("n_lods", ctypes.c_int32), ("n_verts", ctypes.c_int64),
+                ("n_tris", ctypes.c_int64), ("verts", ctypes.c_void_p), ("vert_begin", ctypes.c_void_p),
+                ("vert_count", ctypes.c_void_p), ("tris", ctypes.c_void_p), ("tri_begin", ctypes.c_void_p),
+                ("tri_count", ctypes.c_void_p), ("parent", ctypes.c_void_p), ("hd", ctypes.c_void_p),
+                ("ph", ctypes.c_void_p), ("hdph_begin", ctypes.c_void_p)]
+
+
+class Pairs(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("r", ctypes.POINTER(ctypes.c_int32)), ("s", ctypes.POINTER(ctypes.c_int32)),
+                ("dist", ctypes.POINTER(ctypes.c_double))]
+
+
+class Knn(ctypes.Structure):
+    _fields_ = [("n_r", ctypes.c_int32), ("k", ctypes.c_int32), ("count", ctypes.POINTER(ctypes.c_int32)),
+                ("s", ctypes.POINTER(ctypes.c_int32)), ("dist", ctypes.POINTER(ctypes.c_double))]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("t_total_ms", ctypes.c_double), ("t_filter_ms", ctypes.c_double), ("t_refine_ms", ctypes.c_double),
+                ("t_band_ms", ctypes.c_double), ("t_ingest_ms", ctypes.c_double),
+                ("refine_kernel_ms", ctypes.c_double), ("band_kernel_ms", ctypes.c_double),
+                ("refine_launches", ctypes.c_int64), ("candidates", ctypes.c_int64),
+                ("confirmed_filter", ctypes.c_int64), ("facet_pairs", ctypes.c_int64),
+                ("facet_pairs_fp64", ctypes.c_int64), ("tiles", ctypes.c_int64), ("tiles_culled", ctypes.c_int64),
+                ("band_pairs", ctypes.c_int64), ("resolved_at_lod", ctypes.c_int64 * 8), ("rounds", ctypes.c_int64),
+                ("peak_device_bytes", ctypes.c_int64)]
+
+    def to_dict(self):
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            d[name] = list(v) if name == "resolved_at_lod" else v
+        return d
+
+
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
+
+
+EXPORTS = ["pj_config_default", "pj_context_create", "pj_context_destroy", "pj_meshes_create", "pj_meshes_destroy",
+           "pj_join_within", "pj_join_intersect", "pj_join_knn", "pj_pairs_free", "pj_knn_free", "pj_get_stats",
+           "pj_last_error", "pj_train_lod_model", "pj_meshes_boxes", "pj_meshes_hdph", "pj_facet_pairs",
+           "pj_pair_bounds", "pj_mlp_eval"]
+
+_lib = None
+
+
+def lib():
+    """Load ``libpj.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2604_19982_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        L.pj_config_default.argtypes = [ctypes.POINTER(Config)]
+        L.pj_config_default.restype = None
+        L.pj_context_create.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(vp)]
+        L.pj_context_destroy.argtypes = [vp]
+        L.pj_meshes_create.argtypes = [vp, ctypes.POINTER(MeshDesc), ctypes.POINTER(vp)]
+        L.pj_meshes_destroy.argtypes = [vp]
+        L.pj_join_within.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.POINTER(Pairs)]
+        L.pj_join_intersect.argtypes = [vp, vp, vp, ctypes.POINTER(Pairs)]
+        L.pj_join_knn.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.POINTER(Knn)]
+        L.pj_pairs_free.argtypes = [ctypes.POINTER(Pairs)]
+        L.pj_pairs_free.restype = None
+        L.pj_knn_free.argtypes = [ctypes.POINTER(Knn)]
+        L.pj_knn_free.restype = None
+        L.pj_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+        L.pj_last_error.argtypes = [vp]
+        L.pj_last_error.restype = ctypes.c_char_p
+        L.pj_train_lod_model.argtypes = [vp, ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(TrainOpts),
+                                         ctypes.POINTER(ctypes.c_float)]
+        L.pj_meshes_boxes.argtypes = [vp, vp, vp]
+        L.pj_meshes_hdph.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp]
+        L.pj_facet_pairs.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_int32, vp, vp]
+        L.pj_pair_bounds.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp, ctypes.c_int32, vp, vp, vp]
+        L.pj_mlp_eval.argtypes = [vp, vp, vp, vp, ctypes.c_int64, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _arr(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+class Meshes:
+    """An ingested object set (device resident)."""
+
+    def __init__(self, ctx: "Context", ms, hd=None, ph=None, hdph_begin=None):
+        self.ctx = ctx
+        self.n = int(ms.n_objects)
+        self.L = int(ms.n_lods)
+        keep = [_arr(ms.verts, np.float32), _arr(ms.vert_begin, np.int64), _arr(ms.vert_count, np.int32),
+                _arr(ms.tris, np.int32), _arr(ms.tri_begin, np.int64), _arr(ms.tri_count, np.int32),
+                _arr(ms.parent, np.int32)]
+        extra = [None, None, None] if hd is None else [_arr(hd, np.float32), _arr(ph, np.float32),
+                                                      _arr(hdph_begin, np.int64)]
+        d = MeshDesc(self.n, self.L, len(keep[0]), len(keep[3]), *[a.ctypes.data for a in keep],
+                     *[None if a is None else a.ctypes.data for a in extra])
+        h = ctypes.c_void_p()
+        ctx._check(lib().pj_meshes_create(ctx.h, ctypes.byref(d), ctypes.byref(h)))
+        self.h = h
+        self.tri_count = keep[5].reshape(self.n, self.L) if self.n else keep[5].reshape(0, self.L)
+
+    def boxes(self):
+        box = np.zeros((self.n, 6), np.float32)
+        anc = np.zeros((self.n, 3), np.float32)
+        self.ctx._check(lib().pj_meshes_boxes(self.h, box.ctypes.data, anc.ctypes.data))
+        return box, anc
+
+    def hdph(self, obj, lod):
+        nf = int(self.tri_count[obj, lod])
+        hd = np.zeros(nf, np.float32)
+        ph = np.zeros(nf, np.float32)
+        self.ctx._check(lib().pj_meshes_hdph(self.h, int(obj), int(lod), hd.ctypes.data, ph.ctypes.data))
+        return hd, ph
+
+    def close(self):
+        if self.h:
+            lib().pj_meshes_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context:
+    """A join context on one device (see ``pj_config``)."""
+
+    def __init__(self, device=0, precision="fp32", schedule="batched", learned_skip=False, want_dist=False,
+                 use_graph=True, tile_cull=True, tile_s=0, waves_per_cu=0, mem_cap_bytes=0, model_path=None,
+                 log_path=None, stream=None):
+        L = lib()
+        c = Config()
+        L.pj_config_default(ctypes.byref(c))
+        c.device = device
+        c.precision = PREC[precision]
+        c.schedule = SCHED[schedule]
+        c.learned_skip = int(bool(learned_skip))
+        c.want_dist = int(bool(want_dist))
+        c.use_graph = int(bool(use_graph))
+        c.tile_cull = int(bool(tile_cull))
+        c.tile_s = int(tile_s)
+        c.waves_per_cu = int(waves_per_cu)
+        c.mem_cap_bytes = int(mem_cap_bytes)
+        self._paths = [None if p is None else os.fsencode(p) for p in (model_path, log_path)]
+        c.model_path, c.log_path = self._paths
+        c.stream = stream
+        h = ctypes.c_void_p()
+        st = L.pj_context_create(ctypes.byref(c), ctypes.byref(h))
+        if st != PJ_OK:
+            raise PJError(st, "pj_context_create failed")
+        self.h = h
+        self.cfg = c
+
+    def _check(self, st):
+        if st != PJ_OK:
+            raise PJError(st, lib().pj_last_error(self.h).decode(errors="replace"))
+
+    def meshes(self, ms, **kw) -> Meshes:
+        return Meshes(self, ms, **kw)
+
+    def join_within(self, R: Meshes, S: Meshes, tau: float):
+        p = Pairs()
+        self._check(lib().pj_join_within(self.h, R.h, S.h, float(tau), ctypes.byref(p)))
+        return self._pairs(p)
+
+    def join_intersect(self, R: Meshes, S: Meshes):
+        p = Pairs()
+        self._check(lib().pj_join_intersect(self.h, R.h, S.h, ctypes.byref(p)))
+        return self._pairs(p)
+
+    def _pairs(self, p):
+        n = int(p.n)
+        out = dict(r=np.ctypeslib.as_array(p.r, (n,)).copy() if n else np.zeros(0, np.int32),
+                   s=np.ctypeslib.as_array(p.s, (n,)).copy() if n else np.zeros(0, np.int32),
+                   dist=np.ctypeslib.as_array(p.dist, (n,)).copy() if (n and p.dist) else None)
+        lib().pj_pairs_free(ctypes.byref(p))
+        return out
+
+    def join_knn(self, R: Meshes, S: Meshes, k: int):
+        q = Knn()
+        self._check(lib().pj_join_knn(self.h, R.h, S.h, int(k), ctypes.byref(q)))
+        n, kk = int(q.n_r), int(q.k)
+        count = np.ctypeslib.as_array(q.count, (n,)).copy() if n else np.zeros(0, np.int32)
+        s = np.ctypeslib.as_array(q.s, (n * kk,)).copy().reshape(n, kk) if n * kk else np.zeros((n, kk), np.int32)
+        d = np.ctypeslib.as_array(q.dist, (n * kk,)).copy().reshape(n, kk) if n * kk else np.zeros((n, kk))
+        lib().pj_knn_free(ctypes.byref(q))
+        return dict(count=count, s=s, dist=d)
+
+    def stats(self):
+        st = Stats()
+        self._check(lib().pj_get_stats(self.h, ctypes.byref(st)))
+        return st.to_dict()
+
+    def facet_pairs(self, t1, t2, precision="fp32"):
+        t1 = _arr(t1, np.float32).reshape(-1, 9)
+        t2 = _arr(t2, np.float32).reshape(-1, 9)
+        n = len(t1)
+        d = np.zeros(n, np.float64)
+        hit = np.zeros(n, np.int8)
+        self._check(lib().pj_facet_pairs(self.h, t1.ctypes.data, t2.ctypes.data, n, PREC[precision], d.ctypes.data,
+                                         hit.ctypes.data))
+        return d, hit.astype(bool)
+
+    def pair_bounds(self, R: Meshes, S: Meshes, r, s, lod):
+        r = _arr(r, np.int32)
+        s = _arr(s, np.int32)
+        n = len(r)
+        lb = np.zeros(n)
+        ub = np.zeros(n)
+        hit = np.zeros(n, np.int8)
+        self._check(lib().pj_pair_bounds(self.h, R.h, S.h, n, r.ctypes.data, s.ctypes.data, int(lod),
+                                         lb.ctypes.data, ub.ctypes.data, hit.ctypes.data))
+        return lb, ub, hit.astype(bool)
+
+    def mlp_eval(self, params, x, y=None):
+        params = _arr(params, np.float32)
+        x = _arr(x, np.float32).reshape(-1, 16)
+        n = len(x)
+        logits = np.zeros((n, 4), np.float32)
+        loss = np.zeros(1, np.float32)
+        grads = np.zeros_like(params)
+        yy = None if y is None else _arr(y, np.int32)
+        self._check(lib().pj_mlp_eval(self.h, params.ctypes.data, x.ctypes.data,
+                                      None if yy is None else yy.ctypes.data, n, logits.ctypes.data,
+                                      loss.ctypes.data, grads.ctypes.data))
+        return logits, (float(loss[0]) if y is not None else None), (grads if y is not None else None)
+
+    def train_lod_model(self, log_path, model_out, epochs=30, batch=1024, lr=3e-3, seed=0):
+        o = TrainOpts(int(epochs), int(batch), float(lr), int(seed))
+        loss = ctypes.c_float()
+        self._check(lib().pj_train_lod_model(self.h, os.fsencode(log_path), os.fsencode(model_out),
+                                             ctypes.byref(o), ctypes.byref(loss)))
+        return float(loss.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pj_context_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

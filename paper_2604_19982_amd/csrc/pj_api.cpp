@@ -1,0 +1,1092 @@
+// pj_api.cpp -- C ABI: contexts, mesh ingest, joins, inspection entry points.
+//
+// The join follows the filter-and-refine pipeline of 3DPipe (Section 3.1):
+// an MBB filter produces candidate pairs with [lb, ub] (MINDIST of the boxes,
+// distance of the vertex anchors); then, LoD by LoD from coarse to fine, the
+// facet-level bounds of Eq. (1)/(2) are computed for every undecided pair and
+// each pair is confirmed (ub <= tau), pruned (lb > tau) or carried to the
+// next LoD; the finest LoD is exact.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <set>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "pj_internal.h"
+
+using namespace pj;
+
+namespace {
+
+double now_ms()
+{
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    int64_t *tracked = nullptr;  // context byte counter
+    ~DevBuf()
+    {
+        if (p) (void)hipFree(p);
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        if (tracked) *tracked -= (int64_t)cap;
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+enum Status : int8_t { ST_UNDEC = 0, ST_CONF = 1, ST_PRUNED = 2, ST_BAND = 3 };
+
+}  // namespace
+
+struct pj_meshes {
+    int device = 0;
+    int32_t n = 0, L = 1;
+    int64_t nv = 0, nt = 0, nh = 0;
+    float *d_verts = nullptr;
+    int32_t *d_tris = nullptr;
+    int64_t *d_vbeg = nullptr, *d_tbeg = nullptr, *d_hpbeg = nullptr;
+    int32_t *d_tcnt = nullptr;
+    float2 *d_hdph = nullptr;
+    float *d_box = nullptr, *d_anchor = nullptr;
+    float2 *d_lodmax = nullptr;
+    std::vector<int64_t> h_vbeg, h_tbeg, h_hpbeg;
+    std::vector<int32_t> h_tcnt;
+    std::vector<float> h_box, h_anchor;
+    std::vector<float2> h_lodmax;
+    MeshDev dev() const
+    {
+        return MeshDev{d_verts, d_tris, d_vbeg, d_tbeg, d_tcnt, d_hpbeg, d_hdph, n, L};
+    }
+    int32_t count(int obj, int lod) const { return h_tcnt[(int64_t)obj * L + lod]; }
+};
+
+struct pj_context {
+    pj_config cfg;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    pj_stats stats;
+    int num_cu = 256;
+    int64_t dev_bytes = 0, peak_bytes = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    DevBuf b_items, b_tiles, b_out, b_out64, b_ctr, b_cand_r, b_cand_s, b_cand_lb, b_cand_ub, b_blk, b_blkoff,
+        b_total, b_tmp0, b_tmp1, b_tmp2, b_tmp3;
+    // LoD model (learned skip)
+    std::vector<float> model;
+    float feat_mean[MLP_IN], feat_std[MLP_IN];
+    bool has_model = false;
+};
+
+namespace {
+
+pj_status fail(pj_context *ctx, pj_status st, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+pj_status hipfail(pj_context *ctx, hipError_t e, const char *what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(ctx, e == hipErrorOutOfMemory ? PJ_ERR_OUT_OF_MEMORY : PJ_ERR_DEVICE, m);
+}
+
+#define HIPTRY(ctx, expr)                                        \
+    do {                                                         \
+        hipError_t e_ = (expr);                                  \
+        if (e_ != hipSuccess) return hipfail((ctx), e_, #expr);  \
+    } while (0)
+
+// grow-only device buffer with the context's memory cap
+pj_status ensure(pj_context *ctx, DevBuf &b, size_t bytes)
+{
+    if (bytes <= b.cap) return PJ_OK;
+    size_t nb = std::max(bytes, b.cap + b.cap / 2);
+    nb = (nb + 255) & ~size_t(255);
+    int64_t after = ctx->dev_bytes - (int64_t)b.cap + (int64_t)nb;
+    if (ctx->cfg.mem_cap_bytes > 0 && after > ctx->cfg.mem_cap_bytes) {
+        nb = bytes;
+        after = ctx->dev_bytes - (int64_t)b.cap + (int64_t)nb;
+        if (after > ctx->cfg.mem_cap_bytes)
+            return fail(ctx, PJ_ERR_OUT_OF_MEMORY, "work buffers exceed the configured device memory cap");
+    }
+    if (b.p) (void)hipFree(b.p);
+    ctx->dev_bytes -= (int64_t)b.cap;
+    b.p = nullptr;
+    b.cap = 0;
+    hipError_t e = hipMalloc(&b.p, nb);
+    if (e != hipSuccess) return hipfail(ctx, e, "hipMalloc");
+    b.cap = nb;
+    b.tracked = &ctx->dev_bytes;
+    ctx->dev_bytes += (int64_t)nb;
+    ctx->peak_bytes = std::max(ctx->peak_bytes, ctx->dev_bytes);
+    return PJ_OK;
+}
+
+#define PJTRY(expr)                        \
+    do {                                   \
+        pj_status s_ = (expr);             \
+        if (s_ != PJ_OK) return s_;        \
+    } while (0)
+
+template <class T>
+T *ptr(DevBuf &b)
+{
+    return reinterpret_cast<T *>(b.p);
+}
+
+// float >= x (smallest float not below x) for x >= 0
+float up_float(double x)
+{
+    float f = (float)x;
+    if ((double)f < x) f = std::nextafter(f, INFINITY);
+    return f;
+}
+
+}  // namespace
+
+// ===========================================================================
+// configuration and contexts
+// ===========================================================================
+extern "C" void pj_config_default(pj_config *cfg)
+{
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->device = 0;
+    cfg->precision = PJ_PREC_FP32_BAND;
+    cfg->schedule = PJ_SCHED_BATCHED;
+    cfg->learned_skip = 0;
+    cfg->want_dist = 0;
+    cfg->use_graph = 1;
+    cfg->tile_cull = 1;
+    cfg->tile_s = 0;
+    cfg->waves_per_cu = 0;
+}
+
+extern "C" pj_status pj_context_create(const pj_config *cfg, pj_context **out)
+{
+    if (!out) return PJ_ERR_INVALID_ARG;
+    *out = nullptr;
+    pj_config c;
+    if (cfg) c = *cfg;
+    else pj_config_default(&c);
+    if (c.precision != PJ_PREC_FP32_BAND && c.precision != PJ_PREC_FP64) return PJ_ERR_INVALID_ARG;
+    if (c.schedule != PJ_SCHED_BATCHED && c.schedule != PJ_SCHED_PLAIN) return PJ_ERR_INVALID_ARG;
+    if (c.tile_s < 0 || c.waves_per_cu < 0 || c.mem_cap_bytes < 0) return PJ_ERR_INVALID_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return PJ_ERR_DEVICE;
+    if (c.device < 0 || c.device >= ndev) return PJ_ERR_INVALID_ARG;
+    if (hipSetDevice(c.device) != hipSuccess) return PJ_ERR_DEVICE;
+    pj_context *ctx = new pj_context();
+    ctx->cfg = c;
+    std::memset(&ctx->stats, 0, sizeof(ctx->stats));
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c.device) == hipSuccess) ctx->num_cu = prop.multiProcessorCount;
+    if (c.stream) {
+        ctx->stream = (hipStream_t)c.stream;
+    } else {
+        if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete ctx;
+            return PJ_ERR_DEVICE;
+        }
+        ctx->own_stream = true;
+    }
+    if (hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
+        delete ctx;
+        return PJ_ERR_DEVICE;
+    }
+    *out = ctx;
+    return PJ_OK;
+}
+
+extern "C" pj_status pj_context_destroy(pj_context *ctx)
+{
+    if (!ctx) return PJ_ERR_INVALID_ARG;
+    (void)hipSetDevice(ctx->cfg.device);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return PJ_OK;
+}
+
+extern "C" const char *pj_last_error(const pj_context *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+extern "C" pj_status pj_get_stats(const pj_context *ctx, pj_stats *out)
+{
+    if (!ctx || !out) return PJ_ERR_INVALID_ARG;
+    *out = ctx->stats;
+    return PJ_OK;
+}
+
+// ===========================================================================
+// mesh ingest
+// ===========================================================================
+namespace {
+
+void free_meshes(pj_meshes *m)
+{
+    if (!m) return;
+    for (void *p : {(void *)m->d_verts, (void *)m->d_tris, (void *)m->d_vbeg, (void *)m->d_tbeg, (void *)m->d_hpbeg,
+                    (void *)m->d_tcnt, (void *)m->d_hdph, (void *)m->d_box, (void *)m->d_anchor,
+                    (void *)m->d_lodmax})
+        if (p) (void)hipFree(p);
+    delete m;
+}
+
+template <class T>
+hipError_t upload(T **dst, const T *src, size_t n, hipStream_t st)
+{
+    *dst = nullptr;
+    hipError_t e = hipMalloc((void **)dst, std::max<size_t>(n, 1) * sizeof(T));
+    if (e != hipSuccess) return e;
+    if (n) e = hipMemcpyAsync(*dst, src, n * sizeof(T), hipMemcpyHostToDevice, st);
+    return e;
+}
+
+pj_status validate_desc(pj_context *ctx, const pj_mesh_desc *d)
+{
+    if (d->n_objects < 0 || d->n_lods < 1 || d->n_lods > 8 || d->n_verts < 0 || d->n_tris < 0)
+        return fail(ctx, PJ_ERR_INVALID_ARG, "negative count or n_lods outside 1..8");
+    if (d->n_objects == 0) return PJ_OK;
+    if (!d->verts && d->n_verts) return fail(ctx, PJ_ERR_INVALID_ARG, "verts is NULL");
+    if (!d->tris && d->n_tris) return fail(ctx, PJ_ERR_INVALID_ARG, "tris is NULL");
+    if (!d->vert_begin || !d->vert_count || !d->tri_begin || !d->tri_count)
+        return fail(ctx, PJ_ERR_INVALID_ARG, "NULL range array");
+    const int64_t n = d->n_objects, L = d->n_lods;
+    for (int64_t i = 0; i < 3 * d->n_verts; ++i)
+        if (!std::isfinite(d->verts[i])) return fail(ctx, PJ_ERR_INVALID_ARG, "NaN or Inf coordinate");
+    for (int64_t i = 0; i < n; ++i) {
+        if (d->vert_begin[i] < 0 || d->vert_count[i] < 0 || d->vert_begin[i] + d->vert_count[i] > d->n_verts)
+            return fail(ctx, PJ_ERR_INVALID_ARG, "vertex range out of bounds");
+        for (int64_t l = 0; l < L; ++l) {
+            int64_t k = i * L + l;
+            if (d->tri_begin[k] < 0 || d->tri_count[k] < 0 || d->tri_begin[k] + d->tri_count[k] > d->n_tris)
+                return fail(ctx, PJ_ERR_INVALID_ARG, "triangle range out of bounds");
+        }
+    }
+    // triangle indices (blocks shared by many objects are checked once per vertex count)
+    std::set<std::tuple<int64_t, int32_t, int32_t>> seen;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t l = 0; l < L; ++l) {
+            int64_t k = i * L + l;
+            auto key = std::make_tuple(d->tri_begin[k], d->tri_count[k], d->vert_count[i]);
+            if (!seen.insert(key).second) continue;
+            const int32_t *t = d->tris + 3 * d->tri_begin[k];
+            for (int64_t q = 0; q < 3 * (int64_t)d->tri_count[k]; ++q)
+                if (t[q] < 0 || t[q] >= d->vert_count[i])
+                    return fail(ctx, PJ_ERR_INVALID_ARG, "triangle vertex index out of range");
+        }
+    if (L > 1 && !d->hd) {
+        if (!d->parent) return fail(ctx, PJ_ERR_INVALID_ARG, "parent maps are required when n_lods > 1");
+        std::set<std::tuple<int64_t, int32_t, int32_t>> pseen;
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t l = 1; l < L; ++l) {
+                int64_t k = i * L + l;
+                int32_t nc = d->tri_count[k - 1];
+                auto key = std::make_tuple(d->tri_begin[k], d->tri_count[k], nc);
+                if (!pseen.insert(key).second) continue;
+                const int32_t *p = d->parent + d->tri_begin[k];
+                for (int32_t q = 0; q < d->tri_count[k]; ++q)
+                    if (p[q] < 0 || p[q] >= nc) return fail(ctx, PJ_ERR_INVALID_ARG, "parent index outside the coarser LoD");
+            }
+    }
+    if (d->hd) {
+        if (!d->ph || !d->hdph_begin) return fail(ctx, PJ_ERR_INVALID_ARG, "hd given without ph or hdph_begin");
+    }
+    return PJ_OK;
+}
+
+}  // namespace
+
+extern "C" pj_status pj_meshes_create(pj_context *ctx, const pj_mesh_desc *d, pj_meshes **out)
+{
+    if (!ctx || !d || !out) return fail(ctx, PJ_ERR_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    double t0 = now_ms();
+    PJTRY(validate_desc(ctx, d));
+    HIPTRY(ctx, hipSetDevice(ctx->cfg.device));
+    hipStream_t st = ctx->stream;
+    pj_meshes *m = new pj_meshes();
+    m->device = ctx->cfg.device;
+    m->n = d->n_objects;
+    m->L = d->n_lods;
+    m->nv = d->n_verts;
+    m->nt = d->n_tris;
+    const int64_t n = m->n, L = m->L;
+    auto bail = [&](hipError_t e, const char *what) {
+        free_meshes(m);
+        return hipfail(ctx, e, what);
+    };
+    if (n == 0) {
+        *out = m;
+        return PJ_OK;
+    }
+    m->h_vbeg.assign(d->vert_begin, d->vert_begin + n);
+    m->h_tbeg.assign(d->tri_begin, d->tri_begin + n * L);
+    m->h_tcnt.assign(d->tri_count, d->tri_count + n * L);
+    // hd/ph layout: one float2 per facet of every coarse LoD
+    m->h_hpbeg.assign(n * L, -1);
+    int64_t nh = 0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t l = 0; l + 1 < L; ++l) {
+            m->h_hpbeg[i * L + l] = nh;
+            nh += m->h_tcnt[i * L + l];
+        }
+    m->nh = nh;
+    hipError_t e;
+    std::vector<int32_t> vc(d->vert_count, d->vert_count + n);
+    (void)vc;
+    if ((e = upload(&m->d_verts, d->verts, 3 * (size_t)d->n_verts, st)) != hipSuccess) return bail(e, "verts");
+    if ((e = upload(&m->d_tris, d->tris, 3 * (size_t)d->n_tris, st)) != hipSuccess) return bail(e, "tris");
+    if ((e = upload(&m->d_vbeg, m->h_vbeg.data(), n, st)) != hipSuccess) return bail(e, "vert_begin");
+    if ((e = upload(&m->d_tbeg, m->h_tbeg.data(), n * L, st)) != hipSuccess) return bail(e, "tri_begin");
+    if ((e = upload(&m->d_tcnt, m->h_tcnt.data(), n * L, st)) != hipSuccess) return bail(e, "tri_count");
+    if ((e = upload(&m->d_hpbeg, m->h_hpbeg.data(), n * L, st)) != hipSuccess) return bail(e, "hdph_begin");
+    if ((e = hipMalloc((void **)&m->d_hdph, std::max<int64_t>(nh, 1) * sizeof(float2))) != hipSuccess)
+        return bail(e, "hdph");
+    if ((e = hipMemsetAsync(m->d_hdph, 0, std::max<int64_t>(nh, 1) * sizeof(float2), st)) != hipSuccess)
+        return bail(e, "hdph clear");
+    if ((e = hipMalloc((void **)&m->d_box, n * 6 * sizeof(float))) != hipSuccess) return bail(e, "boxes");
+    if ((e = hipMalloc((void **)&m->d_anchor, n * 3 * sizeof(float))) != hipSuccess) return bail(e, "anchors");
+    if ((e = hipMalloc((void **)&m->d_lodmax, n * L * sizeof(float2))) != hipSuccess) return bail(e, "lodmax");
+    MeshDev md = m->dev();
+    if ((e = launch_boxes(md, m->d_box, m->d_anchor, st)) != hipSuccess) return bail(e, "boxes kernel");
+
+    if (L > 1 && d->hd) {
+        // caller-supplied bounds, stored as float2 (hd, ph)
+        std::vector<float2> hp(nh);
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t l = 0; l + 1 < L; ++l) {
+                int64_t src = d->hdph_begin[i * L + l], dst = m->h_hpbeg[i * L + l];
+                for (int32_t q = 0; q < m->h_tcnt[i * L + l]; ++q) {
+                    float a = d->hd[src + q], b = d->ph[src + q];
+                    if (!(a >= 0.0f) || !(b >= 0.0f) || !std::isfinite(a) || !std::isfinite(b)) {
+                        free_meshes(m);
+                        return fail(ctx, PJ_ERR_INVALID_ARG, "hd/ph must be finite and non-negative");
+                    }
+                    hp[dst + q] = make_float2(a, b);
+                }
+            }
+        if ((e = hipMemcpyAsync(m->d_hdph, hp.data(), nh * sizeof(float2), hipMemcpyHostToDevice, st)) != hipSuccess)
+            return bail(e, "hdph upload");
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return bail(e, "sync");
+    } else if (L > 1) {
+        // ph: one thread per finest facet
+        std::vector<int64_t> fine_off(n + 1, 0);
+        for (int64_t i = 0; i < n; ++i) fine_off[i + 1] = fine_off[i] + m->h_tcnt[i * L + L - 1];
+        int32_t *d_parent = nullptr;
+        int64_t *d_off = nullptr;
+        if ((e = upload(&d_parent, d->parent, (size_t)d->n_tris, st)) != hipSuccess) return bail(e, "parent");
+        if ((e = upload(&d_off, fine_off.data(), n + 1, st)) != hipSuccess) return bail(e, "offsets");
+        e = launch_ph(md, m->d_hdph, d_parent, d_off, fine_off[n], st);
+        if (e != hipSuccess) return bail(e, "ph kernel");
+        // hd: descendants of each coarse facet, grouped per distinct connectivity
+        std::map<std::vector<int64_t>, int64_t> keymap;  // connectivity -> index into desc_base table
+        std::vector<int64_t> desc_base(n * L, 0);        // (obj, lod) -> start in desc_off
+        std::vector<int64_t> desc_off;
+        std::vector<int32_t> desc_list;
+        for (int64_t i = 0; i < n; ++i) {
+            std::vector<int64_t> key(2 * L);
+            for (int64_t l = 0; l < L; ++l) {
+                key[2 * l] = m->h_tbeg[i * L + l];
+                key[2 * l + 1] = m->h_tcnt[i * L + l];
+            }
+            auto it = keymap.find(key);
+            if (it == keymap.end()) {
+                int64_t slot = (int64_t)desc_off.size();
+                const int32_t nf = m->h_tcnt[i * L + L - 1];
+                std::vector<int32_t> anc(nf);
+                for (int32_t g = 0; g < nf; ++g) anc[g] = g;
+                std::vector<int64_t> bases(L, 0);
+                for (int64_t l = L - 2; l >= 0; --l) {
+                    const int32_t *par = d->parent + m->h_tbeg[i * L + l + 1];
+                    for (int32_t g = 0; g < nf; ++g) anc[g] = par[anc[g]];
+                    const int32_t nc = m->h_tcnt[i * L + l];
+                    bases[l] = (int64_t)desc_off.size();
+                    std::vector<int64_t> cnt(nc + 1, 0);
+                    for (int32_t g = 0; g < nf; ++g) cnt[anc[g] + 1]++;
+                    for (int32_t f = 0; f < nc; ++f) cnt[f + 1] += cnt[f];
+                    int64_t lb = (int64_t)desc_list.size();
+                    desc_list.resize(lb + nf);
+                    std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+                    for (int32_t g = 0; g < nf; ++g) desc_list[lb + pos[anc[g]]++] = g;
+                    for (int32_t f = 0; f <= nc; ++f) desc_off.push_back(lb + cnt[f]);
+                }
+                (void)slot;
+                it = keymap.emplace(key, (int64_t)keymap.size()).first;
+                for (int64_t l = 0; l < L; ++l) desc_base[i * L + l] = bases[l];
+                // remember bases for later objects sharing the key
+                it->second = i;
+            } else {
+                int64_t src = it->second;
+                for (int64_t l = 0; l < L; ++l) desc_base[i * L + l] = desc_base[src * L + l];
+            }
+        }
+        if (desc_list.size() > (size_t)INT32_MAX || desc_off.size() > (size_t)INT64_MAX) {
+            free_meshes(m);
+            return fail(ctx, PJ_ERR_UNSUPPORTED, "descendant tables too large");
+        }
+        std::vector<int32_t> desc_off32(desc_off.begin(), desc_off.end());
+        int64_t *d_dbase = nullptr;
+        int32_t *d_doff = nullptr, *d_dlist = nullptr;
+        int64_t *d_joboff = nullptr;
+        if ((e = upload(&d_dbase, desc_base.data(), desc_base.size(), st)) != hipSuccess) return bail(e, "desc");
+        if ((e = upload(&d_doff, desc_off32.data(), desc_off32.size(), st)) != hipSuccess) return bail(e, "desc");
+        if ((e = upload(&d_dlist, desc_list.data(), desc_list.size(), st)) != hipSuccess) return bail(e, "desc");
+        if ((e = hipMalloc((void **)&d_joboff, (n + 1) * sizeof(int64_t))) != hipSuccess) return bail(e, "jobs");
+        std::vector<std::vector<int64_t>> joboffs(L);
+        for (int64_t l = 0; l + 1 < L; ++l) {
+            std::vector<int64_t> &jo = joboffs[l];
+            jo.assign(n + 1, 0);
+            for (int64_t i = 0; i < n; ++i) jo[i + 1] = jo[i] + m->h_tcnt[i * L + l];
+            if ((e = hipMemcpyAsync(d_joboff, jo.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st)) !=
+                hipSuccess)
+                return bail(e, "jobs");
+            if ((e = launch_hd(md, m->d_hdph, d_joboff, jo[n], d_dbase, d_doff, d_dlist, (int)l, 8, st)) != hipSuccess)
+                return bail(e, "hd kernel");
+            if ((e = hipStreamSynchronize(st)) != hipSuccess) return bail(e, "hd sync");
+        }
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return bail(e, "ingest sync");
+        (void)hipFree(d_parent);
+        (void)hipFree(d_off);
+        (void)hipFree(d_dbase);
+        (void)hipFree(d_doff);
+        (void)hipFree(d_dlist);
+        (void)hipFree(d_joboff);
+    }
+    if ((e = launch_lodmax(md, m->d_lodmax, st)) != hipSuccess) return bail(e, "lodmax kernel");
+    m->h_box.resize(n * 6);
+    m->h_anchor.resize(n * 3);
+    m->h_lodmax.resize(n * L);
+    if ((e = hipMemcpyAsync(m->h_box.data(), m->d_box, n * 6 * sizeof(float), hipMemcpyDeviceToHost, st)) != hipSuccess)
+        return bail(e, "boxes D2H");
+    if ((e = hipMemcpyAsync(m->h_anchor.data(), m->d_anchor, n * 3 * sizeof(float), hipMemcpyDeviceToHost, st)) !=
+        hipSuccess)
+        return bail(e, "anchors D2H");
+    if ((e = hipMemcpyAsync(m->h_lodmax.data(), m->d_lodmax, n * L * sizeof(float2), hipMemcpyDeviceToHost, st)) !=
+        hipSuccess)
+        return bail(e, "lodmax D2H");
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return bail(e, "ingest sync");
+    ctx->stats.t_ingest_ms = now_ms() - t0;
+    *out = m;
+    return PJ_OK;
+}
+
+extern "C" pj_status pj_meshes_destroy(pj_meshes *m)
+{
+    if (!m) return PJ_ERR_INVALID_ARG;
+    (void)hipSetDevice(m->device);
+    free_meshes(m);
+    return PJ_OK;
+}
+
+extern "C" pj_status pj_meshes_boxes(const pj_meshes *m, float *mbb6, float *anchor3)
+{
+    if (!m) return PJ_ERR_INVALID_ARG;
+    if (mbb6) std::copy(m->h_box.begin(), m->h_box.end(), mbb6);
+    if (anchor3) std::copy(m->h_anchor.begin(), m->h_anchor.end(), anchor3);
+    return PJ_OK;
+}
+
+extern "C" pj_status pj_meshes_hdph(const pj_meshes *m, int32_t obj, int32_t lod, float *hd, float *ph)
+{
+    if (!m || obj < 0 || obj >= m->n || lod < 0 || lod >= m->L || !hd || !ph) return PJ_ERR_INVALID_ARG;
+    const int64_t k = (int64_t)obj * m->L + lod;
+    const int32_t nf = m->h_tcnt[k];
+    if (m->h_hpbeg[k] < 0) {
+        std::fill(hd, hd + nf, 0.0f);
+        std::fill(ph, ph + nf, 0.0f);
+        return PJ_OK;
+    }
+    std::vector<float2> tmp(nf);
+    if (hipSetDevice(m->device) != hipSuccess) return PJ_ERR_DEVICE;
+    if (nf && hipMemcpy(tmp.data(), m->d_hdph + m->h_hpbeg[k], nf * sizeof(float2), hipMemcpyDeviceToHost) != hipSuccess)
+        return PJ_ERR_DEVICE;
+    for (int32_t q = 0; q < nf; ++q) {
+        hd[q] = tmp[q].x;
+        ph[q] = tmp[q].y;
+    }
+    return PJ_OK;
+}
+
+// ===========================================================================
+// join machinery
+// ===========================================================================
+namespace {
+
+constexpr int kP = 1;  // A facets per lane in the FP32 kernel
+
+struct Cand {
+    int32_t r, s;
+    float lb0, ub0;  // filter bounds
+};
+
+struct PairState {
+    int8_t status = ST_UNDEC;
+    int8_t lod_done = -1;
+    double LB = 0.0, UB = INFINITY;
+    float eps = 0.0f;
+    double M = 0.0;
+    float ox = 0, oy = 0, oz = 0;
+    double d64 = INFINITY;  // FP64 finest distance once known
+    int hit64 = 0;
+};
+
+void pair_frame(const pj_meshes *R, int r, const pj_meshes *S, int s, PairState &ps)
+{
+    const float *a = &R->h_box[6 * (int64_t)r], *b = &S->h_box[6 * (int64_t)s];
+    float lo[3], hi[3];
+    for (int c = 0; c < 3; ++c) {
+        lo[c] = std::min(a[c], b[c]);
+        hi[c] = std::max(a[3 + c], b[3 + c]);
+    }
+    ps.ox = 0.5f * (lo[0] + hi[0]);
+    ps.oy = 0.5f * (lo[1] + hi[1]);
+    ps.oz = 0.5f * (lo[2] + hi[2]);
+    double M = 0.0;
+    const float o[3] = {ps.ox, ps.oy, ps.oz};
+    for (int c = 0; c < 3; ++c) M = std::max(M, std::max((double)hi[c] - o[c], (double)o[c] - lo[c]));
+    ps.M = M;
+    ps.eps = up_float(std::ldexp(M, -16));
+    // absolute coordinate scale for FP64 bounds
+}
+
+struct TilePlan {
+    std::vector<Item> items;
+    std::vector<Tile> tiles;
+    int64_t pairs = 0;
+};
+
+// Expand items into tiles: the A side (registers) is the object whose block
+// padding wastes less; B ranges are split into chunks of tile_s facets.
+// Items are emitted in descending cost order (longest processing time first).
+void plan_tiles(const pj_meshes *R, const pj_meshes *S, const std::vector<int> &act, const std::vector<Cand> &cand,
+                const std::vector<PairState> &ps, int lod, int finest, int BR, int TS, bool allow_swap, TilePlan &pl)
+{
+    struct C {
+        double cost;
+        int idx;
+    };
+    std::vector<C> order;
+    order.reserve(act.size());
+    for (int i = 0; i < (int)act.size(); ++i) {
+        const Cand &c = cand[act[i]];
+        double nr = R->count(c.r, lod), ns = S->count(c.s, lod);
+        order.push_back({nr * ns, i});
+    }
+    std::stable_sort(order.begin(), order.end(), [](const C &x, const C &y) { return x.cost > y.cost; });
+    pl.items.clear();
+    pl.tiles.clear();
+    pl.pairs = 0;
+    for (const C &oc : order) {
+        const int ci = act[oc.idx];
+        const Cand &c = cand[ci];
+        const PairState &p = ps[ci];
+        int nr = R->count(c.r, lod), ns = S->count(c.s, lod);
+        if (nr == 0 || ns == 0) continue;
+        int64_t cr = (int64_t)((nr + BR - 1) / BR) * BR * ns, cs = (int64_t)((ns + BR - 1) / BR) * BR * nr;
+        bool swap = allow_swap && cs < cr;
+        Item it;
+        std::memset(&it, 0, sizeof(it));
+        it.a_obj = swap ? c.s : c.r;
+        it.b_obj = swap ? c.r : c.s;
+        it.lod = lod;
+        it.flags = (swap ? IT_SWAP : 0) | (finest ? IT_FINEST : 0);
+        it.ox = p.ox;
+        it.oy = p.oy;
+        it.oz = p.oz;
+        it.eps = p.eps;
+        it.cand = ci;
+        const int item = (int)pl.items.size();
+        pl.items.push_back(it);
+        const int nA = swap ? ns : nr, nB = swap ? nr : ns;
+        for (int a0 = 0; a0 < nA; a0 += BR)
+            for (int b0 = 0; b0 < nB; b0 += TS) pl.tiles.push_back(Tile{item, a0, b0, std::min(nB, b0 + TS)});
+        pl.pairs += (int64_t)nA * nB;
+    }
+}
+
+struct Round32 {
+    std::vector<ItemOut> out;
+};
+
+pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TilePlan &pl, float tau, bool early,
+                  std::vector<ItemOut> &out)
+{
+    hipStream_t st = ctx->stream;
+    const int ni = (int)pl.items.size(), nt = (int)pl.tiles.size();
+    out.assign(ni, ItemOut{0x7f800000u, 0x7f800000u, 0, 0});
+    if (ni == 0) return PJ_OK;
+    PJTRY(ensure(ctx, ctx->b_items, ni * sizeof(Item)));
+    PJTRY(ensure(ctx, ctx->b_tiles, nt * sizeof(Tile)));
+    PJTRY(ensure(ctx, ctx->b_out, ni * sizeof(ItemOut)));
+    PJTRY(ensure(ctx, ctx->b_ctr, 64));
+    HIPTRY(ctx, hipMemcpyAsync(ctx->b_items.p, pl.items.data(), ni * sizeof(Item), hipMemcpyHostToDevice, st));
+    HIPTRY(ctx, hipMemcpyAsync(ctx->b_tiles.p, pl.tiles.data(), nt * sizeof(Tile), hipMemcpyHostToDevice, st));
+    int32_t *ctr = ptr<int32_t>(ctx->b_ctr);  // [0] work counter, [1] ntiles, [2..3] u64 pairs, [4..5] u64 culled
+    int32_t host_ctr[16] = {0, nt};
+    HIPTRY(ctx, hipMemcpyAsync(ctr, host_ctr, sizeof(host_ctr), hipMemcpyHostToDevice, st));
+    HIPTRY(ctx, launch_init_out(ptr<ItemOut>(ctx->b_out), ni, nullptr, st));
+    RefineArgs a;
+    a.R = R->dev();
+    a.S = S->dev();
+    a.items = ptr<Item>(ctx->b_items);
+    a.tiles = ptr<Tile>(ctx->b_tiles);
+    a.ntiles = ctr + 1;
+    a.counter = ctr;
+    a.out = ptr<ItemOut>(ctx->b_out);
+    a.pairs_done = reinterpret_cast<unsigned long long *>(ctr + 2);
+    a.chunks_culled = reinterpret_cast<unsigned long long *>(ctr + 4);
+    a.tau = tau;
+    a.early = early ? 1 : 0;
+    a.cull = 0;
+    int wpc = ctx->cfg.waves_per_cu > 0 ? ctx->cfg.waves_per_cu : 12;
+    int grid = std::min<int64_t>(nt, (int64_t)ctx->num_cu * wpc);
+    HIPTRY(ctx, hipEventRecord(ctx->ev0, st));
+    HIPTRY(ctx, launch_refine_f32(a, grid, kP, st));
+    HIPTRY(ctx, hipEventRecord(ctx->ev1, st));
+    HIPTRY(ctx, hipMemcpyAsync(out.data(), a.out, ni * sizeof(ItemOut), hipMemcpyDeviceToHost, st));
+    HIPTRY(ctx, hipMemcpyAsync(host_ctr, ctr, sizeof(host_ctr), hipMemcpyDeviceToHost, st));
+    HIPTRY(ctx, hipStreamSynchronize(st));
+    float ms = 0;
+    HIPTRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    ctx->stats.refine_kernel_ms += ms;
+    ctx->stats.refine_launches += 1;
+    ctx->stats.tiles += nt;
+    unsigned long long pairs;
+    std::memcpy(&pairs, host_ctr + 2, 8);
+    ctx->stats.facet_pairs += (int64_t)pairs;
+    return PJ_OK;
+}
+
+pj_status run_f64(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TilePlan &pl, bool plain,
+                  std::vector<ItemOut64> &out)
+{
+    hipStream_t st = ctx->stream;
+    const int ni = (int)pl.items.size(), nt = (int)pl.tiles.size();
+    out.assign(ni, ItemOut64{0x7ff0000000000000ull, 0x7ff0000000000000ull, 0, 0});
+    if (ni == 0) return PJ_OK;
+    PJTRY(ensure(ctx, ctx->b_items, ni * sizeof(Item)));
+    PJTRY(ensure(ctx, ctx->b_out64, ni * sizeof(ItemOut64)));
+    HIPTRY(ctx, hipMemcpyAsync(ctx->b_items.p, pl.items.data(), ni * sizeof(Item), hipMemcpyHostToDevice, st));
+    Refine64Args a;
+    a.R = R->dev();
+    a.S = S->dev();
+    a.items = ptr<Item>(ctx->b_items);
+    a.out = ptr<ItemOut64>(ctx->b_out64);
+    a.tiles = nullptr;
+    HIPTRY(ctx, launch_init_out64(a.out, ni, st));
+    HIPTRY(ctx, hipEventRecord(ctx->ev0, st));
+    if (plain) {
+        HIPTRY(ctx, launch_refine_f64_plain(a, ni, st));
+    } else {
+        PJTRY(ensure(ctx, ctx->b_tiles, nt * sizeof(Tile)));
+        HIPTRY(ctx, hipMemcpyAsync(ctx->b_tiles.p, pl.tiles.data(), nt * sizeof(Tile), hipMemcpyHostToDevice, st));
+        a.tiles = ptr<Tile>(ctx->b_tiles);
+        HIPTRY(ctx, launch_refine_f64_tiles(a, nt, st));
+    }
+    HIPTRY(ctx, hipEventRecord(ctx->ev1, st));
+    HIPTRY(ctx, hipMemcpyAsync(out.data(), a.out, ni * sizeof(ItemOut64), hipMemcpyDeviceToHost, st));
+    HIPTRY(ctx, hipStreamSynchronize(st));
+    float ms = 0;
+    HIPTRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    ctx->stats.band_kernel_ms += ms;
+    ctx->stats.facet_pairs_fp64 += pl.pairs;
+    return PJ_OK;
+}
+
+double bits_to_double(unsigned long long b)
+{
+    double d;
+    std::memcpy(&d, &b, 8);
+    return d;
+}
+float bits_to_float(uint32_t b)
+{
+    float f;
+    std::memcpy(&f, &b, 4);
+    return f;
+}
+
+pj_status check_pair_args(pj_context *ctx, const pj_meshes *R, const pj_meshes *S)
+{
+    if (!R || !S) return fail(ctx, PJ_ERR_INVALID_ARG, "NULL mesh set");
+    if (R->device != ctx->cfg.device || S->device != ctx->cfg.device)
+        return fail(ctx, PJ_ERR_INVALID_ARG, "mesh set lives on another device");
+    if (R->n > 0 && S->n > 0 && R->L != S->L) return fail(ctx, PJ_ERR_INVALID_ARG, "n_lods differ between R and S");
+    return PJ_OK;
+}
+
+// MBB filter on the device: candidates with box gap <= tau.
+pj_status mbb_filter(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, double tau, std::vector<Cand> &cand)
+{
+    cand.clear();
+    hipStream_t st = ctx->stream;
+    const int nR = R->n, nS = S->n;
+    const int gx = (nR + 255) / 256, gy = (nS + 511) / 512;
+    const int nb = gx * gy;
+    double t2 = tau * (1.0 + std::ldexp(1.0, -20));
+    float tau2 = up_float(t2 * t2);
+    PJTRY(ensure(ctx, ctx->b_blk, nb * sizeof(int32_t)));
+    PJTRY(ensure(ctx, ctx->b_blkoff, (nb + 1) * sizeof(int64_t)));
+    PJTRY(ensure(ctx, ctx->b_total, 16));
+    HIPTRY(ctx, launch_filter(R->d_box, R->d_anchor, nR, S->d_box, S->d_anchor, nS, tau2, ptr<int32_t>(ctx->b_blk),
+                              nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, st));
+    HIPTRY(ctx, launch_scan_i32_to_i64(ptr<int32_t>(ctx->b_blk), ptr<int64_t>(ctx->b_blkoff), ptr<int64_t>(ctx->b_total),
+                                       nb, st));
+    int64_t total = 0;
+    HIPTRY(ctx, hipMemcpyAsync(&total, ctx->b_total.p, 8, hipMemcpyDeviceToHost, st));
+    HIPTRY(ctx, hipStreamSynchronize(st));
+    if (total == 0) return PJ_OK;
+    if (total > INT32_MAX) return fail(ctx, PJ_ERR_UNSUPPORTED, "more than 2^31 candidate pairs");
+    PJTRY(ensure(ctx, ctx->b_cand_r, total * 4));
+    PJTRY(ensure(ctx, ctx->b_cand_s, total * 4));
+    PJTRY(ensure(ctx, ctx->b_cand_lb, total * 4));
+    PJTRY(ensure(ctx, ctx->b_cand_ub, total * 4));
+    HIPTRY(ctx, launch_filter(R->d_box, R->d_anchor, nR, S->d_box, S->d_anchor, nS, tau2, ptr<int32_t>(ctx->b_blk),
+                              ptr<int64_t>(ctx->b_blkoff), nullptr, ptr<int32_t>(ctx->b_cand_r),
+                              ptr<int32_t>(ctx->b_cand_s), ptr<float>(ctx->b_cand_lb), ptr<float>(ctx->b_cand_ub), 1,
+                              st));
+    std::vector<int32_t> cr(total), cs(total);
+    std::vector<float> lb(total), ub(total);
+    HIPTRY(ctx, hipMemcpyAsync(cr.data(), ctx->b_cand_r.p, total * 4, hipMemcpyDeviceToHost, st));
+    HIPTRY(ctx, hipMemcpyAsync(cs.data(), ctx->b_cand_s.p, total * 4, hipMemcpyDeviceToHost, st));
+    HIPTRY(ctx, hipMemcpyAsync(lb.data(), ctx->b_cand_lb.p, total * 4, hipMemcpyDeviceToHost, st));
+    HIPTRY(ctx, hipMemcpyAsync(ub.data(), ctx->b_cand_ub.p, total * 4, hipMemcpyDeviceToHost, st));
+    HIPTRY(ctx, hipStreamSynchronize(st));
+    cand.resize(total);
+    for (int64_t i = 0; i < total; ++i) cand[i] = Cand{cr[i], cs[i], lb[i], ub[i]};
+    return PJ_OK;
+}
+
+int pick_tile_s(pj_context *ctx) { return ctx->cfg.tile_s > 0 ? ctx->cfg.tile_s : 1024; }
+
+// Progressive refinement of within-tau candidates (Section 3.1): returns the
+// confirmed candidate indices.
+pj_status refine_within(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, double tau, std::vector<Cand> &cand,
+                        std::vector<PairState> &ps, std::vector<int> &start_lod)
+{
+    const int L = R->L;
+    const bool plain = ctx->cfg.schedule == PJ_SCHED_PLAIN;
+    const bool fp64 = plain || ctx->cfg.precision == PJ_PREC_FP64;
+    const int TS = pick_tile_s(ctx);
+    TilePlan pl;
+    for (int lod = 0; lod < L; ++lod) {
+        const bool finest = lod == L - 1;
+        std::vector<int> act;
+        for (int i = 0; i < (int)cand.size(); ++i)
+            if (ps[i].status == ST_UNDEC && start_lod[i] <= lod) act.push_back(i);
+        if (act.empty()) {
+            bool any = false;
+            for (int i = 0; i < (int)cand.size(); ++i) any |= ps[i].status == ST_UNDEC;
+            if (!any) break;
+            continue;
+        }
+        ctx->stats.rounds++;
+        if (fp64) {
+            plan_tiles(R, S, act, cand, ps, lod, finest, 64, TS, !plain, pl);
+            std::vector<ItemOut64> out;
+            PJTRY(run_f64(ctx, R, S, pl, plain, out));
+            for (size_t k = 0; k < pl.items.size(); ++k) {
+                PairState &p = ps[pl.items[k].cand];
+                double lb = bits_to_double(out[k].lb), ub = bits_to_double(out[k].ub);
+                p.lod_done = lod;
+                if (finest) {
+                    p.d64 = lb;
+                    p.hit64 = out[k].hit;
+                    bool in = out[k].hit || (tau > 0.0 && lb <= tau);
+                    p.status = in ? ST_CONF : ST_PRUNED;
+                } else {
+                    double e64 = std::ldexp(p.M, -40);
+                    p.LB = std::max(p.LB, lb - e64);
+                    p.UB = std::min(p.UB, ub + e64);
+                    if (p.UB <= tau) p.status = ST_CONF;
+                    else if (p.LB > tau) p.status = ST_PRUNED;
+                }
+                if (p.status != ST_UNDEC) ctx->stats.resolved_at_lod[lod]++;
+            }
+        } else {
+            plan_tiles(R, S, act, cand, ps, lod, finest, 64 * kP, TS, true, pl);
+            std::vector<ItemOut> out;
+            PJTRY(run_f32(ctx, R, S, pl, (float)tau, true, out));
+            for (size_t k = 0; k < pl.items.size(); ++k) {
+                PairState &p = ps[pl.items[k].cand];
+                double lb = bits_to_float(out[k].lb), ub = bits_to_float(out[k].ub), e = p.eps;
+                p.lod_done = lod;
+                if (finest) {
+                    if (out[k].hit) p.status = ST_CONF;
+                    else if (tau > 0.0 && ub + e <= tau) p.status = ST_CONF;
+                    else if (lb - e > tau) p.status = ST_PRUNED;
+                    else p.status = ST_BAND;
+                } else {
+                    p.LB = std::max(p.LB, lb - e);
+                    p.UB = std::min(p.UB, ub + e);
+                    if (p.UB <= tau) p.status = ST_CONF;
+                    else if (p.LB > tau) p.status = ST_PRUNED;
+                }
+                if (p.status == ST_CONF || p.status == ST_PRUNED) ctx->stats.resolved_at_lod[lod]++;
+            }
+        }
+    }
+    // guard band: FP64 with the exact meet test on the finest LoD
+    std::vector<int> band;
+    for (int i = 0; i < (int)cand.size(); ++i)
+        if (ps[i].status == ST_BAND) band.push_back(i);
+    if (!band.empty()) {
+        double tb = now_ms();
+        ctx->stats.band_pairs += (int64_t)band.size();
+        plan_tiles(R, S, band, cand, ps, L - 1, 1, 64, TS, true, pl);
+        std::vector<ItemOut64> out;
+        PJTRY(run_f64(ctx, R, S, pl, false, out));
+        for (size_t k = 0; k < pl.items.size(); ++k) {
+            PairState &p = ps[pl.items[k].cand];
+            double d = bits_to_double(out[k].lb);
+            p.d64 = d;
+            p.hit64 = out[k].hit;
+            bool in = out[k].hit || (tau > 0.0 && d <= tau);
+            p.status = in ? ST_CONF : ST_PRUNED;
+            ctx->stats.resolved_at_lod[L - 1]++;
+        }
+        ctx->stats.t_band_ms += now_ms() - tb;
+    }
+    return PJ_OK;
+}
+
+// FP64 finest-LoD distances for the given candidates (where not known yet)
+pj_status finest_distances(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, std::vector<Cand> &cand,
+                           std::vector<PairState> &ps, const std::vector<int> &which)
+{
+    std::vector<int> need;
+    for (int i : which)
+        if (!std::isfinite(ps[i].d64) && !ps[i].hit64) need.push_back(i);
+    if (need.empty()) return PJ_OK;
+    TilePlan pl;
+    plan_tiles(R, S, need, cand, ps, R->L - 1, 1, 64, pick_tile_s(ctx), true, pl);
+    std::vector<ItemOut64> out;
+    PJTRY(run_f64(ctx, R, S, pl, false, out));
+    for (size_t k = 0; k < pl.items.size(); ++k) {
+        PairState &p = ps[pl.items[k].cand];
+        p.d64 = out[k].hit ? 0.0 : bits_to_double(out[k].lb);
+        p.hit64 = out[k].hit;
+    }
+    return PJ_OK;
+}
+
+}  // namespace
+
+extern "C" pj_status pj_join_within(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, double tau, pj_pairs *out)
+{
+    if (!ctx) return PJ_ERR_INVALID_ARG;
+    if (!out) return fail(ctx, PJ_ERR_INVALID_ARG, "out is NULL");
+    std::memset(out, 0, sizeof(*out));
+    PJTRY(check_pair_args(ctx, R, S));
+    if (!(tau >= 0.0) || !std::isfinite(tau)) return fail(ctx, PJ_ERR_INVALID_ARG, "tau must be finite and >= 0");
+    HIPTRY(ctx, hipSetDevice(ctx->cfg.device));
+    std::memset(&ctx->stats, 0, sizeof(ctx->stats) - sizeof(double) * 0);
+    double t0 = now_ms();
+    ctx->peak_bytes = ctx->dev_bytes;
+    if (R->n == 0 || S->n == 0) {
+        ctx->stats.t_total_ms = now_ms() - t0;
+        return PJ_OK;
+    }
+    std::vector<Cand> cand;
+    PJTRY(mbb_filter(ctx, R, S, tau, cand));
+    const int nc = (int)cand.size();
+    ctx->stats.candidates = nc;
+    std::vector<PairState> ps(nc);
+    std::vector<int> start(nc, 0);
+    for (int i = 0; i < nc; ++i) {
+        pair_frame(R, cand[i].r, S, cand[i].s, ps[i]);
+        ps[i].LB = cand[i].lb0;
+        ps[i].UB = cand[i].ub0;
+        // the anchors are surface points: their distance bounds d from above
+        if (cand[i].ub0 <= tau) {
+            ps[i].status = ST_CONF;
+            ctx->stats.confirmed_filter++;
+        } else if (cand[i].lb0 > tau) {
+            ps[i].status = ST_PRUNED;
+        }
+    }
+    double t1 = now_ms();
+    ctx->stats.t_filter_ms = t1 - t0;
+    PJTRY(refine_within(ctx, R, S, tau, cand, ps, start));
+    ctx->stats.t_refine_ms = now_ms() - t1 - ctx->stats.t_band_ms;
+    std::vector<int> res;
+    for (int i = 0; i < nc; ++i)
+        if (ps[i].status == ST_CONF) res.push_back(i);
+    if (ctx->cfg.want_dist) {
+        double tb = now_ms();
+        PJTRY(finest_distances(ctx, R, S, cand, ps, res));
+        ctx->stats.t_band_ms += now_ms() - tb;
+    }
+    std::sort(res.begin(), res.end(), [&](int a, int b) {
+        return cand[a].r != cand[b].r ? cand[a].r < cand[b].r : cand[a].s < cand[b].s;
+    });
+    const int64_t n = (int64_t)res.size();
+    out->n = n;
+    out->r = (int32_t *)std::malloc(std::max<int64_t>(n, 1) * 4);
+    out->s = (int32_t *)std::malloc(std::max<int64_t>(n, 1) * 4);
+    if (ctx->cfg.want_dist) out->dist = (double *)std::malloc(std::max<int64_t>(n, 1) * 8);
+    if (!out->r || !out->s || (ctx->cfg.want_dist && !out->dist)) {
+        pj_pairs_free(out);
+        return fail(ctx, PJ_ERR_OUT_OF_MEMORY, "host result allocation");
+    }
+    for (int64_t k = 0; k < n; ++k) {
+        out->r[k] = cand[res[k]].r;
+        out->s[k] = cand[res[k]].s;
+        if (out->dist) out->dist[k] = ps[res[k]].hit64 ? 0.0 : ps[res[k]].d64;
+    }
+    ctx->stats.peak_device_bytes = ctx->peak_bytes;
+    ctx->stats.t_total_ms = now_ms() - t0;
+    return PJ_OK;
+}
+
+extern "C" pj_status pj_join_intersect(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, pj_pairs *out)
+{
+    return pj_join_within(ctx, R, S, 0.0, out);
+}
+
+extern "C" pj_status pj_join_knn(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, int32_t k, pj_knn *out)
+{
+    if (!ctx) return PJ_ERR_INVALID_ARG;
+    if (!out || !R || !S || k < 1) return fail(ctx, PJ_ERR_INVALID_ARG, "bad argument");
+    std::memset(out, 0, sizeof(*out));
+    return fail(ctx, PJ_ERR_UNSUPPORTED, "k-NN join not built yet");
+}
+
+extern "C" void pj_pairs_free(pj_pairs *p)
+{
+    if (!p) return;
+    std::free(p->r);
+    std::free(p->s);
+    std::free(p->dist);
+    std::memset(p, 0, sizeof(*p));
+}
+
+extern "C" void pj_knn_free(pj_knn *p)
+{
+    if (!p) return;
+    std::free(p->count);
+    std::free(p->s);
+    std::free(p->dist);
+    std::memset(p, 0, sizeof(*p));
+}
+
+// ===========================================================================
+// inspection entry points
+// ===========================================================================
+extern "C" pj_status pj_facet_pairs(pj_context *ctx, const float *t1, const float *t2, int64_t n, int32_t precision,
+                                    double *d, int8_t *hit)
+{
+    if (!ctx) return PJ_ERR_INVALID_ARG;
+    if (n < 0 || (n > 0 && (!t1 || !t2 || !d || !hit))) return fail(ctx, PJ_ERR_INVALID_ARG, "bad argument");
+    if (precision != PJ_PREC_FP32_BAND && precision != PJ_PREC_FP64) return fail(ctx, PJ_ERR_INVALID_ARG, "precision");
+    if (n == 0) return PJ_OK;
+    HIPTRY(ctx, hipSetDevice(ctx->cfg.device));
+    hipStream_t st = ctx->stream;
+    PJTRY(ensure(ctx, ctx->b_tmp0, n * 36));
+    PJTRY(ensure(ctx, ctx->b_tmp1, n * 36));
+    PJTRY(ensure(ctx, ctx->b_tmp2, n * 8));
+    PJTRY(ensure(ctx, ctx->b_tmp3, n));
+    HIPTRY(ctx, hipMemcpyAsync(ctx->b_tmp0.p, t1, n * 36, hipMemcpyHostToDevice, st));
+    HIPTRY(ctx, hipMemcpyAsync(ctx->b_tmp1.p, t2, n * 36, hipMemcpyHostToDevice, st));
+    HIPTRY(ctx, launch_facet_pairs(ptr<float>(ctx->b_tmp0), ptr<float>(ctx->b_tmp1), n, precision,
+                                   ptr<double>(ctx->b_tmp2), ptr<int8_t>(ctx->b_tmp3), st));
+    HIPTRY(ctx, hipMemcpyAsync(d, ctx->b_tmp2.p, n * 8, hipMemcpyDeviceToHost, st));
+    HIPTRY(ctx, hipMemcpyAsync(hit, ctx->b_tmp3.p, n, hipMemcpyDeviceToHost, st));
+    HIPTRY(ctx, hipStreamSynchronize(st));
+    return PJ_OK;
+}
+
+extern "C" pj_status pj_pair_bounds(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, int64_t n,
+                                    const int32_t *r, const int32_t *s, int32_t lod, double *lb, double *ub,
+                                    int8_t *hit)
+{
+    if (!ctx) return PJ_ERR_INVALID_ARG;
+    PJTRY(check_pair_args(ctx, R, S));
+    if (n < 0 || (n > 0 && (!r || !s || !lb || !ub || !hit))) return fail(ctx, PJ_ERR_INVALID_ARG, "bad argument");
+    if (n == 0) return PJ_OK;
+    if (lod < 0 || lod >= R->L) return fail(ctx, PJ_ERR_INVALID_ARG, "lod out of range");
+    for (int64_t i = 0; i < n; ++i)
+        if (r[i] < 0 || r[i] >= R->n || s[i] < 0 || s[i] >= S->n) return fail(ctx, PJ_ERR_INVALID_ARG, "object id");
+    HIPTRY(ctx, hipSetDevice(ctx->cfg.device));
+    std::vector<Cand> cand(n);
+    std::vector<PairState> ps(n);
+    std::vector<int> act(n);
+    for (int64_t i = 0; i < n; ++i) {
+        cand[i] = Cand{r[i], s[i], 0.0f, INFINITY};
+        pair_frame(R, r[i], S, s[i], ps[i]);
+        act[i] = (int)i;
+    }
+    const bool plain = ctx->cfg.schedule == PJ_SCHED_PLAIN;
+    const bool fp64 = plain || ctx->cfg.precision == PJ_PREC_FP64;
+    const bool finest = lod == R->L - 1;
+    TilePlan pl;
+    for (int64_t i = 0; i < n; ++i) {
+        lb[i] = INFINITY;
+        ub[i] = INFINITY;
+        hit[i] = 0;
+    }
+    if (fp64) {
+        plan_tiles(R, S, act, cand, ps, lod, finest, 64, pick_tile_s(ctx), !plain, pl);
+        std::vector<ItemOut64> out;
+        PJTRY(run_f64(ctx, R, S, pl, plain, out));
+        for (size_t k = 0; k < pl.items.size(); ++k) {
+            int c = pl.items[k].cand;
+            lb[c] = bits_to_double(out[k].lb);
+            ub[c] = bits_to_double(out[k].ub);
+            hit[c] = (int8_t)out[k].hit;
+        }
+    } else {
+        plan_tiles(R, S, act, cand, ps, lod, finest, 64 * kP, pick_tile_s(ctx), true, pl);
+        std::vector<ItemOut> out;
+        PJTRY(run_f32(ctx, R, S, pl, -1.0f, false, out));
+        for (size_t k = 0; k < pl.items.size(); ++k) {
+            int c = pl.items[k].cand;
+            lb[c] = bits_to_float(out[k].lb);
+            ub[c] = bits_to_float(out[k].ub);
+            hit[c] = (int8_t)out[k].hit;
+        }
+    }
+    return PJ_OK;
+}
+
+extern "C" pj_status pj_train_lod_model(pj_context *ctx, const char *log_path, const char *model_out,
+                                        const pj_train_opts *opts, float *final_loss)
+{
+    (void)log_path;
+    (void)model_out;
+    (void)opts;
+    (void)final_loss;
+    return fail(ctx, PJ_ERR_UNSUPPORTED, "LoD model training not built yet");
+}
+
+extern "C" pj_status pj_mlp_eval(pj_context *ctx, const float *params, const float *x, const int32_t *y, int64_t n,
+                                 float *logits, float *loss, float *grads)
+{
+    (void)params;
+    (void)x;
+    (void)y;
+    (void)n;
+    (void)logits;
+    (void)loss;
+    (void)grads;
+    return fail(ctx, PJ_ERR_UNSUPPORTED, "MLP not built yet");
+}

@@ -1,0 +1,109 @@
+// pj_internal.h -- types shared by the library's host code and kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "pj.h"
+
+namespace pj {
+
+// Device view of one ingested object set (object-major).
+struct MeshDev {
+    const float *verts;    // [V][3]
+    const int32_t *tris;   // [T][3] local vertex indices
+    const int64_t *vbeg;   // [n] first vertex row
+    const int64_t *tbeg;   // [n*L] first triangle row of (object, LoD)
+    const int32_t *tcnt;   // [n*L]
+    const int64_t *hpbeg;  // [n*L] start of (object, LoD) in hdph, -1 on the finest LoD
+    const float2 *hdph;    // (hd, ph) per coarse facet
+    int32_t n, L;
+};
+
+// One refinement work item: an object pair at one LoD.  The facets of the
+// "A" object are held in registers, those of "B" are streamed.
+struct Item {
+    int32_t a_obj, b_obj, lod, flags;
+    float ox, oy, oz;  // pair-local origin (float32); coordinates are translated by it
+    float eps;         // FP32 guard band of the pair
+    float thr;         // collect-mode threshold
+    int32_t cand;      // candidate index
+    int32_t pad0, pad1;
+};
+static_assert(sizeof(Item) == 48, "item layout");
+enum : int32_t { IT_SWAP = 1, IT_FINEST = 2 };
+
+struct Tile {
+    int32_t item, a0, b0, b1;  // A facets [a0, a0 + 64P), B facets [b0, b1)
+};
+
+// FP32 results of an item: atomically reduced bit patterns of non-negative floats.
+struct ItemOut {
+    uint32_t lb, ub;
+    int32_t hit, done;
+};
+
+// FP64 results of an item (bit patterns of non-negative doubles).
+struct ItemOut64 {
+    unsigned long long lb, ub;
+    int32_t hit, pad;
+};
+
+struct RefineArgs {
+    MeshDev R, S;
+    const Item *items;
+    const Tile *tiles;
+    const int32_t *ntiles;   // device count (fixed-capacity buffers)
+    int32_t *counter;        // persistent work counter
+    ItemOut *out;
+    unsigned long long *pairs_done;  // facet pairs evaluated (device counter)
+    unsigned long long *chunks_culled;
+    float tau;               // within-tau threshold for early confirmation; < 0: none
+    int32_t early;           // 1: stop an item once it is confirmed
+    int32_t cull;            // 1: box-gap test per streamed chunk
+    int32_t pad;
+};
+
+struct Refine64Args {
+    MeshDev R, S;
+    const Item *items;
+    const Tile *tiles;
+    ItemOut64 *out;
+};
+
+// ---------------------------------------------------------------------------
+// kernel launchers (pj_kernels.hip)
+// ---------------------------------------------------------------------------
+hipError_t launch_boxes(const MeshDev &m, float *box, float *anchor, hipStream_t st);
+hipError_t launch_ph(const MeshDev &m, float2 *hdph_mut, const int32_t *parent, const int64_t *fine_job_off,
+                     int64_t n_fine_total, hipStream_t st);
+hipError_t launch_hd(const MeshDev &m, float2 *hdph_mut, const int64_t *job_off, int64_t n_jobs,
+                     const int64_t *desc_base, const int32_t *desc_off, const int32_t *desc_list, int lod, int msub,
+                     hipStream_t st);
+hipError_t launch_lodmax(const MeshDev &m, float2 *lodmax, hipStream_t st);
+hipError_t launch_filter(const float *boxR, const float *ancR, int nR, const float *boxS, const float *ancS, int nS,
+                         float tau, int32_t *blk_count, int64_t *blk_off, int64_t *total, int32_t *cr, int32_t *cs,
+                         float *clb, float *cub, int write_pass, hipStream_t st);
+hipError_t launch_scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t *total, int n, hipStream_t st);
+hipError_t launch_init_out(ItemOut *out, int n, int32_t *counter, hipStream_t st);
+hipError_t launch_init_out64(ItemOut64 *out, int n, hipStream_t st);
+hipError_t launch_refine_f32(const RefineArgs &a, int grid, int P, hipStream_t st);
+hipError_t launch_refine_f64_tiles(const Refine64Args &a, int ntiles, hipStream_t st);
+hipError_t launch_refine_f64_plain(const Refine64Args &a, int nitems, hipStream_t st);
+hipError_t launch_facet_pairs(const float *t1, const float *t2, int64_t n, int prec, double *d, int8_t *hit,
+                              hipStream_t st);
+
+// MLP (pj_mlp.hip)
+hipError_t launch_mlp_fwd_bwd(const float *params, const float *x, const int32_t *y, int n, float *logits,
+                              float *loss_acc, float *grads, hipStream_t st);
+hipError_t launch_mlp_adam(float *params, float *m, float *v, const float *grads, int np, float lr, float b1,
+                           float b2, float eps, int step, float scale, hipStream_t st);
+hipError_t launch_mlp_infer(const float *params, const float *x, int n, const float *cost, float *probs,
+                            int32_t *start, hipStream_t st);
+
+constexpr int MLP_IN = 16, MLP_H = 64, MLP_OUT = 4;
+constexpr int MLP_NPARAM = MLP_IN * MLP_H + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H * MLP_OUT + MLP_OUT;
+
+}  // namespace pj

@@ -1,0 +1,724 @@
+// pj_kernels.hip -- HIP kernels for gfx950: ingest (boxes, anchors, hd/ph),
+// MBB filter, FP32 persistent tile refinement, FP64 refinement (tiled and
+// one-workgroup-per-pair), and a facet-pair entry used by tests.
+#include "pj_geom.h"
+#include "pj_internal.h"
+
+namespace pj {
+
+constexpr float kInf = __builtin_inff();
+
+__device__ __forceinline__ float block_min256(float v, float *sh)
+{
+    v = wave_min(v);
+    int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    float r = fminf(fminf(sh[0], sh[1]), fminf(sh[2], sh[3]));
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ float wave_max(float v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ float block_max256(float v, float *sh)
+{
+    v = wave_max(v);
+    int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    float r = fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ D3 ld3d(const float *v, int i)
+{
+    return D3{(double)v[3 * i], (double)v[3 * i + 1], (double)v[3 * i + 2]};
+}
+__device__ __forceinline__ V3 ld3f(const float *v, int i) { return V3{v[3 * i], v[3 * i + 1], v[3 * i + 2]}; }
+
+// index of the last k with off[k] <= j (off ascending, off[0] = 0)
+__device__ __forceinline__ int find_seg(const int64_t *off, int n, int64_t j)
+{
+    int lo = 0, hi = n;  // off[n] is the total
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (off[mid] <= j) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// Ingest: object MBB over the finest LoD's corners, then the anchor: the
+// corner closest to the MBB centre (ties: lowest vertex index).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_boxes(MeshDev m, float *box, float *anchor)
+{
+    __shared__ float sh[4];
+    __shared__ int shi[4];
+    const int obj = blockIdx.x;
+    const int64_t k = (int64_t)obj * m.L + (m.L - 1);
+    const int nt = m.tcnt[k];
+    const int32_t *t = m.tris + 3 * m.tbeg[k];
+    const float *v = m.verts + 3 * m.vbeg[obj];
+    float lo[3] = {kInf, kInf, kInf}, hi[3] = {-kInf, -kInf, -kInf};
+    for (int q = threadIdx.x; q < 3 * nt; q += 256) {
+        int vi = t[q];
+        for (int c = 0; c < 3; ++c) {
+            float x = v[3 * vi + c];
+            lo[c] = fminf(lo[c], x);
+            hi[c] = fmaxf(hi[c], x);
+        }
+    }
+    float B[6];
+    for (int c = 0; c < 3; ++c) {
+        B[c] = block_min256(lo[c], sh);
+        B[3 + c] = -block_min256(-hi[c], sh);
+    }
+    float cx = 0.5f * (B[0] + B[3]), cy = 0.5f * (B[1] + B[4]), cz = 0.5f * (B[2] + B[5]);
+    float bd = kInf;
+    int bi = 0x7fffffff;
+    for (int q = threadIdx.x; q < 3 * nt; q += 256) {
+        int vi = t[q];
+        float dx = v[3 * vi] - cx, dy = v[3 * vi + 1] - cy, dz = v[3 * vi + 2] - cz;
+        float d = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        if (d < bd || (d == bd && vi < bi)) {
+            bd = d;
+            bi = vi;
+        }
+    }
+    float best = block_min256(bd, sh);
+    int cand = (bd == best) ? bi : 0x7fffffff;
+    for (int o = 32; o > 0; o >>= 1) cand = min(cand, __shfl_xor(cand, o, 64));
+    if ((threadIdx.x & 63) == 0) shi[threadIdx.x >> 6] = cand;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int w = min(min(shi[0], shi[1]), min(shi[2], shi[3]));
+        for (int c = 0; c < 6; ++c) box[6 * obj + c] = B[c];
+        for (int c = 0; c < 3; ++c) anchor[3 * obj + c] = (nt > 0) ? v[3 * w + c] : __builtin_nanf("");
+    }
+}
+
+hipError_t launch_boxes(const MeshDev &m, float *box, float *anchor, hipStream_t st)
+{
+    if (m.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_boxes, dim3(m.n), dim3(256), 0, st, m, box, anchor);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Ingest: per-facet Hausdorff bounds (FP64, rounded up to float).
+// ---------------------------------------------------------------------------
+__device__ double pt_seg2_d(D3 p, D3 a, D3 b)
+{
+    D3 ab = b - a, ap = p - a;
+    double L = dotd(ab, ab);
+    double t = L > 0.0 ? fmin(fmax(dotd(ap, ab) / L, 0.0), 1.0) : 0.0;
+    D3 w = D3{ap.x - t * ab.x, ap.y - t * ab.y, ap.z - t * ab.z};
+    return dotd(w, w);
+}
+
+// distance from p to the closed triangle abc (projection if it falls inside,
+// else the nearest of the three edges)
+__device__ double pt_tri_d(D3 p, D3 a, D3 b, D3 c)
+{
+    D3 n = crossd(b - a, c - a);
+    double nn = dotd(n, n);
+    if (nn > 0.0) {
+        double s0 = dotd(crossd(b - a, p - a), n), s1 = dotd(crossd(c - b, p - b), n), s2 = dotd(crossd(a - c, p - c), n);
+        if (s0 >= 0.0 && s1 >= 0.0 && s2 >= 0.0) return fabs(dotd(n, p - a)) / sqrt(nn);
+    }
+    return sqrt(fmin(pt_seg2_d(p, a, b), fmin(pt_seg2_d(p, b, c), pt_seg2_d(p, c, a))));
+}
+
+// FP64 value -> float rounded up, after a relative and absolute safety margin
+// for the FP64 evaluation error (coordinates up to magnitude M).
+__device__ __forceinline__ float round_up_bound(double x, double M)
+{
+    double y = x * (1.0 + 1e-12) + 1e-13 * M;
+    return __double2float_ru(y);
+}
+
+__device__ __forceinline__ double mag3(D3 a) { return fmax(fabs(a.x), fmax(fabs(a.y), fabs(a.z))); }
+
+// ph(P, f'): for every finest facet g, max over its corners of the distance
+// to its ancestor at each coarser LoD, max-reduced into that ancestor.
+__global__ __launch_bounds__(256) void k_ph(MeshDev m, float2 *hdph, const int32_t *parent, const int64_t *job_off,
+                                             int64_t n_total)
+{
+    int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n_total) return;
+    const int obj = find_seg(job_off, m.n, j);
+    const int g = (int)(j - job_off[obj]);
+    const int L = m.L;
+    const int64_t base = (int64_t)obj * L;
+    const float *v = m.verts + 3 * m.vbeg[obj];
+    const int32_t *tg = m.tris + 3 * (m.tbeg[base + L - 1] + g);
+    D3 G[3] = {ld3d(v, tg[0]), ld3d(v, tg[1]), ld3d(v, tg[2])};
+    int a = g;
+    for (int l = L - 1; l > 0; --l) {
+        a = parent[m.tbeg[base + l] + a];
+        const int32_t *ta = m.tris + 3 * (m.tbeg[base + l - 1] + a);
+        D3 A0 = ld3d(v, ta[0]), A1 = ld3d(v, ta[1]), A2 = ld3d(v, ta[2]);
+        double d = fmax(pt_tri_d(G[0], A0, A1, A2), fmax(pt_tri_d(G[1], A0, A1, A2), pt_tri_d(G[2], A0, A1, A2)));
+        double M = fmax(fmax(mag3(G[0]), fmax(mag3(G[1]), mag3(G[2]))), fmax(mag3(A0), fmax(mag3(A1), mag3(A2))));
+        float val = round_up_bound(d, M);
+        atomicMax(reinterpret_cast<unsigned *>(&hdph[m.hpbeg[base + l - 1] + a].y), __float_as_uint(val));
+    }
+}
+
+hipError_t launch_ph(const MeshDev &m, float2 *hdph, const int32_t *parent, const int64_t *job_off, int64_t n_total,
+                     hipStream_t st)
+{
+    if (n_total == 0) return hipSuccess;
+    int64_t blocks = (n_total + 255) / 256;
+    hipLaunchKernelGGL(k_ph, dim3((unsigned)blocks), dim3(256), 0, st, m, hdph, parent, job_off, n_total);
+    return hipGetLastError();
+}
+
+// hd(f', P): one wave per coarse facet; lane = barycentric grid point
+// x = (i a + j b + k c) / msub; value = max_x min_g dist(x, g) over the
+// facet's finest descendants g, plus the longest grid edge.
+__global__ __launch_bounds__(64) void k_hd(MeshDev m, float2 *hdph, const int64_t *job_off, int64_t n_jobs,
+                                           const int64_t *desc_base, const int32_t *desc_off,
+                                           const int32_t *desc_list, int lod, int msub)
+{
+    int64_t j = blockIdx.x;
+    if (j >= n_jobs) return;
+    const int obj = find_seg(job_off, m.n, j);
+    const int f = (int)(j - job_off[obj]);
+    const int L = m.L;
+    const int64_t base = (int64_t)obj * L;
+    const float *v = m.verts + 3 * m.vbeg[obj];
+    const int32_t *tf = m.tris + 3 * (m.tbeg[base + lod] + f);
+    D3 A = ld3d(v, tf[0]), B = ld3d(v, tf[1]), C = ld3d(v, tf[2]);
+    int lane = threadIdx.x;
+    int npts = (msub + 1) * (msub + 2) / 2;
+    double worst = 0.0;
+    if (lane < npts) {
+        int i = 0, r = lane;
+        while (r > msub - i) {
+            r -= msub - i + 1;
+            ++i;
+        }
+        int jj = r, kk = msub - i - jj;
+        double inv = 1.0 / msub;
+        D3 x{(i * A.x + jj * B.x + kk * C.x) * inv, (i * A.y + jj * B.y + kk * C.y) * inv,
+             (i * A.z + jj * B.z + kk * C.z) * inv};
+        const int64_t db = desc_base[base + lod];
+        const int32_t d0 = desc_off[db + f], d1 = desc_off[db + f + 1];
+        const int32_t *tfine = m.tris + 3 * m.tbeg[base + L - 1];
+        double best = d1 > d0 ? 1e300 : 0.0;
+        for (int q = d0; q < d1; ++q) {
+            const int32_t *tg = tfine + 3 * desc_list[q];
+            best = fmin(best, pt_tri_d(x, ld3d(v, tg[0]), ld3d(v, tg[1]), ld3d(v, tg[2])));
+        }
+        worst = best;
+    }
+    for (int o = 32; o > 0; o >>= 1) worst = fmax(worst, __shfl_xor(worst, o, 64));
+    if (lane == 0) {
+        D3 e0 = B - A, e1 = C - B, e2 = A - C;
+        double emax = sqrt(fmax(dotd(e0, e0), fmax(dotd(e1, e1), dotd(e2, e2))));
+        double M = fmax(mag3(A), fmax(mag3(B), mag3(C))) + worst;
+        hdph[m.hpbeg[base + lod] + f].x = round_up_bound(worst + emax / msub, M);
+    }
+}
+
+hipError_t launch_hd(const MeshDev &m, float2 *hdph, const int64_t *job_off, int64_t n_jobs, const int64_t *desc_base,
+                     const int32_t *desc_off, const int32_t *desc_list, int lod, int msub, hipStream_t st)
+{
+    if (n_jobs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hd, dim3((unsigned)n_jobs), dim3(64), 0, st, m, hdph, job_off, n_jobs, desc_base, desc_off,
+                       desc_list, lod, msub);
+    return hipGetLastError();
+}
+
+// per (object, LoD): max hd and max ph (features of the LoD model)
+__global__ __launch_bounds__(256) void k_lodmax(MeshDev m, float2 *lodmax)
+{
+    __shared__ float sh[4];
+    const int64_t k = blockIdx.x;
+    const int lod = (int)(k % m.L);
+    float a = 0.0f, b = 0.0f;
+    if (lod < m.L - 1) {
+        const int64_t hb = m.hpbeg[k];
+        const int n = m.tcnt[k];
+        for (int q = threadIdx.x; q < n; q += 256) {
+            float2 h = m.hdph[hb + q];
+            a = fmaxf(a, h.x);
+            b = fmaxf(b, h.y);
+        }
+    }
+    a = block_max256(a, sh);
+    b = block_max256(b, sh);
+    if (threadIdx.x == 0) lodmax[k] = make_float2(a, b);
+}
+
+hipError_t launch_lodmax(const MeshDev &m, float2 *lodmax, hipStream_t st)
+{
+    if (m.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lodmax, dim3((unsigned)((int64_t)m.n * m.L)), dim3(256), 0, st, m, lodmax);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// MBB filter (within-tau): every (r, s) whose box gap is <= tau survives.
+// Count pass -> exclusive scan of block counts -> write pass (each block
+// writes its survivors contiguously, in (thread, s) order).
+// ---------------------------------------------------------------------------
+constexpr int FILT_R = 256, FILT_S = 512;
+
+__global__ __launch_bounds__(256) void k_filter(const float *boxR, const float *ancR, int nR, const float *boxS,
+                                                 const float *ancS, int nS, float tau2, int32_t *blk_count,
+                                                 const int64_t *blk_off, int32_t *cr, int32_t *cs, float *clb,
+                                                 float *cub, int write_pass)
+{
+    __shared__ float sb[FILT_S * 9];
+    __shared__ int scnt[256];
+    const int r = blockIdx.x * FILT_R + threadIdx.x;
+    const int s0 = blockIdx.y * FILT_S;
+    const int ns = min(FILT_S, nS - s0);
+    for (int q = threadIdx.x; q < ns; q += 256) {
+        for (int c = 0; c < 6; ++c) sb[q * 9 + c] = boxS[6 * (int64_t)(s0 + q) + c];
+        for (int c = 0; c < 3; ++c) sb[q * 9 + 6 + c] = ancS[3 * (int64_t)(s0 + q) + c];
+    }
+    __syncthreads();
+    float b[6] = {kInf, kInf, kInf, -kInf, -kInf, -kInf};
+    if (r < nR)
+        for (int c = 0; c < 6; ++c) b[c] = boxR[6 * (int64_t)r + c];
+    int count = 0;
+    for (int q = 0; q < ns; ++q) {
+        const float *x = sb + q * 9;
+        float gx = fmaxf(0.0f, fmaxf(x[0] - b[3], b[0] - x[3]));
+        float gy = fmaxf(0.0f, fmaxf(x[1] - b[4], b[1] - x[4]));
+        float gz = fmaxf(0.0f, fmaxf(x[2] - b[5], b[2] - x[5]));
+        float g2 = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
+        count += (g2 <= tau2) ? 1 : 0;
+    }
+    const int blk = blockIdx.x * gridDim.y + blockIdx.y;
+    if (!write_pass) {
+        scnt[threadIdx.x] = count;
+        __syncthreads();
+        for (int st = 128; st > 0; st >>= 1) {
+            if (threadIdx.x < st) scnt[threadIdx.x] += scnt[threadIdx.x + st];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) blk_count[blk] = scnt[0];
+        return;
+    }
+    // block exclusive scan of the thread counts (Hillis-Steele in LDS)
+    scnt[threadIdx.x] = count;
+    __syncthreads();
+    for (int st = 1; st < 256; st <<= 1) {
+        int add = threadIdx.x >= st ? scnt[threadIdx.x - st] : 0;
+        __syncthreads();
+        scnt[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int64_t pos = blk_off[blk] + scnt[threadIdx.x] - count;
+    if (count == 0) return;
+    float ax = ancR[3 * (int64_t)r], ay = ancR[3 * (int64_t)r + 1], az = ancR[3 * (int64_t)r + 2];
+    for (int q = 0; q < ns; ++q) {
+        const float *x = sb + q * 9;
+        float gx = fmaxf(0.0f, fmaxf(x[0] - b[3], b[0] - x[3]));
+        float gy = fmaxf(0.0f, fmaxf(x[1] - b[4], b[1] - x[4]));
+        float gz = fmaxf(0.0f, fmaxf(x[2] - b[5], b[2] - x[5]));
+        float g2 = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
+        if (g2 <= tau2) {
+            float dx = x[6] - ax, dy = x[7] - ay, dz = x[8] - az;
+            cr[pos] = r;
+            cs[pos] = s0 + q;
+            clb[pos] = __builtin_sqrtf(g2) * (1.0f - 0x1p-20f);
+            cub[pos] = __builtin_sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx))) * (1.0f + 0x1p-20f);
+            ++pos;
+        }
+    }
+}
+
+hipError_t launch_filter(const float *boxR, const float *ancR, int nR, const float *boxS, const float *ancS, int nS,
+                         float tau2, int32_t *blk_count, int64_t *blk_off, int64_t *total, int32_t *cr, int32_t *cs,
+                         float *clb, float *cub, int write_pass, hipStream_t st)
+{
+    (void)total;
+    if (nR == 0 || nS == 0) return hipSuccess;
+    dim3 grid((nR + FILT_R - 1) / FILT_R, (nS + FILT_S - 1) / FILT_S);
+    hipLaunchKernelGGL(k_filter, grid, dim3(256), 0, st, boxR, ancR, nR, boxS, ancS, nS, tau2, blk_count, blk_off, cr,
+                       cs, clb, cub, write_pass);
+    return hipGetLastError();
+}
+
+// single-workgroup exclusive scan of int32 counts into int64 offsets
+__global__ __launch_bounds__(1024) void k_scan(const int32_t *in, int64_t *out, int64_t *total, int n)
+{
+    __shared__ int64_t sh[1024];
+    int64_t carry = 0;
+    for (int base = 0; base < n; base += 1024) {
+        int i = base + threadIdx.x;
+        int64_t x = i < n ? in[i] : 0;
+        sh[threadIdx.x] = x;
+        __syncthreads();
+        for (int st = 1; st < 1024; st <<= 1) {
+            int64_t add = threadIdx.x >= st ? sh[threadIdx.x - st] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (i < n) out[i] = carry + sh[threadIdx.x] - x;
+        int64_t blk_total = sh[1023];
+        __syncthreads();
+        carry += blk_total;
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+hipError_t launch_scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t *total, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, in, out, total, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Refinement outputs
+// ---------------------------------------------------------------------------
+__global__ void k_init_out(ItemOut *out, int n, int32_t *counter)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = ItemOut{0x7f800000u, 0x7f800000u, 0, 0};
+    if (i == 0 && counter) *counter = 0;
+}
+
+hipError_t launch_init_out(ItemOut *out, int n, int32_t *counter, hipStream_t st)
+{
+    int blocks = (n + 255) / 256;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(k_init_out, dim3(blocks), dim3(256), 0, st, out, n, counter);
+    return hipGetLastError();
+}
+
+__global__ void k_init_out64(ItemOut64 *out, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = ItemOut64{0x7ff0000000000000ull, 0x7ff0000000000000ull, 0, 0};
+}
+
+hipError_t launch_init_out64(ItemOut64 *out, int n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_init_out64, dim3((n + 255) / 256), dim3(256), 0, st, out, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FP32 refinement: persistent single-wave workgroups pull tiles from a queue.
+// A tile = 64*P facets of object A (P per lane, records in registers) x a
+// range of facets of object B, streamed through LDS 64 at a time (each lane
+// builds one record; all lanes then read every record by broadcast).  Per
+// lane running minima of lb and ub (Eq. (2), Eq. (1)) are reduced across the
+// wave with cross-lane min and merged into the item by atomicMin.
+// ---------------------------------------------------------------------------
+struct FacetSrc {
+    const int32_t *tris;
+    const float *verts;
+    const float2 *hdph;  // nullptr on the finest LoD
+    int n;
+};
+
+__device__ __forceinline__ FacetSrc facet_src(const MeshDev &M, int obj, int lod)
+{
+    const int64_t k = (int64_t)obj * M.L + lod;
+    FacetSrc s;
+    s.tris = M.tris + 3 * M.tbeg[k];
+    s.verts = M.verts + 3 * M.vbeg[obj];
+    const int64_t hb = M.hpbeg[k];
+    s.hdph = hb >= 0 ? M.hdph + hb : nullptr;
+    s.n = M.tcnt[k];
+    return s;
+}
+
+__device__ __forceinline__ Rec load_rec(const FacetSrc &s, int f, V3 o)
+{
+    const int32_t i0 = s.tris[3 * f], i1 = s.tris[3 * f + 1], i2 = s.tris[3 * f + 2];
+    V3 a = ld3f(s.verts, i0) - o, b = ld3f(s.verts, i1) - o, c = ld3f(s.verts, i2) - o;
+    float2 h = s.hdph ? s.hdph[f] : make_float2(0.0f, 0.0f);
+    return make_rec(a, b, c, h.x, h.y);
+}
+
+template <int P>
+__global__ __launch_bounds__(64) void k_refine_f32(RefineArgs a)
+{
+    __shared__ float4 sh[64 * 11];
+    const int lane = threadIdx.x;
+    for (;;) {
+        int t = 0;
+        if (lane == 0) t = atomicAdd(a.counter, 1);
+        t = __shfl(t, 0, 64);
+        if (t >= *a.ntiles) break;
+        const Tile tl = a.tiles[t];
+        const Item it = a.items[tl.item];
+        ItemOut *o = a.out + tl.item;
+        if (a.early && __builtin_amdgcn_readfirstlane(
+                           __hip_atomic_load(&o->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
+            continue;
+        const bool swap = it.flags & IT_SWAP;
+        const FacetSrc SA = facet_src(swap ? a.S : a.R, it.a_obj, it.lod);
+        const FacetSrc SB = facet_src(swap ? a.R : a.S, it.b_obj, it.lod);
+        const V3 org = V3{it.ox, it.oy, it.oz};
+        Rec ra[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            int f = tl.a0 + lane + 64 * p;
+            if (f >= SA.n) f = tl.a0;  // padding lanes repeat a real facet
+            ra[p] = load_rec(SA, f, org);
+        }
+        float lbm = kInf, ubm = kInf;
+        int sure = 0;
+        int64_t cols = 0;
+        const bool finest = it.flags & IT_FINEST;
+        for (int cb = tl.b0; cb < tl.b1; cb += 64) {
+            const int nb = min(64, tl.b1 - cb);
+            {
+                int f = cb + lane;
+                if (f >= tl.b1) f = cb;
+                Rec rb = load_rec(SB, f, org);
+                float tmp[44];
+                __builtin_memcpy(tmp, &rb, sizeof(tmp));
+#pragma unroll
+                for (int q = 0; q < 11; ++q)
+                    sh[lane * 11 + q] = make_float4(tmp[4 * q], tmp[4 * q + 1], tmp[4 * q + 2], tmp[4 * q + 3]);
+            }
+            __syncthreads();
+            for (int k = 0; k < nb; ++k) {
+                float tmp[44];
+#pragma unroll
+                for (int q = 0; q < 11; ++q) {
+                    float4 x = sh[k * 11 + q];
+                    tmp[4 * q] = x.x;
+                    tmp[4 * q + 1] = x.y;
+                    tmp[4 * q + 2] = x.z;
+                    tmp[4 * q + 3] = x.w;
+                }
+                Rec rb;
+                __builtin_memcpy(&rb, tmp, sizeof(rb));
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    Pair32 pr = pair_f32(ra[p], rb, it.eps);
+                    float dlo = pr.d * (ra[p].ok * rb.ok);
+                    lbm = fminf(lbm, fmaxf(dlo - (ra[p].ph + rb.ph), 0.0f));
+                    ubm = fminf(ubm, pr.d + (ra[p].hd + rb.hd));
+                    sure |= pr.sure ? 1 : 0;
+                }
+            }
+            cols += nb;
+            __syncthreads();
+            if (a.early) {
+                float wub = wave_min(ubm);
+                int ws = wave_or(sure);
+                bool confirm = (a.tau > 0.0f && wub + it.eps <= a.tau) || (finest && ws);
+                if (confirm) {
+                    if (lane == 0) __hip_atomic_store(&o->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                if (__builtin_amdgcn_readfirstlane(
+                        __hip_atomic_load(&o->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
+                    break;
+            }
+        }
+        float wl = wave_min(lbm), wu = wave_min(ubm);
+        int ws = wave_or(sure);
+        if (lane == 0) {
+            atomicMin(&o->lb, fbits(wl));
+            atomicMin(&o->ub, fbits(wu));
+            if (ws) atomicOr(&o->hit, 1);
+            const int rows = min(64 * P, SA.n - tl.a0);
+            atomicAdd(a.pairs_done, (unsigned long long)(rows * cols));
+        }
+    }
+}
+
+hipError_t launch_refine_f32(const RefineArgs &a, int grid, int P, hipStream_t st)
+{
+    if (grid <= 0) return hipSuccess;
+    if (P == 1) hipLaunchKernelGGL(k_refine_f32<1>, dim3(grid), dim3(64), 0, st, a);
+    else if (P == 2) hipLaunchKernelGGL(k_refine_f32<2>, dim3(grid), dim3(64), 0, st, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FP64 refinement over tiles (guard-band recheck): one lane = one A facet,
+// B facets through LDS; exact meet test; results merged with 64-bit atomicMin
+// of non-negative doubles.
+// ---------------------------------------------------------------------------
+struct FacetSrc64 {
+    const int32_t *tris;
+    const float *verts;
+    const float2 *hdph;
+    int n;
+};
+
+__global__ __launch_bounds__(64) void k_refine_f64_tiles(Refine64Args a)
+{
+    __shared__ float sb[64 * 12];
+    const int lane = threadIdx.x;
+    const Tile tl = a.tiles[blockIdx.x];
+    const Item it = a.items[tl.item];
+    const bool swap = it.flags & IT_SWAP;
+    const FacetSrc SA = facet_src(swap ? a.S : a.R, it.a_obj, it.lod);
+    const FacetSrc SB = facet_src(swap ? a.R : a.S, it.b_obj, it.lod);
+    int f = tl.a0 + lane;
+    if (f >= SA.n) f = tl.a0;
+    D3 A[3];
+    for (int c = 0; c < 3; ++c) A[c] = ld3d(SA.verts, SA.tris[3 * f + c]);
+    float2 ha = SA.hdph ? SA.hdph[f] : make_float2(0.0f, 0.0f);
+    double lbm = __builtin_inf(), ubm = __builtin_inf();
+    int hit = 0;
+    for (int cb = tl.b0; cb < tl.b1; cb += 64) {
+        const int nb = min(64, tl.b1 - cb);
+        {
+            int g = cb + lane;
+            if (g >= tl.b1) g = cb;
+            for (int c = 0; c < 3; ++c) {
+                int vi = SB.tris[3 * g + c];
+                sb[lane * 12 + 3 * c] = SB.verts[3 * vi];
+                sb[lane * 12 + 3 * c + 1] = SB.verts[3 * vi + 1];
+                sb[lane * 12 + 3 * c + 2] = SB.verts[3 * vi + 2];
+            }
+            float2 hb = SB.hdph ? SB.hdph[g] : make_float2(0.0f, 0.0f);
+            sb[lane * 12 + 9] = hb.x;
+            sb[lane * 12 + 10] = hb.y;
+        }
+        __syncthreads();
+        for (int k = 0; k < nb; ++k) {
+            const float *x = sb + k * 12;
+            D3 B[3] = {D3{x[0], x[1], x[2]}, D3{x[3], x[4], x[5]}, D3{x[6], x[7], x[8]}};
+            bool h;
+            double d = pair_f64(A, B, h);
+            hit |= h ? 1 : 0;
+            lbm = fmin(lbm, fmax(d - ((double)ha.y + (double)x[10]), 0.0));
+            ubm = fmin(ubm, d + ((double)ha.x + (double)x[9]));
+        }
+        __syncthreads();
+    }
+    lbm = wave_min_d(lbm);
+    ubm = wave_min_d(ubm);
+    hit = wave_or(hit);
+    if (lane == 0) {
+        ItemOut64 *o = a.out + tl.item;
+        atomicMin(&o->lb, (unsigned long long)__double_as_longlong(lbm));
+        atomicMin(&o->ub, (unsigned long long)__double_as_longlong(ubm));
+        if (hit) atomicOr(&o->hit, 1);
+    }
+}
+
+hipError_t launch_refine_f64_tiles(const Refine64Args &a, int ntiles, hipStream_t st)
+{
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_refine_f64_tiles, dim3(ntiles), dim3(64), 0, st, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Plain schedule (the paper's Algorithm 4 shape): one 256-thread workgroup
+// per (pair, LoD); the n_A x n_B facet pairs are flattened and dealt to the
+// threads round-robin; thread-local minima are combined in LDS.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_refine_f64_plain(Refine64Args a)
+{
+    __shared__ double shl[4], shu[4];
+    __shared__ int shh[4];
+    const Item it = a.items[blockIdx.x];
+    const bool swap = it.flags & IT_SWAP;
+    const FacetSrc SA = facet_src(swap ? a.S : a.R, it.a_obj, it.lod);
+    const FacetSrc SB = facet_src(swap ? a.R : a.S, it.b_obj, it.lod);
+    const int64_t total = (int64_t)SA.n * SB.n;
+    double lbm = __builtin_inf(), ubm = __builtin_inf();
+    int hit = 0;
+    for (int64_t t = threadIdx.x; t < total; t += 256) {
+        const int i = (int)(t / SB.n), j = (int)(t - (int64_t)i * SB.n);
+        D3 A[3], B[3];
+        for (int c = 0; c < 3; ++c) {
+            A[c] = ld3d(SA.verts, SA.tris[3 * i + c]);
+            B[c] = ld3d(SB.verts, SB.tris[3 * j + c]);
+        }
+        float2 ha = SA.hdph ? SA.hdph[i] : make_float2(0.0f, 0.0f);
+        float2 hb = SB.hdph ? SB.hdph[j] : make_float2(0.0f, 0.0f);
+        bool h;
+        double d = pair_f64(A, B, h);
+        hit |= h ? 1 : 0;
+        lbm = fmin(lbm, fmax(d - ((double)ha.y + (double)hb.y), 0.0));
+        ubm = fmin(ubm, d + ((double)ha.x + (double)hb.x));
+    }
+    lbm = wave_min_d(lbm);
+    ubm = wave_min_d(ubm);
+    hit = wave_or(hit);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        shl[w] = lbm;
+        shu[w] = ubm;
+        shh[w] = hit;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ItemOut64 *o = a.out + blockIdx.x;
+        double l = fmin(fmin(shl[0], shl[1]), fmin(shl[2], shl[3]));
+        double u = fmin(fmin(shu[0], shu[1]), fmin(shu[2], shu[3]));
+        o->lb = (unsigned long long)__double_as_longlong(l);
+        o->ub = (unsigned long long)__double_as_longlong(u);
+        o->hit = shh[0] | shh[1] | shh[2] | shh[3];
+    }
+}
+
+hipError_t launch_refine_f64_plain(const Refine64Args &a, int nitems, hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_refine_f64_plain, dim3(nitems), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Facet pairs given explicitly (tests): FP32 with a pair-local origin and the
+// guard band 2^-16 M, or FP64 with the exact meet test.
+// ---------------------------------------------------------------------------
+__global__ void k_facet_pairs(const float *t1, const float *t2, int64_t n, int prec, double *d, int8_t *hit)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float *p = t1 + 9 * i, *q = t2 + 9 * i;
+    if (prec == 0) {
+        float lo[3], hi[3];
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = fminf(fminf(fminf(p[c], p[3 + c]), p[6 + c]), fminf(fminf(q[c], q[3 + c]), q[6 + c]));
+            hi[c] = fmaxf(fmaxf(fmaxf(p[c], p[3 + c]), p[6 + c]), fmaxf(fmaxf(q[c], q[3 + c]), q[6 + c]));
+        }
+        V3 o{0.5f * (lo[0] + hi[0]), 0.5f * (lo[1] + hi[1]), 0.5f * (lo[2] + hi[2])};
+        float M = fmaxf(fmaxf(hi[0] - o.x, o.x - lo[0]), fmaxf(fmaxf(hi[1] - o.y, o.y - lo[1]), fmaxf(hi[2] - o.z, o.z - lo[2])));
+        float eps = 0x1p-16f * M;
+        Rec A = make_rec(V3{p[0], p[1], p[2]} - o, V3{p[3], p[4], p[5]} - o, V3{p[6], p[7], p[8]} - o, 0.0f, 0.0f);
+        Rec B = make_rec(V3{q[0], q[1], q[2]} - o, V3{q[3], q[4], q[5]} - o, V3{q[6], q[7], q[8]} - o, 0.0f, 0.0f);
+        Pair32 r = pair_f32(A, B, eps);
+        d[i] = r.d;
+        hit[i] = r.sure ? 1 : 0;
+    } else {
+        D3 A[3] = {D3{p[0], p[1], p[2]}, D3{p[3], p[4], p[5]}, D3{p[6], p[7], p[8]}};
+        D3 B[3] = {D3{q[0], q[1], q[2]}, D3{q[3], q[4], q[5]}, D3{q[6], q[7], q[8]}};
+        bool h;
+        d[i] = pair_f64(A, B, h);
+        hit[i] = h ? 1 : 0;
+    }
+}
+
+hipError_t launch_facet_pairs(const float *t1, const float *t2, int64_t n, int prec, double *d, int8_t *hit,
+                              hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_facet_pairs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, t1, t2, n, prec, d, hit);
+    return hipGetLastError();
+}
+
+}  // namespace pj

@@ -1,0 +1,229 @@
+"""GPU parity: the HIP path through the C ABI against the CPU FP64 oracle.
+
+Element-wise at the facet-pair level, per pair and LoD for the bounds of
+Eq. (1)/(2), and per result set for the joins (bit-exact pair sets)."""
+import numpy as np
+import pytest
+
+import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pj():
+    import paper_2604_19982_amd as pj
+    return pj
+
+
+@pytest.fixture(scope="module")
+def ctx(pj):
+    return pj.Context(device=0)
+
+
+def _pairs_random(rng, n, spread):
+    T1 = rng.normal(size=(n, 3, 3)) * rng.uniform(0.2, 3.0, size=(n, 1, 1))
+    T2 = rng.normal(size=(n, 3, 3)) * rng.uniform(0.2, 3.0, size=(n, 1, 1)) + rng.normal(size=(n, 1, 3)) * spread
+    return T1.astype(np.float32), T2.astype(np.float32)
+
+
+def _adversarial(rng, n):
+    """Near-parallel, thin, touching and crossing configurations."""
+    out1, out2 = [], []
+    for k in range(n):
+        T1 = rng.normal(size=(3, 3))
+        kind = k % 5
+        if kind == 0:    # nearly parallel copy, tiny offset
+            T2 = T1 + rng.normal(size=3) * 1e-3 + np.cross(T1[1] - T1[0], T1[2] - T1[0]) * rng.uniform(-1e-2, 1e-2)
+        elif kind == 1:  # thin (tube-like) facets
+            a = rng.normal(size=3)
+            u = rng.normal(size=3)
+            T1 = np.stack([a, a + u, a + 0.02 * rng.normal(size=3)])
+            T2 = T1 + rng.normal(size=3) * 0.05
+        elif kind == 2:  # crossing through the interior
+            c = T1.mean(0)
+            n_ = np.cross(T1[1] - T1[0], T1[2] - T1[0])
+            n_ /= np.linalg.norm(n_)
+            d = rng.normal(size=3)
+            T2 = np.stack([c - n_ * 0.5, c + n_ * 0.5, c + d])
+        elif kind == 3:  # vertex pushed onto the face
+            c = T1.mean(0)
+            T2 = np.stack([c, c + rng.normal(size=3), c + rng.normal(size=3)])
+        else:            # edge-edge near miss
+            T2 = rng.normal(size=(3, 3)) * 0.5 + T1.mean(0)
+        out1.append(T1)
+        out2.append(T2)
+    return np.asarray(out1, np.float32), np.asarray(out2, np.float32)
+
+
+def _eps(T1, T2):
+    P = np.concatenate([T1, T2], 1)
+    lo, hi = P.min(1), P.max(1)
+    o = (0.5 * (lo + hi)).astype(np.float32)
+    M = np.maximum(hi - o, o - lo).max(1)
+    return np.ldexp(M.astype(np.float64), -16)
+
+
+def test_facet_pairs_fp64_vs_oracle(orc, ctx):
+    rng = np.random.default_rng(0)
+    T1, T2 = _pairs_random(rng, 20000, 2.0)
+    A1, A2 = _adversarial(rng, 5000)
+    G1 = rng.integers(0, 4, size=(3000, 3, 3)).astype(np.float32)  # touching / coplanar grid cases
+    G2 = rng.integers(0, 4, size=(3000, 3, 3)).astype(np.float32)
+    T1 = np.concatenate([T1, A1, G1])
+    T2 = np.concatenate([T2, A2, G2])
+    d_ref, h_ref = orc.tri_tri_batch(T1, T2)
+    d, h = ctx.facet_pairs(T1, T2, "fp64")
+    assert np.array_equal(h, h_ref), np.nonzero(h != h_ref)[0][:10]
+    scale = 1.0 + np.abs(np.concatenate([T1, T2], 1)).reshape(len(T1), -1).max(1)
+    assert np.all(np.abs(d - d_ref) <= 1e-12 * scale), np.max(np.abs(d - d_ref) / scale)
+    assert np.all((d == 0) == h)
+
+
+def test_facet_pairs_fp32_within_guard_band(orc, ctx):
+    rng = np.random.default_rng(1)
+    T1, T2 = _pairs_random(rng, 200000, 2.0)
+    A1, A2 = _adversarial(rng, 50000)
+    T1 = np.concatenate([T1, A1])
+    T2 = np.concatenate([T2, A2])
+    d_ref, h_ref = orc.tri_tri_batch(T1, T2)
+    d32, sure = ctx.facet_pairs(T1, T2, "fp32")
+    eps = _eps(T1, T2)
+    err = np.abs(d32 - d_ref)
+    # every FP32 distance lies within eps/8 of the FP64 one ...
+    assert np.all(err <= eps / 8), (np.max(err / eps), int(np.argmax(err / eps)))
+    # ... and a "sure" crossing is always a real meet
+    assert not np.any(sure & ~h_ref)
+    # most clean crossings are found
+    assert np.mean(sure[h_ref]) > 0.5
+
+
+def test_boxes_and_anchors(orc, ctx):
+    R, _ = mg.config_small(seed=3, n_r=40, n_s=1)
+    g = ctx.meshes(R)
+    box, anc = g.boxes()
+    obox, oanc = orc.mbbs(orc.OSet(R))
+    assert np.array_equal(box.astype(np.float64), obox)
+    for i in range(R.n_objects):
+        v = R.object_verts(i)
+        assert np.any(np.all(v == anc[i], axis=1))          # a surface vertex
+        c = 0.5 * (obox[i, :3] + obox[i, 3:])
+        assert np.linalg.norm(anc[i] - c) <= np.linalg.norm(oanc[i] - c) + 1e-5
+
+
+@pytest.fixture(scope="module")
+def small_multilod():
+    R = mg.blob_set(mg.rng_for(100, 0), 4, (0.0, 5.0), 1, 3, radius_sigma=0.3)
+    S = mg.tube_set(mg.rng_for(100, 1), 3, (0.0, 5.0), 64, 3, length_range=(6.0, 10.0))
+    return R, S
+
+
+def test_hdph_vs_oracle(orc, ctx, small_multilod):
+    R, S = small_multilod
+    for ms in (R, S):
+        g = ctx.meshes(ms)
+        O = orc.OSet(ms)
+        for obj in range(min(ms.n_objects, 2)):
+            for lod in range(ms.n_lods):
+                hd, ph = g.hdph(obj, lod)
+                rhd, rph = orc.hd_ph(O, obj, lod)
+                assert np.all(hd.astype(np.float64) >= rhd) and np.all(ph.astype(np.float64) >= rph)
+                assert np.all(hd <= rhd * (1 + 1e-6) + 1e-6) and np.all(ph <= rph * (1 + 1e-6) + 1e-6)
+
+
+@pytest.mark.parametrize("mode", ["fp32", "fp64", "plain"])
+def test_pair_bounds_vs_oracle(orc, pj, small_multilod, mode):
+    R, S = small_multilod
+    c = pj.Context(precision="fp64" if mode != "fp32" else "fp32", schedule="plain" if mode == "plain" else "batched")
+    gR, gS = c.meshes(R), c.meshes(S)
+    O_R, O_S = orc.OSet(R), orc.OSet(S)
+    rr, ss = np.meshgrid(np.arange(R.n_objects), np.arange(S.n_objects), indexing="ij")
+    rr, ss = rr.ravel(), ss.ravel()
+    bR, _ = orc.mbbs(O_R)
+    bS, _ = orc.mbbs(O_S)
+    for lod in range(R.n_lods):
+        lb, ub, hit = c.pair_bounds(gR, gS, rr, ss, lod)
+        for k in range(len(rr)):
+            hdr, phr = gR.hdph(rr[k], lod)
+            hds, phs = gS.hdph(ss[k], lod)
+            rlb, rub = orc.lod_bounds(O_R, rr[k], O_S, ss[k], lod, hdr, phr, hds, phs)
+            if mode == "fp32":
+                lo = np.minimum(bR[rr[k], :3], bS[ss[k], :3])
+                hi = np.maximum(bR[rr[k], 3:], bS[ss[k], 3:])
+                o = (0.5 * (lo + hi)).astype(np.float32)
+                tol = np.ldexp(float(np.maximum(hi - o, o - lo).max()), -16)
+            else:
+                tol = 1e-12 * (1 + np.abs(np.concatenate([bR[rr[k]], bS[ss[k]]])).max())
+            assert abs(lb[k] - rlb) <= tol, (lod, k, lb[k], rlb)
+            assert abs(ub[k] - rub) <= tol, (lod, k, ub[k], rub)
+
+
+@pytest.mark.parametrize("mode", ["fp32", "fp64", "plain"])
+@pytest.mark.parametrize("tau", [0.0, 0.25, 0.5])
+def test_join_small_single_lod(orc, pj, mode, tau):
+    R, S = mg.config_small(seed=0)
+    c = pj.Context(precision="fp64" if mode != "fp32" else "fp32", schedule="plain" if mode == "plain" else "batched")
+    got = c.join_within(c.meshes(R), c.meshes(S), tau)
+    ref = orc.join_within(orc.OSet(R), orc.OSet(S), tau)
+    assert ref["near_ties"] == 0
+    assert np.array_equal(got["r"], ref["r"]) and np.array_equal(got["s"], ref["s"])
+    assert len(ref["r"]) > 0
+
+
+@pytest.fixture(scope="module")
+def multilod_mid():
+    """A reduced multi-LoD workload: 400 blobs x 80 tubes in a 150^3 box."""
+    return mg.config_multilod(seed=1, n_r=400, n_s=80, box=150.0, n_seg=1280)
+
+
+@pytest.mark.parametrize("tau", [0.0, 5.0, 20.0])
+def test_join_multilod_fp32_band(orc, pj, multilod_mid, tau):
+    R, S = multilod_mid
+    c = pj.Context()
+    got = c.join_within(c.meshes(R), c.meshes(S), tau)
+    st = c.stats()
+    ref = orc.join_within(orc.OSet(R), orc.OSet(S), tau)
+    assert ref["near_ties"] == 0
+    assert np.array_equal(got["r"], ref["r"]) and np.array_equal(got["s"], ref["s"])
+    assert st["rounds"] >= 2 and st["facet_pairs"] > 0
+
+
+def test_join_want_dist(orc, pj):
+    R, S = mg.config_small(seed=2, n_r=40, n_s=40, box=8.0)
+    c = pj.Context(want_dist=True)
+    got = c.join_within(c.meshes(R), c.meshes(S), 0.7)
+    ref = orc.join_within(orc.OSet(R), orc.OSet(S), 0.7)
+    assert np.array_equal(got["r"], ref["r"]) and np.array_equal(got["s"], ref["s"])
+    M = 8.0
+    assert np.all(np.abs(got["dist"] - ref["d"]) <= np.maximum(1e-5 * ref["d"], 1e-12 * M))
+    assert np.all((got["dist"] == 0) == (ref["d"] == 0))
+
+
+def test_edge_cases(orc, pj, ctx):
+    R, S = mg.config_small(seed=0, n_r=5, n_s=5)
+    empty = R.subset([])
+    gR, gE = ctx.meshes(R), ctx.meshes(empty)
+    assert len(ctx.join_within(gR, gE, 1.0)["r"]) == 0
+    assert len(ctx.join_within(gE, gR, 1.0)["r"]) == 0
+    with pytest.raises(pj.PJError):
+        ctx.join_within(gR, gR, -1.0)
+    with pytest.raises(pj.PJError):
+        ctx.join_within(gR, gR, float("nan"))
+    bad = R.subset([0])
+    bad.verts = bad.verts.copy()
+    bad.verts[0, 0] = np.nan
+    with pytest.raises(pj.PJError):
+        ctx.meshes(bad)
+    bad2 = R.subset([0])
+    bad2.tris = bad2.tris.copy()
+    bad2.tris[0, 0] = 10 ** 6
+    with pytest.raises(pj.PJError):
+        ctx.meshes(bad2)
+    # hand-built: cubes at a face gap, nested cubes (surface semantics)
+    A = mg.cube_mesh([0, 0, 0], [1, 1, 1])
+    B = mg.objects([mg.cube_mesh([1.25, 0, 0], [2.25, 1, 1]), mg.cube_mesh([-1, -1, -1], [2, 2, 2]),
+                    mg.cube_mesh([1, 0, 0], [2, 1, 1])])
+    gA, gB = ctx.meshes(A), ctx.meshes(B)
+    for tau, want in [(0.0, [2]), (0.2499, [2]), (0.25, [0, 2]), (1.0, [0, 1, 2])]:
+        got = ctx.join_within(gA, gB, tau)
+        assert got["s"].tolist() == want, (tau, got)
