@@ -449,96 +449,106 @@ __device__ __forceinline__ Rec load_rec(const FacetSrc &s, int f, V3 o)
     return make_rec(a, b, c, h.x, h.y);
 }
 
+// One tile.  Every branch below depends only on wave-uniform values (tile
+// and item fields loaded through a uniform index, readfirstlane'd flags), so
+// the compiler emits scalar control flow and the wave never splits.
+template <int P>
+__device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t, float4 *sh)
+{
+    const int lane = threadIdx.x;
+    const Tile tl = a.tiles[t];
+    const Item it = a.items[tl.item];
+    ItemOut *o = a.out + tl.item;
+    if (a.early &&
+        __builtin_amdgcn_readfirstlane(__hip_atomic_load(&o->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
+        return;
+    const bool swap = it.flags & IT_SWAP;
+    const FacetSrc SA = facet_src(swap ? a.S : a.R, it.a_obj, it.lod);
+    const FacetSrc SB = facet_src(swap ? a.R : a.S, it.b_obj, it.lod);
+    const V3 org = V3{it.ox, it.oy, it.oz};
+    Rec ra[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        int f = tl.a0 + lane + 64 * p;
+        if (f >= SA.n) f = tl.a0;  // padding lanes repeat a real facet
+        ra[p] = load_rec(SA, f, org);
+    }
+    float lbm = kInf, ubm = kInf;
+    int sure = 0;
+    int cols = 0;
+    const bool finest = it.flags & IT_FINEST;
+    bool stop = false;
+    for (int cb = tl.b0; cb < tl.b1 && !stop; cb += 64) {
+        const int nb = min(64, tl.b1 - cb);
+        {
+            int f = cb + lane;
+            if (f >= tl.b1) f = cb;
+            Rec rb = load_rec(SB, f, org);
+            float tmp[44];
+            __builtin_memcpy(tmp, &rb, sizeof(tmp));
+#pragma unroll
+            for (int q = 0; q < 11; ++q)
+                sh[lane * 11 + q] = make_float4(tmp[4 * q], tmp[4 * q + 1], tmp[4 * q + 2], tmp[4 * q + 3]);
+        }
+        __syncthreads();
+        for (int k = 0; k < nb; ++k) {
+            float tmp[44];
+#pragma unroll
+            for (int q = 0; q < 11; ++q) {
+                float4 x = sh[k * 11 + q];
+                tmp[4 * q] = x.x;
+                tmp[4 * q + 1] = x.y;
+                tmp[4 * q + 2] = x.z;
+                tmp[4 * q + 3] = x.w;
+            }
+            Rec rb;
+            __builtin_memcpy(&rb, tmp, sizeof(rb));
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                Pair32 pr = pair_f32(ra[p], rb, it.eps);
+                float dlo = pr.d * (ra[p].ok * rb.ok);
+                lbm = fminf(lbm, fmaxf(dlo - (ra[p].ph + rb.ph), 0.0f));
+                ubm = fminf(ubm, pr.d + (ra[p].hd + rb.hd));
+                sure |= pr.sure ? 1 : 0;
+            }
+        }
+        cols += nb;
+        __syncthreads();
+        if (a.early) {
+            const float wub = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wave_min(ubm))));
+            const int ws = __builtin_amdgcn_readfirstlane(wave_or(sure));
+            const bool confirm = (a.tau > 0.0f && wub + it.eps <= a.tau) || (finest && ws);
+            if (confirm) {
+                if (lane == 0) __hip_atomic_store(&o->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                stop = true;
+            } else if (__builtin_amdgcn_readfirstlane(
+                           __hip_atomic_load(&o->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                stop = true;
+            }
+        }
+    }
+    const float wl = wave_min(lbm), wu = wave_min(ubm);
+    const int ws = wave_or(sure);
+    if (lane == 0) {
+        atomicMin(&o->lb, fbits(wl));
+        atomicMin(&o->ub, fbits(wu));
+        if (ws) atomicOr(&o->hit, 1);
+        const int rows = min(64 * P, SA.n - tl.a0);
+        atomicAdd(a.pairs_done, (unsigned long long)rows * (unsigned long long)cols);
+    }
+}
+
+// Persistent single-wave workgroups walk the tile list (longest items
+// first) with a static stride of the grid size.  The loop index depends only
+// on blockIdx, so the loop control is scalar.  (A queue whose index lane 0
+// fetched and broadcast let the compiler split the loop on the lane-0 test,
+// after which lanes 1..63 re-ran tile 0 without end.)
 template <int P>
 __global__ __launch_bounds__(64) void k_refine_f32(RefineArgs a)
 {
     __shared__ float4 sh[64 * 11];
-    const int lane = threadIdx.x;
-    for (;;) {
-        int t = 0;
-        if (lane == 0) t = atomicAdd(a.counter, 1);
-        t = __shfl(t, 0, 64);
-        if (t >= *a.ntiles) break;
-        const Tile tl = a.tiles[t];
-        const Item it = a.items[tl.item];
-        ItemOut *o = a.out + tl.item;
-        if (a.early && __builtin_amdgcn_readfirstlane(
-                           __hip_atomic_load(&o->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
-            continue;
-        const bool swap = it.flags & IT_SWAP;
-        const FacetSrc SA = facet_src(swap ? a.S : a.R, it.a_obj, it.lod);
-        const FacetSrc SB = facet_src(swap ? a.R : a.S, it.b_obj, it.lod);
-        const V3 org = V3{it.ox, it.oy, it.oz};
-        Rec ra[P];
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-            int f = tl.a0 + lane + 64 * p;
-            if (f >= SA.n) f = tl.a0;  // padding lanes repeat a real facet
-            ra[p] = load_rec(SA, f, org);
-        }
-        float lbm = kInf, ubm = kInf;
-        int sure = 0;
-        int64_t cols = 0;
-        const bool finest = it.flags & IT_FINEST;
-        for (int cb = tl.b0; cb < tl.b1; cb += 64) {
-            const int nb = min(64, tl.b1 - cb);
-            {
-                int f = cb + lane;
-                if (f >= tl.b1) f = cb;
-                Rec rb = load_rec(SB, f, org);
-                float tmp[44];
-                __builtin_memcpy(tmp, &rb, sizeof(tmp));
-#pragma unroll
-                for (int q = 0; q < 11; ++q)
-                    sh[lane * 11 + q] = make_float4(tmp[4 * q], tmp[4 * q + 1], tmp[4 * q + 2], tmp[4 * q + 3]);
-            }
-            __syncthreads();
-            for (int k = 0; k < nb; ++k) {
-                float tmp[44];
-#pragma unroll
-                for (int q = 0; q < 11; ++q) {
-                    float4 x = sh[k * 11 + q];
-                    tmp[4 * q] = x.x;
-                    tmp[4 * q + 1] = x.y;
-                    tmp[4 * q + 2] = x.z;
-                    tmp[4 * q + 3] = x.w;
-                }
-                Rec rb;
-                __builtin_memcpy(&rb, tmp, sizeof(rb));
-#pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    Pair32 pr = pair_f32(ra[p], rb, it.eps);
-                    float dlo = pr.d * (ra[p].ok * rb.ok);
-                    lbm = fminf(lbm, fmaxf(dlo - (ra[p].ph + rb.ph), 0.0f));
-                    ubm = fminf(ubm, pr.d + (ra[p].hd + rb.hd));
-                    sure |= pr.sure ? 1 : 0;
-                }
-            }
-            cols += nb;
-            __syncthreads();
-            if (a.early) {
-                float wub = wave_min(ubm);
-                int ws = wave_or(sure);
-                bool confirm = (a.tau > 0.0f && wub + it.eps <= a.tau) || (finest && ws);
-                if (confirm) {
-                    if (lane == 0) __hip_atomic_store(&o->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
-                if (__builtin_amdgcn_readfirstlane(
-                        __hip_atomic_load(&o->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
-                    break;
-            }
-        }
-        float wl = wave_min(lbm), wu = wave_min(ubm);
-        int ws = wave_or(sure);
-        if (lane == 0) {
-            atomicMin(&o->lb, fbits(wl));
-            atomicMin(&o->ub, fbits(wu));
-            if (ws) atomicOr(&o->hit, 1);
-            const int rows = min(64 * P, SA.n - tl.a0);
-            atomicAdd(a.pairs_done, (unsigned long long)(rows * cols));
-        }
-    }
+    const int ntiles = *a.ntiles;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) refine_tile_f32<P>(a, t, sh);
 }
 
 hipError_t launch_refine_f32(const RefineArgs &a, int grid, int P, hipStream_t st)
