@@ -211,6 +211,10 @@ pj_status pj_pair_bounds(pj_context *ctx, const pj_meshes *R, const pj_meshes *S
 pj_status pj_mlp_eval(pj_context *ctx, const float *params, const float *x, const int32_t *y, int64_t n,
                       float *logits, float *loss, float *grads);
 
+/* Calibration: measured FMA throughput of this device in GFLOP/s (FMA = 2
+ * flops) for scalar FP32 (fp64 = 0) or FP64 (fp64 = 1) register-only code. */
+pj_status pj_probe_fma(pj_context *ctx, int32_t fp64, double *gflops);
+
 #ifdef __cplusplus
 }
 #endif

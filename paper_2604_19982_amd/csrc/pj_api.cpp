@@ -1090,3 +1090,21 @@ extern "C" pj_status pj_mlp_eval(pj_context *ctx, const float *params, const flo
     (void)grads;
     return fail(ctx, PJ_ERR_UNSUPPORTED, "MLP not built yet");
 }
+
+extern "C" pj_status pj_probe_fma(pj_context *ctx, int32_t fp64, double *gflops)
+{
+    if (!ctx || !gflops) return PJ_ERR_INVALID_ARG;
+    HIPTRY(ctx, hipSetDevice(ctx->cfg.device));
+    const int blocks = ctx->num_cu * 16, iters = 1 << 16;
+    PJTRY(ensure(ctx, ctx->b_tmp0, (size_t)blocks * 256 * 8));
+    hipStream_t st = ctx->stream;
+    HIPTRY(ctx, launch_fma_probe(fp64, ctx->b_tmp0.p, blocks, 64, st));  // warm-up
+    HIPTRY(ctx, hipEventRecord(ctx->ev0, st));
+    HIPTRY(ctx, launch_fma_probe(fp64, ctx->b_tmp0.p, blocks, iters, st));
+    HIPTRY(ctx, hipEventRecord(ctx->ev1, st));
+    HIPTRY(ctx, hipStreamSynchronize(st));
+    float ms = 0;
+    HIPTRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    *gflops = (double)blocks * 256 * iters * 8 * 2 / (ms * 1e-3) / 1e9;
+    return PJ_OK;
+}

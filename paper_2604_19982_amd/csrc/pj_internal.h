@@ -95,6 +95,8 @@ hipError_t launch_refine_f64_plain(const Refine64Args &a, int nitems, hipStream_
 hipError_t launch_facet_pairs(const float *t1, const float *t2, int64_t n, int prec, double *d, int8_t *hit,
                               hipStream_t st);
 
+hipError_t launch_fma_probe(int fp64, void *out, int blocks, int iters, hipStream_t st);
+
 // MLP (pj_mlp.hip)
 hipError_t launch_mlp_fwd_bwd(const float *params, const float *x, const int32_t *y, int n, float *logits,
                               float *loss_acc, float *grads, hipStream_t st);
