@@ -28,9 +28,13 @@ sys.path.insert(0, ROOT)
 # counted): 6 vertex-plane candidates x 25 + 9 segment pairs x 49 + sqrt 1 +
 # bounds 6.
 FLOP_PER_PAIR = 6 * 25 + 9 * 49 + 1 + 6
-# Non-packed FP32 VALU peak of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA)
-# x 2.4 GHz.  (Packed FP32 instructions are disabled in this build.)
-PEAK_FP32_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# MI355X published FP32 vector peak (256 CUs, 2.4 GHz).  The build disables
+# packed FP32 instructions; scalar FP32 FMA issue alone reaches half of it
+# (256 CUs x 64 lanes x 2 x 2.4 GHz = 78.6 TFLOP/s, measured by the FMA probe
+# reported beside it), while gfx950 can co-issue two VALU instructions per
+# SIMD quad-cycle, which mixed code like the refinement kernel uses.
+PEAK_FP32_TFLOPS = 157.3
+SINGLE_ISSUE_FP32_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 TAUS = (0.0, 5.0, 20.0)
 
 
@@ -120,6 +124,9 @@ def main():
     torch.cuda.synchronize()
     ingest_s = time.time() - t0
     log(f"ingested in {ingest_s:.2f} s")
+    fma_tflops = max(ctx.probe_fma(False) for _ in range(2)) / 1e3
+    copy_gbps = ctx.probe_copy(1 << 30)
+    log(f"probes: scalar FP32 FMA {fma_tflops:.1f} TFLOP/s, copy {copy_gbps:.0f} GB/s")
     for w in range(args.warmup):
         run_step(ctx, gR, gS, TAUS)
         log(f"warmup step {w} done")
@@ -165,7 +172,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
                      "kernel": "k_refine_f32", "launches": launches, "avg_launch_ms": kms / max(launches, 1),
-                     "flop_per_pair": FLOP_PER_PAIR},
+                     "flop_per_pair": FLOP_PER_PAIR, "single_issue_fma_peak": SINGLE_ISSUE_FP32_TFLOPS,
+                     "fma_probe_measured": fma_tflops, "copy_probe_gbps": copy_gbps},
     }
     if args.plain:
         cp = pj.Context(schedule="plain", precision="fp64", stream=stream.cuda_stream)

@@ -214,6 +214,9 @@ pj_status pj_mlp_eval(pj_context *ctx, const float *params, const float *x, cons
 /* Calibration: measured FMA throughput of this device in GFLOP/s (FMA = 2
  * flops) for scalar FP32 (fp64 = 0) or FP64 (fp64 = 1) register-only code. */
 pj_status pj_probe_fma(pj_context *ctx, int32_t fp64, double *gflops);
+/* Calibration: a plain device-to-device copy of nbytes (multiple of 16) with
+ * one kernel launch; returns the achieved read+write bandwidth in GB/s. */
+pj_status pj_probe_copy(pj_context *ctx, int64_t nbytes, double *gbps);
 
 #ifdef __cplusplus
 }

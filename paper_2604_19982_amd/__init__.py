@@ -79,7 +79,7 @@ class TrainOpts(ctypes.Structure):
 EXPORTS = ["pj_config_default", "pj_context_create", "pj_context_destroy", "pj_meshes_create", "pj_meshes_destroy",
            "pj_join_within", "pj_join_intersect", "pj_join_knn", "pj_pairs_free", "pj_knn_free", "pj_get_stats",
            "pj_last_error", "pj_train_lod_model", "pj_meshes_boxes", "pj_meshes_hdph", "pj_facet_pairs",
-           "pj_pair_bounds", "pj_mlp_eval", "pj_probe_fma"]
+           "pj_pair_bounds", "pj_mlp_eval", "pj_probe_fma", "pj_probe_copy"]
 
 _lib = None
 
@@ -116,6 +116,7 @@ def lib():
         L.pj_pair_bounds.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp, ctypes.c_int32, vp, vp, vp]
         L.pj_mlp_eval.argtypes = [vp, vp, vp, vp, ctypes.c_int64, vp, vp, vp]
         L.pj_probe_fma.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+        L.pj_probe_copy.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
         _lib = L
     return _lib
 
@@ -282,6 +283,12 @@ class Context:
         """Measured FMA throughput (GFLOP/s) of register-only FP32 or FP64 code."""
         g = ctypes.c_double()
         self._check(lib().pj_probe_fma(self.h, int(bool(fp64)), ctypes.byref(g)))
+        return g.value
+
+    def probe_copy(self, nbytes):
+        """Achieved bandwidth (GB/s, read + write) of one plain copy of nbytes."""
+        g = ctypes.c_double()
+        self._check(lib().pj_probe_copy(self.h, int(nbytes), ctypes.byref(g)))
         return g.value
 
     def close(self):

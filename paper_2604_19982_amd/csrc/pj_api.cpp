@@ -1108,3 +1108,23 @@ extern "C" pj_status pj_probe_fma(pj_context *ctx, int32_t fp64, double *gflops)
     *gflops = (double)blocks * 256 * iters * 8 * 2 / (ms * 1e-3) / 1e9;
     return PJ_OK;
 }
+
+extern "C" pj_status pj_probe_copy(pj_context *ctx, int64_t nbytes, double *gbps)
+{
+    if (!ctx || !gbps || nbytes <= 0 || nbytes % 16) return fail(ctx, PJ_ERR_INVALID_ARG, "nbytes must be a positive multiple of 16");
+    HIPTRY(ctx, hipSetDevice(ctx->cfg.device));
+    PJTRY(ensure(ctx, ctx->b_tmp0, nbytes));
+    PJTRY(ensure(ctx, ctx->b_tmp1, nbytes));
+    hipStream_t st = ctx->stream;
+    const int blocks = ctx->num_cu * 8;
+    HIPTRY(ctx, hipMemsetAsync(ctx->b_tmp0.p, 0, nbytes, st));
+    HIPTRY(ctx, launch_copy_probe(ctx->b_tmp0.p, ctx->b_tmp1.p, nbytes, blocks, st));  // warm-up
+    HIPTRY(ctx, hipEventRecord(ctx->ev0, st));
+    HIPTRY(ctx, launch_copy_probe(ctx->b_tmp0.p, ctx->b_tmp1.p, nbytes, blocks, st));
+    HIPTRY(ctx, hipEventRecord(ctx->ev1, st));
+    HIPTRY(ctx, hipStreamSynchronize(st));
+    float ms = 0;
+    HIPTRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    *gbps = 2.0 * (double)nbytes / (ms * 1e-3) / 1e9;
+    return PJ_OK;
+}

@@ -96,6 +96,7 @@ hipError_t launch_facet_pairs(const float *t1, const float *t2, int64_t n, int p
                               hipStream_t st);
 
 hipError_t launch_fma_probe(int fp64, void *out, int blocks, int iters, hipStream_t st);
+hipError_t launch_copy_probe(const void *src, void *dst, int64_t nbytes, int blocks, hipStream_t st);
 
 // MLP (pj_mlp.hip)
 hipError_t launch_mlp_fwd_bwd(const float *params, const float *x, const int32_t *y, int n, float *logits,

@@ -31,4 +31,16 @@ hipError_t launch_fma_probe(int fp64, void *out, int blocks, int iters, hipStrea
     return hipGetLastError();
 }
 
+// plain streaming copy (16-byte vectors): calibrates the HBM byte counters
+__global__ __launch_bounds__(256) void k_copy_probe(const float4 *__restrict__ src, float4 *__restrict__ dst, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) dst[i] = src[i];
+}
+
+hipError_t launch_copy_probe(const void *src, void *dst, int64_t nbytes, int blocks, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_copy_probe, dim3(blocks), dim3(256), 0, st, (const float4 *)src, (float4 *)dst, nbytes / 16);
+    return hipGetLastError();
+}
+
 }  // namespace pj
