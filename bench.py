@@ -36,6 +36,19 @@ FLOP_PER_PAIR = 6 * 25 + 9 * 49 + 1 + 6
 PEAK_FP32_TFLOPS = 157.3
 SINGLE_ISSUE_FP32_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 TAUS = (0.0, 5.0, 20.0)
+COUNTERS = os.path.join(ROOT, "profiles", "k_refine_f32_multilod_counters.json")
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed counter runs, or None when the
+    kernel sources changed since they were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(COUNTERS))
+        sha = hashlib.sha256(b"".join(open(os.path.join(ROOT, s), "rb").read() for s in rec["sources"])).hexdigest()
+        return rec["traffic_bytes_per_launch"] if sha == rec["source_sha256"] else None
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def log(msg):
@@ -170,7 +183,7 @@ def main():
                    "band_pairs_per_step": steps[-1]["band"],
                    "ingest_s": ingest_s},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
                      "kernel": "k_refine_f32", "launches": launches, "avg_launch_ms": kms / max(launches, 1),
                      "flop_per_pair": FLOP_PER_PAIR, "single_issue_fma_peak": SINGLE_ISSUE_FP32_TFLOPS,
                      "fma_probe_measured": fma_tflops, "copy_probe_gbps": copy_gbps},
