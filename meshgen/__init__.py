@@ -472,7 +472,64 @@ def config_multilod(seed: int = 1, n_r: int = 10000, n_s: int = 2000, box=500.0,
     return R, S
 
 
+def mixed_set(rng, centres, n_lods: int = 4, f_median: float = 7071.0, f_sigma: float = math.log(50.0) / 4,
+              f_clip=(1000, 50000), radius_sigma: float = 0.3):
+    """Blob/tube mix with lognormal finest facet counts.
+
+    Per object (draw order): kind (blob/tube, 50/50), target finest facet
+    count F ~ lognormal(ln f_median, f_sigma) clipped to f_clip.  A blob is
+    the icosphere whose finest level (3, 4 or 5: 1280/5120/20480 triangles)
+    is nearest to F in log scale, with LoDs at the n_lods levels ending there;
+    a tube gets n_seg = F/16 rounded to a multiple of 4^(n_lods-1) segments.
+    Then blob radii, blob noise, tube shapes (in that order).
+    """
+    centres = np.asarray(centres, np.float64)
+    n = len(centres)
+    kind = rng.integers(0, 2, size=n)
+    F = np.clip(np.exp(rng.normal(math.log(f_median), f_sigma, size=n)), f_clip[0], f_clip[1])
+    step = 4 ** (n_lods - 1)
+    blob_lv = np.clip(np.round(np.log(F / 20.0) / math.log(4.0)), n_lods - 1, 5).astype(int)
+    segs = np.clip(np.round(F / 16.0 / step) * step, step, None).astype(int)
+    radii = np.exp(rng.normal(0.0, radius_sigma, size=n))
+    per_v = [None] * n
+    per_key = [None] * n
+    templ = {}
+    for lv in sorted(set(blob_lv[kind == 0].tolist())):
+        ids = np.nonzero((kind == 0) & (blob_lv == lv))[0]
+        v, tris, par = make_blobs(rng, centres[ids], radii[ids], lv - n_lods + 1, lv)
+        templ[("ico", lv - n_lods + 1, lv)] = (tris, par)
+        for k_, i in enumerate(ids):
+            per_v[i] = v[k_]
+            per_key[i] = ("ico", lv - n_lods + 1, lv)
+    tube_ids = np.nonzero(kind == 1)[0]
+    if len(tube_ids):
+        v, sg = make_tubes(rng, centres[tube_ids], 0, n_lods, n_seg_per_object=segs[tube_ids])
+        for k_, i in enumerate(tube_ids):
+            ns = int(segs[i])
+            key = ("tube", ns, n_lods)
+            if key not in templ:
+                templ[key] = tube_template(ns, n_lods)
+            per_v[i] = v[k_]
+            per_key[i] = key
+    return _assemble(per_v, per_key, templ, n_lods, kind)
+
+
+def config_knn(seed: int = 2, n_r: int = 20000, n_s: int = 20000, n_clusters: int = 50, box: float = 2000.0,
+               sigma: float = 30.0, **kw):
+    """Clustered k-NN workload: object centres = one of n_clusters centres
+    U([0, box]^3) + N(0, sigma^2); objects from ``mixed_set``.  The cluster
+    centres come from stream 2, R from stream 0, S from stream 1."""
+    cl = rng_for(seed, 2).uniform(0.0, box, size=(n_clusters, 3))
+    out = []
+    for stream, n in ((0, n_r), (1, n_s)):
+        rng = rng_for(seed, stream)
+        c = cl[rng.integers(0, n_clusters, size=n)] + rng.normal(0.0, sigma, size=(n, 3))
+        out.append(mixed_set(rng, c, **kw))
+    return out[0], out[1]
+
+
 CONFIGS = {
     "small": dict(builder=config_small, tau=[0.5]),
     "multilod": dict(builder=config_multilod, tau=[0.0, 5.0, 20.0]),
+    "knn": dict(builder=config_knn, k=3),
 }

@@ -85,7 +85,8 @@ struct pj_context {
     int64_t dev_bytes = 0, peak_bytes = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     DevBuf b_items, b_tiles, b_out, b_out64, b_ctr, b_cand_r, b_cand_s, b_cand_lb, b_cand_ub, b_blk, b_blkoff,
-        b_total, b_tmp0, b_tmp1, b_tmp2, b_tmp3;
+        b_total, b_tmp0, b_tmp1, b_tmp2, b_tmp3, b_coll, b_ovf, b_theta, b_koff, b_klb, b_kub, b_kst0, b_kst1,
+        b_kleft;
     // LoD model (learned skip)
     std::vector<float> model;
     float feat_mean[MLP_IN], feat_std[MLP_IN];
@@ -547,6 +548,7 @@ struct PairState {
     float ox = 0, oy = 0, oz = 0;
     double d64 = INFINITY;  // FP64 finest distance once known
     int hit64 = 0;
+    float thr = INFINITY;   // collect threshold on the FP32 lower distance
 };
 
 void pair_frame(const pj_meshes *R, int r, const pj_meshes *S, int s, PairState &ps)
@@ -613,6 +615,7 @@ void plan_tiles(const pj_meshes *R, const pj_meshes *S, const std::vector<int> &
         it.oy = p.oy;
         it.oz = p.oz;
         it.eps = p.eps;
+        it.thr = p.thr;
         it.cand = ci;
         const int item = (int)pl.items.size();
         pl.items.push_back(it);
@@ -712,6 +715,14 @@ pj_status run_f64(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
     return PJ_OK;
 }
 
+// Exact FP64 finest-LoD distance of the candidates `which`: one FP32 pass
+// keeps the facet pairs whose lower distance is within the item's threshold
+// and within 2 eps of the running minimum (this always includes the pair that
+// realises the minimum), then FP64 with the exact meet test recomputes only
+// those.  Items whose pairs overflow the buffer are recomputed in full FP64.
+pj_status exact_finest(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, std::vector<Cand> &cand,
+                       std::vector<PairState> &ps, const std::vector<int> &which);
+
 double bits_to_double(unsigned long long b)
 {
     double d;
@@ -723,6 +734,98 @@ float bits_to_float(uint32_t b)
     float f;
     std::memcpy(&f, &b, 4);
     return f;
+}
+
+int pick_tile_s(pj_context *ctx);
+
+pj_status exact_finest(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, std::vector<Cand> &cand,
+                       std::vector<PairState> &ps, const std::vector<int> &which)
+{
+    if (which.empty()) return PJ_OK;
+    hipStream_t st = ctx->stream;
+    TilePlan pl;
+    plan_tiles(R, S, which, cand, ps, R->L - 1, 1, 64, pick_tile_s(ctx), true, pl);
+    const int ni = (int)pl.items.size(), nt = (int)pl.tiles.size();
+    if (ni == 0) return PJ_OK;
+    int64_t cap = std::max<int64_t>(1 << 20, 256 * (int64_t)ni);
+    PJTRY(ensure(ctx, ctx->b_items, ni * sizeof(Item)));
+    PJTRY(ensure(ctx, ctx->b_tiles, nt * sizeof(Tile)));
+    PJTRY(ensure(ctx, ctx->b_out, ni * sizeof(ItemOut)));
+    PJTRY(ensure(ctx, ctx->b_out64, ni * sizeof(ItemOut64)));
+    PJTRY(ensure(ctx, ctx->b_ovf, ni * sizeof(int32_t)));
+    PJTRY(ensure(ctx, ctx->b_coll, cap * sizeof(PairRef)));
+    PJTRY(ensure(ctx, ctx->b_ctr, 64));
+    HIPTRY(ctx, hipMemcpyAsync(ctx->b_items.p, pl.items.data(), ni * sizeof(Item), hipMemcpyHostToDevice, st));
+    HIPTRY(ctx, hipMemcpyAsync(ctx->b_tiles.p, pl.tiles.data(), nt * sizeof(Tile), hipMemcpyHostToDevice, st));
+    int32_t *ctr = ptr<int32_t>(ctx->b_ctr);
+    int32_t host_ctr[16] = {0, nt};
+    HIPTRY(ctx, hipMemcpyAsync(ctr, host_ctr, sizeof(host_ctr), hipMemcpyHostToDevice, st));
+    HIPTRY(ctx, hipMemsetAsync(ctx->b_ovf.p, 0, ni * sizeof(int32_t), st));
+    HIPTRY(ctx, launch_init_out(ptr<ItemOut>(ctx->b_out), ni, nullptr, st));
+    HIPTRY(ctx, launch_init_out64(ptr<ItemOut64>(ctx->b_out64), ni, st));
+    RefineArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.R = R->dev();
+    a.S = S->dev();
+    a.items = ptr<Item>(ctx->b_items);
+    a.tiles = ptr<Tile>(ctx->b_tiles);
+    a.ntiles = ctr + 1;
+    a.counter = ctr;
+    a.out = ptr<ItemOut>(ctx->b_out);
+    a.pairs_done = reinterpret_cast<unsigned long long *>(ctr + 2);
+    a.chunks_culled = reinterpret_cast<unsigned long long *>(ctr + 4);
+    a.tau = -1.0f;
+    a.collect_cap = (int32_t)std::min<int64_t>(cap, INT32_MAX);
+    a.collected = ptr<PairRef>(ctx->b_coll);
+    a.overflow = ptr<int32_t>(ctx->b_ovf);
+    const int wpc = ctx->cfg.waves_per_cu > 0 ? ctx->cfg.waves_per_cu : 12;
+    const int grid = (int)std::min<int64_t>(nt, (int64_t)ctx->num_cu * wpc);
+    HIPTRY(ctx, hipEventRecord(ctx->ev0, st));
+    HIPTRY(ctx, launch_collect_f32(a, grid, st));
+    HIPTRY(ctx, hipEventRecord(ctx->ev1, st));
+    HIPTRY(ctx, hipMemcpyAsync(host_ctr, ctr, sizeof(host_ctr), hipMemcpyDeviceToHost, st));
+    HIPTRY(ctx, hipStreamSynchronize(st));
+    float ms = 0;
+    HIPTRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    ctx->stats.refine_kernel_ms += ms;
+    ctx->stats.refine_launches += 1;
+    unsigned long long pairs;
+    std::memcpy(&pairs, host_ctr + 2, 8);
+    ctx->stats.facet_pairs += (int64_t)pairs;
+    const int64_t ncoll = std::min<int64_t>(host_ctr[0], cap);
+    HIPTRY(ctx, hipEventRecord(ctx->ev0, st));
+    HIPTRY(ctx, launch_pairs_f64(R->dev(), S->dev(), a.items, a.collected, ncoll, ptr<ItemOut64>(ctx->b_out64), st));
+    HIPTRY(ctx, hipEventRecord(ctx->ev1, st));
+    std::vector<ItemOut64> out(ni);
+    std::vector<int32_t> ovf(ni);
+    HIPTRY(ctx, hipMemcpyAsync(out.data(), ctx->b_out64.p, ni * sizeof(ItemOut64), hipMemcpyDeviceToHost, st));
+    HIPTRY(ctx, hipMemcpyAsync(ovf.data(), ctx->b_ovf.p, ni * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPTRY(ctx, hipStreamSynchronize(st));
+    HIPTRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    ctx->stats.band_kernel_ms += ms;
+    ctx->stats.facet_pairs_fp64 += ncoll;
+    std::vector<int> redo;
+    for (int k = 0; k < ni; ++k) {
+        PairState &p = ps[pl.items[k].cand];
+        if (ovf[k]) {
+            redo.push_back(pl.items[k].cand);
+            continue;
+        }
+        p.hit64 = out[k].hit;
+        p.d64 = p.hit64 ? 0.0 : bits_to_double(out[k].lb);
+    }
+    if (!redo.empty()) {
+        TilePlan p2;
+        plan_tiles(R, S, redo, cand, ps, R->L - 1, 1, 64, pick_tile_s(ctx), true, p2);
+        std::vector<ItemOut64> o2;
+        PJTRY(run_f64(ctx, R, S, p2, false, o2));
+        for (size_t k = 0; k < p2.items.size(); ++k) {
+            PairState &p = ps[p2.items[k].cand];
+            p.hit64 = o2[k].hit;
+            p.d64 = p.hit64 ? 0.0 : bits_to_double(o2[k].lb);
+        }
+    }
+    return PJ_OK;
 }
 
 pj_status check_pair_args(pj_context *ctx, const pj_meshes *R, const pj_meshes *S)
@@ -845,22 +948,21 @@ pj_status refine_within(pj_context *ctx, const pj_meshes *R, const pj_meshes *S,
             }
         }
     }
-    // guard band: FP64 with the exact meet test on the finest LoD
+    // guard band: FP64 with the exact meet test on the facet pairs that can
+    // still decide (FP32 lower distance <= tau + eps)
     std::vector<int> band;
     for (int i = 0; i < (int)cand.size(); ++i)
-        if (ps[i].status == ST_BAND) band.push_back(i);
+        if (ps[i].status == ST_BAND) {
+            band.push_back(i);
+            ps[i].thr = (float)tau + ps[i].eps;
+        }
     if (!band.empty()) {
         double tb = now_ms();
         ctx->stats.band_pairs += (int64_t)band.size();
-        plan_tiles(R, S, band, cand, ps, L - 1, 1, 64, TS, true, pl);
-        std::vector<ItemOut64> out;
-        PJTRY(run_f64(ctx, R, S, pl, false, out));
-        for (size_t k = 0; k < pl.items.size(); ++k) {
-            PairState &p = ps[pl.items[k].cand];
-            double d = bits_to_double(out[k].lb);
-            p.d64 = d;
-            p.hit64 = out[k].hit;
-            bool in = out[k].hit || (tau > 0.0 && d <= tau);
+        PJTRY(exact_finest(ctx, R, S, cand, ps, band));
+        for (int i : band) {
+            PairState &p = ps[i];
+            bool in = p.hit64 || (tau > 0.0 && p.d64 <= tau);
             p.status = in ? ST_CONF : ST_PRUNED;
             ctx->stats.resolved_at_lod[L - 1]++;
         }
@@ -875,18 +977,11 @@ pj_status finest_distances(pj_context *ctx, const pj_meshes *R, const pj_meshes 
 {
     std::vector<int> need;
     for (int i : which)
-        if (!std::isfinite(ps[i].d64) && !ps[i].hit64) need.push_back(i);
-    if (need.empty()) return PJ_OK;
-    TilePlan pl;
-    plan_tiles(R, S, need, cand, ps, R->L - 1, 1, 64, pick_tile_s(ctx), true, pl);
-    std::vector<ItemOut64> out;
-    PJTRY(run_f64(ctx, R, S, pl, false, out));
-    for (size_t k = 0; k < pl.items.size(); ++k) {
-        PairState &p = ps[pl.items[k].cand];
-        p.d64 = out[k].hit ? 0.0 : bits_to_double(out[k].lb);
-        p.hit64 = out[k].hit;
-    }
-    return PJ_OK;
+        if (!std::isfinite(ps[i].d64) && !ps[i].hit64) {
+            need.push_back(i);
+            ps[i].thr = INFINITY;
+        }
+    return exact_finest(ctx, R, S, cand, ps, need);
 }
 
 }  // namespace
@@ -963,12 +1058,201 @@ extern "C" pj_status pj_join_intersect(pj_context *ctx, const pj_meshes *R, cons
     return pj_join_within(ctx, R, S, 0.0, out);
 }
 
+namespace {
+
+// One pruning round of Algorithm 6 (corrected) on the device for every query.
+pj_status knn_prune_round(pj_context *ctx, int nR, int k, const std::vector<int64_t> &off,
+                          const std::vector<Cand> &cand, std::vector<PairState> &ps)
+{
+    hipStream_t st = ctx->stream;
+    const int64_t nc = (int64_t)cand.size();
+    std::vector<double> lb(nc), ub(nc);
+    std::vector<int8_t> sti(nc), sto(nc);
+    std::vector<int32_t> kleft(nR, k);
+    for (int64_t i = 0; i < nc; ++i) {
+        lb[i] = ps[i].LB;
+        ub[i] = ps[i].UB;
+        sti[i] = ps[i].status;
+        if (ps[i].status == ST_CONF) kleft[cand[i].r]--;
+    }
+    PJTRY(ensure(ctx, ctx->b_klb, nc * 8));
+    PJTRY(ensure(ctx, ctx->b_kub, nc * 8));
+    PJTRY(ensure(ctx, ctx->b_kst0, nc));
+    PJTRY(ensure(ctx, ctx->b_kst1, nc));
+    PJTRY(ensure(ctx, ctx->b_kleft, nR * 4));
+    HIPTRY(ctx, hipMemcpyAsync(ctx->b_klb.p, lb.data(), nc * 8, hipMemcpyHostToDevice, st));
+    HIPTRY(ctx, hipMemcpyAsync(ctx->b_kub.p, ub.data(), nc * 8, hipMemcpyHostToDevice, st));
+    HIPTRY(ctx, hipMemcpyAsync(ctx->b_kst0.p, sti.data(), nc, hipMemcpyHostToDevice, st));
+    HIPTRY(ctx, hipMemcpyAsync(ctx->b_kleft.p, kleft.data(), nR * 4, hipMemcpyHostToDevice, st));
+    HIPTRY(ctx, launch_knn_prune(nR, ptr<int64_t>(ctx->b_koff), ptr<double>(ctx->b_klb), ptr<double>(ctx->b_kub),
+                                 ptr<int32_t>(ctx->b_cand_s), ptr<int8_t>(ctx->b_kst0), ptr<int8_t>(ctx->b_kst1),
+                                 ptr<int32_t>(ctx->b_kleft), st));
+    HIPTRY(ctx, hipMemcpyAsync(sto.data(), ctx->b_kst1.p, nc, hipMemcpyDeviceToHost, st));
+    HIPTRY(ctx, hipStreamSynchronize(st));
+    for (int64_t i = 0; i < nc; ++i) ps[i].status = sto[i];
+    return PJ_OK;
+}
+
+}  // namespace
+
 extern "C" pj_status pj_join_knn(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, int32_t k, pj_knn *out)
 {
     if (!ctx) return PJ_ERR_INVALID_ARG;
-    if (!out || !R || !S || k < 1) return fail(ctx, PJ_ERR_INVALID_ARG, "bad argument");
+    if (!out) return fail(ctx, PJ_ERR_INVALID_ARG, "out is NULL");
     std::memset(out, 0, sizeof(*out));
-    return fail(ctx, PJ_ERR_UNSUPPORTED, "k-NN join not built yet");
+    PJTRY(check_pair_args(ctx, R, S));
+    if (k < 1) return fail(ctx, PJ_ERR_INVALID_ARG, "k must be >= 1");
+    HIPTRY(ctx, hipSetDevice(ctx->cfg.device));
+    std::memset(&ctx->stats, 0, sizeof(ctx->stats));
+    const double t0 = now_ms();
+    ctx->peak_bytes = ctx->dev_bytes;
+    const int nR = R->n, nS = S->n;
+    out->n_r = nR;
+    out->k = k;
+    out->count = (int32_t *)std::calloc(std::max(nR, 1), 4);
+    out->s = (int32_t *)std::malloc(std::max<int64_t>((int64_t)nR * k, 1) * 4);
+    out->dist = (double *)std::malloc(std::max<int64_t>((int64_t)nR * k, 1) * 8);
+    if (!out->count || !out->s || !out->dist) {
+        pj_knn_free(out);
+        return fail(ctx, PJ_ERR_OUT_OF_MEMORY, "host result allocation");
+    }
+    for (int64_t i = 0; i < (int64_t)nR * k; ++i) {
+        out->s[i] = -1;
+        out->dist[i] = NAN;
+    }
+    if (nR == 0 || nS == 0) {
+        ctx->stats.t_total_ms = now_ms() - t0;
+        return PJ_OK;
+    }
+    hipStream_t st = ctx->stream;
+    // candidates: theta_r = k-th smallest anchor bound; s with box gap <= theta_r
+    PJTRY(ensure(ctx, ctx->b_theta, nR * 4));
+    PJTRY(ensure(ctx, ctx->b_blk, nR * 4));
+    PJTRY(ensure(ctx, ctx->b_koff, (nR + 1) * 8));
+    PJTRY(ensure(ctx, ctx->b_total, 16));
+    HIPTRY(ctx, launch_knn_theta(R->d_anchor, nR, S->d_anchor, nS, k, ptr<float>(ctx->b_theta), st));
+    HIPTRY(ctx, launch_knn_cand(R->d_box, R->d_anchor, nR, S->d_box, S->d_anchor, nS, ptr<float>(ctx->b_theta),
+                                ptr<int32_t>(ctx->b_blk), nullptr, nullptr, nullptr, nullptr, 0, st));
+    HIPTRY(ctx, launch_scan_i32_to_i64(ptr<int32_t>(ctx->b_blk), ptr<int64_t>(ctx->b_koff), ptr<int64_t>(ctx->b_total),
+                                       nR, st));
+    int64_t total = 0;
+    HIPTRY(ctx, hipMemcpyAsync(&total, ctx->b_total.p, 8, hipMemcpyDeviceToHost, st));
+    HIPTRY(ctx, hipStreamSynchronize(st));
+    if (total > INT32_MAX) return fail(ctx, PJ_ERR_UNSUPPORTED, "more than 2^31 k-NN candidates");
+    HIPTRY(ctx, hipMemcpyAsync(ptr<int64_t>(ctx->b_koff) + nR, &total, 8, hipMemcpyHostToDevice, st));
+    PJTRY(ensure(ctx, ctx->b_cand_s, std::max<int64_t>(total, 1) * 4));
+    PJTRY(ensure(ctx, ctx->b_cand_lb, std::max<int64_t>(total, 1) * 4));
+    PJTRY(ensure(ctx, ctx->b_cand_ub, std::max<int64_t>(total, 1) * 4));
+    HIPTRY(ctx, launch_knn_cand(R->d_box, R->d_anchor, nR, S->d_box, S->d_anchor, nS, ptr<float>(ctx->b_theta),
+                                nullptr, ptr<int64_t>(ctx->b_koff), ptr<int32_t>(ctx->b_cand_s),
+                                ptr<float>(ctx->b_cand_lb), ptr<float>(ctx->b_cand_ub), 1, st));
+    std::vector<int64_t> off(nR + 1);
+    std::vector<int32_t> cs(total);
+    std::vector<float> clb(total), cub(total);
+    HIPTRY(ctx, hipMemcpyAsync(off.data(), ctx->b_koff.p, (nR + 1) * 8, hipMemcpyDeviceToHost, st));
+    if (total) {
+        HIPTRY(ctx, hipMemcpyAsync(cs.data(), ctx->b_cand_s.p, total * 4, hipMemcpyDeviceToHost, st));
+        HIPTRY(ctx, hipMemcpyAsync(clb.data(), ctx->b_cand_lb.p, total * 4, hipMemcpyDeviceToHost, st));
+        HIPTRY(ctx, hipMemcpyAsync(cub.data(), ctx->b_cand_ub.p, total * 4, hipMemcpyDeviceToHost, st));
+    }
+    HIPTRY(ctx, hipStreamSynchronize(st));
+    std::vector<Cand> cand(total);
+    std::vector<PairState> ps(total);
+    for (int r = 0; r < nR; ++r)
+        for (int64_t i = off[r]; i < off[r + 1]; ++i) {
+            cand[i] = Cand{r, cs[i], clb[i], cub[i]};
+            pair_frame(R, r, S, cs[i], ps[i]);
+            ps[i].LB = clb[i];
+            ps[i].UB = cub[i];
+        }
+    ctx->stats.candidates = total;
+    const double t1 = now_ms();
+    ctx->stats.t_filter_ms = t1 - t0;
+    PJTRY(knn_prune_round(ctx, nR, k, off, cand, ps));
+    // coarse LoD rounds on the undecided candidates
+    const int L = R->L;
+    const int TS = pick_tile_s(ctx);
+    const bool plain = ctx->cfg.schedule == PJ_SCHED_PLAIN;
+    const bool fp64 = plain || ctx->cfg.precision == PJ_PREC_FP64;
+    TilePlan pl;
+    for (int lod = 0; lod + 1 < L; ++lod) {
+        std::vector<int> act;
+        for (int64_t i = 0; i < total; ++i)
+            if (ps[i].status == ST_UNDEC) act.push_back((int)i);
+        if (act.empty()) break;
+        ctx->stats.rounds++;
+        if (fp64) {
+            plan_tiles(R, S, act, cand, ps, lod, 0, 64, TS, !plain, pl);
+            std::vector<ItemOut64> o64;
+            PJTRY(run_f64(ctx, R, S, pl, plain, o64));
+            for (size_t q = 0; q < pl.items.size(); ++q) {
+                PairState &p = ps[pl.items[q].cand];
+                double e64 = std::ldexp(p.M, -40);
+                p.LB = std::max(p.LB, bits_to_double(o64[q].lb) - e64);
+                p.UB = std::min(p.UB, bits_to_double(o64[q].ub) + e64);
+            }
+        } else {
+            plan_tiles(R, S, act, cand, ps, lod, 0, 64 * kP, TS, true, pl);
+            std::vector<ItemOut> o32;
+            PJTRY(run_f32(ctx, R, S, pl, -1.0f, false, o32));
+            for (size_t q = 0; q < pl.items.size(); ++q) {
+                PairState &p = ps[pl.items[q].cand];
+                p.LB = std::max(p.LB, (double)bits_to_float(o32[q].lb) - p.eps);
+                p.UB = std::min(p.UB, (double)bits_to_float(o32[q].ub) + p.eps);
+            }
+        }
+        PJTRY(knn_prune_round(ctx, nR, k, off, cand, ps));
+        for (int i : act)
+            if (ps[i].status != ST_UNDEC) ctx->stats.resolved_at_lod[lod]++;
+    }
+    ctx->stats.t_refine_ms = now_ms() - t1;
+    // finest LoD: exact FP64 distances of every candidate still in play
+    const double t2 = now_ms();
+    std::vector<int> fin;
+    for (int64_t i = 0; i < total; ++i)
+        if (ps[i].status == ST_UNDEC || ps[i].status == ST_CONF) {
+            fin.push_back((int)i);
+            ps[i].thr = INFINITY;
+        }
+    ctx->stats.rounds++;
+    if (plain) {
+        plan_tiles(R, S, fin, cand, ps, L - 1, 1, 64, TS, false, pl);
+        std::vector<ItemOut64> o64;
+        PJTRY(run_f64(ctx, R, S, pl, true, o64));
+        for (size_t q = 0; q < pl.items.size(); ++q) {
+            PairState &p = ps[pl.items[q].cand];
+            p.hit64 = o64[q].hit;
+            p.d64 = p.hit64 ? 0.0 : bits_to_double(o64[q].lb);
+        }
+    } else {
+        PJTRY(exact_finest(ctx, R, S, cand, ps, fin));
+    }
+    for (int i : fin) {
+        ps[i].LB = ps[i].UB = ps[i].d64;
+    }
+    const int undecided_before = (int)std::count_if(fin.begin(), fin.end(), [&](int i) { return ps[i].status == ST_UNDEC; });
+    PJTRY(knn_prune_round(ctx, nR, k, off, cand, ps));
+    ctx->stats.resolved_at_lod[L - 1] += undecided_before;
+    ctx->stats.t_band_ms = now_ms() - t2;
+    // results: confirmed candidates of each r ordered by (distance, id)
+    for (int r = 0; r < nR; ++r) {
+        std::vector<std::pair<double, int>> row;
+        for (int64_t i = off[r]; i < off[r + 1]; ++i) {
+            if (ps[i].status == ST_UNDEC) return fail(ctx, PJ_ERR_INTERNAL, "k-NN pruning left a candidate undecided");
+            if (ps[i].status == ST_CONF) row.push_back({ps[i].d64, cand[i].s});
+        }
+        std::sort(row.begin(), row.end());
+        const int want = std::min(k, nS);
+        if ((int)row.size() != want) return fail(ctx, PJ_ERR_INTERNAL, "k-NN confirmed count differs from min(k, |S|)");
+        out->count[r] = want;
+        for (int q = 0; q < want; ++q) {
+            out->s[(int64_t)r * k + q] = row[q].second;
+            out->dist[(int64_t)r * k + q] = row[q].first;
+        }
+    }
+    ctx->stats.peak_device_bytes = ctx->peak_bytes;
+    ctx->stats.t_total_ms = now_ms() - t0;
+    return PJ_OK;
 }
 
 extern "C" void pj_pairs_free(pj_pairs *p)

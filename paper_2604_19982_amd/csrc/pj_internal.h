@@ -51,19 +51,26 @@ struct ItemOut64 {
     int32_t hit, pad;
 };
 
+// A facet pair kept by the collect pass: (item, A facet, B facet).
+struct PairRef {
+    int32_t item, a, b, pad;
+};
+
 struct RefineArgs {
     MeshDev R, S;
     const Item *items;
     const Tile *tiles;
     const int32_t *ntiles;   // device count (fixed-capacity buffers)
-    int32_t *counter;        // persistent work counter
+    int32_t *counter;        // [0] collected pairs, [1] ntiles
     ItemOut *out;
     unsigned long long *pairs_done;  // facet pairs evaluated (device counter)
     unsigned long long *chunks_culled;
     float tau;               // within-tau threshold for early confirmation; < 0: none
     int32_t early;           // 1: stop an item once it is confirmed
     int32_t cull;            // 1: box-gap test per streamed chunk
-    int32_t pad;
+    int32_t collect_cap;     // collect mode: capacity of `collected`
+    PairRef *collected;      // collect mode: facet pairs with d_lo <= item.thr
+    int32_t *overflow;       // collect mode: per item, 1 if its pairs did not fit
 };
 
 struct Refine64Args {
@@ -90,6 +97,15 @@ hipError_t launch_scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t *tota
 hipError_t launch_init_out(ItemOut *out, int n, int32_t *counter, hipStream_t st);
 hipError_t launch_init_out64(ItemOut64 *out, int n, hipStream_t st);
 hipError_t launch_refine_f32(const RefineArgs &a, int grid, int P, hipStream_t st);
+hipError_t launch_collect_f32(const RefineArgs &a, int grid, hipStream_t st);
+hipError_t launch_pairs_f64(const MeshDev &R, const MeshDev &S, const Item *items, const PairRef *pairs, int64_t n,
+                            ItemOut64 *out, hipStream_t st);
+hipError_t launch_knn_theta(const float *ancR, int nR, const float *ancS, int nS, int k, float *theta, hipStream_t st);
+hipError_t launch_knn_cand(const float *boxR, const float *ancR, int nR, const float *boxS, const float *ancS, int nS,
+                           const float *theta, int32_t *count, const int64_t *off, int32_t *cs, float *clb,
+                           float *cub, int write_pass, hipStream_t st);
+hipError_t launch_knn_prune(int nR, const int64_t *off, const double *lb, const double *ub, const int32_t *ids,
+                            const int8_t *status_in, int8_t *status_out, const int32_t *k_left, hipStream_t st);
 hipError_t launch_refine_f64_tiles(const Refine64Args &a, int ntiles, hipStream_t st);
 hipError_t launch_refine_f64_plain(const Refine64Args &a, int nitems, hipStream_t st);
 hipError_t launch_facet_pairs(const float *t1, const float *t2, int64_t n, int prec, double *d, int8_t *hit,

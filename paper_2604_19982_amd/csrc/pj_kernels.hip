@@ -452,14 +452,14 @@ __device__ __forceinline__ Rec load_rec(const FacetSrc &s, int f, V3 o)
 // One tile.  Every branch below depends only on wave-uniform values (tile
 // and item fields loaded through a uniform index, readfirstlane'd flags), so
 // the compiler emits scalar control flow and the wave never splits.
-template <int P>
+template <int P, bool COLLECT>
 __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t, float4 *sh)
 {
     const int lane = threadIdx.x;
     const Tile tl = a.tiles[t];
     const Item it = a.items[tl.item];
     ItemOut *o = a.out + tl.item;
-    if (a.early &&
+    if (!COLLECT && a.early &&
         __builtin_amdgcn_readfirstlane(__hip_atomic_load(&o->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
         return;
     const bool swap = it.flags & IT_SWAP;
@@ -510,11 +510,20 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
                 lbm = fminf(lbm, fmaxf(dlo - (ra[p].ph + rb.ph), 0.0f));
                 ubm = fminf(ubm, pr.d + (ra[p].hd + rb.hd));
                 sure |= pr.sure ? 1 : 0;
+                if (COLLECT) {
+                    const int fa = tl.a0 + lane + 64 * p;
+                    // the pair realising the minimum has dlo <= d + eps <= ubm + 2 eps
+                    if (fa < SA.n && dlo <= fminf(it.thr, ubm + 2.0f * it.eps)) {
+                        const int slot = atomicAdd(a.counter, 1);
+                        if (slot < a.collect_cap) a.collected[slot] = PairRef{tl.item, fa, cb + k, 0};
+                        else a.overflow[tl.item] = 1;
+                    }
+                }
             }
         }
         cols += nb;
         __syncthreads();
-        if (a.early) {
+        if (!COLLECT && a.early) {
             const float wub = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wave_min(ubm))));
             const int ws = __builtin_amdgcn_readfirstlane(wave_or(sure));
             const bool confirm = (a.tau > 0.0f && wub + it.eps <= a.tau) || (finest && ws);
@@ -548,7 +557,23 @@ __global__ __launch_bounds__(64) void k_refine_f32(RefineArgs a)
 {
     __shared__ float4 sh[64 * 11];
     const int ntiles = *a.ntiles;
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) refine_tile_f32<P>(a, t, sh);
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) refine_tile_f32<P, false>(a, t, sh);
+}
+
+// Collect pass: the same tiles, keeping every facet pair whose FP32 lower
+// distance is at most the item's threshold (for the FP64 recheck).
+__global__ __launch_bounds__(64) void k_collect_f32(RefineArgs a)
+{
+    __shared__ float4 sh[64 * 11];
+    const int ntiles = *a.ntiles;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) refine_tile_f32<1, true>(a, t, sh);
+}
+
+hipError_t launch_collect_f32(const RefineArgs &a, int grid, hipStream_t st)
+{
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_collect_f32, dim3(grid), dim3(64), 0, st, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_refine_f32(const RefineArgs &a, int grid, int P, hipStream_t st)
@@ -688,6 +713,180 @@ hipError_t launch_refine_f64_plain(const Refine64Args &a, int nitems, hipStream_
 {
     if (nitems <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_refine_f64_plain, dim3(nitems), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FP64 recheck of collected facet pairs: exact meet test, FP64 distance,
+// 64-bit atomicMin per item.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_pairs_f64(MeshDev R, MeshDev S, const Item *items, const PairRef *pairs,
+                                                   int64_t n, ItemOut64 *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const PairRef pr = pairs[i];
+    const Item it = items[pr.item];
+    const bool swap = it.flags & IT_SWAP;
+    const FacetSrc SA = facet_src(swap ? S : R, it.a_obj, it.lod);
+    const FacetSrc SB = facet_src(swap ? R : S, it.b_obj, it.lod);
+    D3 A[3], B[3];
+    for (int c = 0; c < 3; ++c) {
+        A[c] = ld3d(SA.verts, SA.tris[3 * pr.a + c]);
+        B[c] = ld3d(SB.verts, SB.tris[3 * pr.b + c]);
+    }
+    bool h;
+    const double d = pair_f64(A, B, h);
+    ItemOut64 *o = out + pr.item;
+    atomicMin(&o->lb, (unsigned long long)__double_as_longlong(d));
+    atomicMin(&o->ub, (unsigned long long)__double_as_longlong(d));
+    if (h) atomicOr(&o->hit, 1);
+}
+
+hipError_t launch_pairs_f64(const MeshDev &R, const MeshDev &S, const Item *items, const PairRef *pairs, int64_t n,
+                            ItemOut64 *out, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pairs_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, R, S, items, pairs, n, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// k-NN candidates (Section 3.1, "MBB-based Object Filtering" for k-NN): the
+// k-th smallest anchor upper bound theta_r over S, found by bisection on the
+// float bit pattern (monotone for non-negative floats); then every s whose
+// box gap does not exceed theta_r.  One wave per r.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float anchor_ub(const float *ar, const float *as)
+{
+    float dx = as[0] - ar[0], dy = as[1] - ar[1], dz = as[2] - ar[2];
+    return __builtin_sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx))) * (1.0f + 0x1p-20f);
+}
+
+__global__ __launch_bounds__(64) void k_knn_theta(const float *ancR, int nR, const float *ancS, int nS, int k,
+                                                  float *theta)
+{
+    const int r = blockIdx.x;
+    const float *ar = ancR + 3 * (int64_t)r;
+    if (nS < k) {
+        if (threadIdx.x == 0) theta[r] = __builtin_inff();
+        return;
+    }
+    // invariant: count(ub <= hi) >= k; 32 halvings of [0, +inf bits] end with lo == hi
+    unsigned lo = 0u, hi = 0x7f800000u;
+    for (int step = 0; step < 32; ++step) {
+        const unsigned mid = lo + ((hi - lo) >> 1);
+        int cnt = 0;
+        for (int s = threadIdx.x; s < nS; s += 64) cnt += __float_as_uint(anchor_ub(ar, ancS + 3 * (int64_t)s)) <= mid;
+        for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+        cnt = __builtin_amdgcn_readfirstlane(cnt);
+        if (cnt >= k) hi = mid;
+        else lo = mid + 1;
+    }
+    if (threadIdx.x == 0) theta[r] = __uint_as_float(lo);
+}
+
+hipError_t launch_knn_theta(const float *ancR, int nR, const float *ancS, int nS, int k, float *theta, hipStream_t st)
+{
+    if (nR == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_knn_theta, dim3(nR), dim3(64), 0, st, ancR, nR, ancS, nS, k, theta);
+    return hipGetLastError();
+}
+
+__device__ __forceinline__ float box_gap(const float *b, const float *x)
+{
+    float gx = fmaxf(0.0f, fmaxf(x[0] - b[3], b[0] - x[3]));
+    float gy = fmaxf(0.0f, fmaxf(x[1] - b[4], b[1] - x[4]));
+    float gz = fmaxf(0.0f, fmaxf(x[2] - b[5], b[2] - x[5]));
+    return __builtin_sqrtf(fmaf(gz, gz, fmaf(gy, gy, gx * gx)));
+}
+
+// count pass: count[r]; write pass: survivors of r at off[r].. in s order
+__global__ __launch_bounds__(64) void k_knn_cand(const float *boxR, const float *ancR, int nR, const float *boxS,
+                                                 const float *ancS, int nS, const float *theta, int32_t *count,
+                                                 const int64_t *off, int32_t *cs, float *clb, float *cub,
+                                                 int write_pass)
+{
+    const int r = blockIdx.x;
+    const int lane = threadIdx.x;
+    const float *br = boxR + 6 * (int64_t)r;
+    const float th = theta[r];
+    int64_t pos = write_pass ? off[r] : 0;
+    int total = 0;
+    for (int s0 = 0; s0 < nS; s0 += 64) {
+        const int s = s0 + lane;
+        const float g = s < nS ? box_gap(br, boxS + 6 * (int64_t)s) * (1.0f - 0x1p-20f) : __builtin_inff();
+        const bool keep = s < nS && g <= th;
+        const unsigned long long m = __ballot(keep);
+        if (write_pass && keep) {
+            const int rank = __popcll(m & ((1ull << lane) - 1ull));
+            cs[pos + rank] = s;
+            clb[pos + rank] = g;
+            cub[pos + rank] = anchor_ub(ancR + 3 * (int64_t)r, ancS + 3 * (int64_t)s);
+        }
+        pos += __popcll(m);
+        total += __popcll(m);
+    }
+    if (!write_pass && lane == 0) count[r] = total;
+}
+
+hipError_t launch_knn_cand(const float *boxR, const float *ancR, int nR, const float *boxS, const float *ancS, int nS,
+                           const float *theta, int32_t *count, const int64_t *off, int32_t *cs, float *clb,
+                           float *cub, int write_pass, hipStream_t st)
+{
+    if (nR == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_knn_cand, dim3(nR), dim3(64), 0, st, boxR, ancR, nR, boxS, ancS, nS, theta, count, off, cs,
+                       clb, cub, write_pass);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// k-NN object-pair pruning (Algorithm 6, corrected): one workgroup per query
+// r.  From a snapshot of the undecided set U and kLeft = k - #confirmed:
+//   n surely precedes m  iff  ub_n < lb_m, or ub_n == lb_m and id_n < id_m;
+//   CONFIRM m if #{n in U\m : not (m surely precedes n)} < kLeft;
+//   REMOVE  m if #{n in U\m : n surely precedes m} >= kLeft.
+// Statuses are read from status_in and written to status_out.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_knn_prune(const int64_t *off, const double *lb, const double *ub,
+                                                   const int32_t *ids, const int8_t *status_in, int8_t *status_out,
+                                                   const int32_t *k_left)
+{
+    const int r = blockIdx.x;
+    const int64_t o = off[r];
+    const int N = (int)(off[r + 1] - o);
+    const int kl = k_left[r];
+    for (int m = threadIdx.x; m < N; m += 256) {
+        const int8_t st = status_in[o + m];
+        if (st != 0) {
+            status_out[o + m] = st;
+            continue;
+        }
+        if (kl <= 0) {
+            status_out[o + m] = 2;
+            continue;
+        }
+        const double lbm = lb[o + m], ubm = ub[o + m];
+        const int idm = ids[o + m];
+        int maybe = 0, surely = 0;
+        for (int n = 0; n < N; ++n) {
+            if (n == m || status_in[o + n] != 0) continue;
+            const double lbn = lb[o + n], ubn = ub[o + n];
+            const int idn = ids[o + n];
+            const bool m_first = ubm < lbn || (ubm == lbn && idm < idn);
+            const bool n_first = ubn < lbm || (ubn == lbm && idn < idm);
+            maybe += m_first ? 0 : 1;
+            surely += n_first ? 1 : 0;
+        }
+        status_out[o + m] = maybe < kl ? 1 : (surely >= kl ? 2 : 0);
+    }
+}
+
+hipError_t launch_knn_prune(int nR, const int64_t *off, const double *lb, const double *ub, const int32_t *ids,
+                            const int8_t *status_in, int8_t *status_out, const int32_t *k_left, hipStream_t st)
+{
+    if (nR == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_knn_prune, dim3(nR), dim3(256), 0, st, off, lb, ub, ids, status_in, status_out, k_left);
     return hipGetLastError();
 }
 
