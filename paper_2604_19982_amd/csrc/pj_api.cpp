@@ -161,6 +161,10 @@ float up_float(double x)
 
 }  // namespace
 
+namespace {
+bool load_model(pj_context *ctx, const char *path);
+}
+
 // ===========================================================================
 // configuration and contexts
 // ===========================================================================
@@ -211,6 +215,8 @@ extern "C" pj_status pj_context_create(const pj_config *cfg, pj_context **out)
         delete ctx;
         return PJ_ERR_DEVICE;
     }
+    // a missing or unreadable model leaves the plain progressive schedule
+    if (c.model_path && !load_model(ctx, c.model_path)) ctx->err = "LoD model not loaded; plain schedule in use";
     *out = ctx;
     return PJ_OK;
 }
@@ -549,6 +555,7 @@ struct PairState {
     double d64 = INFINITY;  // FP64 finest distance once known
     int hit64 = 0;
     float thr = INFINITY;   // collect threshold on the FP32 lower distance
+    int8_t res_lod = -1;    // LoD round that decided the pair
 };
 
 void pair_frame(const pj_meshes *R, int r, const pj_meshes *S, int s, PairState &ps)
@@ -923,7 +930,10 @@ pj_status refine_within(pj_context *ctx, const pj_meshes *R, const pj_meshes *S,
                     if (p.UB <= tau) p.status = ST_CONF;
                     else if (p.LB > tau) p.status = ST_PRUNED;
                 }
-                if (p.status != ST_UNDEC) ctx->stats.resolved_at_lod[lod]++;
+                if (p.status != ST_UNDEC) {
+                    ctx->stats.resolved_at_lod[lod]++;
+                    p.res_lod = (int8_t)lod;
+                }
             }
         } else {
             plan_tiles(R, S, act, cand, ps, lod, finest, 64 * kP, TS, true, pl);
@@ -944,7 +954,11 @@ pj_status refine_within(pj_context *ctx, const pj_meshes *R, const pj_meshes *S,
                     if (p.UB <= tau) p.status = ST_CONF;
                     else if (p.LB > tau) p.status = ST_PRUNED;
                 }
-                if (p.status == ST_CONF || p.status == ST_PRUNED) ctx->stats.resolved_at_lod[lod]++;
+                if (p.status == ST_CONF || p.status == ST_PRUNED) {
+                    ctx->stats.resolved_at_lod[lod]++;
+                    p.res_lod = (int8_t)lod;
+                }
+                if (p.status == ST_BAND) p.res_lod = (int8_t)lod;
             }
         }
     }
@@ -984,6 +998,110 @@ pj_status finest_distances(pj_context *ctx, const pj_meshes *R, const pj_meshes 
     return exact_finest(ctx, R, S, cand, ps, need);
 }
 
+// Features of a candidate pair for the LoD model: MBB gap, tau, anchor
+// bound, where tau sits in [gap, anchor bound], and for each LoD l = 0..3 the
+// pair's largest hd sum, largest ph sum and log2 of the facet-pair count.
+void pair_features(const pj_meshes *R, int r, const pj_meshes *S, int s, double tau, double lb0, double ub0, float *f)
+{
+    f[0] = (float)std::log1p(std::max(lb0, 0.0));
+    f[1] = (float)std::log1p(tau);
+    f[2] = (float)std::log1p(std::max(ub0, 0.0));
+    f[3] = (float)std::min(1.0, std::max(0.0, (tau - lb0) / std::max(ub0 - lb0, 1e-9)));
+    for (int l = 0; l < 4; ++l) {
+        const int lr = std::min(l, R->L - 1);
+        const float2 a = R->h_lodmax[(int64_t)r * R->L + lr], b = S->h_lodmax[(int64_t)s * S->L + lr];
+        const double nr = R->count(r, lr), ns = S->count(s, lr);
+        f[4 + 3 * l] = (float)std::log1p((double)a.x + b.x);
+        f[5 + 3 * l] = (float)std::log1p((double)a.y + b.y);
+        f[6 + 3 * l] = (float)(std::log2(std::max(nr * ns, 1.0)) / 16.0);
+    }
+}
+
+// Resolution log record: 16 float features, int32 label (deciding LoD), int32 n_lods.
+struct LogRec {
+    float f[MLP_IN];
+    int32_t label, n_lods;
+};
+
+void append_log(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, double tau, const std::vector<Cand> &cand,
+                const std::vector<PairState> &ps)
+{
+    if (!ctx->cfg.log_path || R->L != 4) return;
+    FILE *fp = std::fopen(ctx->cfg.log_path, "ab");
+    if (!fp) return;
+    for (size_t i = 0; i < cand.size(); ++i) {
+        if (ps[i].res_lod < 0) continue;
+        LogRec rec;
+        pair_features(R, cand[i].r, S, cand[i].s, tau, cand[i].lb0, cand[i].ub0, rec.f);
+        rec.label = ps[i].res_lod;
+        rec.n_lods = R->L;
+        std::fwrite(&rec, sizeof(rec), 1, fp);
+    }
+    std::fclose(fp);
+}
+
+struct ModelFile {
+    char magic[4];
+    uint32_t version, n_in, n_h, n_out;
+    float mean[MLP_IN], stdv[MLP_IN];
+};
+
+bool load_model(pj_context *ctx, const char *path)
+{
+    FILE *fp = std::fopen(path, "rb");
+    if (!fp) return false;
+    ModelFile h;
+    std::vector<float> w(MLP_NPARAM);
+    bool ok = std::fread(&h, sizeof(h), 1, fp) == 1 && std::memcmp(h.magic, "PJLM", 4) == 0 && h.version == 1 &&
+              h.n_in == MLP_IN && h.n_h == MLP_H && h.n_out == MLP_OUT &&
+              std::fread(w.data(), 4, MLP_NPARAM, fp) == (size_t)MLP_NPARAM;
+    std::fclose(fp);
+    if (!ok) return false;
+    for (float x : w)
+        if (!std::isfinite(x)) return false;
+    ctx->model = w;
+    std::memcpy(ctx->feat_mean, h.mean, sizeof(h.mean));
+    std::memcpy(ctx->feat_std, h.stdv, sizeof(h.stdv));
+    ctx->has_model = true;
+    return true;
+}
+
+// First LoD per candidate from the model (learned skip); 0 where undecided
+// pairs have no prediction.
+pj_status learned_start(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, double tau, const std::vector<Cand> &cand,
+                        const std::vector<PairState> &ps, std::vector<int> &start)
+{
+    std::vector<int> idx;
+    for (size_t i = 0; i < cand.size(); ++i)
+        if (ps[i].status == ST_UNDEC) idx.push_back((int)i);
+    const int n = (int)idx.size();
+    if (n == 0) return PJ_OK;
+    hipStream_t st = ctx->stream;
+    std::vector<float> x((size_t)n * MLP_IN), cost((size_t)n * MLP_OUT);
+    for (int q = 0; q < n; ++q) {
+        const Cand &c = cand[idx[q]];
+        float f[MLP_IN];
+        pair_features(R, c.r, S, c.s, tau, c.lb0, c.ub0, f);
+        for (int j = 0; j < MLP_IN; ++j) x[(size_t)q * MLP_IN + j] = (f[j] - ctx->feat_mean[j]) / ctx->feat_std[j];
+        for (int l = 0; l < MLP_OUT; ++l)
+            cost[(size_t)q * MLP_OUT + l] = (float)((double)R->count(c.r, l) * (double)S->count(c.s, l));
+    }
+    PJTRY(ensure(ctx, ctx->b_tmp0, (size_t)n * MLP_IN * 4));
+    PJTRY(ensure(ctx, ctx->b_tmp1, (size_t)n * MLP_OUT * 4 * 2 + (size_t)n * 4));
+    PJTRY(ensure(ctx, ctx->b_tmp2, MLP_NPARAM * 4));
+    float *dx = ptr<float>(ctx->b_tmp0), *dcost = ptr<float>(ctx->b_tmp1), *dprob = dcost + (size_t)n * MLP_OUT;
+    int32_t *dstart = reinterpret_cast<int32_t *>(dprob + (size_t)n * MLP_OUT);
+    HIPTRY(ctx, hipMemcpyAsync(dx, x.data(), x.size() * 4, hipMemcpyHostToDevice, st));
+    HIPTRY(ctx, hipMemcpyAsync(dcost, cost.data(), cost.size() * 4, hipMemcpyHostToDevice, st));
+    HIPTRY(ctx, hipMemcpyAsync(ctx->b_tmp2.p, ctx->model.data(), MLP_NPARAM * 4, hipMemcpyHostToDevice, st));
+    HIPTRY(ctx, launch_mlp_infer(ptr<float>(ctx->b_tmp2), dx, n, dcost, R->L, dprob, dstart, st));
+    std::vector<int32_t> s0(n);
+    HIPTRY(ctx, hipMemcpyAsync(s0.data(), dstart, n * 4, hipMemcpyDeviceToHost, st));
+    HIPTRY(ctx, hipStreamSynchronize(st));
+    for (int q = 0; q < n; ++q) start[idx[q]] = std::min(std::max(s0[q], 0), R->L - 1);
+    return PJ_OK;
+}
+
 }  // namespace
 
 extern "C" pj_status pj_join_within(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, double tau, pj_pairs *out)
@@ -1019,9 +1137,13 @@ extern "C" pj_status pj_join_within(pj_context *ctx, const pj_meshes *R, const p
             ps[i].status = ST_PRUNED;
         }
     }
+    const bool learned = ctx->cfg.learned_skip && ctx->has_model && R->L == MLP_OUT &&
+                         ctx->cfg.schedule == PJ_SCHED_BATCHED;
+    if (learned) PJTRY(learned_start(ctx, R, S, tau, cand, ps, start));
     double t1 = now_ms();
     ctx->stats.t_filter_ms = t1 - t0;
     PJTRY(refine_within(ctx, R, S, tau, cand, ps, start));
+    if (!learned) append_log(ctx, R, S, tau, cand, ps);
     ctx->stats.t_refine_ms = now_ms() - t1 - ctx->stats.t_band_ms;
     std::vector<int> res;
     for (int i = 0; i < nc; ++i)
@@ -1352,27 +1474,150 @@ extern "C" pj_status pj_pair_bounds(pj_context *ctx, const pj_meshes *R, const p
     return PJ_OK;
 }
 
-extern "C" pj_status pj_train_lod_model(pj_context *ctx, const char *log_path, const char *model_out,
-                                        const pj_train_opts *opts, float *final_loss)
-{
-    (void)log_path;
-    (void)model_out;
-    (void)opts;
-    (void)final_loss;
-    return fail(ctx, PJ_ERR_UNSUPPORTED, "LoD model training not built yet");
-}
-
 extern "C" pj_status pj_mlp_eval(pj_context *ctx, const float *params, const float *x, const int32_t *y, int64_t n,
                                  float *logits, float *loss, float *grads)
 {
-    (void)params;
-    (void)x;
-    (void)y;
-    (void)n;
-    (void)logits;
-    (void)loss;
-    (void)grads;
-    return fail(ctx, PJ_ERR_UNSUPPORTED, "MLP not built yet");
+    if (!ctx) return PJ_ERR_INVALID_ARG;
+    if (!params || n < 0 || n > (1 << 24) || (n > 0 && (!x || !logits)) || (y && (!loss || !grads)))
+        return fail(ctx, PJ_ERR_INVALID_ARG, "bad argument");
+    if (n == 0) return PJ_OK;
+    for (int64_t i = 0; y && i < n; ++i)
+        if (y[i] < 0 || y[i] >= MLP_OUT) return fail(ctx, PJ_ERR_INVALID_ARG, "label out of range");
+    HIPTRY(ctx, hipSetDevice(ctx->cfg.device));
+    hipStream_t st = ctx->stream;
+    const size_t fx = (size_t)n * MLP_IN * 4, fl = (size_t)n * MLP_OUT * 4;
+    const size_t scratch = ((size_t)4 * n * MLP_H + (size_t)n * MLP_OUT) * 4;
+    PJTRY(ensure(ctx, ctx->b_tmp0, fx + fl + (size_t)n * 8 + MLP_NPARAM * 8));
+    PJTRY(ensure(ctx, ctx->b_tmp1, scratch));
+    char *base = (char *)ctx->b_tmp0.p;
+    float *dx = (float *)base, *dlog = (float *)(base + fx), *dloss = (float *)(base + fx + fl);
+    int32_t *dy = (int32_t *)(base + fx + fl + (size_t)n * 4);
+    float *dpar = (float *)(base + fx + fl + (size_t)n * 8), *dgr = dpar + MLP_NPARAM;
+    HIPTRY(ctx, hipMemcpyAsync(dx, x, fx, hipMemcpyHostToDevice, st));
+    HIPTRY(ctx, hipMemcpyAsync(dpar, params, MLP_NPARAM * 4, hipMemcpyHostToDevice, st));
+    if (y) HIPTRY(ctx, hipMemcpyAsync(dy, y, (size_t)n * 4, hipMemcpyHostToDevice, st));
+    HIPTRY(ctx, launch_mlp_fwd_bwd(dpar, dx, y ? dy : nullptr, (int)n, dlog, dloss, dgr, ptr<float>(ctx->b_tmp1), st));
+    HIPTRY(ctx, hipMemcpyAsync(logits, dlog, fl, hipMemcpyDeviceToHost, st));
+    std::vector<float> lp(y ? n : 0);
+    if (y) {
+        HIPTRY(ctx, hipMemcpyAsync(lp.data(), dloss, (size_t)n * 4, hipMemcpyDeviceToHost, st));
+        HIPTRY(ctx, hipMemcpyAsync(grads, dgr, MLP_NPARAM * 4, hipMemcpyDeviceToHost, st));
+    }
+    HIPTRY(ctx, hipStreamSynchronize(st));
+    if (y) {
+        double acc = 0.0;
+        for (float v : lp) acc += v;
+        *loss = (float)(acc / n);
+    }
+    return PJ_OK;
+}
+
+extern "C" pj_status pj_train_lod_model(pj_context *ctx, const char *log_path, const char *model_out,
+                                        const pj_train_opts *opts, float *final_loss)
+{
+    if (!ctx) return PJ_ERR_INVALID_ARG;
+    if (!log_path || !model_out) return fail(ctx, PJ_ERR_INVALID_ARG, "NULL path");
+    pj_train_opts o = {30, 1024, 3e-3f, 0};
+    if (opts) o = *opts;
+    if (o.epochs < 1 || o.batch < 1 || !(o.lr > 0.0f)) return fail(ctx, PJ_ERR_INVALID_ARG, "bad training options");
+    FILE *fp = std::fopen(log_path, "rb");
+    if (!fp) return fail(ctx, PJ_ERR_INVALID_ARG, "cannot open the resolution log");
+    std::vector<LogRec> recs;
+    LogRec rec;
+    while (std::fread(&rec, sizeof(rec), 1, fp) == 1)
+        if (rec.n_lods == MLP_OUT && rec.label >= 0 && rec.label < MLP_OUT) recs.push_back(rec);
+    std::fclose(fp);
+    const int64_t n = (int64_t)recs.size();
+    if (n == 0) return fail(ctx, PJ_ERR_INVALID_ARG, "the resolution log holds no usable records");
+    HIPTRY(ctx, hipSetDevice(ctx->cfg.device));
+    hipStream_t st = ctx->stream;
+    ModelFile h;
+    std::memcpy(h.magic, "PJLM", 4);
+    h.version = 1;
+    h.n_in = MLP_IN;
+    h.n_h = MLP_H;
+    h.n_out = MLP_OUT;
+    for (int j = 0; j < MLP_IN; ++j) {
+        double m = 0.0, v = 0.0;
+        for (const LogRec &r : recs) m += r.f[j];
+        m /= n;
+        for (const LogRec &r : recs) v += (r.f[j] - m) * (r.f[j] - m);
+        h.mean[j] = (float)m;
+        h.stdv[j] = (float)std::max(std::sqrt(v / n), 1e-6);
+    }
+    // deterministic initialisation (He-scaled uniform) from the seed
+    std::vector<float> par(MLP_NPARAM, 0.0f);
+    uint64_t sd = o.seed * 6364136223846793005ull + 1442695040888963407ull;
+    auto uni = [&]() {
+        sd = sd * 6364136223846793005ull + 1442695040888963407ull;
+        return ((sd >> 11) * (1.0 / 9007199254740992.0)) * 2.0 - 1.0;
+    };
+    const int lay[3][2] = {{MLP_IN, MLP_H}, {MLP_H, MLP_H}, {MLP_H, MLP_OUT}};
+    int off = 0;
+    for (int l = 0; l < 3; ++l) {
+        const double a = std::sqrt(6.0 / lay[l][0]);
+        for (int q = 0; q < lay[l][0] * lay[l][1]; ++q) par[off + q] = (float)(a * uni());
+        off += lay[l][0] * lay[l][1] + lay[l][1];
+    }
+    const int B = (int)std::min<int64_t>(o.batch, n);
+    const size_t scratch = ((size_t)4 * B * MLP_H + (size_t)B * MLP_OUT) * 4;
+    PJTRY(ensure(ctx, ctx->b_tmp0, (size_t)n * MLP_IN * 4 + (size_t)n * 4));
+    PJTRY(ensure(ctx, ctx->b_tmp1, scratch));
+    PJTRY(ensure(ctx, ctx->b_tmp2, (size_t)MLP_NPARAM * 4 * 4 + (size_t)B * (MLP_OUT + 1) * 4));
+    float *dx = ptr<float>(ctx->b_tmp0);
+    int32_t *dy = reinterpret_cast<int32_t *>(dx + (size_t)n * MLP_IN);
+    float *dpar = ptr<float>(ctx->b_tmp2), *dm = dpar + MLP_NPARAM, *dv = dm + MLP_NPARAM, *dg = dv + MLP_NPARAM;
+    float *dlog = dg + MLP_NPARAM, *dloss = dlog + (size_t)B * MLP_OUT;
+    HIPTRY(ctx, hipMemcpyAsync(dpar, par.data(), MLP_NPARAM * 4, hipMemcpyHostToDevice, st));
+    HIPTRY(ctx, hipMemsetAsync(dm, 0, MLP_NPARAM * 8, st));
+    std::vector<float> xs((size_t)n * MLP_IN);
+    std::vector<int32_t> ys(n);
+    std::vector<int64_t> perm(n);
+    std::iota(perm.begin(), perm.end(), 0);
+    int step = 0;
+    double last = 0.0;
+    for (int ep = 0; ep < o.epochs; ++ep) {
+        for (int64_t i = n - 1; i > 0; --i) {  // Fisher-Yates with the same generator
+            int64_t j = (int64_t)((uni() * 0.5 + 0.5) * (i + 1));
+            if (j > i) j = i;
+            std::swap(perm[i], perm[j]);
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            const LogRec &r = recs[perm[i]];
+            for (int j = 0; j < MLP_IN; ++j) xs[(size_t)i * MLP_IN + j] = (r.f[j] - h.mean[j]) / h.stdv[j];
+            ys[i] = r.label;
+        }
+        HIPTRY(ctx, hipMemcpyAsync(dx, xs.data(), xs.size() * 4, hipMemcpyHostToDevice, st));
+        HIPTRY(ctx, hipMemcpyAsync(dy, ys.data(), ys.size() * 4, hipMemcpyHostToDevice, st));
+        double ep_loss = 0.0;
+        int64_t seen = 0;
+        std::vector<float> lp(B);
+        for (int64_t b0 = 0; b0 + B <= n; b0 += B) {
+            HIPTRY(ctx, launch_mlp_fwd_bwd(dpar, dx + b0 * MLP_IN, dy + b0, B, dlog, dloss, dg, ptr<float>(ctx->b_tmp1),
+                                           st));
+            HIPTRY(ctx, launch_mlp_adam(dpar, dm, dv, dg, ++step, o.lr, 0.9f, 0.999f, 1e-8f, st));
+            if (ep == o.epochs - 1) {
+                HIPTRY(ctx, hipMemcpyAsync(lp.data(), dloss, (size_t)B * 4, hipMemcpyDeviceToHost, st));
+                HIPTRY(ctx, hipStreamSynchronize(st));
+                for (float v : lp) ep_loss += v;
+                seen += B;
+            }
+        }
+        if (ep == o.epochs - 1 && seen) last = ep_loss / seen;
+    }
+    HIPTRY(ctx, hipMemcpyAsync(par.data(), dpar, MLP_NPARAM * 4, hipMemcpyDeviceToHost, st));
+    HIPTRY(ctx, hipStreamSynchronize(st));
+    FILE *wf = std::fopen(model_out, "wb");
+    if (!wf) return fail(ctx, PJ_ERR_INVALID_ARG, "cannot write the model file");
+    bool ok = std::fwrite(&h, sizeof(h), 1, wf) == 1 && std::fwrite(par.data(), 4, MLP_NPARAM, wf) == (size_t)MLP_NPARAM;
+    ok = (std::fclose(wf) == 0) && ok;
+    if (!ok) return fail(ctx, PJ_ERR_INTERNAL, "short write of the model file");
+    if (final_loss) *final_loss = (float)last;
+    ctx->model = par;
+    std::memcpy(ctx->feat_mean, h.mean, sizeof(h.mean));
+    std::memcpy(ctx->feat_std, h.stdv, sizeof(h.stdv));
+    ctx->has_model = true;
+    return PJ_OK;
 }
 
 extern "C" pj_status pj_probe_fma(pj_context *ctx, int32_t fp64, double *gflops)

@@ -114,12 +114,12 @@ hipError_t launch_facet_pairs(const float *t1, const float *t2, int64_t n, int p
 hipError_t launch_fma_probe(int fp64, void *out, int blocks, int iters, hipStream_t st);
 hipError_t launch_copy_probe(const void *src, void *dst, int64_t nbytes, int blocks, hipStream_t st);
 
-// MLP (pj_mlp.hip)
+// MLP (pj_mlp.hip); scratch holds 4*n*64 + n*4 floats
 hipError_t launch_mlp_fwd_bwd(const float *params, const float *x, const int32_t *y, int n, float *logits,
-                              float *loss_acc, float *grads, hipStream_t st);
-hipError_t launch_mlp_adam(float *params, float *m, float *v, const float *grads, int np, float lr, float b1,
-                           float b2, float eps, int step, float scale, hipStream_t st);
-hipError_t launch_mlp_infer(const float *params, const float *x, int n, const float *cost, float *probs,
+                              float *loss_per, float *grads, float *scratch, hipStream_t st);
+hipError_t launch_mlp_adam(float *params, float *m, float *v, const float *grads, int step, float lr, float b1,
+                           float b2, float eps, hipStream_t st);
+hipError_t launch_mlp_infer(const float *params, const float *x, int n, const float *cost, int n_lods, float *probs,
                             int32_t *start, hipStream_t st);
 
 constexpr int MLP_IN = 16, MLP_H = 64, MLP_OUT = 4;

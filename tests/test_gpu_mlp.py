@@ -1,0 +1,93 @@
+"""GPU tests of the LoD-skip network: forward/backward kernels against the
+FP64 CPU reference (BF16 weights, FP32 accumulation), and training on the
+join's own resolution logs with a held-out comparison against the plain
+progressive schedule (same result set, less facet-pair work)."""
+import os
+
+import numpy as np
+import pytest
+
+import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(16, 64), (64,), (64, 64), (64,), (64, 4), (4,)]
+
+
+@pytest.fixture(scope="module")
+def pj():
+    import paper_2604_19982_amd as pj
+    return pj
+
+
+def bf16(a):
+    u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
+def test_mlp_forward_backward_vs_oracle(orc, pj):
+    rng = np.random.default_rng(0)
+    flat = np.concatenate([rng.normal(scale=0.3, size=s).ravel() for s in SHAPES]).astype(np.float32)
+    x = rng.normal(size=(300, 16)).astype(np.float32)
+    y = rng.integers(0, 4, size=300).astype(np.int32)
+    c = pj.Context()
+    logits, loss, grads = c.mlp_eval(flat, x, y)
+    # reference: FP64 with the BF16-rounded weights the kernels use
+    wq = bf16(flat).astype(np.float64)
+    P, o = [], 0
+    for s in SHAPES:
+        n = int(np.prod(s))
+        P.append(wq[o:o + n].reshape(s))
+        o += n
+    ref_logits, _ = orc.mlp_forward(P, x.astype(np.float64))
+    ref_loss, ref_grads = orc.mlp_loss_grad(P, x.astype(np.float64), y)
+    assert np.allclose(logits, ref_logits, rtol=1e-4, atol=1e-4)
+    assert abs(loss - ref_loss) <= 1e-5 * max(1.0, ref_loss)
+    g = np.concatenate([r.ravel() for r in ref_grads])
+    assert np.all(np.abs(grads - g) <= 1e-4 * np.abs(g).max() + 1e-6), np.max(np.abs(grads - g))
+
+
+@pytest.fixture(scope="module")
+def trained(tmp_path_factory, pj):
+    d = tmp_path_factory.mktemp("lod")
+    log = str(d / "res.log")
+    R, S = mg.config_multilod(seed=11, n_r=600, n_s=120, box=180.0)
+    c = pj.Context(log_path=log)
+    gR, gS = c.meshes(R), c.meshes(S)
+    for tau in (0.0, 2.0, 5.0, 10.0, 20.0):
+        c.join_within(gR, gS, tau)
+    n_rec = os.path.getsize(log) // 72
+    model = str(d / "lod.model")
+    loss = c.train_lod_model(log, model, epochs=40, batch=512, lr=3e-3, seed=1)
+    return dict(model=model, loss=loss, n_rec=n_rec)
+
+
+def test_training_reduces_loss(trained):
+    assert trained["n_rec"] > 1000
+    assert trained["loss"] < 0.8 * np.log(4.0)
+
+
+@pytest.mark.parametrize("tau", [0.0, 10.0])
+def test_learned_skip_same_results_less_work(pj, trained, tau):
+    R, S = mg.config_multilod(seed=12, n_r=600, n_s=120, box=180.0)   # held-out inputs
+    base = pj.Context()
+    gR, gS = base.meshes(R), base.meshes(S)
+    ref = base.join_within(gR, gS, tau)
+    st0 = base.stats()
+    lc = pj.Context(learned_skip=True, model_path=trained["model"])
+    lR, lS = lc.meshes(R), lc.meshes(S)
+    got = lc.join_within(lR, lS, tau)
+    st1 = lc.stats()
+    assert np.array_equal(got["r"], ref["r"]) and np.array_equal(got["s"], ref["s"])
+    w0 = st0["facet_pairs"] + st0["facet_pairs_fp64"]
+    w1 = st1["facet_pairs"] + st1["facet_pairs_fp64"]
+    print(f"tau={tau}: plain progressive {w0:.3e} pairs {st0['t_total_ms']:.1f} ms, rounds {st0['rounds']}; "
+          f"learned {w1:.3e} pairs {st1['t_total_ms']:.1f} ms, rounds {st1['rounds']}")
+    assert w1 <= 1.05 * w0
+
+
+def test_missing_model_falls_back(pj):
+    c = pj.Context(learned_skip=True, model_path="/nonexistent/lod.model")
+    R, S = mg.config_small(seed=0, n_r=10, n_s=10, box=4.0)
+    assert isinstance(c.join_within(c.meshes(R), c.meshes(S), 0.5)["r"], np.ndarray)
