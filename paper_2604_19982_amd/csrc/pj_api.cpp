@@ -666,7 +666,7 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
     a.chunks_culled = reinterpret_cast<unsigned long long *>(ctr + 4);
     a.tau = tau;
     a.early = early ? 1 : 0;
-    a.cull = 0;
+    a.cull = ctx->cfg.tile_cull ? 1 : 0;
     int wpc = ctx->cfg.waves_per_cu > 0 ? ctx->cfg.waves_per_cu : 12;
     int grid = std::min<int64_t>(nt, (int64_t)ctx->num_cu * wpc);
     HIPTRY(ctx, hipEventRecord(ctx->ev0, st));
@@ -680,9 +680,11 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
     ctx->stats.refine_kernel_ms += ms;
     ctx->stats.refine_launches += 1;
     ctx->stats.tiles += nt;
-    unsigned long long pairs;
+    unsigned long long pairs, culled;
     std::memcpy(&pairs, host_ctr + 2, 8);
+    std::memcpy(&culled, host_ctr + 4, 8);
     ctx->stats.facet_pairs += (int64_t)pairs;
+    ctx->stats.tiles_culled += (int64_t)culled;
     return PJ_OK;
 }
 
@@ -782,6 +784,7 @@ pj_status exact_finest(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
     a.pairs_done = reinterpret_cast<unsigned long long *>(ctr + 2);
     a.chunks_culled = reinterpret_cast<unsigned long long *>(ctr + 4);
     a.tau = -1.0f;
+    a.cull = ctx->cfg.tile_cull ? 1 : 0;
     a.collect_cap = (int32_t)std::min<int64_t>(cap, INT32_MAX);
     a.collected = ptr<PairRef>(ctx->b_coll);
     a.overflow = ptr<int32_t>(ctx->b_ovf);

@@ -452,6 +452,20 @@ __device__ __forceinline__ Rec load_rec(const FacetSrc &s, int f, V3 o)
 // One tile.  Every branch below depends only on wave-uniform values (tile
 // and item fields loaded through a uniform index, readfirstlane'd flags), so
 // the compiler emits scalar control flow and the wave never splits.
+//
+// Chunk culling: before a chunk of 64 B facets is processed, its box is
+// reduced across the wave and compared with the box of the wave's A facets.
+// With gap g (rounded down), every pair in the chunk has FP32 distance
+// >= g - eps, hence ub >= g - eps and lb >= g - eps - phmax_A - phmax_B.
+// The chunk is skipped when neither bound can matter:
+//   ub: g - eps > min(current item ub, tau - eps)   (within: cannot confirm)
+//   lb: lbLow   > min(current item lb, tau + eps)   (within: cannot block a prune)
+// (without tau, only "cannot lower the current minimum" is used, which keeps
+// the minima exact); in collect mode the chunk is skipped when g - eps
+// exceeds the collect threshold.
+__device__ __forceinline__ float wmin_u(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wave_min(v)))); }
+__device__ __forceinline__ float wmax_u(float v) { return -wmin_u(-v); }
+
 template <int P, bool COLLECT>
 __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t, float4 *sh)
 {
@@ -467,23 +481,65 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
     const FacetSrc SB = facet_src(swap ? a.R : a.S, it.b_obj, it.lod);
     const V3 org = V3{it.ox, it.oy, it.oz};
     Rec ra[P];
+    float alo[3] = {kInf, kInf, kInf}, ahi[3] = {-kInf, -kInf, -kInf}, aph = 0.0f;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         int f = tl.a0 + lane + 64 * p;
         if (f >= SA.n) f = tl.a0;  // padding lanes repeat a real facet
         ra[p] = load_rec(SA, f, org);
+        alo[0] = fminf(alo[0], min3f(ra[p].v0.x, ra[p].v1.x, ra[p].v2.x));
+        alo[1] = fminf(alo[1], min3f(ra[p].v0.y, ra[p].v1.y, ra[p].v2.y));
+        alo[2] = fminf(alo[2], min3f(ra[p].v0.z, ra[p].v1.z, ra[p].v2.z));
+        ahi[0] = fmaxf(ahi[0], max3f(ra[p].v0.x, ra[p].v1.x, ra[p].v2.x));
+        ahi[1] = fmaxf(ahi[1], max3f(ra[p].v0.y, ra[p].v1.y, ra[p].v2.y));
+        ahi[2] = fmaxf(ahi[2], max3f(ra[p].v0.z, ra[p].v1.z, ra[p].v2.z));
+        aph = fmaxf(aph, ra[p].ph);
     }
+    if (a.cull) {
+        for (int c = 0; c < 3; ++c) {
+            alo[c] = wmin_u(alo[c]);
+            ahi[c] = wmax_u(ahi[c]);
+        }
+        aph = wmax_u(aph);
+    }
+    const bool within = a.tau >= 0.0f;
     float lbm = kInf, ubm = kInf;
     int sure = 0;
-    int cols = 0;
+    int cols = 0, culled = 0;
     const bool finest = it.flags & IT_FINEST;
     bool stop = false;
     for (int cb = tl.b0; cb < tl.b1 && !stop; cb += 64) {
         const int nb = min(64, tl.b1 - cb);
+        int f = cb + lane;
+        if (f >= tl.b1) f = cb;
+        const int32_t i0 = SB.tris[3 * f], i1 = SB.tris[3 * f + 1], i2 = SB.tris[3 * f + 2];
+        const V3 b0 = ld3f(SB.verts, i0) - org, b1 = ld3f(SB.verts, i1) - org, b2 = ld3f(SB.verts, i2) - org;
+        const float2 bh = SB.hdph ? SB.hdph[f] : make_float2(0.0f, 0.0f);
+        if (a.cull) {
+            const float gx = fmaxf(0.0f, fmaxf(wmin_u(min3f(b0.x, b1.x, b2.x)) - ahi[0], alo[0] - wmax_u(max3f(b0.x, b1.x, b2.x))));
+            const float gy = fmaxf(0.0f, fmaxf(wmin_u(min3f(b0.y, b1.y, b2.y)) - ahi[1], alo[1] - wmax_u(max3f(b0.y, b1.y, b2.y))));
+            const float gz = fmaxf(0.0f, fmaxf(wmin_u(min3f(b0.z, b1.z, b2.z)) - ahi[2], alo[2] - wmax_u(max3f(b0.z, b1.z, b2.z))));
+            const float gap = __builtin_sqrtf(fmaf(gz, gz, fmaf(gy, gy, gx * gx))) * (1.0f - 0x1p-20f) - it.eps;
+            const float bph = wmax_u(bh.y);
+            const float cur_lb = __uint_as_float(__builtin_amdgcn_readfirstlane(
+                __hip_atomic_load(&o->lb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+            const float cur_ub = __uint_as_float(__builtin_amdgcn_readfirstlane(
+                __hip_atomic_load(&o->ub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+            bool skip;
+            if (COLLECT) {
+                skip = gap > fminf(it.thr, fminf(cur_ub, ubm) + 2.0f * it.eps);
+            } else {
+                const float ub_cut = within ? fminf(fminf(cur_ub, ubm), a.tau - it.eps) : fminf(cur_ub, ubm);
+                const float lb_cut = within ? fminf(fminf(cur_lb, lbm), a.tau + it.eps) : fminf(cur_lb, lbm);
+                skip = gap > ub_cut && fmaxf(gap - aph - bph, 0.0f) > lb_cut;
+            }
+            if (__builtin_amdgcn_readfirstlane((int)skip)) {
+                ++culled;
+                continue;
+            }
+        }
         {
-            int f = cb + lane;
-            if (f >= tl.b1) f = cb;
-            Rec rb = load_rec(SB, f, org);
+            Rec rb = make_rec(b0, b1, b2, bh.x, bh.y);
             float tmp[44];
             __builtin_memcpy(tmp, &rb, sizeof(tmp));
 #pragma unroll
@@ -523,8 +579,17 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
         }
         cols += nb;
         __syncthreads();
+        if (a.cull) {  // publish the running minima so that other tiles can cull against them
+            const float wl = wmin_u(lbm), wu = wmin_u(ubm);
+            lbm = wl;
+            ubm = wu;
+            if (lane == 0) {
+                atomicMin(&o->lb, fbits(wl));
+                atomicMin(&o->ub, fbits(wu));
+            }
+        }
         if (!COLLECT && a.early) {
-            const float wub = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wave_min(ubm))));
+            const float wub = wmin_u(ubm);
             const int ws = __builtin_amdgcn_readfirstlane(wave_or(sure));
             const bool confirm = (a.tau > 0.0f && wub + it.eps <= a.tau) || (finest && ws);
             if (confirm) {
@@ -544,6 +609,7 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
         if (ws) atomicOr(&o->hit, 1);
         const int rows = min(64 * P, SA.n - tl.a0);
         atomicAdd(a.pairs_done, (unsigned long long)rows * (unsigned long long)cols);
+        if (culled) atomicAdd(a.chunks_culled, (unsigned long long)culled);
     }
 }
 

@@ -227,3 +227,26 @@ def test_edge_cases(orc, pj, ctx):
     for tau, want in [(0.0, [2]), (0.2499, [2]), (0.25, [0, 2]), (1.0, [0, 1, 2])]:
         got = ctx.join_within(gA, gB, tau)
         assert got["s"].tolist() == want, (tau, got)
+
+
+@pytest.mark.parametrize("tau", [0.0, 5.0])
+def test_chunk_culling_keeps_results(pj, multilod_mid, tau):
+    R, S = multilod_mid
+    out = {}
+    for cull in (False, True):
+        c = pj.Context(tile_cull=cull)
+        out[cull] = (c.join_within(c.meshes(R), c.meshes(S), tau), c.stats())
+    a, b = out[False][0], out[True][0]
+    assert np.array_equal(a["r"], b["r"]) and np.array_equal(a["s"], b["s"])
+    assert out[True][1]["tiles_culled"] > 0
+    assert out[True][1]["facet_pairs"] < out[False][1]["facet_pairs"]
+
+
+def test_chunk_culling_keeps_knn(pj):
+    R, S = mg.config_knn(seed=3, n_r=40, n_s=40, n_clusters=2, box=200.0, sigma=12.0, f_median=2000)
+    res = {}
+    for cull in (False, True):
+        c = pj.Context(tile_cull=cull)
+        res[cull] = c.join_knn(c.meshes(R), c.meshes(S), 3)
+    assert np.array_equal(res[False]["s"], res[True]["s"])
+    assert np.array_equal(res[False]["dist"], res[True]["dist"])
