@@ -87,6 +87,14 @@ struct pj_context {
     DevBuf b_items, b_tiles, b_out, b_out64, b_ctr, b_cand_r, b_cand_s, b_cand_lb, b_cand_ub, b_blk, b_blkoff,
         b_total, b_tmp0, b_tmp1, b_tmp2, b_tmp3, b_coll, b_ovf, b_theta, b_koff, b_klb, b_kub, b_kst0, b_kst1,
         b_kleft;
+    // captured FP32 rounds, keyed by their kernel arguments
+    struct GraphEntry {
+        std::vector<char> key;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<GraphEntry> graphs;
+    hipStream_t cap_stream = nullptr;
+    int64_t graph_replays = 0;
     // LoD model (learned skip)
     std::vector<float> model;
     float feat_mean[MLP_IN], feat_std[MLP_IN];
@@ -226,6 +234,9 @@ extern "C" pj_status pj_context_destroy(pj_context *ctx)
     if (!ctx) return PJ_ERR_INVALID_ARG;
     (void)hipSetDevice(ctx->cfg.device);
     (void)hipStreamSynchronize(ctx->stream);
+    for (auto &g : ctx->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
@@ -650,11 +661,12 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
     PJTRY(ensure(ctx, ctx->b_ctr, 64));
     HIPTRY(ctx, hipMemcpyAsync(ctx->b_items.p, pl.items.data(), ni * sizeof(Item), hipMemcpyHostToDevice, st));
     HIPTRY(ctx, hipMemcpyAsync(ctx->b_tiles.p, pl.tiles.data(), nt * sizeof(Tile), hipMemcpyHostToDevice, st));
-    int32_t *ctr = ptr<int32_t>(ctx->b_ctr);  // [0] work counter, [1] ntiles, [2..3] u64 pairs, [4..5] u64 culled
-    int32_t host_ctr[16] = {0, nt};
+    // [0] collect counter, [1] ntiles, [2..3] u64 pairs, [4..5] u64 culled chunks, [6] items
+    int32_t *ctr = ptr<int32_t>(ctx->b_ctr);
+    int32_t host_ctr[16] = {0, nt, 0, 0, 0, 0, ni};
     HIPTRY(ctx, hipMemcpyAsync(ctr, host_ctr, sizeof(host_ctr), hipMemcpyHostToDevice, st));
-    HIPTRY(ctx, launch_init_out(ptr<ItemOut>(ctx->b_out), ni, nullptr, st));
     RefineArgs a;
+    std::memset(&a, 0, sizeof(a));
     a.R = R->dev();
     a.S = S->dev();
     a.items = ptr<Item>(ctx->b_items);
@@ -668,9 +680,40 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
     a.early = early ? 1 : 0;
     a.cull = ctx->cfg.tile_cull ? 1 : 0;
     int wpc = ctx->cfg.waves_per_cu > 0 ? ctx->cfg.waves_per_cu : 12;
-    int grid = std::min<int64_t>(nt, (int64_t)ctx->num_cu * wpc);
+    // persistent grid: fixed size, the kernel reads the tile count from memory
+    const int grid = ctx->num_cu * wpc;
     HIPTRY(ctx, hipEventRecord(ctx->ev0, st));
-    HIPTRY(ctx, launch_refine_f32(a, grid, kP, st));
+    if (ctx->cfg.use_graph) {
+        std::vector<char> key(sizeof(a) + sizeof(int));
+        std::memcpy(key.data(), &a, sizeof(a));
+        std::memcpy(key.data() + sizeof(a), &grid, sizeof(int));
+        hipGraphExec_t exec = nullptr;
+        for (auto &g : ctx->graphs)
+            if (g.key == key) exec = g.exec;
+        if (!exec) {
+            if (!ctx->cap_stream) HIPTRY(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+            hipGraph_t graph = nullptr;
+            HIPTRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+            hipError_t e1 = launch_init_out_dev(a.out, ctr + 6, ctx->cap_stream);
+            hipError_t e2 = e1 == hipSuccess ? launch_refine_f32(a, grid, kP, ctx->cap_stream) : e1;
+            hipError_t e3 = hipStreamEndCapture(ctx->cap_stream, &graph);
+            if (e2 != hipSuccess) return hipfail(ctx, e2, "capture of the refinement round");
+            if (e3 != hipSuccess) return hipfail(ctx, e3, "hipStreamEndCapture");
+            hipError_t e4 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e4 != hipSuccess) return hipfail(ctx, e4, "hipGraphInstantiate");
+            if (ctx->graphs.size() >= 16) {
+                (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+                ctx->graphs.erase(ctx->graphs.begin());
+            }
+            ctx->graphs.push_back(pj_context::GraphEntry{key, exec});
+        }
+        HIPTRY(ctx, hipGraphLaunch(exec, st));
+        ctx->graph_replays++;
+    } else {
+        HIPTRY(ctx, launch_init_out(ptr<ItemOut>(ctx->b_out), ni, nullptr, st));
+        HIPTRY(ctx, launch_refine_f32(a, std::min<int64_t>(nt, grid), kP, st));
+    }
     HIPTRY(ctx, hipEventRecord(ctx->ev1, st));
     HIPTRY(ctx, hipMemcpyAsync(out.data(), a.out, ni * sizeof(ItemOut), hipMemcpyDeviceToHost, st));
     HIPTRY(ctx, hipMemcpyAsync(host_ctr, ctr, sizeof(host_ctr), hipMemcpyDeviceToHost, st));

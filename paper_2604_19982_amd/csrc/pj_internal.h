@@ -96,6 +96,7 @@ hipError_t launch_filter(const float *boxR, const float *ancR, int nR, const flo
 hipError_t launch_scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t *total, int n, hipStream_t st);
 hipError_t launch_init_out(ItemOut *out, int n, int32_t *counter, hipStream_t st);
 hipError_t launch_init_out64(ItemOut64 *out, int n, hipStream_t st);
+hipError_t launch_init_out_dev(ItemOut *out, const int32_t *n_ptr, hipStream_t st);
 hipError_t launch_refine_f32(const RefineArgs &a, int grid, int P, hipStream_t st);
 hipError_t launch_collect_f32(const RefineArgs &a, int grid, hipStream_t st);
 hipError_t launch_pairs_f64(const MeshDev &R, const MeshDev &S, const Item *items, const PairRef *pairs, int64_t n,

@@ -401,6 +401,21 @@ hipError_t launch_init_out(ItemOut *out, int n, int32_t *counter, hipStream_t st
     return hipGetLastError();
 }
 
+// grid-stride initialisation whose count lives in device memory, so that a
+// captured graph replays it for any round size
+__global__ void k_init_out_dev(ItemOut *out, const int32_t *n_ptr)
+{
+    const int n = *n_ptr;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        out[i] = ItemOut{0x7f800000u, 0x7f800000u, 0, 0};
+}
+
+hipError_t launch_init_out_dev(ItemOut *out, const int32_t *n_ptr, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_init_out_dev, dim3(256), dim3(256), 0, st, out, n_ptr);
+    return hipGetLastError();
+}
+
 __global__ void k_init_out64(ItemOut64 *out, int n)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
