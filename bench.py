@@ -75,6 +75,34 @@ def run_step(ctx, gR, gS, taus, verbose=False):
     return tot
 
 
+def train_model(pj, mg, stream, workdir):
+    """LoD model for the learned skip, trained on resolution logs of a
+    held-out workload of the same shape (seed 101, 2k x 400 in 300^3)."""
+    log = os.path.join(workdir, "resolution.log")
+    model = os.path.join(workdir, "lod.model")
+    if os.path.exists(log):
+        os.remove(log)
+    R, S = mg.config_multilod(seed=101, n_r=2000, n_s=400, box=300.0)
+    c = pj.Context(log_path=log, stream=stream.cuda_stream)
+    gR, gS = c.meshes(R), c.meshes(S)
+    for tau in (0.0, 2.0, 5.0, 10.0, 20.0):
+        c.join_within(gR, gS, tau)
+    loss = c.train_lod_model(log, model, epochs=40, batch=1024, lr=3e-3, seed=1)
+    return model, loss, os.path.getsize(log) // 72
+
+
+def one_step(pj, stream, R, S, **cfg):
+    import torch
+    c = pj.Context(stream=stream.cuda_stream, **cfg)
+    gR, gS = c.meshes(R), c.meshes(S)
+    torch.cuda.synchronize()
+    ts = time.time()
+    tot = run_step(c, gR, gS, TAUS)
+    torch.cuda.synchronize()
+    tot["ms"] = (time.time() - ts) * 1e3
+    return tot
+
+
 def cpu_baseline(R, S, seconds):
     """The oracle on a bounded sample of the workload's candidate pairs."""
     import numpy as np
@@ -115,6 +143,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--plain", type=int, default=1, help="run the plain FP64 schedule once for comparison")
+    ap.add_argument("--ablations", type=int, default=1, help="one step each without the learned skip / culling")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--n-r", type=int, default=10000)
     ap.add_argument("--n-s", type=int, default=2000)
@@ -131,7 +160,12 @@ def main():
     R, S = mg.config_multilod(seed=1, n_r=args.n_r, n_s=args.n_s)
     log(f"generated {R.n_objects} x {S.n_objects} objects in {time.time() - t0:.1f} s")
     stream = torch.cuda.current_stream()
-    ctx = pj.Context(stream=stream.cuda_stream)
+    import tempfile
+    workdir = tempfile.mkdtemp(prefix="pj_bench_")
+    t0 = time.time()
+    model, train_loss, n_rec = train_model(pj, mg, stream, workdir)
+    log(f"LoD model trained on {n_rec} logged pairs in {time.time() - t0:.1f} s, final loss {train_loss:.3f}")
+    ctx = pj.Context(stream=stream.cuda_stream, learned_skip=True, model_path=model)
     t0 = time.time()
     gR, gS = ctx.meshes(R), ctx.meshes(S)
     torch.cuda.synchronize()
@@ -181,25 +215,30 @@ def main():
                    "facet_pairs_per_step": pairs / args.steps,
                    "results_per_step": steps[-1]["results"],
                    "band_pairs_per_step": steps[-1]["band"],
-                   "ingest_s": ingest_s},
+                   "ingest_s": ingest_s,
+                   "mode": "learned LoD skip + batched persistent tiles + FP32 with FP64 guard band + chunk culling + hipGraph rounds",
+                   "lod_model": {"train_pairs": n_rec, "final_loss": train_loss}},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
                      "kernel": "k_refine_f32", "launches": launches, "avg_launch_ms": kms / max(launches, 1),
                      "flop_per_pair": FLOP_PER_PAIR, "single_issue_fma_peak": SINGLE_ISSUE_FP32_TFLOPS,
                      "fma_probe_measured": fma_tflops, "copy_probe_gbps": copy_gbps},
     }
+    abl = {}
+    if args.ablations:
+        for name, cfg in (("no_learned_skip", {}), ("no_learned_no_cull", dict(tile_cull=False))):
+            t = one_step(pj, stream, R, S, **cfg)
+            abl[name] = {"ms": t["ms"], "facet_pairs": t["pairs"] + t["pairs64"], "results": t["results"]}
+            log(f"ablation {name}: {t['ms']:.1f} ms")
     if args.plain:
-        cp = pj.Context(schedule="plain", precision="fp64", stream=stream.cuda_stream)
-        pR, pS = cp.meshes(R), cp.meshes(S)
-        torch.cuda.synchronize()
-        ts = time.time()
-        tp = run_step(cp, pR, pS, TAUS, verbose=True)
-        torch.cuda.synchronize()
-        plain_ms = (time.time() - ts) * 1e3
-        log(f"plain schedule step: {plain_ms:.1f} ms")
-        out["config"]["plain_ms_per_step"] = plain_ms
-        out["config"]["speedup_vs_plain"] = plain_ms / ms_per_step
-        out["config"]["plain_results_match"] = tp["results"] == steps[-1]["results"]
+        t = one_step(pj, stream, R, S, schedule="plain", precision="fp64")
+        abl["plain_gpu_schedule"] = {"ms": t["ms"], "facet_pairs": t["pairs"] + t["pairs64"], "results": t["results"]}
+        log(f"plain schedule step: {t['ms']:.1f} ms")
+        out["config"]["plain_ms_per_step"] = t["ms"]
+        out["config"]["speedup_vs_plain"] = t["ms"] / ms_per_step
+    for name, a in abl.items():
+        a["results_match"] = a["results"] == steps[-1]["results"]
+    out["config"]["ablations"] = abl
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(R, S, args.cpu_seconds)
     print(json.dumps(out), flush=True)
