@@ -64,13 +64,16 @@ struct pj_meshes {
     float2 *d_hdph = nullptr;
     float *d_box = nullptr, *d_anchor = nullptr;
     float2 *d_lodmax = nullptr;
-    std::vector<int64_t> h_vbeg, h_tbeg, h_hpbeg;
+    int64_t *d_bkbeg = nullptr;
+    float4 *d_blk = nullptr;
+    int64_t nblk = 0;
+    std::vector<int64_t> h_vbeg, h_tbeg, h_hpbeg, h_bkbeg;
     std::vector<int32_t> h_tcnt;
     std::vector<float> h_box, h_anchor;
     std::vector<float2> h_lodmax;
     MeshDev dev() const
     {
-        return MeshDev{d_verts, d_tris, d_vbeg, d_tbeg, d_tcnt, d_hpbeg, d_hdph, n, L};
+        return MeshDev{d_verts, d_tris, d_vbeg, d_tbeg, d_tcnt, d_hpbeg, d_hdph, d_bkbeg, d_blk, n, L};
     }
     int32_t count(int obj, int lod) const { return h_tcnt[(int64_t)obj * L + lod]; }
 };
@@ -263,7 +266,7 @@ void free_meshes(pj_meshes *m)
     if (!m) return;
     for (void *p : {(void *)m->d_verts, (void *)m->d_tris, (void *)m->d_vbeg, (void *)m->d_tbeg, (void *)m->d_hpbeg,
                     (void *)m->d_tcnt, (void *)m->d_hdph, (void *)m->d_box, (void *)m->d_anchor,
-                    (void *)m->d_lodmax})
+                    (void *)m->d_lodmax, (void *)m->d_bkbeg, (void *)m->d_blk})
         if (p) (void)hipFree(p);
     delete m;
 }
@@ -489,6 +492,15 @@ extern "C" pj_status pj_meshes_create(pj_context *ctx, const pj_mesh_desc *d, pj
         (void)hipFree(d_dlist);
         (void)hipFree(d_joboff);
     }
+    // block records (64 consecutive facets each) for chunk culling
+    m->h_bkbeg.assign(n * L + 1, 0);
+    for (int64_t k = 0; k < n * L; ++k) m->h_bkbeg[k + 1] = m->h_bkbeg[k] + (m->h_tcnt[k] + 63) / 64;
+    m->nblk = m->h_bkbeg[n * L];
+    if ((e = upload(&m->d_bkbeg, m->h_bkbeg.data(), n * L + 1, st)) != hipSuccess) return bail(e, "block offsets");
+    if ((e = hipMalloc((void **)&m->d_blk, std::max<int64_t>(m->nblk, 1) * 2 * sizeof(float4))) != hipSuccess)
+        return bail(e, "block records");
+    md = m->dev();
+    if ((e = launch_blocks(md, m->d_blk, m->d_bkbeg, m->nblk, st)) != hipSuccess) return bail(e, "blocks kernel");
     if ((e = launch_lodmax(md, m->d_lodmax, st)) != hipSuccess) return bail(e, "lodmax kernel");
     m->h_box.resize(n * 6);
     m->h_anchor.resize(n * 3);
@@ -932,7 +944,8 @@ pj_status mbb_filter(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, do
     return PJ_OK;
 }
 
-int pick_tile_s(pj_context *ctx) { return ctx->cfg.tile_s > 0 ? ctx->cfg.tile_s : 1024; }
+// streamed-side facets per tile: a multiple of 64 so that chunks are blocks
+int pick_tile_s(pj_context *ctx) { return ctx->cfg.tile_s > 0 ? (ctx->cfg.tile_s + 63) / 64 * 64 : 1024; }
 
 // Progressive refinement of within-tau candidates (Section 3.1): returns the
 // confirmed candidate indices.

@@ -19,6 +19,8 @@ struct MeshDev {
     const int32_t *tcnt;   // [n*L]
     const int64_t *hpbeg;  // [n*L] start of (object, LoD) in hdph, -1 on the finest LoD
     const float2 *hdph;    // (hd, ph) per coarse facet
+    const int64_t *bkbeg;  // [n*L] first block record of (object, LoD)
+    const float4 *blk;     // per block of 64 consecutive facets: (lo.xyz, max hd), (hi.xyz, max ph)
     int32_t n, L;
 };
 
@@ -90,6 +92,7 @@ hipError_t launch_hd(const MeshDev &m, float2 *hdph_mut, const int64_t *job_off,
                      const int64_t *desc_base, const int32_t *desc_off, const int32_t *desc_list, int lod, int msub,
                      hipStream_t st);
 hipError_t launch_lodmax(const MeshDev &m, float2 *lodmax, hipStream_t st);
+hipError_t launch_blocks(const MeshDev &m, float4 *blk, const int64_t *blk_off, int64_t n_blocks, hipStream_t st);
 hipError_t launch_filter(const float *boxR, const float *ancR, int nR, const float *boxS, const float *ancS, int nS,
                          float tau, int32_t *blk_count, int64_t *blk_off, int64_t *total, int32_t *cr, int32_t *cs,
                          float *clb, float *cub, int write_pass, hipStream_t st);

@@ -260,6 +260,45 @@ __global__ __launch_bounds__(256) void k_lodmax(MeshDev m, float2 *lodmax)
     if (threadIdx.x == 0) lodmax[k] = make_float2(a, b);
 }
 
+// Block records: for each run of 64 consecutive facets of an (object, LoD),
+// the exact float box of their corners and their largest hd and ph.
+__global__ __launch_bounds__(256) void k_blocks(MeshDev m, float4 *blk, const int64_t *blk_off, int64_t n_blocks)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n_blocks) return;
+    const int k = find_seg(blk_off, m.n * m.L, j);  // (object, LoD) index
+    const int obj = k / m.L, lod = k % m.L;
+    const int b = (int)(j - blk_off[k]);
+    const int nf = m.tcnt[k];
+    const int32_t *t = m.tris + 3 * m.tbeg[k];
+    const float *v = m.verts + 3 * m.vbeg[obj];
+    const int64_t hb = m.hpbeg[k];
+    float lo[3] = {kInf, kInf, kInf}, hi[3] = {-kInf, -kInf, -kInf}, hd = 0.0f, ph = 0.0f;
+    for (int f = 64 * b; f < min(nf, 64 * b + 64); ++f) {
+        for (int c = 0; c < 3; ++c) {
+            const int vi = t[3 * f + c];
+            for (int q = 0; q < 3; ++q) {
+                lo[q] = fminf(lo[q], v[3 * vi + q]);
+                hi[q] = fmaxf(hi[q], v[3 * vi + q]);
+            }
+        }
+        if (hb >= 0) {
+            hd = fmaxf(hd, m.hdph[hb + f].x);
+            ph = fmaxf(ph, m.hdph[hb + f].y);
+        }
+    }
+    (void)lod;
+    blk[2 * j] = make_float4(lo[0], lo[1], lo[2], hd);
+    blk[2 * j + 1] = make_float4(hi[0], hi[1], hi[2], ph);
+}
+
+hipError_t launch_blocks(const MeshDev &m, float4 *blk, const int64_t *blk_off, int64_t n_blocks, hipStream_t st)
+{
+    if (n_blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_blocks, dim3((unsigned)((n_blocks + 255) / 256)), dim3(256), 0, st, m, blk, blk_off, n_blocks);
+    return hipGetLastError();
+}
+
 hipError_t launch_lodmax(const MeshDev &m, float2 *lodmax, hipStream_t st)
 {
     if (m.n == 0) return hipSuccess;
@@ -441,6 +480,7 @@ struct FacetSrc {
     const int32_t *tris;
     const float *verts;
     const float2 *hdph;  // nullptr on the finest LoD
+    const float4 *blk;   // block records of this (object, LoD)
     int n;
 };
 
@@ -452,6 +492,7 @@ __device__ __forceinline__ FacetSrc facet_src(const MeshDev &M, int obj, int lod
     s.verts = M.verts + 3 * M.vbeg[obj];
     const int64_t hb = M.hpbeg[k];
     s.hdph = hb >= 0 ? M.hdph + hb : nullptr;
+    s.blk = M.blk + 2 * M.bkbeg[k];
     s.n = M.tcnt[k];
     return s;
 }
@@ -468,18 +509,27 @@ __device__ __forceinline__ Rec load_rec(const FacetSrc &s, int f, V3 o)
 // and item fields loaded through a uniform index, readfirstlane'd flags), so
 // the compiler emits scalar control flow and the wave never splits.
 //
-// Chunk culling: before a chunk of 64 B facets is processed, its box is
-// reduced across the wave and compared with the box of the wave's A facets.
-// With gap g (rounded down), every pair in the chunk has FP32 distance
-// >= g - eps, hence ub >= g - eps and lb >= g - eps - phmax_A - phmax_B.
-// The chunk is skipped when neither bound can matter:
+// Chunk culling: a chunk of 64 B facets is one precomputed block record (box
+// of the corners, max hd, max ph); the A side of the tile is the union of its
+// P block records.  With g the box gap (a lower bound of every pair's true
+// distance, evaluated in FP64 and rounded down), every pair in the chunk has
+// FP32 distance >= g - eps, hence ub >= g - eps and
+// lb >= g - eps - phmax_A - phmax_B.  The chunk is skipped when neither bound
+// can matter:
 //   ub: g - eps > min(current item ub, tau - eps)   (within: cannot confirm)
 //   lb: lbLow   > min(current item lb, tau + eps)   (within: cannot block a prune)
-// (without tau, only "cannot lower the current minimum" is used, which keeps
+// (without tau only "cannot lower the current minimum" is used, which keeps
 // the minima exact); in collect mode the chunk is skipped when g - eps
 // exceeds the collect threshold.
 __device__ __forceinline__ float wmin_u(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wave_min(v)))); }
-__device__ __forceinline__ float wmax_u(float v) { return -wmin_u(-v); }
+
+__device__ __forceinline__ float block_gap(const float4 alo, const float4 ahi, const float4 blo, const float4 bhi)
+{
+    const double gx = fmax(0.0, fmax((double)blo.x - ahi.x, (double)alo.x - bhi.x));
+    const double gy = fmax(0.0, fmax((double)blo.y - ahi.y, (double)alo.y - bhi.y));
+    const double gz = fmax(0.0, fmax((double)blo.z - ahi.z, (double)alo.z - bhi.z));
+    return (float)sqrt(gx * gx + gy * gy + gz * gz) * (1.0f - 0x1p-20f);
+}
 
 template <int P, bool COLLECT>
 __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t, float4 *sh)
@@ -496,27 +546,22 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
     const FacetSrc SB = facet_src(swap ? a.R : a.S, it.b_obj, it.lod);
     const V3 org = V3{it.ox, it.oy, it.oz};
     Rec ra[P];
-    float alo[3] = {kInf, kInf, kInf}, ahi[3] = {-kInf, -kInf, -kInf}, aph = 0.0f;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         int f = tl.a0 + lane + 64 * p;
         if (f >= SA.n) f = tl.a0;  // padding lanes repeat a real facet
         ra[p] = load_rec(SA, f, org);
-        alo[0] = fminf(alo[0], min3f(ra[p].v0.x, ra[p].v1.x, ra[p].v2.x));
-        alo[1] = fminf(alo[1], min3f(ra[p].v0.y, ra[p].v1.y, ra[p].v2.y));
-        alo[2] = fminf(alo[2], min3f(ra[p].v0.z, ra[p].v1.z, ra[p].v2.z));
-        ahi[0] = fmaxf(ahi[0], max3f(ra[p].v0.x, ra[p].v1.x, ra[p].v2.x));
-        ahi[1] = fmaxf(ahi[1], max3f(ra[p].v0.y, ra[p].v1.y, ra[p].v2.y));
-        ahi[2] = fmaxf(ahi[2], max3f(ra[p].v0.z, ra[p].v1.z, ra[p].v2.z));
-        aph = fmaxf(aph, ra[p].ph);
     }
-    if (a.cull) {
-        for (int c = 0; c < 3; ++c) {
-            alo[c] = wmin_u(alo[c]);
-            ahi[c] = wmax_u(ahi[c]);
-        }
-        aph = wmax_u(aph);
+    // union of the A block records (tile starts are multiples of 64)
+    float4 alo = SA.blk[2 * (tl.a0 >> 6)], ahi = SA.blk[2 * (tl.a0 >> 6) + 1];
+#pragma unroll
+    for (int p = 1; p < P; ++p) {
+        if (tl.a0 + 64 * p >= SA.n) break;
+        const float4 l2 = SA.blk[2 * ((tl.a0 >> 6) + p)], h2 = SA.blk[2 * ((tl.a0 >> 6) + p) + 1];
+        alo = make_float4(fminf(alo.x, l2.x), fminf(alo.y, l2.y), fminf(alo.z, l2.z), fmaxf(alo.w, l2.w));
+        ahi = make_float4(fmaxf(ahi.x, h2.x), fmaxf(ahi.y, h2.y), fmaxf(ahi.z, h2.z), fmaxf(ahi.w, h2.w));
     }
+    const float aph = ahi.w;
     const bool within = a.tau >= 0.0f;
     float lbm = kInf, ubm = kInf;
     int sure = 0;
@@ -525,17 +570,10 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
     bool stop = false;
     for (int cb = tl.b0; cb < tl.b1 && !stop; cb += 64) {
         const int nb = min(64, tl.b1 - cb);
-        int f = cb + lane;
-        if (f >= tl.b1) f = cb;
-        const int32_t i0 = SB.tris[3 * f], i1 = SB.tris[3 * f + 1], i2 = SB.tris[3 * f + 2];
-        const V3 b0 = ld3f(SB.verts, i0) - org, b1 = ld3f(SB.verts, i1) - org, b2 = ld3f(SB.verts, i2) - org;
-        const float2 bh = SB.hdph ? SB.hdph[f] : make_float2(0.0f, 0.0f);
         if (a.cull) {
-            const float gx = fmaxf(0.0f, fmaxf(wmin_u(min3f(b0.x, b1.x, b2.x)) - ahi[0], alo[0] - wmax_u(max3f(b0.x, b1.x, b2.x))));
-            const float gy = fmaxf(0.0f, fmaxf(wmin_u(min3f(b0.y, b1.y, b2.y)) - ahi[1], alo[1] - wmax_u(max3f(b0.y, b1.y, b2.y))));
-            const float gz = fmaxf(0.0f, fmaxf(wmin_u(min3f(b0.z, b1.z, b2.z)) - ahi[2], alo[2] - wmax_u(max3f(b0.z, b1.z, b2.z))));
-            const float gap = __builtin_sqrtf(fmaf(gz, gz, fmaf(gy, gy, gx * gx))) * (1.0f - 0x1p-20f) - it.eps;
-            const float bph = wmax_u(bh.y);
+            const float4 blo = SB.blk[2 * (cb >> 6)], bhi = SB.blk[2 * (cb >> 6) + 1];
+            const float gap = block_gap(alo, ahi, blo, bhi) - it.eps;
+            const float bph = bhi.w;
             const float cur_lb = __uint_as_float(__builtin_amdgcn_readfirstlane(
                 __hip_atomic_load(&o->lb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
             const float cur_ub = __uint_as_float(__builtin_amdgcn_readfirstlane(
@@ -553,6 +591,11 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
                 continue;
             }
         }
+        int f = cb + lane;
+        if (f >= tl.b1) f = cb;
+        const int32_t i0 = SB.tris[3 * f], i1 = SB.tris[3 * f + 1], i2 = SB.tris[3 * f + 2];
+        const V3 b0 = ld3f(SB.verts, i0) - org, b1 = ld3f(SB.verts, i1) - org, b2 = ld3f(SB.verts, i2) - org;
+        const float2 bh = SB.hdph ? SB.hdph[f] : make_float2(0.0f, 0.0f);
         {
             Rec rb = make_rec(b0, b1, b2, bh.x, bh.y);
             float tmp[44];
