@@ -62,9 +62,13 @@ typedef struct {
     int32_t want_dist;       /* within/intersect: also return FP64 distances of result pairs */
     int32_t use_graph;       /* 1: replay each LoD round's launches from a captured hipGraph */
     int32_t tile_cull;       /* 1: skip facet tiles whose box gap proves they cannot matter */
-    int32_t tile_s;          /* streamed-side facets per tile (0: autotuned) */
-    int32_t waves_per_cu;    /* persistent grid size in waves per CU (0: autotuned) */
+    int32_t tile_s;          /* streamed-side facets per tile, rounded up to 64 (0: tuned or 1024) */
+    int32_t waves_per_cu;    /* persistent grid size in waves per CU (0: tuned or 12) */
     int32_t host_threads;    /* host threads for ingest (0: hardware concurrency) */
+    int32_t chunk_tiles;     /* tiles per streamed refinement chunk (0: derived from mem_cap_bytes) */
+    int32_t autotune;        /* 1: time candidate (tile_s, waves_per_cu) shapes on a sample of the first
+                                round of each work class and keep the fastest (cached in autotune_path);
+                                an explicit tile_s / waves_per_cu always wins */
     int64_t mem_cap_bytes;   /* device-memory budget for join work buffers (0: no cap) */
     const char *model_path;  /* LoD model weights written by pj_train_lod_model (NULL: none) */
     const char *log_path;    /* append per-pair resolution records here (NULL: no log) */
@@ -73,7 +77,8 @@ typedef struct {
 } pj_config;
 
 /* Fill *cfg with defaults: device 0, FP32 band, batched, tile culling on,
- * graphs on, no learned skip, no cap, autotuned shapes. */
+ * graphs on, no learned skip, no cap, autotuner off (tile_s 1024, 12 waves
+ * per CU), one streamed chunk unless the cap forces more. */
 void pj_config_default(pj_config *cfg);
 
 typedef struct pj_context pj_context;
@@ -163,6 +168,11 @@ typedef struct {
     int64_t resolved_at_lod[8]; /* pairs decided in each LoD round */
     int64_t rounds;             /* LoD rounds executed */
     int64_t peak_device_bytes;  /* high-water mark of join work buffers */
+    int64_t chunks;             /* streamed chunks of the bulk refinement */
+    int64_t graph_replays;      /* bulk rounds replayed from a captured hipGraph */
+    int64_t tile_s_used;        /* streamed-side tile length of the last bulk round */
+    int64_t waves_per_cu_used;  /* persistent grid of the last bulk round, waves per CU */
+    double t_tune_ms;           /* host time spent in the autotuner during this join */
 } pj_stats;
 
 pj_status pj_get_stats(const pj_context *ctx, pj_stats *out);

@@ -30,7 +30,8 @@ class Config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("precision", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("learned_skip", ctypes.c_int32), ("want_dist", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("tile_cull", ctypes.c_int32), ("tile_s", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
-                ("host_threads", ctypes.c_int32), ("mem_cap_bytes", ctypes.c_int64),
+                ("host_threads", ctypes.c_int32), ("chunk_tiles", ctypes.c_int32),
+                ("autotune", ctypes.c_int32), ("mem_cap_bytes", ctypes.c_int64),
                 ("model_path", ctypes.c_char_p), ("log_path", ctypes.c_char_p), ("autotune_path", ctypes.c_char_p),
                 ("stream", ctypes.c_void_p)]
 
@@ -61,7 +62,9 @@ class Stats(ctypes.Structure):
                 ("confirmed_filter", ctypes.c_int64), ("facet_pairs", ctypes.c_int64),
                 ("facet_pairs_fp64", ctypes.c_int64), ("tiles", ctypes.c_int64), ("tiles_culled", ctypes.c_int64),
                 ("band_pairs", ctypes.c_int64), ("resolved_at_lod", ctypes.c_int64 * 8), ("rounds", ctypes.c_int64),
-                ("peak_device_bytes", ctypes.c_int64)]
+                ("peak_device_bytes", ctypes.c_int64), ("chunks", ctypes.c_int64),
+                ("graph_replays", ctypes.c_int64), ("tile_s_used", ctypes.c_int64),
+                ("waves_per_cu_used", ctypes.c_int64), ("t_tune_ms", ctypes.c_double)]
 
     def to_dict(self):
         d = {}
@@ -174,7 +177,7 @@ class Context:
 
     def __init__(self, device=0, precision="fp32", schedule="batched", learned_skip=False, want_dist=False,
                  use_graph=True, tile_cull=True, tile_s=0, waves_per_cu=0, mem_cap_bytes=0, model_path=None,
-                 log_path=None, stream=None):
+                 log_path=None, stream=None, chunk_tiles=0, autotune=False, autotune_path=None):
         L = lib()
         c = Config()
         L.pj_config_default(ctypes.byref(c))
@@ -188,8 +191,10 @@ class Context:
         c.tile_s = int(tile_s)
         c.waves_per_cu = int(waves_per_cu)
         c.mem_cap_bytes = int(mem_cap_bytes)
-        self._paths = [None if p is None else os.fsencode(p) for p in (model_path, log_path)]
-        c.model_path, c.log_path = self._paths
+        c.chunk_tiles = int(chunk_tiles)
+        c.autotune = int(bool(autotune))
+        self._paths = [None if p is None else os.fsencode(p) for p in (model_path, log_path, autotune_path)]
+        c.model_path, c.log_path, c.autotune_path = self._paths
         c.stream = stream
         h = ctypes.c_void_p()
         st = L.pj_context_create(ctypes.byref(c), ctypes.byref(h))

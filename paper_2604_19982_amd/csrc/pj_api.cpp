@@ -90,6 +90,23 @@ struct pj_context {
     DevBuf b_items, b_tiles, b_out, b_out64, b_ctr, b_cand_r, b_cand_s, b_cand_lb, b_cand_ub, b_blk, b_blkoff,
         b_total, b_tmp0, b_tmp1, b_tmp2, b_tmp3, b_coll, b_ovf, b_theta, b_koff, b_klb, b_kub, b_kst0, b_kst1,
         b_kleft;
+    // chunked streaming: two buffer sets, upload/download streams, pinned staging
+    struct PinBuf {
+        void *p = nullptr;
+        size_t cap = 0;
+    };
+    DevBuf sb_items[2], sb_tiles[2], sb_out[2], sb_ctr[2];
+    PinBuf pin_items[2], pin_tiles[2], pin_out[2], pin_ctr[2];
+    hipStream_t up_stream = nullptr, down_stream = nullptr;
+    hipEvent_t ev_h2d[2] = {nullptr, nullptr}, ev_comp[2] = {nullptr, nullptr}, ev_d2h[2] = {nullptr, nullptr},
+               ev_k0[2] = {nullptr, nullptr}, ev_k1[2] = {nullptr, nullptr};
+    // launch shape of the bulk rounds: explicit config > tuned > defaults
+    struct Shape {
+        int tile_s = 1024, wpc = 12;
+    };
+    Shape cur;
+    std::map<std::string, Shape> tuned;
+    std::string arch;
     // captured FP32 rounds, keyed by their kernel arguments
     struct GraphEntry {
         std::vector<char> key;
@@ -97,7 +114,6 @@ struct pj_context {
     };
     std::vector<GraphEntry> graphs;
     hipStream_t cap_stream = nullptr;
-    int64_t graph_replays = 0;
     // LoD model (learned skip)
     std::vector<float> model;
     float feat_mean[MLP_IN], feat_std[MLP_IN];
@@ -174,6 +190,7 @@ float up_float(double x)
 
 namespace {
 bool load_model(pj_context *ctx, const char *path);
+void load_tune_cache(pj_context *ctx);
 }
 
 // ===========================================================================
@@ -212,7 +229,17 @@ extern "C" pj_status pj_context_create(const pj_config *cfg, pj_context **out)
     ctx->cfg = c;
     std::memset(&ctx->stats, 0, sizeof(ctx->stats));
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, c.device) == hipSuccess) ctx->num_cu = prop.multiProcessorCount;
+    if (hipGetDeviceProperties(&prop, c.device) == hipSuccess) {
+        ctx->num_cu = prop.multiProcessorCount;
+        ctx->arch = prop.gcnArchName;
+        const size_t colon = ctx->arch.find(':');
+        if (colon != std::string::npos) ctx->arch.resize(colon);
+    }
+    if (ctx->arch.empty()) ctx->arch = "gpu";
+    if (c.chunk_tiles < 0) {
+        delete ctx;
+        return PJ_ERR_INVALID_ARG;
+    }
     if (c.stream) {
         ctx->stream = (hipStream_t)c.stream;
     } else {
@@ -226,6 +253,7 @@ extern "C" pj_status pj_context_create(const pj_config *cfg, pj_context **out)
         delete ctx;
         return PJ_ERR_DEVICE;
     }
+    load_tune_cache(ctx);
     // a missing or unreadable model leaves the plain progressive schedule
     if (c.model_path && !load_model(ctx, c.model_path)) ctx->err = "LoD model not loaded; plain schedule in use";
     *out = ctx;
@@ -239,6 +267,14 @@ extern "C" pj_status pj_context_destroy(pj_context *ctx)
     (void)hipStreamSynchronize(ctx->stream);
     for (auto &g : ctx->graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    for (int b = 0; b < 2; ++b) {
+        for (auto *pb : {&ctx->pin_items[b], &ctx->pin_tiles[b], &ctx->pin_out[b], &ctx->pin_ctr[b]})
+            if (pb->p) (void)hipHostFree(pb->p);
+        for (hipEvent_t e : {ctx->ev_h2d[b], ctx->ev_comp[b], ctx->ev_d2h[b], ctx->ev_k0[b], ctx->ev_k1[b]})
+            if (e) (void)hipEventDestroy(e);
+    }
+    if (ctx->up_stream) (void)hipStreamDestroy(ctx->up_stream);
+    if (ctx->down_stream) (void)hipStreamDestroy(ctx->down_stream);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -604,6 +640,7 @@ struct TilePlan {
     std::vector<Item> items;
     std::vector<Tile> tiles;
     int64_t pairs = 0;
+    int tile_s = 0;
 };
 
 // Expand items into tiles: the A side (registers) is the object whose block
@@ -627,6 +664,7 @@ void plan_tiles(const pj_meshes *R, const pj_meshes *S, const std::vector<int> &
     pl.items.clear();
     pl.tiles.clear();
     pl.pairs = 0;
+    pl.tile_s = TS;
     for (const C &oc : order) {
         const int ci = act[oc.idx];
         const Cand &c = cand[ci];
@@ -656,90 +694,336 @@ void plan_tiles(const pj_meshes *R, const pj_meshes *S, const std::vector<int> &
     }
 }
 
-struct Round32 {
-    std::vector<ItemOut> out;
-};
+// ---------------------------------------------------------------------------
+// Launch-shape autotuner.  Work is classed by (device, mode, size bucket of
+// the mean facet pairs per item); the first bulk round of a class without a
+// cached shape times every (tile_s, waves_per_cu) candidate on a sample of
+// its items (eager launches, kernel time from events, best of two) and keeps
+// the fastest.  Results never depend on the shape: the per-item minima are
+// order independent.  The cache is a text file of lines
+// "<class> <tile_s> <waves_per_cu> <ms>".
+// ---------------------------------------------------------------------------
+constexpr int kTuneTS[] = {256, 512, 1024, 2048, 4096};
+constexpr int kTuneWPC[] = {4, 8, 12, 16, 24};
+
+void load_tune_cache(pj_context *ctx)
+{
+    if (!ctx->cfg.autotune_path) return;
+    FILE *f = std::fopen(ctx->cfg.autotune_path, "r");
+    if (!f) return;
+    char key[256];
+    int ts, wpc;
+    double ms;
+    while (std::fscanf(f, "%255s %d %d %lf", key, &ts, &wpc, &ms) == 4)
+        if (ts >= 64 && ts % 64 == 0 && ts <= (1 << 20) && wpc >= 1 && wpc <= 64)
+            ctx->tuned[key] = pj_context::Shape{ts, wpc};
+    std::fclose(f);
+}
+
+void save_tune_cache(pj_context *ctx, const std::string &key, const pj_context::Shape &sh, double ms)
+{
+    if (!ctx->cfg.autotune_path) return;
+    FILE *f = std::fopen(ctx->cfg.autotune_path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d %.6f\n", key.c_str(), sh.tile_s, sh.wpc, ms);
+    std::fclose(f);
+}
+
+std::string tune_class(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, const std::vector<int> &act,
+                       const std::vector<Cand> &cand, int lod, float tau)
+{
+    double sum = 0.0;
+    for (int i : act) sum += (double)R->count(cand[i].r, lod) * (double)S->count(cand[i].s, lod);
+    const double mean = act.empty() ? 0.0 : sum / (double)act.size();
+    const int bucket = mean > 1.0 ? (int)std::floor(std::log(mean) / std::log(4.0)) : 0;
+    char buf[160];
+    std::snprintf(buf, sizeof(buf), "%s/%dcu/%s/b%d", ctx->arch.c_str(), ctx->num_cu, tau >= 0.0f ? "within" : "min",
+                  bucket);
+    return buf;
+}
 
 pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TilePlan &pl, float tau, bool early,
-                  std::vector<ItemOut> &out)
+                  std::vector<ItemOut> &out, int wpc_override);
+
+// Set ctx->cur for a bulk round over `act` (explicit config values win).
+pj_status choose_shape(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, const std::vector<int> &act,
+                       const std::vector<Cand> &cand, const std::vector<PairState> &ps, int lod, int finest,
+                       float tau, bool early)
 {
+    const int cfg_ts = ctx->cfg.tile_s > 0 ? (ctx->cfg.tile_s + 63) / 64 * 64 : 0;
+    const int cfg_wpc = ctx->cfg.waves_per_cu;
+    pj_context::Shape sh;
+    if (cfg_ts && cfg_wpc) {
+        ctx->cur = pj_context::Shape{cfg_ts, cfg_wpc};
+        return PJ_OK;
+    }
+    const std::string key = tune_class(ctx, R, S, act, cand, lod, tau);
+    auto it = ctx->tuned.find(key);
+    if (it != ctx->tuned.end()) {
+        sh = it->second;
+    } else if (ctx->cfg.autotune && !act.empty()) {
+        const double t0 = now_ms();
+        // sample: items spread over the round, up to about 2e9 facet pairs
+        std::vector<int> idx(act.begin(), act.end());
+        std::vector<int> sample;
+        double pairs = 0.0;
+        const size_t stride = std::max<size_t>(1, idx.size() / 4096);
+        for (size_t i = 0; i < idx.size() && pairs < 2e9; i += stride) {
+            sample.push_back(idx[i]);
+            pairs += (double)R->count(cand[idx[i]].r, lod) * (double)S->count(cand[idx[i]].s, lod);
+        }
+        const pj_stats saved = ctx->stats;
+        double best = INFINITY;
+        pj_context::Shape bs;
+        for (int ts : kTuneTS) {
+            if (cfg_ts && ts != cfg_ts) continue;
+            TilePlan pl;
+            plan_tiles(R, S, sample, cand, ps, lod, finest, 64 * kP, ts, true, pl);
+            for (int wpc : kTuneWPC) {
+                if (cfg_wpc && wpc != cfg_wpc) continue;
+                double t = INFINITY;
+                for (int rep = 0; rep < 2; ++rep) {
+                    ctx->stats.refine_kernel_ms = 0.0;
+                    std::vector<ItemOut> out;
+                    PJTRY(run_f32(ctx, R, S, pl, tau, early, out, wpc));
+                    t = std::min(t, ctx->stats.refine_kernel_ms);
+                }
+                if (t < best) {
+                    best = t;
+                    bs = pj_context::Shape{ts, wpc};
+                }
+            }
+        }
+        ctx->stats = saved;
+        ctx->stats.t_tune_ms += now_ms() - t0;
+        sh = bs;
+        ctx->tuned[key] = sh;
+        save_tune_cache(ctx, key, sh, best);
+    }
+    if (cfg_ts) sh.tile_s = cfg_ts;
+    if (cfg_wpc) sh.wpc = cfg_wpc;
+    ctx->cur = sh;
+    return PJ_OK;
+}
+
+pj_status ensure_pinned(pj_context *ctx, pj_context::PinBuf &b, size_t bytes)
+{
+    if (bytes <= b.cap) return PJ_OK;
+    if (b.p) (void)hipHostFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+    size_t nb = std::max<size_t>(bytes, 4096);
+    hipError_t e = hipHostMalloc(&b.p, nb, hipHostMallocDefault);
+    if (e != hipSuccess) return hipfail(ctx, e, "hipHostMalloc");
+    b.cap = nb;
+    return PJ_OK;
+}
+
+pj_status ensure_streams(pj_context *ctx)
+{
+    if (ctx->up_stream) return PJ_OK;
+    HIPTRY(ctx, hipStreamCreateWithFlags(&ctx->up_stream, hipStreamNonBlocking));
+    HIPTRY(ctx, hipStreamCreateWithFlags(&ctx->down_stream, hipStreamNonBlocking));
+    for (int b = 0; b < 2; ++b) {
+        HIPTRY(ctx, hipEventCreateWithFlags(&ctx->ev_h2d[b], hipEventDisableTiming));
+        HIPTRY(ctx, hipEventCreateWithFlags(&ctx->ev_comp[b], hipEventDisableTiming));
+        HIPTRY(ctx, hipEventCreateWithFlags(&ctx->ev_d2h[b], hipEventDisableTiming));
+        HIPTRY(ctx, hipEventCreate(&ctx->ev_k0[b]));
+        HIPTRY(ctx, hipEventCreate(&ctx->ev_k1[b]));
+    }
+    return PJ_OK;
+}
+
+// Launch one chunk's refinement on `st` (from a cached hipGraph or directly).
+pj_status launch_round(pj_context *ctx, const RefineArgs &a, int32_t *ctr, int ni, int nt, int wpc, bool graph,
+                       hipStream_t st)
+{
+    // persistent grid: fixed size, the kernel reads the tile count from memory
+    const int grid = ctx->num_cu * wpc;
+    if (!graph) {
+        HIPTRY(ctx, launch_init_out(a.out, ni, nullptr, st));
+        HIPTRY(ctx, launch_refine_f32(a, std::min<int64_t>(nt, grid), kP, st));
+        return PJ_OK;
+    }
+    std::vector<char> key(sizeof(a) + sizeof(int));
+    std::memcpy(key.data(), &a, sizeof(a));
+    std::memcpy(key.data() + sizeof(a), &grid, sizeof(int));
+    hipGraphExec_t exec = nullptr;
+    for (auto &g : ctx->graphs)
+        if (g.key == key) exec = g.exec;
+    if (!exec) {
+        if (!ctx->cap_stream) HIPTRY(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        HIPTRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e1 = launch_init_out_dev(a.out, ctr + 6, ctx->cap_stream);
+        hipError_t e2 = e1 == hipSuccess ? launch_refine_f32(a, grid, kP, ctx->cap_stream) : e1;
+        hipError_t e3 = hipStreamEndCapture(ctx->cap_stream, &graph);
+        if (e2 != hipSuccess) return hipfail(ctx, e2, "capture of the refinement round");
+        if (e3 != hipSuccess) return hipfail(ctx, e3, "hipStreamEndCapture");
+        hipError_t e4 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e4 != hipSuccess) return hipfail(ctx, e4, "hipGraphInstantiate");
+        if (ctx->graphs.size() >= 16) {
+            (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+            ctx->graphs.erase(ctx->graphs.begin());
+        }
+        ctx->graphs.push_back(pj_context::GraphEntry{key, exec});
+    }
+    HIPTRY(ctx, hipGraphLaunch(exec, st));
+    ctx->stats.graph_replays++;
+    return PJ_OK;
+}
+
+// FP32 bulk pass over a plan, streamed in chunks (Algorithm 5 of the paper
+// on HIP streams): the host prepares chunk c+1 into pinned staging while
+// chunk c uploads on one stream, computes on the join stream and its
+// per-item results come back on a third stream; two buffer sets alternate
+// and events order their reuse.  A chunk holds at most `max_tiles` tiles;
+// an item whose tiles span chunks appears in each and is merged on the host.
+pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TilePlan &pl, float tau, bool early,
+                  std::vector<ItemOut> &out, int wpc_override)
+{
+    const int wpc = wpc_override > 0 ? wpc_override : ctx->cur.wpc;
+    const bool graph = ctx->cfg.use_graph && wpc_override == 0;
     hipStream_t st = ctx->stream;
     const int ni = (int)pl.items.size(), nt = (int)pl.tiles.size();
     out.assign(ni, ItemOut{0x7f800000u, 0x7f800000u, 0, 0});
-    if (ni == 0) return PJ_OK;
-    PJTRY(ensure(ctx, ctx->b_items, ni * sizeof(Item)));
-    PJTRY(ensure(ctx, ctx->b_tiles, nt * sizeof(Tile)));
-    PJTRY(ensure(ctx, ctx->b_out, ni * sizeof(ItemOut)));
-    PJTRY(ensure(ctx, ctx->b_ctr, 64));
-    HIPTRY(ctx, hipMemcpyAsync(ctx->b_items.p, pl.items.data(), ni * sizeof(Item), hipMemcpyHostToDevice, st));
-    HIPTRY(ctx, hipMemcpyAsync(ctx->b_tiles.p, pl.tiles.data(), nt * sizeof(Tile), hipMemcpyHostToDevice, st));
-    // [0] collect counter, [1] ntiles, [2..3] u64 pairs, [4..5] u64 culled chunks, [6] items
-    int32_t *ctr = ptr<int32_t>(ctx->b_ctr);
-    int32_t host_ctr[16] = {0, nt, 0, 0, 0, 0, ni};
-    HIPTRY(ctx, hipMemcpyAsync(ctr, host_ctr, sizeof(host_ctr), hipMemcpyHostToDevice, st));
-    RefineArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.R = R->dev();
-    a.S = S->dev();
-    a.items = ptr<Item>(ctx->b_items);
-    a.tiles = ptr<Tile>(ctx->b_tiles);
-    a.ntiles = ctr + 1;
-    a.counter = ctr;
-    a.out = ptr<ItemOut>(ctx->b_out);
-    a.pairs_done = reinterpret_cast<unsigned long long *>(ctr + 2);
-    a.chunks_culled = reinterpret_cast<unsigned long long *>(ctr + 4);
-    a.tau = tau;
-    a.early = early ? 1 : 0;
-    a.cull = ctx->cfg.tile_cull ? 1 : 0;
-    int wpc = ctx->cfg.waves_per_cu > 0 ? ctx->cfg.waves_per_cu : 12;
-    // persistent grid: fixed size, the kernel reads the tile count from memory
-    const int grid = ctx->num_cu * wpc;
-    HIPTRY(ctx, hipEventRecord(ctx->ev0, st));
-    if (ctx->cfg.use_graph) {
-        std::vector<char> key(sizeof(a) + sizeof(int));
-        std::memcpy(key.data(), &a, sizeof(a));
-        std::memcpy(key.data() + sizeof(a), &grid, sizeof(int));
-        hipGraphExec_t exec = nullptr;
-        for (auto &g : ctx->graphs)
-            if (g.key == key) exec = g.exec;
-        if (!exec) {
-            if (!ctx->cap_stream) HIPTRY(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
-            hipGraph_t graph = nullptr;
-            HIPTRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-            hipError_t e1 = launch_init_out_dev(a.out, ctr + 6, ctx->cap_stream);
-            hipError_t e2 = e1 == hipSuccess ? launch_refine_f32(a, grid, kP, ctx->cap_stream) : e1;
-            hipError_t e3 = hipStreamEndCapture(ctx->cap_stream, &graph);
-            if (e2 != hipSuccess) return hipfail(ctx, e2, "capture of the refinement round");
-            if (e3 != hipSuccess) return hipfail(ctx, e3, "hipStreamEndCapture");
-            hipError_t e4 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);
-            if (e4 != hipSuccess) return hipfail(ctx, e4, "hipGraphInstantiate");
-            if (ctx->graphs.size() >= 16) {
-                (void)hipGraphExecDestroy(ctx->graphs.front().exec);
-                ctx->graphs.erase(ctx->graphs.begin());
-            }
-            ctx->graphs.push_back(pj_context::GraphEntry{key, exec});
-        }
-        HIPTRY(ctx, hipGraphLaunch(exec, st));
-        ctx->graph_replays++;
-    } else {
-        HIPTRY(ctx, launch_init_out(ptr<ItemOut>(ctx->b_out), ni, nullptr, st));
-        HIPTRY(ctx, launch_refine_f32(a, std::min<int64_t>(nt, grid), kP, st));
+    if (ni == 0 || nt == 0) return PJ_OK;
+    PJTRY(ensure_streams(ctx));
+    // chunk capacity from the memory cap: two buffer sets of (items + tiles + outputs)
+    int64_t max_tiles = ctx->cfg.chunk_tiles > 0 ? ctx->cfg.chunk_tiles : int64_t(1) << 22;
+    if (ctx->cfg.mem_cap_bytes > 0) {
+        // size the chunks for what the cap leaves once the chunk buffers are
+        // given back (the join stream is idle between rounds)
+        HIPTRY(ctx, hipStreamSynchronize(st));
+        for (int b = 0; b < 2; ++b)
+            for (DevBuf *x : {&ctx->sb_items[b], &ctx->sb_tiles[b], &ctx->sb_out[b], &ctx->sb_ctr[b]}) x->release();
+        const int64_t avail = ctx->cfg.mem_cap_bytes - ctx->dev_bytes - 2 * (256 * 4 + 64);
+        const int64_t per_tile = sizeof(Tile) + sizeof(Item) + sizeof(ItemOut);  // worst case: one item per tile
+        max_tiles = std::min<int64_t>(max_tiles, avail / (2 * per_tile) - 1);
+        if (max_tiles < 1) return fail(ctx, PJ_ERR_OUT_OF_MEMORY, "the memory cap cannot hold one refinement tile");
     }
-    HIPTRY(ctx, hipEventRecord(ctx->ev1, st));
-    HIPTRY(ctx, hipMemcpyAsync(out.data(), a.out, ni * sizeof(ItemOut), hipMemcpyDeviceToHost, st));
-    HIPTRY(ctx, hipMemcpyAsync(host_ctr, ctr, sizeof(host_ctr), hipMemcpyDeviceToHost, st));
-    HIPTRY(ctx, hipStreamSynchronize(st));
-    float ms = 0;
-    HIPTRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-    ctx->stats.refine_kernel_ms += ms;
-    ctx->stats.refine_launches += 1;
+    struct Chunk {
+        int64_t t0, t1;
+        std::vector<int> items;  // plan item indices, in chunk-local order
+    };
+    std::vector<Chunk> chunks;
+    std::vector<int32_t> tile_local(nt);  // chunk-local item index of each tile
+    {
+        Chunk c{0, 0, {}};
+        std::vector<int> local(ni, -1);
+        for (int64_t t = 0; t < nt; ++t) {
+            if (t - c.t0 >= max_tiles) {
+                c.t1 = t;
+                for (int it : c.items) local[it] = -1;
+                chunks.push_back(std::move(c));
+                c = Chunk{t, t, {}};
+            }
+            const int it = pl.tiles[t].item;
+            if (local[it] < 0) {
+                local[it] = (int)c.items.size();
+                c.items.push_back(it);
+            }
+            tile_local[t] = local[it];
+        }
+        c.t1 = nt;
+        chunks.push_back(std::move(c));
+    }
+    int32_t *host_ctr_last = nullptr;
+    auto merge = [&](int ci) -> pj_status {
+        const int b = ci & 1;
+        const Chunk &c = chunks[ci];
+        const ItemOut *o = (const ItemOut *)ctx->pin_out[b].p;
+        for (size_t q = 0; q < c.items.size(); ++q) {
+            ItemOut &d = out[c.items[q]];
+            d.lb = std::min(d.lb, o[q].lb);
+            d.ub = std::min(d.ub, o[q].ub);
+            d.hit |= o[q].hit;
+        }
+        const int32_t *hc = (const int32_t *)ctx->pin_ctr[b].p;
+        unsigned long long pairs, culled;
+        std::memcpy(&pairs, hc + 2, 8);
+        std::memcpy(&culled, hc + 4, 8);
+        ctx->stats.facet_pairs += (int64_t)pairs;
+        ctx->stats.tiles_culled += (int64_t)culled;
+        float ms = 0;
+        HIPTRY(ctx, hipEventElapsedTime(&ms, ctx->ev_k0[b], ctx->ev_k1[b]));
+        ctx->stats.refine_kernel_ms += ms;
+        ctx->stats.refine_launches += 1;
+        host_ctr_last = (int32_t *)hc;
+        return PJ_OK;
+    };
+    for (int ci = 0; ci < (int)chunks.size(); ++ci) {
+        const int b = ci & 1;
+        const Chunk &c = chunks[ci];
+        const int cni = (int)c.items.size();
+        const int cnt = (int)(c.t1 - c.t0);
+        PJTRY(ensure(ctx, ctx->sb_items[b], cni * sizeof(Item)));
+        PJTRY(ensure(ctx, ctx->sb_tiles[b], cnt * sizeof(Tile)));
+        PJTRY(ensure(ctx, ctx->sb_out[b], cni * sizeof(ItemOut)));
+        PJTRY(ensure(ctx, ctx->sb_ctr[b], 64));
+        PJTRY(ensure_pinned(ctx, ctx->pin_items[b], cni * sizeof(Item)));
+        PJTRY(ensure_pinned(ctx, ctx->pin_tiles[b], cnt * sizeof(Tile)));
+        PJTRY(ensure_pinned(ctx, ctx->pin_out[b], cni * sizeof(ItemOut)));
+        PJTRY(ensure_pinned(ctx, ctx->pin_ctr[b], 64));
+        // host preparation of this chunk (the buffers of set b are free: the
+        // results of chunk ci - 2 were merged after its download event)
+        Item *hi = (Item *)ctx->pin_items[b].p;
+        Tile *ht = (Tile *)ctx->pin_tiles[b].p;
+        for (int q = 0; q < cni; ++q) hi[q] = pl.items[c.items[q]];
+        for (int64_t t = c.t0; t < c.t1; ++t) {
+            Tile x = pl.tiles[t];
+            x.item = tile_local[t];
+            ht[t - c.t0] = x;
+        }
+        int32_t *hc = (int32_t *)ctx->pin_ctr[b].p;
+        std::memset(hc, 0, 64);
+        hc[1] = cnt;
+        hc[6] = cni;
+        int32_t *dctr = ptr<int32_t>(ctx->sb_ctr[b]);
+        HIPTRY(ctx, hipMemcpyAsync(ctx->sb_items[b].p, hi, cni * sizeof(Item), hipMemcpyHostToDevice, ctx->up_stream));
+        HIPTRY(ctx, hipMemcpyAsync(ctx->sb_tiles[b].p, ht, cnt * sizeof(Tile), hipMemcpyHostToDevice, ctx->up_stream));
+        HIPTRY(ctx, hipMemcpyAsync(dctr, hc, 64, hipMemcpyHostToDevice, ctx->up_stream));
+        HIPTRY(ctx, hipEventRecord(ctx->ev_h2d[b], ctx->up_stream));
+        RefineArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.R = R->dev();
+        a.S = S->dev();
+        a.items = ptr<Item>(ctx->sb_items[b]);
+        a.tiles = ptr<Tile>(ctx->sb_tiles[b]);
+        a.ntiles = dctr + 1;
+        a.counter = dctr;
+        a.out = ptr<ItemOut>(ctx->sb_out[b]);
+        a.pairs_done = reinterpret_cast<unsigned long long *>(dctr + 2);
+        a.chunks_culled = reinterpret_cast<unsigned long long *>(dctr + 4);
+        a.tau = tau;
+        a.early = early ? 1 : 0;
+        a.cull = ctx->cfg.tile_cull ? 1 : 0;
+        HIPTRY(ctx, hipStreamWaitEvent(st, ctx->ev_h2d[b], 0));
+        HIPTRY(ctx, hipEventRecord(ctx->ev_k0[b], st));
+        PJTRY(launch_round(ctx, a, dctr, cni, cnt, wpc, graph, st));
+        HIPTRY(ctx, hipEventRecord(ctx->ev_k1[b], st));
+        HIPTRY(ctx, hipEventRecord(ctx->ev_comp[b], st));
+        HIPTRY(ctx, hipStreamWaitEvent(ctx->down_stream, ctx->ev_comp[b], 0));
+        HIPTRY(ctx, hipMemcpyAsync(ctx->pin_out[b].p, a.out, cni * sizeof(ItemOut), hipMemcpyDeviceToHost,
+                                   ctx->down_stream));
+        HIPTRY(ctx, hipMemcpyAsync(hc, dctr, 64, hipMemcpyDeviceToHost, ctx->down_stream));
+        HIPTRY(ctx, hipEventRecord(ctx->ev_d2h[b], ctx->down_stream));
+        ctx->stats.chunks++;
+        if (ci >= 1) {
+            HIPTRY(ctx, hipEventSynchronize(ctx->ev_d2h[(ci - 1) & 1]));
+            PJTRY(merge(ci - 1));
+        }
+    }
+    const int last = (int)chunks.size() - 1;
+    HIPTRY(ctx, hipEventSynchronize(ctx->ev_d2h[last & 1]));
+    PJTRY(merge(last));
+    // the join stream must not run ahead of the downloads
+    HIPTRY(ctx, hipStreamWaitEvent(st, ctx->ev_d2h[last & 1], 0));
     ctx->stats.tiles += nt;
-    unsigned long long pairs, culled;
-    std::memcpy(&pairs, host_ctr + 2, 8);
-    std::memcpy(&culled, host_ctr + 4, 8);
-    ctx->stats.facet_pairs += (int64_t)pairs;
-    ctx->stats.tiles_culled += (int64_t)culled;
+    ctx->stats.tile_s_used = pl.tile_s;
+    ctx->stats.waves_per_cu_used = wpc;
+    (void)host_ctr_last;
     return PJ_OK;
 }
 
@@ -812,6 +1096,19 @@ pj_status exact_finest(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
     const int ni = (int)pl.items.size(), nt = (int)pl.tiles.size();
     if (ni == 0) return PJ_OK;
     int64_t cap = std::max<int64_t>(1 << 20, 256 * (int64_t)ni);
+    if (ctx->cfg.mem_cap_bytes > 0) {
+        // the collect list takes what the cap leaves; items that overflow it
+        // are recomputed in full FP64 below
+        HIPTRY(ctx, hipStreamSynchronize(st));
+        for (DevBuf *x : {&ctx->b_items, &ctx->b_tiles, &ctx->b_out, &ctx->b_out64, &ctx->b_ovf, &ctx->b_coll,
+                          &ctx->b_ctr})
+            x->release();
+        const int64_t fixed = (int64_t)(ni * (sizeof(Item) + sizeof(ItemOut) + sizeof(ItemOut64) + sizeof(int32_t)) +
+                                        nt * sizeof(Tile) + 64 + 7 * 256);
+        const int64_t room = ctx->cfg.mem_cap_bytes - ctx->dev_bytes - fixed;
+        cap = std::min<int64_t>(cap, room / (int64_t)sizeof(PairRef));
+        if (cap < 256) return fail(ctx, PJ_ERR_OUT_OF_MEMORY, "the memory cap leaves no room for the FP64 recheck");
+    }
     PJTRY(ensure(ctx, ctx->b_items, ni * sizeof(Item)));
     PJTRY(ensure(ctx, ctx->b_tiles, nt * sizeof(Tile)));
     PJTRY(ensure(ctx, ctx->b_out, ni * sizeof(ItemOut)));
@@ -843,8 +1140,7 @@ pj_status exact_finest(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
     a.collect_cap = (int32_t)std::min<int64_t>(cap, INT32_MAX);
     a.collected = ptr<PairRef>(ctx->b_coll);
     a.overflow = ptr<int32_t>(ctx->b_ovf);
-    const int wpc = ctx->cfg.waves_per_cu > 0 ? ctx->cfg.waves_per_cu : 12;
-    const int grid = (int)std::min<int64_t>(nt, (int64_t)ctx->num_cu * wpc);
+    const int grid = (int)std::min<int64_t>(nt, (int64_t)ctx->num_cu * ctx->cur.wpc);
     HIPTRY(ctx, hipEventRecord(ctx->ev0, st));
     HIPTRY(ctx, launch_collect_f32(a, grid, st));
     HIPTRY(ctx, hipEventRecord(ctx->ev1, st));
@@ -945,7 +1241,19 @@ pj_status mbb_filter(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, do
 }
 
 // streamed-side facets per tile: a multiple of 64 so that chunks are blocks
-int pick_tile_s(pj_context *ctx) { return ctx->cfg.tile_s > 0 ? (ctx->cfg.tile_s + 63) / 64 * 64 : 1024; }
+int pick_tile_s(pj_context *ctx) { return ctx->cur.tile_s; }
+
+// per-join reset: counters (the ingest time stays) and the launch shape
+void begin_join(pj_context *ctx)
+{
+    const double ingest = ctx->stats.t_ingest_ms;
+    std::memset(&ctx->stats, 0, sizeof(ctx->stats));
+    ctx->stats.t_ingest_ms = ingest;
+    ctx->cur = pj_context::Shape{};
+    if (ctx->cfg.tile_s > 0) ctx->cur.tile_s = (ctx->cfg.tile_s + 63) / 64 * 64;
+    if (ctx->cfg.waves_per_cu > 0) ctx->cur.wpc = ctx->cfg.waves_per_cu;
+    ctx->peak_bytes = ctx->dev_bytes;
+}
 
 // Progressive refinement of within-tau candidates (Section 3.1): returns the
 // confirmed candidate indices.
@@ -995,9 +1303,10 @@ pj_status refine_within(pj_context *ctx, const pj_meshes *R, const pj_meshes *S,
                 }
             }
         } else {
-            plan_tiles(R, S, act, cand, ps, lod, finest, 64 * kP, TS, true, pl);
+            PJTRY(choose_shape(ctx, R, S, act, cand, ps, lod, finest, (float)tau, true));
+            plan_tiles(R, S, act, cand, ps, lod, finest, 64 * kP, ctx->cur.tile_s, true, pl);
             std::vector<ItemOut> out;
-            PJTRY(run_f32(ctx, R, S, pl, (float)tau, true, out));
+            PJTRY(run_f32(ctx, R, S, pl, (float)tau, true, out, 0));
             for (size_t k = 0; k < pl.items.size(); ++k) {
                 PairState &p = ps[pl.items[k].cand];
                 double lb = bits_to_float(out[k].lb), ub = bits_to_float(out[k].ub), e = p.eps;
@@ -1171,9 +1480,8 @@ extern "C" pj_status pj_join_within(pj_context *ctx, const pj_meshes *R, const p
     PJTRY(check_pair_args(ctx, R, S));
     if (!(tau >= 0.0) || !std::isfinite(tau)) return fail(ctx, PJ_ERR_INVALID_ARG, "tau must be finite and >= 0");
     HIPTRY(ctx, hipSetDevice(ctx->cfg.device));
-    std::memset(&ctx->stats, 0, sizeof(ctx->stats) - sizeof(double) * 0);
+    begin_join(ctx);
     double t0 = now_ms();
-    ctx->peak_bytes = ctx->dev_bytes;
     if (R->n == 0 || S->n == 0) {
         ctx->stats.t_total_ms = now_ms() - t0;
         return PJ_OK;
@@ -1284,9 +1592,8 @@ extern "C" pj_status pj_join_knn(pj_context *ctx, const pj_meshes *R, const pj_m
     PJTRY(check_pair_args(ctx, R, S));
     if (k < 1) return fail(ctx, PJ_ERR_INVALID_ARG, "k must be >= 1");
     HIPTRY(ctx, hipSetDevice(ctx->cfg.device));
-    std::memset(&ctx->stats, 0, sizeof(ctx->stats));
+    begin_join(ctx);
     const double t0 = now_ms();
-    ctx->peak_bytes = ctx->dev_bytes;
     const int nR = R->n, nS = S->n;
     out->n_r = nR;
     out->k = k;
@@ -1373,9 +1680,10 @@ extern "C" pj_status pj_join_knn(pj_context *ctx, const pj_meshes *R, const pj_m
                 p.UB = std::min(p.UB, bits_to_double(o64[q].ub) + e64);
             }
         } else {
-            plan_tiles(R, S, act, cand, ps, lod, 0, 64 * kP, TS, true, pl);
+            PJTRY(choose_shape(ctx, R, S, act, cand, ps, lod, 0, -1.0f, false));
+            plan_tiles(R, S, act, cand, ps, lod, 0, 64 * kP, ctx->cur.tile_s, true, pl);
             std::vector<ItemOut> o32;
-            PJTRY(run_f32(ctx, R, S, pl, -1.0f, false, o32));
+            PJTRY(run_f32(ctx, R, S, pl, -1.0f, false, o32, 0));
             for (size_t q = 0; q < pl.items.size(); ++q) {
                 PairState &p = ps[pl.items[q].cand];
                 p.LB = std::max(p.LB, (double)bits_to_float(o32[q].lb) - p.eps);
@@ -1522,7 +1830,7 @@ extern "C" pj_status pj_pair_bounds(pj_context *ctx, const pj_meshes *R, const p
     } else {
         plan_tiles(R, S, act, cand, ps, lod, finest, 64 * kP, pick_tile_s(ctx), true, pl);
         std::vector<ItemOut> out;
-        PJTRY(run_f32(ctx, R, S, pl, -1.0f, false, out));
+        PJTRY(run_f32(ctx, R, S, pl, -1.0f, false, out, 0));
         for (size_t k = 0; k < pl.items.size(); ++k) {
             int c = pl.items[k].cand;
             lb[c] = bits_to_float(out[k].lb);

@@ -1,0 +1,128 @@
+"""GPU: chunked streaming of the bulk rounds and the launch-shape autotuner.
+
+Neither may change a result: the per-item minima are merged over chunks and
+are independent of tiling and grid size, so every variant is compared pair
+set for pair set (and kNN list for list) with the oracle or the default
+launch."""
+import os
+
+import numpy as np
+import pytest
+
+import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pj():
+    import paper_2604_19982_amd as pj
+    return pj
+
+
+@pytest.fixture(scope="module")
+def mid():
+    return mg.config_multilod(seed=1, n_r=400, n_s=80, box=150.0, n_seg=1280)
+
+
+@pytest.mark.parametrize("tau", [0.0, 5.0, 20.0])
+def test_streamed_chunks_match_oracle(orc, pj, mid, tau):
+    """A few tiles per chunk: items are split over many chunks, uploaded on
+    one stream, computed on the join stream and read back on a third."""
+    R, S = mid
+    c = pj.Context(chunk_tiles=37)
+    got = c.join_within(c.meshes(R), c.meshes(S), tau)
+    st = c.stats()
+    ref = orc.join_within(orc.OSet(R), orc.OSet(S), tau)
+    assert ref["near_ties"] == 0
+    assert np.array_equal(got["r"], ref["r"]) and np.array_equal(got["s"], ref["s"])
+    assert st["chunks"] > st["rounds"]
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_streamed_chunks_match_single_chunk(pj, mid, use_graph):
+    R, S = mid
+    one = pj.Context(use_graph=use_graph)
+    many = pj.Context(use_graph=use_graph, chunk_tiles=101)
+    oR, oS = one.meshes(R), one.meshes(S)
+    mR, mS = many.meshes(R), many.meshes(S)
+    for tau in (5.0, 0.0, 20.0):
+        a = one.join_within(oR, oS, tau)
+        b = many.join_within(mR, mS, tau)
+        assert np.array_equal(a["r"], b["r"]) and np.array_equal(a["s"], b["s"]), tau
+        assert many.stats()["chunks"] > one.stats()["chunks"]
+
+
+def test_streamed_chunks_knn(orc, pj):
+    R, S = mg.config_knn(seed=3, n_r=40, n_s=40, n_clusters=2, box=200.0, sigma=12.0, f_median=2000)
+    base = pj.Context()
+    many = pj.Context(chunk_tiles=13)
+    a = base.join_knn(base.meshes(R), base.meshes(S), 3)
+    b = many.join_knn(many.meshes(R), many.meshes(S), 3)
+    assert np.array_equal(a["s"], b["s"]) and np.array_equal(a["count"], b["count"])
+    assert np.array_equal(a["dist"], b["dist"])
+    assert many.stats()["chunks"] > base.stats()["chunks"]
+
+
+def test_mem_cap_too_small_is_an_error(pj, mid):
+    R, S = mid
+    c = pj.Context(mem_cap_bytes=4096)
+    gR, gS = c.meshes(R), c.meshes(S)
+    with pytest.raises(pj.PJError) as e:
+        c.join_within(gR, gS, 5.0)
+    assert e.value.status == 2  # PJ_ERR_OUT_OF_MEMORY
+
+
+def test_mem_cap_streams_under_budget(pj, mid):
+    """Caps below the uncapped high-water mark: the bulk rounds stream in
+    more chunks, the FP64 recheck list shrinks, results stay the same and
+    the work buffers stay under the cap (or the join says it cannot fit)."""
+    R, S = mid
+    free = pj.Context()
+    ref = free.join_within(free.meshes(R), free.meshes(S), 5.0)
+    peak = free.stats()["peak_device_bytes"]
+    streamed = 0
+    for frac in (0.5, 0.2, 0.08):
+        cap = int(peak * frac)
+        c = pj.Context(mem_cap_bytes=cap)
+        gR, gS = c.meshes(R), c.meshes(S)
+        try:
+            got = c.join_within(gR, gS, 5.0)
+        except pj.PJError as e:
+            assert e.status == 2 and frac < 0.5, (frac, str(e))
+            continue
+        st = c.stats()
+        assert np.array_equal(got["r"], ref["r"]) and np.array_equal(got["s"], ref["s"]), frac
+        assert st["peak_device_bytes"] <= cap, frac
+        streamed += st["chunks"] > st["rounds"]
+    assert streamed
+
+
+def test_autotune_picks_cached_shape(pj, mid, tmp_path):
+    R, S = mid
+    path = str(tmp_path / "tune.txt")
+    base = pj.Context()
+    ref = base.join_within(base.meshes(R), base.meshes(S), 5.0)
+    t1 = pj.Context(autotune=True, autotune_path=path)
+    a = t1.join_within(t1.meshes(R), t1.meshes(S), 5.0)
+    s1 = t1.stats()
+    assert np.array_equal(a["r"], ref["r"]) and np.array_equal(a["s"], ref["s"])
+    assert s1["t_tune_ms"] > 0.0
+    assert s1["tile_s_used"] in (256, 512, 1024, 2048, 4096)
+    assert s1["waves_per_cu_used"] in (4, 8, 12, 16, 24)
+    lines = open(path).read().split("\n")
+    rows = [ln.split() for ln in lines if ln.strip()]
+    assert rows and all(len(r) == 4 for r in rows)
+    # a second context reads the cache and does not tune again
+    t2 = pj.Context(autotune=True, autotune_path=path)
+    b = t2.join_within(t2.meshes(R), t2.meshes(S), 5.0)
+    s2 = t2.stats()
+    assert np.array_equal(b["r"], ref["r"]) and np.array_equal(b["s"], ref["s"])
+    assert s2["t_tune_ms"] == 0.0
+    assert s2["tile_s_used"] == s1["tile_s_used"] and s2["waves_per_cu_used"] == s1["waves_per_cu_used"]
+    # explicit shapes win over the cache
+    t3 = pj.Context(autotune=True, autotune_path=path, tile_s=512, waves_per_cu=8)
+    t3.join_within(t3.meshes(R), t3.meshes(S), 5.0)
+    s3 = t3.stats()
+    assert (s3["tile_s_used"], s3["waves_per_cu_used"]) == (512, 8)
+    assert os.path.getsize(path) > 0
