@@ -69,12 +69,23 @@ typedef struct {
     int32_t autotune;        /* 1: time candidate (tile_s, waves_per_cu) shapes on a sample of the first
                                 round of each work class and keep the fastest (cached in autotune_path);
                                 an explicit tile_s / waves_per_cu always wins */
+    int32_t mesh_residency;  /* pj_residency of mesh sets created on this context */
+    int32_t stage_sets;      /* staging buffer sets for streamed chunks, 2 or 3 (0: 2) */
     int64_t mem_cap_bytes;   /* device-memory budget for join work buffers (0: no cap) */
     const char *model_path;  /* LoD model weights written by pj_train_lod_model (NULL: none) */
     const char *log_path;    /* append per-pair resolution records here (NULL: no log) */
     const char *autotune_path; /* autotuner cache file (NULL: none) */
     void *stream;            /* hipStream_t to run on (NULL: the library creates one) */
 } pj_config;
+
+/* Where a mesh set's facet data live.  DEVICE: uploaded once at ingest.
+ * HOST: kept in host memory; each refinement chunk gathers the facets of
+ * its objects at the round's LoD into pinned staging on host threads and
+ * uploads them on a copy stream while the previous chunk computes (the
+ * paper's pipelined data transfer, Section 4.2 and Algorithm 5).  The device
+ * then holds only boxes, anchors and per-LoD maxima of the set, and the
+ * streamed chunks are sized by mem_cap_bytes. */
+typedef enum { PJ_RESIDENT_DEVICE = 0, PJ_RESIDENT_HOST = 1 } pj_residency;
 
 /* Fill *cfg with defaults: device 0, FP32 band, batched, tile culling on,
  * graphs on, no learned skip, no cap, autotuner off (tile_s 1024, 12 waves
@@ -173,6 +184,7 @@ typedef struct {
     int64_t tile_s_used;        /* streamed-side tile length of the last bulk round */
     int64_t waves_per_cu_used;  /* persistent grid of the last bulk round, waves per CU */
     double t_tune_ms;           /* host time spent in the autotuner during this join */
+    int64_t staged_bytes;       /* host-to-device bytes of staged facet data (host-resident sets) */
 } pj_stats;
 
 pj_status pj_get_stats(const pj_context *ctx, pj_stats *out);

@@ -31,7 +31,8 @@ class Config(ctypes.Structure):
                 ("learned_skip", ctypes.c_int32), ("want_dist", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("tile_cull", ctypes.c_int32), ("tile_s", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
                 ("host_threads", ctypes.c_int32), ("chunk_tiles", ctypes.c_int32),
-                ("autotune", ctypes.c_int32), ("mem_cap_bytes", ctypes.c_int64),
+                ("autotune", ctypes.c_int32), ("mesh_residency", ctypes.c_int32), ("stage_sets", ctypes.c_int32),
+                ("mem_cap_bytes", ctypes.c_int64),
                 ("model_path", ctypes.c_char_p), ("log_path", ctypes.c_char_p), ("autotune_path", ctypes.c_char_p),
                 ("stream", ctypes.c_void_p)]
 
@@ -64,7 +65,8 @@ class Stats(ctypes.Structure):
                 ("band_pairs", ctypes.c_int64), ("resolved_at_lod", ctypes.c_int64 * 8), ("rounds", ctypes.c_int64),
                 ("peak_device_bytes", ctypes.c_int64), ("chunks", ctypes.c_int64),
                 ("graph_replays", ctypes.c_int64), ("tile_s_used", ctypes.c_int64),
-                ("waves_per_cu_used", ctypes.c_int64), ("t_tune_ms", ctypes.c_double)]
+                ("waves_per_cu_used", ctypes.c_int64), ("t_tune_ms", ctypes.c_double),
+                ("staged_bytes", ctypes.c_int64)]
 
     def to_dict(self):
         d = {}
@@ -177,7 +179,8 @@ class Context:
 
     def __init__(self, device=0, precision="fp32", schedule="batched", learned_skip=False, want_dist=False,
                  use_graph=True, tile_cull=True, tile_s=0, waves_per_cu=0, mem_cap_bytes=0, model_path=None,
-                 log_path=None, stream=None, chunk_tiles=0, autotune=False, autotune_path=None):
+                 log_path=None, stream=None, chunk_tiles=0, autotune=False, autotune_path=None,
+                 host_resident=False, stage_sets=0):
         L = lib()
         c = Config()
         L.pj_config_default(ctypes.byref(c))
@@ -193,6 +196,8 @@ class Context:
         c.mem_cap_bytes = int(mem_cap_bytes)
         c.chunk_tiles = int(chunk_tiles)
         c.autotune = int(bool(autotune))
+        c.mesh_residency = 1 if host_resident else 0
+        c.stage_sets = int(stage_sets)
         self._paths = [None if p is None else os.fsencode(p) for p in (model_path, log_path, autotune_path)]
         c.model_path, c.log_path, c.autotune_path = self._paths
         c.stream = stream

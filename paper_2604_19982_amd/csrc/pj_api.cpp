@@ -19,6 +19,7 @@
 #include <set>
 #include <string>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "pj_internal.h"
@@ -68,15 +69,24 @@ struct pj_meshes {
     float4 *d_blk = nullptr;
     int64_t nblk = 0;
     std::vector<int64_t> h_vbeg, h_tbeg, h_hpbeg, h_bkbeg;
-    std::vector<int32_t> h_tcnt;
+    std::vector<int32_t> h_tcnt, h_vcnt;
     std::vector<float> h_box, h_anchor;
     std::vector<float2> h_lodmax;
+    // host-resident sets: facet data in host memory (the device holds only
+    // d_box, d_anchor and d_lodmax)
+    bool host = false;
+    std::vector<float> h_verts;
+    std::vector<int32_t> h_tris;
+    std::vector<float2> h_hdph;
+    std::vector<float4> h_blk;
     MeshDev dev() const
     {
         return MeshDev{d_verts, d_tris, d_vbeg, d_tbeg, d_tcnt, d_hpbeg, d_hdph, d_bkbeg, d_blk, n, L};
     }
     int32_t count(int obj, int lod) const { return h_tcnt[(int64_t)obj * L + lod]; }
 };
+
+constexpr int kMaxSets = 3;  // staging buffer sets of the streamed rounds
 
 struct pj_context {
     pj_config cfg;
@@ -95,11 +105,11 @@ struct pj_context {
         void *p = nullptr;
         size_t cap = 0;
     };
-    DevBuf sb_items[2], sb_tiles[2], sb_out[2], sb_ctr[2];
-    PinBuf pin_items[2], pin_tiles[2], pin_out[2], pin_ctr[2];
+    DevBuf sb_items[kMaxSets], sb_tiles[kMaxSets], sb_out[kMaxSets], sb_ctr[kMaxSets], sb_stage[kMaxSets];
+    PinBuf pin_items[kMaxSets], pin_tiles[kMaxSets], pin_out[kMaxSets], pin_ctr[kMaxSets], pin_stage[kMaxSets];
     hipStream_t up_stream = nullptr, down_stream = nullptr;
-    hipEvent_t ev_h2d[2] = {nullptr, nullptr}, ev_comp[2] = {nullptr, nullptr}, ev_d2h[2] = {nullptr, nullptr},
-               ev_k0[2] = {nullptr, nullptr}, ev_k1[2] = {nullptr, nullptr};
+    hipEvent_t ev_h2d[kMaxSets] = {}, ev_comp[kMaxSets] = {}, ev_d2h[kMaxSets] = {}, ev_k0[kMaxSets] = {},
+               ev_k1[kMaxSets] = {};
     // launch shape of the bulk rounds: explicit config > tuned > defaults
     struct Shape {
         int tile_s = 1024, wpc = 12;
@@ -236,7 +246,8 @@ extern "C" pj_status pj_context_create(const pj_config *cfg, pj_context **out)
         if (colon != std::string::npos) ctx->arch.resize(colon);
     }
     if (ctx->arch.empty()) ctx->arch = "gpu";
-    if (c.chunk_tiles < 0) {
+    if (c.chunk_tiles < 0 || (c.mesh_residency != PJ_RESIDENT_DEVICE && c.mesh_residency != PJ_RESIDENT_HOST) ||
+        (c.stage_sets != 0 && c.stage_sets != 2 && c.stage_sets != 3)) {
         delete ctx;
         return PJ_ERR_INVALID_ARG;
     }
@@ -267,8 +278,8 @@ extern "C" pj_status pj_context_destroy(pj_context *ctx)
     (void)hipStreamSynchronize(ctx->stream);
     for (auto &g : ctx->graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
-    for (int b = 0; b < 2; ++b) {
-        for (auto *pb : {&ctx->pin_items[b], &ctx->pin_tiles[b], &ctx->pin_out[b], &ctx->pin_ctr[b]})
+    for (int b = 0; b < kMaxSets; ++b) {
+        for (auto *pb : {&ctx->pin_items[b], &ctx->pin_tiles[b], &ctx->pin_out[b], &ctx->pin_ctr[b], &ctx->pin_stage[b]})
             if (pb->p) (void)hipHostFree(pb->p);
         for (hipEvent_t e : {ctx->ev_h2d[b], ctx->ev_comp[b], ctx->ev_d2h[b], ctx->ev_k0[b], ctx->ev_k1[b]})
             if (e) (void)hipEventDestroy(e);
@@ -372,29 +383,21 @@ pj_status validate_desc(pj_context *ctx, const pj_mesh_desc *d)
 
 }  // namespace
 
-extern "C" pj_status pj_meshes_create(pj_context *ctx, const pj_mesh_desc *d, pj_meshes **out)
+// Device-resident ingest of a validated description into m (on failure the
+// caller frees m).  Boxes, anchors, hd/ph, block records and per-LoD maxima
+// are computed on the GPU; host copies of the small per-object arrays stay.
+pj_status ingest_device(pj_context *ctx, const pj_mesh_desc *d, pj_meshes *m)
 {
-    if (!ctx || !d || !out) return fail(ctx, PJ_ERR_INVALID_ARG, "NULL argument");
-    *out = nullptr;
-    double t0 = now_ms();
-    PJTRY(validate_desc(ctx, d));
-    HIPTRY(ctx, hipSetDevice(ctx->cfg.device));
     hipStream_t st = ctx->stream;
-    pj_meshes *m = new pj_meshes();
     m->device = ctx->cfg.device;
     m->n = d->n_objects;
     m->L = d->n_lods;
     m->nv = d->n_verts;
     m->nt = d->n_tris;
     const int64_t n = m->n, L = m->L;
-    auto bail = [&](hipError_t e, const char *what) {
-        free_meshes(m);
-        return hipfail(ctx, e, what);
-    };
-    if (n == 0) {
-        *out = m;
-        return PJ_OK;
-    }
+    auto bail = [&](hipError_t e, const char *what) { return hipfail(ctx, e, what); };
+    if (n == 0) return PJ_OK;
+    m->h_vcnt.assign(d->vert_count, d->vert_count + n);
     m->h_vbeg.assign(d->vert_begin, d->vert_begin + n);
     m->h_tbeg.assign(d->tri_begin, d->tri_begin + n * L);
     m->h_tcnt.assign(d->tri_count, d->tri_count + n * L);
@@ -408,8 +411,6 @@ extern "C" pj_status pj_meshes_create(pj_context *ctx, const pj_mesh_desc *d, pj
         }
     m->nh = nh;
     hipError_t e;
-    std::vector<int32_t> vc(d->vert_count, d->vert_count + n);
-    (void)vc;
     if ((e = upload(&m->d_verts, d->verts, 3 * (size_t)d->n_verts, st)) != hipSuccess) return bail(e, "verts");
     if ((e = upload(&m->d_tris, d->tris, 3 * (size_t)d->n_tris, st)) != hipSuccess) return bail(e, "tris");
     if ((e = upload(&m->d_vbeg, m->h_vbeg.data(), n, st)) != hipSuccess) return bail(e, "vert_begin");
@@ -434,10 +435,8 @@ extern "C" pj_status pj_meshes_create(pj_context *ctx, const pj_mesh_desc *d, pj
                 int64_t src = d->hdph_begin[i * L + l], dst = m->h_hpbeg[i * L + l];
                 for (int32_t q = 0; q < m->h_tcnt[i * L + l]; ++q) {
                     float a = d->hd[src + q], b = d->ph[src + q];
-                    if (!(a >= 0.0f) || !(b >= 0.0f) || !std::isfinite(a) || !std::isfinite(b)) {
-                        free_meshes(m);
+                    if (!(a >= 0.0f) || !(b >= 0.0f) || !std::isfinite(a) || !std::isfinite(b))
                         return fail(ctx, PJ_ERR_INVALID_ARG, "hd/ph must be finite and non-negative");
-                    }
                     hp[dst + q] = make_float2(a, b);
                 }
             }
@@ -496,10 +495,8 @@ extern "C" pj_status pj_meshes_create(pj_context *ctx, const pj_mesh_desc *d, pj
                 for (int64_t l = 0; l < L; ++l) desc_base[i * L + l] = desc_base[src * L + l];
             }
         }
-        if (desc_list.size() > (size_t)INT32_MAX || desc_off.size() > (size_t)INT64_MAX) {
-            free_meshes(m);
+        if (desc_list.size() > (size_t)INT32_MAX || desc_off.size() > (size_t)INT64_MAX)
             return fail(ctx, PJ_ERR_UNSUPPORTED, "descendant tables too large");
-        }
         std::vector<int32_t> desc_off32(desc_off.begin(), desc_off.end());
         int64_t *d_dbase = nullptr;
         int32_t *d_doff = nullptr, *d_dlist = nullptr;
@@ -550,6 +547,167 @@ extern "C" pj_status pj_meshes_create(pj_context *ctx, const pj_mesh_desc *d, pj
         hipSuccess)
         return bail(e, "lodmax D2H");
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return bail(e, "ingest sync");
+    return PJ_OK;
+}
+
+// Host-resident ingest: the per-object preprocessing runs on the GPU over
+// batches of objects (each batch a compact device-resident set of its own,
+// released afterwards); hd/ph and block records come back to host memory.
+pj_status ingest_host(pj_context *ctx, const pj_mesh_desc *d, pj_meshes *m)
+{
+    hipStream_t st = ctx->stream;
+    m->host = true;
+    m->device = ctx->cfg.device;
+    m->n = d->n_objects;
+    m->L = d->n_lods;
+    m->nv = d->n_verts;
+    m->nt = d->n_tris;
+    const int64_t n = m->n, L = m->L;
+    if (n == 0) return PJ_OK;
+    m->h_vbeg.assign(d->vert_begin, d->vert_begin + n);
+    m->h_vcnt.assign(d->vert_count, d->vert_count + n);
+    m->h_tbeg.assign(d->tri_begin, d->tri_begin + n * L);
+    m->h_tcnt.assign(d->tri_count, d->tri_count + n * L);
+    m->h_verts.assign(d->verts, d->verts + 3 * d->n_verts);
+    m->h_tris.assign(d->tris, d->tris + 3 * d->n_tris);
+    m->h_hpbeg.assign(n * L, -1);
+    int64_t nh = 0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t l = 0; l + 1 < L; ++l) {
+            m->h_hpbeg[i * L + l] = nh;
+            nh += m->h_tcnt[i * L + l];
+        }
+    m->nh = nh;
+    m->h_bkbeg.assign(n * L + 1, 0);
+    for (int64_t k = 0; k < n * L; ++k) m->h_bkbeg[k + 1] = m->h_bkbeg[k] + (m->h_tcnt[k] + 63) / 64;
+    m->nblk = m->h_bkbeg[n * L];
+    m->h_hdph.assign(nh, make_float2(0.0f, 0.0f));
+    m->h_blk.resize(2 * m->nblk);
+    m->h_box.resize(n * 6);
+    m->h_anchor.resize(n * 3);
+    m->h_lodmax.resize(n * L);
+    const int64_t budget =
+        ctx->cfg.mem_cap_bytes > 0 ? std::max<int64_t>(ctx->cfg.mem_cap_bytes / 4, int64_t(1) << 20) : int64_t(2) << 30;
+    for (int64_t o0 = 0; o0 < n;) {
+        // batch [o0, o1): vertices, the distinct triangle ranges, their
+        // parents and (when given) the caller's hd/ph
+        int64_t o1 = o0, bytes = 0;
+        while (o1 < n) {
+            int64_t b = 12 * (int64_t)m->h_vcnt[o1] + 64;
+            for (int64_t l = 0; l < L; ++l) b += 64 * (int64_t)m->h_tcnt[o1 * L + l] + 64;
+            if (o1 > o0 && bytes + b > budget) break;
+            bytes += b;
+            ++o1;
+        }
+        const int64_t nb = o1 - o0;
+        std::vector<float> sv;
+        std::vector<int64_t> svb(nb), stb(nb * L), shb;
+        std::vector<int32_t> svc(nb), stc(nb * L), stris, spar;
+        std::vector<float> shd, sph;
+        std::map<std::pair<int64_t, int32_t>, int64_t> ranges;
+        for (int64_t i = 0; i < nb; ++i) {
+            const int64_t o = o0 + i;
+            svb[i] = (int64_t)sv.size() / 3;
+            svc[i] = m->h_vcnt[o];
+            sv.insert(sv.end(), d->verts + 3 * m->h_vbeg[o], d->verts + 3 * (m->h_vbeg[o] + m->h_vcnt[o]));
+            for (int64_t l = 0; l < L; ++l) {
+                const int64_t tb = m->h_tbeg[o * L + l];
+                const int32_t tc = m->h_tcnt[o * L + l];
+                auto it = ranges.find({tb, tc});
+                if (it == ranges.end()) {
+                    it = ranges.emplace(std::make_pair(tb, tc), (int64_t)stris.size() / 3).first;
+                    stris.insert(stris.end(), d->tris + 3 * tb, d->tris + 3 * (tb + tc));
+                    if (d->parent) spar.insert(spar.end(), d->parent + tb, d->parent + tb + tc);
+                }
+                stb[i * L + l] = it->second;
+                stc[i * L + l] = tc;
+            }
+        }
+        if (d->hd) {
+            shb.assign(nb * L, 0);
+            for (int64_t i = 0; i < nb; ++i)
+                for (int64_t l = 0; l + 1 < L; ++l) {
+                    const int64_t src = d->hdph_begin[(o0 + i) * L + l];
+                    const int32_t tc = stc[i * L + l];
+                    shb[i * L + l] = (int64_t)shd.size();
+                    shd.insert(shd.end(), d->hd + src, d->hd + src + tc);
+                    sph.insert(sph.end(), d->ph + src, d->ph + src + tc);
+                }
+        }
+        pj_mesh_desc sub;
+        std::memset(&sub, 0, sizeof(sub));
+        sub.n_objects = (int32_t)nb;
+        sub.n_lods = (int32_t)L;
+        sub.n_verts = (int64_t)sv.size() / 3;
+        sub.n_tris = (int64_t)stris.size() / 3;
+        sub.verts = sv.data();
+        sub.vert_begin = svb.data();
+        sub.vert_count = svc.data();
+        sub.tris = stris.data();
+        sub.tri_begin = stb.data();
+        sub.tri_count = stc.data();
+        sub.parent = d->parent ? spar.data() : nullptr;
+        if (d->hd) {
+            sub.hd = shd.data();
+            sub.ph = sph.data();
+            sub.hdph_begin = shb.data();
+        }
+        pj_meshes *tmp = new pj_meshes();
+        pj_status s = ingest_device(ctx, &sub, tmp);
+        if (s == PJ_OK) {
+            std::vector<float2> hp(std::max<int64_t>(tmp->nh, 1));
+            std::vector<float4> bk(std::max<int64_t>(2 * tmp->nblk, 1));
+            hipError_t e = hipMemcpyAsync(hp.data(), tmp->d_hdph, tmp->nh * sizeof(float2), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(bk.data(), tmp->d_blk, 2 * tmp->nblk * sizeof(float4), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) {
+                s = hipfail(ctx, e, "host-resident ingest download");
+            } else {
+                for (int64_t i = 0; i < nb; ++i) {
+                    const int64_t o = o0 + i;
+                    std::memcpy(&m->h_box[6 * o], &tmp->h_box[6 * i], 6 * sizeof(float));
+                    std::memcpy(&m->h_anchor[3 * o], &tmp->h_anchor[3 * i], 3 * sizeof(float));
+                    for (int64_t l = 0; l < L; ++l) {
+                        const int64_t kf = o * L + l, ks = i * L + l;
+                        m->h_lodmax[kf] = tmp->h_lodmax[ks];
+                        const int32_t tc = m->h_tcnt[kf];
+                        if (l + 1 < L && tc)
+                            std::memcpy(&m->h_hdph[m->h_hpbeg[kf]], &hp[tmp->h_hpbeg[ks]], tc * sizeof(float2));
+                        const int64_t nbk = (tc + 63) / 64;
+                        if (nbk)
+                            std::memcpy(&m->h_blk[2 * m->h_bkbeg[kf]], &bk[2 * tmp->h_bkbeg[ks]],
+                                        2 * nbk * sizeof(float4));
+                    }
+                }
+            }
+        }
+        free_meshes(tmp);
+        if (s != PJ_OK) return s;
+        o0 = o1;
+    }
+    hipError_t e;
+    if ((e = upload(&m->d_box, m->h_box.data(), 6 * n, st)) != hipSuccess) return hipfail(ctx, e, "boxes");
+    if ((e = upload(&m->d_anchor, m->h_anchor.data(), 3 * n, st)) != hipSuccess) return hipfail(ctx, e, "anchors");
+    if ((e = upload(&m->d_lodmax, m->h_lodmax.data(), n * L, st)) != hipSuccess) return hipfail(ctx, e, "lodmax");
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hipfail(ctx, e, "ingest sync");
+    return PJ_OK;
+}
+
+extern "C" pj_status pj_meshes_create(pj_context *ctx, const pj_mesh_desc *d, pj_meshes **out)
+{
+    if (!ctx || !d || !out) return fail(ctx, PJ_ERR_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    const double t0 = now_ms();
+    PJTRY(validate_desc(ctx, d));
+    HIPTRY(ctx, hipSetDevice(ctx->cfg.device));
+    pj_meshes *m = new pj_meshes();
+    const pj_status s =
+        ctx->cfg.mesh_residency == PJ_RESIDENT_HOST ? ingest_host(ctx, d, m) : ingest_device(ctx, d, m);
+    if (s != PJ_OK) {
+        free_meshes(m);
+        return s;
+    }
     ctx->stats.t_ingest_ms = now_ms() - t0;
     *out = m;
     return PJ_OK;
@@ -582,9 +740,14 @@ extern "C" pj_status pj_meshes_hdph(const pj_meshes *m, int32_t obj, int32_t lod
         return PJ_OK;
     }
     std::vector<float2> tmp(nf);
-    if (hipSetDevice(m->device) != hipSuccess) return PJ_ERR_DEVICE;
-    if (nf && hipMemcpy(tmp.data(), m->d_hdph + m->h_hpbeg[k], nf * sizeof(float2), hipMemcpyDeviceToHost) != hipSuccess)
-        return PJ_ERR_DEVICE;
+    if (m->host) {
+        if (nf) std::memcpy(tmp.data(), &m->h_hdph[m->h_hpbeg[k]], nf * sizeof(float2));
+    } else {
+        if (hipSetDevice(m->device) != hipSuccess) return PJ_ERR_DEVICE;
+        if (nf &&
+            hipMemcpy(tmp.data(), m->d_hdph + m->h_hpbeg[k], nf * sizeof(float2), hipMemcpyDeviceToHost) != hipSuccess)
+            return PJ_ERR_DEVICE;
+    }
     for (int32_t q = 0; q < nf; ++q) {
         hd[q] = tmp[q].x;
         ph[q] = tmp[q].y;
@@ -813,6 +976,7 @@ pj_status ensure_pinned(pj_context *ctx, pj_context::PinBuf &b, size_t bytes)
     b.p = nullptr;
     b.cap = 0;
     size_t nb = std::max<size_t>(bytes, 4096);
+    nb = std::max(nb, b.cap + b.cap / 2);
     hipError_t e = hipHostMalloc(&b.p, nb, hipHostMallocDefault);
     if (e != hipSuccess) return hipfail(ctx, e, "hipHostMalloc");
     b.cap = nb;
@@ -824,12 +988,262 @@ pj_status ensure_streams(pj_context *ctx)
     if (ctx->up_stream) return PJ_OK;
     HIPTRY(ctx, hipStreamCreateWithFlags(&ctx->up_stream, hipStreamNonBlocking));
     HIPTRY(ctx, hipStreamCreateWithFlags(&ctx->down_stream, hipStreamNonBlocking));
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < kMaxSets; ++b) {
         HIPTRY(ctx, hipEventCreateWithFlags(&ctx->ev_h2d[b], hipEventDisableTiming));
         HIPTRY(ctx, hipEventCreateWithFlags(&ctx->ev_comp[b], hipEventDisableTiming));
         HIPTRY(ctx, hipEventCreateWithFlags(&ctx->ev_d2h[b], hipEventDisableTiming));
         HIPTRY(ctx, hipEventCreate(&ctx->ev_k0[b]));
         HIPTRY(ctx, hipEventCreate(&ctx->ev_k1[b]));
+    }
+    return PJ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Staging of host-resident facet data.  The objects a chunk needs from one
+// side are packed, at the chunk's LoD, as a mesh set of their own (same
+// arrays as a device-resident set, one buffer, rows renumbered; triangle
+// ranges shared by several objects are staged once), so the kernels read
+// staged and resident sets alike.  Only the round's LoD entries of the
+// per-(object, LoD) arrays are filled.
+// ---------------------------------------------------------------------------
+struct SideStage {
+    int lod = 0;
+    bool finest = false;
+    std::vector<int32_t> objs;                  // original ids, in local order
+    std::vector<int64_t> vdst, tdst, hdst, bdst;  // staged first rows per object
+    std::vector<char> tcopy;                    // object copies its triangle range
+    int64_t V = 0, T = 0, H = 0, B = 0;
+    size_t o_verts = 0, o_tris = 0, o_vbeg = 0, o_tbeg = 0, o_tcnt = 0, o_hpbeg = 0, o_hdph = 0, o_bkbeg = 0,
+           o_blk = 0, end = 0;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+constexpr int64_t kStageFixed = 10 * 256;
+
+// staged bytes of one object at one LoD (an upper bound: no range sharing)
+int64_t stage_obj_bytes(const pj_meshes *m, int obj, int lod, bool finest)
+{
+    const int64_t tc = m->count(obj, lod);
+    return 12 * (int64_t)m->h_vcnt[obj] + 12 * tc + (finest ? 0 : 8 * tc) + 32 * ((tc + 63) / 64) + 8 +
+           28 * (int64_t)m->L + 5 * 256 / 64;
+}
+
+void stage_plan(const pj_meshes *m, SideStage &s, size_t base)
+{
+    const int64_t n = (int64_t)s.objs.size(), L = m->L;
+    s.vdst.resize(n);
+    s.tdst.resize(n);
+    s.hdst.resize(n);
+    s.bdst.resize(n);
+    s.tcopy.assign(n, 0);
+    std::unordered_map<int64_t, std::pair<int32_t, int64_t>> rows;  // source row -> (count, staged row)
+    s.V = s.T = s.H = s.B = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        const int o = s.objs[k];
+        const int64_t key = (int64_t)o * L + s.lod;
+        const int64_t tb = m->h_tbeg[key];
+        const int32_t tc = m->h_tcnt[key];
+        s.vdst[k] = s.V;
+        s.V += m->h_vcnt[o];
+        auto it = rows.find(tb);
+        if (it != rows.end() && it->second.first == tc) {
+            s.tdst[k] = it->second.second;
+        } else {
+            s.tdst[k] = s.T;
+            s.tcopy[k] = 1;
+            rows[tb] = {tc, s.T};
+            s.T += tc;
+        }
+        s.hdst[k] = s.finest ? -1 : s.H;
+        if (!s.finest) s.H += tc;
+        s.bdst[k] = s.B;
+        s.B += (tc + 63) / 64;
+    }
+    size_t off = base;
+    auto put = [&](size_t &o, size_t bytes) {
+        o = off;
+        off = align256(off + std::max<size_t>(bytes, 1));
+    };
+    put(s.o_verts, 12 * s.V);
+    put(s.o_tris, 12 * s.T);
+    put(s.o_vbeg, 8 * n);
+    put(s.o_tbeg, 8 * n * L);
+    put(s.o_tcnt, 4 * n * L);
+    put(s.o_hpbeg, 8 * n * L);
+    put(s.o_hdph, 8 * s.H);
+    put(s.o_bkbeg, 8 * (n * L + 1));
+    put(s.o_blk, 32 * s.B);
+    s.end = off;
+}
+
+template <class F>
+void parallel_for(int64_t n, int nthreads, F f)
+{
+    if (n <= 0) return;
+    nthreads = (int)std::max<int64_t>(1, std::min<int64_t>(nthreads, n / 16));
+    if (nthreads <= 1) {
+        for (int64_t i = 0; i < n; ++i) f(i);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int t = 0; t < nthreads; ++t)
+        th.emplace_back([=, &f] {
+            for (int64_t i = t; i < n; i += nthreads) f(i);
+        });
+    for (auto &x : th) x.join();
+}
+
+void stage_fill(const pj_meshes *m, const SideStage &s, char *base, int nthreads)
+{
+    const int64_t n = (int64_t)s.objs.size(), L = m->L;
+    float *verts = reinterpret_cast<float *>(base + s.o_verts);
+    int32_t *tris = reinterpret_cast<int32_t *>(base + s.o_tris);
+    int64_t *vbeg = reinterpret_cast<int64_t *>(base + s.o_vbeg);
+    int64_t *tbeg = reinterpret_cast<int64_t *>(base + s.o_tbeg);
+    int32_t *tcnt = reinterpret_cast<int32_t *>(base + s.o_tcnt);
+    int64_t *hpbeg = reinterpret_cast<int64_t *>(base + s.o_hpbeg);
+    float2 *hdph = reinterpret_cast<float2 *>(base + s.o_hdph);
+    int64_t *bkbeg = reinterpret_cast<int64_t *>(base + s.o_bkbeg);
+    float4 *blk = reinterpret_cast<float4 *>(base + s.o_blk);
+    for (int64_t k = 0; k < n; ++k) {
+        vbeg[k] = s.vdst[k];
+        for (int64_t l = 0; l < L; ++l) {
+            const bool here = l == s.lod;
+            tbeg[k * L + l] = here ? s.tdst[k] : 0;
+            tcnt[k * L + l] = here ? m->h_tcnt[(int64_t)s.objs[k] * L + l] : 0;
+            hpbeg[k * L + l] = here ? s.hdst[k] : -1;
+            bkbeg[k * L + l] = here ? s.bdst[k] : 0;
+        }
+    }
+    bkbeg[n * L] = s.B;
+    parallel_for(n, nthreads, [&](int64_t k) {
+        const int o = s.objs[k];
+        const int64_t key = (int64_t)o * L + s.lod;
+        const int32_t tc = m->h_tcnt[key];
+        std::memcpy(verts + 3 * s.vdst[k], m->h_verts.data() + 3 * m->h_vbeg[o], 12 * (size_t)m->h_vcnt[o]);
+        if (s.tcopy[k]) std::memcpy(tris + 3 * s.tdst[k], m->h_tris.data() + 3 * m->h_tbeg[key], 12 * (size_t)tc);
+        if (!s.finest && tc) std::memcpy(hdph + s.hdst[k], m->h_hdph.data() + m->h_hpbeg[key], 8 * (size_t)tc);
+        const int64_t nb = (tc + 63) / 64;
+        if (nb) std::memcpy(blk + 2 * s.bdst[k], m->h_blk.data() + 2 * m->h_bkbeg[key], 32 * (size_t)nb);
+    });
+}
+
+MeshDev stage_view(const pj_meshes *m, const SideStage &s, char *dbase)
+{
+    return MeshDev{reinterpret_cast<const float *>(dbase + s.o_verts),
+                   reinterpret_cast<const int32_t *>(dbase + s.o_tris),
+                   reinterpret_cast<const int64_t *>(dbase + s.o_vbeg),
+                   reinterpret_cast<const int64_t *>(dbase + s.o_tbeg),
+                   reinterpret_cast<const int32_t *>(dbase + s.o_tcnt),
+                   reinterpret_cast<const int64_t *>(dbase + s.o_hpbeg),
+                   reinterpret_cast<const float2 *>(dbase + s.o_hdph),
+                   reinterpret_cast<const int64_t *>(dbase + s.o_bkbeg),
+                   reinterpret_cast<const float4 *>(dbase + s.o_blk),
+                   (int32_t)s.objs.size(),
+                   m->L};
+}
+
+int prep_threads(pj_context *ctx)
+{
+    int t = ctx->cfg.host_threads > 0 ? ctx->cfg.host_threads : (int)std::thread::hardware_concurrency();
+    return std::max(1, std::min(t, 16));
+}
+
+// Items of a plan split into groups whose staged objects fit `budget`; each
+// group is staged (synchronously, buffer set 0) and handed to fn with a
+// sub-plan whose object ids are local to the staged views, and the plan
+// index of each of its items.  Resident sets: one call with the full plan.
+template <class F>
+pj_status for_staged(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TilePlan &pl, F fn)
+{
+    const int ni = (int)pl.items.size();
+    if (!R->host && !S->host) {
+        std::vector<int> orig(ni);
+        std::iota(orig.begin(), orig.end(), 0);
+        return fn(pl, R->dev(), S->dev(), orig);
+    }
+    if (ni == 0) return PJ_OK;
+    hipStream_t st = ctx->stream;
+    HIPTRY(ctx, hipStreamSynchronize(st));
+    int64_t budget = int64_t(1) << 30;
+    if (ctx->cfg.mem_cap_bytes > 0) {
+        ctx->sb_stage[0].release();
+        budget = (ctx->cfg.mem_cap_bytes - ctx->dev_bytes) / 2;
+    }
+    const int lod = pl.items[0].lod;
+    const bool finest = pl.items[0].flags & IT_FINEST;
+    // tiles of each item (an item's tiles are contiguous in a plan)
+    std::vector<int64_t> tfirst(ni + 1, 0);
+    for (const Tile &t : pl.tiles) tfirst[t.item + 1]++;
+    for (int i = 0; i < ni; ++i) tfirst[i + 1] += tfirst[i];
+    std::vector<int32_t> stampR(R->host ? R->n : 0, -1), stampS(S->host ? S->n : 0, -1);
+    std::vector<int32_t> locR(stampR.size()), locS(stampS.size());
+    int group = 0;
+    for (int i0 = 0; i0 < ni; ++group) {
+        SideStage sR, sS;
+        sR.lod = sS.lod = lod;
+        sR.finest = sS.finest = finest;
+        int64_t bytes = 2 * kStageFixed;
+        TilePlan sp;
+        sp.tile_s = pl.tile_s;
+        std::vector<int> orig;
+        int i = i0;
+        for (; i < ni; ++i) {
+            Item it = pl.items[i];
+            const bool sw = it.flags & IT_SWAP;
+            const int ro = sw ? it.b_obj : it.a_obj, so = sw ? it.a_obj : it.b_obj;
+            int64_t need = 0;
+            if (R->host && stampR[ro] != group) need += stage_obj_bytes(R, ro, lod, finest);
+            if (S->host && stampS[so] != group) need += stage_obj_bytes(S, so, lod, finest);
+            if (i > i0 && bytes + need > budget) break;
+            if (bytes + need > budget)
+                return fail(ctx, PJ_ERR_OUT_OF_MEMORY, "an object pair does not fit the staging budget of the cap");
+            bytes += need;
+            int lr = ro, ls = so;
+            if (R->host) {
+                if (stampR[ro] != group) {
+                    stampR[ro] = group;
+                    locR[ro] = (int32_t)sR.objs.size();
+                    sR.objs.push_back(ro);
+                }
+                lr = locR[ro];
+            }
+            if (S->host) {
+                if (stampS[so] != group) {
+                    stampS[so] = group;
+                    locS[so] = (int32_t)sS.objs.size();
+                    sS.objs.push_back(so);
+                }
+                ls = locS[so];
+            }
+            it.a_obj = sw ? ls : lr;
+            it.b_obj = sw ? lr : ls;
+            const int local = (int)sp.items.size();
+            sp.items.push_back(it);
+            orig.push_back(i);
+            for (int64_t t = tfirst[i]; t < tfirst[i + 1]; ++t) {
+                Tile x = pl.tiles[t];
+                x.item = local;
+                sp.tiles.push_back(x);
+            }
+            sp.pairs += (int64_t)R->count(ro, lod) * S->count(so, lod);
+        }
+        stage_plan(R, sR, 0);
+        stage_plan(S, sS, R->host ? sR.end : 0);
+        const size_t total = std::max(R->host ? sR.end : 0, S->host ? sS.end : 0);
+        PJTRY(ensure(ctx, ctx->sb_stage[0], total));
+        PJTRY(ensure_pinned(ctx, ctx->pin_stage[0], total));
+        char *hb = (char *)ctx->pin_stage[0].p;
+        if (R->host) stage_fill(R, sR, hb, prep_threads(ctx));
+        if (S->host) stage_fill(S, sS, hb, prep_threads(ctx));
+        HIPTRY(ctx, hipMemcpyAsync(ctx->sb_stage[0].p, hb, total, hipMemcpyHostToDevice, st));
+        ctx->stats.staged_bytes += (int64_t)total;
+        char *db = (char *)ctx->sb_stage[0].p;
+        const MeshDev Rv = R->host ? stage_view(R, sR, db) : R->dev();
+        const MeshDev Sv = S->host ? stage_view(S, sS, db) : S->dev();
+        PJTRY(fn(sp, Rv, Sv, orig));
+        HIPTRY(ctx, hipStreamSynchronize(st));
+        i0 = i;
     }
     return PJ_OK;
 }
@@ -874,12 +1288,15 @@ pj_status launch_round(pj_context *ctx, const RefineArgs &a, int32_t *ctr, int n
     return PJ_OK;
 }
 
-// FP32 bulk pass over a plan, streamed in chunks (Algorithm 5 of the paper
-// on HIP streams): the host prepares chunk c+1 into pinned staging while
-// chunk c uploads on one stream, computes on the join stream and its
-// per-item results come back on a third stream; two buffer sets alternate
-// and events order their reuse.  A chunk holds at most `max_tiles` tiles;
-// an item whose tiles span chunks appears in each and is merged on the host.
+// FP32 bulk pass over a plan, streamed in chunks (the refinement pipeline of
+// Section 3.3, Algorithm 5, on HIP streams).  A prep thread gathers chunk
+// c+1 (items, tiles and, for host-resident sets, the chunk's facet data)
+// into pinned staging while chunk c uploads on a copy stream, computes on the
+// join stream and returns its per-item results on a third stream; two or
+// three buffer sets rotate, and a set is refilled only after its previous
+// chunk's results were merged.  A chunk ends at `max_tiles` tiles or when its
+// staged objects fill the staging budget; an item whose tiles span chunks
+// appears in each and its minima are merged on the host.
 pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TilePlan &pl, float tau, bool early,
                   std::vector<ItemOut> &out, int wpc_override)
 {
@@ -890,74 +1307,116 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
     out.assign(ni, ItemOut{0x7f800000u, 0x7f800000u, 0, 0});
     if (ni == 0 || nt == 0) return PJ_OK;
     PJTRY(ensure_streams(ctx));
-    // chunk capacity from the memory cap: two buffer sets of (items + tiles + outputs)
+    const int nsets = ctx->cfg.stage_sets == 3 ? 3 : 2;
+    const bool hostR = R->host, hostS = S->host, staged = hostR || hostS;
+    const int lod = pl.items[0].lod;
+    const bool finest = pl.items[0].flags & IT_FINEST;
+    const int64_t per_tile = sizeof(Tile) + sizeof(Item) + sizeof(ItemOut);  // worst case: one item per tile
     int64_t max_tiles = ctx->cfg.chunk_tiles > 0 ? ctx->cfg.chunk_tiles : int64_t(1) << 22;
+    int64_t stage_budget = int64_t(1) << 30;
     if (ctx->cfg.mem_cap_bytes > 0) {
         // size the chunks for what the cap leaves once the chunk buffers are
         // given back (the join stream is idle between rounds)
         HIPTRY(ctx, hipStreamSynchronize(st));
-        for (int b = 0; b < 2; ++b)
-            for (DevBuf *x : {&ctx->sb_items[b], &ctx->sb_tiles[b], &ctx->sb_out[b], &ctx->sb_ctr[b]}) x->release();
-        const int64_t avail = ctx->cfg.mem_cap_bytes - ctx->dev_bytes - 2 * (256 * 4 + 64);
-        const int64_t per_tile = sizeof(Tile) + sizeof(Item) + sizeof(ItemOut);  // worst case: one item per tile
-        max_tiles = std::min<int64_t>(max_tiles, avail / (2 * per_tile) - 1);
-        if (max_tiles < 1) return fail(ctx, PJ_ERR_OUT_OF_MEMORY, "the memory cap cannot hold one refinement tile");
+        for (int b = 0; b < kMaxSets; ++b)
+            for (DevBuf *x : {&ctx->sb_items[b], &ctx->sb_tiles[b], &ctx->sb_out[b], &ctx->sb_ctr[b], &ctx->sb_stage[b]})
+                x->release();
+        const int64_t per_set = (ctx->cfg.mem_cap_bytes - ctx->dev_bytes) / nsets - (5 * 256 + 64);
+        int64_t tile_part = per_set;
+        if (staged) {
+            stage_budget = per_set * 3 / 4;
+            tile_part = per_set - stage_budget;
+        }
+        max_tiles = std::min<int64_t>(max_tiles, tile_part / per_tile - 1);
+        if (max_tiles < 1 || (staged && stage_budget < 4 * kStageFixed))
+            return fail(ctx, PJ_ERR_OUT_OF_MEMORY, "the memory cap cannot hold one refinement chunk");
     }
     struct Chunk {
-        int64_t t0, t1;
-        std::vector<int> items;  // plan item indices, in chunk-local order
+        int64_t t0 = 0, t1 = 0;
+        std::vector<int> items;           // plan item indices, in chunk-local order
+        std::vector<int32_t> locR, locS;  // per chunk item: object ids in the chunk's views
+        SideStage sR, sS;
+        size_t stage_bytes = 0;
     };
     std::vector<Chunk> chunks;
     std::vector<int32_t> tile_local(nt);  // chunk-local item index of each tile
     {
-        Chunk c{0, 0, {}};
         std::vector<int> local(ni, -1);
+        std::vector<int32_t> stampR(hostR ? R->n : 0, -1), stampS(hostS ? S->n : 0, -1);
+        std::vector<int32_t> locR_of(stampR.size()), locS_of(stampS.size());
+        Chunk c;
+        int cid = 0;
+        int64_t sbytes = 2 * kStageFixed;
+        auto close = [&](int64_t t) {
+            c.t1 = t;
+            for (int it : c.items) local[it] = -1;
+            chunks.push_back(std::move(c));
+            c = Chunk();
+            c.t0 = t;
+            ++cid;
+            sbytes = 2 * kStageFixed;
+        };
         for (int64_t t = 0; t < nt; ++t) {
-            if (t - c.t0 >= max_tiles) {
-                c.t1 = t;
-                for (int it : c.items) local[it] = -1;
-                chunks.push_back(std::move(c));
-                c = Chunk{t, t, {}};
-            }
+            if (t - c.t0 >= max_tiles) close(t);
             const int it = pl.tiles[t].item;
             if (local[it] < 0) {
+                const Item &I = pl.items[it];
+                const bool sw = I.flags & IT_SWAP;
+                const int ro = sw ? I.b_obj : I.a_obj, so = sw ? I.a_obj : I.b_obj;
+                auto need_of = [&]() {
+                    int64_t need = 0;
+                    if (hostR && stampR[ro] != cid) need += stage_obj_bytes(R, ro, lod, finest);
+                    if (hostS && stampS[so] != cid) need += stage_obj_bytes(S, so, lod, finest);
+                    return need;
+                };
+                int64_t need = need_of();
+                if (need && sbytes + need > stage_budget && t > c.t0) {
+                    close(t);
+                    need = need_of();
+                }
+                if (sbytes + need > stage_budget)
+                    return fail(ctx, PJ_ERR_OUT_OF_MEMORY, "an object pair does not fit the staging budget of the cap");
+                sbytes += need;
+                int lr = ro, ls = so;
+                if (hostR) {
+                    if (stampR[ro] != cid) {
+                        stampR[ro] = cid;
+                        locR_of[ro] = (int32_t)c.sR.objs.size();
+                        c.sR.objs.push_back(ro);
+                    }
+                    lr = locR_of[ro];
+                }
+                if (hostS) {
+                    if (stampS[so] != cid) {
+                        stampS[so] = cid;
+                        locS_of[so] = (int32_t)c.sS.objs.size();
+                        c.sS.objs.push_back(so);
+                    }
+                    ls = locS_of[so];
+                }
                 local[it] = (int)c.items.size();
                 c.items.push_back(it);
+                c.locR.push_back(lr);
+                c.locS.push_back(ls);
             }
             tile_local[t] = local[it];
         }
-        c.t1 = nt;
-        chunks.push_back(std::move(c));
+        close(nt);
     }
-    int32_t *host_ctr_last = nullptr;
-    auto merge = [&](int ci) -> pj_status {
-        const int b = ci & 1;
-        const Chunk &c = chunks[ci];
-        const ItemOut *o = (const ItemOut *)ctx->pin_out[b].p;
-        for (size_t q = 0; q < c.items.size(); ++q) {
-            ItemOut &d = out[c.items[q]];
-            d.lb = std::min(d.lb, o[q].lb);
-            d.ub = std::min(d.ub, o[q].ub);
-            d.hit |= o[q].hit;
-        }
-        const int32_t *hc = (const int32_t *)ctx->pin_ctr[b].p;
-        unsigned long long pairs, culled;
-        std::memcpy(&pairs, hc + 2, 8);
-        std::memcpy(&culled, hc + 4, 8);
-        ctx->stats.facet_pairs += (int64_t)pairs;
-        ctx->stats.tiles_culled += (int64_t)culled;
-        float ms = 0;
-        HIPTRY(ctx, hipEventElapsedTime(&ms, ctx->ev_k0[b], ctx->ev_k1[b]));
-        ctx->stats.refine_kernel_ms += ms;
-        ctx->stats.refine_launches += 1;
-        host_ctr_last = (int32_t *)hc;
-        return PJ_OK;
-    };
-    for (int ci = 0; ci < (int)chunks.size(); ++ci) {
-        const int b = ci & 1;
-        const Chunk &c = chunks[ci];
-        const int cni = (int)c.items.size();
-        const int cnt = (int)(c.t1 - c.t0);
+    const int nch = (int)chunks.size();
+    for (Chunk &c : chunks) {
+        c.sR.lod = c.sS.lod = lod;
+        c.sR.finest = c.sS.finest = finest;
+        if (hostR) stage_plan(R, c.sR, 0);
+        if (hostS) stage_plan(S, c.sS, hostR ? c.sR.end : 0);
+        c.stage_bytes = std::max(hostR ? c.sR.end : 0, hostS ? c.sS.end : 0);
+    }
+    const int nthreads = prep_threads(ctx);
+    // buffers of chunk j's set (main thread: HIP allocation calls stay here)
+    auto alloc = [&](int j) -> pj_status {
+        const int b = j % nsets;
+        const Chunk &c = chunks[j];
+        const size_t cni = c.items.size(), cnt = (size_t)(c.t1 - c.t0);
         PJTRY(ensure(ctx, ctx->sb_items[b], cni * sizeof(Item)));
         PJTRY(ensure(ctx, ctx->sb_tiles[b], cnt * sizeof(Tile)));
         PJTRY(ensure(ctx, ctx->sb_out[b], cni * sizeof(ItemOut)));
@@ -966,11 +1425,26 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
         PJTRY(ensure_pinned(ctx, ctx->pin_tiles[b], cnt * sizeof(Tile)));
         PJTRY(ensure_pinned(ctx, ctx->pin_out[b], cni * sizeof(ItemOut)));
         PJTRY(ensure_pinned(ctx, ctx->pin_ctr[b], 64));
-        // host preparation of this chunk (the buffers of set b are free: the
-        // results of chunk ci - 2 were merged after its download event)
+        if (staged) {
+            PJTRY(ensure(ctx, ctx->sb_stage[b], c.stage_bytes));
+            PJTRY(ensure_pinned(ctx, ctx->pin_stage[b], c.stage_bytes));
+        }
+        return PJ_OK;
+    };
+    // host preparation of chunk j into the pinned buffers of its set (no HIP calls)
+    auto prep = [&, nthreads](int j) {
+        const int b = j % nsets;
+        const Chunk &c = chunks[j];
+        const int cni = (int)c.items.size();
         Item *hi = (Item *)ctx->pin_items[b].p;
         Tile *ht = (Tile *)ctx->pin_tiles[b].p;
-        for (int q = 0; q < cni; ++q) hi[q] = pl.items[c.items[q]];
+        for (int q = 0; q < cni; ++q) {
+            Item x = pl.items[c.items[q]];
+            const bool sw = x.flags & IT_SWAP;
+            x.a_obj = sw ? c.locS[q] : c.locR[q];
+            x.b_obj = sw ? c.locR[q] : c.locS[q];
+            hi[q] = x;
+        }
         for (int64_t t = c.t0; t < c.t1; ++t) {
             Tile x = pl.tiles[t];
             x.item = tile_local[t];
@@ -978,17 +1452,33 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
         }
         int32_t *hc = (int32_t *)ctx->pin_ctr[b].p;
         std::memset(hc, 0, 64);
-        hc[1] = cnt;
+        hc[1] = (int32_t)(c.t1 - c.t0);
         hc[6] = cni;
+        char *hs = (char *)ctx->pin_stage[b].p;
+        if (hostR) stage_fill(R, c.sR, hs, nthreads);
+        if (hostS) stage_fill(S, c.sS, hs, nthreads);
+    };
+    auto enqueue = [&](int j) -> pj_status {
+        const int b = j % nsets;
+        const Chunk &c = chunks[j];
+        const int cni = (int)c.items.size(), cnt = (int)(c.t1 - c.t0);
         int32_t *dctr = ptr<int32_t>(ctx->sb_ctr[b]);
-        HIPTRY(ctx, hipMemcpyAsync(ctx->sb_items[b].p, hi, cni * sizeof(Item), hipMemcpyHostToDevice, ctx->up_stream));
-        HIPTRY(ctx, hipMemcpyAsync(ctx->sb_tiles[b].p, ht, cnt * sizeof(Tile), hipMemcpyHostToDevice, ctx->up_stream));
-        HIPTRY(ctx, hipMemcpyAsync(dctr, hc, 64, hipMemcpyHostToDevice, ctx->up_stream));
+        if (staged) {
+            HIPTRY(ctx, hipMemcpyAsync(ctx->sb_stage[b].p, ctx->pin_stage[b].p, c.stage_bytes, hipMemcpyHostToDevice,
+                                       ctx->up_stream));
+            ctx->stats.staged_bytes += (int64_t)c.stage_bytes;
+        }
+        HIPTRY(ctx, hipMemcpyAsync(ctx->sb_items[b].p, ctx->pin_items[b].p, cni * sizeof(Item), hipMemcpyHostToDevice,
+                                   ctx->up_stream));
+        HIPTRY(ctx, hipMemcpyAsync(ctx->sb_tiles[b].p, ctx->pin_tiles[b].p, cnt * sizeof(Tile), hipMemcpyHostToDevice,
+                                   ctx->up_stream));
+        HIPTRY(ctx, hipMemcpyAsync(dctr, ctx->pin_ctr[b].p, 64, hipMemcpyHostToDevice, ctx->up_stream));
         HIPTRY(ctx, hipEventRecord(ctx->ev_h2d[b], ctx->up_stream));
         RefineArgs a;
         std::memset(&a, 0, sizeof(a));
-        a.R = R->dev();
-        a.S = S->dev();
+        char *ds = (char *)ctx->sb_stage[b].p;
+        a.R = hostR ? stage_view(R, c.sR, ds) : R->dev();
+        a.S = hostS ? stage_view(S, c.sS, ds) : S->dev();
         a.items = ptr<Item>(ctx->sb_items[b]);
         a.tiles = ptr<Tile>(ctx->sb_tiles[b]);
         a.ntiles = dctr + 1;
@@ -1007,28 +1497,71 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
         HIPTRY(ctx, hipStreamWaitEvent(ctx->down_stream, ctx->ev_comp[b], 0));
         HIPTRY(ctx, hipMemcpyAsync(ctx->pin_out[b].p, a.out, cni * sizeof(ItemOut), hipMemcpyDeviceToHost,
                                    ctx->down_stream));
-        HIPTRY(ctx, hipMemcpyAsync(hc, dctr, 64, hipMemcpyDeviceToHost, ctx->down_stream));
+        HIPTRY(ctx, hipMemcpyAsync(ctx->pin_ctr[b].p, dctr, 64, hipMemcpyDeviceToHost, ctx->down_stream));
         HIPTRY(ctx, hipEventRecord(ctx->ev_d2h[b], ctx->down_stream));
         ctx->stats.chunks++;
-        if (ci >= 1) {
-            HIPTRY(ctx, hipEventSynchronize(ctx->ev_d2h[(ci - 1) & 1]));
-            PJTRY(merge(ci - 1));
+        return PJ_OK;
+    };
+    std::vector<char> merged(nch, 0);
+    auto merge = [&](int j) -> pj_status {
+        if (merged[j]) return PJ_OK;
+        const int b = j % nsets;
+        HIPTRY(ctx, hipEventSynchronize(ctx->ev_d2h[b]));
+        const Chunk &c = chunks[j];
+        const ItemOut *o = (const ItemOut *)ctx->pin_out[b].p;
+        for (size_t q = 0; q < c.items.size(); ++q) {
+            ItemOut &d = out[c.items[q]];
+            d.lb = std::min(d.lb, o[q].lb);
+            d.ub = std::min(d.ub, o[q].ub);
+            d.hit |= o[q].hit;
         }
+        const int32_t *hc = (const int32_t *)ctx->pin_ctr[b].p;
+        unsigned long long pairs, culled;
+        std::memcpy(&pairs, hc + 2, 8);
+        std::memcpy(&culled, hc + 4, 8);
+        ctx->stats.facet_pairs += (int64_t)pairs;
+        ctx->stats.tiles_culled += (int64_t)culled;
+        float ms = 0;
+        HIPTRY(ctx, hipEventElapsedTime(&ms, ctx->ev_k0[b], ctx->ev_k1[b]));
+        ctx->stats.refine_kernel_ms += ms;
+        ctx->stats.refine_launches += 1;
+        merged[j] = 1;
+        return PJ_OK;
+    };
+    PJTRY(alloc(0));
+    prep(0);
+    std::thread worker;
+    pj_status st_all = PJ_OK;
+    for (int ci = 0; ci < nch && st_all == PJ_OK; ++ci) {
+        if (worker.joinable()) worker.join();  // chunk ci is prepared
+        st_all = enqueue(ci);
+        if (st_all != PJ_OK) break;
+        const int j = ci + 1;
+        if (j < nch) {
+            // the set of chunk j is free once chunk j - nsets is merged
+            if (j - nsets >= 0) st_all = merge(j - nsets);
+            if (st_all == PJ_OK) st_all = alloc(j);
+            if (st_all != PJ_OK) break;
+            worker = std::thread(prep, j);
+        }
+        if (ci >= 1) st_all = merge(ci - 1);
     }
-    const int last = (int)chunks.size() - 1;
-    HIPTRY(ctx, hipEventSynchronize(ctx->ev_d2h[last & 1]));
-    PJTRY(merge(last));
+    if (worker.joinable()) worker.join();
+    if (st_all != PJ_OK) {
+        (void)hipStreamSynchronize(ctx->down_stream);
+        return st_all;
+    }
+    for (int j = 0; j < nch; ++j) PJTRY(merge(j));
     // the join stream must not run ahead of the downloads
-    HIPTRY(ctx, hipStreamWaitEvent(st, ctx->ev_d2h[last & 1], 0));
+    HIPTRY(ctx, hipStreamWaitEvent(st, ctx->ev_d2h[(nch - 1) % nsets], 0));
     ctx->stats.tiles += nt;
     ctx->stats.tile_s_used = pl.tile_s;
     ctx->stats.waves_per_cu_used = wpc;
-    (void)host_ctr_last;
     return PJ_OK;
 }
 
-pj_status run_f64(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TilePlan &pl, bool plain,
-                  std::vector<ItemOut64> &out)
+pj_status run_f64_view(pj_context *ctx, const MeshDev &Rv, const MeshDev &Sv, TilePlan &pl, bool plain,
+                       std::vector<ItemOut64> &out)
 {
     hipStream_t st = ctx->stream;
     const int ni = (int)pl.items.size(), nt = (int)pl.tiles.size();
@@ -1038,8 +1571,8 @@ pj_status run_f64(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
     PJTRY(ensure(ctx, ctx->b_out64, ni * sizeof(ItemOut64)));
     HIPTRY(ctx, hipMemcpyAsync(ctx->b_items.p, pl.items.data(), ni * sizeof(Item), hipMemcpyHostToDevice, st));
     Refine64Args a;
-    a.R = R->dev();
-    a.S = S->dev();
+    a.R = Rv;
+    a.S = Sv;
     a.items = ptr<Item>(ctx->b_items);
     a.out = ptr<ItemOut64>(ctx->b_out64);
     a.tiles = nullptr;
@@ -1061,6 +1594,21 @@ pj_status run_f64(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
     ctx->stats.band_kernel_ms += ms;
     ctx->stats.facet_pairs_fp64 += pl.pairs;
     return PJ_OK;
+}
+
+// FP64 pass over a plan (plain schedule, FP64 precision and the overflow
+// path of the band recheck); host-resident sets are staged in item groups.
+pj_status run_f64(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TilePlan &pl, bool plain,
+                  std::vector<ItemOut64> &out)
+{
+    out.assign(pl.items.size(), ItemOut64{0x7ff0000000000000ull, 0x7ff0000000000000ull, 0, 0});
+    return for_staged(ctx, R, S, pl,
+                      [&](TilePlan &sp, const MeshDev &Rv, const MeshDev &Sv, const std::vector<int> &orig) {
+                          std::vector<ItemOut64> o;
+                          PJTRY(run_f64_view(ctx, Rv, Sv, sp, plain, o));
+                          for (size_t k = 0; k < o.size(); ++k) out[orig[k]] = o[k];
+                          return PJ_OK;
+                      });
 }
 
 // Exact FP64 finest-LoD distance of the candidates `which`: one FP32 pass
@@ -1086,13 +1634,11 @@ float bits_to_float(uint32_t b)
 
 int pick_tile_s(pj_context *ctx);
 
-pj_status exact_finest(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, std::vector<Cand> &cand,
-                       std::vector<PairState> &ps, const std::vector<int> &which)
+// collect + FP64 pass of one (staged) plan; overflowed candidates go to redo
+pj_status exact_finest_view(pj_context *ctx, const MeshDev &Rv, const MeshDev &Sv, TilePlan &pl,
+                            std::vector<PairState> &ps, std::vector<int> &redo)
 {
-    if (which.empty()) return PJ_OK;
     hipStream_t st = ctx->stream;
-    TilePlan pl;
-    plan_tiles(R, S, which, cand, ps, R->L - 1, 1, 64, pick_tile_s(ctx), true, pl);
     const int ni = (int)pl.items.size(), nt = (int)pl.tiles.size();
     if (ni == 0) return PJ_OK;
     int64_t cap = std::max<int64_t>(1 << 20, 256 * (int64_t)ni);
@@ -1126,8 +1672,8 @@ pj_status exact_finest(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
     HIPTRY(ctx, launch_init_out64(ptr<ItemOut64>(ctx->b_out64), ni, st));
     RefineArgs a;
     std::memset(&a, 0, sizeof(a));
-    a.R = R->dev();
-    a.S = S->dev();
+    a.R = Rv;
+    a.S = Sv;
     a.items = ptr<Item>(ctx->b_items);
     a.tiles = ptr<Tile>(ctx->b_tiles);
     a.ntiles = ctr + 1;
@@ -1155,7 +1701,7 @@ pj_status exact_finest(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
     ctx->stats.facet_pairs += (int64_t)pairs;
     const int64_t ncoll = std::min<int64_t>(host_ctr[0], cap);
     HIPTRY(ctx, hipEventRecord(ctx->ev0, st));
-    HIPTRY(ctx, launch_pairs_f64(R->dev(), S->dev(), a.items, a.collected, ncoll, ptr<ItemOut64>(ctx->b_out64), st));
+    HIPTRY(ctx, launch_pairs_f64(Rv, Sv, a.items, a.collected, ncoll, ptr<ItemOut64>(ctx->b_out64), st));
     HIPTRY(ctx, hipEventRecord(ctx->ev1, st));
     std::vector<ItemOut64> out(ni);
     std::vector<int32_t> ovf(ni);
@@ -1165,7 +1711,6 @@ pj_status exact_finest(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
     HIPTRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
     ctx->stats.band_kernel_ms += ms;
     ctx->stats.facet_pairs_fp64 += ncoll;
-    std::vector<int> redo;
     for (int k = 0; k < ni; ++k) {
         PairState &p = ps[pl.items[k].cand];
         if (ovf[k]) {
@@ -1175,6 +1720,20 @@ pj_status exact_finest(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
         p.hit64 = out[k].hit;
         p.d64 = p.hit64 ? 0.0 : bits_to_double(out[k].lb);
     }
+    return PJ_OK;
+}
+
+pj_status exact_finest(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, std::vector<Cand> &cand,
+                       std::vector<PairState> &ps, const std::vector<int> &which)
+{
+    if (which.empty()) return PJ_OK;
+    TilePlan pl;
+    plan_tiles(R, S, which, cand, ps, R->L - 1, 1, 64, pick_tile_s(ctx), true, pl);
+    std::vector<int> redo;
+    PJTRY(for_staged(ctx, R, S, pl,
+                     [&](TilePlan &sp, const MeshDev &Rv, const MeshDev &Sv, const std::vector<int> &) {
+                         return exact_finest_view(ctx, Rv, Sv, sp, ps, redo);
+                     }));
     if (!redo.empty()) {
         TilePlan p2;
         plan_tiles(R, S, redo, cand, ps, R->L - 1, 1, 64, pick_tile_s(ctx), true, p2);

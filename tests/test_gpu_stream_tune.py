@@ -126,3 +126,90 @@ def test_autotune_picks_cached_shape(pj, mid, tmp_path):
     s3 = t3.stats()
     assert (s3["tile_s_used"], s3["waves_per_cu_used"]) == (512, 8)
     assert os.path.getsize(path) > 0
+
+
+# ---------------------------------------------------------------------------
+# host-resident mesh sets: facet data gathered per chunk into pinned staging
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def dev_ref(pj, mid):
+    R, S = mid
+    c = pj.Context()
+    gR, gS = c.meshes(R), c.meshes(S)
+    return {tau: c.join_within(gR, gS, tau) for tau in (0.0, 5.0, 20.0)}
+
+
+def test_host_resident_ingest_matches_device(pj, mid):
+    R, S = mid
+    d = pj.Context()
+    h = pj.Context(host_resident=True, mem_cap_bytes=1 << 20)  # ingest in many object batches
+    for ms in (R, S):
+        gd, gh = d.meshes(ms), h.meshes(ms)
+        bd, bh = gd.boxes(), gh.boxes()
+        for a, b in zip(bd, bh):
+            assert np.array_equal(a, b)
+        for obj in (0, ms.n_objects // 2, ms.n_objects - 1):
+            for lod in range(ms.n_lods):
+                hd1, ph1 = gd.hdph(obj, lod)
+                hd2, ph2 = gh.hdph(obj, lod)
+                assert np.array_equal(hd1, hd2) and np.array_equal(ph1, ph2)
+
+
+@pytest.mark.parametrize("sets", [2, 3])
+@pytest.mark.parametrize("cap", [0, 6 << 20])
+def test_host_resident_join_matches_device(pj, mid, dev_ref, sets, cap):
+    R, S = mid
+    c = pj.Context(host_resident=True, stage_sets=sets, mem_cap_bytes=cap)
+    gR, gS = c.meshes(R), c.meshes(S)
+    for tau in (0.0, 5.0, 20.0):
+        got = c.join_within(gR, gS, tau)
+        st = c.stats()
+        ref = dev_ref[tau]
+        assert np.array_equal(got["r"], ref["r"]) and np.array_equal(got["s"], ref["s"]), tau
+        assert st["staged_bytes"] > 0
+        if cap:
+            assert st["chunks"] > st["rounds"] and st["peak_device_bytes"] <= cap
+
+
+def test_host_resident_join_vs_oracle(orc, pj):
+    R, S = mg.config_small(seed=4, n_r=60, n_s=60, box=10.0)
+    c = pj.Context(host_resident=True, want_dist=True)
+    got = c.join_within(c.meshes(R), c.meshes(S), 0.5)
+    ref = orc.join_within(orc.OSet(R), orc.OSet(S), 0.5)
+    assert np.array_equal(got["r"], ref["r"]) and np.array_equal(got["s"], ref["s"])
+    assert np.all(np.abs(got["dist"] - ref["d"]) <= np.maximum(1e-5 * ref["d"], 1e-12 * 10.0))
+
+
+@pytest.mark.parametrize("mode", ["fp64", "plain"])
+def test_host_resident_fp64_paths(pj, mid, dev_ref, mode):
+    R, S = mid
+    c = pj.Context(host_resident=True, precision="fp64", schedule="plain" if mode == "plain" else "batched",
+                   mem_cap_bytes=16 << 20)
+    got = c.join_within(c.meshes(R), c.meshes(S), 5.0)
+    assert np.array_equal(got["r"], dev_ref[5.0]["r"]) and np.array_equal(got["s"], dev_ref[5.0]["s"])
+
+
+def test_host_resident_knn(pj):
+    R, S = mg.config_knn(seed=3, n_r=40, n_s=40, n_clusters=2, box=200.0, sigma=12.0, f_median=2000)
+    d = pj.Context()
+    h = pj.Context(host_resident=True, mem_cap_bytes=8 << 20, stage_sets=3)
+    a = d.join_knn(d.meshes(R), d.meshes(S), 3)
+    b = h.join_knn(h.meshes(R), h.meshes(S), 3)
+    assert np.array_equal(a["s"], b["s"]) and np.array_equal(a["count"], b["count"])
+    assert np.array_equal(a["dist"], b["dist"])
+    assert h.stats()["staged_bytes"] > 0
+
+
+def test_host_resident_pair_bounds(pj, mid):
+    R, S = mid
+    d = pj.Context()
+    h = pj.Context(host_resident=True)
+    dR, dS, hR, hS = d.meshes(R), d.meshes(S), h.meshes(R), h.meshes(S)
+    rng = np.random.default_rng(5)
+    rr = rng.integers(0, R.n_objects, 64)
+    ss = rng.integers(0, S.n_objects, 64)
+    for lod in range(R.n_lods):
+        a = d.pair_bounds(dR, dS, rr, ss, lod)
+        b = h.pair_bounds(hR, hS, rr, ss, lod)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y), lod
