@@ -570,6 +570,8 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
     bool stop = false;
     for (int cb = tl.b0; cb < tl.b1 && !stop; cb += 64) {
         const int nb = min(64, tl.b1 - cb);
+        // cut values shared by the chunk test and the per-facet test
+        float ub_cut = kInf, lb_cut = kInf, col_cut = kInf;
         if (a.cull) {
             const float4 blo = SB.blk[2 * (cb >> 6)], bhi = SB.blk[2 * (cb >> 6) + 1];
             const float gap = block_gap(alo, ahi, blo, bhi) - it.eps;
@@ -580,10 +582,11 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
                 __hip_atomic_load(&o->ub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
             bool skip;
             if (COLLECT) {
-                skip = gap > fminf(it.thr, fminf(cur_ub, ubm) + 2.0f * it.eps);
+                col_cut = fminf(it.thr, fminf(cur_ub, ubm) + 2.0f * it.eps);
+                skip = gap > col_cut;
             } else {
-                const float ub_cut = within ? fminf(fminf(cur_ub, ubm), a.tau - it.eps) : fminf(cur_ub, ubm);
-                const float lb_cut = within ? fminf(fminf(cur_lb, lbm), a.tau + it.eps) : fminf(cur_lb, lbm);
+                ub_cut = within ? fminf(fminf(cur_ub, ubm), a.tau - it.eps) : fminf(cur_ub, ubm);
+                lb_cut = within ? fminf(fminf(cur_lb, lbm), a.tau + it.eps) : fminf(cur_lb, lbm);
                 skip = gap > ub_cut && fmaxf(gap - aph - bph, 0.0f) > lb_cut;
             }
             if (__builtin_amdgcn_readfirstlane((int)skip)) {
@@ -594,18 +597,40 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
         int f = cb + lane;
         if (f >= tl.b1) f = cb;
         const int32_t i0 = SB.tris[3 * f], i1 = SB.tris[3 * f + 1], i2 = SB.tris[3 * f + 2];
-        const V3 b0 = ld3f(SB.verts, i0) - org, b1 = ld3f(SB.verts, i1) - org, b2 = ld3f(SB.verts, i2) - org;
+        const V3 w0 = ld3f(SB.verts, i0), w1 = ld3f(SB.verts, i1), w2 = ld3f(SB.verts, i2);
         const float2 bh = SB.hdph ? SB.hdph[f] : make_float2(0.0f, 0.0f);
-        {
-            Rec rb = make_rec(b0, b1, b2, bh.x, bh.y);
+        // Facet culling: the same two-sided test with this facet's own box
+        // and ph against the A block; surviving facets are packed to the
+        // front of the LDS chunk (their index rides in the record's pad).
+        bool keep = lane < nb;
+        if (a.cull) {
+            const float4 flo = make_float4(fminf(fminf(w0.x, w1.x), w2.x), fminf(fminf(w0.y, w1.y), w2.y),
+                                           fminf(fminf(w0.z, w1.z), w2.z), 0.0f);
+            const float4 fhi = make_float4(fmaxf(fmaxf(w0.x, w1.x), w2.x), fmaxf(fmaxf(w0.y, w1.y), w2.y),
+                                           fmaxf(fmaxf(w0.z, w1.z), w2.z), 0.0f);
+            const float g = block_gap(alo, ahi, flo, fhi) - it.eps;
+            const bool cut = COLLECT ? g > col_cut : (g > ub_cut && fmaxf(g - aph - bh.y, 0.0f) > lb_cut);
+            keep = keep && !cut;
+        }
+        const unsigned long long kmask = __ballot(keep);
+        const int nk = __popcll(kmask);
+        if (nk == 0) {
+            ++culled;
+            continue;
+        }
+        if (keep) {
+            const int pos = __builtin_amdgcn_mbcnt_hi((unsigned)(kmask >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((unsigned)kmask, 0u));
+            Rec rb = make_rec(w0 - org, w1 - org, w2 - org, bh.x, bh.y);
+            rb.pad = __int_as_float(f);
             float tmp[44];
             __builtin_memcpy(tmp, &rb, sizeof(tmp));
 #pragma unroll
             for (int q = 0; q < 11; ++q)
-                sh[lane * 11 + q] = make_float4(tmp[4 * q], tmp[4 * q + 1], tmp[4 * q + 2], tmp[4 * q + 3]);
+                sh[pos * 11 + q] = make_float4(tmp[4 * q], tmp[4 * q + 1], tmp[4 * q + 2], tmp[4 * q + 3]);
         }
         __syncthreads();
-        for (int k = 0; k < nb; ++k) {
+        for (int k = 0; k < nk; ++k) {
             float tmp[44];
 #pragma unroll
             for (int q = 0; q < 11; ++q) {
@@ -629,13 +654,13 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
                     // the pair realising the minimum has dlo <= d + eps <= ubm + 2 eps
                     if (fa < SA.n && dlo <= fminf(it.thr, ubm + 2.0f * it.eps)) {
                         const int slot = atomicAdd(a.counter, 1);
-                        if (slot < a.collect_cap) a.collected[slot] = PairRef{tl.item, fa, cb + k, 0};
+                        if (slot < a.collect_cap) a.collected[slot] = PairRef{tl.item, fa, __float_as_int(rb.pad), 0};
                         else a.overflow[tl.item] = 1;
                     }
                 }
             }
         }
-        cols += nb;
+        cols += nk;
         __syncthreads();
         if (a.cull) {  // publish the running minima so that other tiles can cull against them
             const float wl = wmin_u(lbm), wu = wmin_u(ubm);
