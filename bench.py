@@ -91,34 +91,52 @@ def train_model(pj, mg, stream, workdir):
     return model, loss, os.path.getsize(log) // 72
 
 
-def one_step(pj, stream, R, S, **cfg):
+def one_step(pj, stream, R, S, taus, **cfg):
     import torch
     c = pj.Context(stream=stream.cuda_stream, **cfg)
     gR, gS = c.meshes(R), c.meshes(S)
     torch.cuda.synchronize()
     ts = time.time()
-    tot = run_step(c, gR, gS, TAUS)
+    tot = run_step(c, gR, gS, taus)
     torch.cuda.synchronize()
     tot["ms"] = (time.time() - ts) * 1e3
     return tot
 
 
-def cpu_baseline(R, S, seconds):
+def sample_candidates(oracle, O_R, O_S, gap, max_r=20000, seed=0):
+    """MBB candidate pairs (box gap <= gap) of up to max_r random R objects,
+    found by an x-sorted sweep over S with the oracle's boxes."""
+    import numpy as np
+    bR, _ = oracle.mbbs(O_R)
+    bS, _ = oracle.mbbs(O_S)
+    rng = np.random.default_rng(seed)
+    rs = np.sort(rng.permutation(len(bR))[:max_r])
+    order = np.argsort(bS[:, 0], kind="stable")
+    xs = bS[order, 0]
+    wmax = float(np.max(bS[:, 3] - bS[:, 0])) if len(bS) else 0.0
+    cr, cs = [], []
+    for r in rs:
+        lo = np.searchsorted(xs, bR[r, 0] - gap - wmax, "left")
+        hi = np.searchsorted(xs, bR[r, 3] + gap, "right")
+        js = order[lo:hi]
+        if len(js) == 0:
+            continue
+        md = oracle.mindist(bR[r:r + 1], bS[js])[0]
+        js = js[md <= gap]
+        cr.append(np.full(len(js), r))
+        cs.append(js)
+    if not cr:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64)
+    return np.concatenate(cr), np.concatenate(cs)
+
+
+def cpu_baseline(R, S, seconds, gap=5.0):
     """The oracle on a bounded sample of the workload's candidate pairs."""
     import numpy as np
     import oracle
     O_R, O_S = oracle.OSet(R), oracle.OSet(S)
-    bR, _ = oracle.mbbs(O_R)
-    bS, _ = oracle.mbbs(O_S)
     rng = np.random.default_rng(0)
-    cr, cs = [], []
-    for c0 in range(0, R.n_objects, 2000):
-        md = oracle.mindist(bR[c0:c0 + 2000], bS)
-        i, j = np.nonzero(md <= 5.0)
-        cr.append(i + c0)
-        cs.append(j)
-    cr = np.concatenate(cr)
-    cs = np.concatenate(cs)
+    cr, cs = sample_candidates(oracle, O_R, O_S, gap)
     order = rng.permutation(len(cr))
     threads = oracle.lib().oracle_num_threads()
     L = R.n_lods
@@ -132,9 +150,27 @@ def cpu_baseline(R, S, seconds):
         done += len(idx)
     el = time.time() - t0
     return dict(value=span / el, unit="facet-pair evals/s", cores=threads, kind="oracle",
-                sample=(f"finest-LoD distance of {done} random MBB candidate pairs (tau=5) of the same workload, "
+                sample=(f"finest-LoD distance of {done} random MBB candidate pairs (box gap <= {gap}) of the same "
+                        f"workload, "
                         f"{el:.1f} s; evals = sum n_r*n_s of the sampled pairs (the oracle covers them with exact "
                         f"box-gap skipping)"))
+
+
+# Workloads: the default is the multi-LoD join the metric is quoted on; the
+# other two are the learned-skip join (10x the objects, sparser) and the
+# large intersection join with host-resident meshes under a 32 GB device cap.
+WORKLOADS = {
+    "multilod": dict(builder="config_multilod", taus=TAUS, ctx={}, cpu_gap=5.0,
+                     desc="multilod within-tau join: {nr} blobs (80/320/1280/5120 triangles) x {ns} tubes "
+                          "(336..20496 triangles), 500^3 box, tau in {{0, 5, 20}} per step"),
+    "learned": dict(builder="config_learned", taus=(10.0,), ctx={}, cpu_gap=10.0,
+                    desc="learned-skip within-tau join: {nr} blobs (80..5120 triangles) x {ns} tubes "
+                         "(336..20496 triangles), 5000^3 box, tau = 10"),
+    "large": dict(builder="config_large", taus=(0.0,), ctx=dict(host_resident=True, mem_cap_bytes=32 << 30),
+                  cpu_gap=5.0,
+                  desc="large intersection join: {nr} blobs (80..5120 triangles) x {ns} tubes (336..20496 "
+                       "triangles), 20000^3 box, tau = 0, meshes host-resident, 32 GB device cap"),
+}
 
 
 def main():
@@ -142,22 +178,29 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="multilod")
     ap.add_argument("--plain", type=int, default=1, help="run the plain FP64 schedule once for comparison")
     ap.add_argument("--ablations", type=int, default=1, help="one step each without the learned skip / culling")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--n-r", type=int, default=10000)
-    ap.add_argument("--n-s", type=int, default=2000)
+    ap.add_argument("--n-r", type=int, default=None)
+    ap.add_argument("--n-s", type=int, default=None)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
         sys.exit(2)
-    import numpy as np
     import torch
     import meshgen as mg
     import paper_2604_19982_amd as pj
 
+    wl = WORKLOADS[args.workload]
+    taus = wl["taus"]
+    size = {}
+    if args.n_r:
+        size["n_r"] = args.n_r
+    if args.n_s:
+        size["n_s"] = args.n_s
     t0 = time.time()
-    R, S = mg.config_multilod(seed=1, n_r=args.n_r, n_s=args.n_s)
+    R, S = getattr(mg, wl["builder"])(**size)
     log(f"generated {R.n_objects} x {S.n_objects} objects in {time.time() - t0:.1f} s")
     stream = torch.cuda.current_stream()
     import tempfile
@@ -165,7 +208,7 @@ def main():
     t0 = time.time()
     model, train_loss, n_rec = train_model(pj, mg, stream, workdir)
     log(f"LoD model trained on {n_rec} logged pairs in {time.time() - t0:.1f} s, final loss {train_loss:.3f}")
-    ctx = pj.Context(stream=stream.cuda_stream, learned_skip=True, model_path=model)
+    ctx = pj.Context(stream=stream.cuda_stream, learned_skip=True, model_path=model, **wl["ctx"])
     t0 = time.time()
     gR, gS = ctx.meshes(R), ctx.meshes(S)
     torch.cuda.synchronize()
@@ -175,14 +218,14 @@ def main():
     copy_gbps = ctx.probe_copy(1 << 30)
     log(f"probes: scalar FP32 FMA {fma_tflops:.1f} TFLOP/s, copy {copy_gbps:.0f} GB/s")
     for w in range(args.warmup):
-        run_step(ctx, gR, gS, TAUS)
+        run_step(ctx, gR, gS, taus)
         log(f"warmup step {w} done")
     torch.cuda.synchronize()
     steps = []
     t_start = time.time()
     for k in range(args.steps):
         ts = time.time()
-        tot = run_step(ctx, gR, gS, TAUS, verbose=True)
+        tot = run_step(ctx, gR, gS, taus, verbose=True)
         torch.cuda.synchronize()
         tot["ms"] = (time.time() - ts) * 1e3
         steps.append(tot)
@@ -197,6 +240,7 @@ def main():
     launches = sum(s["launches"] for s in steps)
     p32 = sum(s["pairs"] for s in steps)
     achieved = (p32 * FLOP_PER_PAIR) / (kms * 1e-3) / 1e12 if kms > 0 else 0.0
+    st = ctx.stats()
     out = {
         "metric": "facet-pair evals/s; end-to-end join time, learned+batched vs plain GPU",
         "value": value,
@@ -210,13 +254,15 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": (f"multilod within-tau join: {R.n_objects} blobs (80/320/1280/5120 triangles) x "
-                                f"{S.n_objects} tubes (336..20496 triangles), 500^3 box, tau in {{0, 5, 20}} per step"),
+        "config": {"workload": wl["desc"].format(nr=R.n_objects, ns=S.n_objects),
                    "facet_pairs_per_step": pairs / args.steps,
                    "results_per_step": steps[-1]["results"],
                    "band_pairs_per_step": steps[-1]["band"],
                    "ingest_s": ingest_s,
-                   "mode": "learned LoD skip + batched persistent tiles + FP32 with FP64 guard band + chunk culling + hipGraph rounds",
+                   "chunks_last_join": st["chunks"],
+                   "staged_bytes_last_join": st["staged_bytes"],
+                   "mode": "learned LoD skip + batched persistent tiles + FP32 with FP64 guard band + chunk and "
+                           "facet culling + hipGraph rounds",
                    "lod_model": {"train_pairs": n_rec, "final_loss": train_loss}},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
@@ -224,14 +270,15 @@ def main():
                      "flop_per_pair": FLOP_PER_PAIR, "single_issue_fma_peak": SINGLE_ISSUE_FP32_TFLOPS,
                      "fma_probe_measured": fma_tflops, "copy_probe_gbps": copy_gbps},
     }
+    del gR, gS, ctx
     abl = {}
     if args.ablations:
         for name, cfg in (("no_learned_skip", {}), ("no_learned_no_cull", dict(tile_cull=False))):
-            t = one_step(pj, stream, R, S, **cfg)
+            t = one_step(pj, stream, R, S, taus, **cfg, **wl["ctx"])
             abl[name] = {"ms": t["ms"], "facet_pairs": t["pairs"] + t["pairs64"], "results": t["results"]}
             log(f"ablation {name}: {t['ms']:.1f} ms")
     if args.plain:
-        t = one_step(pj, stream, R, S, schedule="plain", precision="fp64")
+        t = one_step(pj, stream, R, S, taus, schedule="plain", precision="fp64", **wl["ctx"])
         abl["plain_gpu_schedule"] = {"ms": t["ms"], "facet_pairs": t["pairs"] + t["pairs64"], "results": t["results"]}
         log(f"plain schedule step: {t['ms']:.1f} ms")
         out["config"]["plain_ms_per_step"] = t["ms"]
@@ -240,7 +287,7 @@ def main():
         a["results_match"] = a["results"] == steps[-1]["results"]
     out["config"]["ablations"] = abl
     if args.cpu_seconds > 0:
-        out["cpu_baseline"] = cpu_baseline(R, S, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(R, S, args.cpu_seconds, gap=wl["cpu_gap"])
     print(json.dumps(out), flush=True)
 
 

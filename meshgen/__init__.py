@@ -274,6 +274,18 @@ def make_tubes(rng, centres, n_seg: int, n_lods: int, length_range=(20.0, 80.0),
     d2 = _unit(d1 + rng.normal(scale=0.5, size=(n, 3)))
     lengths = rng.uniform(length_range[0], length_range[1], size=n)
     segs = np.full(n, n_seg, np.int64) if n_seg_per_object is None else np.asarray(n_seg_per_object, np.int64)
+    per_obj = [None] * n
+    # the shapes are fixed by the draws above; build them in blocks of tubes
+    step = 4096
+    for c0 in range(0, n, step):
+        c1 = min(n, c0 + step)
+        _tube_block(per_obj, c0, centres[c0:c1], d0[c0:c1], d1[c0:c1], d2[c0:c1], lengths[c0:c1], segs[c0:c1],
+                    radius)
+    return per_obj, segs
+
+
+def _tube_block(per_obj, c0, centres, d0, d1, d2, lengths, segs, radius):
+    n = len(centres)
     P = np.zeros((n, 4, 3))
     P[:, 1] = d0
     P[:, 2] = d0 + d1
@@ -286,11 +298,9 @@ def make_tubes(rng, centres, n_seg: int, n_lods: int, length_range=(20.0, 80.0),
     scale = lengths / cum[:, -1]
     P *= scale[:, None, None]
     cum *= scale[:, None]
-    out_v = []
     groups = {}
     for t in range(n):
         groups.setdefault(int(segs[t]), []).append(t)
-    per_obj = [None] * n
     theta = 2.0 * np.pi * np.arange(8) / 8.0
     for ns, ids in groups.items():
         ids = np.asarray(ids)
@@ -324,8 +334,7 @@ def make_tubes(rng, centres, n_seg: int, n_lods: int, length_range=(20.0, 80.0),
         lo, hi = v.min(1), v.max(1)
         v += (centres[ids] - 0.5 * (lo + hi))[:, None, :]
         for k, t in enumerate(ids):
-            per_obj[t] = v[k].astype(np.float32)
-    return per_obj, segs
+            per_obj[c0 + t] = v[k].astype(np.float32)
 
 
 def make_blobs(rng, centres, radii, level_min: int, level_max: int, noise=(0.9, 1.1)):
@@ -340,12 +349,17 @@ def make_blobs(rng, centres, radii, level_min: int, level_max: int, noise=(0.9, 
     n = len(centres)
     tv, faces, parents = icosphere_template(level_max)
     nv = 10 * 4 ** level_max + 2
-    noise_v = rng.uniform(noise[0], noise[1], size=(n, nv))
-    v = tv[None, :nv, :] * (noise_v * radii[:, None])[:, :, None] + centres[:, None, :]
+    # generated in row blocks (the noise stream is the same as one n x V draw)
+    v = np.empty((n, nv, 3), np.float32)
+    step = max(1, (1 << 22) // nv)
+    for i0 in range(0, n, step):
+        i1 = min(n, i0 + step)
+        noise_v = rng.uniform(noise[0], noise[1], size=(i1 - i0, nv))
+        v[i0:i1] = tv[None, :nv, :] * (noise_v * radii[i0:i1, None])[:, :, None] + centres[i0:i1, None, :]
     lods = list(range(level_min, level_max + 1))
     tris = [faces[l] for l in lods]
     par = [parents[l] if i > 0 else np.full(len(faces[l]), -1, np.int32) for i, l in enumerate(lods)]
-    return v.astype(np.float32), tris, par
+    return v, tris, par
 
 
 def _assemble(per_obj_verts, per_obj_template, templates, n_lods, kind):
@@ -354,11 +368,16 @@ def _assemble(per_obj_verts, per_obj_template, templates, n_lods, kind):
     templates: dict key -> (list of tris per LoD, list of parents per LoD)
     """
     n = len(per_obj_verts)
-    vc = np.array([len(v) for v in per_obj_verts], np.int64)
+    if isinstance(per_obj_verts, np.ndarray) and per_obj_verts.ndim == 3:
+        # every object has the same vertex count: one reshape, no copy
+        vc = np.full(n, per_obj_verts.shape[1], np.int64)
+        verts = per_obj_verts.reshape(-1, 3)
+    else:
+        vc = np.array([len(v) for v in per_obj_verts], np.int64)
+        verts = np.concatenate(per_obj_verts).astype(np.float32) if n else np.zeros((0, 3), np.float32)
     vb = np.zeros(n, np.int64)
     if n:
         vb[1:] = np.cumsum(vc)[:-1]
-    verts = np.concatenate(per_obj_verts).astype(np.float32) if n else np.zeros((0, 3), np.float32)
     blocks_t, blocks_p = [], []
     start = {}
     pos = 0
@@ -370,13 +389,16 @@ def _assemble(per_obj_verts, per_obj_template, templates, n_lods, kind):
             pos += len(tl[l])
     tris = np.concatenate(blocks_t).astype(np.int32)
     parent = np.concatenate(blocks_p).astype(np.int32)
-    tb = np.empty(n * n_lods, np.int64)
-    tc = np.empty(n * n_lods, np.int32)
-    for i in range(n):
-        key = per_obj_template[i]
-        for l in range(n_lods):
-            tb[i * n_lods + l] = start[(key, l)]
-            tc[i * n_lods + l] = len(templates[key][0][l])
+    keys = list(templates.keys())
+    kid = {k: j for j, k in enumerate(keys)}
+    tb_k = np.array([[start[(k, l)] for l in range(n_lods)] for k in keys], np.int64).reshape(len(keys), n_lods)
+    tc_k = np.array([[len(templates[k][0][l]) for l in range(n_lods)] for k in keys], np.int32).reshape(len(keys), n_lods)
+    if len(keys) == 1:
+        obj_k = np.zeros(n, np.int64)
+    else:
+        obj_k = np.array([kid[k] for k in per_obj_template], np.int64)
+    tb = tb_k[obj_k].reshape(-1)
+    tc = tc_k[obj_k].reshape(-1)
     return MeshSet(n, n_lods, np.ascontiguousarray(verts), vb, vc.astype(np.int32), np.ascontiguousarray(tris),
                    tb, tc, parent, np.asarray(kind, np.int8))
 
@@ -392,7 +414,7 @@ def blob_set(rng, n, box, level_min, level_max, radius_sigma=None, radius=1.0):
     v, tris, par = make_blobs(rng, centres, radii, level_min, level_max)
     L = level_max - level_min + 1
     templ = {("ico", level_min, level_max): (tris, par)}
-    return _assemble(list(v), [("ico", level_min, level_max)] * n, templ, L, np.zeros(n))
+    return _assemble(v, [("ico", level_min, level_max)] * n, templ, L, np.zeros(n))
 
 
 def tube_set(rng, n, box, n_seg, n_lods, length_range=(20.0, 80.0), radius=1.0):
@@ -528,8 +550,22 @@ def config_knn(seed: int = 2, n_r: int = 20000, n_s: int = 20000, n_clusters: in
     return out[0], out[1]
 
 
+def config_learned(seed: int = 4, n_r: int = 100000, n_s: int = 20000, box: float = 5000.0, n_seg: int = 1280):
+    """Learned-skip workload: the multi-LoD object shapes at 10x the counts in
+    a 5000^3 box, joined within tau = 10."""
+    return config_multilod(seed=seed, n_r=n_r, n_s=n_s, box=box, n_seg=n_seg)
+
+
+def config_large(seed: int = 5, n_r: int = 1000000, n_s: int = 200000, box: float = 20000.0, n_seg: int = 1280):
+    """Large intersection workload: 1M blobs (80..5120 triangles) and 200k
+    tubes (336..20,496 triangles) in a 20000^3 box, joined at tau = 0."""
+    return config_multilod(seed=seed, n_r=n_r, n_s=n_s, box=box, n_seg=n_seg)
+
+
 CONFIGS = {
     "small": dict(builder=config_small, tau=[0.5]),
     "multilod": dict(builder=config_multilod, tau=[0.0, 5.0, 20.0]),
     "knn": dict(builder=config_knn, k=3),
+    "learned": dict(builder=config_learned, tau=[10.0]),
+    "large": dict(builder=config_large, tau=[0.0]),
 }
