@@ -531,6 +531,31 @@ __device__ __forceinline__ float block_gap(const float4 alo, const float4 ahi, c
     return (float)sqrt(gx * gx + gy * gy + gz * gz) * (1.0f - 0x1p-20f);
 }
 
+// Box gap in FP32 rounded down: each difference, square, sum and the
+// hardware square root add at most a few ulps, so scaling by (1 - 2^-20)
+// keeps it below the exact gap (a flushed denormal only lowers it).
+__device__ __forceinline__ float box_gap32(const float4 alo, const float4 ahi, const float4 blo, const float4 bhi)
+{
+    const float gx = fmaxf(0.0f, fmaxf(blo.x - ahi.x, alo.x - bhi.x));
+    const float gy = fmaxf(0.0f, fmaxf(blo.y - ahi.y, alo.y - bhi.y));
+    const float gz = fmaxf(0.0f, fmaxf(blo.z - ahi.z, alo.z - bhi.z));
+    return __builtin_amdgcn_sqrtf(fmaf(gz, gz, fmaf(gy, gy, gx * gx))) * (1.0f - 0x1p-20f);
+}
+
+// The cut of a chunk or facet whose FP32 distance to every A facet of the
+// tile is >= g (box gap minus eps) and whose max ph is bph: it cannot change
+// a decision (within), the exact minima (no tau), or the collected set.
+// lbm/ubm may be any lane's running minima: each is >= the item's final one.
+template <bool COLLECT>
+__device__ __forceinline__ bool chunk_cut(float g, float bph, float aph, float cur_lb, float cur_ub, float lbm,
+                                          float ubm, const Item &it, float tau, bool within)
+{
+    if (COLLECT) return g > fminf(it.thr, fminf(cur_ub, ubm) + 2.0f * it.eps);
+    const float ub_cut = within ? fminf(fminf(cur_ub, ubm), tau - it.eps) : fminf(cur_ub, ubm);
+    const float lb_cut = within ? fminf(fminf(cur_lb, lbm), tau + it.eps) : fminf(cur_lb, lbm);
+    return g > ub_cut && fmaxf(g - aph - bph, 0.0f) > lb_cut;
+}
+
 template <int P, bool COLLECT>
 __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t, float4 *sh)
 {
@@ -568,119 +593,137 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
     int cols = 0, culled = 0;
     const bool finest = it.flags & IT_FINEST;
     bool stop = false;
-    for (int cb = tl.b0; cb < tl.b1 && !stop; cb += 64) {
-        const int nb = min(64, tl.b1 - cb);
-        // cut values shared by the chunk test and the per-facet test
-        float ub_cut = kInf, lb_cut = kInf, col_cut = kInf;
+    // Groups of up to 64 streamed chunks: lane j tests chunk j of the group
+    // from its block record, a ballot leaves the chunks that may matter, and
+    // the wave walks those in order.  Before a chunk is loaded its test is
+    // repeated with the minima found so far (read back from the testing lane).
+    for (int g0 = tl.b0; g0 < tl.b1 && !stop; g0 += 64 * 64) {
+        const int nch = min(64, (tl.b1 - g0 + 63) >> 6);
+        float cur_lb = kInf, cur_ub = kInf;
+        float gap_l = 0.0f, bph_l = 0.0f;
+        unsigned long long cmask;
         if (a.cull) {
-            const float4 blo = SB.blk[2 * (cb >> 6)], bhi = SB.blk[2 * (cb >> 6) + 1];
-            const float gap = block_gap(alo, ahi, blo, bhi) - it.eps;
-            const float bph = bhi.w;
-            const float cur_lb = __uint_as_float(__builtin_amdgcn_readfirstlane(
+            cur_lb = __uint_as_float(__builtin_amdgcn_readfirstlane(
                 __hip_atomic_load(&o->lb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
-            const float cur_ub = __uint_as_float(__builtin_amdgcn_readfirstlane(
+            cur_ub = __uint_as_float(__builtin_amdgcn_readfirstlane(
                 __hip_atomic_load(&o->ub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
-            bool skip;
-            if (COLLECT) {
-                col_cut = fminf(it.thr, fminf(cur_ub, ubm) + 2.0f * it.eps);
-                skip = gap > col_cut;
-            } else {
-                ub_cut = within ? fminf(fminf(cur_ub, ubm), a.tau - it.eps) : fminf(cur_ub, ubm);
-                lb_cut = within ? fminf(fminf(cur_lb, lbm), a.tau + it.eps) : fminf(cur_lb, lbm);
-                skip = gap > ub_cut && fmaxf(gap - aph - bph, 0.0f) > lb_cut;
+            bool live = false;
+            if (lane < nch) {
+                const int c = (g0 >> 6) + lane;
+                const float4 blo = SB.blk[2 * c], bhi = SB.blk[2 * c + 1];
+                gap_l = box_gap32(alo, ahi, blo, bhi) - it.eps;
+                bph_l = bhi.w;
+                live = !chunk_cut<COLLECT>(gap_l, bph_l, aph, cur_lb, cur_ub, lbm, ubm, it, a.tau, within);
             }
-            if (__builtin_amdgcn_readfirstlane((int)skip)) {
+            cmask = __ballot(live);
+            culled += nch - __popcll(cmask);
+        } else {
+            cmask = nch == 64 ? ~0ull : ((1ull << nch) - 1ull);
+        }
+        while (cmask != 0ull && !stop) {
+            const int j = __builtin_ctzll(cmask);
+            cmask &= cmask - 1ull;
+            const int cb = g0 + 64 * j;
+            const int nb = min(64, tl.b1 - cb);
+            if (a.cull) {
+                const float gj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gap_l), j));
+                const float bj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bph_l), j));
+                const float l0 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(lbm)));
+                const float u0 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(ubm)));
+                if (__builtin_amdgcn_readfirstlane(
+                        (int)chunk_cut<COLLECT>(gj, bj, aph, cur_lb, cur_ub, l0, u0, it, a.tau, within))) {
+                    ++culled;
+                    continue;
+                }
+            }
+            int f = cb + lane;
+            if (f >= tl.b1) f = cb;
+            const int32_t i0 = SB.tris[3 * f], i1 = SB.tris[3 * f + 1], i2 = SB.tris[3 * f + 2];
+            const V3 w0 = ld3f(SB.verts, i0), w1 = ld3f(SB.verts, i1), w2 = ld3f(SB.verts, i2);
+            const float2 bh = SB.hdph ? SB.hdph[f] : make_float2(0.0f, 0.0f);
+            // Facet culling: the same two-sided test with this facet's own box
+            // and ph against the A block; surviving facets are packed to the
+            // front of the LDS chunk (their index rides in the record's pad).
+            bool keep = lane < nb;
+            if (a.cull) {
+                const float4 flo = make_float4(fminf(fminf(w0.x, w1.x), w2.x), fminf(fminf(w0.y, w1.y), w2.y),
+                                               fminf(fminf(w0.z, w1.z), w2.z), 0.0f);
+                const float4 fhi = make_float4(fmaxf(fmaxf(w0.x, w1.x), w2.x), fmaxf(fmaxf(w0.y, w1.y), w2.y),
+                                               fmaxf(fmaxf(w0.z, w1.z), w2.z), 0.0f);
+                const float g = box_gap32(alo, ahi, flo, fhi) - it.eps;
+                keep = keep && !chunk_cut<COLLECT>(g, bh.y, aph, cur_lb, cur_ub, lbm, ubm, it, a.tau, within);
+            }
+            const unsigned long long kmask = __ballot(keep);
+            const int nk = __popcll(kmask);
+            if (nk == 0) {
                 ++culled;
                 continue;
             }
-        }
-        int f = cb + lane;
-        if (f >= tl.b1) f = cb;
-        const int32_t i0 = SB.tris[3 * f], i1 = SB.tris[3 * f + 1], i2 = SB.tris[3 * f + 2];
-        const V3 w0 = ld3f(SB.verts, i0), w1 = ld3f(SB.verts, i1), w2 = ld3f(SB.verts, i2);
-        const float2 bh = SB.hdph ? SB.hdph[f] : make_float2(0.0f, 0.0f);
-        // Facet culling: the same two-sided test with this facet's own box
-        // and ph against the A block; surviving facets are packed to the
-        // front of the LDS chunk (their index rides in the record's pad).
-        bool keep = lane < nb;
-        if (a.cull) {
-            const float4 flo = make_float4(fminf(fminf(w0.x, w1.x), w2.x), fminf(fminf(w0.y, w1.y), w2.y),
-                                           fminf(fminf(w0.z, w1.z), w2.z), 0.0f);
-            const float4 fhi = make_float4(fmaxf(fmaxf(w0.x, w1.x), w2.x), fmaxf(fmaxf(w0.y, w1.y), w2.y),
-                                           fmaxf(fmaxf(w0.z, w1.z), w2.z), 0.0f);
-            const float g = block_gap(alo, ahi, flo, fhi) - it.eps;
-            const bool cut = COLLECT ? g > col_cut : (g > ub_cut && fmaxf(g - aph - bh.y, 0.0f) > lb_cut);
-            keep = keep && !cut;
-        }
-        const unsigned long long kmask = __ballot(keep);
-        const int nk = __popcll(kmask);
-        if (nk == 0) {
-            ++culled;
-            continue;
-        }
-        if (keep) {
-            const int pos = __builtin_amdgcn_mbcnt_hi((unsigned)(kmask >> 32),
-                                                      __builtin_amdgcn_mbcnt_lo((unsigned)kmask, 0u));
-            Rec rb = make_rec(w0 - org, w1 - org, w2 - org, bh.x, bh.y);
-            rb.pad = __int_as_float(f);
-            float tmp[44];
-            __builtin_memcpy(tmp, &rb, sizeof(tmp));
+            if (keep) {
+                const int pos = __builtin_amdgcn_mbcnt_hi((unsigned)(kmask >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((unsigned)kmask, 0u));
+                Rec rb = make_rec(w0 - org, w1 - org, w2 - org, bh.x, bh.y);
+                rb.pad = __int_as_float(f);
+                float tmp[44];
+                __builtin_memcpy(tmp, &rb, sizeof(tmp));
 #pragma unroll
-            for (int q = 0; q < 11; ++q)
-                sh[pos * 11 + q] = make_float4(tmp[4 * q], tmp[4 * q + 1], tmp[4 * q + 2], tmp[4 * q + 3]);
-        }
-        __syncthreads();
-        for (int k = 0; k < nk; ++k) {
-            float tmp[44];
-#pragma unroll
-            for (int q = 0; q < 11; ++q) {
-                float4 x = sh[k * 11 + q];
-                tmp[4 * q] = x.x;
-                tmp[4 * q + 1] = x.y;
-                tmp[4 * q + 2] = x.z;
-                tmp[4 * q + 3] = x.w;
+                for (int q = 0; q < 11; ++q)
+                    sh[pos * 11 + q] = make_float4(tmp[4 * q], tmp[4 * q + 1], tmp[4 * q + 2], tmp[4 * q + 3]);
             }
-            Rec rb;
-            __builtin_memcpy(&rb, tmp, sizeof(rb));
+            __syncthreads();
+            for (int k = 0; k < nk; ++k) {
+                float tmp[44];
 #pragma unroll
-            for (int p = 0; p < P; ++p) {
-                Pair32 pr = pair_f32(ra[p], rb, it.eps);
-                float dlo = pr.d * (ra[p].ok * rb.ok);
-                lbm = fminf(lbm, fmaxf(dlo - (ra[p].ph + rb.ph), 0.0f));
-                ubm = fminf(ubm, pr.d + (ra[p].hd + rb.hd));
-                sure |= pr.sure ? 1 : 0;
-                if (COLLECT) {
-                    const int fa = tl.a0 + lane + 64 * p;
-                    // the pair realising the minimum has dlo <= d + eps <= ubm + 2 eps
-                    if (fa < SA.n && dlo <= fminf(it.thr, ubm + 2.0f * it.eps)) {
-                        const int slot = atomicAdd(a.counter, 1);
-                        if (slot < a.collect_cap) a.collected[slot] = PairRef{tl.item, fa, __float_as_int(rb.pad), 0};
-                        else a.overflow[tl.item] = 1;
+                for (int q = 0; q < 11; ++q) {
+                    float4 x = sh[k * 11 + q];
+                    tmp[4 * q] = x.x;
+                    tmp[4 * q + 1] = x.y;
+                    tmp[4 * q + 2] = x.z;
+                    tmp[4 * q + 3] = x.w;
+                }
+                Rec rb;
+                __builtin_memcpy(&rb, tmp, sizeof(rb));
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    Pair32 pr = pair_f32(ra[p], rb, it.eps);
+                    float dlo = pr.d * (ra[p].ok * rb.ok);
+                    lbm = fminf(lbm, fmaxf(dlo - (ra[p].ph + rb.ph), 0.0f));
+                    ubm = fminf(ubm, pr.d + (ra[p].hd + rb.hd));
+                    sure |= pr.sure ? 1 : 0;
+                    if (COLLECT) {
+                        const int fa = tl.a0 + lane + 64 * p;
+                        // the pair realising the minimum has dlo <= d + eps <= ubm + 2 eps
+                        if (fa < SA.n && dlo <= fminf(it.thr, ubm + 2.0f * it.eps)) {
+                            const int slot = atomicAdd(a.counter, 1);
+                            if (slot < a.collect_cap)
+                                a.collected[slot] = PairRef{tl.item, fa, __float_as_int(rb.pad), 0};
+                            else a.overflow[tl.item] = 1;
+                        }
                     }
                 }
             }
-        }
-        cols += nk;
-        __syncthreads();
-        if (a.cull) {  // publish the running minima so that other tiles can cull against them
-            const float wl = wmin_u(lbm), wu = wmin_u(ubm);
-            lbm = wl;
-            ubm = wu;
-            if (lane == 0) {
-                atomicMin(&o->lb, fbits(wl));
-                atomicMin(&o->ub, fbits(wu));
+            cols += nk;
+            __syncthreads();
+            if (a.cull) {  // publish the running minima so that other tiles can cull against them
+                const float wl = wmin_u(lbm), wu = wmin_u(ubm);
+                lbm = wl;
+                ubm = wu;
+                if (lane == 0) {
+                    atomicMin(&o->lb, fbits(wl));
+                    atomicMin(&o->ub, fbits(wu));
+                }
             }
-        }
-        if (!COLLECT && a.early) {
-            const float wub = wmin_u(ubm);
-            const int ws = __builtin_amdgcn_readfirstlane(wave_or(sure));
-            const bool confirm = (a.tau > 0.0f && wub + it.eps <= a.tau) || (finest && ws);
-            if (confirm) {
-                if (lane == 0) __hip_atomic_store(&o->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                stop = true;
-            } else if (__builtin_amdgcn_readfirstlane(
-                           __hip_atomic_load(&o->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-                stop = true;
+            if (!COLLECT && a.early) {
+                const float wub = wmin_u(ubm);
+                const int ws = __builtin_amdgcn_readfirstlane(wave_or(sure));
+                const bool confirm = (a.tau > 0.0f && wub + it.eps <= a.tau) || (finest && ws);
+                if (confirm) {
+                    if (lane == 0) __hip_atomic_store(&o->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    stop = true;
+                } else if (__builtin_amdgcn_readfirstlane(
+                               __hip_atomic_load(&o->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                    stop = true;
+                }
             }
         }
     }
