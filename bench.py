@@ -65,6 +65,9 @@ def run_step(ctx, gR, gS, taus, verbose=False):
                 f"band {st['t_band_ms']:.1f}), kernel {st['refine_kernel_ms']:.1f} ms, cand {st['candidates']}, "
                 f"pairs {st['facet_pairs']:.3e}+{st['facet_pairs_fp64']:.3e}, band {st['band_pairs']}, "
                 f"resolved/lod {st['resolved_at_lod'][:4]}, results {len(res['r'])}")
+            log(f"    per LoD: items {st['lod_items'][:4]}, tiles {st['lod_tiles'][:4]}, "
+                f"pairs {[f'{x:.2e}' for x in st['lod_pairs'][:4]]}, "
+                f"kernel ms {[round(x, 2) for x in st['lod_kernel_ms'][:4]]}, chunks culled {st['tiles_culled']}")
         tot["pairs"] += st["facet_pairs"]
         tot["pairs64"] += st["facet_pairs_fp64"]
         tot["kms"] += st["refine_kernel_ms"]

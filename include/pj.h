@@ -185,6 +185,10 @@ typedef struct {
     int64_t waves_per_cu_used;  /* persistent grid of the last bulk round, waves per CU */
     double t_tune_ms;           /* host time spent in the autotuner during this join */
     int64_t staged_bytes;       /* host-to-device bytes of staged facet data (host-resident sets) */
+    int64_t lod_items[8];       /* bulk FP32 work items per LoD round */
+    int64_t lod_tiles[8];       /* bulk FP32 tiles per LoD round */
+    int64_t lod_pairs[8];       /* facet pairs evaluated by the bulk kernel per LoD round */
+    double lod_kernel_ms[8];    /* bulk kernel time per LoD round (HIP events) */
 } pj_stats;
 
 pj_status pj_get_stats(const pj_context *ctx, pj_stats *out);

@@ -66,13 +66,14 @@ class Stats(ctypes.Structure):
                 ("peak_device_bytes", ctypes.c_int64), ("chunks", ctypes.c_int64),
                 ("graph_replays", ctypes.c_int64), ("tile_s_used", ctypes.c_int64),
                 ("waves_per_cu_used", ctypes.c_int64), ("t_tune_ms", ctypes.c_double),
-                ("staged_bytes", ctypes.c_int64)]
+                ("staged_bytes", ctypes.c_int64), ("lod_items", ctypes.c_int64 * 8), ("lod_tiles", ctypes.c_int64 * 8),
+                ("lod_pairs", ctypes.c_int64 * 8), ("lod_kernel_ms", ctypes.c_double * 8)]
 
     def to_dict(self):
         d = {}
         for name, _ in self._fields_:
             v = getattr(self, name)
-            d[name] = list(v) if name == "resolved_at_lod" else v
+            d[name] = list(v) if isinstance(v, ctypes.Array) else v
         return d
 
 

@@ -1525,6 +1525,10 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
         HIPTRY(ctx, hipEventElapsedTime(&ms, ctx->ev_k0[b], ctx->ev_k1[b]));
         ctx->stats.refine_kernel_ms += ms;
         ctx->stats.refine_launches += 1;
+        if (lod < 8) {
+            ctx->stats.lod_pairs[lod] += (int64_t)pairs;
+            ctx->stats.lod_kernel_ms[lod] += ms;
+        }
         merged[j] = 1;
         return PJ_OK;
     };
@@ -1555,6 +1559,10 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
     // the join stream must not run ahead of the downloads
     HIPTRY(ctx, hipStreamWaitEvent(st, ctx->ev_d2h[(nch - 1) % nsets], 0));
     ctx->stats.tiles += nt;
+    if (lod < 8) {
+        ctx->stats.lod_items[lod] += ni;
+        ctx->stats.lod_tiles[lod] += nt;
+    }
     ctx->stats.tile_s_used = pl.tile_s;
     ctx->stats.waves_per_cu_used = wpc;
     return PJ_OK;
