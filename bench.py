@@ -211,7 +211,10 @@ def main():
     t0 = time.time()
     model, train_loss, n_rec = train_model(pj, mg, stream, workdir)
     log(f"LoD model trained on {n_rec} logged pairs in {time.time() - t0:.1f} s, final loss {train_loss:.3f}")
-    ctx = pj.Context(stream=stream.cuda_stream, learned_skip=True, model_path=model, **wl["ctx"])
+    # launch shapes come from the autotuner (it times candidates during the
+    # warmup step and caches them for the ablation contexts)
+    tune = dict(autotune=True, autotune_path=os.path.join(workdir, "shapes.txt"))
+    ctx = pj.Context(stream=stream.cuda_stream, learned_skip=True, model_path=model, **tune, **wl["ctx"])
     t0 = time.time()
     gR, gS = ctx.meshes(R), ctx.meshes(S)
     torch.cuda.synchronize()
@@ -244,6 +247,7 @@ def main():
     p32 = sum(s["pairs"] for s in steps)
     achieved = (p32 * FLOP_PER_PAIR) / (kms * 1e-3) / 1e12 if kms > 0 else 0.0
     st = ctx.stats()
+    shapes = open(tune["autotune_path"]).read().split("\n") if os.path.exists(tune["autotune_path"]) else []
     out = {
         "metric": "facet-pair evals/s; end-to-end join time, learned+batched vs plain GPU",
         "value": value,
@@ -266,7 +270,8 @@ def main():
                    "staged_bytes_last_join": st["staged_bytes"],
                    "mode": "learned LoD skip + batched persistent tiles + FP32 with FP64 guard band + chunk and "
                            "facet culling + hipGraph rounds",
-                   "lod_model": {"train_pairs": n_rec, "final_loss": train_loss}},
+                   "lod_model": {"train_pairs": n_rec, "final_loss": train_loss},
+                   "tuned_shapes": [ln for ln in shapes if ln.strip()]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
                      "kernel": "k_refine_f32", "launches": launches, "avg_launch_ms": kms / max(launches, 1),
@@ -277,7 +282,7 @@ def main():
     abl = {}
     if args.ablations:
         for name, cfg in (("no_learned_skip", {}), ("no_learned_no_cull", dict(tile_cull=False))):
-            t = one_step(pj, stream, R, S, taus, **cfg, **wl["ctx"])
+            t = one_step(pj, stream, R, S, taus, **cfg, **tune, **wl["ctx"])
             abl[name] = {"ms": t["ms"], "facet_pairs": t["pairs"] + t["pairs64"], "results": t["results"]}
             log(f"ablation {name}: {t['ms']:.1f} ms")
     if args.plain:

@@ -866,7 +866,7 @@ void plan_tiles(const pj_meshes *R, const pj_meshes *S, const std::vector<int> &
 // order independent.  The cache is a text file of lines
 // "<class> <tile_s> <waves_per_cu> <ms>".
 // ---------------------------------------------------------------------------
-constexpr int kTuneTS[] = {256, 512, 1024, 2048, 4096};
+constexpr int kTuneTS[] = {256, 512, 1024, 2048, 4096, 8192};
 constexpr int kTuneWPC[] = {4, 8, 12, 16, 24};
 
 void load_tune_cache(pj_context *ctx)

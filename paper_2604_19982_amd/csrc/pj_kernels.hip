@@ -570,13 +570,10 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
     const FacetSrc SA = facet_src(swap ? a.S : a.R, it.a_obj, it.lod);
     const FacetSrc SB = facet_src(swap ? a.R : a.S, it.b_obj, it.lod);
     const V3 org = V3{it.ox, it.oy, it.oz};
+    // the A records are built when the first chunk survives its test, so a
+    // tile whose chunks are all culled costs only block-record reads
     Rec ra[P];
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-        int f = tl.a0 + lane + 64 * p;
-        if (f >= SA.n) f = tl.a0;  // padding lanes repeat a real facet
-        ra[p] = load_rec(SA, f, org);
-    }
+    bool built = false;
     // union of the A block records (tile starts are multiples of 64)
     float4 alo = SA.blk[2 * (tl.a0 >> 6)], ahi = SA.blk[2 * (tl.a0 >> 6) + 1];
 #pragma unroll
@@ -635,6 +632,15 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
                     ++culled;
                     continue;
                 }
+            }
+            if (!built) {
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    int fa = tl.a0 + lane + 64 * p;
+                    if (fa >= SA.n) fa = tl.a0;  // padding lanes repeat a real facet
+                    ra[p] = load_rec(SA, fa, org);
+                }
+                built = true;
             }
             int f = cb + lane;
             if (f >= tl.b1) f = cb;
