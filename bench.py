@@ -284,6 +284,12 @@ def main():
         for name, cfg in (("no_learned_skip", {}), ("no_learned_no_cull", dict(tile_cull=False))):
             t = one_step(pj, stream, R, S, taus, **cfg, **tune, **wl["ctx"])
             abl[name] = {"ms": t["ms"], "facet_pairs": t["pairs"] + t["pairs64"], "results": t["results"]}
+            if t["kms"] > 0:
+                # the same kernel without culling: every facet pair of every visited item is evaluated
+                ach = t["pairs"] * FLOP_PER_PAIR / (t["kms"] * 1e-3) / 1e12
+                abl[name]["kernel_ms"] = t["kms"]
+                abl[name]["kernel_tflops"] = ach
+                abl[name]["kernel_frac"] = ach / PEAK_FP32_TFLOPS
             log(f"ablation {name}: {t['ms']:.1f} ms")
     if args.plain:
         t = one_step(pj, stream, R, S, taus, schedule="plain", precision="fp64", **wl["ctx"])
