@@ -189,6 +189,9 @@ typedef struct {
     int64_t lod_tiles[8];       /* bulk FP32 tiles per LoD round */
     int64_t lod_pairs[8];       /* facet pairs evaluated by the bulk kernel per LoD round */
     double lod_kernel_ms[8];    /* bulk kernel time per LoD round (HIP events) */
+    int64_t collect_launches;   /* FP32 collect passes of the exact recheck (not in refine_*) */
+    int64_t collect_pairs;      /* facet pairs they evaluated */
+    double collect_kernel_ms;   /* their device time */
 } pj_stats;
 
 pj_status pj_get_stats(const pj_context *ctx, pj_stats *out);

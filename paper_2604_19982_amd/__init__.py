@@ -67,7 +67,9 @@ class Stats(ctypes.Structure):
                 ("graph_replays", ctypes.c_int64), ("tile_s_used", ctypes.c_int64),
                 ("waves_per_cu_used", ctypes.c_int64), ("t_tune_ms", ctypes.c_double),
                 ("staged_bytes", ctypes.c_int64), ("lod_items", ctypes.c_int64 * 8), ("lod_tiles", ctypes.c_int64 * 8),
-                ("lod_pairs", ctypes.c_int64 * 8), ("lod_kernel_ms", ctypes.c_double * 8)]
+                ("lod_pairs", ctypes.c_int64 * 8), ("lod_kernel_ms", ctypes.c_double * 8),
+                ("collect_launches", ctypes.c_int64), ("collect_pairs", ctypes.c_int64),
+                ("collect_kernel_ms", ctypes.c_double)]
 
     def to_dict(self):
         d = {}

@@ -1702,11 +1702,11 @@ pj_status exact_finest_view(pj_context *ctx, const MeshDev &Rv, const MeshDev &S
     HIPTRY(ctx, hipStreamSynchronize(st));
     float ms = 0;
     HIPTRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-    ctx->stats.refine_kernel_ms += ms;
-    ctx->stats.refine_launches += 1;
+    ctx->stats.collect_kernel_ms += ms;
+    ctx->stats.collect_launches += 1;
     unsigned long long pairs;
     std::memcpy(&pairs, host_ctr + 2, 8);
-    ctx->stats.facet_pairs += (int64_t)pairs;
+    ctx->stats.collect_pairs += (int64_t)pairs;
     const int64_t ncoll = std::min<int64_t>(host_ctr[0], cap);
     HIPTRY(ctx, hipEventRecord(ctx->ev0, st));
     HIPTRY(ctx, launch_pairs_f64(Rv, Sv, a.items, a.collected, ncoll, ptr<ItemOut64>(ctx->b_out64), st));
