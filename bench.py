@@ -39,9 +39,11 @@ TAUS = (0.0, 5.0, 20.0)
 COUNTERS = os.path.join(ROOT, "profiles", "k_refine_f32_multilod_counters.json")
 
 
-def measured_traffic():
+def measured_traffic(workload="multilod"):
     """HBM bytes per launch from the committed counter runs, or None when the
-    kernel sources changed since they were taken."""
+    kernel sources changed since they were taken (or for another workload)."""
+    if workload != "multilod":
+        return None
     import hashlib
     try:
         rec = json.load(open(COUNTERS))
@@ -275,7 +277,7 @@ def main():
                    "lod_model": {"train_pairs": n_rec, "final_loss": train_loss},
                    "tuned_shapes": [ln for ln in shapes if ln.strip()]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(args.workload),
                      "kernel": "k_refine_f32", "launches": launches, "avg_launch_ms": kms / max(launches, 1),
                      "flop_per_pair": FLOP_PER_PAIR, "single_issue_fma_peak": SINGLE_ISSUE_FP32_TFLOPS,
                      "fma_probe_measured": fma_tflops, "copy_probe_gbps": copy_gbps},
