@@ -97,10 +97,11 @@ def train_model(pj, mg, stream, workdir):
     return model, loss, os.path.getsize(log) // 72
 
 
-def one_step(pj, stream, R, S, taus, **cfg):
+def one_step(pj, stream, gR, gS, taus, **cfg):
+    """One step on another context over the already ingested mesh sets (a
+    mesh set may be shared by contexts on its device)."""
     import torch
     c = pj.Context(stream=stream.cuda_stream, **cfg)
-    gR, gS = c.meshes(R), c.meshes(S)
     torch.cuda.synchronize()
     ts = time.time()
     tot = run_step(c, gR, gS, taus)
@@ -206,7 +207,7 @@ def main():
     if args.n_s:
         size["n_s"] = args.n_s
     t0 = time.time()
-    R, S = getattr(mg, wl["builder"])(**size)
+    R, S = getattr(mg, wl["builder"])(progress=lambda m: log(f"generating: {m}"), **size)
     log(f"generated {R.n_objects} x {S.n_objects} objects in {time.time() - t0:.1f} s")
     stream = torch.cuda.current_stream()
     import tempfile
@@ -219,7 +220,9 @@ def main():
     tune = dict(autotune=True, autotune_path=os.path.join(workdir, "shapes.txt"))
     ctx = pj.Context(stream=stream.cuda_stream, learned_skip=True, model_path=model, **tune, **wl["ctx"])
     t0 = time.time()
-    gR, gS = ctx.meshes(R), ctx.meshes(S)
+    gR = ctx.meshes(R)
+    log(f"ingested R in {time.time() - t0:.1f} s")
+    gS = ctx.meshes(S)
     torch.cuda.synchronize()
     ingest_s = time.time() - t0
     log(f"ingested in {ingest_s:.2f} s")
@@ -282,11 +285,10 @@ def main():
                      "flop_per_pair": FLOP_PER_PAIR, "single_issue_fma_peak": SINGLE_ISSUE_FP32_TFLOPS,
                      "fma_probe_measured": fma_tflops, "copy_probe_gbps": copy_gbps},
     }
-    del gR, gS, ctx
     abl = {}
     if args.ablations:
         for name, cfg in (("no_learned_skip", {}), ("no_learned_no_cull", dict(tile_cull=False))):
-            t = one_step(pj, stream, R, S, taus, **cfg, **tune, **wl["ctx"])
+            t = one_step(pj, stream, gR, gS, taus, **cfg, **tune, **wl["ctx"])
             abl[name] = {"ms": t["ms"], "facet_pairs": t["pairs"] + t["pairsc"] + t["pairs64"], "results": t["results"]}
             if t["kms"] > 0:
                 # the same kernel without culling: every facet pair of every visited item is evaluated
@@ -296,7 +298,7 @@ def main():
                 abl[name]["kernel_frac"] = ach / PEAK_FP32_TFLOPS
             log(f"ablation {name}: {t['ms']:.1f} ms")
     if args.plain:
-        t = one_step(pj, stream, R, S, taus, schedule="plain", precision="fp64", **wl["ctx"])
+        t = one_step(pj, stream, gR, gS, taus, schedule="plain", precision="fp64", **wl["ctx"])
         abl["plain_gpu_schedule"] = {"ms": t["ms"], "facet_pairs": t["pairs"] + t["pairsc"] + t["pairs64"],
                                      "results": t["results"]}
         log(f"plain schedule step: {t['ms']:.1f} ms")

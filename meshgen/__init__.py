@@ -261,7 +261,7 @@ def _unit(x):
 
 
 def make_tubes(rng, centres, n_seg: int, n_lods: int, length_range=(20.0, 80.0), radius: float = 1.0,
-               n_seg_per_object=None):
+               n_seg_per_object=None, progress=None):
     """Tubes with MBB centres at ``centres`` (float64 [n, 3]).
 
     Draw order per call: directions (n x 3 normals x 3), lengths (n).
@@ -281,6 +281,8 @@ def make_tubes(rng, centres, n_seg: int, n_lods: int, length_range=(20.0, 80.0),
         c1 = min(n, c0 + step)
         _tube_block(per_obj, c0, centres[c0:c1], d0[c0:c1], d1[c0:c1], d2[c0:c1], lengths[c0:c1], segs[c0:c1],
                     radius)
+        if progress is not None:
+            progress(f"tubes {c1}/{n}")
     return per_obj, segs
 
 
@@ -337,7 +339,7 @@ def _tube_block(per_obj, c0, centres, d0, d1, d2, lengths, segs, radius):
             per_obj[c0 + t] = v[k].astype(np.float32)
 
 
-def make_blobs(rng, centres, radii, level_min: int, level_max: int, noise=(0.9, 1.1)):
+def make_blobs(rng, centres, radii, level_min: int, level_max: int, noise=(0.9, 1.1), progress=None):
     """Perturbed icospheres; LoD l is subdivision level level_min + l.
 
     Each finest vertex is scaled radially by U(noise) (coarse vertices are a
@@ -356,6 +358,8 @@ def make_blobs(rng, centres, radii, level_min: int, level_max: int, noise=(0.9, 
         i1 = min(n, i0 + step)
         noise_v = rng.uniform(noise[0], noise[1], size=(i1 - i0, nv))
         v[i0:i1] = tv[None, :nv, :] * (noise_v * radii[i0:i1, None])[:, :, None] + centres[i0:i1, None, :]
+        if progress is not None and (i1 == n or (i0 // step) % 64 == 63):
+            progress(f"blobs {i1}/{n}")
     lods = list(range(level_min, level_max + 1))
     tris = [faces[l] for l in lods]
     par = [parents[l] if i > 0 else np.full(len(faces[l]), -1, np.int32) for i, l in enumerate(lods)]
@@ -403,7 +407,7 @@ def _assemble(per_obj_verts, per_obj_template, templates, n_lods, kind):
                    tb, tc, parent, np.asarray(kind, np.int8))
 
 
-def blob_set(rng, n, box, level_min, level_max, radius_sigma=None, radius=1.0):
+def blob_set(rng, n, box, level_min, level_max, radius_sigma=None, radius=1.0, progress=None):
     """n blobs, centres U(box) then radii then noise (in that draw order)."""
     lo, hi = box
     centres = rng.uniform(lo, hi, size=(n, 3))
@@ -411,17 +415,17 @@ def blob_set(rng, n, box, level_min, level_max, radius_sigma=None, radius=1.0):
         radii = np.full(n, radius)
     else:
         radii = np.exp(rng.normal(0.0, radius_sigma, size=n))
-    v, tris, par = make_blobs(rng, centres, radii, level_min, level_max)
+    v, tris, par = make_blobs(rng, centres, radii, level_min, level_max, progress=progress)
     L = level_max - level_min + 1
     templ = {("ico", level_min, level_max): (tris, par)}
     return _assemble(v, [("ico", level_min, level_max)] * n, templ, L, np.zeros(n))
 
 
-def tube_set(rng, n, box, n_seg, n_lods, length_range=(20.0, 80.0), radius=1.0):
+def tube_set(rng, n, box, n_seg, n_lods, length_range=(20.0, 80.0), radius=1.0, progress=None):
     """n tubes, centres U(box) then tube shape draws."""
     lo, hi = box
     centres = rng.uniform(lo, hi, size=(n, 3))
-    v, segs = make_tubes(rng, centres, n_seg, n_lods, length_range, radius)
+    v, segs = make_tubes(rng, centres, n_seg, n_lods, length_range, radius, progress=progress)
     tl, pl = tube_template(n_seg, n_lods)
     templ = {("tube", n_seg, n_lods): (tl, pl)}
     return _assemble(v, [("tube", n_seg, n_lods)] * n, templ, n_lods, np.ones(n))
@@ -484,13 +488,13 @@ def config_small(seed: int = 0, n_r: int = 100, n_s: int = 100, box=15.0):
     return R, S
 
 
-def config_multilod(seed: int = 1, n_r: int = 10000, n_s: int = 2000, box=500.0, n_seg=1280):
+def config_multilod(seed: int = 1, n_r: int = 10000, n_s: int = 2000, box=500.0, n_seg=1280, progress=None):
     """Multi-LoD join: R = blobs with LoDs at icosphere levels 1..4
     (80/320/1280/5120 triangles), radius lognormal(0, 0.3); S = tubes of
     length U(20, 80), radius 1, 4 LoDs decimated 4x per level (finest n_seg
     segments, 16*n_seg+16 triangles).  Centres U([0, box]^3)."""
-    R = blob_set(rng_for(seed, 0), n_r, (0.0, box), 1, 4, radius_sigma=0.3)
-    S = tube_set(rng_for(seed, 1), n_s, (0.0, box), n_seg, 4)
+    R = blob_set(rng_for(seed, 0), n_r, (0.0, box), 1, 4, radius_sigma=0.3, progress=progress)
+    S = tube_set(rng_for(seed, 1), n_s, (0.0, box), n_seg, 4, progress=progress)
     return R, S
 
 
@@ -550,16 +554,18 @@ def config_knn(seed: int = 2, n_r: int = 20000, n_s: int = 20000, n_clusters: in
     return out[0], out[1]
 
 
-def config_learned(seed: int = 4, n_r: int = 100000, n_s: int = 20000, box: float = 5000.0, n_seg: int = 1280):
+def config_learned(seed: int = 4, n_r: int = 100000, n_s: int = 20000, box: float = 5000.0, n_seg: int = 1280,
+                   progress=None):
     """Learned-skip workload: the multi-LoD object shapes at 10x the counts in
     a 5000^3 box, joined within tau = 10."""
-    return config_multilod(seed=seed, n_r=n_r, n_s=n_s, box=box, n_seg=n_seg)
+    return config_multilod(seed=seed, n_r=n_r, n_s=n_s, box=box, n_seg=n_seg, progress=progress)
 
 
-def config_large(seed: int = 5, n_r: int = 1000000, n_s: int = 200000, box: float = 20000.0, n_seg: int = 1280):
+def config_large(seed: int = 5, n_r: int = 1000000, n_s: int = 200000, box: float = 20000.0, n_seg: int = 1280,
+                 progress=None):
     """Large intersection workload: 1M blobs (80..5120 triangles) and 200k
     tubes (336..20,496 triangles) in a 20000^3 box, joined at tau = 0."""
-    return config_multilod(seed=seed, n_r=n_r, n_s=n_s, box=box, n_seg=n_seg)
+    return config_multilod(seed=seed, n_r=n_r, n_s=n_s, box=box, n_seg=n_seg, progress=progress)
 
 
 CONFIGS = {
