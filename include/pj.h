@@ -71,6 +71,8 @@ typedef struct {
                                 an explicit tile_s / waves_per_cu always wins */
     int32_t mesh_residency;  /* pj_residency of mesh sets created on this context */
     int32_t stage_sets;      /* staging buffer sets for streamed chunks, 2 or 3 (0: 2) */
+    int32_t filter_mode;     /* MBB filter: 0 auto (x sweep when |R|*|S| > 2^26), 1 all pairs, 2 x sweep */
+    int32_t reserved0;       /* must be 0 */
     int64_t mem_cap_bytes;   /* device-memory budget for join work buffers (0: no cap) */
     const char *model_path;  /* LoD model weights written by pj_train_lod_model (NULL: none) */
     const char *log_path;    /* append per-pair resolution records here (NULL: no log) */

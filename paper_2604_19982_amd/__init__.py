@@ -32,6 +32,7 @@ class Config(ctypes.Structure):
                 ("tile_cull", ctypes.c_int32), ("tile_s", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
                 ("host_threads", ctypes.c_int32), ("chunk_tiles", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("mesh_residency", ctypes.c_int32), ("stage_sets", ctypes.c_int32),
+                ("filter_mode", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("mem_cap_bytes", ctypes.c_int64),
                 ("model_path", ctypes.c_char_p), ("log_path", ctypes.c_char_p), ("autotune_path", ctypes.c_char_p),
                 ("stream", ctypes.c_void_p)]
@@ -183,7 +184,7 @@ class Context:
     def __init__(self, device=0, precision="fp32", schedule="batched", learned_skip=False, want_dist=False,
                  use_graph=True, tile_cull=True, tile_s=0, waves_per_cu=0, mem_cap_bytes=0, model_path=None,
                  log_path=None, stream=None, chunk_tiles=0, autotune=False, autotune_path=None,
-                 host_resident=False, stage_sets=0):
+                 host_resident=False, stage_sets=0, filter_mode="auto"):
         L = lib()
         c = Config()
         L.pj_config_default(ctypes.byref(c))
@@ -201,6 +202,7 @@ class Context:
         c.autotune = int(bool(autotune))
         c.mesh_residency = 1 if host_resident else 0
         c.stage_sets = int(stage_sets)
+        c.filter_mode = {"auto": 0, "pairs": 1, "sweep": 2}[filter_mode]
         self._paths = [None if p is None else os.fsencode(p) for p in (model_path, log_path, autotune_path)]
         c.model_path, c.log_path, c.autotune_path = self._paths
         c.stream = stream

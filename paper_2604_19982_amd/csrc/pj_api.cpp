@@ -72,8 +72,12 @@ struct pj_meshes {
     std::vector<int32_t> h_tcnt, h_vcnt;
     std::vector<float> h_box, h_anchor;
     std::vector<float2> h_lodmax;
+    // x-sorted copy of the boxes for the sweep filter
+    int32_t *d_xord = nullptr;
+    float *d_xbox = nullptr, *d_xanc = nullptr, *d_xmin = nullptr;
+    double max_w = 0.0, max_abs = 0.0;
     // host-resident sets: facet data in host memory (the device holds only
-    // d_box, d_anchor and d_lodmax)
+    // d_box, d_anchor, d_lodmax and the sorted boxes)
     bool host = false;
     std::vector<float> h_verts;
     std::vector<int32_t> h_tris;
@@ -246,7 +250,8 @@ extern "C" pj_status pj_context_create(const pj_config *cfg, pj_context **out)
         if (colon != std::string::npos) ctx->arch.resize(colon);
     }
     if (ctx->arch.empty()) ctx->arch = "gpu";
-    if (c.chunk_tiles < 0 || (c.mesh_residency != PJ_RESIDENT_DEVICE && c.mesh_residency != PJ_RESIDENT_HOST) ||
+    if (c.chunk_tiles < 0 || c.filter_mode < 0 || c.filter_mode > 2 || c.reserved0 != 0 ||
+        (c.mesh_residency != PJ_RESIDENT_DEVICE && c.mesh_residency != PJ_RESIDENT_HOST) ||
         (c.stage_sets != 0 && c.stage_sets != 2 && c.stage_sets != 3)) {
         delete ctx;
         return PJ_ERR_INVALID_ARG;
@@ -313,7 +318,8 @@ void free_meshes(pj_meshes *m)
     if (!m) return;
     for (void *p : {(void *)m->d_verts, (void *)m->d_tris, (void *)m->d_vbeg, (void *)m->d_tbeg, (void *)m->d_hpbeg,
                     (void *)m->d_tcnt, (void *)m->d_hdph, (void *)m->d_box, (void *)m->d_anchor,
-                    (void *)m->d_lodmax, (void *)m->d_bkbeg, (void *)m->d_blk})
+                    (void *)m->d_lodmax, (void *)m->d_bkbeg, (void *)m->d_blk, (void *)m->d_xord, (void *)m->d_xbox,
+                    (void *)m->d_xanc, (void *)m->d_xmin})
         if (p) (void)hipFree(p);
     delete m;
 }
@@ -694,6 +700,40 @@ pj_status ingest_host(pj_context *ctx, const pj_mesh_desc *d, pj_meshes *m)
     return PJ_OK;
 }
 
+// Boxes sorted by xmin (ties by id) for the sweep filter, with their anchors
+// and ids, plus the widest box and the largest coordinate magnitude.
+pj_status sort_boxes(pj_context *ctx, pj_meshes *m)
+{
+    const int64_t n = m->n;
+    if (n == 0) return PJ_OK;
+    std::vector<int32_t> ord(n);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
+        const float xa = m->h_box[6 * (int64_t)a], xb = m->h_box[6 * (int64_t)b];
+        return xa < xb || (xa == xb && a < b);
+    });
+    std::vector<float> xb(6 * n), xa(3 * n), xm(n);
+    double mw = 0.0, ma = 0.0;
+    for (int64_t k = 0; k < n; ++k) {
+        const float *b = &m->h_box[6 * (int64_t)ord[k]];
+        std::copy(b, b + 6, &xb[6 * k]);
+        std::copy(&m->h_anchor[3 * (int64_t)ord[k]], &m->h_anchor[3 * (int64_t)ord[k]] + 3, &xa[3 * k]);
+        xm[k] = b[0];
+        mw = std::max(mw, (double)b[3] - (double)b[0]);
+        for (int c = 0; c < 6; ++c) ma = std::max(ma, std::fabs((double)b[c]));
+    }
+    m->max_w = mw;
+    m->max_abs = ma;
+    hipStream_t st = ctx->stream;
+    hipError_t e;
+    if ((e = upload(&m->d_xord, ord.data(), n, st)) != hipSuccess) return hipfail(ctx, e, "sorted ids");
+    if ((e = upload(&m->d_xbox, xb.data(), 6 * n, st)) != hipSuccess) return hipfail(ctx, e, "sorted boxes");
+    if ((e = upload(&m->d_xanc, xa.data(), 3 * n, st)) != hipSuccess) return hipfail(ctx, e, "sorted anchors");
+    if ((e = upload(&m->d_xmin, xm.data(), n, st)) != hipSuccess) return hipfail(ctx, e, "sorted xmin");
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hipfail(ctx, e, "sort sync");
+    return PJ_OK;
+}
+
 extern "C" pj_status pj_meshes_create(pj_context *ctx, const pj_mesh_desc *d, pj_meshes **out)
 {
     if (!ctx || !d || !out) return fail(ctx, PJ_ERR_INVALID_ARG, "NULL argument");
@@ -702,8 +742,8 @@ extern "C" pj_status pj_meshes_create(pj_context *ctx, const pj_mesh_desc *d, pj
     PJTRY(validate_desc(ctx, d));
     HIPTRY(ctx, hipSetDevice(ctx->cfg.device));
     pj_meshes *m = new pj_meshes();
-    const pj_status s =
-        ctx->cfg.mesh_residency == PJ_RESIDENT_HOST ? ingest_host(ctx, d, m) : ingest_device(ctx, d, m);
+    pj_status s = ctx->cfg.mesh_residency == PJ_RESIDENT_HOST ? ingest_host(ctx, d, m) : ingest_device(ctx, d, m);
+    if (s == PJ_OK) s = sort_boxes(ctx, m);
     if (s != PJ_OK) {
         free_meshes(m);
         return s;
@@ -1765,16 +1805,66 @@ pj_status check_pair_args(pj_context *ctx, const pj_meshes *R, const pj_meshes *
     return PJ_OK;
 }
 
+// Sweep filter: same candidates and bounds as the all-pairs test (order:
+// R by xmin, then S by xmin).  The window around each r is widened by the
+// widest S box and by relative margins that cover every rounding in the
+// FP32 gap test, so each s the all-pairs test keeps lies inside it.
+pj_status mbb_filter_sweep(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, float tau2,
+                           std::vector<Cand> &cand)
+{
+    hipStream_t st = ctx->stream;
+    const int nR = R->n, nS = S->n;
+    const double T = std::sqrt((double)tau2) * (1.0 + std::ldexp(1.0, -20));
+    const double cmax = std::max(R->max_abs, S->max_abs) + T;
+    const float w_hi = up_float(T * (1.0 + std::ldexp(1.0, -20)) + std::ldexp(cmax, -20));
+    const float w_lo = up_float((double)w_hi + S->max_w * (1.0 + std::ldexp(1.0, -20)) + std::ldexp(cmax, -20));
+    const int nb = (nR + 255) / 256;
+    PJTRY(ensure(ctx, ctx->b_blk, nb * sizeof(int32_t)));
+    PJTRY(ensure(ctx, ctx->b_blkoff, (nb + 1) * sizeof(int64_t)));
+    PJTRY(ensure(ctx, ctx->b_total, 16));
+    HIPTRY(ctx, launch_filter_sweep(R->d_box, R->d_anchor, R->d_xord, nR, S->d_xbox, S->d_xanc, S->d_xord, S->d_xmin,
+                                    nS, tau2, w_lo, w_hi, ptr<int32_t>(ctx->b_blk), nullptr, nullptr, nullptr,
+                                    nullptr, nullptr, 0, st));
+    HIPTRY(ctx, launch_scan_i32_to_i64(ptr<int32_t>(ctx->b_blk), ptr<int64_t>(ctx->b_blkoff), ptr<int64_t>(ctx->b_total),
+                                       nb, st));
+    int64_t total = 0;
+    HIPTRY(ctx, hipMemcpyAsync(&total, ctx->b_total.p, 8, hipMemcpyDeviceToHost, st));
+    HIPTRY(ctx, hipStreamSynchronize(st));
+    if (total == 0) return PJ_OK;
+    if (total > INT32_MAX) return fail(ctx, PJ_ERR_UNSUPPORTED, "more than 2^31 candidate pairs");
+    PJTRY(ensure(ctx, ctx->b_cand_r, total * 4));
+    PJTRY(ensure(ctx, ctx->b_cand_s, total * 4));
+    PJTRY(ensure(ctx, ctx->b_cand_lb, total * 4));
+    PJTRY(ensure(ctx, ctx->b_cand_ub, total * 4));
+    HIPTRY(ctx, launch_filter_sweep(R->d_box, R->d_anchor, R->d_xord, nR, S->d_xbox, S->d_xanc, S->d_xord, S->d_xmin,
+                                    nS, tau2, w_lo, w_hi, ptr<int32_t>(ctx->b_blk), ptr<int64_t>(ctx->b_blkoff),
+                                    ptr<int32_t>(ctx->b_cand_r), ptr<int32_t>(ctx->b_cand_s),
+                                    ptr<float>(ctx->b_cand_lb), ptr<float>(ctx->b_cand_ub), 1, st));
+    std::vector<int32_t> cr(total), cs(total);
+    std::vector<float> lb(total), ub(total);
+    HIPTRY(ctx, hipMemcpyAsync(cr.data(), ctx->b_cand_r.p, total * 4, hipMemcpyDeviceToHost, st));
+    HIPTRY(ctx, hipMemcpyAsync(cs.data(), ctx->b_cand_s.p, total * 4, hipMemcpyDeviceToHost, st));
+    HIPTRY(ctx, hipMemcpyAsync(lb.data(), ctx->b_cand_lb.p, total * 4, hipMemcpyDeviceToHost, st));
+    HIPTRY(ctx, hipMemcpyAsync(ub.data(), ctx->b_cand_ub.p, total * 4, hipMemcpyDeviceToHost, st));
+    HIPTRY(ctx, hipStreamSynchronize(st));
+    cand.resize(total);
+    for (int64_t i = 0; i < total; ++i) cand[i] = Cand{cr[i], cs[i], lb[i], ub[i]};
+    return PJ_OK;
+}
+
 // MBB filter on the device: candidates with box gap <= tau.
 pj_status mbb_filter(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, double tau, std::vector<Cand> &cand)
 {
     cand.clear();
     hipStream_t st = ctx->stream;
     const int nR = R->n, nS = S->n;
-    const int gx = (nR + 255) / 256, gy = (nS + 511) / 512;
-    const int nb = gx * gy;
     double t2 = tau * (1.0 + std::ldexp(1.0, -20));
     float tau2 = up_float(t2 * t2);
+    const bool sweep = ctx->cfg.filter_mode == 2 ||
+                       (ctx->cfg.filter_mode == 0 && (double)nR * (double)nS > (double)(int64_t(1) << 26));
+    if (sweep) return mbb_filter_sweep(ctx, R, S, tau2, cand);
+    const int gx = (nR + 255) / 256, gy = (nS + 511) / 512;
+    const int nb = gx * gy;
     PJTRY(ensure(ctx, ctx->b_blk, nb * sizeof(int32_t)));
     PJTRY(ensure(ctx, ctx->b_blkoff, (nb + 1) * sizeof(int64_t)));
     PJTRY(ensure(ctx, ctx->b_total, 16));

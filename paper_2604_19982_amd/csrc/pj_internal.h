@@ -96,6 +96,10 @@ hipError_t launch_blocks(const MeshDev &m, float4 *blk, const int64_t *blk_off, 
 hipError_t launch_filter(const float *boxR, const float *ancR, int nR, const float *boxS, const float *ancS, int nS,
                          float tau, int32_t *blk_count, int64_t *blk_off, int64_t *total, int32_t *cr, int32_t *cs,
                          float *clb, float *cub, int write_pass, hipStream_t st);
+hipError_t launch_filter_sweep(const float *boxR, const float *ancR, const int32_t *rord, int nR, const float *sbox,
+                               const float *sanc, const int32_t *sid, const float *sxs, int nS, float tau2,
+                               float w_lo, float w_hi, int32_t *blk_count, const int64_t *blk_off, int32_t *cr,
+                               int32_t *cs, float *clb, float *cub, int write_pass, hipStream_t st);
 hipError_t launch_scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t *total, int n, hipStream_t st);
 hipError_t launch_init_out(ItemOut *out, int n, int32_t *counter, hipStream_t st);
 hipError_t launch_init_out64(ItemOut64 *out, int n, hipStream_t st);

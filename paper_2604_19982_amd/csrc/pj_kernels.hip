@@ -392,6 +392,103 @@ hipError_t launch_filter(const float *boxR, const float *ancR, int nR, const flo
     return hipGetLastError();
 }
 
+// MBB filter by an x sweep (large sets).  S is held sorted by box xmin
+// (boxes and anchors in that order, with the original ids); R is visited in
+// its own x order so that neighbouring threads search overlapping windows.
+// Thread t takes r = rord[t] and scans the S boxes whose xmin lies in
+// [r.xmin - w_lo, r.xmax + w_hi]; the window is widened so that every s the
+// all-pairs test would keep is inside it, and each s in it gets exactly that
+// test.  Count pass -> block totals; write pass -> block scan + positions.
+__device__ __forceinline__ int lower_bound_f(const float *xs, int n, float v)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (xs[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_filter_sweep(const float *boxR, const float *ancR, const int32_t *rord,
+                                                      int nR, const float *sbox, const float *sanc,
+                                                      const int32_t *sid, const float *sxs, int nS, float tau2,
+                                                      float w_lo, float w_hi, int32_t *blk_count,
+                                                      const int64_t *blk_off, int32_t *cr, int32_t *cs, float *clb,
+                                                      float *cub, int write_pass)
+{
+    __shared__ int scnt[256];
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    int r = -1;
+    float b[6] = {kInf, kInf, kInf, -kInf, -kInf, -kInf};
+    int j0 = 0, j1 = 0;
+    if (t < nR) {
+        r = rord[t];
+        for (int c = 0; c < 6; ++c) b[c] = boxR[6 * (int64_t)r + c];
+        j0 = lower_bound_f(sxs, nS, b[0] - w_lo);
+        j1 = lower_bound_f(sxs, nS, b[3] + w_hi);
+        // xs[j1] >= b[3] + w_hi: include equal keys at the upper end
+        while (j1 < nS && sxs[j1] <= b[3] + w_hi) ++j1;
+    }
+    int count = 0;
+    for (int j = j0; j < j1; ++j) {
+        const float *x = sbox + 6 * (int64_t)j;
+        float gx = fmaxf(0.0f, fmaxf(x[0] - b[3], b[0] - x[3]));
+        float gy = fmaxf(0.0f, fmaxf(x[1] - b[4], b[1] - x[4]));
+        float gz = fmaxf(0.0f, fmaxf(x[2] - b[5], b[2] - x[5]));
+        float g2 = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
+        count += (g2 <= tau2) ? 1 : 0;
+    }
+    if (!write_pass) {
+        scnt[threadIdx.x] = count;
+        __syncthreads();
+        for (int st = 128; st > 0; st >>= 1) {
+            if (threadIdx.x < st) scnt[threadIdx.x] += scnt[threadIdx.x + st];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) blk_count[blockIdx.x] = scnt[0];
+        return;
+    }
+    scnt[threadIdx.x] = count;
+    __syncthreads();
+    for (int st = 1; st < 256; st <<= 1) {
+        int add = threadIdx.x >= st ? scnt[threadIdx.x - st] : 0;
+        __syncthreads();
+        scnt[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int64_t pos = blk_off[blockIdx.x] + scnt[threadIdx.x] - count;
+    if (count == 0) return;
+    const float ax = ancR[3 * (int64_t)r], ay = ancR[3 * (int64_t)r + 1], az = ancR[3 * (int64_t)r + 2];
+    for (int j = j0; j < j1; ++j) {
+        const float *x = sbox + 6 * (int64_t)j;
+        float gx = fmaxf(0.0f, fmaxf(x[0] - b[3], b[0] - x[3]));
+        float gy = fmaxf(0.0f, fmaxf(x[1] - b[4], b[1] - x[4]));
+        float gz = fmaxf(0.0f, fmaxf(x[2] - b[5], b[2] - x[5]));
+        float g2 = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
+        if (g2 <= tau2) {
+            const float *y = sanc + 3 * (int64_t)j;
+            float dx = y[0] - ax, dy = y[1] - ay, dz = y[2] - az;
+            cr[pos] = r;
+            cs[pos] = sid[j];
+            clb[pos] = __builtin_sqrtf(g2) * (1.0f - 0x1p-20f);
+            cub[pos] = __builtin_sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx))) * (1.0f + 0x1p-20f);
+            ++pos;
+        }
+    }
+}
+
+hipError_t launch_filter_sweep(const float *boxR, const float *ancR, const int32_t *rord, int nR, const float *sbox,
+                               const float *sanc, const int32_t *sid, const float *sxs, int nS, float tau2,
+                               float w_lo, float w_hi, int32_t *blk_count, const int64_t *blk_off, int32_t *cr,
+                               int32_t *cs, float *clb, float *cub, int write_pass, hipStream_t st)
+{
+    if (nR == 0 || nS == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_filter_sweep, dim3((nR + 255) / 256), dim3(256), 0, st, boxR, ancR, rord, nR, sbox, sanc,
+                       sid, sxs, nS, tau2, w_lo, w_hi, blk_count, blk_off, cr, cs, clb, cub, write_pass);
+    return hipGetLastError();
+}
+
 // single-workgroup exclusive scan of int32 counts into int64 offsets
 __global__ __launch_bounds__(1024) void k_scan(const int32_t *in, int64_t *out, int64_t *total, int n)
 {

@@ -37,7 +37,7 @@ def test_config_default_is_host_only():
 
 def test_struct_sizes_match_header_layout():
     import paper_2604_19982_amd as pj
-    assert ctypes.sizeof(pj.Config) == 4 * 14 + 8 + 8 * 4
+    assert ctypes.sizeof(pj.Config) == 4 * 16 + 8 + 8 * 4
     assert ctypes.sizeof(pj.MeshDesc) == 8 + 8 + 8 + 8 * 10
     assert ctypes.sizeof(pj.Pairs) == 32
     assert ctypes.sizeof(pj.Stats) == 7 * 8 + 8 * 8 + 8 * 8 + 16 + 4 * 8 + 8 + 8 + 4 * 64 + 24

@@ -213,3 +213,41 @@ def test_host_resident_pair_bounds(pj, mid):
         b = h.pair_bounds(hR, hS, rr, ss, lod)
         for x, y in zip(a, b):
             assert np.array_equal(x, y), lod
+
+
+# ---------------------------------------------------------------------------
+# MBB filter: x sweep against all pairs
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("tau", [0.0, 5.0, 20.0, 400.0])
+def test_sweep_filter_matches_all_pairs(pj, mid, tau):
+    R, S = mid
+    out = {}
+    for mode in ("pairs", "sweep"):
+        c = pj.Context(filter_mode=mode)
+        res = c.join_within(c.meshes(R), c.meshes(S), tau)
+        out[mode] = (res, c.stats())
+    a, b = out["pairs"][0], out["sweep"][0]
+    assert np.array_equal(a["r"], b["r"]) and np.array_equal(a["s"], b["s"])
+    assert out["pairs"][1]["candidates"] == out["sweep"][1]["candidates"] > 0
+    assert out["pairs"][1]["confirmed_filter"] == out["sweep"][1]["confirmed_filter"]
+
+
+def test_sweep_filter_ties_and_edges(orc, pj):
+    # many boxes with equal xmin (a lattice in y and z), touching boxes, empty sides
+    A = mg.objects([mg.cube_mesh([0, y, z], [1, y + 1, z + 1]) for y in range(4) for z in range(4)])
+    B = mg.objects([mg.cube_mesh([1, y + 0.5, z], [2, y + 1.5, z + 1]) for y in range(4) for z in range(3)]
+                   + [mg.cube_mesh([1.25, 0, 0], [2, 1, 1]), mg.cube_mesh([-3, 0, 0], [-1.0, 1, 1])])
+    ref = orc.join_within(orc.OSet(A), orc.OSet(B), 0.0)
+    for tau in (0.0, 0.25, 1.0, 3.0):
+        got = {}
+        for mode in ("pairs", "sweep"):
+            c = pj.Context(filter_mode=mode)
+            r = c.join_within(c.meshes(A), c.meshes(B), tau)
+            got[mode] = set(zip(r["r"].tolist(), r["s"].tolist()))
+        assert got["pairs"] == got["sweep"], tau
+        if tau == 0.0:
+            assert got["sweep"] == set(zip(ref["r"].tolist(), ref["s"].tolist()))
+    c = pj.Context(filter_mode="sweep")
+    gA, gE = c.meshes(A), c.meshes(A.subset([]))
+    assert len(c.join_within(gA, gE, 1.0)["r"]) == 0
+    assert len(c.join_within(gE, gA, 1.0)["r"]) == 0
