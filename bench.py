@@ -57,13 +57,18 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_step(ctx, gR, gS, taus, verbose=False):
+def run_step(ctx, gR, gS, taus, verbose=False, k=None):
+    """One pass of the hot path: a within-tau join per tau, or one k-NN join."""
     tot = dict(pairs=0, pairs64=0, pairsc=0, kms=0.0, launches=0, results=0, band=0, ms=0.0, kms64=0.0)
-    for tau in taus:
-        res = ctx.join_within(gR, gS, tau)
+    for tau in (taus if k is None else [None]):
+        if k is None:
+            res = ctx.join_within(gR, gS, tau)
+        else:
+            kn = ctx.join_knn(gR, gS, k)
+            res = {"r": kn["s"][kn["s"] >= 0]}
         st = ctx.stats()
         if verbose:
-            log(f"  tau={tau}: {st['t_total_ms']:.1f} ms (filter {st['t_filter_ms']:.1f}, refine {st['t_refine_ms']:.1f}, "
+            log(f"  {'tau=' + str(tau) if k is None else 'k=' + str(k)}: {st['t_total_ms']:.1f} ms (filter {st['t_filter_ms']:.1f}, refine {st['t_refine_ms']:.1f}, "
                 f"band {st['t_band_ms']:.1f}), kernel {st['refine_kernel_ms']:.1f} ms, cand {st['candidates']}, "
                 f"pairs {st['facet_pairs']:.3e}+{st['facet_pairs_fp64']:.3e}, band {st['band_pairs']}, "
                 f"resolved/lod {st['resolved_at_lod'][:4]}, results {len(res['r'])}")
@@ -97,14 +102,14 @@ def train_model(pj, mg, stream, workdir):
     return model, loss, os.path.getsize(log) // 72
 
 
-def one_step(pj, stream, gR, gS, taus, **cfg):
+def one_step(pj, stream, gR, gS, taus, k=None, **cfg):
     """One step on another context over the already ingested mesh sets (a
     mesh set may be shared by contexts on its device)."""
     import torch
     c = pj.Context(stream=stream.cuda_stream, **cfg)
     torch.cuda.synchronize()
     ts = time.time()
-    tot = run_step(c, gR, gS, taus)
+    tot = run_step(c, gR, gS, taus, k=k)
     torch.cuda.synchronize()
     tot["ms"] = (time.time() - ts) * 1e3
     return tot
@@ -173,6 +178,9 @@ WORKLOADS = {
     "learned": dict(builder="config_learned", taus=(10.0,), ctx={}, cpu_gap=10.0,
                     desc="learned-skip within-tau join: {nr} blobs (80..5120 triangles) x {ns} tubes "
                          "(336..20496 triangles), 5000^3 box, tau = 10"),
+    "knn": dict(builder="config_knn", taus=(), k=3, ctx={}, cpu_gap=5.0,
+                desc="batched k-NN join, k = 3: {nr} x {ns} blob/tube mix (finest 1k..50k triangles, 4 LoDs), "
+                     "50 Gaussian clusters (sigma 30) in a 2000^3 box"),
     "large": dict(builder="config_large", taus=(0.0,), ctx=dict(host_resident=True, mem_cap_bytes=32 << 30),
                   cpu_gap=5.0,
                   desc="large intersection join: {nr} blobs (80..5120 triangles) x {ns} tubes (336..20496 "
@@ -201,6 +209,7 @@ def main():
 
     wl = WORKLOADS[args.workload]
     taus = wl["taus"]
+    kk = wl.get("k")
     size = {}
     if args.n_r:
         size["n_r"] = args.n_r
@@ -230,14 +239,14 @@ def main():
     copy_gbps = ctx.probe_copy(1 << 30)
     log(f"probes: scalar FP32 FMA {fma_tflops:.1f} TFLOP/s, copy {copy_gbps:.0f} GB/s")
     for w in range(args.warmup):
-        run_step(ctx, gR, gS, taus)
+        run_step(ctx, gR, gS, taus, k=kk)
         log(f"warmup step {w} done")
     torch.cuda.synchronize()
     steps = []
     t_start = time.time()
     for k in range(args.steps):
         ts = time.time()
-        tot = run_step(ctx, gR, gS, taus, verbose=True)
+        tot = run_step(ctx, gR, gS, taus, verbose=True, k=kk)
         torch.cuda.synchronize()
         tot["ms"] = (time.time() - ts) * 1e3
         steps.append(tot)
@@ -288,7 +297,7 @@ def main():
     abl = {}
     if args.ablations:
         for name, cfg in (("no_learned_skip", {}), ("no_learned_no_cull", dict(tile_cull=False))):
-            t = one_step(pj, stream, gR, gS, taus, **cfg, **tune, **wl["ctx"])
+            t = one_step(pj, stream, gR, gS, taus, k=kk, **cfg, **tune, **wl["ctx"])
             abl[name] = {"ms": t["ms"], "facet_pairs": t["pairs"] + t["pairsc"] + t["pairs64"], "results": t["results"]}
             if t["kms"] > 0:
                 # the same kernel without culling: every facet pair of every visited item is evaluated
@@ -298,7 +307,7 @@ def main():
                 abl[name]["kernel_frac"] = ach / PEAK_FP32_TFLOPS
             log(f"ablation {name}: {t['ms']:.1f} ms")
     if args.plain:
-        t = one_step(pj, stream, gR, gS, taus, schedule="plain", precision="fp64", **wl["ctx"])
+        t = one_step(pj, stream, gR, gS, taus, k=kk, schedule="plain", precision="fp64", **wl["ctx"])
         abl["plain_gpu_schedule"] = {"ms": t["ms"], "facet_pairs": t["pairs"] + t["pairsc"] + t["pairs64"],
                                      "results": t["results"]}
         log(f"plain schedule step: {t['ms']:.1f} ms")

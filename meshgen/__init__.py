@@ -541,7 +541,7 @@ def mixed_set(rng, centres, n_lods: int = 4, f_median: float = 7071.0, f_sigma: 
 
 
 def config_knn(seed: int = 2, n_r: int = 20000, n_s: int = 20000, n_clusters: int = 50, box: float = 2000.0,
-               sigma: float = 30.0, **kw):
+               sigma: float = 30.0, progress=None, **kw):
     """Clustered k-NN workload: object centres = one of n_clusters centres
     U([0, box]^3) + N(0, sigma^2); objects from ``mixed_set``.  The cluster
     centres come from stream 2, R from stream 0, S from stream 1."""
@@ -551,6 +551,8 @@ def config_knn(seed: int = 2, n_r: int = 20000, n_s: int = 20000, n_clusters: in
         rng = rng_for(seed, stream)
         c = cl[rng.integers(0, n_clusters, size=n)] + rng.normal(0.0, sigma, size=(n, 3))
         out.append(mixed_set(rng, c, **kw))
+        if progress is not None:
+            progress(f"{'RS'[stream]}: {n} objects")
     return out[0], out[1]
 
 
