@@ -39,6 +39,12 @@ __all__ = [
 ]
 
 
+# Large sets are built in blocks (noise values per blob block, tubes per
+# tube block); the arrays do not depend on these sizes.
+BLOB_BLOCK_VALUES = 1 << 22
+TUBE_BLOCK = 4096
+
+
 def rng_for(seed: int, stream: int) -> np.random.Generator:
     """PCG64 stream ``stream`` of experiment seed ``seed``."""
     return np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), int(stream)])))
@@ -276,7 +282,7 @@ def make_tubes(rng, centres, n_seg: int, n_lods: int, length_range=(20.0, 80.0),
     segs = np.full(n, n_seg, np.int64) if n_seg_per_object is None else np.asarray(n_seg_per_object, np.int64)
     per_obj = [None] * n
     # the shapes are fixed by the draws above; build them in blocks of tubes
-    step = 4096
+    step = TUBE_BLOCK
     for c0 in range(0, n, step):
         c1 = min(n, c0 + step)
         _tube_block(per_obj, c0, centres[c0:c1], d0[c0:c1], d1[c0:c1], d2[c0:c1], lengths[c0:c1], segs[c0:c1],
@@ -353,7 +359,7 @@ def make_blobs(rng, centres, radii, level_min: int, level_max: int, noise=(0.9, 
     nv = 10 * 4 ** level_max + 2
     # generated in row blocks (the noise stream is the same as one n x V draw)
     v = np.empty((n, nv, 3), np.float32)
-    step = max(1, (1 << 22) // nv)
+    step = max(1, BLOB_BLOCK_VALUES // nv)
     for i0 in range(0, n, step):
         i1 = min(n, i0 + step)
         noise_v = rng.uniform(noise[0], noise[1], size=(i1 - i0, nv))
