@@ -1522,7 +1522,6 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
         a.items = ptr<Item>(ctx->sb_items[b]);
         a.tiles = ptr<Tile>(ctx->sb_tiles[b]);
         a.ntiles = dctr + 1;
-        a.counter = dctr;
         a.out = ptr<ItemOut>(ctx->sb_out[b]);
         a.pairs_done = reinterpret_cast<unsigned long long *>(dctr + 2);
         a.chunks_culled = reinterpret_cast<unsigned long long *>(dctr + 4);
@@ -1725,13 +1724,13 @@ pj_status exact_finest_view(pj_context *ctx, const MeshDev &Rv, const MeshDev &S
     a.items = ptr<Item>(ctx->b_items);
     a.tiles = ptr<Tile>(ctx->b_tiles);
     a.ntiles = ctr + 1;
-    a.counter = ctr;
+    a.collected_n = reinterpret_cast<unsigned long long *>(ctr + 8);
     a.out = ptr<ItemOut>(ctx->b_out);
     a.pairs_done = reinterpret_cast<unsigned long long *>(ctr + 2);
     a.chunks_culled = reinterpret_cast<unsigned long long *>(ctr + 4);
     a.tau = -1.0f;
     a.cull = ctx->cfg.tile_cull ? 1 : 0;
-    a.collect_cap = (int32_t)std::min<int64_t>(cap, INT32_MAX);
+    a.collect_cap = cap;
     a.collected = ptr<PairRef>(ctx->b_coll);
     a.overflow = ptr<int32_t>(ctx->b_ovf);
     const int grid = (int)std::min<int64_t>(nt, (int64_t)ctx->num_cu * ctx->cur.wpc);
@@ -1744,10 +1743,11 @@ pj_status exact_finest_view(pj_context *ctx, const MeshDev &Rv, const MeshDev &S
     HIPTRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
     ctx->stats.collect_kernel_ms += ms;
     ctx->stats.collect_launches += 1;
-    unsigned long long pairs;
+    unsigned long long pairs, offered;
     std::memcpy(&pairs, host_ctr + 2, 8);
+    std::memcpy(&offered, host_ctr + 8, 8);
     ctx->stats.collect_pairs += (int64_t)pairs;
-    const int64_t ncoll = std::min<int64_t>(host_ctr[0], cap);
+    const int64_t ncoll = (int64_t)std::min<unsigned long long>(offered, (unsigned long long)cap);
     HIPTRY(ctx, hipEventRecord(ctx->ev0, st));
     HIPTRY(ctx, launch_pairs_f64(Rv, Sv, a.items, a.collected, ncoll, ptr<ItemOut64>(ctx->b_out64), st));
     HIPTRY(ctx, hipEventRecord(ctx->ev1, st));
@@ -1777,6 +1777,19 @@ pj_status exact_finest(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
     if (which.empty()) return PJ_OK;
     TilePlan pl;
     plan_tiles(R, S, which, cand, ps, R->L - 1, 1, 64, pick_tile_s(ctx), true, pl);
+    // FP32 minimum pass first: with u the item's FP32 upper distance, the
+    // pair that realises the exact minimum d* has FP32 lower distance
+    // <= d* + eps <= u + 2 eps, so that bound can replace an open threshold
+    // and the collect pass keeps only pairs near the minimum.
+    {
+        std::vector<ItemOut> o32;
+        PJTRY(run_f32(ctx, R, S, pl, -1.0f, false, o32, 0));
+        for (size_t k = 0; k < pl.items.size(); ++k) {
+            Item &it = pl.items[k];
+            const float u = bits_to_float(o32[k].ub);
+            if (std::isfinite(u)) it.thr = std::min(it.thr, up_float((double)u + 2.0 * (double)it.eps));
+        }
+    }
     std::vector<int> redo;
     PJTRY(for_staged(ctx, R, S, pl,
                      [&](TilePlan &sp, const MeshDev &Rv, const MeshDev &Sv, const std::vector<int> &) {

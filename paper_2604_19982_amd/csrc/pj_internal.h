@@ -63,14 +63,14 @@ struct RefineArgs {
     const Item *items;
     const Tile *tiles;
     const int32_t *ntiles;   // device count (fixed-capacity buffers)
-    int32_t *counter;        // [0] collected pairs, [1] ntiles
+    unsigned long long *collected_n;  // collect mode: pairs offered (64-bit, compared with the capacity)
     ItemOut *out;
     unsigned long long *pairs_done;  // facet pairs evaluated (device counter)
     unsigned long long *chunks_culled;
     float tau;               // within-tau threshold for early confirmation; < 0: none
     int32_t early;           // 1: stop an item once it is confirmed
     int32_t cull;            // 1: box-gap test per streamed chunk
-    int32_t collect_cap;     // collect mode: capacity of `collected`
+    long long collect_cap;   // collect mode: capacity of `collected`
     PairRef *collected;      // collect mode: facet pairs with d_lo <= item.thr
     int32_t *overflow;       // collect mode: per item, 1 if its pairs did not fit
 };

@@ -797,8 +797,8 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
                         const int fa = tl.a0 + lane + 64 * p;
                         // the pair realising the minimum has dlo <= d + eps <= ubm + 2 eps
                         if (fa < SA.n && dlo <= fminf(it.thr, ubm + 2.0f * it.eps)) {
-                            const int slot = atomicAdd(a.counter, 1);
-                            if (slot < a.collect_cap)
+                            const unsigned long long slot = atomicAdd(a.collected_n, 1ull);
+                            if (slot < (unsigned long long)a.collect_cap)
                                 a.collected[slot] = PairRef{tl.item, fa, __float_as_int(rb.pad), 0};
                             else a.overflow[tl.item] = 1;
                         }
