@@ -906,7 +906,7 @@ void plan_tiles(const pj_meshes *R, const pj_meshes *S, const std::vector<int> &
 // order independent.  The cache is a text file of lines
 // "<class> <tile_s> <waves_per_cu> <ms>".
 // ---------------------------------------------------------------------------
-constexpr int kTuneTS[] = {256, 512, 1024, 2048, 4096, 8192};
+constexpr int kTuneTS[] = {256, 512, 1024, 2048, 4096, 8192, 16384, 65536};
 constexpr int kTuneWPC[] = {4, 8, 12, 16, 24};
 
 void load_tune_cache(pj_context *ctx)
@@ -1775,21 +1775,28 @@ pj_status exact_finest(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
                        std::vector<PairState> &ps, const std::vector<int> &which)
 {
     if (which.empty()) return PJ_OK;
-    TilePlan pl;
-    plan_tiles(R, S, which, cand, ps, R->L - 1, 1, 64, pick_tile_s(ctx), true, pl);
-    // FP32 minimum pass first: with u the item's FP32 upper distance, the
-    // pair that realises the exact minimum d* has FP32 lower distance
-    // <= d* + eps <= u + 2 eps, so that bound can replace an open threshold
-    // and the collect pass keeps only pairs near the minimum.
-    {
+    const int L = R->L;
+    PJTRY(choose_shape(ctx, R, S, which, cand, ps, L - 1, 1, -1.0f, false));
+    // FP32 minimum pass for candidates with an open threshold: with u the
+    // FP32 upper distance, the pair that realises the exact minimum d* has
+    // FP32 lower distance <= d* + eps <= u + 2 eps, so that bound replaces
+    // the open threshold and the collect pass keeps only pairs near the minimum.
+    std::vector<int> open;
+    for (int i : which)
+        if (!std::isfinite(ps[i].thr)) open.push_back(i);
+    if (!open.empty()) {
+        TilePlan po;
+        plan_tiles(R, S, open, cand, ps, L - 1, 1, 64 * kP, ctx->cur.tile_s, true, po);
         std::vector<ItemOut> o32;
-        PJTRY(run_f32(ctx, R, S, pl, -1.0f, false, o32, 0));
-        for (size_t k = 0; k < pl.items.size(); ++k) {
-            Item &it = pl.items[k];
+        PJTRY(run_f32(ctx, R, S, po, -1.0f, false, o32, 0));
+        for (size_t k = 0; k < po.items.size(); ++k) {
+            PairState &p = ps[po.items[k].cand];
             const float u = bits_to_float(o32[k].ub);
-            if (std::isfinite(u)) it.thr = std::min(it.thr, up_float((double)u + 2.0 * (double)it.eps));
+            if (std::isfinite(u)) p.thr = std::min(p.thr, up_float((double)u + 2.0 * (double)p.eps));
         }
     }
+    TilePlan pl;
+    plan_tiles(R, S, which, cand, ps, L - 1, 1, 64, ctx->cur.tile_s, true, pl);
     std::vector<int> redo;
     PJTRY(for_staged(ctx, R, S, pl,
                      [&](TilePlan &sp, const MeshDev &Rv, const MeshDev &Sv, const std::vector<int> &) {
@@ -2333,7 +2340,10 @@ extern "C" pj_status pj_join_knn(pj_context *ctx, const pj_meshes *R, const pj_m
     const bool plain = ctx->cfg.schedule == PJ_SCHED_PLAIN;
     const bool fp64 = plain || ctx->cfg.precision == PJ_PREC_FP64;
     TilePlan pl;
-    for (int lod = 0; lod + 1 < L; ++lod) {
+    // (FP32 schedule: the finest LoD is a round too; its FP32 minimum u also
+    // bounds the exact recheck's collect threshold, u + 2 eps)
+    for (int lod = 0; lod < (fp64 ? L - 1 : L); ++lod) {
+        const bool fin_round = lod == L - 1;
         std::vector<int> act;
         for (int64_t i = 0; i < total; ++i)
             if (ps[i].status == ST_UNDEC) act.push_back((int)i);
@@ -2350,14 +2360,16 @@ extern "C" pj_status pj_join_knn(pj_context *ctx, const pj_meshes *R, const pj_m
                 p.UB = std::min(p.UB, bits_to_double(o64[q].ub) + e64);
             }
         } else {
-            PJTRY(choose_shape(ctx, R, S, act, cand, ps, lod, 0, -1.0f, false));
-            plan_tiles(R, S, act, cand, ps, lod, 0, 64 * kP, ctx->cur.tile_s, true, pl);
+            PJTRY(choose_shape(ctx, R, S, act, cand, ps, lod, fin_round, -1.0f, false));
+            plan_tiles(R, S, act, cand, ps, lod, fin_round, 64 * kP, ctx->cur.tile_s, true, pl);
             std::vector<ItemOut> o32;
             PJTRY(run_f32(ctx, R, S, pl, -1.0f, false, o32, 0));
             for (size_t q = 0; q < pl.items.size(); ++q) {
                 PairState &p = ps[pl.items[q].cand];
+                const float u = bits_to_float(o32[q].ub);
                 p.LB = std::max(p.LB, (double)bits_to_float(o32[q].lb) - p.eps);
-                p.UB = std::min(p.UB, (double)bits_to_float(o32[q].ub) + p.eps);
+                p.UB = std::min(p.UB, (double)u + p.eps);
+                if (fin_round && std::isfinite(u)) p.thr = std::min(p.thr, up_float((double)u + 2.0 * (double)p.eps));
             }
         }
         PJTRY(knn_prune_round(ctx, nR, k, off, cand, ps));
@@ -2369,10 +2381,7 @@ extern "C" pj_status pj_join_knn(pj_context *ctx, const pj_meshes *R, const pj_m
     const double t2 = now_ms();
     std::vector<int> fin;
     for (int64_t i = 0; i < total; ++i)
-        if (ps[i].status == ST_UNDEC || ps[i].status == ST_CONF) {
-            fin.push_back((int)i);
-            ps[i].thr = INFINITY;
-        }
+        if (ps[i].status == ST_UNDEC || ps[i].status == ST_CONF) fin.push_back((int)i);
     ctx->stats.rounds++;
     if (plain) {
         plan_tiles(R, S, fin, cand, ps, L - 1, 1, 64, TS, false, pl);
