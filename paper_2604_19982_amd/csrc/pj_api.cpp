@@ -901,8 +901,8 @@ void plan_tiles(const pj_meshes *R, const pj_meshes *S, const std::vector<int> &
 // Launch-shape autotuner.  Work is classed by (device, mode, size bucket of
 // the mean facet pairs per item); the first bulk round of a class without a
 // cached shape times every (tile_s, waves_per_cu) candidate on a sample of
-// its items (eager launches, kernel time from events, best of two) and keeps
-// the fastest.  Results never depend on the shape: the per-item minima are
+// its items (eager launches; wall time of planning plus the streamed round,
+// best of two) and keeps the fastest.  Results never depend on the shape: the per-item minima are
 // order independent.  The cache is a text file of lines
 // "<class> <tile_s> <waves_per_cu> <ms>".
 // ---------------------------------------------------------------------------
@@ -980,16 +980,21 @@ pj_status choose_shape(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
         pj_context::Shape bs;
         for (int ts : kTuneTS) {
             if (cfg_ts && ts != cfg_ts) continue;
+            // wall time of planning + the streamed round (host work per tile
+            // counts as much as the kernel when items have many tiles)
+            const double tp = now_ms();
             TilePlan pl;
             plan_tiles(R, S, sample, cand, ps, lod, finest, 64 * kP, ts, true, pl);
+            const double plan_ms = now_ms() - tp;
             for (int wpc : kTuneWPC) {
                 if (cfg_wpc && wpc != cfg_wpc) continue;
                 double t = INFINITY;
                 for (int rep = 0; rep < 2; ++rep) {
-                    ctx->stats.refine_kernel_ms = 0.0;
                     std::vector<ItemOut> out;
+                    HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+                    const double tr = now_ms();
                     PJTRY(run_f32(ctx, R, S, pl, tau, early, out, wpc));
-                    t = std::min(t, ctx->stats.refine_kernel_ms);
+                    t = std::min(t, plan_ms + (now_ms() - tr));
                 }
                 if (t < best) {
                     best = t;
