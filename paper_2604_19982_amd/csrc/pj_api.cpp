@@ -850,7 +850,8 @@ struct TilePlan {
 // padding wastes less; B ranges are split into chunks of tile_s facets.
 // Items are emitted in descending cost order (longest processing time first).
 void plan_tiles(const pj_meshes *R, const pj_meshes *S, const std::vector<int> &act, const std::vector<Cand> &cand,
-                const std::vector<PairState> &ps, int lod, int finest, int BR, int TS, bool allow_swap, TilePlan &pl)
+                const std::vector<PairState> &ps, int lod, int finest, int BR, int TS, bool allow_swap, TilePlan &pl,
+                int64_t target_tiles = 0)
 {
     struct C {
         double cost;
@@ -868,6 +869,18 @@ void plan_tiles(const pj_meshes *R, const pj_meshes *S, const std::vector<int> &
     pl.tiles.clear();
     pl.pairs = 0;
     pl.tile_s = TS;
+    // A blocks per tile: one, or as many as bring the round near the target
+    // tile count (a tile walks its A blocks one after the other)
+    int64_t ga = 1;
+    if (target_tiles > 0) {
+        int64_t n1 = 0;
+        for (const C &oc : order) {
+            const Cand &c = cand[act[oc.idx]];
+            const int64_t nr = R->count(c.r, lod), ns = S->count(c.s, lod);
+            n1 += std::max<int64_t>((std::min(nr, ns) + BR - 1) / BR, 1) * ((std::max(nr, ns) + TS - 1) / TS);
+        }
+        ga = std::max<int64_t>(1, n1 / target_tiles);
+    }
     for (const C &oc : order) {
         const int ci = act[oc.idx];
         const Cand &c = cand[ci];
@@ -891,11 +904,19 @@ void plan_tiles(const pj_meshes *R, const pj_meshes *S, const std::vector<int> &
         const int item = (int)pl.items.size();
         pl.items.push_back(it);
         const int nA = swap ? ns : nr, nB = swap ? nr : ns;
-        for (int a0 = 0; a0 < nA; a0 += BR)
-            for (int b0 = 0; b0 < nB; b0 += TS) pl.tiles.push_back(Tile{item, a0, b0, std::min(nB, b0 + TS)});
+        const int64_t astep = (int64_t)BR * ga;
+        for (int64_t a0 = 0; a0 < nA; a0 += astep) {
+            const int a1 = (int)std::min<int64_t>(nA, a0 + astep);
+            for (int b0 = 0; b0 < nB; b0 += TS)
+                pl.tiles.push_back(Tile{item, (int)a0, b0, std::min(nB, b0 + TS), a1, 0, 0, 0});
+        }
         pl.pairs += (int64_t)nA * nB;
     }
 }
+
+// Tiles per bulk round to aim for: 16 per resident wave keeps the
+// longest-first order balanced while bounding per-tile host work.
+int64_t tile_target(const pj_context *ctx, int wpc) { return (int64_t)ctx->num_cu * wpc * 16; }
 
 // ---------------------------------------------------------------------------
 // Launch-shape autotuner.  Work is classed by (device, mode, size bucket of
@@ -984,7 +1005,7 @@ pj_status choose_shape(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
             // counts as much as the kernel when items have many tiles)
             const double tp = now_ms();
             TilePlan pl;
-            plan_tiles(R, S, sample, cand, ps, lod, finest, 64 * kP, ts, true, pl);
+            plan_tiles(R, S, sample, cand, ps, lod, finest, 64 * kP, ts, true, pl, tile_target(ctx, 12));
             const double plan_ms = now_ms() - tp;
             for (int wpc : kTuneWPC) {
                 if (cfg_wpc && wpc != cfg_wpc) continue;
@@ -1791,7 +1812,7 @@ pj_status exact_finest(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
         if (!std::isfinite(ps[i].thr)) open.push_back(i);
     if (!open.empty()) {
         TilePlan po;
-        plan_tiles(R, S, open, cand, ps, L - 1, 1, 64 * kP, ctx->cur.tile_s, true, po);
+        plan_tiles(R, S, open, cand, ps, L - 1, 1, 64 * kP, ctx->cur.tile_s, true, po, tile_target(ctx, ctx->cur.wpc));
         std::vector<ItemOut> o32;
         PJTRY(run_f32(ctx, R, S, po, -1.0f, false, o32, 0));
         for (size_t k = 0; k < po.items.size(); ++k) {
@@ -1801,7 +1822,7 @@ pj_status exact_finest(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
         }
     }
     TilePlan pl;
-    plan_tiles(R, S, which, cand, ps, L - 1, 1, 64, ctx->cur.tile_s, true, pl);
+    plan_tiles(R, S, which, cand, ps, L - 1, 1, 64, ctx->cur.tile_s, true, pl, tile_target(ctx, ctx->cur.wpc));
     std::vector<int> redo;
     PJTRY(for_staged(ctx, R, S, pl,
                      [&](TilePlan &sp, const MeshDev &Rv, const MeshDev &Sv, const std::vector<int> &) {
@@ -1986,7 +2007,8 @@ pj_status refine_within(pj_context *ctx, const pj_meshes *R, const pj_meshes *S,
             }
         } else {
             PJTRY(choose_shape(ctx, R, S, act, cand, ps, lod, finest, (float)tau, true));
-            plan_tiles(R, S, act, cand, ps, lod, finest, 64 * kP, ctx->cur.tile_s, true, pl);
+            plan_tiles(R, S, act, cand, ps, lod, finest, 64 * kP, ctx->cur.tile_s, true, pl,
+                       tile_target(ctx, ctx->cur.wpc));
             std::vector<ItemOut> out;
             PJTRY(run_f32(ctx, R, S, pl, (float)tau, true, out, 0));
             for (size_t k = 0; k < pl.items.size(); ++k) {
@@ -2366,7 +2388,8 @@ extern "C" pj_status pj_join_knn(pj_context *ctx, const pj_meshes *R, const pj_m
             }
         } else {
             PJTRY(choose_shape(ctx, R, S, act, cand, ps, lod, fin_round, -1.0f, false));
-            plan_tiles(R, S, act, cand, ps, lod, fin_round, 64 * kP, ctx->cur.tile_s, true, pl);
+            plan_tiles(R, S, act, cand, ps, lod, fin_round, 64 * kP, ctx->cur.tile_s, true, pl,
+                       tile_target(ctx, ctx->cur.wpc));
             std::vector<ItemOut> o32;
             PJTRY(run_f32(ctx, R, S, pl, -1.0f, false, o32, 0));
             for (size_t q = 0; q < pl.items.size(); ++q) {
@@ -2512,7 +2535,8 @@ extern "C" pj_status pj_pair_bounds(pj_context *ctx, const pj_meshes *R, const p
             hit[c] = (int8_t)out[k].hit;
         }
     } else {
-        plan_tiles(R, S, act, cand, ps, lod, finest, 64 * kP, pick_tile_s(ctx), true, pl);
+        plan_tiles(R, S, act, cand, ps, lod, finest, 64 * kP, pick_tile_s(ctx), true, pl,
+                   tile_target(ctx, ctx->cur.wpc));
         std::vector<ItemOut> out;
         PJTRY(run_f32(ctx, R, S, pl, -1.0f, false, out, 0));
         for (size_t k = 0; k < pl.items.size(); ++k) {

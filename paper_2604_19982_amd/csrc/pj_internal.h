@@ -38,7 +38,8 @@ static_assert(sizeof(Item) == 48, "item layout");
 enum : int32_t { IT_SWAP = 1, IT_FINEST = 2 };
 
 struct Tile {
-    int32_t item, a0, b0, b1;  // A facets [a0, a0 + 64P), B facets [b0, b1)
+    int32_t item, a0, b0, b1;    // A facets from a0, B facets [b0, b1)
+    int32_t a1, pad0, pad1, pad2;  // A facets [a0, a1), walked in blocks of 64P
 };
 
 // FP32 results of an item: atomically reduced bit patterns of non-negative floats.

@@ -667,177 +667,182 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
     const FacetSrc SA = facet_src(swap ? a.S : a.R, it.a_obj, it.lod);
     const FacetSrc SB = facet_src(swap ? a.R : a.S, it.b_obj, it.lod);
     const V3 org = V3{it.ox, it.oy, it.oz};
-    // the A records are built when the first chunk survives its test, so a
-    // tile whose chunks are all culled costs only block-record reads
-    Rec ra[P];
-    bool built = false;
-    // union of the A block records (tile starts are multiples of 64)
-    float4 alo = SA.blk[2 * (tl.a0 >> 6)], ahi = SA.blk[2 * (tl.a0 >> 6) + 1];
-#pragma unroll
-    for (int p = 1; p < P; ++p) {
-        if (tl.a0 + 64 * p >= SA.n) break;
-        const float4 l2 = SA.blk[2 * ((tl.a0 >> 6) + p)], h2 = SA.blk[2 * ((tl.a0 >> 6) + p) + 1];
-        alo = make_float4(fminf(alo.x, l2.x), fminf(alo.y, l2.y), fminf(alo.z, l2.z), fmaxf(alo.w, l2.w));
-        ahi = make_float4(fmaxf(ahi.x, h2.x), fmaxf(ahi.y, h2.y), fmaxf(ahi.z, h2.z), fmaxf(ahi.w, h2.w));
-    }
-    const float aph = ahi.w;
     const bool within = a.tau >= 0.0f;
     float lbm = kInf, ubm = kInf;
     int sure = 0;
-    int cols = 0, culled = 0;
+    int culled = 0;
+    unsigned long long npairs = 0;
     const bool finest = it.flags & IT_FINEST;
     bool stop = false;
-    // Groups of up to 64 streamed chunks: lane j tests chunk j of the group
-    // from its block record, a ballot leaves the chunks that may matter, and
-    // the wave walks those in order.  Before a chunk is loaded its test is
-    // repeated with the minima found so far (read back from the testing lane).
-    for (int g0 = tl.b0; g0 < tl.b1 && !stop; g0 += 64 * 64) {
-        const int nch = min(64, (tl.b1 - g0 + 63) >> 6);
-        float cur_lb = kInf, cur_ub = kInf;
-        float gap_l = 0.0f, bph_l = 0.0f;
-        unsigned long long cmask;
-        if (a.cull) {
-            cur_lb = __uint_as_float(__builtin_amdgcn_readfirstlane(
-                __hip_atomic_load(&o->lb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
-            cur_ub = __uint_as_float(__builtin_amdgcn_readfirstlane(
-                __hip_atomic_load(&o->ub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
-            bool live = false;
-            if (lane < nch) {
-                const int c = (g0 >> 6) + lane;
-                const float4 blo = SB.blk[2 * c], bhi = SB.blk[2 * c + 1];
-                gap_l = box_gap32(alo, ahi, blo, bhi) - it.eps;
-                bph_l = bhi.w;
-                live = !chunk_cut<COLLECT>(gap_l, bph_l, aph, cur_lb, cur_ub, lbm, ubm, it, a.tau, within);
-            }
-            cmask = __ballot(live);
-            culled += nch - __popcll(cmask);
-        } else {
-            cmask = nch == 64 ? ~0ull : ((1ull << nch) - 1ull);
+    // the tile's A facets, one register block of 64P at a time
+    for (int a0 = tl.a0; a0 < tl.a1 && !stop; a0 += 64 * P) {
+        int cols = 0;
+        // the A records are built when the first chunk survives its test, so a
+        // block whose chunks are all culled costs only block-record reads
+        Rec ra[P];
+        bool built = false;
+        // union of the A block records (block starts are multiples of 64)
+        float4 alo = SA.blk[2 * (a0 >> 6)], ahi = SA.blk[2 * (a0 >> 6) + 1];
+#pragma unroll
+        for (int p = 1; p < P; ++p) {
+            if (a0 + 64 * p >= SA.n) break;
+            const float4 l2 = SA.blk[2 * ((a0 >> 6) + p)], h2 = SA.blk[2 * ((a0 >> 6) + p) + 1];
+            alo = make_float4(fminf(alo.x, l2.x), fminf(alo.y, l2.y), fminf(alo.z, l2.z), fmaxf(alo.w, l2.w));
+            ahi = make_float4(fmaxf(ahi.x, h2.x), fmaxf(ahi.y, h2.y), fmaxf(ahi.z, h2.z), fmaxf(ahi.w, h2.w));
         }
-        while (cmask != 0ull && !stop) {
-            const int j = __builtin_ctzll(cmask);
-            cmask &= cmask - 1ull;
-            const int cb = g0 + 64 * j;
-            const int nb = min(64, tl.b1 - cb);
+        const float aph = ahi.w;
+        // Groups of up to 64 streamed chunks: lane j tests chunk j of the group
+        // from its block record, a ballot leaves the chunks that may matter, and
+        // the wave walks those in order.  Before a chunk is loaded its test is
+        // repeated with the minima found so far (read back from the testing lane).
+        for (int g0 = tl.b0; g0 < tl.b1 && !stop; g0 += 64 * 64) {
+            const int nch = min(64, (tl.b1 - g0 + 63) >> 6);
+            float cur_lb = kInf, cur_ub = kInf;
+            float gap_l = 0.0f, bph_l = 0.0f;
+            unsigned long long cmask;
             if (a.cull) {
-                const float gj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gap_l), j));
-                const float bj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bph_l), j));
-                const float l0 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(lbm)));
-                const float u0 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(ubm)));
-                if (__builtin_amdgcn_readfirstlane(
-                        (int)chunk_cut<COLLECT>(gj, bj, aph, cur_lb, cur_ub, l0, u0, it, a.tau, within))) {
+                cur_lb = __uint_as_float(__builtin_amdgcn_readfirstlane(
+                    __hip_atomic_load(&o->lb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+                cur_ub = __uint_as_float(__builtin_amdgcn_readfirstlane(
+                    __hip_atomic_load(&o->ub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+                bool live = false;
+                if (lane < nch) {
+                    const int c = (g0 >> 6) + lane;
+                    const float4 blo = SB.blk[2 * c], bhi = SB.blk[2 * c + 1];
+                    gap_l = box_gap32(alo, ahi, blo, bhi) - it.eps;
+                    bph_l = bhi.w;
+                    live = !chunk_cut<COLLECT>(gap_l, bph_l, aph, cur_lb, cur_ub, lbm, ubm, it, a.tau, within);
+                }
+                cmask = __ballot(live);
+                culled += nch - __popcll(cmask);
+            } else {
+                cmask = nch == 64 ? ~0ull : ((1ull << nch) - 1ull);
+            }
+            while (cmask != 0ull && !stop) {
+                const int j = __builtin_ctzll(cmask);
+                cmask &= cmask - 1ull;
+                const int cb = g0 + 64 * j;
+                const int nb = min(64, tl.b1 - cb);
+                if (a.cull) {
+                    const float gj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gap_l), j));
+                    const float bj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bph_l), j));
+                    const float l0 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(lbm)));
+                    const float u0 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(ubm)));
+                    if (__builtin_amdgcn_readfirstlane(
+                            (int)chunk_cut<COLLECT>(gj, bj, aph, cur_lb, cur_ub, l0, u0, it, a.tau, within))) {
+                        ++culled;
+                        continue;
+                    }
+                }
+                if (!built) {
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        int fa = a0 + lane + 64 * p;
+                        if (fa >= SA.n) fa = a0;  // padding lanes repeat a real facet
+                        ra[p] = load_rec(SA, fa, org);
+                    }
+                    built = true;
+                }
+                int f = cb + lane;
+                if (f >= tl.b1) f = cb;
+                const int32_t i0 = SB.tris[3 * f], i1 = SB.tris[3 * f + 1], i2 = SB.tris[3 * f + 2];
+                const V3 w0 = ld3f(SB.verts, i0), w1 = ld3f(SB.verts, i1), w2 = ld3f(SB.verts, i2);
+                const float2 bh = SB.hdph ? SB.hdph[f] : make_float2(0.0f, 0.0f);
+                // Facet culling: the same two-sided test with this facet's own box
+                // and ph against the A block; surviving facets are packed to the
+                // front of the LDS chunk (their index rides in the record's pad).
+                bool keep = lane < nb;
+                if (a.cull) {
+                    const float4 flo = make_float4(fminf(fminf(w0.x, w1.x), w2.x), fminf(fminf(w0.y, w1.y), w2.y),
+                                                   fminf(fminf(w0.z, w1.z), w2.z), 0.0f);
+                    const float4 fhi = make_float4(fmaxf(fmaxf(w0.x, w1.x), w2.x), fmaxf(fmaxf(w0.y, w1.y), w2.y),
+                                                   fmaxf(fmaxf(w0.z, w1.z), w2.z), 0.0f);
+                    const float g = box_gap32(alo, ahi, flo, fhi) - it.eps;
+                    keep = keep && !chunk_cut<COLLECT>(g, bh.y, aph, cur_lb, cur_ub, lbm, ubm, it, a.tau, within);
+                }
+                const unsigned long long kmask = __ballot(keep);
+                const int nk = __popcll(kmask);
+                if (nk == 0) {
                     ++culled;
                     continue;
                 }
-            }
-            if (!built) {
+                if (keep) {
+                    const int pos = __builtin_amdgcn_mbcnt_hi((unsigned)(kmask >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((unsigned)kmask, 0u));
+                    Rec rb = make_rec(w0 - org, w1 - org, w2 - org, bh.x, bh.y);
+                    rb.pad = __int_as_float(f);
+                    float tmp[44];
+                    __builtin_memcpy(tmp, &rb, sizeof(tmp));
 #pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    int fa = tl.a0 + lane + 64 * p;
-                    if (fa >= SA.n) fa = tl.a0;  // padding lanes repeat a real facet
-                    ra[p] = load_rec(SA, fa, org);
+                    for (int q = 0; q < 11; ++q)
+                        sh[pos * 11 + q] = make_float4(tmp[4 * q], tmp[4 * q + 1], tmp[4 * q + 2], tmp[4 * q + 3]);
                 }
-                built = true;
-            }
-            int f = cb + lane;
-            if (f >= tl.b1) f = cb;
-            const int32_t i0 = SB.tris[3 * f], i1 = SB.tris[3 * f + 1], i2 = SB.tris[3 * f + 2];
-            const V3 w0 = ld3f(SB.verts, i0), w1 = ld3f(SB.verts, i1), w2 = ld3f(SB.verts, i2);
-            const float2 bh = SB.hdph ? SB.hdph[f] : make_float2(0.0f, 0.0f);
-            // Facet culling: the same two-sided test with this facet's own box
-            // and ph against the A block; surviving facets are packed to the
-            // front of the LDS chunk (their index rides in the record's pad).
-            bool keep = lane < nb;
-            if (a.cull) {
-                const float4 flo = make_float4(fminf(fminf(w0.x, w1.x), w2.x), fminf(fminf(w0.y, w1.y), w2.y),
-                                               fminf(fminf(w0.z, w1.z), w2.z), 0.0f);
-                const float4 fhi = make_float4(fmaxf(fmaxf(w0.x, w1.x), w2.x), fmaxf(fmaxf(w0.y, w1.y), w2.y),
-                                               fmaxf(fmaxf(w0.z, w1.z), w2.z), 0.0f);
-                const float g = box_gap32(alo, ahi, flo, fhi) - it.eps;
-                keep = keep && !chunk_cut<COLLECT>(g, bh.y, aph, cur_lb, cur_ub, lbm, ubm, it, a.tau, within);
-            }
-            const unsigned long long kmask = __ballot(keep);
-            const int nk = __popcll(kmask);
-            if (nk == 0) {
-                ++culled;
-                continue;
-            }
-            if (keep) {
-                const int pos = __builtin_amdgcn_mbcnt_hi((unsigned)(kmask >> 32),
-                                                          __builtin_amdgcn_mbcnt_lo((unsigned)kmask, 0u));
-                Rec rb = make_rec(w0 - org, w1 - org, w2 - org, bh.x, bh.y);
-                rb.pad = __int_as_float(f);
-                float tmp[44];
-                __builtin_memcpy(tmp, &rb, sizeof(tmp));
+                __syncthreads();
+                for (int k = 0; k < nk; ++k) {
+                    float tmp[44];
 #pragma unroll
-                for (int q = 0; q < 11; ++q)
-                    sh[pos * 11 + q] = make_float4(tmp[4 * q], tmp[4 * q + 1], tmp[4 * q + 2], tmp[4 * q + 3]);
-            }
-            __syncthreads();
-            for (int k = 0; k < nk; ++k) {
-                float tmp[44];
+                    for (int q = 0; q < 11; ++q) {
+                        float4 x = sh[k * 11 + q];
+                        tmp[4 * q] = x.x;
+                        tmp[4 * q + 1] = x.y;
+                        tmp[4 * q + 2] = x.z;
+                        tmp[4 * q + 3] = x.w;
+                    }
+                    Rec rb;
+                    __builtin_memcpy(&rb, tmp, sizeof(rb));
 #pragma unroll
-                for (int q = 0; q < 11; ++q) {
-                    float4 x = sh[k * 11 + q];
-                    tmp[4 * q] = x.x;
-                    tmp[4 * q + 1] = x.y;
-                    tmp[4 * q + 2] = x.z;
-                    tmp[4 * q + 3] = x.w;
-                }
-                Rec rb;
-                __builtin_memcpy(&rb, tmp, sizeof(rb));
-#pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    Pair32 pr = pair_f32(ra[p], rb, it.eps);
-                    float dlo = pr.d * (ra[p].ok * rb.ok);
-                    lbm = fminf(lbm, fmaxf(dlo - (ra[p].ph + rb.ph), 0.0f));
-                    ubm = fminf(ubm, pr.d + (ra[p].hd + rb.hd));
-                    sure |= pr.sure ? 1 : 0;
-                    if (COLLECT) {
-                        const int fa = tl.a0 + lane + 64 * p;
-                        // the pair realising the minimum has dlo <= d + eps <= ubm + 2 eps
-                        if (fa < SA.n && dlo <= fminf(it.thr, ubm + 2.0f * it.eps)) {
-                            const unsigned long long slot = atomicAdd(a.collected_n, 1ull);
-                            if (slot < (unsigned long long)a.collect_cap)
-                                a.collected[slot] = PairRef{tl.item, fa, __float_as_int(rb.pad), 0};
-                            else a.overflow[tl.item] = 1;
+                    for (int p = 0; p < P; ++p) {
+                        Pair32 pr = pair_f32(ra[p], rb, it.eps);
+                        float dlo = pr.d * (ra[p].ok * rb.ok);
+                        lbm = fminf(lbm, fmaxf(dlo - (ra[p].ph + rb.ph), 0.0f));
+                        ubm = fminf(ubm, pr.d + (ra[p].hd + rb.hd));
+                        sure |= pr.sure ? 1 : 0;
+                        if (COLLECT) {
+                            const int fa = a0 + lane + 64 * p;
+                            // the pair realising the minimum has dlo <= d + eps <= ubm + 2 eps
+                            if (fa < SA.n && dlo <= fminf(it.thr, ubm + 2.0f * it.eps)) {
+                                const unsigned long long slot = atomicAdd(a.collected_n, 1ull);
+                                if (slot < (unsigned long long)a.collect_cap)
+                                    a.collected[slot] = PairRef{tl.item, fa, __float_as_int(rb.pad), 0};
+                                else a.overflow[tl.item] = 1;
+                            }
                         }
                     }
                 }
-            }
-            cols += nk;
-            __syncthreads();
-            if (a.cull) {  // publish the running minima so that other tiles can cull against them
-                const float wl = wmin_u(lbm), wu = wmin_u(ubm);
-                lbm = wl;
-                ubm = wu;
-                if (lane == 0) {
-                    atomicMin(&o->lb, fbits(wl));
-                    atomicMin(&o->ub, fbits(wu));
+                cols += nk;
+                __syncthreads();
+                if (a.cull) {  // publish the running minima so that other tiles can cull against them
+                    const float wl = wmin_u(lbm), wu = wmin_u(ubm);
+                    lbm = wl;
+                    ubm = wu;
+                    if (lane == 0) {
+                        atomicMin(&o->lb, fbits(wl));
+                        atomicMin(&o->ub, fbits(wu));
+                    }
                 }
-            }
-            if (!COLLECT && a.early) {
-                const float wub = wmin_u(ubm);
-                const int ws = __builtin_amdgcn_readfirstlane(wave_or(sure));
-                const bool confirm = (a.tau > 0.0f && wub + it.eps <= a.tau) || (finest && ws);
-                if (confirm) {
-                    if (lane == 0) __hip_atomic_store(&o->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    stop = true;
-                } else if (__builtin_amdgcn_readfirstlane(
-                               __hip_atomic_load(&o->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-                    stop = true;
+                if (!COLLECT && a.early) {
+                    const float wub = wmin_u(ubm);
+                    const int ws = __builtin_amdgcn_readfirstlane(wave_or(sure));
+                    const bool confirm = (a.tau > 0.0f && wub + it.eps <= a.tau) || (finest && ws);
+                    if (confirm) {
+                        if (lane == 0) __hip_atomic_store(&o->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        stop = true;
+                    } else if (__builtin_amdgcn_readfirstlane(
+                                   __hip_atomic_load(&o->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                        stop = true;
+                    }
                 }
             }
         }
-    }
+        npairs += (unsigned long long)min(64 * P, SA.n - a0) * (unsigned long long)cols;
+    }  // A blocks
     const float wl = wave_min(lbm), wu = wave_min(ubm);
     const int ws = wave_or(sure);
     if (lane == 0) {
         atomicMin(&o->lb, fbits(wl));
         atomicMin(&o->ub, fbits(wu));
         if (ws) atomicOr(&o->hit, 1);
-        const int rows = min(64 * P, SA.n - tl.a0);
-        atomicAdd(a.pairs_done, (unsigned long long)rows * (unsigned long long)cols);
+        atomicAdd(a.pairs_done, npairs);
         if (culled) atomicAdd(a.chunks_culled, (unsigned long long)culled);
     }
 }
