@@ -871,13 +871,20 @@ void plan_tiles(const pj_meshes *R, const pj_meshes *S, const std::vector<int> &
     pl.tile_s = TS;
     // A blocks per tile: one, or as many as bring the round near the target
     // tile count (a tile walks its A blocks one after the other)
+    // register side: the object whose block padding wastes less
+    auto swapped = [&](int64_t nr, int64_t ns) {
+        const int64_t cr = (nr + BR - 1) / BR * BR * ns, cs = (ns + BR - 1) / BR * BR * nr;
+        return allow_swap && cs < cr;
+    };
     int64_t ga = 1;
     if (target_tiles > 0) {
         int64_t n1 = 0;
         for (const C &oc : order) {
             const Cand &c = cand[act[oc.idx]];
             const int64_t nr = R->count(c.r, lod), ns = S->count(c.s, lod);
-            n1 += std::max<int64_t>((std::min(nr, ns) + BR - 1) / BR, 1) * ((std::max(nr, ns) + TS - 1) / TS);
+            const bool sw = swapped(nr, ns);
+            const int64_t nA = sw ? ns : nr, nB = sw ? nr : ns;
+            n1 += ((nA + BR - 1) / BR) * ((nB + TS - 1) / TS);
         }
         ga = std::max<int64_t>(1, n1 / target_tiles);
     }
@@ -887,8 +894,7 @@ void plan_tiles(const pj_meshes *R, const pj_meshes *S, const std::vector<int> &
         const PairState &p = ps[ci];
         int nr = R->count(c.r, lod), ns = S->count(c.s, lod);
         if (nr == 0 || ns == 0) continue;
-        int64_t cr = (int64_t)((nr + BR - 1) / BR) * BR * ns, cs = (int64_t)((ns + BR - 1) / BR) * BR * nr;
-        bool swap = allow_swap && cs < cr;
+        const bool swap = swapped(nr, ns);
         Item it;
         std::memset(&it, 0, sizeof(it));
         it.a_obj = swap ? c.s : c.r;
