@@ -64,3 +64,77 @@ def test_sampled_pairs_match_oracle(orc, full, tau):
     assert not np.any(~hit.astype(bool) & (np.abs(d - tau) <= 1e-12 * np.maximum(M, tau)))
     assert np.all(inside[:len(sp)]), [pairs[k] for k in np.nonzero(~inside[:len(sp)])[0]]
     assert not np.any(inside[len(sp):]), [pairs[len(sp) + k] for k in np.nonzero(inside[len(sp):])[0]]
+
+
+# ---------------------------------------------------------------------------
+# The learned-skip workload (100k blobs x 20k tubes, 5000^3, tau = 10) in the
+# bench configuration: the oracle decides every MBB candidate, so the whole
+# result set is compared.
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def learned_full(tmp_path_factory):
+    sys.path.insert(0, ROOT)
+    import torch
+    import bench
+    import paper_2604_19982_amd as pj
+    stream = torch.cuda.current_stream()
+    work = str(tmp_path_factory.mktemp("lod_learned"))
+    model, _, _ = bench.train_model(pj, mg, stream, work)
+    R, S = mg.config_learned()
+    ctx = pj.Context(stream=stream.cuda_stream, learned_skip=True, model_path=model, autotune=True,
+                     autotune_path=os.path.join(work, "shapes.txt"))
+    gR, gS = ctx.meshes(R), ctx.meshes(S)
+    res = ctx.join_within(gR, gS, 10.0)
+    return R, S, res
+
+
+def test_learned_workload_full_parity(orc, learned_full):
+    """Every MBB candidate (box gap <= 10, found by an x sweep over the
+    oracle's boxes) is decided by the oracle's exact distance."""
+    import bench
+    R, S, res = learned_full
+    tau = 10.0
+    O_R, O_S = orc.OSet(R), orc.OSet(S)
+    cr, cs = bench.sample_candidates(orc, O_R, O_S, tau, max_r=R.n_objects)
+    assert len(cr) > 1000
+    d, hit = orc.pair_distances(O_R, O_S, cr, cs)
+    bR, _ = orc.mbbs(O_R)
+    bS, _ = orc.mbbs(O_S)
+    M = orc.pair_scale(bR[cr], bS[cs])
+    assert not np.any(~hit & (np.abs(d - tau) <= 1e-12 * np.maximum(M, tau)))  # no near ties
+    keep = d <= tau
+    want = sorted(zip(cr[keep].tolist(), cs[keep].tolist()))
+    got = list(zip(res["r"].tolist(), res["s"].tolist()))
+    assert got == want
+
+
+# ---------------------------------------------------------------------------
+# The k-NN workload (k = 3, 20k x 20k clustered blob/tube mix): sampled
+# queries against the oracle's exact k-NN of the same r.
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def knn_full(tmp_path_factory):
+    import torch
+    import paper_2604_19982_amd as pj
+    stream = torch.cuda.current_stream()
+    work = str(tmp_path_factory.mktemp("knn_full"))
+    R, S = mg.config_knn()
+    ctx = pj.Context(stream=stream.cuda_stream, autotune=True, autotune_path=os.path.join(work, "shapes.txt"))
+    res = ctx.join_knn(ctx.meshes(R), ctx.meshes(S), 3)
+    return R, S, res
+
+
+def test_knn_workload_sampled_parity(orc, knn_full):
+    R, S, res = knn_full
+    rs = np.sort(np.random.default_rng(11).choice(R.n_objects, 24, replace=False))
+    O_R, O_S = orc.OSet(R), orc.OSet(S)
+    ref = orc.join_knn(O_R, O_S, 3, r_subset=rs)
+    assert ref["near_ties"] == 0
+    bR, _ = orc.mbbs(O_R)
+    bS, _ = orc.mbbs(O_S)
+    M = float(max(np.abs(bR).max(), np.abs(bS).max()))
+    assert np.all(res["count"] == 3)
+    for r in rs:
+        assert res["s"][r].tolist() == ref["s"][int(r)].tolist(), r
+        d, e = res["dist"][r], ref["d"][int(r)]
+        assert np.all(np.abs(d - e) <= np.maximum(1e-5 * e, 1e-12 * M)), (r, d, e)
