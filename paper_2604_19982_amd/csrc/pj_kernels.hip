@@ -654,7 +654,7 @@ __device__ __forceinline__ bool chunk_cut(float g, float bph, float aph, float c
 }
 
 template <int P, bool COLLECT>
-__device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t, float4 *sh)
+__device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t, float4 *sh, int *qidx)
 {
     const int lane = threadIdx.x;
     const Tile tl = a.tiles[t];
@@ -691,6 +691,90 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
             ahi = make_float4(fmaxf(ahi.x, h2.x), fmaxf(ahi.y, h2.y), fmaxf(ahi.z, h2.z), fmaxf(ahi.w, h2.w));
         }
         const float aph = ahi.w;
+        // Surviving B facets wait in an LDS queue (qidx) and are evaluated 64
+        // at a time: their records are built by all lanes at once, then every
+        // lane runs its A facet against each of them.
+        int qn = 0;
+        auto flush = [&](const int n) {
+            if (!built) {
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    int fa = a0 + lane + 64 * p;
+                    if (fa >= SA.n) fa = a0;  // padding lanes repeat a real facet
+                    ra[p] = load_rec(SA, fa, org);
+                }
+                built = true;
+            }
+            if (lane < n) {
+                const int f = qidx[lane];
+                const int32_t i0 = SB.tris[3 * f], i1 = SB.tris[3 * f + 1], i2 = SB.tris[3 * f + 2];
+                const V3 w0 = ld3f(SB.verts, i0), w1 = ld3f(SB.verts, i1), w2 = ld3f(SB.verts, i2);
+                const float2 bh = SB.hdph ? SB.hdph[f] : make_float2(0.0f, 0.0f);
+                Rec rb = make_rec(w0 - org, w1 - org, w2 - org, bh.x, bh.y);
+                rb.pad = __int_as_float(f);
+                float tmp[44];
+                __builtin_memcpy(tmp, &rb, sizeof(tmp));
+#pragma unroll
+                for (int q = 0; q < 11; ++q)
+                    sh[lane * 11 + q] = make_float4(tmp[4 * q], tmp[4 * q + 1], tmp[4 * q + 2], tmp[4 * q + 3]);
+            }
+            __syncthreads();
+#pragma unroll 1
+            for (int k = 0; k < n; ++k) {
+                float tmp[44];
+#pragma unroll
+                for (int q = 0; q < 11; ++q) {
+                    float4 x = sh[k * 11 + q];
+                    tmp[4 * q] = x.x;
+                    tmp[4 * q + 1] = x.y;
+                    tmp[4 * q + 2] = x.z;
+                    tmp[4 * q + 3] = x.w;
+                }
+                Rec rb;
+                __builtin_memcpy(&rb, tmp, sizeof(rb));
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    Pair32 pr = pair_f32(ra[p], rb, it.eps);
+                    float dlo = pr.d * (ra[p].ok * rb.ok);
+                    lbm = fminf(lbm, fmaxf(dlo - (ra[p].ph + rb.ph), 0.0f));
+                    ubm = fminf(ubm, pr.d + (ra[p].hd + rb.hd));
+                    sure |= pr.sure ? 1 : 0;
+                    if (COLLECT) {
+                        const int fa = a0 + lane + 64 * p;
+                        // the pair realising the minimum has dlo <= d + eps <= ubm + 2 eps
+                        if (fa < SA.n && dlo <= fminf(it.thr, ubm + 2.0f * it.eps)) {
+                            const unsigned long long slot = atomicAdd(a.collected_n, 1ull);
+                            if (slot < (unsigned long long)a.collect_cap)
+                                a.collected[slot] = PairRef{tl.item, fa, __float_as_int(rb.pad), 0};
+                            else a.overflow[tl.item] = 1;
+                        }
+                    }
+                }
+            }
+            cols += n;
+            __syncthreads();
+            if (a.cull) {  // publish the running minima so that other tiles can cull against them
+                const float wl = wmin_u(lbm), wu = wmin_u(ubm);
+                lbm = wl;
+                ubm = wu;
+                if (lane == 0) {
+                    atomicMin(&o->lb, fbits(wl));
+                    atomicMin(&o->ub, fbits(wu));
+                }
+            }
+            if (!COLLECT && a.early) {
+                const float wub = wmin_u(ubm);
+                const int ws = __builtin_amdgcn_readfirstlane(wave_or(sure));
+                const bool confirm = (a.tau > 0.0f && wub + it.eps <= a.tau) || (finest && ws);
+                if (confirm) {
+                    if (lane == 0) __hip_atomic_store(&o->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    stop = true;
+                } else if (__builtin_amdgcn_readfirstlane(
+                               __hip_atomic_load(&o->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                    stop = true;
+                }
+            }
+        };
         // Groups of up to 64 streamed chunks: lane j tests chunk j of the group
         // from its block record, a ballot leaves the chunks that may matter, and
         // the wave walks those in order.  Before a chunk is loaded its test is
@@ -734,31 +818,21 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
                         continue;
                     }
                 }
-                if (!built) {
-#pragma unroll
-                    for (int p = 0; p < P; ++p) {
-                        int fa = a0 + lane + 64 * p;
-                        if (fa >= SA.n) fa = a0;  // padding lanes repeat a real facet
-                        ra[p] = load_rec(SA, fa, org);
-                    }
-                    built = true;
-                }
                 int f = cb + lane;
                 if (f >= tl.b1) f = cb;
-                const int32_t i0 = SB.tris[3 * f], i1 = SB.tris[3 * f + 1], i2 = SB.tris[3 * f + 2];
-                const V3 w0 = ld3f(SB.verts, i0), w1 = ld3f(SB.verts, i1), w2 = ld3f(SB.verts, i2);
-                const float2 bh = SB.hdph ? SB.hdph[f] : make_float2(0.0f, 0.0f);
-                // Facet culling: the same two-sided test with this facet's own box
-                // and ph against the A block; surviving facets are packed to the
-                // front of the LDS chunk (their index rides in the record's pad).
+                // Facet culling: the same two-sided test with this facet's own
+                // box and ph against the A block; survivors join the LDS queue.
                 bool keep = lane < nb;
                 if (a.cull) {
+                    const int32_t i0 = SB.tris[3 * f], i1 = SB.tris[3 * f + 1], i2 = SB.tris[3 * f + 2];
+                    const V3 w0 = ld3f(SB.verts, i0), w1 = ld3f(SB.verts, i1), w2 = ld3f(SB.verts, i2);
+                    const float bph = SB.hdph ? SB.hdph[f].y : 0.0f;
                     const float4 flo = make_float4(fminf(fminf(w0.x, w1.x), w2.x), fminf(fminf(w0.y, w1.y), w2.y),
                                                    fminf(fminf(w0.z, w1.z), w2.z), 0.0f);
                     const float4 fhi = make_float4(fmaxf(fmaxf(w0.x, w1.x), w2.x), fmaxf(fmaxf(w0.y, w1.y), w2.y),
                                                    fmaxf(fmaxf(w0.z, w1.z), w2.z), 0.0f);
                     const float g = box_gap32(alo, ahi, flo, fhi) - it.eps;
-                    keep = keep && !chunk_cut<COLLECT>(g, bh.y, aph, cur_lb, cur_ub, lbm, ubm, it, a.tau, within);
+                    keep = keep && !chunk_cut<COLLECT>(g, bph, aph, cur_lb, cur_ub, lbm, ubm, it, a.tau, within);
                 }
                 const unsigned long long kmask = __ballot(keep);
                 const int nk = __popcll(kmask);
@@ -769,71 +843,24 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
                 if (keep) {
                     const int pos = __builtin_amdgcn_mbcnt_hi((unsigned)(kmask >> 32),
                                                               __builtin_amdgcn_mbcnt_lo((unsigned)kmask, 0u));
-                    Rec rb = make_rec(w0 - org, w1 - org, w2 - org, bh.x, bh.y);
-                    rb.pad = __int_as_float(f);
-                    float tmp[44];
-                    __builtin_memcpy(tmp, &rb, sizeof(tmp));
-#pragma unroll
-                    for (int q = 0; q < 11; ++q)
-                        sh[pos * 11 + q] = make_float4(tmp[4 * q], tmp[4 * q + 1], tmp[4 * q + 2], tmp[4 * q + 3]);
+                    qidx[qn + pos] = f;
                 }
+                qn += nk;
                 __syncthreads();
-                for (int k = 0; k < nk; ++k) {
-                    float tmp[44];
-#pragma unroll
-                    for (int q = 0; q < 11; ++q) {
-                        float4 x = sh[k * 11 + q];
-                        tmp[4 * q] = x.x;
-                        tmp[4 * q + 1] = x.y;
-                        tmp[4 * q + 2] = x.z;
-                        tmp[4 * q + 3] = x.w;
-                    }
-                    Rec rb;
-                    __builtin_memcpy(&rb, tmp, sizeof(rb));
-#pragma unroll
-                    for (int p = 0; p < P; ++p) {
-                        Pair32 pr = pair_f32(ra[p], rb, it.eps);
-                        float dlo = pr.d * (ra[p].ok * rb.ok);
-                        lbm = fminf(lbm, fmaxf(dlo - (ra[p].ph + rb.ph), 0.0f));
-                        ubm = fminf(ubm, pr.d + (ra[p].hd + rb.hd));
-                        sure |= pr.sure ? 1 : 0;
-                        if (COLLECT) {
-                            const int fa = a0 + lane + 64 * p;
-                            // the pair realising the minimum has dlo <= d + eps <= ubm + 2 eps
-                            if (fa < SA.n && dlo <= fminf(it.thr, ubm + 2.0f * it.eps)) {
-                                const unsigned long long slot = atomicAdd(a.collected_n, 1ull);
-                                if (slot < (unsigned long long)a.collect_cap)
-                                    a.collected[slot] = PairRef{tl.item, fa, __float_as_int(rb.pad), 0};
-                                else a.overflow[tl.item] = 1;
-                            }
-                        }
-                    }
-                }
-                cols += nk;
-                __syncthreads();
-                if (a.cull) {  // publish the running minima so that other tiles can cull against them
-                    const float wl = wmin_u(lbm), wu = wmin_u(ubm);
-                    lbm = wl;
-                    ubm = wu;
-                    if (lane == 0) {
-                        atomicMin(&o->lb, fbits(wl));
-                        atomicMin(&o->ub, fbits(wu));
-                    }
-                }
-                if (!COLLECT && a.early) {
-                    const float wub = wmin_u(ubm);
-                    const int ws = __builtin_amdgcn_readfirstlane(wave_or(sure));
-                    const bool confirm = (a.tau > 0.0f && wub + it.eps <= a.tau) || (finest && ws);
-                    if (confirm) {
-                        if (lane == 0) __hip_atomic_store(&o->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        stop = true;
-                    } else if (__builtin_amdgcn_readfirstlane(
-                                   __hip_atomic_load(&o->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-                        stop = true;
-                    }
+                if (qn >= 64) {
+                    flush(64);
+                    // move the rest of the queue to its front
+                    const int rest = qn - 64;
+                    const int v = lane < rest ? qidx[64 + lane] : 0;
+                    __syncthreads();
+                    if (lane < rest) qidx[lane] = v;
+                    __syncthreads();
+                    qn = rest;
                 }
             }
         }
+        if (qn > 0 && !stop) flush(qn);
+        qn = 0;
         npairs += (unsigned long long)min(64 * P, SA.n - a0) * (unsigned long long)cols;
     }  // A blocks
     const float wl = wave_min(lbm), wu = wave_min(ubm);
@@ -856,8 +883,9 @@ template <int P>
 __global__ __launch_bounds__(64) void k_refine_f32(RefineArgs a)
 {
     __shared__ float4 sh[64 * 11];
+    __shared__ int qidx[128];
     const int ntiles = *a.ntiles;
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) refine_tile_f32<P, false>(a, t, sh);
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) refine_tile_f32<P, false>(a, t, sh, qidx);
 }
 
 // Collect pass: the same tiles, keeping every facet pair whose FP32 lower
@@ -865,8 +893,9 @@ __global__ __launch_bounds__(64) void k_refine_f32(RefineArgs a)
 __global__ __launch_bounds__(64) void k_collect_f32(RefineArgs a)
 {
     __shared__ float4 sh[64 * 11];
+    __shared__ int qidx[128];
     const int ntiles = *a.ntiles;
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) refine_tile_f32<1, true>(a, t, sh);
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) refine_tile_f32<1, true>(a, t, sh, qidx);
 }
 
 hipError_t launch_collect_f32(const RefineArgs &a, int grid, hipStream_t st)
