@@ -183,27 +183,35 @@ __device__ __forceinline__ Pair32 pair_f32(const Rec &A, const Rec &B, float eps
     // f = B.e_j . (A.v_i - B.v_j).  Walking the corners along the edges
     // (v_{k+1} = v_k + e_k) gives c(i, j+1) = c(i, j) - b(i, j) and
     // f(i+1, j) = f(i, j) + b(i, j), so only c(i, 0) and f(0, j) are dot
-    // products.
-    const float b00 = dot(A.e0, B.e0), b01 = dot(A.e0, B.e1), b02 = dot(A.e0, B.e2);
-    const float b10 = dot(A.e1, B.e0), b11 = dot(A.e1, B.e1), b12 = dot(A.e1, B.e2);
-    const float b20 = dot(A.e2, B.e0), b21 = dot(A.e2, B.e1), b22 = dot(A.e2, B.e2);
-    const float c00 = dot(A.e0, A.v0 - B.v0), c10 = dot(A.e1, A.v1 - B.v0), c20 = dot(A.e2, A.v2 - B.v0);
-    const float c01 = c00 - b00, c02 = c01 - b01;
-    const float c11 = c10 - b10, c12 = c11 - b11;
-    const float c21 = c20 - b20, c22 = c21 - b21;
-    const float f00 = dot(B.e0, A.v0 - B.v0), f01 = dot(B.e1, A.v0 - B.v1), f02 = dot(B.e2, A.v0 - B.v2);
-    const float f10 = f00 + b00, f20 = f10 + b10;
-    const float f11 = f01 + b01, f21 = f11 + b11;
-    const float f12 = f02 + b02, f22 = f12 + b12;
-    best = fminf(best, segseg2(A.v0, A.e0, A.ee0, A.i0, B.v0, B.e0, B.ee0, B.i0, b00, c00, f00));
-    best = fminf(best, segseg2(A.v0, A.e0, A.ee0, A.i0, B.v1, B.e1, B.ee1, B.i1, b01, c01, f01));
-    best = fminf(best, segseg2(A.v0, A.e0, A.ee0, A.i0, B.v2, B.e2, B.ee2, B.i2, b02, c02, f02));
-    best = fminf(best, segseg2(A.v1, A.e1, A.ee1, A.i1, B.v0, B.e0, B.ee0, B.i0, b10, c10, f10));
-    best = fminf(best, segseg2(A.v1, A.e1, A.ee1, A.i1, B.v1, B.e1, B.ee1, B.i1, b11, c11, f11));
-    best = fminf(best, segseg2(A.v1, A.e1, A.ee1, A.i1, B.v2, B.e2, B.ee2, B.i2, b12, c12, f12));
-    best = fminf(best, segseg2(A.v2, A.e2, A.ee2, A.i2, B.v0, B.e0, B.ee0, B.i0, b20, c20, f20));
-    best = fminf(best, segseg2(A.v2, A.e2, A.ee2, A.i2, B.v1, B.e1, B.ee1, B.i1, b21, c21, f21));
-    best = fminf(best, segseg2(A.v2, A.e2, A.ee2, A.i2, B.v2, B.e2, B.ee2, B.i2, b22, c22, f22));
+    // products.  A's edges are taken one at a time (few values live at once).
+    float f0 = dot(B.e0, A.v0 - B.v0), f1 = dot(B.e1, A.v0 - B.v1), f2 = dot(B.e2, A.v0 - B.v2);
+    {
+        const float b0 = dot(A.e0, B.e0), b1 = dot(A.e0, B.e1), b2 = dot(A.e0, B.e2);
+        const float c0 = dot(A.e0, A.v0 - B.v0), c1 = c0 - b0, c2 = c1 - b1;
+        best = fminf(best, segseg2(A.v0, A.e0, A.ee0, A.i0, B.v0, B.e0, B.ee0, B.i0, b0, c0, f0));
+        best = fminf(best, segseg2(A.v0, A.e0, A.ee0, A.i0, B.v1, B.e1, B.ee1, B.i1, b1, c1, f1));
+        best = fminf(best, segseg2(A.v0, A.e0, A.ee0, A.i0, B.v2, B.e2, B.ee2, B.i2, b2, c2, f2));
+        f0 += b0;
+        f1 += b1;
+        f2 += b2;
+    }
+    {
+        const float b0 = dot(A.e1, B.e0), b1 = dot(A.e1, B.e1), b2 = dot(A.e1, B.e2);
+        const float c0 = dot(A.e1, A.v1 - B.v0), c1 = c0 - b0, c2 = c1 - b1;
+        best = fminf(best, segseg2(A.v1, A.e1, A.ee1, A.i1, B.v0, B.e0, B.ee0, B.i0, b0, c0, f0));
+        best = fminf(best, segseg2(A.v1, A.e1, A.ee1, A.i1, B.v1, B.e1, B.ee1, B.i1, b1, c1, f1));
+        best = fminf(best, segseg2(A.v1, A.e1, A.ee1, A.i1, B.v2, B.e2, B.ee2, B.i2, b2, c2, f2));
+        f0 += b0;
+        f1 += b1;
+        f2 += b2;
+    }
+    {
+        const float b0 = dot(A.e2, B.e0), b1 = dot(A.e2, B.e1), b2 = dot(A.e2, B.e2);
+        const float c0 = dot(A.e2, A.v2 - B.v0), c1 = c0 - b0, c2 = c1 - b1;
+        best = fminf(best, segseg2(A.v2, A.e2, A.ee2, A.i2, B.v0, B.e0, B.ee0, B.i0, b0, c0, f0));
+        best = fminf(best, segseg2(A.v2, A.e2, A.ee2, A.i2, B.v1, B.e1, B.ee1, B.i1, b1, c1, f1));
+        best = fminf(best, segseg2(A.v2, A.e2, A.ee2, A.i2, B.v2, B.e2, B.ee2, B.i2, b2, c2, f2));
+    }
     Pair32 out;
     // hardware square root (about 1 ulp; the guard band is 2^-16 of the
     // pair's extent, far above it); a denormal square may flush to 0, which
