@@ -223,11 +223,16 @@ pj_status pj_meshes_boxes(const pj_meshes *m, float *mbb6, float *anchor3);
 /* Per-facet hd and ph of one (object, LoD), float32 (0 on the finest LoD). */
 pj_status pj_meshes_hdph(const pj_meshes *m, int32_t obj, int32_t lod, float *hd, float *ph);
 
-/* Distance of n triangle pairs (t1[n][9], t2[n][9] float32 corners).
- * precision FP32_BAND: d = FP32 facet distance, hit = 1 where the FP32 test
- * is sure the triangles cross; FP64: exact meet test and FP64 distance. */
+/* Distance of n triangle pairs (t1[n][9], t2[n][9] float32 corners; the
+ * surface distance of Section 2, 0 when the closed triangles meet).
+ * precision FP32_BAND: d = lower and d_hi = upper FP32 estimate (equal unless
+ * the FP32 crossing test can neither confirm nor exclude a crossing; then
+ * d = 0 and d_hi = the vertex-face / edge-edge minimum), hit = 1 where the
+ * FP32 test is certain that the triangles cross.  FP64: exact meet test and
+ * FP64 distance, d_hi = d.  All arrays are host memory of n entries;
+ * PJ_ERR_INVALID_ARG for a null array with n > 0 or another precision. */
 pj_status pj_facet_pairs(pj_context *ctx, const float *t1, const float *t2, int64_t n, int32_t precision,
-                         double *d, int8_t *hit);
+                         double *d, double *d_hi, int8_t *hit);
 
 /* LoD bounds of n object pairs (r[i], s[i]) at one LoD (Eq. (1), Eq. (2)),
  * with the given precision and schedule: lb, ub and the sure-meet flag. */

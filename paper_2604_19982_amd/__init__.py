@@ -121,7 +121,7 @@ def lib():
                                          ctypes.POINTER(ctypes.c_float)]
         L.pj_meshes_boxes.argtypes = [vp, vp, vp]
         L.pj_meshes_hdph.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp]
-        L.pj_facet_pairs.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_int32, vp, vp]
+        L.pj_facet_pairs.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_int32, vp, vp, vp]
         L.pj_pair_bounds.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp, ctypes.c_int32, vp, vp, vp]
         L.pj_mlp_eval.argtypes = [vp, vp, vp, vp, ctypes.c_int64, vp, vp, vp]
         L.pj_probe_fma.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
@@ -253,14 +253,18 @@ class Context:
         self._check(lib().pj_get_stats(self.h, ctypes.byref(st)))
         return st.to_dict()
 
-    def facet_pairs(self, t1, t2, precision="fp32"):
+    def facet_pairs(self, t1, t2, precision="fp32", bounds=False):
+        """Facet-pair distances: (d, hit), or (d_lo, d_hi, hit) with bounds=True."""
         t1 = _arr(t1, np.float32).reshape(-1, 9)
         t2 = _arr(t2, np.float32).reshape(-1, 9)
         n = len(t1)
         d = np.zeros(n, np.float64)
+        d_hi = np.zeros(n, np.float64)
         hit = np.zeros(n, np.int8)
         self._check(lib().pj_facet_pairs(self.h, t1.ctypes.data, t2.ctypes.data, n, PREC[precision], d.ctypes.data,
-                                         hit.ctypes.data))
+                                         d_hi.ctypes.data, hit.ctypes.data))
+        if bounds:
+            return d, d_hi, hit.astype(bool)
         return d, hit.astype(bool)
 
     def pair_bounds(self, R: Meshes, S: Meshes, r, s, lod):

@@ -2479,23 +2479,25 @@ extern "C" void pj_knn_free(pj_knn *p)
 // inspection entry points
 // ===========================================================================
 extern "C" pj_status pj_facet_pairs(pj_context *ctx, const float *t1, const float *t2, int64_t n, int32_t precision,
-                                    double *d, int8_t *hit)
+                                    double *d, double *d_hi, int8_t *hit)
 {
     if (!ctx) return PJ_ERR_INVALID_ARG;
-    if (n < 0 || (n > 0 && (!t1 || !t2 || !d || !hit))) return fail(ctx, PJ_ERR_INVALID_ARG, "bad argument");
+    if (n < 0 || (n > 0 && (!t1 || !t2 || !d || !d_hi || !hit))) return fail(ctx, PJ_ERR_INVALID_ARG, "bad argument");
     if (precision != PJ_PREC_FP32_BAND && precision != PJ_PREC_FP64) return fail(ctx, PJ_ERR_INVALID_ARG, "precision");
     if (n == 0) return PJ_OK;
     HIPTRY(ctx, hipSetDevice(ctx->cfg.device));
     hipStream_t st = ctx->stream;
     PJTRY(ensure(ctx, ctx->b_tmp0, n * 36));
     PJTRY(ensure(ctx, ctx->b_tmp1, n * 36));
-    PJTRY(ensure(ctx, ctx->b_tmp2, n * 8));
+    PJTRY(ensure(ctx, ctx->b_tmp2, n * 16));
     PJTRY(ensure(ctx, ctx->b_tmp3, n));
     HIPTRY(ctx, hipMemcpyAsync(ctx->b_tmp0.p, t1, n * 36, hipMemcpyHostToDevice, st));
     HIPTRY(ctx, hipMemcpyAsync(ctx->b_tmp1.p, t2, n * 36, hipMemcpyHostToDevice, st));
     HIPTRY(ctx, launch_facet_pairs(ptr<float>(ctx->b_tmp0), ptr<float>(ctx->b_tmp1), n, precision,
-                                   ptr<double>(ctx->b_tmp2), ptr<int8_t>(ctx->b_tmp3), st));
+                                   ptr<double>(ctx->b_tmp2), ptr<double>(ctx->b_tmp2) + n, ptr<int8_t>(ctx->b_tmp3),
+                                   st));
     HIPTRY(ctx, hipMemcpyAsync(d, ctx->b_tmp2.p, n * 8, hipMemcpyDeviceToHost, st));
+    HIPTRY(ctx, hipMemcpyAsync(d_hi, ptr<double>(ctx->b_tmp2) + n, n * 8, hipMemcpyDeviceToHost, st));
     HIPTRY(ctx, hipMemcpyAsync(hit, ctx->b_tmp3.p, n, hipMemcpyDeviceToHost, st));
     HIPTRY(ctx, hipStreamSynchronize(st));
     return PJ_OK;

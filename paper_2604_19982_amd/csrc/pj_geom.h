@@ -163,11 +163,18 @@ __device__ __forceinline__ void cross_interval(V3 L, V3 p0, V3 p1, V3 p2, float 
     if (h2 * h0 < 0.0f) { float x = t2 + (t0 - t2) * (h2 / (h2 - h0)); lo = fminf(lo, x); hi = fmaxf(hi, x); }
 }
 
-// Result of one FP32 facet pair.
+// Result of one FP32 facet pair.  The crossing test (both triangles straddle
+// the other's plane and the crossing segments overlap on the planes' common
+// line) decides d = 0 against d = the 15-candidate minimum.  Its FP32 form is
+// taken twice: a loose one (plain signs) whose firing sets the lower estimate
+// to 0, and a strict one (every sign and the overlap clear of their rounding
+// error) that alone makes the upper estimate 0.  Between the two the pair is
+// left open for the FP64 recheck (near-coplanar pairs whose plane distances
+// are rounding noise land there).
 struct Pair32 {
-    float d;    // distance estimate: 0 if the FP32 crossing test fires, else the 15-candidate minimum
-    float d15;  // 15-candidate minimum
-    bool sure;  // crossing found and d15 > eps: the triangles certainly meet
+    float lo;   // lower estimate of the distance (0 if a crossing is possible)
+    float hi;   // upper estimate (0 only for a certain crossing, else the 15-candidate minimum)
+    bool sure;  // certain crossing, with the 15-candidate minimum above eps: the triangles meet
 };
 
 __device__ __forceinline__ Pair32 pair_f32(const Rec &A, const Rec &B, float eps)
@@ -216,20 +223,45 @@ __device__ __forceinline__ Pair32 pair_f32(const Rec &A, const Rec &B, float eps
     // hardware square root (about 1 ulp; the guard band is 2^-16 of the
     // pair's extent, far above it); a denormal square may flush to 0, which
     // only lowers the estimate of a distance far below the band
-    out.d15 = __builtin_amdgcn_sqrtf(best);
-    out.d = out.d15;
+    const float d15 = __builtin_amdgcn_sqrtf(best);
+    out.lo = d15;
+    out.hi = d15;
     out.sure = false;
-    // crossing: each triangle strictly straddles the other's plane
-    bool sa = min3f(ha0, ha1, ha2) < 0.0f && max3f(ha0, ha1, ha2) > 0.0f;
-    bool sb = min3f(hb0, hb1, hb2) < 0.0f && max3f(hb0, hb1, hb2) > 0.0f;
-    if (sa && sb) {
+    // loose crossing test: each triangle strictly straddles the other's plane
+    // by the FP32 signs
+    const float ha_lo = min3f(ha0, ha1, ha2), ha_hi = max3f(ha0, ha1, ha2);
+    const float hb_lo = min3f(hb0, hb1, hb2), hb_hi = max3f(hb0, hb1, hb2);
+    if (ha_lo < 0.0f && ha_hi > 0.0f && hb_lo < 0.0f && hb_hi > 0.0f) {
         V3 L = cross(A.n, B.n);
         float alo, ahi, blo, bhi;
         cross_interval(L, A.v0, A.v1, A.v2, ha0, ha1, ha2, alo, ahi);
         cross_interval(L, B.v0, B.v1, B.v2, hb0, hb1, hb2, blo, bhi);
         if (fmaxf(alo, blo) <= fminf(ahi, bhi)) {
-            out.d = 0.0f;
-            out.sure = out.d15 > eps;
+            out.lo = 0.0f;
+            // Strict test.  A corner's plane distance is off the exact one by
+            // less than eh: the unit normal and the offset are each rounded
+            // once from FP64 (2^-24 relative) and the FP32 dot product adds a
+            // few roundings of terms below sqrt(3) M, about 10 x 2^-24 M in
+            // all, against eh = 2^-19 M.  Let the margin m be the smaller of
+            // the largest distance on either side.  Each edge that changes
+            // sign joins corners whose distances add to at least m, so with
+            // m > 4 eh its crossing point moves by at most 2 eh / m of the
+            // triangle's extent along L, and a middle corner that may sit on
+            // either side moves the endpoint by at most 3 eh / m of it.  The
+            // direction L (from two rounded normals) shifts positions by less
+            // than 2^-21 M, under eh.
+            const float eh = 0.125f * eps;
+            const float ma = fminf(ha_hi, -ha_lo), mb = fminf(hb_hi, -hb_lo);
+            if (ma > 4.0f * eh && mb > 4.0f * eh) {
+                const float ta0 = dot(L, A.v0), ta1 = dot(L, A.v1), ta2 = dot(L, A.v2);
+                const float tb0 = dot(L, B.v0), tb1 = dot(L, B.v1), tb2 = dot(L, B.v2);
+                const float ea = 4.0f * eh * (max3f(ta0, ta1, ta2) - min3f(ta0, ta1, ta2)) / ma;
+                const float eb = 4.0f * eh * (max3f(tb0, tb1, tb2) - min3f(tb0, tb1, tb2)) / mb;
+                if (fmaxf(alo, blo) + (ea + eb + 2.0f * eh) < fminf(ahi, bhi)) {
+                    out.hi = 0.0f;
+                    out.sure = d15 > eps;
+                }
+            }
         }
     }
     return out;

@@ -117,8 +117,8 @@ hipError_t launch_knn_prune(int nR, const int64_t *off, const double *lb, const 
                             const int8_t *status_in, int8_t *status_out, const int32_t *k_left, hipStream_t st);
 hipError_t launch_refine_f64_tiles(const Refine64Args &a, int ntiles, hipStream_t st);
 hipError_t launch_refine_f64_plain(const Refine64Args &a, int nitems, hipStream_t st);
-hipError_t launch_facet_pairs(const float *t1, const float *t2, int64_t n, int prec, double *d, int8_t *hit,
-                              hipStream_t st);
+hipError_t launch_facet_pairs(const float *t1, const float *t2, int64_t n, int prec, double *d, double *d_hi,
+                              int8_t *hit, hipStream_t st);
 
 hipError_t launch_fma_probe(int fp64, void *out, int blocks, int iters, hipStream_t st);
 hipError_t launch_copy_probe(const void *src, void *dst, int64_t nbytes, int blocks, hipStream_t st);

@@ -735,9 +735,9 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
 #pragma unroll
                 for (int p = 0; p < P; ++p) {
                     Pair32 pr = pair_f32(ra[p], rb, it.eps);
-                    float dlo = pr.d * (ra[p].ok * rb.ok);
+                    float dlo = pr.lo * (ra[p].ok * rb.ok);
                     lbm = fminf(lbm, fmaxf(dlo - (ra[p].ph + rb.ph), 0.0f));
-                    ubm = fminf(ubm, pr.d + (ra[p].hd + rb.hd));
+                    ubm = fminf(ubm, pr.hi + (ra[p].hd + rb.hd));
                     sure |= pr.sure ? 1 : 0;
                     if (COLLECT) {
                         const int fa = a0 + lane + 64 * p;
@@ -1223,7 +1223,8 @@ hipError_t launch_knn_prune(int nR, const int64_t *off, const double *lb, const 
 // Facet pairs given explicitly (tests): FP32 with a pair-local origin and the
 // guard band 2^-16 M, or FP64 with the exact meet test.
 // ---------------------------------------------------------------------------
-__global__ void k_facet_pairs(const float *t1, const float *t2, int64_t n, int prec, double *d, int8_t *hit)
+__global__ void k_facet_pairs(const float *t1, const float *t2, int64_t n, int prec, double *d, double *d_hi,
+                              int8_t *hit)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -1240,22 +1241,25 @@ __global__ void k_facet_pairs(const float *t1, const float *t2, int64_t n, int p
         Rec A = make_rec(V3{p[0], p[1], p[2]} - o, V3{p[3], p[4], p[5]} - o, V3{p[6], p[7], p[8]} - o, 0.0f, 0.0f);
         Rec B = make_rec(V3{q[0], q[1], q[2]} - o, V3{q[3], q[4], q[5]} - o, V3{q[6], q[7], q[8]} - o, 0.0f, 0.0f);
         Pair32 r = pair_f32(A, B, eps);
-        d[i] = r.d;
+        d[i] = r.lo;
+        d_hi[i] = r.hi;
         hit[i] = r.sure ? 1 : 0;
     } else {
         D3 A[3] = {D3{p[0], p[1], p[2]}, D3{p[3], p[4], p[5]}, D3{p[6], p[7], p[8]}};
         D3 B[3] = {D3{q[0], q[1], q[2]}, D3{q[3], q[4], q[5]}, D3{q[6], q[7], q[8]}};
         bool h;
         d[i] = pair_f64(A, B, h);
+        d_hi[i] = d[i];
         hit[i] = h ? 1 : 0;
     }
 }
 
-hipError_t launch_facet_pairs(const float *t1, const float *t2, int64_t n, int prec, double *d, int8_t *hit,
-                              hipStream_t st)
+hipError_t launch_facet_pairs(const float *t1, const float *t2, int64_t n, int prec, double *d, double *d_hi,
+                              int8_t *hit, hipStream_t st)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_facet_pairs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, t1, t2, n, prec, d, hit);
+    hipLaunchKernelGGL(k_facet_pairs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, t1, t2, n, prec, d, d_hi,
+                       hit);
     return hipGetLastError();
 }
 
