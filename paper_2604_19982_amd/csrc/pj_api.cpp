@@ -103,7 +103,8 @@ struct pj_context {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     DevBuf b_items, b_tiles, b_out, b_out64, b_ctr, b_cand_r, b_cand_s, b_cand_lb, b_cand_ub, b_blk, b_blkoff,
         b_total, b_tmp0, b_tmp1, b_tmp2, b_tmp3, b_coll, b_ovf, b_theta, b_koff, b_klb, b_kub, b_kst0, b_kst1,
-        b_kleft;
+        b_kleft,
+        b_sched;  // scheduling state of the FP32 rounds: workgroup slots, then A-block cursors
     // chunked streaming: two buffer sets, upload/download streams, pinned staging
     struct PinBuf {
         void *p = nullptr;
@@ -869,25 +870,16 @@ void plan_tiles(const pj_meshes *R, const pj_meshes *S, const std::vector<int> &
     pl.tiles.clear();
     pl.pairs = 0;
     pl.tile_s = TS;
-    // A blocks per tile: one, or as many as bring the round near the target
-    // tile count (a tile walks its A blocks one after the other)
     // register side: the object whose block padding wastes less
     auto swapped = [&](int64_t nr, int64_t ns) {
         const int64_t cr = (nr + BR - 1) / BR * BR * ns, cs = (ns + BR - 1) / BR * BR * nr;
         return allow_swap && cs < cr;
     };
-    int64_t ga = 1;
-    if (target_tiles > 0) {
-        int64_t n1 = 0;
-        for (const C &oc : order) {
-            const Cand &c = cand[act[oc.idx]];
-            const int64_t nr = R->count(c.r, lod), ns = S->count(c.s, lod);
-            const bool sw = swapped(nr, ns);
-            const int64_t nA = sw ? ns : nr, nB = sw ? nr : ns;
-            n1 += ((nA + BR - 1) / BR) * ((nB + TS - 1) / TS);
-        }
-        ga = std::max<int64_t>(1, n1 / target_tiles);
-    }
+    // A blocks per tile: one for the FP64 kernels (a workgroup per tile); the
+    // whole A side for the persistent FP32 rounds, whose waves claim a tile's
+    // A blocks one at a time and, once the list is used up, join the tiles
+    // still in progress (few large tiles cost less setup and still balance)
+    const int64_t ga = target_tiles > 0 ? (int64_t(1) << 40) : 1;
     for (const C &oc : order) {
         const int ci = act[oc.idx];
         const Cand &c = cand[ci];
@@ -920,8 +912,8 @@ void plan_tiles(const pj_meshes *R, const pj_meshes *S, const std::vector<int> &
     }
 }
 
-// Tiles per bulk round to aim for: 16 per resident wave keeps the
-// longest-first order balanced while bounding per-tile host work.
+// Tile-count hint of the persistent FP32 rounds (any positive value selects
+// their whole-A-side tiles; 16 per resident wave).
 int64_t tile_target(const pj_context *ctx, int wpc) { return (int64_t)ctx->num_cu * wpc * 16; }
 
 // ---------------------------------------------------------------------------
@@ -1327,7 +1319,7 @@ pj_status launch_round(pj_context *ctx, const RefineArgs &a, int32_t *ctr, int n
     // persistent grid: fixed size, the kernel reads the tile count from memory
     const int grid = ctx->num_cu * wpc;
     if (!graph) {
-        HIPTRY(ctx, launch_init_out(a.out, ni, nullptr, st));
+        HIPTRY(ctx, launch_init_round(a.out, ctr, a.wave_slot, grid, a.tile_cur, st));
         HIPTRY(ctx, launch_refine_f32(a, std::min<int64_t>(nt, grid), kP, st));
         return PJ_OK;
     }
@@ -1341,7 +1333,7 @@ pj_status launch_round(pj_context *ctx, const RefineArgs &a, int32_t *ctr, int n
         if (!ctx->cap_stream) HIPTRY(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
         hipGraph_t graph = nullptr;
         HIPTRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e1 = launch_init_out_dev(a.out, ctr + 6, ctx->cap_stream);
+        hipError_t e1 = launch_init_round(a.out, ctr, a.wave_slot, grid, a.tile_cur, ctx->cap_stream);
         hipError_t e2 = e1 == hipSuccess ? launch_refine_f32(a, grid, kP, ctx->cap_stream) : e1;
         hipError_t e3 = hipStreamEndCapture(ctx->cap_stream, &graph);
         if (e2 != hipSuccess) return hipfail(ctx, e2, "capture of the refinement round");
@@ -1383,7 +1375,9 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
     const bool hostR = R->host, hostS = S->host, staged = hostR || hostS;
     const int lod = pl.items[0].lod;
     const bool finest = pl.items[0].flags & IT_FINEST;
-    const int64_t per_tile = sizeof(Tile) + sizeof(Item) + sizeof(ItemOut);  // worst case: one item per tile
+    const int grid = ctx->num_cu * wpc;  // persistent grid of the rounds
+    // worst case one item per tile; each tile also has an A-block cursor
+    const int64_t per_tile = sizeof(Tile) + sizeof(Item) + sizeof(ItemOut);
     int64_t max_tiles = ctx->cfg.chunk_tiles > 0 ? ctx->cfg.chunk_tiles : int64_t(1) << 22;
     int64_t stage_budget = int64_t(1) << 30;
     if (ctx->cfg.mem_cap_bytes > 0) {
@@ -1393,13 +1387,17 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
         for (int b = 0; b < kMaxSets; ++b)
             for (DevBuf *x : {&ctx->sb_items[b], &ctx->sb_tiles[b], &ctx->sb_out[b], &ctx->sb_ctr[b], &ctx->sb_stage[b]})
                 x->release();
-        const int64_t per_set = (ctx->cfg.mem_cap_bytes - ctx->dev_bytes) / nsets - (5 * 256 + 64);
+        ctx->b_sched.release();
+        // the shared scheduling buffer: a slot per workgroup (reserved here)
+        // and a cursor per tile of a chunk (charged with each tile below)
+        const int64_t room = ctx->cfg.mem_cap_bytes - ctx->dev_bytes - 4 * grid - 256;
+        const int64_t per_set = room / nsets - (5 * 256 + 64);
         int64_t tile_part = per_set;
         if (staged) {
             stage_budget = per_set * 3 / 4;
             tile_part = per_set - stage_budget;
         }
-        max_tiles = std::min<int64_t>(max_tiles, tile_part / per_tile - 1);
+        max_tiles = std::min<int64_t>(max_tiles, tile_part / (per_tile + 4) - 1);
         if (max_tiles < 1 || (staged && stage_budget < 4 * kStageFixed))
             return fail(ctx, PJ_ERR_OUT_OF_MEMORY, "the memory cap cannot hold one refinement chunk");
     }
@@ -1523,6 +1521,8 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
             ht[t - c.t0] = x;
         }
         int32_t *hc = (int32_t *)ctx->pin_ctr[b].p;
+        // counter block: [1] tiles, [2..3] pairs evaluated, [4..5] chunks
+        // culled, [6] items, [10] next tile to take (all others 0)
         std::memset(hc, 0, 64);
         hc[1] = (int32_t)(c.t1 - c.t0);
         hc[6] = cni;
@@ -1554,6 +1554,11 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
         a.items = ptr<Item>(ctx->sb_items[b]);
         a.tiles = ptr<Tile>(ctx->sb_tiles[b]);
         a.ntiles = dctr + 1;
+        a.tile_next = dctr + 10;
+        // rounds run one after another on the join stream, so all chunks
+        // share one set of slots and cursors (reset by the round's init kernel)
+        a.wave_slot = ptr<int32_t>(ctx->b_sched);
+        a.tile_cur = ptr<int32_t>(ctx->b_sched) + grid;
         a.out = ptr<ItemOut>(ctx->sb_out[b]);
         a.pairs_done = reinterpret_cast<unsigned long long *>(dctr + 2);
         a.chunks_culled = reinterpret_cast<unsigned long long *>(dctr + 4);
@@ -1603,6 +1608,9 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
         merged[j] = 1;
         return PJ_OK;
     };
+    int64_t max_cnt = 0;
+    for (const Chunk &c : chunks) max_cnt = std::max<int64_t>(max_cnt, c.t1 - c.t0);
+    PJTRY(ensure(ctx, ctx->b_sched, 4 * (grid + max_cnt)));
     PJTRY(alloc(0));
     prep(0);
     std::thread worker;
@@ -1636,6 +1644,15 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
     }
     ctx->stats.tile_s_used = pl.tile_s;
     ctx->stats.waves_per_cu_used = wpc;
+    if (ctx->cfg.mem_cap_bytes > 0) {
+        // under a cap the chunk buffers were sized to what the cap left:
+        // give them back so that the next phase has the same room
+        HIPTRY(ctx, hipStreamSynchronize(st));
+        for (int b = 0; b < kMaxSets; ++b)
+            for (DevBuf *x : {&ctx->sb_items[b], &ctx->sb_tiles[b], &ctx->sb_out[b], &ctx->sb_ctr[b], &ctx->sb_stage[b]})
+                x->release();
+        ctx->b_sched.release();
+    }
     return PJ_OK;
 }
 
@@ -1720,6 +1737,7 @@ pj_status exact_finest_view(pj_context *ctx, const MeshDev &Rv, const MeshDev &S
     hipStream_t st = ctx->stream;
     const int ni = (int)pl.items.size(), nt = (int)pl.tiles.size();
     if (ni == 0) return PJ_OK;
+    const int cgrid = (int)std::min<int64_t>(nt, (int64_t)ctx->num_cu * ctx->cur.wpc);
     int64_t cap = std::max<int64_t>(1 << 20, 256 * (int64_t)ni);
     if (ctx->cfg.mem_cap_bytes > 0) {
         // the collect list takes what the cap leaves; items that overflow it
@@ -1729,7 +1747,7 @@ pj_status exact_finest_view(pj_context *ctx, const MeshDev &Rv, const MeshDev &S
                           &ctx->b_ctr})
             x->release();
         const int64_t fixed = (int64_t)(ni * (sizeof(Item) + sizeof(ItemOut) + sizeof(ItemOut64) + sizeof(int32_t)) +
-                                        nt * sizeof(Tile) + 64 + 7 * 256);
+                                        nt * (sizeof(Tile) + 4) + 64 + 4 * cgrid + 7 * 256);
         const int64_t room = ctx->cfg.mem_cap_bytes - ctx->dev_bytes - fixed;
         cap = std::min<int64_t>(cap, room / (int64_t)sizeof(PairRef));
         if (cap < 256) return fail(ctx, PJ_ERR_OUT_OF_MEMORY, "the memory cap leaves no room for the FP64 recheck");
@@ -1740,14 +1758,15 @@ pj_status exact_finest_view(pj_context *ctx, const MeshDev &Rv, const MeshDev &S
     PJTRY(ensure(ctx, ctx->b_out64, ni * sizeof(ItemOut64)));
     PJTRY(ensure(ctx, ctx->b_ovf, ni * sizeof(int32_t)));
     PJTRY(ensure(ctx, ctx->b_coll, cap * sizeof(PairRef)));
-    PJTRY(ensure(ctx, ctx->b_ctr, 64));
+    PJTRY(ensure(ctx, ctx->b_ctr, 64 + 4 * (cgrid + nt)));
     HIPTRY(ctx, hipMemcpyAsync(ctx->b_items.p, pl.items.data(), ni * sizeof(Item), hipMemcpyHostToDevice, st));
     HIPTRY(ctx, hipMemcpyAsync(ctx->b_tiles.p, pl.tiles.data(), nt * sizeof(Tile), hipMemcpyHostToDevice, st));
     int32_t *ctr = ptr<int32_t>(ctx->b_ctr);
     int32_t host_ctr[16] = {0, nt};
+    host_ctr[6] = ni;
     HIPTRY(ctx, hipMemcpyAsync(ctr, host_ctr, sizeof(host_ctr), hipMemcpyHostToDevice, st));
     HIPTRY(ctx, hipMemsetAsync(ctx->b_ovf.p, 0, ni * sizeof(int32_t), st));
-    HIPTRY(ctx, launch_init_out(ptr<ItemOut>(ctx->b_out), ni, nullptr, st));
+    HIPTRY(ctx, launch_init_round(ptr<ItemOut>(ctx->b_out), ctr, ctr + 16, cgrid, ctr + 16 + cgrid, st));
     HIPTRY(ctx, launch_init_out64(ptr<ItemOut64>(ctx->b_out64), ni, st));
     RefineArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -1756,6 +1775,9 @@ pj_status exact_finest_view(pj_context *ctx, const MeshDev &Rv, const MeshDev &S
     a.items = ptr<Item>(ctx->b_items);
     a.tiles = ptr<Tile>(ctx->b_tiles);
     a.ntiles = ctr + 1;
+    a.tile_next = ctr + 10;
+    a.wave_slot = ctr + 16;
+    a.tile_cur = ctr + 16 + cgrid;
     a.collected_n = reinterpret_cast<unsigned long long *>(ctr + 8);
     a.out = ptr<ItemOut>(ctx->b_out);
     a.pairs_done = reinterpret_cast<unsigned long long *>(ctr + 2);
@@ -1765,9 +1787,8 @@ pj_status exact_finest_view(pj_context *ctx, const MeshDev &Rv, const MeshDev &S
     a.collect_cap = cap;
     a.collected = ptr<PairRef>(ctx->b_coll);
     a.overflow = ptr<int32_t>(ctx->b_ovf);
-    const int grid = (int)std::min<int64_t>(nt, (int64_t)ctx->num_cu * ctx->cur.wpc);
     HIPTRY(ctx, hipEventRecord(ctx->ev0, st));
-    HIPTRY(ctx, launch_collect_f32(a, grid, st));
+    HIPTRY(ctx, launch_collect_f32(a, cgrid, st));
     HIPTRY(ctx, hipEventRecord(ctx->ev1, st));
     HIPTRY(ctx, hipMemcpyAsync(host_ctr, ctr, sizeof(host_ctr), hipMemcpyDeviceToHost, st));
     HIPTRY(ctx, hipStreamSynchronize(st));
@@ -1835,6 +1856,14 @@ pj_status exact_finest(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
                          return exact_finest_view(ctx, Rv, Sv, sp, ps, redo);
                      }));
     if (!redo.empty()) {
+        if (ctx->cfg.mem_cap_bytes > 0) {
+            // under a cap the collect list took all the room it could: give
+            // the collect buffers back before the full FP64 pass
+            HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+            for (DevBuf *x : {&ctx->b_items, &ctx->b_tiles, &ctx->b_out, &ctx->b_out64, &ctx->b_ovf, &ctx->b_coll,
+                              &ctx->b_ctr})
+                x->release();
+        }
         TilePlan p2;
         plan_tiles(R, S, redo, cand, ps, R->L - 1, 1, 64, pick_tile_s(ctx), true, p2);
         std::vector<ItemOut64> o2;
@@ -1844,6 +1873,12 @@ pj_status exact_finest(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
             p.hit64 = o2[k].hit;
             p.d64 = p.hit64 ? 0.0 : bits_to_double(o2[k].lb);
         }
+    }
+    if (ctx->cfg.mem_cap_bytes > 0) {
+        HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+        for (DevBuf *x : {&ctx->b_items, &ctx->b_tiles, &ctx->b_out, &ctx->b_out64, &ctx->b_ovf, &ctx->b_coll,
+                          &ctx->b_ctr, &ctx->sb_stage[0]})
+            x->release();
     }
     return PJ_OK;
 }

@@ -64,6 +64,9 @@ struct RefineArgs {
     const Item *items;
     const Tile *tiles;
     const int32_t *ntiles;   // device count (fixed-capacity buffers)
+    int32_t *tile_next;      // next tile to take (zeroed by the host before each launch)
+    int32_t *tile_cur;       // per tile: next A block to claim (zeroed before each launch)
+    int32_t *wave_slot;      // per workgroup: the multi-block tile it owns, -1 if none
     unsigned long long *collected_n;  // collect mode: pairs offered (64-bit, compared with the capacity)
     ItemOut *out;
     unsigned long long *pairs_done;  // facet pairs evaluated (device counter)
@@ -102,9 +105,10 @@ hipError_t launch_filter_sweep(const float *boxR, const float *ancR, const int32
                                float w_lo, float w_hi, int32_t *blk_count, const int64_t *blk_off, int32_t *cr,
                                int32_t *cs, float *clb, float *cub, int write_pass, hipStream_t st);
 hipError_t launch_scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t *total, int n, hipStream_t st);
-hipError_t launch_init_out(ItemOut *out, int n, int32_t *counter, hipStream_t st);
+hipError_t launch_init_round(ItemOut *out, const int32_t *ctr, int32_t *slots, int nslots, int32_t *cur,
+                             hipStream_t st);
 hipError_t launch_init_out64(ItemOut64 *out, int n, hipStream_t st);
-hipError_t launch_init_out_dev(ItemOut *out, const int32_t *n_ptr, hipStream_t st);
+
 hipError_t launch_refine_f32(const RefineArgs &a, int grid, int P, hipStream_t st);
 hipError_t launch_collect_f32(const RefineArgs &a, int grid, hipStream_t st);
 hipError_t launch_pairs_f64(const MeshDev &R, const MeshDev &S, const Item *items, const PairRef *pairs, int64_t n,

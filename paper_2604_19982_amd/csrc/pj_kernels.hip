@@ -522,33 +522,24 @@ hipError_t launch_scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t *tota
 // ---------------------------------------------------------------------------
 // Refinement outputs
 // ---------------------------------------------------------------------------
-__global__ void k_init_out(ItemOut *out, int n, int32_t *counter)
+// Per-round initialisation (a plain kernel, so that a captured graph
+// replays it): item results to +inf, A-block cursors to 0, workgroup slots to
+// -1.  The item and tile counts are read from the round's counter block
+// ([6] items, [1] tiles), so one graph serves every round size.
+__global__ void k_init_round(ItemOut *out, const int32_t *ctr, int32_t *slots, int nslots, int32_t *cur)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = ItemOut{0x7f800000u, 0x7f800000u, 0, 0};
-    if (i == 0 && counter) *counter = 0;
-}
-
-hipError_t launch_init_out(ItemOut *out, int n, int32_t *counter, hipStream_t st)
-{
-    int blocks = (n + 255) / 256;
-    if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(k_init_out, dim3(blocks), dim3(256), 0, st, out, n, counter);
-    return hipGetLastError();
-}
-
-// grid-stride initialisation whose count lives in device memory, so that a
-// captured graph replays it for any round size
-__global__ void k_init_out_dev(ItemOut *out, const int32_t *n_ptr)
-{
-    const int n = *n_ptr;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    const int ni = ctr[6], nt = ctr[1];
+    const int stride = gridDim.x * blockDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ni; i += stride)
         out[i] = ItemOut{0x7f800000u, 0x7f800000u, 0, 0};
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += stride) cur[i] = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nslots; i += stride) slots[i] = -1;
 }
 
-hipError_t launch_init_out_dev(ItemOut *out, const int32_t *n_ptr, hipStream_t st)
+hipError_t launch_init_round(ItemOut *out, const int32_t *ctr, int32_t *slots, int nslots, int32_t *cur,
+                             hipStream_t st)
 {
-    hipLaunchKernelGGL(k_init_out_dev, dim3(256), dim3(256), 0, st, out, n_ptr);
+    hipLaunchKernelGGL(k_init_round, dim3(256), dim3(256), 0, st, out, ctr, slots, nslots, cur);
     return hipGetLastError();
 }
 
@@ -653,8 +644,13 @@ __device__ __forceinline__ bool chunk_cut(float g, float bph, float aph, float c
     return g > ub_cut && fmaxf(g - aph - bph, 0.0f) > lb_cut;
 }
 
+// The A blocks of a tile with more than one are claimed one at a time from
+// the tile's cursor, so other waves can take part in a tile once the list is
+// used up; the owner (the wave that took the tile from the list) shows the
+// tile in its workgroup slot until the cursor is exhausted.
 template <int P, bool COLLECT>
-__device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t, float4 *sh, int *qidx)
+__device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t, float4 *sh, int *qidx, bool owner,
+                                                unsigned long long &pairs_acc, unsigned long long &culled_acc)
 {
     const int lane = threadIdx.x;
     const Tile tl = a.tiles[t];
@@ -675,7 +671,17 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
     const bool finest = it.flags & IT_FINEST;
     bool stop = false;
     // the tile's A facets, one register block of 64P at a time
-    for (int a0 = tl.a0; a0 < tl.a1 && !stop; a0 += 64 * P) {
+    const int nblk = (tl.a1 - tl.a0 + 64 * P - 1) / (64 * P);
+    if (owner && nblk > 1 && lane == 0) __hip_atomic_store(a.wave_slot + blockIdx.x, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int k = 0;; ++k) {
+        int j = k;
+        if (nblk > 1) {
+            int c = 0;
+            if (lane == 0) c = atomicAdd(a.tile_cur + t, 1);
+            j = __builtin_amdgcn_readfirstlane(c);
+        }
+        if (j >= nblk || stop) break;
+        const int a0 = tl.a0 + j * 64 * P;
         int cols = 0;
         // the A records are built when the first chunk survives its test, so a
         // block whose chunks are all culled costs only block-record reads
@@ -863,29 +869,84 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
         qn = 0;
         npairs += (unsigned long long)min(64 * P, SA.n - a0) * (unsigned long long)cols;
     }  // A blocks
+    if (owner && nblk > 1 && lane == 0) __hip_atomic_store(a.wave_slot + blockIdx.x, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const float wl = wave_min(lbm), wu = wave_min(ubm);
     const int ws = wave_or(sure);
     if (lane == 0) {
         atomicMin(&o->lb, fbits(wl));
         atomicMin(&o->ub, fbits(wu));
         if (ws) atomicOr(&o->hit, 1);
-        atomicAdd(a.pairs_done, npairs);
-        if (culled) atomicAdd(a.chunks_culled, (unsigned long long)culled);
+    }
+    pairs_acc += npairs;
+    culled_acc += (unsigned long long)culled;
+}
+
+// Persistent single-wave workgroups take tiles from the list (longest items
+// first) in order, each fetching the next index with one atomic on a counter
+// that the host zeroes before the launch, so a wave that finishes early takes
+// more tiles.  Lane 0 fetches and readfirstlane makes the index uniform: the
+// loop control is scalar and every lane runs the same tiles.  The fetch for
+// the next tile is issued before the current one is processed.
+//
+// Once the list is used up, the wave makes one pass over the workgroup slots
+// and joins every tile that still has unclaimed A blocks, so a tile whose
+// facets meet over a large area (most of its pairs survive culling) is
+// finished by many waves instead of holding one to the end of the launch.
+// Termination: every fetch raises the list counter; every claim raises a
+// tile cursor; the pass visits each slot at most once.
+template <int P, bool COLLECT>
+__device__ __forceinline__ void refine_tiles(const RefineArgs &a, float4 *sh, int *qidx)
+{
+    const int ntiles = *a.ntiles;
+    // launch-wide statistics, published once per wave
+    unsigned long long pairs_acc = 0, culled_acc = 0;
+    int t0 = 0;
+    if (threadIdx.x == 0) t0 = atomicAdd(a.tile_next, 1);
+    int t = __builtin_amdgcn_readfirstlane(t0);
+    while (t < ntiles) {
+        int nxt = 0;
+        if (threadIdx.x == 0) nxt = atomicAdd(a.tile_next, 1);
+        refine_tile_f32<P, COLLECT>(a, t, sh, qidx, true, pairs_acc, culled_acc);
+        t = __builtin_amdgcn_readfirstlane(nxt);
+    }
+    // one pass over the slots, starting at this workgroup's own so that the
+    // helpers spread over the tiles in progress
+    const int nslot = gridDim.x;
+    for (int h = 0; h < nslot;) {
+        const int hw = h + (int)threadIdx.x;
+        int w = hw + (int)blockIdx.x;
+        if (w >= nslot) w -= nslot;
+        int c = -1;
+        if (hw < nslot) {
+            const int tt = __hip_atomic_load(a.wave_slot + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (tt >= 0 && tt < ntiles) {
+                const Tile x = a.tiles[tt];
+                const int nb = (x.a1 - x.a0 + 64 * P - 1) / (64 * P);
+                if (__hip_atomic_load(a.tile_cur + tt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < nb) c = tt;
+            }
+        }
+        const unsigned long long m = __ballot(c >= 0);
+        if (m == 0ull) {
+            h += 64;
+            continue;
+        }
+        const int l = __builtin_ctzll(m);
+        const int tt = __builtin_amdgcn_readlane(c, l);
+        refine_tile_f32<P, COLLECT>(a, tt, sh, qidx, false, pairs_acc, culled_acc);
+        h += l + 1;
+    }
+    if (threadIdx.x == 0) {
+        if (pairs_acc) atomicAdd(a.pairs_done, pairs_acc);
+        if (culled_acc) atomicAdd(a.chunks_culled, culled_acc);
     }
 }
 
-// Persistent single-wave workgroups walk the tile list (longest items
-// first) with a static stride of the grid size.  The loop index depends only
-// on blockIdx, so the loop control is scalar.  (A queue whose index lane 0
-// fetched and broadcast let the compiler split the loop on the lane-0 test,
-// after which lanes 1..63 re-ran tile 0 without end.)
 template <int P>
 __global__ __launch_bounds__(64) void k_refine_f32(RefineArgs a)
 {
     __shared__ float4 sh[64 * 11];
     __shared__ int qidx[128];
-    const int ntiles = *a.ntiles;
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) refine_tile_f32<P, false>(a, t, sh, qidx);
+    refine_tiles<P, false>(a, sh, qidx);
 }
 
 // Collect pass: the same tiles, keeping every facet pair whose FP32 lower
@@ -894,8 +955,7 @@ __global__ __launch_bounds__(64) void k_collect_f32(RefineArgs a)
 {
     __shared__ float4 sh[64 * 11];
     __shared__ int qidx[128];
-    const int ntiles = *a.ntiles;
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) refine_tile_f32<1, true>(a, t, sh, qidx);
+    refine_tiles<1, true>(a, sh, qidx);
 }
 
 hipError_t launch_collect_f32(const RefineArgs &a, int grid, hipStream_t st)
