@@ -2191,14 +2191,15 @@ pj_status learned_start(pj_context *ctx, const pj_meshes *R, const pj_meshes *S,
     if (n == 0) return PJ_OK;
     hipStream_t st = ctx->stream;
     std::vector<float> x((size_t)n * MLP_IN), cost((size_t)n * MLP_OUT);
-    for (int q = 0; q < n; ++q) {
+    // features on the host threads (each candidate writes its own rows)
+    parallel_for(n, prep_threads(ctx), [&](int64_t q) {
         const Cand &c = cand[idx[q]];
         float f[MLP_IN];
         pair_features(R, c.r, S, c.s, tau, c.lb0, c.ub0, f);
         for (int j = 0; j < MLP_IN; ++j) x[(size_t)q * MLP_IN + j] = (f[j] - ctx->feat_mean[j]) / ctx->feat_std[j];
         for (int l = 0; l < MLP_OUT; ++l)
             cost[(size_t)q * MLP_OUT + l] = (float)((double)R->count(c.r, l) * (double)S->count(c.s, l));
-    }
+    });
     PJTRY(ensure(ctx, ctx->b_tmp0, (size_t)n * MLP_IN * 4));
     PJTRY(ensure(ctx, ctx->b_tmp1, (size_t)n * MLP_OUT * 4 * 2 + (size_t)n * 4));
     PJTRY(ensure(ctx, ctx->b_tmp2, MLP_NPARAM * 4));
