@@ -117,7 +117,7 @@ struct pj_context {
                ev_k1[kMaxSets] = {};
     // launch shape of the bulk rounds: explicit config > tuned > defaults
     struct Shape {
-        int tile_s = 1024, wpc = 12;
+        int tile_s = 1024, wpc = 8;
     };
     Shape cur;
     std::map<std::string, Shape> tuned;
@@ -924,9 +924,15 @@ int64_t tile_target(const pj_context *ctx, int wpc) { return (int64_t)ctx->num_c
 // best of two) and keeps the fastest.  Results never depend on the shape: the per-item minima are
 // order independent.  The cache is a text file of lines
 // "<class> <tile_s> <waves_per_cu> <ms>".
+// B ranges below 1024 facets are not offered: on a sample they win by
+// parallelism, but over a full round many small tiles of one pair start
+// before its running minimum has tightened and cull far less (the finest
+// k-NN round of 20k x 20k evaluated 1.6x the pairs at 256).
 // ---------------------------------------------------------------------------
-constexpr int kTuneTS[] = {256, 512, 1024, 2048, 4096, 8192, 16384, 65536};
-constexpr int kTuneWPC[] = {4, 8, 12, 16, 24};
+constexpr int kTuneTS[] = {1024, 2048, 4096, 8192, 16384};
+// waves per CU: the refinement kernel holds two waves per SIMD (eight per
+// CU), so a larger grid only queues waves that find the list used up
+constexpr int kTuneWPC[] = {4, 8, 16};
 
 void load_tune_cache(pj_context *ctx)
 {
@@ -997,16 +1003,17 @@ pj_status choose_shape(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
         const pj_stats saved = ctx->stats;
         double best = INFINITY;
         pj_context::Shape bs;
-        for (int ts : kTuneTS) {
-            if (cfg_ts && ts != cfg_ts) continue;
+        std::vector<int> ts_list(std::begin(kTuneTS), std::end(kTuneTS)), wpc_list(std::begin(kTuneWPC), std::end(kTuneWPC));
+        if (cfg_ts) ts_list.assign(1, cfg_ts);  // an explicit value is the only candidate
+        if (cfg_wpc) wpc_list.assign(1, cfg_wpc);
+        for (int ts : ts_list) {
             // wall time of planning + the streamed round (host work per tile
             // counts as much as the kernel when items have many tiles)
             const double tp = now_ms();
             TilePlan pl;
             plan_tiles(R, S, sample, cand, ps, lod, finest, 64 * kP, ts, true, pl, tile_target(ctx, 12));
             const double plan_ms = now_ms() - tp;
-            for (int wpc : kTuneWPC) {
-                if (cfg_wpc && wpc != cfg_wpc) continue;
+            for (int wpc : wpc_list) {
                 double t = INFINITY;
                 for (int rep = 0; rep < 2; ++rep) {
                     std::vector<ItemOut> out;
