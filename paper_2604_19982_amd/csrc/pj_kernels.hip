@@ -558,11 +558,12 @@ hipError_t launch_init_out64(ItemOut64 *out, int n, hipStream_t st)
 
 // ---------------------------------------------------------------------------
 // FP32 refinement: persistent single-wave workgroups pull tiles from a queue.
-// A tile = 64*P facets of object A (P per lane, records in registers) x a
-// range of facets of object B, streamed through LDS 64 at a time (each lane
-// builds one record; all lanes then read every record by broadcast).  Per
-// lane running minima of lb and ub (Eq. (2), Eq. (1)) are reduced across the
-// wave with cross-lane min and merged into the item by atomicMin.
+// A tile = the A facets of one (pair, LoD) item, taken in register blocks of
+// 64*P (P per lane) that any wave may claim, x a range of facets of object B,
+// streamed through LDS 64 at a time (each lane builds one record; all lanes
+// then read every record by broadcast).  Per lane running minima of lb and
+// ub (Eq. (2), Eq. (1)) are reduced across the wave with cross-lane min and
+// merged into the item by atomicMin.
 // ---------------------------------------------------------------------------
 struct FacetSrc {
     const int32_t *tris;
