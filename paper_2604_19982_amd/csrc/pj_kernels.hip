@@ -726,6 +726,11 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
                     sh[lane * 11 + q] = make_float4(tmp[4 * q], tmp[4 * q + 1], tmp[4 * q + 2], tmp[4 * q + 3]);
             }
             __syncthreads();
+            // the item's done flag, read now and used after the pair loop (a
+            // stale value costs at most one more flush), so the load's latency
+            // is hidden behind the loop
+            int done_pre = 0;
+            if (!COLLECT && a.early) done_pre = __hip_atomic_load(&o->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll 1
             for (int k = 0; k < n; ++k) {
                 float tmp[44];
@@ -776,8 +781,7 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
                 if (confirm) {
                     if (lane == 0) __hip_atomic_store(&o->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     stop = true;
-                } else if (__builtin_amdgcn_readfirstlane(
-                               __hip_atomic_load(&o->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                } else if (__builtin_amdgcn_readfirstlane(done_pre)) {
                     stop = true;
                 }
             }
@@ -869,6 +873,7 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
         if (qn > 0 && !stop) flush(qn);
         qn = 0;
         npairs += (unsigned long long)min(64 * P, SA.n - a0) * (unsigned long long)cols;
+        if (j == nblk - 1) break;  // this wave took the last block: no claim is left to try
     }  // A blocks
     if (owner && nblk > 1 && lane == 0) __hip_atomic_store(a.wave_slot + blockIdx.x, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const float wl = wave_min(lbm), wu = wave_min(ubm);
