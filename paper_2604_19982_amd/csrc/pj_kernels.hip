@@ -650,7 +650,7 @@ __device__ __forceinline__ bool chunk_cut(float g, float bph, float aph, float c
 // used up; the owner (the wave that took the tile from the list) shows the
 // tile in its workgroup slot until the cursor is exhausted.
 template <int P, bool COLLECT>
-__device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t, float4 *sh, int *qidx, bool owner,
+__device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t, float4 *sh, float4 *qv, bool owner,
                                                 unsigned long long &pairs_acc, unsigned long long &culled_acc)
 {
     const int lane = threadIdx.x;
@@ -698,9 +698,10 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
             ahi = make_float4(fmaxf(ahi.x, h2.x), fmaxf(ahi.y, h2.y), fmaxf(ahi.z, h2.z), fmaxf(ahi.w, h2.w));
         }
         const float aph = ahi.w;
-        // Surviving B facets wait in an LDS queue (qidx) and are evaluated 64
-        // at a time: their records are built by all lanes at once, then every
-        // lane runs its A facet against each of them.
+        // Surviving B facets wait in an LDS queue (qv: corners, hd, ph and
+        // index, as gathered for the facet test) and are evaluated 64 at a
+        // time: their records are built by all lanes at once, then every lane
+        // runs its A facet against each of them.
         int qn = 0;
         auto flush = [&](const int n) {
             if (!built) {
@@ -713,12 +714,10 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
                 built = true;
             }
             if (lane < n) {
-                const int f = qidx[lane];
-                const int32_t i0 = SB.tris[3 * f], i1 = SB.tris[3 * f + 1], i2 = SB.tris[3 * f + 2];
-                const V3 w0 = ld3f(SB.verts, i0), w1 = ld3f(SB.verts, i1), w2 = ld3f(SB.verts, i2);
-                const float2 bh = SB.hdph ? SB.hdph[f] : make_float2(0.0f, 0.0f);
-                Rec rb = make_rec(w0 - org, w1 - org, w2 - org, bh.x, bh.y);
-                rb.pad = __int_as_float(f);
+                const float4 q0 = qv[3 * lane], q1 = qv[3 * lane + 1], q2 = qv[3 * lane + 2];
+                const V3 w0{q0.x, q0.y, q0.z}, w1{q0.w, q1.x, q1.y}, w2{q1.z, q1.w, q2.x};
+                Rec rb = make_rec(w0 - org, w1 - org, w2 - org, q2.y, q2.z);
+                rb.pad = q2.w;
                 float tmp[44];
                 __builtin_memcpy(tmp, &rb, sizeof(tmp));
 #pragma unroll
@@ -832,12 +831,14 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
                 int f = cb + lane;
                 if (f >= tl.b1) f = cb;
                 // Facet culling: the same two-sided test with this facet's own
-                // box and ph against the A block; survivors join the LDS queue.
+                // box and ph against the A block; survivors join the LDS queue
+                // with the corners and bounds gathered here.
                 bool keep = lane < nb;
+                const int32_t i0 = SB.tris[3 * f], i1 = SB.tris[3 * f + 1], i2 = SB.tris[3 * f + 2];
+                const V3 w0 = ld3f(SB.verts, i0), w1 = ld3f(SB.verts, i1), w2 = ld3f(SB.verts, i2);
+                const float2 bh = SB.hdph ? SB.hdph[f] : make_float2(0.0f, 0.0f);
                 if (a.cull) {
-                    const int32_t i0 = SB.tris[3 * f], i1 = SB.tris[3 * f + 1], i2 = SB.tris[3 * f + 2];
-                    const V3 w0 = ld3f(SB.verts, i0), w1 = ld3f(SB.verts, i1), w2 = ld3f(SB.verts, i2);
-                    const float bph = SB.hdph ? SB.hdph[f].y : 0.0f;
+                    const float bph = bh.y;
                     const float4 flo = make_float4(fminf(fminf(w0.x, w1.x), w2.x), fminf(fminf(w0.y, w1.y), w2.y),
                                                    fminf(fminf(w0.z, w1.z), w2.z), 0.0f);
                     const float4 fhi = make_float4(fmaxf(fmaxf(w0.x, w1.x), w2.x), fmaxf(fmaxf(w0.y, w1.y), w2.y),
@@ -852,9 +853,11 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
                     continue;
                 }
                 if (keep) {
-                    const int pos = __builtin_amdgcn_mbcnt_hi((unsigned)(kmask >> 32),
-                                                              __builtin_amdgcn_mbcnt_lo((unsigned)kmask, 0u));
-                    qidx[qn + pos] = f;
+                    const int pos = qn + __builtin_amdgcn_mbcnt_hi((unsigned)(kmask >> 32),
+                                                                   __builtin_amdgcn_mbcnt_lo((unsigned)kmask, 0u));
+                    qv[3 * pos] = make_float4(w0.x, w0.y, w0.z, w1.x);
+                    qv[3 * pos + 1] = make_float4(w1.y, w1.z, w2.x, w2.y);
+                    qv[3 * pos + 2] = make_float4(w2.z, bh.x, bh.y, __int_as_float(f));
                 }
                 qn += nk;
                 __syncthreads();
@@ -862,9 +865,18 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
                     flush(64);
                     // move the rest of the queue to its front
                     const int rest = qn - 64;
-                    const int v = lane < rest ? qidx[64 + lane] : 0;
+                    float4 v0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), v1 = v0, v2 = v0;
+                    if (lane < rest) {
+                        v0 = qv[3 * (64 + lane)];
+                        v1 = qv[3 * (64 + lane) + 1];
+                        v2 = qv[3 * (64 + lane) + 2];
+                    }
                     __syncthreads();
-                    if (lane < rest) qidx[lane] = v;
+                    if (lane < rest) {
+                        qv[3 * lane] = v0;
+                        qv[3 * lane + 1] = v1;
+                        qv[3 * lane + 2] = v2;
+                    }
                     __syncthreads();
                     qn = rest;
                 }
@@ -901,7 +913,7 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
 // Termination: every fetch raises the list counter; every claim raises a
 // tile cursor; the pass visits each slot at most once.
 template <int P, bool COLLECT>
-__device__ __forceinline__ void refine_tiles(const RefineArgs &a, float4 *sh, int *qidx)
+__device__ __forceinline__ void refine_tiles(const RefineArgs &a, float4 *sh, float4 *qv)
 {
     const int ntiles = *a.ntiles;
     // launch-wide statistics, published once per wave
@@ -912,7 +924,7 @@ __device__ __forceinline__ void refine_tiles(const RefineArgs &a, float4 *sh, in
     while (t < ntiles) {
         int nxt = 0;
         if (threadIdx.x == 0) nxt = atomicAdd(a.tile_next, 1);
-        refine_tile_f32<P, COLLECT>(a, t, sh, qidx, true, pairs_acc, culled_acc);
+        refine_tile_f32<P, COLLECT>(a, t, sh, qv, true, pairs_acc, culled_acc);
         t = __builtin_amdgcn_readfirstlane(nxt);
     }
     // one pass over the slots, starting at this workgroup's own so that the
@@ -938,7 +950,7 @@ __device__ __forceinline__ void refine_tiles(const RefineArgs &a, float4 *sh, in
         }
         const int l = __builtin_ctzll(m);
         const int tt = __builtin_amdgcn_readlane(c, l);
-        refine_tile_f32<P, COLLECT>(a, tt, sh, qidx, false, pairs_acc, culled_acc);
+        refine_tile_f32<P, COLLECT>(a, tt, sh, qv, false, pairs_acc, culled_acc);
         h += l + 1;
     }
     if (threadIdx.x == 0) {
@@ -951,8 +963,8 @@ template <int P>
 __global__ __launch_bounds__(64) void k_refine_f32(RefineArgs a)
 {
     __shared__ float4 sh[64 * 11];
-    __shared__ int qidx[128];
-    refine_tiles<P, false>(a, sh, qidx);
+    __shared__ float4 qv[128 * 3];
+    refine_tiles<P, false>(a, sh, qv);
 }
 
 // Collect pass: the same tiles, keeping every facet pair whose FP32 lower
@@ -960,8 +972,8 @@ __global__ __launch_bounds__(64) void k_refine_f32(RefineArgs a)
 __global__ __launch_bounds__(64) void k_collect_f32(RefineArgs a)
 {
     __shared__ float4 sh[64 * 11];
-    __shared__ int qidx[128];
-    refine_tiles<1, true>(a, sh, qidx);
+    __shared__ float4 qv[128 * 3];
+    refine_tiles<1, true>(a, sh, qv);
 }
 
 hipError_t launch_collect_f32(const RefineArgs &a, int grid, hipStream_t st)
