@@ -9,7 +9,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <condition_variable>
+#include <functional>
+#include <memory>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -92,7 +97,81 @@ struct pj_meshes {
 
 constexpr int kMaxSets = 3;  // staging buffer sets of the streamed rounds
 
+// Persistent host workers for the per-candidate loops of a join (thread
+// creation would cost more than the loop).  One job at a time, from the
+// thread that owns the context; the caller works on the job too.  Every
+// worker takes part in every job (a generation count wakes them) and the
+// caller returns only once all of them have finished it, so the job's fields
+// never change while a worker reads them.
+struct HostPool {
+    std::vector<std::thread> th;
+    std::mutex m;
+    std::condition_variable go, done;
+    const std::function<void(int64_t)> *job = nullptr;
+    int64_t n = 0, chunk = 1;
+    std::atomic<int64_t> next{0};
+    uint64_t gen = 0;
+    size_t finished = 0;
+    bool quit = false;
+
+    explicit HostPool(int workers)
+    {
+        for (int w = 0; w < workers; ++w)
+            th.emplace_back([this] {
+                uint64_t seen = 0;
+                for (;;) {
+                    {
+                        std::unique_lock<std::mutex> lk(m);
+                        go.wait(lk, [&] { return quit || gen != seen; });
+                        if (quit) return;
+                        seen = gen;
+                    }
+                    work();
+                    std::lock_guard<std::mutex> lk(m);
+                    if (++finished == th.size()) done.notify_all();
+                }
+            });
+    }
+    ~HostPool()
+    {
+        {
+            std::lock_guard<std::mutex> lk(m);
+            quit = true;
+        }
+        go.notify_all();
+        for (auto &t : th) t.join();
+    }
+    void work()
+    {
+        for (;;) {
+            const int64_t i0 = next.fetch_add(chunk);
+            if (i0 >= n) return;
+            const int64_t i1 = std::min(n, i0 + chunk);
+            for (int64_t i = i0; i < i1; ++i) (*job)(i);
+        }
+    }
+    void run(int64_t count, const std::function<void(int64_t)> &f)
+    {
+        if (count <= 0) return;
+        {
+            std::lock_guard<std::mutex> lk(m);
+            job = &f;
+            n = count;
+            chunk = std::max<int64_t>(1, count / (int64_t)(8 * (th.size() + 1)));
+            next.store(0);
+            finished = 0;
+            ++gen;
+        }
+        go.notify_all();
+        work();
+        std::unique_lock<std::mutex> lk(m);
+        done.wait(lk, [&] { return finished == th.size(); });
+        job = nullptr;
+    }
+};
+
 struct pj_context {
+    std::unique_ptr<HostPool> pool;  // created on first use
     pj_config cfg;
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -2198,8 +2277,9 @@ pj_status learned_start(pj_context *ctx, const pj_meshes *R, const pj_meshes *S,
     if (n == 0) return PJ_OK;
     hipStream_t st = ctx->stream;
     std::vector<float> x((size_t)n * MLP_IN), cost((size_t)n * MLP_OUT);
-    // features on the host threads (each candidate writes its own rows)
-    parallel_for(n, prep_threads(ctx), [&](int64_t q) {
+    // features on the host workers (each candidate writes its own rows)
+    if (!ctx->pool) ctx->pool.reset(new HostPool(std::max(0, prep_threads(ctx) - 1)));
+    ctx->pool->run(n, [&](int64_t q) {
         const Cand &c = cand[idx[q]];
         float f[MLP_IN];
         pair_features(R, c.r, S, c.s, tau, c.lb0, c.ub0, f);
@@ -2245,18 +2325,16 @@ extern "C" pj_status pj_join_within(pj_context *ctx, const pj_meshes *R, const p
     ctx->stats.candidates = nc;
     std::vector<PairState> ps(nc);
     std::vector<int> start(nc, 0);
-    for (int i = 0; i < nc; ++i) {
+    if (!ctx->pool) ctx->pool.reset(new HostPool(std::max(0, prep_threads(ctx) - 1)));
+    ctx->pool->run(nc, [&](int64_t i) {
         pair_frame(R, cand[i].r, S, cand[i].s, ps[i]);
         ps[i].LB = cand[i].lb0;
         ps[i].UB = cand[i].ub0;
         // the anchors are surface points: their distance bounds d from above
-        if (cand[i].ub0 <= tau) {
-            ps[i].status = ST_CONF;
-            ctx->stats.confirmed_filter++;
-        } else if (cand[i].lb0 > tau) {
-            ps[i].status = ST_PRUNED;
-        }
-    }
+        if (cand[i].ub0 <= tau) ps[i].status = ST_CONF;
+        else if (cand[i].lb0 > tau) ps[i].status = ST_PRUNED;
+    });
+    for (int i = 0; i < nc; ++i) ctx->stats.confirmed_filter += ps[i].status == ST_CONF;
     const bool learned = ctx->cfg.learned_skip && ctx->has_model && R->L == MLP_OUT &&
                          ctx->cfg.schedule == PJ_SCHED_BATCHED;
     if (learned) PJTRY(learned_start(ctx, R, S, tau, cand, ps, start));
