@@ -1070,18 +1070,20 @@ pj_status choose_shape(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
         sh = it->second;
     } else if (ctx->cfg.autotune && !act.empty()) {
         const double t0 = now_ms();
-        // sample: items spread over the round, up to about 2e9 facet pairs
+        // sample: items spread over the round, up to about 8e9 facet pairs
+        // (large enough that a candidate's time is not launch overhead)
         std::vector<int> idx(act.begin(), act.end());
         std::vector<int> sample;
         double pairs = 0.0;
-        const size_t stride = std::max<size_t>(1, idx.size() / 4096);
-        for (size_t i = 0; i < idx.size() && pairs < 2e9; i += stride) {
+        const size_t stride = std::max<size_t>(1, idx.size() / 8192);
+        for (size_t i = 0; i < idx.size() && pairs < 8e9; i += stride) {
             sample.push_back(idx[i]);
             pairs += (double)R->count(cand[idx[i]].r, lod) * (double)S->count(cand[idx[i]].s, lod);
         }
         const pj_stats saved = ctx->stats;
-        double best = INFINITY;
+        double best = INFINITY, t_default = INFINITY;
         pj_context::Shape bs;
+        const pj_context::Shape def{};
         std::vector<int> ts_list(std::begin(kTuneTS), std::end(kTuneTS)), wpc_list(std::begin(kTuneWPC), std::end(kTuneWPC));
         if (cfg_ts) ts_list.assign(1, cfg_ts);  // an explicit value is the only candidate
         if (cfg_wpc) wpc_list.assign(1, cfg_wpc);
@@ -1094,7 +1096,7 @@ pj_status choose_shape(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
             const double plan_ms = now_ms() - tp;
             for (int wpc : wpc_list) {
                 double t = INFINITY;
-                for (int rep = 0; rep < 2; ++rep) {
+                for (int rep = 0; rep < 3; ++rep) {
                     std::vector<ItemOut> out;
                     HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
                     const double tr = now_ms();
@@ -1105,7 +1107,14 @@ pj_status choose_shape(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
                     best = t;
                     bs = pj_context::Shape{ts, wpc};
                 }
+                if (ts == def.tile_s && wpc == def.wpc) t_default = t;
             }
+        }
+        // within 3% the default wins: run-to-run timing noise should not
+        // move the shape
+        if (t_default <= 1.03 * best) {
+            bs = def;
+            best = t_default;
         }
         ctx->stats = saved;
         ctx->stats.t_tune_ms += now_ms() - t0;
