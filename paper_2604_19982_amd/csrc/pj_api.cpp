@@ -954,11 +954,12 @@ void plan_tiles(const pj_meshes *R, const pj_meshes *S, const std::vector<int> &
         const int64_t cr = (nr + BR - 1) / BR * BR * ns, cs = (ns + BR - 1) / BR * BR * nr;
         return allow_swap && cs < cr;
     };
-    // A blocks per tile: one for the FP64 kernels (a workgroup per tile); the
-    // whole A side for the persistent FP32 rounds, whose waves claim a tile's
-    // A blocks one at a time and, once the list is used up, join the tiles
-    // still in progress (few large tiles cost less setup and still balance)
-    const int64_t ga = target_tiles > 0 ? (int64_t(1) << 40) : 1;
+    // A side of a tile: one block for the FP64 kernels (a workgroup per
+    // tile); the whole A side for the persistent FP32 rounds, whose waves
+    // claim a tile's A blocks one at a time and, once the list is used up,
+    // join the tiles still in progress (few large tiles cost less setup and
+    // still balance)
+    const bool whole_a = target_tiles > 0;
     for (const C &oc : order) {
         const int ci = act[oc.idx];
         const Cand &c = cand[ci];
@@ -981,7 +982,7 @@ void plan_tiles(const pj_meshes *R, const pj_meshes *S, const std::vector<int> &
         const int item = (int)pl.items.size();
         pl.items.push_back(it);
         const int nA = swap ? ns : nr, nB = swap ? nr : ns;
-        const int64_t astep = (int64_t)BR * ga;
+        const int64_t astep = whole_a ? (int64_t)nA : (int64_t)BR;
         for (int64_t a0 = 0; a0 < nA; a0 += astep) {
             const int a1 = (int)std::min<int64_t>(nA, a0 + astep);
             for (int b0 = 0; b0 < nB; b0 += TS)
