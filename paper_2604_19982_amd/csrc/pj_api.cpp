@@ -1309,6 +1309,19 @@ int prep_threads(pj_context *ctx)
     return std::max(1, std::min(t, 16));
 }
 
+// A per-candidate host loop of a join: serial when short, else on the
+// context's persistent workers (at most 7 besides the caller; created on the
+// first long loop).
+void host_for(pj_context *ctx, int64_t n, const std::function<void(int64_t)> &f)
+{
+    if (n < 2048 || prep_threads(ctx) <= 1) {
+        for (int64_t i = 0; i < n; ++i) f(i);
+        return;
+    }
+    if (!ctx->pool) ctx->pool.reset(new HostPool(std::min(7, prep_threads(ctx) - 1)));
+    ctx->pool->run(n, f);
+}
+
 // Items of a plan split into groups whose staged objects fit `budget`; each
 // group is staged (synchronously, buffer set 0) and handed to fn with a
 // sub-plan whose object ids are local to the staged views, and the plan
@@ -2288,8 +2301,7 @@ pj_status learned_start(pj_context *ctx, const pj_meshes *R, const pj_meshes *S,
     hipStream_t st = ctx->stream;
     std::vector<float> x((size_t)n * MLP_IN), cost((size_t)n * MLP_OUT);
     // features on the host workers (each candidate writes its own rows)
-    if (!ctx->pool) ctx->pool.reset(new HostPool(std::max(0, prep_threads(ctx) - 1)));
-    ctx->pool->run(n, [&](int64_t q) {
+    host_for(ctx, n, [&](int64_t q) {
         const Cand &c = cand[idx[q]];
         float f[MLP_IN];
         pair_features(R, c.r, S, c.s, tau, c.lb0, c.ub0, f);
@@ -2335,8 +2347,7 @@ extern "C" pj_status pj_join_within(pj_context *ctx, const pj_meshes *R, const p
     ctx->stats.candidates = nc;
     std::vector<PairState> ps(nc);
     std::vector<int> start(nc, 0);
-    if (!ctx->pool) ctx->pool.reset(new HostPool(std::max(0, prep_threads(ctx) - 1)));
-    ctx->pool->run(nc, [&](int64_t i) {
+    host_for(ctx, nc, [&](int64_t i) {
         pair_frame(R, cand[i].r, S, cand[i].s, ps[i]);
         ps[i].LB = cand[i].lb0;
         ps[i].UB = cand[i].ub0;
