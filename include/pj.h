@@ -226,8 +226,9 @@ pj_status pj_meshes_hdph(const pj_meshes *m, int32_t obj, int32_t lod, float *hd
 /* Distance of n triangle pairs (t1[n][9], t2[n][9] float32 corners; the
  * surface distance of Section 2, 0 when the closed triangles meet).
  * precision FP32_BAND: d = lower and d_hi = upper FP32 estimate (equal unless
- * the FP32 crossing test can neither confirm nor exclude a crossing; then
- * d = 0 and d_hi = the vertex-face / edge-edge minimum), hit = 1 where the
+ * the FP32 crossing test can neither confirm nor exclude a crossing, or a
+ * facet has numerically zero area; then d = 0 and d_hi = the vertex-face /
+ * edge-edge minimum), hit = 1 where the
  * FP32 test is certain that the triangles cross.  FP64: exact meet test and
  * FP64 distance, d_hi = d.  All arrays are host memory of n entries;
  * PJ_ERR_INVALID_ARG for a null array with n > 0 or another precision. */

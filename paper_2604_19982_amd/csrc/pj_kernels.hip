@@ -1319,7 +1319,9 @@ __global__ void k_facet_pairs(const float *t1, const float *t2, int64_t n, int p
         Rec A = make_rec(V3{p[0], p[1], p[2]} - o, V3{p[3], p[4], p[5]} - o, V3{p[6], p[7], p[8]} - o, 0.0f, 0.0f);
         Rec B = make_rec(V3{q[0], q[1], q[2]} - o, V3{q[3], q[4], q[5]} - o, V3{q[6], q[7], q[8]} - o, 0.0f, 0.0f);
         Pair32 r = pair_f32(A, B, eps);
-        d[i] = r.lo;
+        // a facet of (numerically) zero area has no plane for the crossing
+        // test: its lower estimate is 0, as in the refinement kernel
+        d[i] = r.lo * (A.ok * B.ok);
         d_hi[i] = r.hi;
         hit[i] = r.sure ? 1 : 0;
     } else {

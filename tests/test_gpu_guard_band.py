@@ -160,6 +160,40 @@ def test_guard_band_near_coplanar_thin_pair(ctx):
     assert lo[0] <= d64[0] + eps / 8 and hi[0] >= d64[0] - eps / 8
 
 
+def test_guard_band_degenerate_facets(orc, ctx):
+    """Zero-area facets (a segment, a point) against regular triangles: a
+    segment piercing a face meets it although none of the 15 candidates is
+    0, so the lower estimate must drop to 0; the upper one stays an attained
+    distance."""
+    rng = np.random.default_rng(22)
+    n = 20000
+    T2 = rng.standard_normal((n, 3, 3)).astype(np.float32)
+    c = T2.mean(1)
+    nrm = _unit(np.cross(T2[:, 1] - T2[:, 0], T2[:, 2] - T2[:, 0]))
+    k = rng.integers(0, 3, n)
+    T1 = np.empty_like(T2)
+    h = rng.uniform(0.1, 1.0, (n, 1)).astype(np.float32)
+    # 0: a segment (a repeated corner) through the face's interior
+    seg = np.stack([c - h * nrm, c + h * nrm, c + h * nrm], 1)
+    # 1: a point on or next to the face
+    pt = np.repeat((c + rng.uniform(-1e-3, 1e-3, (n, 1)).astype(np.float32) * nrm)[:, None, :], 3, 1)
+    # 2: three collinear corners beside the face
+    d = rng.standard_normal((n, 3)).astype(np.float32)
+    col = np.stack([c + 2 * nrm, c + 2 * nrm + d, c + 2 * nrm + 2 * d], 1)
+    T1[k == 0], T1[k == 1], T1[k == 2] = seg[k == 0], pt[k == 1], col[k == 2]
+    lo, hi, sure = ctx.facet_pairs(T1, T2, "fp32", bounds=True)
+    d64, h64 = ctx.facet_pairs(T1, T2, "fp64")
+    # the FP64 path against the oracle's exact predicates on these inputs
+    d_ref, h_ref = orc.tri_tri_batch(T1, T2)
+    assert np.array_equal(h64, h_ref)
+    assert np.all(np.abs(d64 - d_ref) <= 1e-12 * (1.0 + np.abs(np.concatenate([T1, T2], 1)).reshape(n, -1).max(1)))
+    eps = _eps(T1, T2)
+    assert np.all(lo - d64 <= eps / 8), float(np.max((lo - d64) / eps))
+    assert np.all(d64 - hi <= eps / 8), float(np.max((d64 - hi) / eps))
+    assert not np.any(sure & ~h64)
+    assert h64[k == 0].all()   # every piercing segment meets its face
+
+
 def test_guard_band_1e8_pairs(ctx):
     rng = np.random.default_rng(21)
     worst, meets, total, n_open = 0.0, 0, 0, 0
