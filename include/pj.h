@@ -183,7 +183,8 @@ typedef struct {
     int64_t peak_device_bytes;  /* high-water mark of join work buffers */
     int64_t chunks;             /* streamed chunks of the bulk refinement */
     int64_t graph_replays;      /* bulk rounds replayed from a captured hipGraph */
-    int64_t tile_s_used;        /* streamed-side tile length of the last bulk round */
+    int64_t tile_s_used;        /* streamed-side tile length (configured or tuned) of the last bulk round;
+                                   rounds of few object pairs cut it shorter to fill the GPU */
     int64_t waves_per_cu_used;  /* persistent grid of the last bulk round, waves per CU */
     double t_tune_ms;           /* host time spent in the autotuner during this join */
     int64_t staged_bytes;       /* host-to-device bytes of staged facet data (host-resident sets) */

@@ -960,6 +960,25 @@ void plan_tiles(const pj_meshes *R, const pj_meshes *S, const std::vector<int> &
     // join the tiles still in progress (few large tiles cost less setup and
     // still balance)
     const bool whole_a = target_tiles > 0;
+    // A round of few object pairs has few claimable units (A block x B
+    // range): below about four per wave slot the B ranges are halved until
+    // there are (at most down to one chunk), so that the round's waves are not
+    // left idle.
+    if (whole_a && (int64_t)act.size() < target_tiles / 4) {  // every item is at least one unit
+        auto units = [&](int64_t ts) {
+            int64_t u = 0;
+            for (const C &oc : order) {
+                const Cand &c = cand[act[oc.idx]];
+                const int64_t nr = R->count(c.r, lod), ns = S->count(c.s, lod);
+                const bool sw = swapped(nr, ns);
+                const int64_t nA = sw ? ns : nr, nB = sw ? nr : ns;
+                u += ((nA + BR - 1) / BR) * ((nB + ts - 1) / ts);
+            }
+            return u;
+        };
+        while (TS > 64 && units(TS) < target_tiles / 4) TS = std::max(64, TS / 2 / 64 * 64);
+        pl.tile_s = TS;
+    }
     for (const C &oc : order) {
         const int ci = act[oc.idx];
         const Cand &c = cand[ci];
@@ -1751,7 +1770,7 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
         ctx->stats.lod_items[lod] += ni;
         ctx->stats.lod_tiles[lod] += nt;
     }
-    ctx->stats.tile_s_used = pl.tile_s;
+    ctx->stats.tile_s_used = wpc_override > 0 ? pl.tile_s : ctx->cur.tile_s;
     ctx->stats.waves_per_cu_used = wpc;
     if (ctx->cfg.mem_cap_bytes > 0) {
         // under a cap the chunk buffers were sized to what the cap left:
