@@ -305,6 +305,8 @@ def main():
                    "mode": "learned LoD skip + batched persistent tiles + FP32 with FP64 guard band + chunk and "
                            "facet culling + hipGraph rounds",
                    "lod_model": {"train_pairs": n_rec, "final_loss": train_loss},
+                   # evaluated FP32 facet pairs per second of refinement-kernel time
+                   "fp32_kernel_facet_pair_evals_per_s": p32 / (kms * 1e-3) if kms > 0 else 0.0,
                    "tuned_shapes": [ln for ln in shapes if ln.strip()]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(args.workload),
@@ -327,7 +329,10 @@ def main():
     if args.plain:
         t = one_step(pj, stream, gR, gS, taus, k=kk, schedule="plain", precision="fp64", **wl["ctx"])
         abl["plain_gpu_schedule"] = {"ms": t["ms"], "facet_pairs": t["pairs"] + t["pairsc"] + t["pairs64"],
-                                     "results": t["results"]}
+                                     "results": t["results"], "kernel_ms": t["kms64"]}
+        if t["kms64"] > 0:
+            # the plain FP64 kernel's facet pairs per second of its kernel time
+            abl["plain_gpu_schedule"]["fp64_kernel_facet_pair_evals_per_s"] = t["pairs64"] / (t["kms64"] * 1e-3)
         log(f"plain schedule step: {t['ms']:.1f} ms")
         out["config"]["plain_ms_per_step"] = t["ms"]
         out["config"]["speedup_vs_plain"] = t["ms"] / ms_per_step
