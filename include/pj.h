@@ -195,6 +195,8 @@ typedef struct {
     int64_t collect_launches;   /* FP32 collect passes of the exact recheck (not in refine_*) */
     int64_t collect_pairs;      /* facet pairs they evaluated */
     double collect_kernel_ms;   /* their device time */
+    int64_t collected_pairs;    /* facet pairs they kept for the FP64 recheck */
+    int64_t collect_overflow;   /* object pairs whose kept pairs overflowed the list (full FP64 pass) */
 } pj_stats;
 
 pj_status pj_get_stats(const pj_context *ctx, pj_stats *out);

@@ -70,7 +70,8 @@ class Stats(ctypes.Structure):
                 ("staged_bytes", ctypes.c_int64), ("lod_items", ctypes.c_int64 * 8), ("lod_tiles", ctypes.c_int64 * 8),
                 ("lod_pairs", ctypes.c_int64 * 8), ("lod_kernel_ms", ctypes.c_double * 8),
                 ("collect_launches", ctypes.c_int64), ("collect_pairs", ctypes.c_int64),
-                ("collect_kernel_ms", ctypes.c_double)]
+                ("collect_kernel_ms", ctypes.c_double), ("collected_pairs", ctypes.c_int64),
+                ("collect_overflow", ctypes.c_int64)]
 
     def to_dict(self):
         d = {}

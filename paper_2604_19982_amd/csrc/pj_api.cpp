@@ -1866,7 +1866,9 @@ pj_status exact_finest_view(pj_context *ctx, const MeshDev &Rv, const MeshDev &S
     const int ni = (int)pl.items.size(), nt = (int)pl.tiles.size();
     if (ni == 0) return PJ_OK;
     const int cgrid = (int)std::min<int64_t>(nt, (int64_t)ctx->num_cu * ctx->cur.wpc);
-    int64_t cap = std::max<int64_t>(1 << 20, 256 * (int64_t)ni);
+    // room for 4096 kept pairs per item (thresholds from a coarse LoD's
+    // bound keep more than those from the finest FP32 minimum), at most 2^28
+    int64_t cap = std::min<int64_t>(std::max<int64_t>(1 << 20, 4096 * (int64_t)ni), int64_t(1) << 28);
     if (ctx->cfg.mem_cap_bytes > 0) {
         // the collect list takes what the cap leaves; items that overflow it
         // are recomputed in full FP64 below
@@ -1929,6 +1931,7 @@ pj_status exact_finest_view(pj_context *ctx, const MeshDev &Rv, const MeshDev &S
     std::memcpy(&offered, host_ctr + 8, 8);
     ctx->stats.collect_pairs += (int64_t)pairs;
     const int64_t ncoll = (int64_t)std::min<unsigned long long>(offered, (unsigned long long)cap);
+    ctx->stats.collected_pairs += (int64_t)offered;
     HIPTRY(ctx, hipEventRecord(ctx->ev0, st));
     HIPTRY(ctx, launch_pairs_f64(Rv, Sv, a.items, a.collected, ncoll, ptr<ItemOut64>(ctx->b_out64), st));
     HIPTRY(ctx, hipEventRecord(ctx->ev1, st));
@@ -1943,6 +1946,7 @@ pj_status exact_finest_view(pj_context *ctx, const MeshDev &Rv, const MeshDev &S
     for (int k = 0; k < ni; ++k) {
         PairState &p = ps[pl.items[k].cand];
         if (ovf[k]) {
+            ctx->stats.collect_overflow++;
             redo.push_back(pl.items[k].cand);
             continue;
         }
@@ -1958,13 +1962,20 @@ pj_status exact_finest(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
     if (which.empty()) return PJ_OK;
     const int L = R->L;
     PJTRY(choose_shape(ctx, R, S, which, cand, ps, L - 1, 1, -1.0f, false));
-    // FP32 minimum pass for candidates with an open threshold: with u the
-    // FP32 upper distance, the pair that realises the exact minimum d* has
-    // FP32 lower distance <= d* + eps <= u + 2 eps, so that bound replaces
-    // the open threshold and the collect pass keeps only pairs near the minimum.
+    // An open threshold is closed from the pair's upper bound UB (filter
+    // anchors or a coarser LoD): the facet pair that realises the exact
+    // minimum d* <= UB has FP32 lower distance <= d* + eps <= UB + 2 eps (one
+    // eps more covers the FP64 rounding of d*).  The collect pass tightens it
+    // with the running FP32 minimum as it goes.  Only a pair with no finite
+    // UB gets an FP32 minimum pass first: with u its FP32 upper distance, the
+    // bound is u + 2 eps.
     std::vector<int> open;
-    for (int i : which)
-        if (!std::isfinite(ps[i].thr)) open.push_back(i);
+    for (int i : which) {
+        PairState &p = ps[i];
+        if (std::isfinite(p.thr)) continue;
+        if (std::isfinite(p.UB)) p.thr = up_float(p.UB + 2.0 * (double)p.eps);
+        else open.push_back(i);
+    }
     if (!open.empty()) {
         TilePlan po;
         plan_tiles(R, S, open, cand, ps, L - 1, 1, 64 * kP, ctx->cur.tile_s, true, po, tile_target(ctx, ctx->cur.wpc));

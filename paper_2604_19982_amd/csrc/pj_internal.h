@@ -119,7 +119,7 @@ hipError_t launch_knn_cand(const float *boxR, const float *ancR, int nR, const f
                            float *cub, int write_pass, hipStream_t st);
 hipError_t launch_knn_prune(int nR, const int64_t *off, const double *lb, const double *ub, const int32_t *ids,
                             const int8_t *status_in, int8_t *status_out, const int32_t *k_left, hipStream_t st);
-hipError_t launch_refine_f64_tiles(const Refine64Args &a, int ntiles, hipStream_t st);
+hipError_t launch_refine_f64_tiles(const Refine64Args &a, int64_t ntiles, hipStream_t st);
 hipError_t launch_refine_f64_plain(const Refine64Args &a, int nitems, hipStream_t st);
 hipError_t launch_facet_pairs(const float *t1, const float *t2, int64_t n, int prec, double *d, double *d_hi,
                               int8_t *hit, hipStream_t st);

@@ -8,6 +8,16 @@ namespace pj {
 
 constexpr float kInf = __builtin_inff();
 
+// A dispatch counts its grid in work-items per dimension with 32 bits: a
+// larger grid would wrap and run only part of the work, so launchers check
+// it (and the kernels over long lists stride over them with a capped grid).
+inline bool grid_fits(int64_t blocks, int threads) { return blocks * (int64_t)threads <= 0xffffffffLL; }
+constexpr int64_t kStrideBlocks = int64_t(1) << 20;
+#define PJ_GRID_CHECK(blocks, threads) \
+    do { \
+        if (!grid_fits((blocks), (threads))) return hipErrorInvalidConfiguration; \
+    } while (0)
+
 __device__ __forceinline__ float block_min256(float v, float *sh)
 {
     v = wave_min(v);
@@ -108,6 +118,7 @@ __global__ __launch_bounds__(256) void k_boxes(MeshDev m, float *box, float *anc
 hipError_t launch_boxes(const MeshDev &m, float *box, float *anchor, hipStream_t st)
 {
     if (m.n == 0) return hipSuccess;
+    PJ_GRID_CHECK(m.n, 256);
     hipLaunchKernelGGL(k_boxes, dim3(m.n), dim3(256), 0, st, m, box, anchor);
     return hipGetLastError();
 }
@@ -149,11 +160,9 @@ __device__ __forceinline__ double mag3(D3 a) { return fmax(fabs(a.x), fmax(fabs(
 
 // ph(P, f'): for every finest facet g, max over its corners of the distance
 // to its ancestor at each coarser LoD, max-reduced into that ancestor.
-__global__ __launch_bounds__(256) void k_ph(MeshDev m, float2 *hdph, const int32_t *parent, const int64_t *job_off,
-                                             int64_t n_total)
+__device__ __forceinline__ void ph_job(const MeshDev &m, float2 *hdph, const int32_t *parent, const int64_t *job_off,
+                                       const int64_t j)
 {
-    int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= n_total) return;
     const int obj = find_seg(job_off, m.n, j);
     const int g = (int)(j - job_off[obj]);
     const int L = m.L;
@@ -173,11 +182,18 @@ __global__ __launch_bounds__(256) void k_ph(MeshDev m, float2 *hdph, const int32
     }
 }
 
+__global__ __launch_bounds__(256) void k_ph(MeshDev m, float2 *hdph, const int32_t *parent, const int64_t *job_off,
+                                             int64_t n_total)
+{
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n_total; j += (int64_t)gridDim.x * 256)
+        ph_job(m, hdph, parent, job_off, j);
+}
+
 hipError_t launch_ph(const MeshDev &m, float2 *hdph, const int32_t *parent, const int64_t *job_off, int64_t n_total,
                      hipStream_t st)
 {
     if (n_total == 0) return hipSuccess;
-    int64_t blocks = (n_total + 255) / 256;
+    const int64_t blocks = std::min<int64_t>((n_total + 255) / 256, kStrideBlocks);
     hipLaunchKernelGGL(k_ph, dim3((unsigned)blocks), dim3(256), 0, st, m, hdph, parent, job_off, n_total);
     return hipGetLastError();
 }
@@ -185,12 +201,10 @@ hipError_t launch_ph(const MeshDev &m, float2 *hdph, const int32_t *parent, cons
 // hd(f', P): one wave per coarse facet; lane = barycentric grid point
 // x = (i a + j b + k c) / msub; value = max_x min_g dist(x, g) over the
 // facet's finest descendants g, plus the longest grid edge.
-__global__ __launch_bounds__(64) void k_hd(MeshDev m, float2 *hdph, const int64_t *job_off, int64_t n_jobs,
-                                           const int64_t *desc_base, const int32_t *desc_off,
-                                           const int32_t *desc_list, int lod, int msub)
+__device__ __forceinline__ void hd_job(const MeshDev &m, float2 *hdph, const int64_t *job_off, const int64_t *desc_base,
+                                       const int32_t *desc_off, const int32_t *desc_list, const int lod, const int msub,
+                                       const int64_t j)
 {
-    int64_t j = blockIdx.x;
-    if (j >= n_jobs) return;
     const int obj = find_seg(job_off, m.n, j);
     const int f = (int)(j - job_off[obj]);
     const int L = m.L;
@@ -230,11 +244,20 @@ __global__ __launch_bounds__(64) void k_hd(MeshDev m, float2 *hdph, const int64_
     }
 }
 
+// one wave per facet job, striding over the jobs when they outnumber the grid
+__global__ __launch_bounds__(64) void k_hd(MeshDev m, float2 *hdph, const int64_t *job_off, int64_t n_jobs,
+                                           const int64_t *desc_base, const int32_t *desc_off,
+                                           const int32_t *desc_list, int lod, int msub)
+{
+    for (int64_t j = blockIdx.x; j < n_jobs; j += gridDim.x)
+        hd_job(m, hdph, job_off, desc_base, desc_off, desc_list, lod, msub, j);
+}
+
 hipError_t launch_hd(const MeshDev &m, float2 *hdph, const int64_t *job_off, int64_t n_jobs, const int64_t *desc_base,
                      const int32_t *desc_off, const int32_t *desc_list, int lod, int msub, hipStream_t st)
 {
     if (n_jobs == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_hd, dim3((unsigned)n_jobs), dim3(64), 0, st, m, hdph, job_off, n_jobs, desc_base, desc_off,
+    hipLaunchKernelGGL(k_hd, dim3((unsigned)std::min<int64_t>(n_jobs, 4 * kStrideBlocks)), dim3(64), 0, st, m, hdph, job_off, n_jobs, desc_base, desc_off,
                        desc_list, lod, msub);
     return hipGetLastError();
 }
@@ -262,10 +285,8 @@ __global__ __launch_bounds__(256) void k_lodmax(MeshDev m, float2 *lodmax)
 
 // Block records: for each run of 64 consecutive facets of an (object, LoD),
 // the exact float box of their corners and their largest hd and ph.
-__global__ __launch_bounds__(256) void k_blocks(MeshDev m, float4 *blk, const int64_t *blk_off, int64_t n_blocks)
+__device__ __forceinline__ void block_rec(const MeshDev &m, float4 *blk, const int64_t *blk_off, const int64_t j)
 {
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= n_blocks) return;
     const int k = find_seg(blk_off, m.n * m.L, j);  // (object, LoD) index
     const int obj = k / m.L, lod = k % m.L;
     const int b = (int)(j - blk_off[k]);
@@ -292,16 +313,23 @@ __global__ __launch_bounds__(256) void k_blocks(MeshDev m, float4 *blk, const in
     blk[2 * j + 1] = make_float4(hi[0], hi[1], hi[2], ph);
 }
 
+__global__ __launch_bounds__(256) void k_blocks(MeshDev m, float4 *blk, const int64_t *blk_off, int64_t n_blocks)
+{
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n_blocks; j += (int64_t)gridDim.x * 256)
+        block_rec(m, blk, blk_off, j);
+}
+
 hipError_t launch_blocks(const MeshDev &m, float4 *blk, const int64_t *blk_off, int64_t n_blocks, hipStream_t st)
 {
     if (n_blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_blocks, dim3((unsigned)((n_blocks + 255) / 256)), dim3(256), 0, st, m, blk, blk_off, n_blocks);
+    hipLaunchKernelGGL(k_blocks, dim3((unsigned)std::min<int64_t>((n_blocks + 255) / 256, kStrideBlocks)), dim3(256), 0, st, m, blk, blk_off, n_blocks);
     return hipGetLastError();
 }
 
 hipError_t launch_lodmax(const MeshDev &m, float2 *lodmax, hipStream_t st)
 {
     if (m.n == 0) return hipSuccess;
+    PJ_GRID_CHECK((int64_t)m.n * m.L, 256);
     hipLaunchKernelGGL(k_lodmax, dim3((unsigned)((int64_t)m.n * m.L)), dim3(256), 0, st, m, lodmax);
     return hipGetLastError();
 }
@@ -387,6 +415,7 @@ hipError_t launch_filter(const float *boxR, const float *ancR, int nR, const flo
     (void)total;
     if (nR == 0 || nS == 0) return hipSuccess;
     dim3 grid((nR + FILT_R - 1) / FILT_R, (nS + FILT_S - 1) / FILT_S);
+    PJ_GRID_CHECK(grid.x, 256);
     hipLaunchKernelGGL(k_filter, grid, dim3(256), 0, st, boxR, ancR, nR, boxS, ancS, nS, tau2, blk_count, blk_off, cr,
                        cs, clb, cub, write_pass);
     return hipGetLastError();
@@ -484,6 +513,7 @@ hipError_t launch_filter_sweep(const float *boxR, const float *ancR, const int32
                                int32_t *cs, float *clb, float *cub, int write_pass, hipStream_t st)
 {
     if (nR == 0 || nS == 0) return hipSuccess;
+    PJ_GRID_CHECK((nR + 255) / 256, 256);
     hipLaunchKernelGGL(k_filter_sweep, dim3((nR + 255) / 256), dim3(256), 0, st, boxR, ancR, rord, nR, sbox, sanc,
                        sid, sxs, nS, tau2, w_lo, w_hi, blk_count, blk_off, cr, cs, clb, cub, write_pass);
     return hipGetLastError();
@@ -545,14 +575,15 @@ hipError_t launch_init_round(ItemOut *out, const int32_t *ctr, int32_t *slots, i
 
 __global__ void k_init_out64(ItemOut64 *out, int n)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = ItemOut64{0x7ff0000000000000ull, 0x7ff0000000000000ull, 0, 0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = ItemOut64{0x7ff0000000000000ull, 0x7ff0000000000000ull, 0, 0};
 }
 
 hipError_t launch_init_out64(ItemOut64 *out, int n, hipStream_t st)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_init_out64, dim3((n + 255) / 256), dim3(256), 0, st, out, n);
+    hipLaunchKernelGGL(k_init_out64, dim3((unsigned)std::min<int64_t>((n + 255) / 256, kStrideBlocks)), dim3(256), 0, st,
+                       out, n);
     return hipGetLastError();
 }
 
@@ -730,6 +761,12 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
             // is hidden behind the loop
             int done_pre = 0;
             if (!COLLECT && a.early) done_pre = __hip_atomic_load(&o->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // collect: the item's published minimum (>= its final one) also
+            // bounds what is kept, so a lane's first pairs of a block are not
+            // all kept against its own still-open minimum
+            if (COLLECT && a.cull)
+                ubm = fminf(ubm, __uint_as_float(__builtin_amdgcn_readfirstlane(
+                                     __hip_atomic_load(&o->ub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))));
 #pragma unroll 1
             for (int k = 0; k < n; ++k) {
                 float tmp[44];
@@ -1004,11 +1041,11 @@ struct FacetSrc64 {
     int n;
 };
 
-__global__ __launch_bounds__(64) void k_refine_f64_tiles(Refine64Args a)
+// One tile (64 A facets x a B range) of the tiled FP64 kernel; the B facets
+// are staged in LDS 64 at a time and the barrier after the last chunk leaves
+// sb free for the next tile.
+__device__ __forceinline__ void refine_tile_f64(const Refine64Args &a, const Tile tl, float *sb, const int lane)
 {
-    __shared__ float sb[64 * 12];
-    const int lane = threadIdx.x;
-    const Tile tl = a.tiles[blockIdx.x];
     const Item it = a.items[tl.item];
     const bool swap = it.flags & IT_SWAP;
     const FacetSrc SA = facet_src(swap ? a.S : a.R, it.a_obj, it.lod);
@@ -1058,10 +1095,19 @@ __global__ __launch_bounds__(64) void k_refine_f64_tiles(Refine64Args a)
     }
 }
 
-hipError_t launch_refine_f64_tiles(const Refine64Args &a, int ntiles, hipStream_t st)
+// one workgroup per tile, striding over the list when it is longer than the grid
+__global__ __launch_bounds__(64) void k_refine_f64_tiles(Refine64Args a, int64_t ntiles)
+{
+    __shared__ float sb[64 * 12];
+    const int lane = threadIdx.x;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) refine_tile_f64(a, a.tiles[t], sb, lane);
+}
+
+hipError_t launch_refine_f64_tiles(const Refine64Args &a, int64_t ntiles, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_refine_f64_tiles, dim3(ntiles), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(k_refine_f64_tiles, dim3((unsigned)std::min<int64_t>(ntiles, 4 * kStrideBlocks)), dim3(64), 0,
+                       st, a, ntiles);
     return hipGetLastError();
 }
 
@@ -1070,11 +1116,10 @@ hipError_t launch_refine_f64_tiles(const Refine64Args &a, int ntiles, hipStream_
 // per (pair, LoD); the n_A x n_B facet pairs are flattened and dealt to the
 // threads round-robin; thread-local minima are combined in LDS.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_refine_f64_plain(Refine64Args a)
+__device__ __forceinline__ void refine_item_f64_plain(const Refine64Args &a, const int item, double *shl, double *shu,
+                                                      int *shh)
 {
-    __shared__ double shl[4], shu[4];
-    __shared__ int shh[4];
-    const Item it = a.items[blockIdx.x];
+    const Item it = a.items[item];
     const bool swap = it.flags & IT_SWAP;
     const FacetSrc SA = facet_src(swap ? a.S : a.R, it.a_obj, it.lod);
     const FacetSrc SB = facet_src(swap ? a.R : a.S, it.b_obj, it.lod);
@@ -1107,19 +1152,29 @@ __global__ __launch_bounds__(256) void k_refine_f64_plain(Refine64Args a)
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        ItemOut64 *o = a.out + blockIdx.x;
+        ItemOut64 *o = a.out + item;
         double l = fmin(fmin(shl[0], shl[1]), fmin(shl[2], shl[3]));
         double u = fmin(fmin(shu[0], shu[1]), fmin(shu[2], shu[3]));
         o->lb = (unsigned long long)__double_as_longlong(l);
         o->ub = (unsigned long long)__double_as_longlong(u);
         o->hit = shh[0] | shh[1] | shh[2] | shh[3];
     }
+    __syncthreads();  // the LDS partials are rewritten by the next item
+}
+
+// one workgroup per (pair, LoD), striding over the list when it is longer than the grid
+__global__ __launch_bounds__(256) void k_refine_f64_plain(Refine64Args a, int nitems)
+{
+    __shared__ double shl[4], shu[4];
+    __shared__ int shh[4];
+    for (int i = blockIdx.x; i < nitems; i += gridDim.x) refine_item_f64_plain(a, i, shl, shu, shh);
 }
 
 hipError_t launch_refine_f64_plain(const Refine64Args &a, int nitems, hipStream_t st)
 {
     if (nitems <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_refine_f64_plain, dim3(nitems), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_refine_f64_plain, dim3((unsigned)std::min<int64_t>(nitems, kStrideBlocks)), dim3(256), 0, st, a,
+                       nitems);
     return hipGetLastError();
 }
 
@@ -1127,12 +1182,9 @@ hipError_t launch_refine_f64_plain(const Refine64Args &a, int nitems, hipStream_
 // FP64 recheck of collected facet pairs: exact meet test, FP64 distance,
 // 64-bit atomicMin per item.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_pairs_f64(MeshDev R, MeshDev S, const Item *items, const PairRef *pairs,
-                                                   int64_t n, ItemOut64 *out)
+__device__ __forceinline__ void pair_f64_ref(const MeshDev &R, const MeshDev &S, const Item *items, const PairRef pr,
+                                             ItemOut64 *out)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const PairRef pr = pairs[i];
     const Item it = items[pr.item];
     const bool swap = it.flags & IT_SWAP;
     const FacetSrc SA = facet_src(swap ? S : R, it.a_obj, it.lod);
@@ -1150,11 +1202,19 @@ __global__ __launch_bounds__(256) void k_pairs_f64(MeshDev R, MeshDev S, const I
     if (h) atomicOr(&o->hit, 1);
 }
 
+__global__ __launch_bounds__(256) void k_pairs_f64(MeshDev R, MeshDev S, const Item *items, const PairRef *pairs,
+                                                   int64_t n, ItemOut64 *out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        pair_f64_ref(R, S, items, pairs[i], out);
+}
+
 hipError_t launch_pairs_f64(const MeshDev &R, const MeshDev &S, const Item *items, const PairRef *pairs, int64_t n,
                             ItemOut64 *out, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pairs_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, R, S, items, pairs, n, out);
+    hipLaunchKernelGGL(k_pairs_f64, dim3((unsigned)std::min<int64_t>((n + 255) / 256, kStrideBlocks)), dim3(256), 0, st, R,
+                       S, items, pairs, n, out);
     return hipGetLastError();
 }
 
@@ -1196,6 +1256,7 @@ __global__ __launch_bounds__(64) void k_knn_theta(const float *ancR, int nR, con
 hipError_t launch_knn_theta(const float *ancR, int nR, const float *ancS, int nS, int k, float *theta, hipStream_t st)
 {
     if (nR == 0) return hipSuccess;
+    PJ_GRID_CHECK(nR, 64);
     hipLaunchKernelGGL(k_knn_theta, dim3(nR), dim3(64), 0, st, ancR, nR, ancS, nS, k, theta);
     return hipGetLastError();
 }
@@ -1242,6 +1303,7 @@ hipError_t launch_knn_cand(const float *boxR, const float *ancR, int nR, const f
                            float *cub, int write_pass, hipStream_t st)
 {
     if (nR == 0) return hipSuccess;
+    PJ_GRID_CHECK(nR, 64);
     hipLaunchKernelGGL(k_knn_cand, dim3(nR), dim3(64), 0, st, boxR, ancR, nR, boxS, ancS, nS, theta, count, off, cs,
                        clb, cub, write_pass);
     return hipGetLastError();
@@ -1293,6 +1355,7 @@ hipError_t launch_knn_prune(int nR, const int64_t *off, const double *lb, const 
                             const int8_t *status_in, int8_t *status_out, const int32_t *k_left, hipStream_t st)
 {
     if (nR == 0) return hipSuccess;
+    PJ_GRID_CHECK(nR, 256);
     hipLaunchKernelGGL(k_knn_prune, dim3(nR), dim3(256), 0, st, off, lb, ub, ids, status_in, status_out, k_left);
     return hipGetLastError();
 }
@@ -1301,12 +1364,9 @@ hipError_t launch_knn_prune(int nR, const int64_t *off, const double *lb, const 
 // Facet pairs given explicitly (tests): FP32 with a pair-local origin and the
 // guard band 2^-16 M, or FP64 with the exact meet test.
 // ---------------------------------------------------------------------------
-__global__ void k_facet_pairs(const float *t1, const float *t2, int64_t n, int prec, double *d, double *d_hi,
-                              int8_t *hit)
+__device__ __forceinline__ void facet_pair_one(const float *p, const float *q, int prec, double *d, double *d_hi,
+                                               int8_t *hit)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float *p = t1 + 9 * i, *q = t2 + 9 * i;
     if (prec == 0) {
         float lo[3], hi[3];
         for (int c = 0; c < 3; ++c) {
@@ -1321,25 +1381,32 @@ __global__ void k_facet_pairs(const float *t1, const float *t2, int64_t n, int p
         Pair32 r = pair_f32(A, B, eps);
         // a facet of (numerically) zero area has no plane for the crossing
         // test: its lower estimate is 0, as in the refinement kernel
-        d[i] = r.lo * (A.ok * B.ok);
-        d_hi[i] = r.hi;
-        hit[i] = r.sure ? 1 : 0;
+        *d = r.lo * (A.ok * B.ok);
+        *d_hi = r.hi;
+        *hit = r.sure ? 1 : 0;
     } else {
         D3 A[3] = {D3{p[0], p[1], p[2]}, D3{p[3], p[4], p[5]}, D3{p[6], p[7], p[8]}};
         D3 B[3] = {D3{q[0], q[1], q[2]}, D3{q[3], q[4], q[5]}, D3{q[6], q[7], q[8]}};
         bool h;
-        d[i] = pair_f64(A, B, h);
-        d_hi[i] = d[i];
-        hit[i] = h ? 1 : 0;
+        *d = pair_f64(A, B, h);
+        *d_hi = *d;
+        *hit = h ? 1 : 0;
     }
+}
+
+__global__ void k_facet_pairs(const float *t1, const float *t2, int64_t n, int prec, double *d, double *d_hi,
+                              int8_t *hit)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        facet_pair_one(t1 + 9 * i, t2 + 9 * i, prec, d + i, d_hi + i, hit + i);
 }
 
 hipError_t launch_facet_pairs(const float *t1, const float *t2, int64_t n, int prec, double *d, double *d_hi,
                               int8_t *hit, hipStream_t st)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_facet_pairs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, t1, t2, n, prec, d, d_hi,
-                       hit);
+    hipLaunchKernelGGL(k_facet_pairs, dim3((unsigned)std::min<int64_t>((n + 255) / 256, kStrideBlocks)), dim3(256), 0, st,
+                       t1, t2, n, prec, d, d_hi, hit);
     return hipGetLastError();
 }
 

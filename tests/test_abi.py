@@ -40,7 +40,7 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(pj.Config) == 4 * 16 + 8 + 8 * 4
     assert ctypes.sizeof(pj.MeshDesc) == 8 + 8 + 8 + 8 * 10
     assert ctypes.sizeof(pj.Pairs) == 32
-    assert ctypes.sizeof(pj.Stats) == 7 * 8 + 8 * 8 + 8 * 8 + 16 + 4 * 8 + 8 + 8 + 4 * 64 + 24
+    assert ctypes.sizeof(pj.Stats) == 7 * 8 + 8 * 8 + 8 * 8 + 16 + 4 * 8 + 8 + 8 + 4 * 64 + 24 + 16
 
 
 def test_product_path_does_not_import_oracle():
