@@ -10,9 +10,11 @@ constexpr float kInf = __builtin_inff();
 
 // A dispatch counts its grid in work-items per dimension with 32 bits: a
 // larger grid would wrap and run only part of the work, so launchers check
-// it (and the kernels over long lists stride over them with a capped grid).
+// it, and the kernels over long lists stride over them with a grid capped at
+// 2^16 workgroups (at least 8x what the 256 CUs hold at once, so the cap
+// costs no parallelism and lists of ordinary size already take the stride).
 inline bool grid_fits(int64_t blocks, int threads) { return blocks * (int64_t)threads <= 0xffffffffLL; }
-constexpr int64_t kStrideBlocks = int64_t(1) << 20;
+constexpr int64_t kStrideBlocks = int64_t(1) << 16;
 #define PJ_GRID_CHECK(blocks, threads) \
     do { \
         if (!grid_fits((blocks), (threads))) return hipErrorInvalidConfiguration; \
@@ -257,8 +259,8 @@ hipError_t launch_hd(const MeshDev &m, float2 *hdph, const int64_t *job_off, int
                      const int32_t *desc_off, const int32_t *desc_list, int lod, int msub, hipStream_t st)
 {
     if (n_jobs == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_hd, dim3((unsigned)std::min<int64_t>(n_jobs, 4 * kStrideBlocks)), dim3(64), 0, st, m, hdph, job_off, n_jobs, desc_base, desc_off,
-                       desc_list, lod, msub);
+    hipLaunchKernelGGL(k_hd, dim3((unsigned)std::min<int64_t>(n_jobs, kStrideBlocks)), dim3(64), 0, st, m, hdph, job_off,
+                       n_jobs, desc_base, desc_off, desc_list, lod, msub);
     return hipGetLastError();
 }
 
@@ -322,7 +324,8 @@ __global__ __launch_bounds__(256) void k_blocks(MeshDev m, float4 *blk, const in
 hipError_t launch_blocks(const MeshDev &m, float4 *blk, const int64_t *blk_off, int64_t n_blocks, hipStream_t st)
 {
     if (n_blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_blocks, dim3((unsigned)std::min<int64_t>((n_blocks + 255) / 256, kStrideBlocks)), dim3(256), 0, st, m, blk, blk_off, n_blocks);
+    hipLaunchKernelGGL(k_blocks, dim3((unsigned)std::min<int64_t>((n_blocks + 255) / 256, kStrideBlocks)), dim3(256), 0,
+                       st, m, blk, blk_off, n_blocks);
     return hipGetLastError();
 }
 
@@ -1106,7 +1109,7 @@ __global__ __launch_bounds__(64) void k_refine_f64_tiles(Refine64Args a, int64_t
 hipError_t launch_refine_f64_tiles(const Refine64Args &a, int64_t ntiles, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_refine_f64_tiles, dim3((unsigned)std::min<int64_t>(ntiles, 4 * kStrideBlocks)), dim3(64), 0,
+    hipLaunchKernelGGL(k_refine_f64_tiles, dim3((unsigned)std::min<int64_t>(ntiles, kStrideBlocks)), dim3(64), 0,
                        st, a, ntiles);
     return hipGetLastError();
 }
