@@ -191,6 +191,7 @@ struct pj_context {
     };
     DevBuf sb_items[kMaxSets], sb_tiles[kMaxSets], sb_out[kMaxSets], sb_ctr[kMaxSets], sb_stage[kMaxSets];
     PinBuf pin_items[kMaxSets], pin_tiles[kMaxSets], pin_out[kMaxSets], pin_ctr[kMaxSets], pin_stage[kMaxSets];
+    PinBuf pin_cand;  // the filter's candidate count and arrays on their way to the host
     hipStream_t up_stream = nullptr, down_stream = nullptr;
     hipEvent_t ev_h2d[kMaxSets] = {}, ev_comp[kMaxSets] = {}, ev_d2h[kMaxSets] = {}, ev_k0[kMaxSets] = {},
                ev_k1[kMaxSets] = {};
@@ -369,6 +370,7 @@ extern "C" pj_status pj_context_destroy(pj_context *ctx)
         for (hipEvent_t e : {ctx->ev_h2d[b], ctx->ev_comp[b], ctx->ev_d2h[b], ctx->ev_k0[b], ctx->ev_k1[b]})
             if (e) (void)hipEventDestroy(e);
     }
+    if (ctx->pin_cand.p) (void)hipHostFree(ctx->pin_cand.p);
     if (ctx->up_stream) (void)hipStreamDestroy(ctx->up_stream);
     if (ctx->down_stream) (void)hipStreamDestroy(ctx->down_stream);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
@@ -2031,6 +2033,31 @@ pj_status check_pair_args(pj_context *ctx, const pj_meshes *R, const pj_meshes *
     return PJ_OK;
 }
 
+// The filter's count pass leaves the candidate total on the device; it comes
+// back through pinned memory.
+pj_status read_cand_total(pj_context *ctx, int64_t &total)
+{
+    PJTRY(ensure_pinned(ctx, ctx->pin_cand, 4096));
+    HIPTRY(ctx, hipMemcpyAsync(ctx->pin_cand.p, ctx->b_total.p, 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+    std::memcpy(&total, ctx->pin_cand.p, 8);
+    return PJ_OK;
+}
+
+// The write pass stores the candidates as four arrays of `total` (r, s, lb,
+// ub) in one device buffer, which comes back in one copy through pinned memory.
+pj_status download_cands(pj_context *ctx, int64_t total, std::vector<Cand> &cand)
+{
+    PJTRY(ensure_pinned(ctx, ctx->pin_cand, (size_t)total * 16));
+    HIPTRY(ctx, hipMemcpyAsync(ctx->pin_cand.p, ctx->b_cand_r.p, (size_t)total * 16, hipMemcpyDeviceToHost, ctx->stream));
+    HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+    const int32_t *cr = static_cast<const int32_t *>(ctx->pin_cand.p), *cs = cr + total;
+    const float *lb = reinterpret_cast<const float *>(cs + total), *ub = lb + total;
+    cand.resize(total);
+    for (int64_t i = 0; i < total; ++i) cand[i] = Cand{cr[i], cs[i], lb[i], ub[i]};
+    return PJ_OK;
+}
+
 // Sweep filter: same candidates and bounds as the all-pairs test (order:
 // R by xmin, then S by xmin).  The window around each r is widened by the
 // widest S box and by relative margins that cover every rounding in the
@@ -2054,28 +2081,16 @@ pj_status mbb_filter_sweep(pj_context *ctx, const pj_meshes *R, const pj_meshes 
     HIPTRY(ctx, launch_scan_i32_to_i64(ptr<int32_t>(ctx->b_blk), ptr<int64_t>(ctx->b_blkoff), ptr<int64_t>(ctx->b_total),
                                        nb, st));
     int64_t total = 0;
-    HIPTRY(ctx, hipMemcpyAsync(&total, ctx->b_total.p, 8, hipMemcpyDeviceToHost, st));
-    HIPTRY(ctx, hipStreamSynchronize(st));
+    PJTRY(read_cand_total(ctx, total));
     if (total == 0) return PJ_OK;
     if (total > INT32_MAX) return fail(ctx, PJ_ERR_UNSUPPORTED, "more than 2^31 candidate pairs");
-    PJTRY(ensure(ctx, ctx->b_cand_r, total * 4));
-    PJTRY(ensure(ctx, ctx->b_cand_s, total * 4));
-    PJTRY(ensure(ctx, ctx->b_cand_lb, total * 4));
-    PJTRY(ensure(ctx, ctx->b_cand_ub, total * 4));
+    PJTRY(ensure(ctx, ctx->b_cand_r, total * 16));
+    int32_t *d_cr = ptr<int32_t>(ctx->b_cand_r), *d_cs = d_cr + total;
+    float *d_lb = reinterpret_cast<float *>(d_cs + total), *d_ub = d_lb + total;
     HIPTRY(ctx, launch_filter_sweep(R->d_box, R->d_anchor, R->d_xord, nR, S->d_xbox, S->d_xanc, S->d_xord, S->d_xmin,
                                     nS, tau2, w_lo, w_hi, ptr<int32_t>(ctx->b_blk), ptr<int64_t>(ctx->b_blkoff),
-                                    ptr<int32_t>(ctx->b_cand_r), ptr<int32_t>(ctx->b_cand_s),
-                                    ptr<float>(ctx->b_cand_lb), ptr<float>(ctx->b_cand_ub), 1, st));
-    std::vector<int32_t> cr(total), cs(total);
-    std::vector<float> lb(total), ub(total);
-    HIPTRY(ctx, hipMemcpyAsync(cr.data(), ctx->b_cand_r.p, total * 4, hipMemcpyDeviceToHost, st));
-    HIPTRY(ctx, hipMemcpyAsync(cs.data(), ctx->b_cand_s.p, total * 4, hipMemcpyDeviceToHost, st));
-    HIPTRY(ctx, hipMemcpyAsync(lb.data(), ctx->b_cand_lb.p, total * 4, hipMemcpyDeviceToHost, st));
-    HIPTRY(ctx, hipMemcpyAsync(ub.data(), ctx->b_cand_ub.p, total * 4, hipMemcpyDeviceToHost, st));
-    HIPTRY(ctx, hipStreamSynchronize(st));
-    cand.resize(total);
-    for (int64_t i = 0; i < total; ++i) cand[i] = Cand{cr[i], cs[i], lb[i], ub[i]};
-    return PJ_OK;
+                                    d_cr, d_cs, d_lb, d_ub, 1, st));
+    return download_cands(ctx, total, cand);
 }
 
 // MBB filter on the device: candidates with box gap <= tau.
@@ -2099,28 +2114,15 @@ pj_status mbb_filter(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, do
     HIPTRY(ctx, launch_scan_i32_to_i64(ptr<int32_t>(ctx->b_blk), ptr<int64_t>(ctx->b_blkoff), ptr<int64_t>(ctx->b_total),
                                        nb, st));
     int64_t total = 0;
-    HIPTRY(ctx, hipMemcpyAsync(&total, ctx->b_total.p, 8, hipMemcpyDeviceToHost, st));
-    HIPTRY(ctx, hipStreamSynchronize(st));
+    PJTRY(read_cand_total(ctx, total));
     if (total == 0) return PJ_OK;
     if (total > INT32_MAX) return fail(ctx, PJ_ERR_UNSUPPORTED, "more than 2^31 candidate pairs");
-    PJTRY(ensure(ctx, ctx->b_cand_r, total * 4));
-    PJTRY(ensure(ctx, ctx->b_cand_s, total * 4));
-    PJTRY(ensure(ctx, ctx->b_cand_lb, total * 4));
-    PJTRY(ensure(ctx, ctx->b_cand_ub, total * 4));
+    PJTRY(ensure(ctx, ctx->b_cand_r, total * 16));
+    int32_t *d_cr = ptr<int32_t>(ctx->b_cand_r), *d_cs = d_cr + total;
+    float *d_lb = reinterpret_cast<float *>(d_cs + total), *d_ub = d_lb + total;
     HIPTRY(ctx, launch_filter(R->d_box, R->d_anchor, nR, S->d_box, S->d_anchor, nS, tau2, ptr<int32_t>(ctx->b_blk),
-                              ptr<int64_t>(ctx->b_blkoff), nullptr, ptr<int32_t>(ctx->b_cand_r),
-                              ptr<int32_t>(ctx->b_cand_s), ptr<float>(ctx->b_cand_lb), ptr<float>(ctx->b_cand_ub), 1,
-                              st));
-    std::vector<int32_t> cr(total), cs(total);
-    std::vector<float> lb(total), ub(total);
-    HIPTRY(ctx, hipMemcpyAsync(cr.data(), ctx->b_cand_r.p, total * 4, hipMemcpyDeviceToHost, st));
-    HIPTRY(ctx, hipMemcpyAsync(cs.data(), ctx->b_cand_s.p, total * 4, hipMemcpyDeviceToHost, st));
-    HIPTRY(ctx, hipMemcpyAsync(lb.data(), ctx->b_cand_lb.p, total * 4, hipMemcpyDeviceToHost, st));
-    HIPTRY(ctx, hipMemcpyAsync(ub.data(), ctx->b_cand_ub.p, total * 4, hipMemcpyDeviceToHost, st));
-    HIPTRY(ctx, hipStreamSynchronize(st));
-    cand.resize(total);
-    for (int64_t i = 0; i < total; ++i) cand[i] = Cand{cr[i], cs[i], lb[i], ub[i]};
-    return PJ_OK;
+                              ptr<int64_t>(ctx->b_blkoff), nullptr, d_cr, d_cs, d_lb, d_ub, 1, st));
+    return download_cands(ctx, total, cand);
 }
 
 // streamed-side facets per tile: a multiple of 64 so that chunks are blocks
