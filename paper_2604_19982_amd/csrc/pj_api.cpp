@@ -930,7 +930,8 @@ struct TilePlan {
 
 // Expand items into tiles: the A side (registers) is the object whose block
 // padding wastes less; B ranges are split into chunks of tile_s facets.
-// Items are emitted in descending cost order (longest processing time first).
+// Items are emitted in descending cost order, to within a quarter octave
+// (longest processing time first).
 void plan_tiles(const pj_meshes *R, const pj_meshes *S, const std::vector<int> &act, const std::vector<Cand> &cand,
                 const std::vector<PairState> &ps, int lod, int finest, int BR, int TS, bool allow_swap, TilePlan &pl,
                 int64_t target_tiles = 0)
@@ -939,14 +940,29 @@ void plan_tiles(const pj_meshes *R, const pj_meshes *S, const std::vector<int> &
         double cost;
         int idx;
     };
-    std::vector<C> order;
-    order.reserve(act.size());
-    for (int i = 0; i < (int)act.size(); ++i) {
+    // Largest items first (for the persistent rounds' balance), by a stable
+    // counting sort on quarter-octave buckets of the facet-pair count: linear
+    // in the item count (a comparison sort of a 30k-item round costs more
+    // host time than its planning otherwise), deterministic, and the order
+    // within a bucket is the input order.
+    const int na = (int)act.size();
+    std::vector<C> order(na);
+    std::vector<uint8_t> bucket(na);
+    int cnt[257] = {0};
+    for (int i = 0; i < na; ++i) {
         const Cand &c = cand[act[i]];
-        double nr = R->count(c.r, lod), ns = S->count(c.s, lod);
-        order.push_back({nr * ns, i});
+        const uint64_t nr = (uint64_t)R->count(c.r, lod), ns = (uint64_t)S->count(c.s, lod);
+        const uint64_t q = std::max<uint64_t>(nr * ns, 1);
+        const int oct = 63 - __builtin_clzll(q);
+        const int sub = oct >= 2 ? (int)((q >> (oct - 2)) & 3) : (int)((q << (2 - oct)) & 3);
+        bucket[i] = (uint8_t)(255 - std::min(255, oct * 4 + sub));  // 0 = largest
+        cnt[bucket[i] + 1]++;
     }
-    std::stable_sort(order.begin(), order.end(), [](const C &x, const C &y) { return x.cost > y.cost; });
+    for (int k = 0; k < 256; ++k) cnt[k + 1] += cnt[k];
+    for (int i = 0; i < na; ++i) {
+        const Cand &c = cand[act[i]];
+        order[cnt[bucket[i]]++] = C{(double)R->count(c.r, lod) * (double)S->count(c.s, lod), i};
+    }
     pl.items.clear();
     pl.tiles.clear();
     pl.pairs = 0;
