@@ -200,6 +200,33 @@ def test_host_resident_knn(pj):
     assert h.stats()["staged_bytes"] > 0
 
 
+def test_knn_recheck_overflow_redo(pj):
+    """Memory caps small enough that the recheck's collect list overflows:
+    those items are recomputed by the tiled FP64 kernel over all their finest
+    facet pairs, and the lists and distances must equal the uncapped join's
+    (both take the minimum of the same FP64 pair distance over a set holding
+    the minimising pair)."""
+    R, S = mg.config_knn(seed=3, n_r=40, n_s=40, n_clusters=2, box=200.0, sigma=12.0, f_median=2000)
+    d = pj.Context()
+    ref = d.join_knn(d.meshes(R), d.meshes(S), 3)
+    assert d.stats()["collect_overflow"] == 0
+    overflowed = []
+    for cap in (8 << 20, 6 << 20, 4 << 20, 3 << 20, 2 << 20, 3 << 19, 1 << 20, 3 << 18, 1 << 19):
+        h = pj.Context(host_resident=True, mem_cap_bytes=cap, stage_sets=2)
+        try:
+            got = h.join_knn(h.meshes(R), h.meshes(S), 3)
+        except pj.PJError as e:  # a cap below what one chunk or the recheck needs
+            assert pj.STATUS_NAMES[e.status] == "OUT_OF_MEMORY", (cap, e)
+            continue
+        st = h.stats()
+        print(cap, st["collected_pairs"], st["collect_overflow"])
+        assert np.array_equal(got["s"], ref["s"]) and np.array_equal(got["count"], ref["count"]), cap
+        assert np.array_equal(got["dist"], ref["dist"]), cap
+        if st["collect_overflow"] > 0:
+            overflowed.append(cap)
+    assert overflowed, "no cap made the collect list overflow"
+
+
 def test_host_resident_pair_bounds(pj, mid):
     R, S = mid
     d = pj.Context()
