@@ -2420,9 +2420,24 @@ extern "C" pj_status pj_join_within(pj_context *ctx, const pj_meshes *R, const p
         PJTRY(finest_distances(ctx, R, S, cand, ps, res));
         ctx->stats.t_band_ms += now_ms() - tb;
     }
-    std::sort(res.begin(), res.end(), [&](int a, int b) {
-        return cand[a].r != cand[b].r ? cand[a].r < cand[b].r : cand[a].s < cand[b].s;
-    });
+    // results in (r, s) order (each pair occurs once): two stable counting
+    // passes, by s and then by r, when the result count is comparable to the
+    // object counts; otherwise a comparison sort
+    if ((int64_t)res.size() * 8 >= (int64_t)R->n + S->n) {
+        std::vector<int> tmp(res.size()), cnt((size_t)std::max(R->n, S->n) + 1);
+        std::fill(cnt.begin(), cnt.begin() + S->n + 1, 0);
+        for (int i : res) cnt[cand[i].s + 1]++;
+        for (int k = 0; k < S->n; ++k) cnt[k + 1] += cnt[k];
+        for (int i : res) tmp[cnt[cand[i].s]++] = i;
+        std::fill(cnt.begin(), cnt.begin() + R->n + 1, 0);
+        for (int i : tmp) cnt[cand[i].r + 1]++;
+        for (int k = 0; k < R->n; ++k) cnt[k + 1] += cnt[k];
+        for (int i : tmp) res[cnt[cand[i].r]++] = i;
+    } else {
+        std::sort(res.begin(), res.end(), [&](int a, int b) {
+            return cand[a].r != cand[b].r ? cand[a].r < cand[b].r : cand[a].s < cand[b].s;
+        });
+    }
     const int64_t n = (int64_t)res.size();
     out->n = n;
     out->r = (int32_t *)std::malloc(std::max<int64_t>(n, 1) * 4);
