@@ -1984,14 +1984,15 @@ pj_status exact_finest(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
     // anchors or a coarser LoD): the facet pair that realises the exact
     // minimum d* <= UB has FP32 lower distance <= d* + eps <= UB + 2 eps (one
     // eps more covers the FP64 rounding of d*).  The collect pass tightens it
-    // with the running FP32 minimum as it goes.  Only a pair with no finite
-    // UB gets an FP32 minimum pass first: with u its FP32 upper distance, the
-    // bound is u + 2 eps.
+    // with the item's running FP32 minimum as it goes, which it shares across
+    // lanes and tiles only with culling on.  A pair with no finite UB, or any
+    // open pair with culling off, gets an FP32 minimum pass first: with u its
+    // FP32 upper distance, the bound is u + 2 eps.
     std::vector<int> open;
     for (int i : which) {
         PairState &p = ps[i];
         if (std::isfinite(p.thr)) continue;
-        if (std::isfinite(p.UB)) p.thr = up_float(p.UB + 2.0 * (double)p.eps);
+        if (std::isfinite(p.UB) && ctx->cfg.tile_cull) p.thr = up_float(p.UB + 2.0 * (double)p.eps);
         else open.push_back(i);
     }
     if (!open.empty()) {
