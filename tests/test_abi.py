@@ -48,3 +48,29 @@ def test_product_path_does_not_import_oracle():
     assert "import oracle" not in src and "from oracle" not in src
     for f in os.listdir(os.path.join(ROOT, "paper_2604_19982_amd", "csrc")):
         assert "oracle" not in open(os.path.join(ROOT, "paper_2604_19982_amd", "csrc", f)).read().lower()
+
+
+def test_every_launch_fits_a_dispatch():
+    """A dispatch counts its grid in 32-bit work-items per dimension; a larger
+    grid would run only part of the work.  Each kernel launch either checks its
+    grid (PJ_GRID_CHECK), strides over its list with a capped grid
+    (kStrideBlocks), or has a grid bounded by construction (listed here: one
+    block, the persistent CU-sized grids, the model kernels over int counts of
+    at most 128 per block, and the probes)."""
+    import re
+    bounded = {"k_scan", "k_init_round", "k_refine_f32", "k_collect_f32", "k_mlp_fwd_bwd", "k_mlp_wgrad",
+               "k_mlp_adam", "k_mlp_infer", "k_fma_probe", "k_copy_probe"}
+    csrc = os.path.join(ROOT, "paper_2604_19982_amd", "csrc")
+    seen = set()
+    for f in sorted(os.listdir(csrc)):
+        if not f.endswith(".hip"):
+            continue
+        src = open(os.path.join(csrc, f)).read()
+        for m in re.finditer(r"hipLaunchKernelGGL\((\w+)", src):
+            name = m.group(1)
+            seen.add(name)
+            start = src.rfind("hipError_t launch_", 0, m.start())
+            end = src.index(";", m.start())
+            span = src[start:end]
+            assert name in bounded or "PJ_GRID_CHECK" in span or "kStrideBlocks" in span, (f, name)
+    assert {"k_refine_f64_tiles", "k_refine_f64_plain", "k_pairs_f64", "k_hd", "k_ph"} <= seen
