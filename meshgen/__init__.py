@@ -470,6 +470,31 @@ def objects(list_of_sets) -> MeshSet:
     return out
 
 
+def orphan_facet_object(height: float = 5.0) -> MeshSet:
+    """Two-LoD object whose coarse LoD has a facet no finest facet descends
+    from: the finest LoD is the unit square [0,1]^2 at z = 0 (2 triangles);
+    the coarse LoD repeats those two (each the parent of its copy) and adds
+    a triangle at z = ``height`` with no children."""
+    v = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0],
+                  [0, 0, height], [1, 0, height], [0, 1, height]], np.float32)
+    square = np.array([[0, 1, 2], [0, 2, 3]], np.int32)
+    coarse = np.concatenate([square, np.array([[4, 5, 6]], np.int32)])
+    return single_object(v, [coarse, square], [np.full(3, -1, np.int32), np.array([0, 1], np.int32)])
+
+
+def orphan_facet_cube(side: float = 10.0) -> MeshSet:
+    """Two-LoD object: the finest LoD is the surface of the cube [0, side]^3
+    (12 triangles); the coarse LoD repeats them (each the parent of its copy)
+    and adds a unit triangle at the cube's centre with no children, far from
+    the finest surface yet inside its bounding box."""
+    cube = cube_mesh([0, 0, 0], [side, side, side])
+    h = 0.5 * side
+    extra = np.array([[h, h, h], [h + 1, h, h], [h, h + 1, h]], np.float32)
+    v = np.concatenate([cube.verts, extra])
+    coarse = np.concatenate([cube.tris, np.array([[8, 9, 10]], np.int32)])
+    return single_object(v, [coarse, cube.tris], [np.full(13, -1, np.int32), np.arange(12, dtype=np.int32)])
+
+
 def cube_mesh(lo, hi) -> MeshSet:
     """Axis-aligned box surface, 8 vertices, 12 triangles, one LoD."""
     lo = np.asarray(lo, np.float64)

@@ -552,7 +552,12 @@ void oracle_mbb_all(const om_set *M, double *out6, double *anchor3)
  *              the longest grid edge (|f' edge| / m).  dist(., P) is
  *              1-Lipschitz and every point of f' is within one grid edge of
  *              a grid point, so hd >= max_{x in f'} dist(x, P), which is what
- *              Eq. (1) needs.
+ *              Eq. (1) needs.  A facet with no finest descendant takes the
+ *              minimum over every finest facet of the object instead (the
+ *              minimum over an empty set would be +inf, not 0).
+ *   A facet with no descendant gets ph = 0: Eq. (2) needs ph only for the
+ *   facets that are some surface point's ancestor, and a smaller lower bound
+ *   from an extra facet pair is still a lower bound.
  * Both are 0 on the finest LoD.
  * ---------------------------------------------------------------------- */
 int oracle_hd_ph(const om_set *M, int obj, int lod, int m, double *hd, double *ph)
@@ -597,14 +602,20 @@ int oracle_hd_ph(const om_set *M, int obj, int lod, int m, double *hd, double *p
     for (int f = 0; f < nc; f++) {
         facet_corners(M, obj, lod, f, t);
         int nd = cnt[f + 1] - cnt[f];
-        for (int q = 0; q < nd; q++) facet_corners(M, obj, L - 1, lst[cnt[f] + q], desc + 9 * q);
-        double worst = 0.0;
+        /* A facet that no finest facet descends from is bounded against the
+         * whole finest mesh P: dist(x, P) is what Eq. (1) needs, and the
+         * descendants are only a subset of P chosen to make the bound
+         * tighter.  With an empty P the bound is +inf. */
+        const int whole = nd == 0;
+        if (whole) nd = nfine;
+        for (int q = 0; q < nd; q++) facet_corners(M, obj, L - 1, whole ? q : lst[cnt[f] + q], desc + 9 * q);
+        double worst = nd ? 0.0 : INFINITY;
         for (int i = 0; i <= m; i++)
             for (int j = 0; i + j <= m; j++) {
                 int k = m - i - j;
                 double x[3];
                 for (int c = 0; c < 3; c++) x[c] = ((double)i * t[c] + (double)j * t[3 + c] + (double)k * t[6 + c]) / (double)m;
-                double best = nd ? DBL_MAX : 0.0;
+                double best = nd ? DBL_MAX : INFINITY;
                 for (int q = 0; q < nd; q++) {
                     const double *gg = desc + 9 * q;
                     best = fmin(best, oracle_pt_tri(x, gg, gg + 3, gg + 6));

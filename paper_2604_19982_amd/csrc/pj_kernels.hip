@@ -202,7 +202,8 @@ hipError_t launch_ph(const MeshDev &m, float2 *hdph, const int32_t *parent, cons
 
 // hd(f', P): one wave per coarse facet; lane = barycentric grid point
 // x = (i a + j b + k c) / msub; value = max_x min_g dist(x, g) over the
-// facet's finest descendants g, plus the longest grid edge.
+// facet's finest descendants g (every finest facet of the object when it has
+// none), plus the longest grid edge.
 __device__ __forceinline__ void hd_job(const MeshDev &m, float2 *hdph, const int64_t *job_off, const int64_t *desc_base,
                                        const int32_t *desc_off, const int32_t *desc_list, const int lod, const int msub,
                                        const int64_t j)
@@ -230,10 +231,21 @@ __device__ __forceinline__ void hd_job(const MeshDev &m, float2 *hdph, const int
         const int64_t db = desc_base[base + lod];
         const int32_t d0 = desc_off[db + f], d1 = desc_off[db + f + 1];
         const int32_t *tfine = m.tris + 3 * m.tbeg[base + L - 1];
-        double best = d1 > d0 ? 1e300 : 0.0;
-        for (int q = d0; q < d1; ++q) {
-            const int32_t *tg = tfine + 3 * desc_list[q];
-            best = fmin(best, pt_tri_d(x, ld3d(v, tg[0]), ld3d(v, tg[1]), ld3d(v, tg[2])));
+        double best = __builtin_inf();
+        if (d1 > d0) {
+            for (int q = d0; q < d1; ++q) {
+                const int32_t *tg = tfine + 3 * desc_list[q];
+                best = fmin(best, pt_tri_d(x, ld3d(v, tg[0]), ld3d(v, tg[1]), ld3d(v, tg[2])));
+            }
+        } else {
+            // no finest facet descends from f: bound it against the whole
+            // finest mesh (dist(x, P) is what Eq. (1) needs; the descendants
+            // are only the subset that makes it cheap); +inf if P is empty
+            const int nfine = m.tcnt[base + L - 1];
+            for (int q = 0; q < nfine; ++q) {
+                const int32_t *tg = tfine + 3 * q;
+                best = fmin(best, pt_tri_d(x, ld3d(v, tg[0]), ld3d(v, tg[1]), ld3d(v, tg[2])));
+            }
         }
         worst = best;
     }

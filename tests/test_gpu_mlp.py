@@ -48,6 +48,17 @@ def test_mlp_forward_backward_vs_oracle(orc, pj):
     assert np.all(np.abs(grads - g) <= 1e-4 * np.abs(g).max() + 1e-6), np.max(np.abs(grads - g))
 
 
+def test_mlp_forward_hand_values_gpu(pj):
+    """The forward kernel on the hand-built network of the oracle's pin: every
+    weight and input is a small dyadic number, so the BF16 weights and FP32
+    sums are exact and the logits must equal the hand values."""
+    import test_oracle_mlp as hand
+    flat = np.concatenate([p.ravel() for p in hand.hand_net()]).astype(np.float32)
+    assert np.array_equal(bf16(flat), flat)
+    logits, _, _ = pj.Context().mlp_eval(flat, hand.HAND_X.astype(np.float32))
+    assert np.array_equal(logits.astype(np.float64), hand.hand_logits(hand.HAND_X)), logits
+
+
 @pytest.fixture(scope="module")
 def trained(tmp_path_factory, pj):
     d = tmp_path_factory.mktemp("lod")

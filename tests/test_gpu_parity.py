@@ -133,6 +133,50 @@ def test_hdph_vs_oracle(orc, ctx, small_multilod):
                 assert np.all(hd <= rhd * (1 + 1e-6) + 1e-6) and np.all(ph <= rph * (1 + 1e-6) + 1e-6)
 
 
+def _orphan_sets():
+    """R: cubes whose coarse LoD holds a unit facet at the centre that no
+    finest facet descends from (4.5 or more from the surface); S: small
+    two-LoD triangles 0.2 above each such facet, inside the cube's box, so a
+    too-small hd of that facet would confirm them at the coarse LoD."""
+    offs = np.array([[0, 0, 0], [20, 0, 0], [0, 20, 0]], np.float32)
+    cubes = []
+    for o in offs:
+        c = mg.orphan_facet_cube(10.0)
+        c.verts = c.verts + o
+        cubes.append(c)
+    R = mg.objects(cubes)
+    q = np.array([[5.1, 5.1, 5.2], [5.3, 5.1, 5.2], [5.1, 5.3, 5.2]], np.float32)
+    tri = [np.array([[0, 1, 2]]), np.array([[0, 1, 2]])]
+    par = [np.full(1, -1, np.int32), np.zeros(1, np.int32)]
+    S = mg.objects([mg.single_object(q + o, tri, par) for o in np.concatenate([offs, [[40, 0, 0]]]).astype(np.float32)])
+    return R, S
+
+
+@pytest.mark.parametrize("host_resident", [False, True])
+def test_orphan_facet_hd_and_join(orc, pj, host_resident):
+    """hd of a coarse facet with no finest descendant is bounded against the
+    whole finest mesh (Eq. (1)): the library agrees with the oracle, and the
+    joins agree with the oracle's finest-LoD joins."""
+    R, S = _orphan_sets()
+    O_R, O_S = orc.OSet(R), orc.OSet(S)
+    for mode in ("fp32", "fp64", "plain"):
+        c = pj.Context(precision="fp64" if mode != "fp32" else "fp32",
+                       schedule="plain" if mode == "plain" else "batched", host_resident=host_resident)
+        gR, gS = c.meshes(R), c.meshes(S)
+        for obj in range(R.n_objects):
+            hd, ph = gR.hdph(obj, 0)
+            rhd, rph = orc.hd_ph(O_R, obj, 0)
+            assert rhd[12] >= 4.5 and hd[12] >= 4.5, (hd, rhd)
+            assert np.all(hd.astype(np.float64) >= rhd) and np.all(hd <= rhd * (1 + 1e-6) + 1e-6)
+            assert np.all(ph.astype(np.float64) >= rph) and ph[12] == 0.0
+        for tau in (0.0, 1.0, 4.6, 4.8):
+            got = c.join_within(gR, gS, tau)
+            ref = orc.join_within(O_R, O_S, tau)
+            assert ref["near_ties"] == 0
+            assert np.array_equal(got["r"], ref["r"]) and np.array_equal(got["s"], ref["s"]), (mode, tau)
+    assert len(orc.join_within(O_R, O_S, 1.0)["r"]) == 0 and len(orc.join_within(O_R, O_S, 4.8)["r"]) == 3
+
+
 @pytest.mark.parametrize("mode", ["fp32", "fp64", "plain"])
 def test_pair_bounds_vs_oracle(orc, pj, small_multilod, mode):
     R, S = small_multilod

@@ -186,3 +186,40 @@ def test_knn_full_order(orc, small_join):
             order = np.lexsort((np.arange(30), d[r]))[:min(k, 30)]
             assert np.array_equal(res["s"][r], order)
             assert np.array_equal(res["d"][r], d[r][order])
+
+
+def _dist_to_unit_square(x):
+    """Closed-form distance of points x [n, 3] to the square [0,1]^2 x {0}."""
+    dx = np.maximum(0.0, np.maximum(-x[:, 0], x[:, 0] - 1.0))
+    dy = np.maximum(0.0, np.maximum(-x[:, 1], x[:, 1] - 1.0))
+    return np.sqrt(dx * dx + dy * dy + x[:, 2] * x[:, 2])
+
+
+def test_hd_of_facet_without_descendants(orc):
+    """A coarse facet that no finest facet descends from (a triangle at z = 5
+    over the unit square) still gets an hd that bounds its distance to the
+    finest mesh (Eq. (1) needs hd(f', P) >= max_x dist(x, P)); ph only has
+    to cover descendants, so it is 0 there."""
+    ms = mg.orphan_facet_object(5.0)
+    O = orc.OSet(ms)
+    hd, ph = orc.hd_ph(O, 0, 0)
+    F = ms.facets(0, 0).astype(np.float64)
+    rng = np.random.default_rng(3)
+    for f in range(3):
+        X = np.concatenate([F[f], rng.dirichlet(np.ones(3), size=200) @ F[f]])
+        assert hd[f] >= _dist_to_unit_square(X).max() - 1e-12, (f, hd[f])
+    assert hd[2] >= 5.0 and ph[2] == 0.0
+    # the two square facets are their own descendants: hd is the grid edge
+    assert hd[0] == pytest.approx(np.sqrt(2.0) / 8.0, abs=1e-12)
+    assert hd[1] == pytest.approx(np.sqrt(2.0) / 8.0, abs=1e-12)
+    # Eq. (1)/(2) at the coarse LoD against a small facet 0.2 above the
+    # orphan: LB <= d <= UB (with hd = the grid edge alone, UB would be ~0.38)
+    q = np.array([[0.1, 0.1, 5.2], [0.3, 0.1, 5.2], [0.1, 0.3, 5.2]], np.float32)
+    T = orc.OSet(mg.single_object(q, [np.array([[0, 1, 2]]), np.array([[0, 1, 2]])],
+                                  [np.full(1, -1, np.int32), np.zeros(1, np.int32)]))
+    hq, pq = orc.hd_ph(T, 0, 0)
+    d, _ = orc.object_distance(O, 0, T, 0)
+    assert d == pytest.approx(5.2, abs=1e-6)
+    lb, ub = orc.lod_bounds(O, 0, T, 0, 0, hd, ph, hq, pq)
+    assert lb <= d <= ub
+    assert ub >= 5.0
