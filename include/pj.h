@@ -27,6 +27,7 @@
 #ifndef PJ_H
 #define PJ_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -54,6 +55,14 @@ typedef enum {
     PJ_SCHED_PLAIN = 1    /* one workgroup per (pair, LoD), one launch per LoD (the paper's Algorithm 4) */
 } pj_schedule;
 
+/* Device-memory hooks.  alloc returns device memory of at least `bytes`
+ * (256-byte aligned) or NULL when it cannot; free returns a block that alloc
+ * handed out.  The library waits for all of its queued device work before it
+ * calls free, so the caller's allocator may reuse the block at once.  Both
+ * are called on the thread that called into the library. */
+typedef void *(*pj_alloc_fn)(size_t bytes, void *user);
+typedef void (*pj_free_fn)(void *ptr, void *user);
+
 typedef struct {
     int32_t device;          /* HIP device ordinal */
     int32_t precision;       /* pj_precision */
@@ -78,6 +87,10 @@ typedef struct {
     const char *log_path;    /* append per-pair resolution records here (NULL: no log) */
     const char *autotune_path; /* autotuner cache file (NULL: none) */
     void *stream;            /* hipStream_t to run on (NULL: the library creates one) */
+    pj_alloc_fn dev_alloc;   /* device memory of the context and of the mesh sets created on it
+                                (work buffers, ingested facet data); NULL: hipMalloc.  Set both or neither */
+    pj_free_fn dev_free;     /* NULL: hipFree */
+    void *alloc_user;        /* passed to dev_alloc / dev_free */
 } pj_config;
 
 /* Where a mesh set's facet data live.  DEVICE: uploaded once at ingest.

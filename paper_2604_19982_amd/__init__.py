@@ -26,6 +26,10 @@ class PJError(RuntimeError):
         self.status = status
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
 class Config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("precision", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("learned_skip", ctypes.c_int32), ("want_dist", ctypes.c_int32), ("use_graph", ctypes.c_int32),
@@ -35,7 +39,8 @@ class Config(ctypes.Structure):
                 ("filter_mode", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("mem_cap_bytes", ctypes.c_int64),
                 ("model_path", ctypes.c_char_p), ("log_path", ctypes.c_char_p), ("autotune_path", ctypes.c_char_p),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
+                ("alloc_user", ctypes.c_void_p)]
 
 
 class MeshDesc(ctypes.Structure):
@@ -100,6 +105,14 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2604_19982_amd.build.build()")
+        # One HIP runtime per process: torch ships its own libamdhip64 under
+        # the same soname.  Loaded first, torch's copy is the one the library
+        # binds to; loaded after the library, it would be a second runtime
+        # whose streams and device memory the library cannot use.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         vp = ctypes.c_void_p
         L.pj_config_default.argtypes = [ctypes.POINTER(Config)]
@@ -185,7 +198,10 @@ class Context:
     def __init__(self, device=0, precision="fp32", schedule="batched", learned_skip=False, want_dist=False,
                  use_graph=True, tile_cull=True, tile_s=0, waves_per_cu=0, mem_cap_bytes=0, model_path=None,
                  log_path=None, stream=None, chunk_tiles=0, autotune=False, autotune_path=None,
-                 host_resident=False, stage_sets=0, filter_mode="auto"):
+                 host_resident=False, stage_sets=0, filter_mode="auto", allocator=None):
+        """``allocator``: optional (alloc, free) Python callables for the
+        library's device memory: alloc(nbytes) -> device address (int) or
+        None, free(address).  They back pj_config.dev_alloc / dev_free."""
         L = lib()
         c = Config()
         L.pj_config_default(ctypes.byref(c))
@@ -207,6 +223,25 @@ class Context:
         self._paths = [None if p is None else os.fsencode(p) for p in (model_path, log_path, autotune_path)]
         c.model_path, c.log_path, c.autotune_path = self._paths
         c.stream = stream
+        self._hooks = None
+        if allocator is not None:
+            fa, ff = allocator
+
+            def _alloc(nbytes, _user):
+                try:
+                    p = fa(int(nbytes))
+                    return int(p) if p else None
+                except Exception:  # an exception may not cross into the library
+                    return None
+
+            def _free(ptr, _user):
+                try:
+                    ff(int(ptr))
+                except Exception:
+                    pass
+
+            self._hooks = (ALLOC_FN(_alloc), FREE_FN(_free))
+            c.dev_alloc, c.dev_free = self._hooks
         h = ctypes.c_void_p()
         st = L.pj_context_create(ctypes.byref(c), ctypes.byref(h))
         if st != PJ_OK:

@@ -38,20 +38,72 @@ double now_ms()
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+}  // namespace
+
+// Device memory of the library: hipMalloc / hipFree, or the caller's hooks
+// (pj_config.dev_alloc / dev_free).  Before a block goes back to the
+// caller's allocator every queued device operation is waited for, since that
+// allocator may hand the block out again at once.
+struct DevAlloc {
+    pj_alloc_fn fa = nullptr;
+    pj_free_fn ff = nullptr;
+    void *user = nullptr;
+    hipError_t alloc(void **p, size_t bytes) const
+    {
+        if (!fa) return hipMalloc(p, bytes);
+        *p = fa(bytes, user);
+        return *p ? hipSuccess : hipErrorOutOfMemory;
+    }
+    void free(void *p) const
+    {
+        if (!p) return;
+        if (!ff) {
+            (void)hipFree(p);
+            return;
+        }
+        (void)hipDeviceSynchronize();
+        ff(p, user);
+    }
+};
+
+namespace {
+
 struct DevBuf {
     void *p = nullptr;
     size_t cap = 0;
-    int64_t *tracked = nullptr;  // context byte counter
+    int64_t *tracked = nullptr;      // context byte counter
+    const DevAlloc *al = nullptr;  // allocator that gave p
     ~DevBuf()
     {
-        if (p) (void)hipFree(p);
+        if (p && al) al->free(p);
     }
     void release()
     {
-        if (p) (void)hipFree(p);
+        if (p && al) al->free(p);
         if (tracked) *tracked -= (int64_t)cap;
         p = nullptr;
         cap = 0;
+    }
+};
+
+// Device blocks that live only during one call (ingest tables): freed when
+// the holder goes out of scope, also on an early error return.
+struct TmpDev {
+    const DevAlloc &al;
+    std::vector<void *> ps;
+    explicit TmpDev(const DevAlloc &a) : al(a) {}
+    ~TmpDev()
+    {
+        for (void *p : ps) al.free(p);
+    }
+    template <class T>
+    hipError_t get(T **out, size_t count)
+    {
+        void *p = nullptr;
+        const hipError_t e = al.alloc(&p, std::max<size_t>(count, 1) * sizeof(T));
+        *out = static_cast<T *>(p);
+        if (e == hipSuccess) ps.push_back(p);
+        return e;
     }
 };
 
@@ -61,6 +113,7 @@ enum Status : int8_t { ST_UNDEC = 0, ST_CONF = 1, ST_PRUNED = 2, ST_BAND = 3 };
 
 struct pj_meshes {
     int device = 0;
+    DevAlloc al;  // allocator of the device arrays below
     int32_t n = 0, L = 1;
     int64_t nv = 0, nt = 0, nh = 0;
     float *d_verts = nullptr;
@@ -171,6 +224,7 @@ struct HostPool {
 };
 
 struct pj_context {
+    DevAlloc alloc;  // declared first: the work buffers below are freed through it
     std::unique_ptr<HostPool> pool;  // created on first use
     pj_config cfg;
     hipStream_t stream = nullptr;
@@ -248,13 +302,17 @@ pj_status ensure(pj_context *ctx, DevBuf &b, size_t bytes)
         if (after > ctx->cfg.mem_cap_bytes)
             return fail(ctx, PJ_ERR_OUT_OF_MEMORY, "work buffers exceed the configured device memory cap");
     }
-    if (b.p) (void)hipFree(b.p);
+    if (b.p) b.al->free(b.p);
     ctx->dev_bytes -= (int64_t)b.cap;
     b.p = nullptr;
     b.cap = 0;
-    hipError_t e = hipMalloc(&b.p, nb);
-    if (e != hipSuccess) return hipfail(ctx, e, "hipMalloc");
+    hipError_t e = ctx->alloc.alloc(&b.p, nb);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return hipfail(ctx, e, "device allocation");
+    }
     b.cap = nb;
+    b.al = &ctx->alloc;
     b.tracked = &ctx->dev_bytes;
     ctx->dev_bytes += (int64_t)nb;
     ctx->peak_bytes = std::max(ctx->peak_bytes, ctx->dev_bytes);
@@ -316,12 +374,14 @@ extern "C" pj_status pj_context_create(const pj_config *cfg, pj_context **out)
     if (c.precision != PJ_PREC_FP32_BAND && c.precision != PJ_PREC_FP64) return PJ_ERR_INVALID_ARG;
     if (c.schedule != PJ_SCHED_BATCHED && c.schedule != PJ_SCHED_PLAIN) return PJ_ERR_INVALID_ARG;
     if (c.tile_s < 0 || c.waves_per_cu < 0 || c.mem_cap_bytes < 0) return PJ_ERR_INVALID_ARG;
+    if ((c.dev_alloc == nullptr) != (c.dev_free == nullptr)) return PJ_ERR_INVALID_ARG;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return PJ_ERR_DEVICE;
     if (c.device < 0 || c.device >= ndev) return PJ_ERR_INVALID_ARG;
     if (hipSetDevice(c.device) != hipSuccess) return PJ_ERR_DEVICE;
     pj_context *ctx = new pj_context();
     ctx->cfg = c;
+    ctx->alloc = DevAlloc{c.dev_alloc, c.dev_free, c.alloc_user};
     std::memset(&ctx->stats, 0, sizeof(ctx->stats));
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, c.device) == hipSuccess) {
@@ -402,15 +462,23 @@ void free_meshes(pj_meshes *m)
                     (void *)m->d_tcnt, (void *)m->d_hdph, (void *)m->d_box, (void *)m->d_anchor,
                     (void *)m->d_lodmax, (void *)m->d_bkbeg, (void *)m->d_blk, (void *)m->d_xord, (void *)m->d_xbox,
                     (void *)m->d_xanc, (void *)m->d_xmin})
-        if (p) (void)hipFree(p);
+        if (p) m->al.free(p);
     delete m;
 }
 
 template <class T>
-hipError_t upload(T **dst, const T *src, size_t n, hipStream_t st)
+hipError_t dev_new(const DevAlloc &al, T **dst, size_t n)
 {
-    *dst = nullptr;
-    hipError_t e = hipMalloc((void **)dst, std::max<size_t>(n, 1) * sizeof(T));
+    void *p = nullptr;
+    const hipError_t e = al.alloc(&p, std::max<size_t>(n, 1) * sizeof(T));
+    *dst = e == hipSuccess ? static_cast<T *>(p) : nullptr;
+    return e;
+}
+
+template <class T>
+hipError_t upload(const DevAlloc &al, T **dst, const T *src, size_t n, hipStream_t st)
+{
+    hipError_t e = dev_new(al, dst, n);
     if (e != hipSuccess) return e;
     if (n) e = hipMemcpyAsync(*dst, src, n * sizeof(T), hipMemcpyHostToDevice, st);
     return e;
@@ -499,19 +567,19 @@ pj_status ingest_device(pj_context *ctx, const pj_mesh_desc *d, pj_meshes *m)
         }
     m->nh = nh;
     hipError_t e;
-    if ((e = upload(&m->d_verts, d->verts, 3 * (size_t)d->n_verts, st)) != hipSuccess) return bail(e, "verts");
-    if ((e = upload(&m->d_tris, d->tris, 3 * (size_t)d->n_tris, st)) != hipSuccess) return bail(e, "tris");
-    if ((e = upload(&m->d_vbeg, m->h_vbeg.data(), n, st)) != hipSuccess) return bail(e, "vert_begin");
-    if ((e = upload(&m->d_tbeg, m->h_tbeg.data(), n * L, st)) != hipSuccess) return bail(e, "tri_begin");
-    if ((e = upload(&m->d_tcnt, m->h_tcnt.data(), n * L, st)) != hipSuccess) return bail(e, "tri_count");
-    if ((e = upload(&m->d_hpbeg, m->h_hpbeg.data(), n * L, st)) != hipSuccess) return bail(e, "hdph_begin");
-    if ((e = hipMalloc((void **)&m->d_hdph, std::max<int64_t>(nh, 1) * sizeof(float2))) != hipSuccess)
+    if ((e = upload(m->al, &m->d_verts, d->verts, 3 * (size_t)d->n_verts, st)) != hipSuccess) return bail(e, "verts");
+    if ((e = upload(m->al, &m->d_tris, d->tris, 3 * (size_t)d->n_tris, st)) != hipSuccess) return bail(e, "tris");
+    if ((e = upload(m->al, &m->d_vbeg, m->h_vbeg.data(), n, st)) != hipSuccess) return bail(e, "vert_begin");
+    if ((e = upload(m->al, &m->d_tbeg, m->h_tbeg.data(), n * L, st)) != hipSuccess) return bail(e, "tri_begin");
+    if ((e = upload(m->al, &m->d_tcnt, m->h_tcnt.data(), n * L, st)) != hipSuccess) return bail(e, "tri_count");
+    if ((e = upload(m->al, &m->d_hpbeg, m->h_hpbeg.data(), n * L, st)) != hipSuccess) return bail(e, "hdph_begin");
+    if ((e = dev_new(m->al, &m->d_hdph, (size_t)std::max<int64_t>(nh, 1))) != hipSuccess)
         return bail(e, "hdph");
     if ((e = hipMemsetAsync(m->d_hdph, 0, std::max<int64_t>(nh, 1) * sizeof(float2), st)) != hipSuccess)
         return bail(e, "hdph clear");
-    if ((e = hipMalloc((void **)&m->d_box, n * 6 * sizeof(float))) != hipSuccess) return bail(e, "boxes");
-    if ((e = hipMalloc((void **)&m->d_anchor, n * 3 * sizeof(float))) != hipSuccess) return bail(e, "anchors");
-    if ((e = hipMalloc((void **)&m->d_lodmax, n * L * sizeof(float2))) != hipSuccess) return bail(e, "lodmax");
+    if ((e = dev_new(m->al, &m->d_box, n * 6)) != hipSuccess) return bail(e, "boxes");
+    if ((e = dev_new(m->al, &m->d_anchor, n * 3)) != hipSuccess) return bail(e, "anchors");
+    if ((e = dev_new(m->al, &m->d_lodmax, n * L)) != hipSuccess) return bail(e, "lodmax");
     MeshDev md = m->dev();
     if ((e = launch_boxes(md, m->d_box, m->d_anchor, st)) != hipSuccess) return bail(e, "boxes kernel");
 
@@ -535,10 +603,17 @@ pj_status ingest_device(pj_context *ctx, const pj_mesh_desc *d, pj_meshes *m)
         // ph: one thread per finest facet
         std::vector<int64_t> fine_off(n + 1, 0);
         for (int64_t i = 0; i < n; ++i) fine_off[i + 1] = fine_off[i] + m->h_tcnt[i * L + L - 1];
+        // device tables of this call only (freed on every return)
+        TmpDev tmp(m->al);
         int32_t *d_parent = nullptr;
         int64_t *d_off = nullptr;
-        if ((e = upload(&d_parent, d->parent, (size_t)d->n_tris, st)) != hipSuccess) return bail(e, "parent");
-        if ((e = upload(&d_off, fine_off.data(), n + 1, st)) != hipSuccess) return bail(e, "offsets");
+        if ((e = tmp.get(&d_parent, (size_t)d->n_tris)) != hipSuccess) return bail(e, "parent");
+        if (d->n_tris && (e = hipMemcpyAsync(d_parent, d->parent, (size_t)d->n_tris * 4, hipMemcpyHostToDevice, st)) !=
+                             hipSuccess)
+            return bail(e, "parent");
+        if ((e = tmp.get(&d_off, n + 1)) != hipSuccess) return bail(e, "offsets");
+        if ((e = hipMemcpyAsync(d_off, fine_off.data(), (n + 1) * 8, hipMemcpyHostToDevice, st)) != hipSuccess)
+            return bail(e, "offsets");
         e = launch_ph(md, m->d_hdph, d_parent, d_off, fine_off[n], st);
         if (e != hipSuccess) return bail(e, "ph kernel");
         // hd: descendants of each coarse facet, grouped per distinct connectivity
@@ -589,10 +664,15 @@ pj_status ingest_device(pj_context *ctx, const pj_mesh_desc *d, pj_meshes *m)
         int64_t *d_dbase = nullptr;
         int32_t *d_doff = nullptr, *d_dlist = nullptr;
         int64_t *d_joboff = nullptr;
-        if ((e = upload(&d_dbase, desc_base.data(), desc_base.size(), st)) != hipSuccess) return bail(e, "desc");
-        if ((e = upload(&d_doff, desc_off32.data(), desc_off32.size(), st)) != hipSuccess) return bail(e, "desc");
-        if ((e = upload(&d_dlist, desc_list.data(), desc_list.size(), st)) != hipSuccess) return bail(e, "desc");
-        if ((e = hipMalloc((void **)&d_joboff, (n + 1) * sizeof(int64_t))) != hipSuccess) return bail(e, "jobs");
+        auto tmp_upload = [&](auto **dst, const auto *src, size_t cnt) {
+            hipError_t r = tmp.get(dst, cnt);
+            if (r == hipSuccess && cnt) r = hipMemcpyAsync(*dst, src, cnt * sizeof(*src), hipMemcpyHostToDevice, st);
+            return r;
+        };
+        if ((e = tmp_upload(&d_dbase, desc_base.data(), desc_base.size())) != hipSuccess) return bail(e, "desc");
+        if ((e = tmp_upload(&d_doff, desc_off32.data(), desc_off32.size())) != hipSuccess) return bail(e, "desc");
+        if ((e = tmp_upload(&d_dlist, desc_list.data(), desc_list.size())) != hipSuccess) return bail(e, "desc");
+        if ((e = tmp.get(&d_joboff, n + 1)) != hipSuccess) return bail(e, "jobs");
         std::vector<std::vector<int64_t>> joboffs(L);
         for (int64_t l = 0; l + 1 < L; ++l) {
             std::vector<int64_t> &jo = joboffs[l];
@@ -606,19 +686,13 @@ pj_status ingest_device(pj_context *ctx, const pj_mesh_desc *d, pj_meshes *m)
             if ((e = hipStreamSynchronize(st)) != hipSuccess) return bail(e, "hd sync");
         }
         if ((e = hipStreamSynchronize(st)) != hipSuccess) return bail(e, "ingest sync");
-        (void)hipFree(d_parent);
-        (void)hipFree(d_off);
-        (void)hipFree(d_dbase);
-        (void)hipFree(d_doff);
-        (void)hipFree(d_dlist);
-        (void)hipFree(d_joboff);
     }
     // block records (64 consecutive facets each) for chunk culling
     m->h_bkbeg.assign(n * L + 1, 0);
     for (int64_t k = 0; k < n * L; ++k) m->h_bkbeg[k + 1] = m->h_bkbeg[k] + (m->h_tcnt[k] + 63) / 64;
     m->nblk = m->h_bkbeg[n * L];
-    if ((e = upload(&m->d_bkbeg, m->h_bkbeg.data(), n * L + 1, st)) != hipSuccess) return bail(e, "block offsets");
-    if ((e = hipMalloc((void **)&m->d_blk, std::max<int64_t>(m->nblk, 1) * 2 * sizeof(float4))) != hipSuccess)
+    if ((e = upload(m->al, &m->d_bkbeg, m->h_bkbeg.data(), n * L + 1, st)) != hipSuccess) return bail(e, "block offsets");
+    if ((e = dev_new(m->al, &m->d_blk, (size_t)std::max<int64_t>(m->nblk, 1) * 2)) != hipSuccess)
         return bail(e, "block records");
     md = m->dev();
     if ((e = launch_blocks(md, m->d_blk, m->d_bkbeg, m->nblk, st)) != hipSuccess) return bail(e, "blocks kernel");
@@ -741,6 +815,7 @@ pj_status ingest_host(pj_context *ctx, const pj_mesh_desc *d, pj_meshes *m)
             sub.hdph_begin = shb.data();
         }
         pj_meshes *tmp = new pj_meshes();
+        tmp->al = ctx->alloc;
         pj_status s = ingest_device(ctx, &sub, tmp);
         if (s == PJ_OK) {
             std::vector<float2> hp(std::max<int64_t>(tmp->nh, 1));
@@ -775,9 +850,9 @@ pj_status ingest_host(pj_context *ctx, const pj_mesh_desc *d, pj_meshes *m)
         o0 = o1;
     }
     hipError_t e;
-    if ((e = upload(&m->d_box, m->h_box.data(), 6 * n, st)) != hipSuccess) return hipfail(ctx, e, "boxes");
-    if ((e = upload(&m->d_anchor, m->h_anchor.data(), 3 * n, st)) != hipSuccess) return hipfail(ctx, e, "anchors");
-    if ((e = upload(&m->d_lodmax, m->h_lodmax.data(), n * L, st)) != hipSuccess) return hipfail(ctx, e, "lodmax");
+    if ((e = upload(m->al, &m->d_box, m->h_box.data(), 6 * n, st)) != hipSuccess) return hipfail(ctx, e, "boxes");
+    if ((e = upload(m->al, &m->d_anchor, m->h_anchor.data(), 3 * n, st)) != hipSuccess) return hipfail(ctx, e, "anchors");
+    if ((e = upload(m->al, &m->d_lodmax, m->h_lodmax.data(), n * L, st)) != hipSuccess) return hipfail(ctx, e, "lodmax");
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hipfail(ctx, e, "ingest sync");
     return PJ_OK;
 }
@@ -808,10 +883,10 @@ pj_status sort_boxes(pj_context *ctx, pj_meshes *m)
     m->max_abs = ma;
     hipStream_t st = ctx->stream;
     hipError_t e;
-    if ((e = upload(&m->d_xord, ord.data(), n, st)) != hipSuccess) return hipfail(ctx, e, "sorted ids");
-    if ((e = upload(&m->d_xbox, xb.data(), 6 * n, st)) != hipSuccess) return hipfail(ctx, e, "sorted boxes");
-    if ((e = upload(&m->d_xanc, xa.data(), 3 * n, st)) != hipSuccess) return hipfail(ctx, e, "sorted anchors");
-    if ((e = upload(&m->d_xmin, xm.data(), n, st)) != hipSuccess) return hipfail(ctx, e, "sorted xmin");
+    if ((e = upload(m->al, &m->d_xord, ord.data(), n, st)) != hipSuccess) return hipfail(ctx, e, "sorted ids");
+    if ((e = upload(m->al, &m->d_xbox, xb.data(), 6 * n, st)) != hipSuccess) return hipfail(ctx, e, "sorted boxes");
+    if ((e = upload(m->al, &m->d_xanc, xa.data(), 3 * n, st)) != hipSuccess) return hipfail(ctx, e, "sorted anchors");
+    if ((e = upload(m->al, &m->d_xmin, xm.data(), n, st)) != hipSuccess) return hipfail(ctx, e, "sorted xmin");
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hipfail(ctx, e, "sort sync");
     return PJ_OK;
 }
@@ -824,6 +899,7 @@ extern "C" pj_status pj_meshes_create(pj_context *ctx, const pj_mesh_desc *d, pj
     PJTRY(validate_desc(ctx, d));
     HIPTRY(ctx, hipSetDevice(ctx->cfg.device));
     pj_meshes *m = new pj_meshes();
+    m->al = ctx->alloc;
     pj_status s = ctx->cfg.mesh_residency == PJ_RESIDENT_HOST ? ingest_host(ctx, d, m) : ingest_device(ctx, d, m);
     if (s == PJ_OK) s = sort_boxes(ctx, m);
     if (s != PJ_OK) {

@@ -37,7 +37,7 @@ def test_config_default_is_host_only():
 
 def test_struct_sizes_match_header_layout():
     import paper_2604_19982_amd as pj
-    assert ctypes.sizeof(pj.Config) == 4 * 16 + 8 + 8 * 4
+    assert ctypes.sizeof(pj.Config) == 4 * 16 + 8 + 8 * 4 + 8 * 3
     assert ctypes.sizeof(pj.MeshDesc) == 8 + 8 + 8 + 8 * 10
     assert ctypes.sizeof(pj.Pairs) == 32
     assert ctypes.sizeof(pj.Stats) == 7 * 8 + 8 * 8 + 8 * 8 + 16 + 4 * 8 + 8 + 8 + 4 * 64 + 24 + 16
@@ -74,3 +74,15 @@ def test_every_launch_fits_a_dispatch():
             span = src[start:end]
             assert name in bounded or "PJ_GRID_CHECK" in span or "kStrideBlocks" in span, (f, name)
     assert {"k_refine_f64_tiles", "k_refine_f64_plain", "k_pairs_f64", "k_hd", "k_ph"} <= seen
+
+
+def test_one_hip_runtime_with_torch():
+    """The library and torch share one HIP runtime (torch's copy is loaded
+    first), so torch streams and device memory can be handed to it."""
+    import subprocess
+    import sys
+    code = ("import paper_2604_19982_amd as pj; pj.lib(); import torch; "
+            "print(len({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=600)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
