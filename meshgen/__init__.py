@@ -29,6 +29,9 @@ from __future__ import annotations
 
 from dataclasses import dataclass, field
 import math
+import mmap
+import multiprocessing
+import os
 
 import numpy as np
 
@@ -43,6 +46,62 @@ __all__ = [
 # tube block); the arrays do not depend on these sizes.
 BLOB_BLOCK_VALUES = 1 << 22
 TUBE_BLOCK = 4096
+
+
+def default_workers() -> int:
+    """Worker processes for large sets: the host's CPU share (at most 16)."""
+    env = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    return max(1, min(16, env if env > 0 else (os.cpu_count() or 1)))
+
+
+def _shared_array(shape, dtype):
+    """A zeroed array in anonymous shared memory: processes forked after its
+    creation write into the same pages."""
+    nbytes = int(np.prod(shape)) * np.dtype(dtype).itemsize
+    mm = mmap.mmap(-1, max(nbytes, 1))
+    return np.frombuffer(mm, dtype=dtype, count=int(np.prod(shape))).reshape(shape)
+
+
+_FORK_JOB = None
+
+
+def _fork_entry(item):
+    fn, args = _FORK_JOB
+    fn(*args, *item)
+    return 0
+
+
+def _gpu_opened() -> bool:
+    """Whether this process holds a GPU device file open (a process that has
+    touched the GPU is never forked)."""
+    try:
+        for fd in os.listdir("/proc/self/fd"):
+            try:
+                target = os.readlink(os.path.join("/proc/self/fd", fd))
+            except OSError:
+                continue
+            if target == "/dev/kfd" or target.startswith("/dev/dri/"):
+                return True
+    except OSError:
+        return True
+    return False
+
+
+def _run_blocks(fn, args, blocks, workers):
+    """fn(*args, *block) for every block, in forked worker processes (which
+    write their results into shared arrays among ``args``) or serially (one
+    worker, or a process that has opened the GPU)."""
+    global _FORK_JOB
+    if workers <= 1 or len(blocks) <= 1 or _gpu_opened():
+        for b in blocks:
+            fn(*args, *b)
+        return
+    _FORK_JOB = (fn, args)
+    try:
+        with multiprocessing.get_context("fork").Pool(min(workers, len(blocks))) as pool:
+            pool.map(_fork_entry, blocks, chunksize=1)
+    finally:
+        _FORK_JOB = None
 
 
 def rng_for(seed: int, stream: int) -> np.random.Generator:
@@ -267,7 +326,7 @@ def _unit(x):
 
 
 def make_tubes(rng, centres, n_seg: int, n_lods: int, length_range=(20.0, 80.0), radius: float = 1.0,
-               n_seg_per_object=None, progress=None):
+               n_seg_per_object=None, progress=None, workers=1):
     """Tubes with MBB centres at ``centres`` (float64 [n, 3]).
 
     Draw order per call: directions (n x 3 normals x 3), lengths (n).
@@ -280,9 +339,17 @@ def make_tubes(rng, centres, n_seg: int, n_lods: int, length_range=(20.0, 80.0),
     d2 = _unit(d1 + rng.normal(scale=0.5, size=(n, 3)))
     lengths = rng.uniform(length_range[0], length_range[1], size=n)
     segs = np.full(n, n_seg, np.int64) if n_seg_per_object is None else np.asarray(n_seg_per_object, np.int64)
+    step = TUBE_BLOCK
+    if workers > 1 and n > step and n_seg_per_object is None:
+        # equal tubes: blocks in worker processes, into one shared [n, V, 3]
+        out = _shared_array((n, 8 * (n_seg + 1) + 2, 3), np.float32)
+        _run_blocks(_tube_block_into, (out, centres, d0, d1, d2, lengths, segs, radius),
+                    [(c0, min(n, c0 + step)) for c0 in range(0, n, step)], workers)
+        if progress is not None:
+            progress(f"tubes {n}/{n}")
+        return out, segs
     per_obj = [None] * n
     # the shapes are fixed by the draws above; build them in blocks of tubes
-    step = TUBE_BLOCK
     for c0 in range(0, n, step):
         c1 = min(n, c0 + step)
         _tube_block(per_obj, c0, centres[c0:c1], d0[c0:c1], d1[c0:c1], d2[c0:c1], lengths[c0:c1], segs[c0:c1],
@@ -290,6 +357,10 @@ def make_tubes(rng, centres, n_seg: int, n_lods: int, length_range=(20.0, 80.0),
         if progress is not None:
             progress(f"tubes {c1}/{n}")
     return per_obj, segs
+
+
+def _tube_block_into(out, centres, d0, d1, d2, lengths, segs, radius, c0, c1):
+    _tube_block(out, c0, centres[c0:c1], d0[c0:c1], d1[c0:c1], d2[c0:c1], lengths[c0:c1], segs[c0:c1], radius)
 
 
 def _tube_block(per_obj, c0, centres, d0, d1, d2, lengths, segs, radius):
@@ -345,7 +416,15 @@ def _tube_block(per_obj, c0, centres, d0, d1, d2, lengths, segs, radius):
             per_obj[c0 + t] = v[k].astype(np.float32)
 
 
-def make_blobs(rng, centres, radii, level_min: int, level_max: int, noise=(0.9, 1.1), progress=None):
+def _blob_block(v, state, tv, centres, radii, noise, nv, i0, i1):
+    g = np.random.PCG64()
+    g.state = state
+    g.advance(i0 * nv)
+    noise_v = np.random.Generator(g).uniform(noise[0], noise[1], size=(i1 - i0, nv))
+    v[i0:i1] = tv[None, :, :] * (noise_v * radii[i0:i1, None])[:, :, None] + centres[i0:i1, None, :]
+
+
+def make_blobs(rng, centres, radii, level_min: int, level_max: int, noise=(0.9, 1.1), progress=None, workers=1):
     """Perturbed icospheres; LoD l is subdivision level level_min + l.
 
     Each finest vertex is scaled radially by U(noise) (coarse vertices are a
@@ -358,14 +437,26 @@ def make_blobs(rng, centres, radii, level_min: int, level_max: int, noise=(0.9, 
     tv, faces, parents = icosphere_template(level_max)
     nv = 10 * 4 ** level_max + 2
     # generated in row blocks (the noise stream is the same as one n x V draw)
-    v = np.empty((n, nv, 3), np.float32)
     step = max(1, BLOB_BLOCK_VALUES // nv)
-    for i0 in range(0, n, step):
-        i1 = min(n, i0 + step)
-        noise_v = rng.uniform(noise[0], noise[1], size=(i1 - i0, nv))
-        v[i0:i1] = tv[None, :nv, :] * (noise_v * radii[i0:i1, None])[:, :, None] + centres[i0:i1, None, :]
-        if progress is not None and (i1 == n or (i0 // step) % 64 == 63):
-            progress(f"blobs {i1}/{n}")
+    if workers > 1 and n > step and isinstance(rng.bit_generator, np.random.PCG64):
+        # Each block draws its noise from a copy of the generator advanced by
+        # the draws of the blocks before it (one 64-bit output per uniform
+        # value), so the arrays are those of one pass.
+        v = _shared_array((n, nv, 3), np.float32)
+        state = rng.bit_generator.state
+        _run_blocks(_blob_block, (v, state, tv[:nv], centres, radii, noise, nv),
+                    [(i0, min(n, i0 + step)) for i0 in range(0, n, step)], workers)
+        rng.bit_generator.advance(n * nv)
+        if progress is not None:
+            progress(f"blobs {n}/{n}")
+    else:
+        v = np.empty((n, nv, 3), np.float32)
+        for i0 in range(0, n, step):
+            i1 = min(n, i0 + step)
+            noise_v = rng.uniform(noise[0], noise[1], size=(i1 - i0, nv))
+            v[i0:i1] = tv[None, :nv, :] * (noise_v * radii[i0:i1, None])[:, :, None] + centres[i0:i1, None, :]
+            if progress is not None and (i1 == n or (i0 // step) % 64 == 63):
+                progress(f"blobs {i1}/{n}")
     lods = list(range(level_min, level_max + 1))
     tris = [faces[l] for l in lods]
     par = [parents[l] if i > 0 else np.full(len(faces[l]), -1, np.int32) for i, l in enumerate(lods)]
@@ -413,7 +504,7 @@ def _assemble(per_obj_verts, per_obj_template, templates, n_lods, kind):
                    tb, tc, parent, np.asarray(kind, np.int8))
 
 
-def blob_set(rng, n, box, level_min, level_max, radius_sigma=None, radius=1.0, progress=None):
+def blob_set(rng, n, box, level_min, level_max, radius_sigma=None, radius=1.0, progress=None, workers=1):
     """n blobs, centres U(box) then radii then noise (in that draw order)."""
     lo, hi = box
     centres = rng.uniform(lo, hi, size=(n, 3))
@@ -421,17 +512,17 @@ def blob_set(rng, n, box, level_min, level_max, radius_sigma=None, radius=1.0, p
         radii = np.full(n, radius)
     else:
         radii = np.exp(rng.normal(0.0, radius_sigma, size=n))
-    v, tris, par = make_blobs(rng, centres, radii, level_min, level_max, progress=progress)
+    v, tris, par = make_blobs(rng, centres, radii, level_min, level_max, progress=progress, workers=workers)
     L = level_max - level_min + 1
     templ = {("ico", level_min, level_max): (tris, par)}
     return _assemble(v, [("ico", level_min, level_max)] * n, templ, L, np.zeros(n))
 
 
-def tube_set(rng, n, box, n_seg, n_lods, length_range=(20.0, 80.0), radius=1.0, progress=None):
+def tube_set(rng, n, box, n_seg, n_lods, length_range=(20.0, 80.0), radius=1.0, progress=None, workers=1):
     """n tubes, centres U(box) then tube shape draws."""
     lo, hi = box
     centres = rng.uniform(lo, hi, size=(n, 3))
-    v, segs = make_tubes(rng, centres, n_seg, n_lods, length_range, radius, progress=progress)
+    v, segs = make_tubes(rng, centres, n_seg, n_lods, length_range, radius, progress=progress, workers=workers)
     tl, pl = tube_template(n_seg, n_lods)
     templ = {("tube", n_seg, n_lods): (tl, pl)}
     return _assemble(v, [("tube", n_seg, n_lods)] * n, templ, n_lods, np.ones(n))
@@ -519,13 +610,14 @@ def config_small(seed: int = 0, n_r: int = 100, n_s: int = 100, box=15.0):
     return R, S
 
 
-def config_multilod(seed: int = 1, n_r: int = 10000, n_s: int = 2000, box=500.0, n_seg=1280, progress=None):
+def config_multilod(seed: int = 1, n_r: int = 10000, n_s: int = 2000, box=500.0, n_seg=1280, progress=None,
+                    workers=1):
     """Multi-LoD join: R = blobs with LoDs at icosphere levels 1..4
     (80/320/1280/5120 triangles), radius lognormal(0, 0.3); S = tubes of
     length U(20, 80), radius 1, 4 LoDs decimated 4x per level (finest n_seg
     segments, 16*n_seg+16 triangles).  Centres U([0, box]^3)."""
-    R = blob_set(rng_for(seed, 0), n_r, (0.0, box), 1, 4, radius_sigma=0.3, progress=progress)
-    S = tube_set(rng_for(seed, 1), n_s, (0.0, box), n_seg, 4, progress=progress)
+    R = blob_set(rng_for(seed, 0), n_r, (0.0, box), 1, 4, radius_sigma=0.3, progress=progress, workers=workers)
+    S = tube_set(rng_for(seed, 1), n_s, (0.0, box), n_seg, 4, progress=progress, workers=workers)
     return R, S
 
 
@@ -588,17 +680,21 @@ def config_knn(seed: int = 2, n_r: int = 20000, n_s: int = 20000, n_clusters: in
 
 
 def config_learned(seed: int = 4, n_r: int = 100000, n_s: int = 20000, box: float = 5000.0, n_seg: int = 1280,
-                   progress=None):
+                   progress=None, workers=None):
     """Learned-skip workload: the multi-LoD object shapes at 10x the counts in
     a 5000^3 box, joined within tau = 10."""
-    return config_multilod(seed=seed, n_r=n_r, n_s=n_s, box=box, n_seg=n_seg, progress=progress)
+    return config_multilod(seed=seed, n_r=n_r, n_s=n_s, box=box, n_seg=n_seg, progress=progress,
+                           workers=default_workers() if workers is None else workers)
 
 
 def config_large(seed: int = 5, n_r: int = 1000000, n_s: int = 200000, box: float = 20000.0, n_seg: int = 1280,
-                 progress=None):
+                 progress=None, workers=None):
     """Large intersection workload: 1M blobs (80..5120 triangles) and 200k
-    tubes (336..20,496 triangles) in a 20000^3 box, joined at tau = 0."""
-    return config_multilod(seed=seed, n_r=n_r, n_s=n_s, box=box, n_seg=n_seg, progress=progress)
+    tubes (336..20,496 triangles) in a 20000^3 box, joined at tau = 0.  The
+    vertex arrays (55 GB at full size) are built by worker processes into
+    shared memory; the arrays do not depend on the worker count."""
+    return config_multilod(seed=seed, n_r=n_r, n_s=n_s, box=box, n_seg=n_seg, progress=progress,
+                           workers=default_workers() if workers is None else workers)
 
 
 CONFIGS = {

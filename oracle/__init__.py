@@ -73,6 +73,9 @@ def lib():
         L.oracle_object_distance.restype = ctypes.c_double
         L.oracle_pair_distances.argtypes = [sp, sp, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                             ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+        L.oracle_pair_distances_counted.argtypes = [sp, sp, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                                    ctypes.c_void_p, ctypes.c_void_p]
         L.oracle_mbb_all.argtypes = [sp, ctypes.c_void_p, ctypes.c_void_p]
         L.oracle_hd_ph.argtypes = [sp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
         L.oracle_lod_bounds.argtypes = [sp, ctypes.c_int, sp, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
@@ -177,6 +180,20 @@ def pair_distances(R: OSet, S: OSet, rr, ss, lod: int = -1, mode: int = 1, threa
         lib().oracle_pair_distances(R.ref, S.ref, len(rr), rr.ctypes.data, ss.ctypes.data, int(lod), int(mode),
                                     int(threads), d.ctypes.data, h.ctypes.data)
     return d, h.astype(bool)
+
+
+def pair_distances_counted(R: OSet, S: OSet, rr, ss, threads: int = 0):
+    """pair_distances (finest LoD, culled scan) plus the number of facet pairs
+    the scan evaluated for each object pair."""
+    rr = np.ascontiguousarray(rr, np.int32)
+    ss = np.ascontiguousarray(ss, np.int32)
+    d = np.empty(len(rr), np.float64)
+    h = np.zeros(len(rr), np.int8)
+    ev = np.zeros(len(rr), np.int64)
+    if len(rr):
+        lib().oracle_pair_distances_counted(R.ref, S.ref, len(rr), rr.ctypes.data, ss.ctypes.data, -1, 1,
+                                            int(threads), d.ctypes.data, h.ctypes.data, ev.ctypes.data)
+    return d, h.astype(bool), ev
 
 
 def mbbs(S: OSet):

@@ -379,8 +379,20 @@ static int cmp_bp(const void *x, const void *y)
  * mode 1 ("culled"): a facet pair whose boxes are at least the current best
  * apart cannot lower the minimum and is skipped; the first meeting pair ends
  * the scan (d = 0).  Both modes return the same minimum. */
+static double object_distance_counted(const om_set *R, int r, int lod_r, const om_set *S, int s, int lod_s, int mode,
+                                      int *hit, int64_t *evals);
+
 double oracle_object_distance(const om_set *R, int r, int lod_r, const om_set *S, int s, int lod_s, int mode, int *hit)
 {
+    return object_distance_counted(R, r, lod_r, S, s, lod_s, mode, hit, NULL);
+}
+
+/* The same scan, also counting the facet pairs whose distance (or meet
+ * test) it evaluated, when evals is not NULL (instrumentation only). */
+static double object_distance_counted(const om_set *R, int r, int lod_r, const om_set *S, int s, int lod_s, int mode,
+                                      int *hit, int64_t *evals)
+{
+    int64_t ne = 0;
     int nr, ns;
     double *FR = load_facets(R, r, lod_r, &nr);
     double *FS = load_facets(S, s, lod_s, &ns);
@@ -389,6 +401,7 @@ double oracle_object_distance(const om_set *R, int r, int lod_r, const om_set *S
     if (mode == 0) {
         for (int i = 0; i < nr && !h; i++)
             for (int j = 0; j < ns; j++) {
+                ne++;
                 if (oracle_tri_tri_intersect_d(FR + 9 * i, FS + 9 * j)) { h = 1; best = 0.0; break; }
                 best = fmin(best, oracle_tri_tri_d15(FR + 9 * i, FS + 9 * j));
             }
@@ -451,6 +464,7 @@ double oracle_object_distance(const om_set *R, int r, int lod_r, const om_set *S
                         g2 += g * g;
                     }
                     if (g2 >= best2) continue;
+                    ne++;
                     if (g2 == 0.0 && oracle_tri_tri_intersect_d(FR + 9 * i, FS + 9 * j)) { h = 1; best = 0.0; break; }
                     double d = oracle_tri_tri_d15(FR + 9 * i, FS + 9 * j);
                     if (d < best) { best = d; best2 = d * d; }
@@ -466,6 +480,7 @@ double oracle_object_distance(const om_set *R, int r, int lod_r, const om_set *S
     free(FR);
     free(FS);
     if (hit) *hit = h;
+    if (evals) *evals = ne;
     return (nr == 0 || ns == 0) ? INFINITY : best;
 }
 
@@ -482,6 +497,23 @@ void oracle_pair_distances(const om_set *R, const om_set *S, int64_t n, const in
         int ls = lod < 0 ? S->n_lods - 1 : lod;
         int h = 0;
         d[k] = oracle_object_distance(R, rr[k], lr, S, ss[k], ls, mode, &h);
+        if (hit) hit[k] = (int8_t)h;
+    }
+}
+
+/* oracle_pair_distances plus the facet pairs evaluated per object pair. */
+void oracle_pair_distances_counted(const om_set *R, const om_set *S, int64_t n, const int32_t *rr, const int32_t *ss,
+                                   int lod, int mode, int threads, double *d, int8_t *hit, int64_t *evals)
+{
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t k = 0; k < n; k++) {
+        int lr = lod < 0 ? R->n_lods - 1 : lod;
+        int ls = lod < 0 ? S->n_lods - 1 : lod;
+        int h = 0;
+        d[k] = object_distance_counted(R, rr[k], lr, S, ss[k], ls, mode, &h, evals + k);
         if (hit) hit[k] = (int8_t)h;
     }
 }

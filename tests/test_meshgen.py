@@ -35,3 +35,15 @@ def test_multilod_structure():
             v = ms.verts[ms.vert_begin[o]:ms.vert_begin[o] + ms.vert_count[o]]
             c = 0.5 * (v.min(0) + v.max(0))
             assert np.all(c >= -1e-3) and np.all(c <= 50.0 + 1e-3)
+
+
+def test_worker_processes_do_not_change_arrays(monkeypatch):
+    """The large sets are built by forked workers into shared memory (blob
+    noise from a generator advanced past the earlier blocks); the arrays are
+    those of one serial pass."""
+    monkeypatch.setattr(mg, "BLOB_BLOCK_VALUES", 4 * 2562)
+    monkeypatch.setattr(mg, "TUBE_BLOCK", 3)
+    a = mg.config_large(n_r=41, n_s=10, box=300.0, n_seg=64, workers=1)
+    b = mg.config_large(n_r=41, n_s=10, box=300.0, n_seg=64, workers=3)
+    for x, y in zip(a, b):
+        assert all(np.array_equal(p, q) for p, q in zip(_arrays(x), _arrays(y)))
