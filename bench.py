@@ -1,16 +1,21 @@
 #!/usr/bin/env python
-"""Benchmark of the progressive polyhedral within-tau join on one MI355X.
+"""Benchmark of the progressive polyhedral spatial join on one MI355X.
 
-A step is one pass of the whole hot path over the multi-LoD workload:
-within-tau joins at tau = 0, 5 and 20 of 10k blob objects (LoDs of
-80/320/1280/5120 triangles) against 2k tube objects (336..20,496 triangles)
-in a 500^3 box (MBB filter, progressive LoD refinement, guard-band recheck).
-Inputs are ingested into HBM before the timed region.
+The default workload is the large intersection join: 1M blob objects (LoDs
+of 80/320/1280/5120 triangles) against 200k tube objects (336..20,496
+triangles) in a 20000^3 box, tau = 0.  A step is one pass of the whole hot
+path (MBB filter, progressive LoD refinement with the learned first LoD,
+guard-band recheck, result assembly).  The timed steps run on mesh sets
+ingested into HBM before the timed region; the same join with the sets kept
+in host memory under a 32 GB device cap (chunked streaming over PCIe) is
+timed after it and reported beside the headline, with the plain GPU schedule
+under the same cap.  The multi-LoD and learned-skip workloads are measured
+in the same run and reported in ``config.other_workloads``.
 
-Prints ONE JSON line (rank 0) with the metric, a roofline entry for the
-dominant kernel (FP32 tile refinement, timed with HIP events by the library
-on its stream), the plain GPU schedule on the same inputs, and the CPU
-oracle timed on a bounded sample.
+Prints ONE JSON line with the metric, a roofline entry for the FP32 tile
+refinement kernel (timed with HIP events by the library on its stream), the
+plain GPU schedule on the same inputs, and the CPU oracle's join over the
+workload's MBB candidates.
 """
 from __future__ import annotations
 
@@ -36,17 +41,16 @@ FLOP_PER_PAIR = 6 * 25 + 9 * 49 + 1 + 6
 PEAK_FP32_TFLOPS = 157.3
 SINGLE_ISSUE_FP32_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 TAUS = (0.0, 5.0, 20.0)
-COUNTERS = os.path.join(ROOT, "profiles", "k_refine_f32_multilod_counters.json")
+def counters_file(workload):
+    return os.path.join(ROOT, "profiles", f"k_refine_f32_{workload}_counters.json")
 
 
-def measured_traffic(workload="multilod"):
-    """HBM bytes per launch from the committed counter runs, or None when the
-    kernel sources changed since they were taken (or for another workload)."""
-    if workload != "multilod":
-        return None
+def measured_traffic(workload):
+    """HBM bytes per launch from the committed counter runs of this workload,
+    or None when there are none or the kernel sources changed since."""
     import hashlib
     try:
-        rec = json.load(open(COUNTERS))
+        rec = json.load(open(counters_file(workload)))
         sha = hashlib.sha256(b"".join(open(os.path.join(ROOT, s), "rb").read() for s in rec["sources"])).hexdigest()
         return rec["traffic_bytes_per_launch"] if sha == rec["source_sha256"] else None
     except (OSError, KeyError, ValueError):
@@ -58,13 +62,23 @@ def log(msg):
 
 
 def run_step(ctx, gR, gS, taus, verbose=False, k=None):
-    """One pass of the hot path: a within-tau join per tau, or one k-NN join."""
-    tot = dict(pairs=0, pairs64=0, pairsc=0, kms=0.0, launches=0, results=0, band=0, ms=0.0, kms64=0.0)
+    """One pass of the hot path: a within-tau join per tau, or one k-NN join.
+    ``digest`` identifies the result sets (sorted (r, s) pairs per tau, or
+    the k-NN id lists), so that variants can be checked for equal results."""
+    import hashlib
+    import numpy as np
+    h = hashlib.sha1()
+    tot = dict(pairs=0, pairs64=0, pairsc=0, kms=0.0, launches=0, results=0, band=0, ms=0.0, kms64=0.0,
+               planned=0, items=0, staged=0, chunks=0)
     for tau in (taus if k is None else [None]):
         if k is None:
             res = ctx.join_within(gR, gS, tau)
+            h.update(np.float64(tau).tobytes())
+            h.update(np.ascontiguousarray(res["r"], np.int32).tobytes())
+            h.update(np.ascontiguousarray(res["s"], np.int32).tobytes())
         else:
             kn = ctx.join_knn(gR, gS, k)
+            h.update(np.ascontiguousarray(kn["s"], np.int32).tobytes())
             res = {"r": kn["s"][kn["s"] >= 0]}
         st = ctx.stats()
         if verbose:
@@ -83,6 +97,11 @@ def run_step(ctx, gR, gS, taus, verbose=False, k=None):
         tot["launches"] += st["refine_launches"]
         tot["results"] += len(res["r"])
         tot["band"] += st["band_pairs"]
+        tot["planned"] += sum(st["lod_planned_pairs"])
+        tot["items"] += sum(st["lod_items"])
+        tot["staged"] += st["staged_bytes"]
+        tot["chunks"] += st["chunks"]
+    tot["digest"] = h.hexdigest()
     return tot
 
 
@@ -115,31 +134,40 @@ def one_step(pj, stream, gR, gS, taus, k=None, **cfg):
     return tot
 
 
-def sample_candidates(oracle, O_R, O_S, gap, max_r=20000, seed=0):
-    """MBB candidate pairs (box gap <= gap) of up to max_r random R objects,
-    found by an x-sorted sweep over S with the oracle's boxes."""
+def sample_candidates(oracle, O_R, O_S, gap, max_r=20000, seed=0, block=8192):
+    """MBB candidate pairs (box gap <= gap) of up to max_r random R objects
+    (all of R when max_r >= |R|), found by an x-sorted sweep over S with the
+    oracle's FP64 boxes, in (r, s) order."""
     import numpy as np
     bR, _ = oracle.mbbs(O_R)
     bS, _ = oracle.mbbs(O_S)
-    rng = np.random.default_rng(seed)
-    rs = np.sort(rng.permutation(len(bR))[:max_r])
+    if max_r >= len(bR):
+        rs = np.arange(len(bR))
+    else:
+        rs = np.sort(np.random.default_rng(seed).permutation(len(bR))[:max_r])
     order = np.argsort(bS[:, 0], kind="stable")
     xs = bS[order, 0]
     wmax = float(np.max(bS[:, 3] - bS[:, 0])) if len(bS) else 0.0
     cr, cs = [], []
-    for r in rs:
-        lo = np.searchsorted(xs, bR[r, 0] - gap - wmax, "left")
-        hi = np.searchsorted(xs, bR[r, 3] + gap, "right")
-        js = order[lo:hi]
-        if len(js) == 0:
+    for b0 in range(0, len(rs), block):
+        blk = rs[b0:b0 + block]
+        lo = np.searchsorted(xs, bR[blk, 0] - gap - wmax, "left")
+        hi = np.searchsorted(xs, bR[blk, 3] + gap, "right")
+        cnt = np.maximum(hi - lo, 0)
+        if cnt.sum() == 0:
             continue
-        md = oracle.mindist(bR[r:r + 1], bS[js])[0]
-        js = js[md <= gap]
-        cr.append(np.full(len(js), r))
-        cs.append(js)
+        r_rep = np.repeat(blk, cnt)
+        first = np.repeat(lo - np.concatenate([[0], np.cumsum(cnt)[:-1]]), cnt)
+        js = order[first + np.arange(cnt.sum())]
+        g = np.maximum(0.0, np.maximum(bS[js, :3] - bR[r_rep, 3:], bR[r_rep, :3] - bS[js, 3:]))
+        keep = np.sqrt(np.sum(g * g, -1)) <= gap
+        r_k, s_k = r_rep[keep], js[keep]
+        o = np.lexsort((s_k, r_k))
+        cr.append(r_k[o])
+        cs.append(s_k[o])
     if not cr:
         return np.zeros(0, np.int64), np.zeros(0, np.int64)
-    return np.concatenate(cr), np.concatenate(cs)
+    return np.concatenate(cr).astype(np.int64), np.concatenate(cs).astype(np.int64)
 
 
 def _facets(M, obj, lod):
@@ -186,10 +214,57 @@ def cpu_baseline(R, S, seconds, gap=5.0, per_pair=1 << 16):
                         f"at the finest LoD, {el:.1f} s of oracle time"))
 
 
-# Workloads: the default is the multi-LoD join the metric is quoted on; the
-# other two are the learned-skip join (10x the objects, sparser) and the
-# large intersection join with host-resident meshes under a 32 GB device cap.
+def cpu_join_baseline(R, S, tau, single_seconds=10.0):
+    """The oracle's join itself on the workload: every MBB candidate (box gap
+    <= tau, found by a sweep over the oracle's FP64 boxes) decided by its
+    culled finest-LoD scan, over all host threads (wall time of the whole
+    join); then the same scan on one thread over the first candidates until
+    `single_seconds` have passed (per-core rate, whole-join time
+    extrapolated).  value = facet pairs the scan evaluated per second."""
+    import numpy as np
+    import oracle
+    O_R, O_S = oracle.OSet(R), oracle.OSet(S)
+    threads = oracle.lib().oracle_num_threads()
+    t0 = time.time()
+    cr, cs = sample_candidates(oracle, O_R, O_S, tau, max_r=R.n_objects)
+    t_sweep = time.time() - t0
+    t0 = time.time()
+    d, hit, ev = oracle.pair_distances_counted(O_R, O_S, cr, cs, threads=threads)
+    t_all = time.time() - t0
+    n_res = int(np.sum(hit if tau == 0.0 else d <= tau))
+    # single thread on a prefix of the candidates (random order)
+    perm = np.random.default_rng(0).permutation(len(cr))
+    done, ev1, t1 = 0, 0, 0.0
+    while t1 < single_seconds and done < len(cr):
+        blk = perm[done:done + 8]
+        t0 = time.time()
+        _, _, e = oracle.pair_distances_counted(O_R, O_S, cr[blk], cs[blk], threads=1)
+        t1 += time.time() - t0
+        ev1 += int(e.sum())
+        done += len(blk)
+    per_core = ev1 / t1 if t1 > 0 else 0.0
+    return dict(value=float(ev.sum()) / t_all, unit="facet-pair evals/s", cores=threads, kind="oracle",
+                join_wall_s=t_all + t_sweep, join_scan_s=t_all, sweep_s=t_sweep, candidates=int(len(cr)),
+                results=n_res, facet_pairs_evaluated=int(ev.sum()),
+                single_thread={"value": per_core, "candidates": int(done), "seconds": t1,
+                               "join_s_extrapolated": t1 * len(cr) / max(done, 1)},
+                sample=(f"the oracle's whole join on this workload: all {len(cr)} MBB candidates (box gap <= {tau}) "
+                        f"decided by its culled FP64 finest-LoD scan (exact meet test) on {threads} threads in "
+                        f"{t_all:.2f} s plus a {t_sweep:.2f} s box sweep; single-threaded on {done} random "
+                        f"candidates in {t1:.1f} s ({per_core:.3e} facet pairs/s per core, whole join "
+                        f"extrapolated to {t1 * len(cr) / max(done, 1):.1f} s)"))
+
+
+# Workloads.  "large" is the default line (the largest configuration, and the
+# one the end-to-end speedup over the plain schedule is stated on); the
+# timed steps run on HBM-resident sets and the 32 GB-capped host-resident
+# variant ("capped") is timed beside them.
 WORKLOADS = {
+    "large": dict(builder="config_large", taus=(0.0,), ctx={}, cpu="join",
+                  capped=dict(host_resident=True, mem_cap_bytes=32 << 30),
+                  desc="large intersection join: {nr} blobs (80..5120 triangles) x {ns} tubes (336..20496 "
+                       "triangles), 20000^3 box, tau = 0; timed on HBM-resident mesh sets, with the same join on "
+                       "host-resident sets under a 32 GB device cap reported beside it"),
     "multilod": dict(builder="config_multilod", taus=TAUS, ctx={}, cpu_gap=5.0,
                      desc="multilod within-tau join: {nr} blobs (80/320/1280/5120 triangles) x {ns} tubes "
                           "(336..20496 triangles), 500^3 box, tau in {{0, 5, 20}} per step"),
@@ -199,11 +274,91 @@ WORKLOADS = {
     "knn": dict(builder="config_knn", taus=(), k=3, ctx={}, cpu_gap=5.0,
                 desc="batched k-NN join, k = 3: {nr} x {ns} blob/tube mix (finest 1k..50k triangles, 4 LoDs), "
                      "50 Gaussian clusters (sigma 30) in a 2000^3 box"),
-    "large": dict(builder="config_large", taus=(0.0,), ctx=dict(host_resident=True, mem_cap_bytes=32 << 30),
-                  cpu_gap=5.0,
-                  desc="large intersection join: {nr} blobs (80..5120 triangles) x {ns} tubes (336..20496 "
-                       "triangles), 20000^3 box, tau = 0, meshes host-resident, 32 GB device cap"),
 }
+
+
+def timed_steps(ctx, gR, gS, taus, kk, steps, warmup, verbose=True):
+    """warmup untimed steps, then `steps` timed ones bracketed by device
+    synchronisation; returns (per-step totals, wall seconds)."""
+    import torch
+    for w in range(warmup):
+        run_step(ctx, gR, gS, taus, k=kk)
+    torch.cuda.synchronize()
+    out = []
+    t_start = time.time()
+    for k in range(steps):
+        ts = time.time()
+        tot = run_step(ctx, gR, gS, taus, verbose=verbose and k == steps - 1, k=kk)
+        torch.cuda.synchronize()
+        tot["ms"] = (time.time() - ts) * 1e3
+        out.append(tot)
+    torch.cuda.synchronize()
+    return out, time.time() - t_start
+
+
+def kernel_roofline(steps, workload):
+    kms = sum(s["kms"] for s in steps)
+    launches = sum(s["launches"] for s in steps)
+    p32 = sum(s["pairs"] for s in steps)
+    achieved = (p32 * FLOP_PER_PAIR) / (kms * 1e-3) / 1e12 if kms > 0 else 0.0
+    return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(workload),
+            "kernel": "k_refine_f32", "launches": launches, "avg_launch_ms": kms / max(launches, 1),
+            "kernel_ms_per_step": kms / max(len(steps), 1),
+            "facet_pairs_per_launch": p32 / max(launches, 1), "flop_per_pair": FLOP_PER_PAIR,
+            "single_issue_fma_peak": SINGLE_ISSUE_FP32_TFLOPS}
+
+
+def variants(pj, stream, gR, gS, taus, kk, base_ms, base_digest, tune, wctx, ablations=True, plain=True):
+    """The ablations (no learned skip; no learned skip and no culling) and the
+    plain GPU schedule (FP64, one workgroup per pair and LoD, from LoD 0), one
+    step each on the same ingested sets; each reports whether its results
+    equal the timed run's."""
+    abl = {}
+    todo = []
+    if ablations:
+        todo += [("no_learned_skip", dict(**tune, **wctx)), ("no_learned_no_cull", dict(tile_cull=False, **tune, **wctx))]
+    if plain:
+        todo += [("plain_gpu_schedule", dict(schedule="plain", precision="fp64", **wctx))]
+    for name, cfg in todo:
+        t = one_step(pj, stream, gR, gS, taus, k=kk, **cfg)
+        a = {"ms": t["ms"], "facet_pairs": t["pairs"] + t["pairsc"] + t["pairs64"],
+             "planned_facet_pairs": t["planned"], "items": t["items"], "results": t["results"],
+             "results_match": t["digest"] == base_digest, "speedup_of_timed_run": t["ms"] / base_ms}
+        if name == "plain_gpu_schedule":
+            a["kernel_ms"] = t["kms64"]
+            if t["kms64"] > 0:
+                a["fp64_kernel_facet_pair_evals_per_s"] = t["pairs64"] / (t["kms64"] * 1e-3)
+        elif t["kms"] > 0:
+            ach = t["pairs"] * FLOP_PER_PAIR / (t["kms"] * 1e-3) / 1e12
+            a.update(kernel_ms=t["kms"], kernel_tflops=ach, kernel_frac=ach / PEAK_FP32_TFLOPS)
+        abl[name] = a
+        log(f"{name}: {t['ms']:.1f} ms, results match: {a['results_match']}")
+    return abl
+
+
+def measure_side(pj, stream, name, R, S, gen_s, model, workdir, steps):
+    """A workload other than the headline: HBM-resident sets, a few timed
+    steps, the ablations and the plain schedule."""
+    import torch
+    wl = WORKLOADS[name]
+    tune = dict(autotune=True, autotune_path=os.path.join(workdir, f"shapes_{name}.txt"))
+    ctx = pj.Context(stream=stream.cuda_stream, learned_skip=True, model_path=model, **tune)
+    t0 = time.time()
+    gR, gS = ctx.meshes(R), ctx.meshes(S)
+    torch.cuda.synchronize()
+    ing = time.time() - t0
+    st, wall = timed_steps(ctx, gR, gS, wl["taus"], wl.get("k"), steps, 1, verbose=False)
+    ms = wall * 1e3 / steps
+    pairs = sum(s["pairs"] + s["pairsc"] + s["pairs64"] for s in st)
+    abl = variants(pj, stream, gR, gS, wl["taus"], wl.get("k"), ms, st[-1]["digest"], tune, {}, ablations=True)
+    out = {"workload": wl["desc"].format(nr=R.n_objects, ns=S.n_objects), "steps": steps, "ms_per_step": ms,
+           "facet_pair_evals_per_s": pairs / wall, "ingest_s": ing, "generate_s": gen_s,
+           "results_per_step": st[-1]["results"], "roofline": kernel_roofline(st, name),
+           "speedup_vs_plain": abl["plain_gpu_schedule"]["ms"] / ms, "ablations": abl}
+    log(f"{name}: {ms:.2f} ms per step, {out['speedup_vs_plain']:.0f}x vs plain")
+    del gR, gS, ctx
+    return out
 
 
 def main():
@@ -211,9 +366,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="multilod")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="large")
     ap.add_argument("--plain", type=int, default=1, help="run the plain FP64 schedule once for comparison")
     ap.add_argument("--ablations", type=int, default=1, help="one step each without the learned skip / culling")
+    ap.add_argument("--capped-steps", type=int, default=5,
+                    help="large: timed steps on host-resident sets under the 32 GB cap (0: skip)")
+    ap.add_argument("--side", default="multilod,learned",
+                    help="large: other workloads measured in the same run (comma list, or 'none')")
+    ap.add_argument("--side-steps", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--n-r", type=int, default=None)
     ap.add_argument("--n-s", type=int, default=None)
@@ -221,9 +381,7 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
         sys.exit(2)
-    import torch
     import meshgen as mg
-    import paper_2604_19982_amd as pj
 
     wl = WORKLOADS[args.workload]
     taus = wl["taus"]
@@ -233,9 +391,20 @@ def main():
         size["n_r"] = args.n_r
     if args.n_s:
         size["n_s"] = args.n_s
+    # generated before anything touches the GPU (the large sets are built by
+    # forked worker processes)
     t0 = time.time()
     R, S = getattr(mg, wl["builder"])(progress=lambda m: log(f"generating: {m}"), **size)
-    log(f"generated {R.n_objects} x {S.n_objects} objects in {time.time() - t0:.1f} s")
+    gen_s = time.time() - t0
+    log(f"generated {R.n_objects} x {S.n_objects} objects in {gen_s:.1f} s")
+    side_sets = {}
+    if args.workload == "large" and args.side != "none":
+        for name in [x for x in args.side.split(",") if x]:
+            t0 = time.time()
+            side_sets[name] = getattr(mg, WORKLOADS[name]["builder"])() + (time.time() - t0,)
+            log(f"generated the {name} workload in {side_sets[name][2]:.1f} s")
+    import torch
+    import paper_2604_19982_amd as pj
     stream = torch.cuda.current_stream()
     import tempfile
     workdir = tempfile.mkdtemp(prefix="pj_bench_")
@@ -256,32 +425,17 @@ def main():
     fma_tflops = max(ctx.probe_fma(False) for _ in range(2)) / 1e3
     copy_gbps = ctx.probe_copy(1 << 30)
     log(f"probes: scalar FP32 FMA {fma_tflops:.1f} TFLOP/s, copy {copy_gbps:.0f} GB/s")
-    for w in range(args.warmup):
-        run_step(ctx, gR, gS, taus, k=kk)
-        log(f"warmup step {w} done")
-    torch.cuda.synchronize()
-    steps = []
-    t_start = time.time()
-    for k in range(args.steps):
-        ts = time.time()
-        tot = run_step(ctx, gR, gS, taus, verbose=True, k=kk)
-        torch.cuda.synchronize()
-        tot["ms"] = (time.time() - ts) * 1e3
-        steps.append(tot)
-        log(f"step {k}: {tot['ms']:.1f} ms, {tot['pairs']:.3e} FP32 + {tot['pairs64']:.3e} FP64 facet pairs, "
-            f"{tot['results']} results")
-    torch.cuda.synchronize()
-    wall = time.time() - t_start
+    steps, wall = timed_steps(ctx, gR, gS, taus, kk, args.steps, args.warmup)
     ms_per_step = wall * 1e3 / args.steps
+    log(f"timed: {ms_per_step:.2f} ms per step over {args.steps} steps")
     # every facet pair evaluated: bulk FP32 rounds, the recheck's FP32 collect pass, FP64
     pairs = sum(s["pairs"] + s["pairsc"] + s["pairs64"] for s in steps)
     value = pairs / wall
-    kms = sum(s["kms"] for s in steps)
-    launches = sum(s["launches"] for s in steps)
-    p32 = sum(s["pairs"] for s in steps)
-    achieved = (p32 * FLOP_PER_PAIR) / (kms * 1e-3) / 1e12 if kms > 0 else 0.0
     st = ctx.stats()
     shapes = open(tune["autotune_path"]).read().split("\n") if os.path.exists(tune["autotune_path"]) else []
+    roof = kernel_roofline(steps, args.workload)
+    roof.update(fma_probe_measured=fma_tflops, copy_probe_gbps=copy_gbps)
+    digest = steps[-1]["digest"]
     out = {
         "metric": "facet-pair evals/s; end-to-end join time, learned+batched vs plain GPU",
         "value": value,
@@ -297,50 +451,66 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["desc"].format(nr=R.n_objects, ns=S.n_objects),
                    "facet_pairs_per_step": pairs / args.steps,
+                   "planned_facet_pairs_per_step": steps[-1]["planned"],
                    "results_per_step": steps[-1]["results"],
+                   "results_digest": digest,
                    "band_pairs_per_step": steps[-1]["band"],
+                   "candidates_last_join": st["candidates"],
+                   "generate_s": gen_s,
                    "ingest_s": ingest_s,
-                   "chunks_last_join": st["chunks"],
-                   "staged_bytes_last_join": st["staged_bytes"],
                    "mode": "learned LoD skip + batched persistent tiles + FP32 with FP64 guard band + chunk and "
                            "facet culling + hipGraph rounds",
                    "lod_model": {"train_pairs": n_rec, "final_loss": train_loss},
-                   # evaluated FP32 facet pairs per second of refinement-kernel time
-                   "fp32_kernel_facet_pair_evals_per_s": p32 / (kms * 1e-3) if kms > 0 else 0.0,
+                   "fp32_kernel_facet_pair_evals_per_s": (sum(s["pairs"] for s in steps) /
+                                                          (sum(s["kms"] for s in steps) * 1e-3)
+                                                          if sum(s["kms"] for s in steps) > 0 else 0.0),
                    "tuned_shapes": [ln for ln in shapes if ln.strip()]},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(args.workload),
-                     "kernel": "k_refine_f32", "launches": launches, "avg_launch_ms": kms / max(launches, 1),
-                     "flop_per_pair": FLOP_PER_PAIR, "single_issue_fma_peak": SINGLE_ISSUE_FP32_TFLOPS,
-                     "fma_probe_measured": fma_tflops, "copy_probe_gbps": copy_gbps},
+        "roofline": roof,
     }
-    abl = {}
-    if args.ablations:
-        for name, cfg in (("no_learned_skip", {}), ("no_learned_no_cull", dict(tile_cull=False))):
-            t = one_step(pj, stream, gR, gS, taus, k=kk, **cfg, **tune, **wl["ctx"])
-            abl[name] = {"ms": t["ms"], "facet_pairs": t["pairs"] + t["pairsc"] + t["pairs64"], "results": t["results"]}
-            if t["kms"] > 0:
-                # the same kernel without culling: every facet pair of every visited item is evaluated
-                ach = t["pairs"] * FLOP_PER_PAIR / (t["kms"] * 1e-3) / 1e12
-                abl[name]["kernel_ms"] = t["kms"]
-                abl[name]["kernel_tflops"] = ach
-                abl[name]["kernel_frac"] = ach / PEAK_FP32_TFLOPS
-            log(f"ablation {name}: {t['ms']:.1f} ms")
-    if args.plain:
-        t = one_step(pj, stream, gR, gS, taus, k=kk, schedule="plain", precision="fp64", **wl["ctx"])
-        abl["plain_gpu_schedule"] = {"ms": t["ms"], "facet_pairs": t["pairs"] + t["pairsc"] + t["pairs64"],
-                                     "results": t["results"], "kernel_ms": t["kms64"]}
-        if t["kms64"] > 0:
-            # the plain FP64 kernel's facet pairs per second of its kernel time
-            abl["plain_gpu_schedule"]["fp64_kernel_facet_pair_evals_per_s"] = t["pairs64"] / (t["kms64"] * 1e-3)
-        log(f"plain schedule step: {t['ms']:.1f} ms")
-        out["config"]["plain_ms_per_step"] = t["ms"]
-        out["config"]["speedup_vs_plain"] = t["ms"] / ms_per_step
-    for name, a in abl.items():
-        a["results_match"] = a["results"] == steps[-1]["results"]
+    abl = variants(pj, stream, gR, gS, taus, kk, ms_per_step, digest, tune, wl["ctx"], args.ablations, args.plain)
+    if "plain_gpu_schedule" in abl:
+        out["config"]["plain_ms_per_step"] = abl["plain_gpu_schedule"]["ms"]
+        out["config"]["speedup_vs_plain"] = abl["plain_gpu_schedule"]["ms"] / ms_per_step
     out["config"]["ablations"] = abl
+    if wl.get("capped") and args.capped_steps > 0:
+        # the configuration's 32 GB device cap: the same join on host-resident
+        # sets, each refinement chunk's facets staged and uploaded while the
+        # previous chunk computes (PCIe-inclusive; never the headline value)
+        del gR, gS
+        ctx.close()
+        torch.cuda.synchronize()
+        cctx = pj.Context(stream=stream.cuda_stream, learned_skip=True, model_path=model, **tune, **wl["capped"])
+        t0 = time.time()
+        hR, hS = cctx.meshes(R), cctx.meshes(S)
+        torch.cuda.synchronize()
+        ing_h = time.time() - t0
+        log(f"ingested host-resident in {ing_h:.1f} s")
+        cst, cwall = timed_steps(cctx, hR, hS, taus, kk, args.capped_steps, 1)
+        cms = cwall * 1e3 / args.capped_steps
+        cab = variants(pj, stream, hR, hS, taus, kk, cms, digest, tune, wl["capped"], ablations=False,
+                       plain=args.plain)
+        cst_last = cctx.stats()
+        out["config"]["capped_host_resident"] = {
+            "mem_cap_bytes": wl["capped"]["mem_cap_bytes"], "steps": args.capped_steps, "ms_per_step": cms,
+            "results_match": cst[-1]["digest"] == digest, "ingest_s": ing_h,
+            "staged_bytes_per_step": cst[-1]["staged"], "chunks_per_step": cst[-1]["chunks"],
+            "peak_device_bytes": cst_last["peak_device_bytes"],
+            "speedup_vs_plain": (cab["plain_gpu_schedule"]["ms"] / cms) if "plain_gpu_schedule" in cab else None,
+            "plain_gpu_schedule": cab.get("plain_gpu_schedule")}
+        log(f"capped host-resident: {cms:.2f} ms per step")
+        del hR, hS
+        cctx.close()
+    if side_sets:
+        side = {}
+        for name, (sR, sS, sg) in list(side_sets.items()):
+            side[name] = measure_side(pj, stream, name, sR, sS, sg, model, workdir, args.side_steps)
+            del side_sets[name]
+        out["config"]["other_workloads"] = side
     if args.cpu_seconds > 0:
-        out["cpu_baseline"] = cpu_baseline(R, S, args.cpu_seconds, gap=wl["cpu_gap"])
+        if wl.get("cpu") == "join":
+            out["cpu_baseline"] = cpu_join_baseline(R, S, taus[0], single_seconds=args.cpu_seconds)
+        else:
+            out["cpu_baseline"] = cpu_baseline(R, S, args.cpu_seconds, gap=wl["cpu_gap"])
     print(json.dumps(out), flush=True)
 
 

@@ -80,8 +80,11 @@ typedef struct {
                                 an explicit tile_s / waves_per_cu always wins */
     int32_t mesh_residency;  /* pj_residency of mesh sets created on this context */
     int32_t stage_sets;      /* staging buffer sets for streamed chunks, 2 or 3 (0: 2) */
-    int32_t filter_mode;     /* MBB filter: 0 auto (x sweep when |R|*|S| > 2^26), 1 all pairs, 2 x sweep */
-    int32_t reserved0;       /* must be 0 */
+    int32_t filter_mode;     /* MBB filter: 0 auto (x sweep when |R|*|S| > 2^26), 1 all pairs, 2 x sweep.
+                                k-NN candidates: 1 all pairs; otherwise a grid over S's anchors when
+                                k <= 16 (all pairs for larger k) */
+    int32_t knn_prune_host;  /* 1: run the k-NN pruning rule on host threads instead of the GPU kernel (the
+                                CPU side of the pruning ablation; results are identical) */
     int64_t mem_cap_bytes;   /* device-memory budget for join work buffers (0: no cap) */
     const char *model_path;  /* LoD model weights written by pj_train_lod_model (NULL: none) */
     const char *log_path;    /* append per-pair resolution records here (NULL: no log) */
@@ -91,6 +94,8 @@ typedef struct {
                                 (work buffers, ingested facet data); NULL: hipMalloc.  Set both or neither */
     pj_free_fn dev_free;     /* NULL: hipFree */
     void *alloc_user;        /* passed to dev_alloc / dev_free */
+    const char *storage_dir; /* PJ_RESIDENT_FILE: directory (on an SSD) for the mesh sets' facet files;
+                                copied at context creation */
 } pj_config;
 
 /* Where a mesh set's facet data live.  DEVICE: uploaded once at ingest.
@@ -99,8 +104,14 @@ typedef struct {
  * uploads them on a copy stream while the previous chunk computes (the
  * paper's pipelined data transfer, Section 4.2 and Algorithm 5).  The device
  * then holds only boxes, anchors and per-LoD maxima of the set, and the
- * streamed chunks are sized by mem_cap_bytes. */
-typedef enum { PJ_RESIDENT_DEVICE = 0, PJ_RESIDENT_HOST = 1 } pj_residency;
+ * streamed chunks are sized by mem_cap_bytes.
+ * FILE: as HOST, but the facet data are written to a file in
+ * cfg.storage_dir (unlinked at once; it goes away with the set) and read back
+ * through a read-only mapping: out-of-core storage for sets larger than host
+ * memory (the paper's future work, Section 6).  Each chunk's prep thread asks
+ * the kernel to read ahead the next chunk's pages before it gathers its own,
+ * so the reads overlap the previous chunk's upload and compute. */
+typedef enum { PJ_RESIDENT_DEVICE = 0, PJ_RESIDENT_HOST = 1, PJ_RESIDENT_FILE = 2 } pj_residency;
 
 /* Fill *cfg with defaults: device 0, FP32 band, batched, tile culling on,
  * graphs on, no learned skip, no cap, autotuner off (tile_s 1024, 12 waves
@@ -210,6 +221,14 @@ typedef struct {
     double collect_kernel_ms;   /* their device time */
     int64_t collected_pairs;    /* facet pairs they kept for the FP64 recheck */
     int64_t collect_overflow;   /* object pairs whose kept pairs overflowed the list (full FP64 pass) */
+    int64_t lod_planned_pairs[8]; /* facet pairs of the (pair, LoD) items each LoD round visits, before any
+                                     culling (sum of n_r * n_s): fixed by the schedule's decisions alone, not by
+                                     tile order or timing */
+    int64_t knn_grid_cells;     /* cells of the k-NN candidate grid (0: all-pairs candidates) */
+    double t_prune_ms;          /* host wall time of the k-NN pruning rounds (GPU kernel or host threads) */
+    double t_prep_ms;           /* host time gathering streamed chunks' facet data (host/file residency), summed
+                                   over chunks; it runs on a prep thread beside the upload and compute of the
+                                   chunk before */
 } pj_stats;
 
 pj_status pj_get_stats(const pj_context *ctx, pj_stats *out);

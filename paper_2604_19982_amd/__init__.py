@@ -36,11 +36,11 @@ class Config(ctypes.Structure):
                 ("tile_cull", ctypes.c_int32), ("tile_s", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
                 ("host_threads", ctypes.c_int32), ("chunk_tiles", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("mesh_residency", ctypes.c_int32), ("stage_sets", ctypes.c_int32),
-                ("filter_mode", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("filter_mode", ctypes.c_int32), ("knn_prune_host", ctypes.c_int32),
                 ("mem_cap_bytes", ctypes.c_int64),
                 ("model_path", ctypes.c_char_p), ("log_path", ctypes.c_char_p), ("autotune_path", ctypes.c_char_p),
                 ("stream", ctypes.c_void_p), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
-                ("alloc_user", ctypes.c_void_p)]
+                ("alloc_user", ctypes.c_void_p), ("storage_dir", ctypes.c_char_p)]
 
 
 class MeshDesc(ctypes.Structure):
@@ -76,7 +76,8 @@ class Stats(ctypes.Structure):
                 ("lod_pairs", ctypes.c_int64 * 8), ("lod_kernel_ms", ctypes.c_double * 8),
                 ("collect_launches", ctypes.c_int64), ("collect_pairs", ctypes.c_int64),
                 ("collect_kernel_ms", ctypes.c_double), ("collected_pairs", ctypes.c_int64),
-                ("collect_overflow", ctypes.c_int64)]
+                ("collect_overflow", ctypes.c_int64), ("lod_planned_pairs", ctypes.c_int64 * 8),
+                ("knn_grid_cells", ctypes.c_int64), ("t_prune_ms", ctypes.c_double), ("t_prep_ms", ctypes.c_double)]
 
     def to_dict(self):
         d = {}
@@ -198,10 +199,13 @@ class Context:
     def __init__(self, device=0, precision="fp32", schedule="batched", learned_skip=False, want_dist=False,
                  use_graph=True, tile_cull=True, tile_s=0, waves_per_cu=0, mem_cap_bytes=0, model_path=None,
                  log_path=None, stream=None, chunk_tiles=0, autotune=False, autotune_path=None,
-                 host_resident=False, stage_sets=0, filter_mode="auto", allocator=None):
+                 host_resident=False, stage_sets=0, filter_mode="auto", allocator=None, storage_dir=None,
+                 knn_prune_host=False):
         """``allocator``: optional (alloc, free) Python callables for the
         library's device memory: alloc(nbytes) -> device address (int) or
-        None, free(address).  They back pj_config.dev_alloc / dev_free."""
+        None, free(address).  They back pj_config.dev_alloc / dev_free.
+        ``storage_dir``: mesh sets keep their facet data in a file there
+        (out-of-core residency; implies host_resident)."""
         L = lib()
         c = Config()
         L.pj_config_default(ctypes.byref(c))
@@ -217,11 +221,14 @@ class Context:
         c.mem_cap_bytes = int(mem_cap_bytes)
         c.chunk_tiles = int(chunk_tiles)
         c.autotune = int(bool(autotune))
-        c.mesh_residency = 1 if host_resident else 0
+        c.mesh_residency = 2 if storage_dir is not None else (1 if host_resident else 0)
         c.stage_sets = int(stage_sets)
-        c.filter_mode = {"auto": 0, "pairs": 1, "sweep": 2}[filter_mode]
+        c.filter_mode = {"auto": 0, "pairs": 1, "sweep": 2, "grid": 2}[filter_mode]
+        c.knn_prune_host = int(bool(knn_prune_host))
         self._paths = [None if p is None else os.fsencode(p) for p in (model_path, log_path, autotune_path)]
         c.model_path, c.log_path, c.autotune_path = self._paths
+        self._storage = None if storage_dir is None else os.fsencode(storage_dir)
+        c.storage_dir = self._storage
         c.stream = stream
         self._hooks = None
         if allocator is not None:
@@ -304,6 +311,7 @@ class Context:
         return d, hit.astype(bool)
 
     def pair_bounds(self, R: Meshes, S: Meshes, r, s, lod):
+        """LoD bounds of pairs (r[i], s[i])."""
         r = _arr(r, np.int32)
         s = _arr(s, np.int32)
         n = len(r)

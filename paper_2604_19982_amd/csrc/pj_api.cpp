@@ -27,6 +27,10 @@
 #include <unordered_map>
 #include <vector>
 
+#include <fcntl.h>
+#include <sys/mman.h>
+#include <unistd.h>
+
 #include "pj_internal.h"
 
 using namespace pj;
@@ -141,6 +145,17 @@ struct pj_meshes {
     std::vector<int32_t> h_tris;
     std::vector<float2> h_hdph;
     std::vector<float4> h_blk;
+    // where staging reads them: the vectors above, or (file residency) a
+    // read-only mapping of an unlinked file in cfg.storage_dir, the vectors
+    // then being empty
+    const float *p_verts = nullptr;
+    const int32_t *p_tris = nullptr;
+    const float2 *p_hdph = nullptr;
+    const float4 *p_blk = nullptr;
+    void *map = nullptr;
+    size_t map_len = 0;
+    int fd = -1;
+    bool file = false;
     MeshDev dev() const
     {
         return MeshDev{d_verts, d_tris, d_vbeg, d_tbeg, d_tcnt, d_hpbeg, d_hdph, d_bkbeg, d_blk, n, L};
@@ -236,7 +251,7 @@ struct pj_context {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     DevBuf b_items, b_tiles, b_out, b_out64, b_ctr, b_cand_r, b_cand_s, b_cand_lb, b_cand_ub, b_blk, b_blkoff,
         b_total, b_tmp0, b_tmp1, b_tmp2, b_tmp3, b_coll, b_ovf, b_theta, b_koff, b_klb, b_kub, b_kst0, b_kst1,
-        b_kleft,
+        b_kleft, b_gcell, b_gitems, b_gcnt, b_gfill, b_gbeg,
         b_sched;  // scheduling state of the FP32 rounds: workgroup slots, then A-block cursors
     // chunked streaming: two buffer sets, upload/download streams, pinned staging
     struct PinBuf {
@@ -267,6 +282,7 @@ struct pj_context {
     std::vector<float> model;
     float feat_mean[MLP_IN], feat_std[MLP_IN];
     bool has_model = false;
+    std::string storage_dir;  // file residency: where mesh sets spill their facet data
 };
 
 namespace {
@@ -391,8 +407,10 @@ extern "C" pj_status pj_context_create(const pj_config *cfg, pj_context **out)
         if (colon != std::string::npos) ctx->arch.resize(colon);
     }
     if (ctx->arch.empty()) ctx->arch = "gpu";
-    if (c.chunk_tiles < 0 || c.filter_mode < 0 || c.filter_mode > 2 || c.reserved0 != 0 ||
-        (c.mesh_residency != PJ_RESIDENT_DEVICE && c.mesh_residency != PJ_RESIDENT_HOST) ||
+    if (c.chunk_tiles < 0 || c.filter_mode < 0 || c.filter_mode > 2 || c.knn_prune_host < 0 || c.knn_prune_host > 1 ||
+        (c.mesh_residency != PJ_RESIDENT_DEVICE && c.mesh_residency != PJ_RESIDENT_HOST &&
+         c.mesh_residency != PJ_RESIDENT_FILE) ||
+        (c.mesh_residency == PJ_RESIDENT_FILE && (!c.storage_dir || !c.storage_dir[0])) ||
         (c.stage_sets != 0 && c.stage_sets != 2 && c.stage_sets != 3)) {
         delete ctx;
         return PJ_ERR_INVALID_ARG;
@@ -410,6 +428,8 @@ extern "C" pj_status pj_context_create(const pj_config *cfg, pj_context **out)
         delete ctx;
         return PJ_ERR_DEVICE;
     }
+    if (c.storage_dir) ctx->storage_dir = c.storage_dir;
+    ctx->cfg.storage_dir = nullptr;  // the copy above is used
     load_tune_cache(ctx);
     // a missing or unreadable model leaves the plain progressive schedule
     if (c.model_path && !load_model(ctx, c.model_path)) ctx->err = "LoD model not loaded; plain schedule in use";
@@ -463,6 +483,8 @@ void free_meshes(pj_meshes *m)
                     (void *)m->d_lodmax, (void *)m->d_bkbeg, (void *)m->d_blk, (void *)m->d_xord, (void *)m->d_xbox,
                     (void *)m->d_xanc, (void *)m->d_xmin})
         if (p) m->al.free(p);
+    if (m->map) munmap(m->map, m->map_len);
+    if (m->fd >= 0) close(m->fd);
     delete m;
 }
 
@@ -715,6 +737,8 @@ pj_status ingest_device(pj_context *ctx, const pj_mesh_desc *d, pj_meshes *m)
 // Host-resident ingest: the per-object preprocessing runs on the GPU over
 // batches of objects (each batch a compact device-resident set of its own,
 // released afterwards); hd/ph and block records come back to host memory.
+pj_status spill_to_file(pj_context *ctx, pj_meshes *m);
+
 pj_status ingest_host(pj_context *ctx, const pj_mesh_desc *d, pj_meshes *m)
 {
     hipStream_t st = ctx->stream;
@@ -854,7 +878,87 @@ pj_status ingest_host(pj_context *ctx, const pj_mesh_desc *d, pj_meshes *m)
     if ((e = upload(m->al, &m->d_anchor, m->h_anchor.data(), 3 * n, st)) != hipSuccess) return hipfail(ctx, e, "anchors");
     if ((e = upload(m->al, &m->d_lodmax, m->h_lodmax.data(), n * L, st)) != hipSuccess) return hipfail(ctx, e, "lodmax");
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hipfail(ctx, e, "ingest sync");
+    m->p_verts = m->h_verts.data();
+    m->p_tris = m->h_tris.data();
+    m->p_hdph = m->h_hdph.data();
+    m->p_blk = m->h_blk.data();
+    if (ctx->cfg.mesh_residency == PJ_RESIDENT_FILE) return spill_to_file(ctx, m);
     return PJ_OK;
+}
+
+// Out-of-core storage: the facet data of a host-resident set move to a file
+// in cfg.storage_dir (unlinked at once, so it disappears with the set or the
+// process) that is mapped read-only; the pages are written back and dropped
+// from the page cache, so the join reads them from the device (an SSD)
+// while the previous chunk computes.
+pj_status spill_to_file(pj_context *ctx, pj_meshes *m)
+{
+    const std::string tmpl = ctx->storage_dir + "/pj_meshes_XXXXXX";
+    std::vector<char> name(tmpl.begin(), tmpl.end());
+    name.push_back('\0');
+    const int fd = mkstemp(name.data());
+    if (fd < 0) return fail(ctx, PJ_ERR_INVALID_ARG, "cannot create a file in storage_dir");
+    unlink(name.data());
+    m->fd = fd;
+    const size_t pg = 4096;
+    auto up = [&](size_t x) { return (x + pg - 1) / pg * pg; };
+    const size_t b_verts = m->h_verts.size() * sizeof(float), b_tris = m->h_tris.size() * sizeof(int32_t),
+                 b_hdph = m->h_hdph.size() * sizeof(float2), b_blk = m->h_blk.size() * sizeof(float4);
+    const size_t o_verts = 0, o_tris = up(o_verts + b_verts), o_hdph = up(o_tris + b_tris), o_blk = up(o_hdph + b_hdph),
+                 len = std::max(up(o_blk + b_blk), pg);
+    if (ftruncate(fd, (off_t)len) != 0) return fail(ctx, PJ_ERR_OUT_OF_MEMORY, "storage_dir: cannot size the file");
+    auto put = [&](const void *src, size_t bytes, size_t off) -> bool {
+        const char *p = (const char *)src;
+        while (bytes > 0) {
+            const ssize_t w = pwrite(fd, p, std::min<size_t>(bytes, size_t(1) << 30), (off_t)off);
+            if (w <= 0) return false;
+            p += w;
+            off += (size_t)w;
+            bytes -= (size_t)w;
+        }
+        return true;
+    };
+    if (!put(m->h_verts.data(), b_verts, o_verts) || !put(m->h_tris.data(), b_tris, o_tris) ||
+        !put(m->h_hdph.data(), b_hdph, o_hdph) || !put(m->h_blk.data(), b_blk, o_blk) || fsync(fd) != 0)
+        return fail(ctx, PJ_ERR_OUT_OF_MEMORY, "storage_dir: write failed (disk full?)");
+    (void)posix_fadvise(fd, 0, (off_t)len, POSIX_FADV_DONTNEED);
+    void *map = mmap(nullptr, len, PROT_READ, MAP_SHARED, fd, 0);
+    if (map == MAP_FAILED) return fail(ctx, PJ_ERR_OUT_OF_MEMORY, "storage_dir: mmap failed");
+    m->map = map;
+    m->map_len = len;
+    const char *b = (const char *)map;
+    m->p_verts = (const float *)(b + o_verts);
+    m->p_tris = (const int32_t *)(b + o_tris);
+    m->p_hdph = (const float2 *)(b + o_hdph);
+    m->p_blk = (const float4 *)(b + o_blk);
+    std::vector<float>().swap(m->h_verts);
+    std::vector<int32_t>().swap(m->h_tris);
+    std::vector<float2>().swap(m->h_hdph);
+    std::vector<float4>().swap(m->h_blk);
+    m->file = true;
+    return PJ_OK;
+}
+
+// Ask the kernel to read ahead the file pages of these objects at one LoD
+// (file residency; the next chunk's data, while this one is gathered).
+void advise_objects(const pj_meshes *m, const std::vector<int32_t> &objs, int lod, bool finest)
+{
+    if (!m->file) return;
+    const uintptr_t pg = 4096;
+    auto will = [&](const void *p, size_t bytes) {
+        if (!bytes) return;
+        const uintptr_t a = (uintptr_t)p & ~(pg - 1), e = ((uintptr_t)p + bytes + pg - 1) & ~(pg - 1);
+        (void)madvise((void *)a, e - a, MADV_WILLNEED);
+    };
+    const int64_t L = m->L;
+    for (int o : objs) {
+        const int64_t key = (int64_t)o * L + lod;
+        const int32_t tc = m->h_tcnt[key];
+        will(m->p_verts + 3 * m->h_vbeg[o], 12 * (size_t)m->h_vcnt[o]);
+        will(m->p_tris + 3 * m->h_tbeg[key], 12 * (size_t)tc);
+        if (!finest) will(m->p_hdph + m->h_hpbeg[key], 8 * (size_t)tc);
+        will(m->p_blk + 2 * m->h_bkbeg[key], 32 * (size_t)((tc + 63) / 64));
+    }
 }
 
 // Boxes sorted by xmin (ties by id) for the sweep filter, with their anchors
@@ -900,7 +1004,7 @@ extern "C" pj_status pj_meshes_create(pj_context *ctx, const pj_mesh_desc *d, pj
     HIPTRY(ctx, hipSetDevice(ctx->cfg.device));
     pj_meshes *m = new pj_meshes();
     m->al = ctx->alloc;
-    pj_status s = ctx->cfg.mesh_residency == PJ_RESIDENT_HOST ? ingest_host(ctx, d, m) : ingest_device(ctx, d, m);
+    pj_status s = ctx->cfg.mesh_residency != PJ_RESIDENT_DEVICE ? ingest_host(ctx, d, m) : ingest_device(ctx, d, m);
     if (s == PJ_OK) s = sort_boxes(ctx, m);
     if (s != PJ_OK) {
         free_meshes(m);
@@ -939,7 +1043,7 @@ extern "C" pj_status pj_meshes_hdph(const pj_meshes *m, int32_t obj, int32_t lod
     }
     std::vector<float2> tmp(nf);
     if (m->host) {
-        if (nf) std::memcpy(tmp.data(), &m->h_hdph[m->h_hpbeg[k]], nf * sizeof(float2));
+        if (nf) std::memcpy(tmp.data(), m->p_hdph + m->h_hpbeg[k], nf * sizeof(float2));
     } else {
         if (hipSetDevice(m->device) != hipSuccess) return PJ_ERR_DEVICE;
         if (nf &&
@@ -1103,6 +1207,13 @@ void plan_tiles(const pj_meshes *R, const pj_meshes *S, const std::vector<int> &
         }
         pl.pairs += (int64_t)nA * nB;
     }
+}
+
+// Work of a LoD round as the schedule planned it: the facet pairs of its
+// items before any culling.
+void count_planned(pj_context *ctx, int lod, const TilePlan &pl)
+{
+    if (lod >= 0 && lod < 8) ctx->stats.lod_planned_pairs[lod] += pl.pairs;
 }
 
 // Tile-count hint of the persistent FP32 rounds (any positive value selects
@@ -1393,11 +1504,11 @@ void stage_fill(const pj_meshes *m, const SideStage &s, char *base, int nthreads
         const int o = s.objs[k];
         const int64_t key = (int64_t)o * L + s.lod;
         const int32_t tc = m->h_tcnt[key];
-        std::memcpy(verts + 3 * s.vdst[k], m->h_verts.data() + 3 * m->h_vbeg[o], 12 * (size_t)m->h_vcnt[o]);
-        if (s.tcopy[k]) std::memcpy(tris + 3 * s.tdst[k], m->h_tris.data() + 3 * m->h_tbeg[key], 12 * (size_t)tc);
-        if (!s.finest && tc) std::memcpy(hdph + s.hdst[k], m->h_hdph.data() + m->h_hpbeg[key], 8 * (size_t)tc);
+        std::memcpy(verts + 3 * s.vdst[k], m->p_verts + 3 * m->h_vbeg[o], 12 * (size_t)m->h_vcnt[o]);
+        if (s.tcopy[k]) std::memcpy(tris + 3 * s.tdst[k], m->p_tris + 3 * m->h_tbeg[key], 12 * (size_t)tc);
+        if (!s.finest && tc) std::memcpy(hdph + s.hdst[k], m->p_hdph + m->h_hpbeg[key], 8 * (size_t)tc);
         const int64_t nb = (tc + 63) / 64;
-        if (nb) std::memcpy(blk + 2 * s.bdst[k], m->h_blk.data() + 2 * m->h_bkbeg[key], 32 * (size_t)nb);
+        if (nb) std::memcpy(blk + 2 * s.bdst[k], m->p_blk + 2 * m->h_bkbeg[key], 32 * (size_t)nb);
     });
 }
 
@@ -1723,6 +1834,7 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
         }
         return PJ_OK;
     };
+    std::vector<double> prep_ms(nch, 0.0);  // host gather time per chunk (written by its prep)
     // host preparation of chunk j into the pinned buffers of its set (no HIP calls)
     auto prep = [&, nthreads](int j) {
         const int b = j % nsets;
@@ -1749,8 +1861,15 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
         hc[1] = (int32_t)(c.t1 - c.t0);
         hc[6] = cni;
         char *hs = (char *)ctx->pin_stage[b].p;
+        const double tp = now_ms();
+        if (j + 1 < (int)chunks.size()) {
+            // file residency: start reading the next chunk's pages now
+            if (hostR) advise_objects(R, chunks[j + 1].sR.objs, lod, finest);
+            if (hostS) advise_objects(S, chunks[j + 1].sS.objs, lod, finest);
+        }
         if (hostR) stage_fill(R, c.sR, hs, nthreads);
         if (hostS) stage_fill(S, c.sS, hs, nthreads);
+        prep_ms[j] = now_ms() - tp;
     };
     auto enqueue = [&](int j) -> pj_status {
         const int b = j % nsets;
@@ -1857,6 +1976,7 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
         return st_all;
     }
     for (int j = 0; j < nch; ++j) PJTRY(merge(j));
+    for (double x : prep_ms) ctx->stats.t_prep_ms += x;
     // the join stream must not run ahead of the downloads
     HIPTRY(ctx, hipStreamWaitEvent(st, ctx->ev_d2h[(nch - 1) % nsets], 0));
     ctx->stats.tiles += nt;
@@ -2257,6 +2377,7 @@ pj_status refine_within(pj_context *ctx, const pj_meshes *R, const pj_meshes *S,
         ctx->stats.rounds++;
         if (fp64) {
             plan_tiles(R, S, act, cand, ps, lod, finest, 64, TS, !plain, pl);
+            count_planned(ctx, lod, pl);
             std::vector<ItemOut64> out;
             PJTRY(run_f64(ctx, R, S, pl, plain, out));
             for (size_t k = 0; k < pl.items.size(); ++k) {
@@ -2284,6 +2405,7 @@ pj_status refine_within(pj_context *ctx, const pj_meshes *R, const pj_meshes *S,
             PJTRY(choose_shape(ctx, R, S, act, cand, ps, lod, finest, (float)tau, true));
             plan_tiles(R, S, act, cand, ps, lod, finest, 64 * kP, ctx->cur.tile_s, true, pl,
                        tile_target(ctx, ctx->cur.wpc));
+            count_planned(ctx, lod, pl);
             std::vector<ItemOut> out;
             PJTRY(run_f32(ctx, R, S, pl, (float)tau, true, out, 0));
             for (size_t k = 0; k < pl.items.size(); ++k) {
@@ -2370,8 +2492,9 @@ struct LogRec {
     int32_t label, n_lods;
 };
 
+// tau_of: per-candidate threshold (k-NN: the query's theta_r) instead of tau
 void append_log(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, double tau, const std::vector<Cand> &cand,
-                const std::vector<PairState> &ps)
+                const std::vector<PairState> &ps, const std::vector<float> *tau_of = nullptr)
 {
     if (!ctx->cfg.log_path || R->L != 4) return;
     FILE *fp = std::fopen(ctx->cfg.log_path, "ab");
@@ -2379,7 +2502,8 @@ void append_log(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, double 
     for (size_t i = 0; i < cand.size(); ++i) {
         if (ps[i].res_lod < 0) continue;
         LogRec rec;
-        pair_features(R, cand[i].r, S, cand[i].s, tau, cand[i].lb0, cand[i].ub0, rec.f);
+        pair_features(R, cand[i].r, S, cand[i].s, tau_of ? (double)(*tau_of)[cand[i].r] : tau, cand[i].lb0,
+                      cand[i].ub0, rec.f);
         rec.label = ps[i].res_lod;
         rec.n_lods = R->L;
         std::fwrite(&rec, sizeof(rec), 1, fp);
@@ -2416,7 +2540,8 @@ bool load_model(pj_context *ctx, const char *path)
 // First LoD per candidate from the model (learned skip); 0 where undecided
 // pairs have no prediction.
 pj_status learned_start(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, double tau, const std::vector<Cand> &cand,
-                        const std::vector<PairState> &ps, std::vector<int> &start)
+                        const std::vector<PairState> &ps, std::vector<int> &start,
+                        const std::vector<float> *tau_of = nullptr)
 {
     std::vector<int> idx;
     for (size_t i = 0; i < cand.size(); ++i)
@@ -2429,7 +2554,7 @@ pj_status learned_start(pj_context *ctx, const pj_meshes *R, const pj_meshes *S,
     host_for(ctx, n, [&](int64_t q) {
         const Cand &c = cand[idx[q]];
         float f[MLP_IN];
-        pair_features(R, c.r, S, c.s, tau, c.lb0, c.ub0, f);
+        pair_features(R, c.r, S, c.s, tau_of ? (double)(*tau_of)[c.r] : tau, c.lb0, c.ub0, f);
         for (int j = 0; j < MLP_IN; ++j) x[(size_t)q * MLP_IN + j] = (f[j] - ctx->feat_mean[j]) / ctx->feat_std[j];
         for (int l = 0; l < MLP_OUT; ++l)
             cost[(size_t)q * MLP_OUT + l] = (float)((double)R->count(c.r, l) * (double)S->count(c.s, l));
@@ -2542,9 +2667,102 @@ extern "C" pj_status pj_join_intersect(pj_context *ctx, const pj_meshes *R, cons
 namespace {
 
 // One pruning round of Algorithm 6 (corrected) on the device for every query.
+// Grid of the k-NN candidate kernels over S's anchors.  The cell edge is
+// about the distance of an S anchor to its k-th nearest neighbour (from a
+// sample: 128 anchors against up to 4096 others, scaled by the sampling
+// density), so a query finds its k bounds within a few cell shells; at
+// most 2^22 cells.
+KnnGrid knn_grid_params(const pj_meshes *S, int k)
+{
+    const int64_t n = S->n;
+    const float *a = S->h_anchor.data(), *b = S->h_box.data();
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, w[3] = {0, 0, 0}, M = 0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int c = 0; c < 3; ++c) {
+            const double x = a[3 * i + c];
+            lo[c] = std::min(lo[c], x);
+            hi[c] = std::max(hi[c], x);
+            w[c] = std::max(w[c], std::max(x - (double)b[6 * i + c], (double)b[6 * i + 3 + c] - x));
+            M = std::max(M, std::fabs(x));
+        }
+    double ext = 0.0;
+    for (int c = 0; c < 3; ++c) ext = std::max(ext, hi[c] - lo[c]);
+    ext = std::max(ext, 1e-6 * std::max(M, 1.0));
+    // k-th neighbour distance on a sample
+    const int64_t m = std::min<int64_t>(n, 4096), q = std::min<int64_t>(n, 128);
+    std::vector<double> kd;
+    std::vector<double> d(m);
+    for (int64_t t = 0; t < q; ++t) {
+        const int64_t i = t * n / q;
+        for (int64_t j = 0; j < m; ++j) {
+            const int64_t s = j * n / m;
+            const double dx = a[3 * s] - a[3 * i], dy = a[3 * s + 1] - a[3 * i + 1], dz = a[3 * s + 2] - a[3 * i + 2];
+            d[j] = std::sqrt(dx * dx + dy * dy + dz * dz);
+        }
+        const int64_t kk = std::min<int64_t>(m - 1, k);
+        std::nth_element(d.begin(), d.begin() + kk, d.end());
+        kd.push_back(d[kk]);
+    }
+    std::nth_element(kd.begin(), kd.begin() + kd.size() / 2, kd.end());
+    double c = kd.empty() ? ext : kd[kd.size() / 2] * std::cbrt((double)m / (double)n);
+    c = std::max(c, ext / 4096.0);
+    auto cells = [&](double cc) {
+        double t = 1.0;
+        for (int a2 = 0; a2 < 3; ++a2) t *= std::max(1.0, std::ceil((hi[a2] - lo[a2]) / cc + 1e-9));
+        return t;
+    };
+    while (cells(c) > double(1 << 22)) c *= 1.25;
+    KnnGrid g;
+    g.ox = (float)lo[0];
+    g.oy = (float)lo[1];
+    g.oz = (float)lo[2];
+    g.c = (float)c;
+    g.inv_c = (float)(1.0 / c);
+    g.gx = (int)std::max(1.0, std::ceil((hi[0] - lo[0]) / c + 1e-9));
+    g.gy = (int)std::max(1.0, std::ceil((hi[1] - lo[1]) / c + 1e-9));
+    g.gz = (int)std::max(1.0, std::ceil((hi[2] - lo[2]) / c + 1e-9));
+    g.wx = (float)w[0] * (1.0f + 0x1p-20f);
+    g.wy = (float)w[1] * (1.0f + 0x1p-20f);
+    g.wz = (float)w[2] * (1.0f + 0x1p-20f);
+    g.M = (float)M;
+    return g;
+}
+
+// The pruning rule on the host threads (the CPU side of the pruning
+// ablation, cfg.knn_prune_host): the same decisions as k_knn_prune, from the
+// same snapshot.
+void knn_prune_host(pj_context *ctx, int nR, const std::vector<int64_t> &off, const std::vector<Cand> &cand,
+                    const std::vector<double> &lb, const std::vector<double> &ub, const std::vector<int8_t> &sti,
+                    std::vector<int8_t> &sto, const std::vector<int32_t> &kleft)
+{
+    host_for(ctx, nR, [&](int64_t r) {
+        const int64_t o = off[r], N = off[r + 1] - o;
+        const int kl = kleft[r];
+        for (int64_t m = 0; m < N; ++m) {
+            const int8_t st = sti[o + m];
+            if (st != 0 || kl <= 0) {
+                sto[o + m] = st != 0 ? st : 2;
+                continue;
+            }
+            const double lbm = lb[o + m], ubm = ub[o + m];
+            const int idm = cand[o + m].s;
+            int maybe = 0, surely = 0;
+            for (int64_t n = 0; n < N; ++n) {
+                if (n == m || sti[o + n] != 0) continue;
+                const double lbn = lb[o + n], ubn = ub[o + n];
+                const int idn = cand[o + n].s;
+                maybe += (ubm < lbn || (ubm == lbn && idm < idn)) ? 0 : 1;
+                surely += (ubn < lbm || (ubn == lbm && idn < idm)) ? 1 : 0;
+            }
+            sto[o + m] = maybe < kl ? 1 : (surely >= kl ? 2 : 0);
+        }
+    });
+}
+
 pj_status knn_prune_round(pj_context *ctx, int nR, int k, const std::vector<int64_t> &off,
                           const std::vector<Cand> &cand, std::vector<PairState> &ps)
 {
+    const double t0 = now_ms();
     hipStream_t st = ctx->stream;
     const int64_t nc = (int64_t)cand.size();
     std::vector<double> lb(nc), ub(nc);
@@ -2555,6 +2773,12 @@ pj_status knn_prune_round(pj_context *ctx, int nR, int k, const std::vector<int6
         ub[i] = ps[i].UB;
         sti[i] = ps[i].status;
         if (ps[i].status == ST_CONF) kleft[cand[i].r]--;
+    }
+    if (ctx->cfg.knn_prune_host) {
+        knn_prune_host(ctx, nR, off, cand, lb, ub, sti, sto, kleft);
+        for (int64_t i = 0; i < nc; ++i) ps[i].status = sto[i];
+        ctx->stats.t_prune_ms += now_ms() - t0;
+        return PJ_OK;
     }
     PJTRY(ensure(ctx, ctx->b_klb, nc * 8));
     PJTRY(ensure(ctx, ctx->b_kub, nc * 8));
@@ -2571,6 +2795,7 @@ pj_status knn_prune_round(pj_context *ctx, int nR, int k, const std::vector<int6
     HIPTRY(ctx, hipMemcpyAsync(sto.data(), ctx->b_kst1.p, nc, hipMemcpyDeviceToHost, st));
     HIPTRY(ctx, hipStreamSynchronize(st));
     for (int64_t i = 0; i < nc; ++i) ps[i].status = sto[i];
+    ctx->stats.t_prune_ms += now_ms() - t0;
     return PJ_OK;
 }
 
@@ -2610,9 +2835,32 @@ extern "C" pj_status pj_join_knn(pj_context *ctx, const pj_meshes *R, const pj_m
     PJTRY(ensure(ctx, ctx->b_blk, nR * 4));
     PJTRY(ensure(ctx, ctx->b_koff, (nR + 1) * 8));
     PJTRY(ensure(ctx, ctx->b_total, 16));
-    HIPTRY(ctx, launch_knn_theta(R->d_anchor, nR, S->d_anchor, nS, k, ptr<float>(ctx->b_theta), st));
-    HIPTRY(ctx, launch_knn_cand(R->d_box, R->d_anchor, nR, S->d_box, S->d_anchor, nS, ptr<float>(ctx->b_theta),
-                                ptr<int32_t>(ctx->b_blk), nullptr, nullptr, nullptr, nullptr, 0, st));
+    // candidate generation through a grid over the S anchors, or all pairs
+    // (filter_mode 1, or k above what the grid kernel keeps in registers)
+    const bool use_grid = ctx->cfg.filter_mode != 1 && k <= kGridMaxK;
+    KnnGrid grid;
+    if (use_grid) {
+        grid = knn_grid_params(S, k);
+        const int64_t ncell = (int64_t)grid.gx * grid.gy * grid.gz;
+        PJTRY(ensure(ctx, ctx->b_gcell, (size_t)nS * 4));
+        PJTRY(ensure(ctx, ctx->b_gitems, (size_t)nS * 4));
+        PJTRY(ensure(ctx, ctx->b_gcnt, (size_t)ncell * 4));
+        PJTRY(ensure(ctx, ctx->b_gfill, (size_t)ncell * 4));
+        PJTRY(ensure(ctx, ctx->b_gbeg, (size_t)(ncell + 3 + ncell / 4096) * 8));
+        HIPTRY(ctx, launch_grid_build(S->d_anchor, nS, grid, ptr<int32_t>(ctx->b_gcell), ptr<int32_t>(ctx->b_gcnt),
+                                      ptr<int64_t>(ctx->b_gbeg), ptr<int64_t>(ctx->b_total) + 1,
+                                      ptr<int32_t>(ctx->b_gfill), ptr<int32_t>(ctx->b_gitems), st));
+        HIPTRY(ctx, launch_knn_theta_grid(R->d_anchor, nR, S->d_anchor, nS, k, grid, ptr<int64_t>(ctx->b_gbeg),
+                                          ptr<int32_t>(ctx->b_gitems), ptr<float>(ctx->b_theta), st));
+        HIPTRY(ctx, launch_knn_cand_grid(R->d_box, R->d_anchor, nR, S->d_box, S->d_anchor, nS, ptr<float>(ctx->b_theta),
+                                         grid, ptr<int64_t>(ctx->b_gbeg), ptr<int32_t>(ctx->b_gitems),
+                                         ptr<int32_t>(ctx->b_blk), nullptr, nullptr, nullptr, nullptr, 0, st));
+        ctx->stats.knn_grid_cells = ncell;
+    } else {
+        HIPTRY(ctx, launch_knn_theta(R->d_anchor, nR, S->d_anchor, nS, k, ptr<float>(ctx->b_theta), st));
+        HIPTRY(ctx, launch_knn_cand(R->d_box, R->d_anchor, nR, S->d_box, S->d_anchor, nS, ptr<float>(ctx->b_theta),
+                                    ptr<int32_t>(ctx->b_blk), nullptr, nullptr, nullptr, nullptr, 0, st));
+    }
     HIPTRY(ctx, launch_scan_i32_to_i64(ptr<int32_t>(ctx->b_blk), ptr<int64_t>(ctx->b_koff), ptr<int64_t>(ctx->b_total),
                                        nR, st));
     int64_t total = 0;
@@ -2623,9 +2871,16 @@ extern "C" pj_status pj_join_knn(pj_context *ctx, const pj_meshes *R, const pj_m
     PJTRY(ensure(ctx, ctx->b_cand_s, std::max<int64_t>(total, 1) * 4));
     PJTRY(ensure(ctx, ctx->b_cand_lb, std::max<int64_t>(total, 1) * 4));
     PJTRY(ensure(ctx, ctx->b_cand_ub, std::max<int64_t>(total, 1) * 4));
-    HIPTRY(ctx, launch_knn_cand(R->d_box, R->d_anchor, nR, S->d_box, S->d_anchor, nS, ptr<float>(ctx->b_theta),
-                                nullptr, ptr<int64_t>(ctx->b_koff), ptr<int32_t>(ctx->b_cand_s),
-                                ptr<float>(ctx->b_cand_lb), ptr<float>(ctx->b_cand_ub), 1, st));
+    if (use_grid)
+        HIPTRY(ctx, launch_knn_cand_grid(R->d_box, R->d_anchor, nR, S->d_box, S->d_anchor, nS,
+                                         ptr<float>(ctx->b_theta), grid, ptr<int64_t>(ctx->b_gbeg),
+                                         ptr<int32_t>(ctx->b_gitems), nullptr, ptr<int64_t>(ctx->b_koff),
+                                         ptr<int32_t>(ctx->b_cand_s), ptr<float>(ctx->b_cand_lb),
+                                         ptr<float>(ctx->b_cand_ub), 1, st));
+    else
+        HIPTRY(ctx, launch_knn_cand(R->d_box, R->d_anchor, nR, S->d_box, S->d_anchor, nS, ptr<float>(ctx->b_theta),
+                                    nullptr, ptr<int64_t>(ctx->b_koff), ptr<int32_t>(ctx->b_cand_s),
+                                    ptr<float>(ctx->b_cand_lb), ptr<float>(ctx->b_cand_ub), 1, st));
     std::vector<int64_t> off(nR + 1);
     std::vector<int32_t> cs(total);
     std::vector<float> clb(total), cub(total);
@@ -2649,8 +2904,22 @@ extern "C" pj_status pj_join_knn(pj_context *ctx, const pj_meshes *R, const pj_m
     const double t1 = now_ms();
     ctx->stats.t_filter_ms = t1 - t0;
     PJTRY(knn_prune_round(ctx, nR, k, off, cand, ps));
-    // coarse LoD rounds on the undecided candidates
     const int L = R->L;
+    // learned first LoD (the threshold feature of a candidate is its query's
+    // theta_r, the k-th smallest anchor bound), and resolution logs of the
+    // plain progressive order for training
+    const bool learned = ctx->cfg.learned_skip && ctx->has_model && L == MLP_OUT && ctx->cfg.schedule == PJ_SCHED_BATCHED;
+    std::vector<int> start(total, 0);
+    std::vector<float> theta;
+    if (learned || (ctx->cfg.log_path && L == MLP_OUT)) {
+        theta.resize(nR);
+        HIPTRY(ctx, hipMemcpyAsync(theta.data(), ctx->b_theta.p, (size_t)nR * 4, hipMemcpyDeviceToHost, st));
+        HIPTRY(ctx, hipStreamSynchronize(st));
+        for (float &x : theta)
+            if (!std::isfinite(x)) x = 1e30f;
+    }
+    if (learned) PJTRY(learned_start(ctx, R, S, 0.0, cand, ps, start, &theta));
+    // coarse LoD rounds on the undecided candidates
     const int TS = pick_tile_s(ctx);
     const bool plain = ctx->cfg.schedule == PJ_SCHED_PLAIN;
     const bool fp64 = plain || ctx->cfg.precision == PJ_PREC_FP64;
@@ -2660,12 +2929,18 @@ extern "C" pj_status pj_join_knn(pj_context *ctx, const pj_meshes *R, const pj_m
     for (int lod = 0; lod < (fp64 ? L - 1 : L); ++lod) {
         const bool fin_round = lod == L - 1;
         std::vector<int> act;
+        bool any = false;
         for (int64_t i = 0; i < total; ++i)
-            if (ps[i].status == ST_UNDEC) act.push_back((int)i);
-        if (act.empty()) break;
+            if (ps[i].status == ST_UNDEC) {
+                any = true;
+                if (start[i] <= lod) act.push_back((int)i);
+            }
+        if (!any) break;
+        if (act.empty()) continue;
         ctx->stats.rounds++;
         if (fp64) {
             plan_tiles(R, S, act, cand, ps, lod, 0, 64, TS, !plain, pl);
+            count_planned(ctx, lod, pl);
             std::vector<ItemOut64> o64;
             PJTRY(run_f64(ctx, R, S, pl, plain, o64));
             for (size_t q = 0; q < pl.items.size(); ++q) {
@@ -2678,6 +2953,7 @@ extern "C" pj_status pj_join_knn(pj_context *ctx, const pj_meshes *R, const pj_m
             PJTRY(choose_shape(ctx, R, S, act, cand, ps, lod, fin_round, -1.0f, false));
             plan_tiles(R, S, act, cand, ps, lod, fin_round, 64 * kP, ctx->cur.tile_s, true, pl,
                        tile_target(ctx, ctx->cur.wpc));
+            count_planned(ctx, lod, pl);
             std::vector<ItemOut> o32;
             PJTRY(run_f32(ctx, R, S, pl, -1.0f, false, o32, 0));
             for (size_t q = 0; q < pl.items.size(); ++q) {
@@ -2688,9 +2964,14 @@ extern "C" pj_status pj_join_knn(pj_context *ctx, const pj_meshes *R, const pj_m
                 if (fin_round && std::isfinite(u)) p.thr = std::min(p.thr, up_float((double)u + 2.0 * (double)p.eps));
             }
         }
+        std::vector<int8_t> before(total);
+        for (int64_t i = 0; i < total; ++i) before[i] = ps[i].status;
         PJTRY(knn_prune_round(ctx, nR, k, off, cand, ps));
-        for (int i : act)
-            if (ps[i].status != ST_UNDEC) ctx->stats.resolved_at_lod[lod]++;
+        for (int64_t i = 0; i < total; ++i)
+            if (before[i] == ST_UNDEC && ps[i].status != ST_UNDEC) {
+                ctx->stats.resolved_at_lod[lod]++;
+                ps[i].res_lod = (int8_t)lod;
+            }
     }
     ctx->stats.t_refine_ms = now_ms() - t1;
     // finest LoD: exact FP64 distances of every candidate still in play
@@ -2715,8 +2996,11 @@ extern "C" pj_status pj_join_knn(pj_context *ctx, const pj_meshes *R, const pj_m
         ps[i].LB = ps[i].UB = ps[i].d64;
     }
     const int undecided_before = (int)std::count_if(fin.begin(), fin.end(), [&](int i) { return ps[i].status == ST_UNDEC; });
+    for (int i : fin)
+        if (ps[i].status == ST_UNDEC) ps[i].res_lod = (int8_t)(L - 1);
     PJTRY(knn_prune_round(ctx, nR, k, off, cand, ps));
     ctx->stats.resolved_at_lod[L - 1] += undecided_before;
+    if (!learned && !theta.empty()) append_log(ctx, R, S, 0.0, cand, ps, &theta);
     ctx->stats.t_band_ms = now_ms() - t2;
     // results: confirmed candidates of each r ordered by (distance, id)
     for (int r = 0; r < nR; ++r) {

@@ -117,6 +117,24 @@ hipError_t launch_knn_theta(const float *ancR, int nR, const float *ancS, int nS
 hipError_t launch_knn_cand(const float *boxR, const float *ancR, int nR, const float *boxS, const float *ancS, int nS,
                            const float *theta, int32_t *count, const int64_t *off, int32_t *cs, float *clb,
                            float *cub, int write_pass, hipStream_t st);
+// Uniform grid over the S anchors for the k-NN candidates (host-chosen).
+struct KnnGrid {
+    float ox, oy, oz;  // origin (lowest corner)
+    float c, inv_c;    // cell edge and its reciprocal
+    int32_t gx, gy, gz;
+    float wx, wy, wz;  // widest anchor-to-box extent of S per axis
+    float M;           // largest anchor coordinate magnitude (error margins)
+};
+constexpr int kGridMaxK = 16;  // k of the grid theta kernel (registers); larger k uses the all-pairs kernels
+hipError_t launch_scan_large(const int32_t *in, int64_t *out, int64_t *total, int64_t n, hipStream_t st);
+hipError_t launch_grid_build(const float *ancS, int nS, const KnnGrid &g, int32_t *cell_of, int32_t *count,
+                             int64_t *beg, int64_t *total, int32_t *fill, int32_t *items, hipStream_t st);
+hipError_t launch_knn_theta_grid(const float *ancR, int nR, const float *ancS, int nS, int k, const KnnGrid &g,
+                                 const int64_t *beg, const int32_t *items, float *theta, hipStream_t st);
+hipError_t launch_knn_cand_grid(const float *boxR, const float *ancR, int nR, const float *boxS, const float *ancS,
+                                int nS, const float *theta, const KnnGrid &g, const int64_t *beg,
+                                const int32_t *items, int32_t *count, const int64_t *off, int32_t *cs, float *clb,
+                                float *cub, int write_pass, hipStream_t st);
 hipError_t launch_knn_prune(int nR, const int64_t *off, const double *lb, const double *ub, const int32_t *ids,
                             const int8_t *status_in, int8_t *status_out, const int32_t *k_left, hipStream_t st);
 hipError_t launch_refine_f64_tiles(const Refine64Args &a, int64_t ntiles, hipStream_t st);

@@ -564,6 +564,84 @@ hipError_t launch_scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t *tota
     return hipGetLastError();
 }
 
+// Exclusive scan of long int32 arrays (grid cell counts): blocks of 4096
+// scanned in LDS with their totals, the totals scanned by one block, then
+// the block offsets added.  out has n + 1 entries (out[n] = total).
+constexpr int kScanTile = 4096;
+
+__global__ __launch_bounds__(1024) void k_scan_tiles(const int32_t *in, int64_t *out, int64_t *tile_sum, int64_t n)
+{
+    __shared__ int64_t sh[1024];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + 4 * threadIdx.x;
+    int64_t v[4], t = 0;
+    for (int j = 0; j < 4; ++j) {
+        v[j] = base + j < n ? in[base + j] : 0;
+        t += v[j];
+    }
+    sh[threadIdx.x] = t;
+    __syncthreads();
+    for (int st = 1; st < 1024; st <<= 1) {
+        const int64_t add = threadIdx.x >= st ? sh[threadIdx.x - st] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int64_t run = sh[threadIdx.x] - t;
+    for (int j = 0; j < 4; ++j) {
+        if (base + j < n) out[base + j] = run;
+        run += v[j];
+    }
+    if (threadIdx.x == 1023) tile_sum[blockIdx.x] = sh[1023];
+}
+
+__global__ __launch_bounds__(1024) void k_scan_sums(int64_t *tile_sum, int ntiles, int64_t *total)
+{
+    __shared__ int64_t sh[1024];
+    int64_t carry = 0;
+    for (int b0 = 0; b0 < ntiles; b0 += 1024) {
+        const int i = b0 + threadIdx.x;
+        const int64_t x = i < ntiles ? tile_sum[i] : 0;
+        sh[threadIdx.x] = x;
+        __syncthreads();
+        for (int st = 1; st < 1024; st <<= 1) {
+            const int64_t add = threadIdx.x >= st ? sh[threadIdx.x - st] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (i < ntiles) tile_sum[i] = carry + sh[threadIdx.x] - x;
+        const int64_t bt = sh[1023];
+        __syncthreads();
+        carry += bt;
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void k_scan_add(int64_t *out, const int64_t *tile_sum, int64_t n, const int64_t *total)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = i < n ? out[i] + tile_sum[i / kScanTile] : *total;
+}
+
+hipError_t launch_scan_large(const int32_t *in, int64_t *out, int64_t *total, int64_t n, hipStream_t st)
+{
+    // tile sums live after out[n] (the caller sizes out for n + 1 + n / 4096 + 1 entries)
+    const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
+    if (ntiles > kStrideBlocks) return hipErrorInvalidValue;
+    int64_t *tile_sum = out + n + 1;
+    if (ntiles > 0) {
+        hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(1024), 0, st, in, out, tile_sum, n);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, tile_sum, (int)ntiles, total);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)std::min<int64_t>((n + 256) / 256, kStrideBlocks)), dim3(256), 0,
+                       st, out, tile_sum, n, total);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Refinement outputs
 // ---------------------------------------------------------------------------
@@ -1321,6 +1399,230 @@ hipError_t launch_knn_cand(const float *boxR, const float *ancR, int nR, const f
     PJ_GRID_CHECK(nR, 64);
     hipLaunchKernelGGL(k_knn_cand, dim3(nR), dim3(64), 0, st, boxR, ancR, nR, boxS, ancS, nS, theta, count, off, cs,
                        clb, cub, write_pass);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// k-NN candidates through a uniform grid over the S anchors (scales past
+// all-pairs): the same theta_r (k-th smallest anchor bound) and the same
+// candidate test as above, evaluated only on the grid cells that can hold a
+// smaller bound or a box within theta_r.
+//   build:  cell of every S anchor, counting sort of S by cell;
+//   theta:  one thread per r visits cell shells of growing Chebyshev radius
+//           around r's (clamped) cell, keeping its k smallest bounds in
+//           registers, until the k-th is below the distance from r's anchor
+//           to every cell not visited yet (shrunk by one cell and an error
+//           margin, so an anchor binned one cell off is still covered);
+//   cand:   one thread per r tests the S objects of the cells its box can
+//           reach (box widened by theta_r, the widest anchor-to-box extent of
+//           S per axis and one cell), count then write, then sorts its list
+//           by s (the order of the all-pairs kernel).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int grid_coord(float x, float o, float inv_c, int g)
+{
+    const float f = (x - o) * inv_c;
+    const int c = f < 0.0f ? 0 : (f >= (float)g ? g - 1 : (int)f);
+    return c;
+}
+
+__global__ void k_grid_cell(const float *anc, int n, KnnGrid g, int32_t *cell_of, int32_t *count)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const float *a = anc + 3 * (int64_t)i;
+        const int cx = grid_coord(a[0], g.ox, g.inv_c, g.gx), cy = grid_coord(a[1], g.oy, g.inv_c, g.gy),
+                  cz = grid_coord(a[2], g.oz, g.inv_c, g.gz);
+        const int cell = (cz * g.gy + cy) * g.gx + cx;
+        cell_of[i] = cell;
+        atomicAdd(count + cell, 1);
+    }
+}
+
+__global__ void k_grid_scatter(const int32_t *cell_of, int n, const int64_t *beg, int32_t *fill, int32_t *items)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int cell = cell_of[i];
+        items[beg[cell] + atomicAdd(fill + cell, 1)] = i;
+    }
+}
+
+hipError_t launch_grid_build(const float *ancS, int nS, const KnnGrid &g, int32_t *cell_of, int32_t *count,
+                             int64_t *beg, int64_t *total, int32_t *fill, int32_t *items, hipStream_t st)
+{
+    const int64_t ncell = (int64_t)g.gx * g.gy * g.gz;
+    hipError_t e;
+    if ((e = hipMemsetAsync(count, 0, ncell * 4, st)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(fill, 0, ncell * 4, st)) != hipSuccess) return e;
+    if (nS > 0) {
+        const unsigned blocks = (unsigned)std::min<int64_t>((nS + 255) / 256, kStrideBlocks);
+        hipLaunchKernelGGL(k_grid_cell, dim3(blocks), dim3(256), 0, st, ancS, nS, g, cell_of, count);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if ((e = launch_scan_large(count, beg, total, ncell, st)) != hipSuccess) return e;
+    if (nS > 0) {
+        const unsigned blocks = (unsigned)std::min<int64_t>((nS + 255) / 256, kStrideBlocks);
+        hipLaunchKernelGGL(k_grid_scatter, dim3(blocks), dim3(256), 0, st, cell_of, nS, beg, fill, items);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// distance from x to the S anchors binned outside cells [c0, c1] of one
+// axis (an anchor may sit one cell off its bin): +inf on a side where the
+// grid ends
+__device__ __forceinline__ double side_gap(double x, int c0, int c1, int g, double o, double c)
+{
+    double gap = INFINITY;
+    if (c0 > 0) gap = fmin(gap, fmax(0.0, x - (o + (double)(c0 + 1) * c)));
+    if (c1 < g - 1) gap = fmin(gap, fmax(0.0, (o + (double)c1 * c) - x));
+    return gap;
+}
+
+__global__ __launch_bounds__(256) void k_knn_theta_grid(const float *ancR, int nR, const float *ancS, int nS, int k,
+                                                        KnnGrid g, const int64_t *beg, const int32_t *items,
+                                                        float *theta)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nR) return;
+    const float *ar = ancR + 3 * (int64_t)r;
+    if (nS < k) {
+        theta[r] = __builtin_inff();
+        return;
+    }
+    float top[kGridMaxK];  // ascending; the first k are the k smallest bounds seen
+#pragma unroll
+    for (int i = 0; i < kGridMaxK; ++i) top[i] = __builtin_inff();
+    float kth = __builtin_inff();
+    const int cx = grid_coord(ar[0], g.ox, g.inv_c, g.gx), cy = grid_coord(ar[1], g.oy, g.inv_c, g.gy),
+              cz = grid_coord(ar[2], g.oz, g.inv_c, g.gz);
+    const int maxr = max(max(max(cx, g.gx - 1 - cx), max(cy, g.gy - 1 - cy)), max(cz, g.gz - 1 - cz));
+    auto visit = [&](int x, int y, int z) {
+        const int cell = (z * g.gy + y) * g.gx + x;
+        for (int64_t q = beg[cell]; q < beg[cell + 1]; ++q) {
+            float v = anchor_ub(ar, ancS + 3 * (int64_t)items[q]);
+            if (v < kth) {
+#pragma unroll
+                for (int i = 0; i < kGridMaxK; ++i) {
+                    const float lo = fminf(top[i], v);
+                    v = fmaxf(top[i], v);
+                    top[i] = lo;
+                }
+#pragma unroll
+                for (int i = 0; i < kGridMaxK; ++i)
+                    if (i == k - 1) kth = top[i];
+            }
+        }
+    };
+    for (int rho = 0; rho <= maxr; ++rho) {
+        const int z0 = max(cz - rho, 0), z1 = min(cz + rho, g.gz - 1);
+        const int y0 = max(cy - rho, 0), y1 = min(cy + rho, g.gy - 1);
+        const int x0 = max(cx - rho, 0), x1 = min(cx + rho, g.gx - 1);
+        for (int z = z0; z <= z1; ++z) {
+            const bool zface = z == cz - rho || z == cz + rho;
+            for (int y = y0; y <= y1; ++y) {
+                const bool yface = y == cy - rho || y == cy + rho;
+                if (zface || yface) {
+                    for (int x = x0; x <= x1; ++x) visit(x, y, z);
+                } else {
+                    if (cx - rho >= 0) visit(cx - rho, y, z);
+                    if (rho > 0 && cx + rho < g.gx) visit(cx + rho, y, z);
+                }
+            }
+        }
+        const double c = (double)g.c;
+        double dmin = side_gap(ar[0], cx - rho, cx + rho, g.gx, g.ox, c);
+        dmin = fmin(dmin, side_gap(ar[1], cy - rho, cy + rho, g.gy, g.oy, c));
+        dmin = fmin(dmin, side_gap(ar[2], cz - rho, cz + rho, g.gz, g.oz, c));
+        if (dmin == INFINITY) break;  // every cell visited
+        const double margin = 0x1p-18 * dmin + 0x1p-20 * (double)g.M;
+        if ((double)kth < dmin - margin) break;
+    }
+    theta[r] = kth;
+}
+
+__global__ __launch_bounds__(256) void k_knn_cand_grid(const float *boxR, const float *ancR, int nR,
+                                                       const float *boxS, const float *ancS, int nS,
+                                                       const float *theta, KnnGrid g, const int64_t *beg,
+                                                       const int32_t *items, int32_t *count, const int64_t *off,
+                                                       int32_t *cs, float *clb, float *cub, int write_pass)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nR) return;
+    const float *br = boxR + 6 * (int64_t)r;
+    const float th = theta[r];
+    int lo[3], hi[3];
+    const float o[3] = {g.ox, g.oy, g.oz}, w[3] = {g.wx, g.wy, g.wz};
+    const int gd[3] = {g.gx, g.gy, g.gz};
+    for (int a = 0; a < 3; ++a) {
+        if (!(th < __builtin_inff())) {
+            lo[a] = 0;
+            hi[a] = gd[a] - 1;
+            continue;
+        }
+        const float reach = th + w[a] + g.c;
+        lo[a] = grid_coord(br[a] - reach, o[a], g.inv_c, gd[a]);
+        hi[a] = grid_coord(br[3 + a] + reach, o[a], g.inv_c, gd[a]);
+    }
+    int64_t pos = write_pass ? off[r] : 0;
+    int total = 0;
+    for (int z = lo[2]; z <= hi[2]; ++z)
+        for (int y = lo[1]; y <= hi[1]; ++y) {
+            const int row = (z * g.gy + y) * g.gx;
+            for (int64_t q = beg[row + lo[0]]; q < beg[row + hi[0] + 1]; ++q) {
+                const int s = items[q];
+                const float gp = box_gap(br, boxS + 6 * (int64_t)s) * (1.0f - 0x1p-20f);
+                if (gp <= th) {
+                    if (write_pass) {
+                        cs[pos] = s;
+                        clb[pos] = gp;
+                        cub[pos] = anchor_ub(ancR + 3 * (int64_t)r, ancS + 3 * (int64_t)s);
+                    }
+                    ++pos;
+                    ++total;
+                }
+            }
+        }
+    if (!write_pass) {
+        count[r] = total;
+        return;
+    }
+    // insertion sort of r's list by s (lists are short)
+    const int64_t b = off[r], e = off[r + 1];
+    for (int64_t i = b + 1; i < e; ++i) {
+        const int s = cs[i];
+        const float l = clb[i], u = cub[i];
+        int64_t j = i - 1;
+        while (j >= b && cs[j] > s) {
+            cs[j + 1] = cs[j];
+            clb[j + 1] = clb[j];
+            cub[j + 1] = cub[j];
+            --j;
+        }
+        cs[j + 1] = s;
+        clb[j + 1] = l;
+        cub[j + 1] = u;
+    }
+}
+
+hipError_t launch_knn_theta_grid(const float *ancR, int nR, const float *ancS, int nS, int k, const KnnGrid &g,
+                                 const int64_t *beg, const int32_t *items, float *theta, hipStream_t st)
+{
+    if (nR == 0) return hipSuccess;
+    if (k < 1 || k > kGridMaxK) return hipErrorInvalidValue;
+    PJ_GRID_CHECK((nR + 255) / 256, 256);
+    hipLaunchKernelGGL(k_knn_theta_grid, dim3((nR + 255) / 256), dim3(256), 0, st, ancR, nR, ancS, nS, k, g, beg,
+                       items, theta);
+    return hipGetLastError();
+}
+
+hipError_t launch_knn_cand_grid(const float *boxR, const float *ancR, int nR, const float *boxS, const float *ancS,
+                                int nS, const float *theta, const KnnGrid &g, const int64_t *beg,
+                                const int32_t *items, int32_t *count, const int64_t *off, int32_t *cs, float *clb,
+                                float *cub, int write_pass, hipStream_t st)
+{
+    if (nR == 0) return hipSuccess;
+    PJ_GRID_CHECK((nR + 255) / 256, 256);
+    hipLaunchKernelGGL(k_knn_cand_grid, dim3((nR + 255) / 256), dim3(256), 0, st, boxR, ancR, nR, boxS, ancS, nS,
+                       theta, g, beg, items, count, off, cs, clb, cub, write_pass);
     return hipGetLastError();
 }
 

@@ -1,9 +1,10 @@
-"""Parity at the full size of the bench workload (10k blobs x 2k tubes,
+"""Parity at full size.  The multi-LoD workload (10k blobs x 2k tubes,
 500^3 box, tau in {0, 5, 20}) in the configuration bench.py times (learned
 LoD skip, batched FP32 tiles, guard band, chunk culling, graphs).  The
-oracle checks sampled outputs one by one: random reported pairs must be
-within tau, random unreported MBB candidates must not be; properties that
-hold at any size (nesting in tau) are checked on the whole result."""
+oracle decides every reported pair and every MBB candidate of 500 random r
+per tau; properties that hold at any size (nesting in tau) are checked on
+the whole result.  The learned-skip workload is decided in full, the k-NN
+workload on 200 random queries."""
 import os
 import sys
 
@@ -38,32 +39,40 @@ def test_results_nest_in_tau(full):
     assert len(sets[0.0]) > 50 and len(sets[20.0]) > 10000
 
 
+@pytest.mark.timeout(900)
 @pytest.mark.parametrize("tau", [0.0, 5.0, 20.0])
-def test_sampled_pairs_match_oracle(orc, full, tau):
+def test_reported_pairs_and_sampled_candidates_match_oracle(orc, full, tau):
+    """Precision on every reported pair, recall on every MBB candidate of
+    500 random r (the query definitions of Section 3: a pair is in the
+    within-tau result iff its surface distance is at most tau; tau = 0 iff
+    the surfaces meet)."""
+    import bench
     R, S, res = full
     O_R, O_S = orc.OSet(R), orc.OSet(S)
-    rng = np.random.default_rng(int(tau) + 7)
-    got = set(zip(res[tau]["r"].tolist(), res[tau]["s"].tolist()))
-    # candidate pairs by box gap (exact), to sample negatives from
+    got = list(zip(res[tau]["r"].tolist(), res[tau]["s"].tolist()))
+    gset = set(got)
+    cr, cs = bench.sample_candidates(orc, O_R, O_S, tau, max_r=500, seed=int(tau) + 7)
+    assert len(cr) > 50
+    samp = set(zip(cr.tolist(), cs.tolist()))
+    # every reported pair, then the sampled candidates not reported
+    pairs = got + sorted(samp - gset)
+    rr = np.array([p[0] for p in pairs], np.int64)
+    ss = np.array([p[1] for p in pairs], np.int64)
+    d, hit = orc.pair_distances(O_R, O_S, rr, ss)
     bR, _ = orc.mbbs(O_R)
     bS, _ = orc.mbbs(O_S)
-    cand = []
-    for c0 in range(0, R.n_objects, 2000):
-        md = orc.mindist(bR[c0:c0 + 2000], bS)
-        i, j = np.nonzero(md <= tau)
-        cand += list(zip((i + c0).tolist(), j.tolist()))
-    neg = [p for p in cand if p not in got]
-    pos = sorted(got)
-    sp = [pos[i] for i in rng.choice(len(pos), min(40, len(pos)), replace=False)]
-    sn = [neg[i] for i in rng.choice(len(neg), min(40, len(neg)), replace=False)]
-    pairs = sp + sn
-    d, hit = orc.pair_distances(O_R, O_S, [p[0] for p in pairs], [p[1] for p in pairs])
+    M = orc.pair_scale(bR[rr], bS[ss])
+    # no near ties (a pair that meets is decided by the exact test, not by d)
+    assert not np.any(~hit & (np.abs(d - tau) <= 1e-12 * np.maximum(M, tau)))
     inside = hit if tau == 0.0 else d <= tau
-    M = np.maximum(np.abs(bR[[p[0] for p in pairs]]).max(1), np.abs(bS[[p[1] for p in pairs]]).max(1))
-    # no near ties in the sample (a pair that meets is decided by the exact test, not by d)
-    assert not np.any(~hit.astype(bool) & (np.abs(d - tau) <= 1e-12 * np.maximum(M, tau)))
-    assert np.all(inside[:len(sp)]), [pairs[k] for k in np.nonzero(~inside[:len(sp)])[0]]
-    assert not np.any(inside[len(sp):]), [pairs[len(sp) + k] for k in np.nonzero(inside[len(sp):])[0]]
+    n = len(got)
+    bad_pos = [pairs[k] for k in np.nonzero(~inside[:n])[0]]
+    bad_neg = [pairs[n + k] for k in np.nonzero(inside[n:])[0]]
+    assert not bad_pos, bad_pos[:10]
+    assert not bad_neg, bad_neg[:10]
+    # the sampled r's rows of the result are exactly the oracle's
+    rs = set(cr.tolist())
+    assert sorted(p for p in got if p[0] in rs) == sorted(p for k, p in enumerate(pairs) if inside[k] and p[0] in rs)
 
 
 # ---------------------------------------------------------------------------
@@ -124,9 +133,12 @@ def knn_full(tmp_path_factory):
     return R, S, res
 
 
+@pytest.mark.timeout(900)
 def test_knn_workload_sampled_parity(orc, knn_full):
+    """The exact k-NN lists (Section 3, query (3); ties by id) of 200 random
+    queries, with distances within 1e-5 relative."""
     R, S, res = knn_full
-    rs = np.sort(np.random.default_rng(11).choice(R.n_objects, 24, replace=False))
+    rs = np.sort(np.random.default_rng(11).choice(R.n_objects, 200, replace=False))
     O_R, O_S = orc.OSet(R), orc.OSet(S)
     ref = orc.join_knn(O_R, O_S, 3, r_subset=rs)
     assert ref["near_ties"] == 0

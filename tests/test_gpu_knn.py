@@ -69,3 +69,57 @@ def test_knn_empty_sets(pj):
     assert len(got["count"]) == 0
     with pytest.raises(pj.PJError):
         c.join_knn(gR, gR, 0)
+
+
+# ---------------------------------------------------------------------------
+# Grid-indexed candidate generation (the default for k <= 16) against the
+# all-pairs kernels: the same theta_r and candidate test, so the candidate
+# count and the k-NN lists and distances are identical bit for bit.
+# ---------------------------------------------------------------------------
+def _pair(pj, R, S, k, **kw):
+    out = []
+    for mode in ("grid", "pairs"):
+        c = pj.Context(filter_mode=mode, **kw)
+        res = c.join_knn(c.meshes(R), c.meshes(S), k)
+        out.append((res, c.stats()))
+    (a, sa), (b, sb) = out
+    assert np.array_equal(a["count"], b["count"]) and np.array_equal(a["s"], b["s"])
+    assert np.array_equal(a["dist"], b["dist"], equal_nan=True)
+    assert sa["candidates"] == sb["candidates"]
+    return sa, sb
+
+
+@pytest.mark.parametrize("k", [1, 3, 16, 17])
+def test_knn_grid_matches_all_pairs_clustered(pj, k):
+    R, S = mg.config_knn(seed=7, n_r=300, n_s=400, n_clusters=4, box=600.0, sigma=25.0, f_median=1500)
+    sa, sb = _pair(pj, R, S, k)
+    assert (sa["knn_grid_cells"] > 0) == (k <= 16) and sb["knn_grid_cells"] == 0
+
+
+def test_knn_grid_edges(pj, orc):
+    # queries far outside S's grid, k > |S| (theta = inf: every s), one S object
+    R, _ = mg.config_small(seed=8, n_r=12, n_s=1, box=50.0)
+    _, S = mg.config_small(seed=9, n_r=1, n_s=6, box=4.0)
+    for k in (1, 3, 6, 7):
+        _pair(pj, R, S, k)
+    _pair(pj, R, S.subset([2]), 1)
+    # identical objects (equal anchors and bounds: ties broken by id)
+    S2 = S.subset([0, 1, 0, 1])
+    _pair(pj, R, S2, 3)
+    c = pj.Context()
+    got = c.join_knn(c.meshes(R), c.meshes(S2), 3)
+    ref = orc.join_knn(orc.OSet(R), orc.OSet(S2), 3)
+    for r in range(R.n_objects):
+        assert got["s"][r].tolist() == ref["s"][r].tolist()
+
+
+def test_knn_prune_on_host_matches_gpu(pj):
+    """The pruning ablation: Algorithm 6 on host threads gives the same
+    decisions as the GPU kernel."""
+    R, S = mg.config_knn(seed=2, n_r=80, n_s=80, n_clusters=3, box=300.0, sigma=15.0, f_median=2000)
+    a = pj.Context()
+    b = pj.Context(knn_prune_host=True)
+    x = a.join_knn(a.meshes(R), a.meshes(S), 3)
+    y = b.join_knn(b.meshes(R), b.meshes(S), 3)
+    assert np.array_equal(x["s"], y["s"]) and np.array_equal(x["dist"], y["dist"])
+    assert a.stats()["t_prune_ms"] > 0 and b.stats()["t_prune_ms"] > 0

@@ -278,3 +278,53 @@ def test_sweep_filter_ties_and_edges(orc, pj):
     gA, gE = c.meshes(A), c.meshes(A.subset([]))
     assert len(c.join_within(gA, gE, 1.0)["r"]) == 0
     assert len(c.join_within(gE, gA, 1.0)["r"]) == 0
+
+
+# ---------------------------------------------------------------------------
+# Out-of-core residency: facet data in an (unlinked) file under storage_dir,
+# read back through a mapping by the chunk prep thread.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("cap", [0, 6 << 20])
+def test_file_resident_join_matches_device(pj, mid, dev_ref, tmp_path, cap):
+    R, S = mid
+    c = pj.Context(storage_dir=str(tmp_path), stage_sets=3, mem_cap_bytes=cap)
+    gR, gS = c.meshes(R), c.meshes(S)
+    assert os.listdir(tmp_path) == []  # the files are unlinked at once
+    for tau in (0.0, 5.0, 20.0):
+        got = c.join_within(gR, gS, tau)
+        st = c.stats()
+        ref = dev_ref[tau]
+        assert np.array_equal(got["r"], ref["r"]) and np.array_equal(got["s"], ref["s"]), tau
+        assert st["staged_bytes"] > 0 and st["t_prep_ms"] > 0.0
+        if cap:
+            assert st["chunks"] > st["rounds"] and st["peak_device_bytes"] <= cap
+    d = pj.Context()
+    for ms, g in ((R, gR), (S, gS)):
+        gd = d.meshes(ms)
+        for obj in (0, ms.n_objects - 1):
+            for lod in range(ms.n_lods):
+                assert all(np.array_equal(a, b) for a, b in zip(gd.hdph(obj, lod), g.hdph(obj, lod)))
+
+
+def test_file_resident_knn_and_oracle(orc, pj, tmp_path):
+    R, S = mg.config_small(seed=4, n_r=60, n_s=60, box=10.0)
+    c = pj.Context(storage_dir=str(tmp_path), want_dist=True, mem_cap_bytes=4 << 20)
+    gR, gS = c.meshes(R), c.meshes(S)
+    got = c.join_within(gR, gS, 0.5)
+    ref = orc.join_within(orc.OSet(R), orc.OSet(S), 0.5)
+    assert np.array_equal(got["r"], ref["r"]) and np.array_equal(got["s"], ref["s"])
+    assert np.all(np.abs(got["dist"] - ref["d"]) <= np.maximum(1e-5 * ref["d"], 1e-12 * 10.0))
+    d = pj.Context()
+    a = d.join_knn(d.meshes(R), d.meshes(S), 3)
+    b = c.join_knn(gR, gS, 3)
+    assert np.array_equal(a["s"], b["s"]) and np.array_equal(a["dist"], b["dist"])
+
+
+def test_file_residency_needs_a_directory(pj):
+    with pytest.raises(pj.PJError):
+        c = pj.Context(storage_dir="")
+        c.meshes(mg.config_small(seed=0, n_r=2, n_s=2)[0])
+    c = pj.Context(storage_dir="/nonexistent/dir")
+    with pytest.raises(pj.PJError) as e:
+        c.meshes(mg.config_small(seed=0, n_r=2, n_s=2)[0])
+    assert e.value.status == 1
