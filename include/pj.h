@@ -275,6 +275,23 @@ pj_status pj_facet_pairs(pj_context *ctx, const float *t1, const float *t2, int6
 pj_status pj_pair_bounds(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, int64_t n, const int32_t *r,
                          const int32_t *s, int32_t lod, double *lb, double *ub, int8_t *hit);
 
+/* Allocation-free variant of pj_pair_bounds, for callers that cannot
+ * allocate device memory (code running under stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, layout and
+ * results as pj_pair_bounds on a context with precision FP32_BAND and the
+ * batched schedule, over device-resident mesh sets; inputs and outputs are
+ * host arrays the caller owns.  The work lists live in a fixed 4 MiB device
+ * array that the library holds on each device until the process ends; the
+ * call makes no device or pinned allocation, no hipMalloc/hipFree and no
+ * graph.  Limits: n <= 4096 pairs (INVALID_ARG beyond); UNSUPPORTED for
+ * other precisions or schedules and for host-resident sets.  Every call on
+ * a device shares that device's array: calls that overlap on one device
+ * (from several threads or contexts) race and must be serialised by the
+ * caller. */
+pj_status pj_pair_bounds_noalloc(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, int64_t n,
+                                 const int32_t *r, const int32_t *s, int32_t lod, double *lb, double *ub,
+                                 int8_t *hit);
+
 /* The LoD-skip network on n feature rows (x[n][16]) with the given
  * parameters (FP32 master copies, layout W1[16][64] b1 W2[64][64] b2 W3[64][4]
  * b3), weights rounded to BF16 as in inference.  logits[n][4]; if y is not

@@ -95,7 +95,7 @@ class TrainOpts(ctypes.Structure):
 EXPORTS = ["pj_config_default", "pj_context_create", "pj_context_destroy", "pj_meshes_create", "pj_meshes_destroy",
            "pj_join_within", "pj_join_intersect", "pj_join_knn", "pj_pairs_free", "pj_knn_free", "pj_get_stats",
            "pj_last_error", "pj_train_lod_model", "pj_meshes_boxes", "pj_meshes_hdph", "pj_facet_pairs",
-           "pj_pair_bounds", "pj_mlp_eval", "pj_probe_fma", "pj_probe_copy"]
+           "pj_pair_bounds", "pj_pair_bounds_noalloc", "pj_mlp_eval", "pj_probe_fma", "pj_probe_copy"]
 
 _lib = None
 
@@ -138,6 +138,7 @@ def lib():
         L.pj_meshes_hdph.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp]
         L.pj_facet_pairs.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_int32, vp, vp, vp]
         L.pj_pair_bounds.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp, ctypes.c_int32, vp, vp, vp]
+        L.pj_pair_bounds_noalloc.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp, ctypes.c_int32, vp, vp, vp]
         L.pj_mlp_eval.argtypes = [vp, vp, vp, vp, ctypes.c_int64, vp, vp, vp]
         L.pj_probe_fma.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
         L.pj_probe_copy.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
@@ -310,16 +311,18 @@ class Context:
             return d, d_hi, hit.astype(bool)
         return d, hit.astype(bool)
 
-    def pair_bounds(self, R: Meshes, S: Meshes, r, s, lod):
-        """LoD bounds of pairs (r[i], s[i])."""
+    def pair_bounds(self, R: Meshes, S: Meshes, r, s, lod, noalloc=False):
+        """LoD bounds of pairs (r[i], s[i]); noalloc=True calls the
+        allocation-free entry point."""
         r = _arr(r, np.int32)
         s = _arr(s, np.int32)
         n = len(r)
         lb = np.zeros(n)
         ub = np.zeros(n)
         hit = np.zeros(n, np.int8)
-        self._check(lib().pj_pair_bounds(self.h, R.h, S.h, n, r.ctypes.data, s.ctypes.data, int(lod),
-                                         lb.ctypes.data, ub.ctypes.data, hit.ctypes.data))
+        fn = lib().pj_pair_bounds_noalloc if noalloc else lib().pj_pair_bounds
+        self._check(fn(self.h, R.h, S.h, n, r.ctypes.data, s.ctypes.data, int(lod), lb.ctypes.data, ub.ctypes.data,
+                       hit.ctypes.data))
         return lb, ub, hit.astype(bool)
 
     def mlp_eval(self, params, x, y=None):

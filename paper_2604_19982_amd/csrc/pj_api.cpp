@@ -282,6 +282,10 @@ struct pj_context {
     std::vector<float> model;
     float feat_mean[MLP_IN], feat_std[MLP_IN];
     bool has_model = false;
+    // device address of this device's fixed scratch array (allocation-free
+    // entry point), looked up at context creation; null if the lookup failed
+    void *scratch = nullptr;
+    hipError_t scratch_err = hipSuccess;
     std::string storage_dir;  // file residency: where mesh sets spill their facet data
 };
 
@@ -428,6 +432,7 @@ extern "C" pj_status pj_context_create(const pj_config *cfg, pj_context **out)
         delete ctx;
         return PJ_ERR_DEVICE;
     }
+    ctx->scratch_err = scratch_address(c.device, &ctx->scratch);
     if (c.storage_dir) ctx->storage_dir = c.storage_dir;
     ctx->cfg.storage_dir = nullptr;  // the copy above is used
     load_tune_cache(ctx);
@@ -3119,6 +3124,108 @@ extern "C" pj_status pj_pair_bounds(pj_context *ctx, const pj_meshes *R, const p
             ub[c] = bits_to_float(out[k].ub);
             hit[c] = (int8_t)out[k].hit;
         }
+    }
+    return PJ_OK;
+}
+
+// Allocation-free variant of pj_pair_bounds: the FP32 batched path with
+// its work lists in this device's fixed scratch array instead of the
+// context's grow-only buffers; host arrays move with plain (pageable)
+// copies, and the round launches directly (no graph, no pinned staging).
+extern "C" pj_status pj_pair_bounds_noalloc(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, int64_t n,
+                                            const int32_t *r, const int32_t *s, int32_t lod, double *lb, double *ub,
+                                            int8_t *hit)
+{
+    if (!ctx) return PJ_ERR_INVALID_ARG;
+    PJTRY(check_pair_args(ctx, R, S));
+    if (n < 0 || (n > 0 && (!r || !s || !lb || !ub || !hit))) return fail(ctx, PJ_ERR_INVALID_ARG, "bad argument");
+    if (n > kNoAllocMaxPairs)
+        return fail(ctx, PJ_ERR_INVALID_ARG, "more than " + std::to_string(kNoAllocMaxPairs) +
+                                                 " pairs for the allocation-free entry point");
+    if (ctx->cfg.precision != PJ_PREC_FP32_BAND || ctx->cfg.schedule != PJ_SCHED_BATCHED)
+        return fail(ctx, PJ_ERR_UNSUPPORTED, "the allocation-free entry point runs the FP32 batched path only");
+    if (R->host || S->host)
+        return fail(ctx, PJ_ERR_UNSUPPORTED, "the allocation-free entry point needs device-resident mesh sets");
+    if (n == 0) return PJ_OK;
+    if (lod < 0 || lod >= R->L) return fail(ctx, PJ_ERR_INVALID_ARG, "lod out of range");
+    for (int64_t i = 0; i < n; ++i)
+        if (r[i] < 0 || r[i] >= R->n || s[i] < 0 || s[i] >= S->n) return fail(ctx, PJ_ERR_INVALID_ARG, "object id");
+    HIPTRY(ctx, hipSetDevice(ctx->cfg.device));
+    if (!ctx->scratch) return hipfail(ctx, ctx->scratch_err, "device scratch address");
+    std::vector<Cand> cand(n);
+    std::vector<PairState> ps(n);
+    std::vector<int> act(n);
+    for (int64_t i = 0; i < n; ++i) {
+        cand[i] = Cand{r[i], s[i], 0.0f, INFINITY};
+        pair_frame(R, r[i], S, s[i], ps[i]);
+        act[i] = (int)i;
+        lb[i] = INFINITY;
+        ub[i] = INFINITY;
+        hit[i] = 0;
+    }
+    const int wpc = std::min(ctx->cfg.waves_per_cu > 0 ? ctx->cfg.waves_per_cu : ctx->cur.wpc,
+                             kNoAllocMaxGrid / std::max(ctx->num_cu, 1));
+    const int grid = ctx->num_cu * wpc;
+    if (grid < 1 || grid > kNoAllocMaxGrid) return fail(ctx, PJ_ERR_UNSUPPORTED, "persistent grid beyond the scratch slots");
+    // whole-A-side tiles; B ranges lengthened until the tiles fit (one tile
+    // per item always does)
+    // (the tile-count hint is capped too: a round of few pairs shortens its B
+    // ranges only until it has about a quarter of the hint in claimable units)
+    TilePlan pl;
+    int TS = pick_tile_s(ctx);
+    const int64_t hint = std::min<int64_t>(tile_target(ctx, wpc), kNoAllocMaxTiles / 2);
+    for (int tries = 0;; ++tries) {
+        plan_tiles(R, S, act, cand, ps, lod, lod == R->L - 1, 64 * kP, TS, true, pl, hint);
+        if ((int64_t)pl.tiles.size() <= kNoAllocMaxTiles) break;
+        if (tries >= 40) return fail(ctx, PJ_ERR_INTERNAL, "no tile plan fits the scratch array");
+        TS = TS >= (1 << 29) ? TS : TS * 2;
+    }
+    const int ni = (int)pl.items.size(), nt = (int)pl.tiles.size();
+    if (ni == 0 || nt == 0) return PJ_OK;
+    // scratch layout: items | tiles | results | counter block | slots, cursors
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    char *base = (char *)ctx->scratch;
+    const size_t o_items = 0, o_tiles = al(o_items + sizeof(Item) * kNoAllocMaxPairs),
+                 o_out = al(o_tiles + sizeof(Tile) * kNoAllocMaxTiles), o_ctr = al(o_out + sizeof(ItemOut) * kNoAllocMaxPairs),
+                 o_sched = al(o_ctr + 64), o_end = o_sched + 4 * (size_t)(kNoAllocMaxGrid + kNoAllocMaxTiles);
+    static_assert(sizeof(Item) * kNoAllocMaxPairs + sizeof(Tile) * kNoAllocMaxTiles + sizeof(ItemOut) * kNoAllocMaxPairs +
+                          64 + 4 * (size_t)(kNoAllocMaxGrid + kNoAllocMaxTiles) + 5 * 256 <=
+                      kScratchBytes,
+                  "scratch layout");
+    if (o_end > kScratchBytes) return fail(ctx, PJ_ERR_INTERNAL, "scratch layout");
+    hipStream_t st = ctx->stream;
+    int32_t hc[16] = {0};  // [1] tiles, [2..5] counters, [6] items, [10] next tile to take
+    hc[1] = nt;
+    hc[6] = ni;
+    int32_t *dctr = (int32_t *)(base + o_ctr);
+    HIPTRY(ctx, hipMemcpyAsync(base + o_items, pl.items.data(), ni * sizeof(Item), hipMemcpyHostToDevice, st));
+    HIPTRY(ctx, hipMemcpyAsync(base + o_tiles, pl.tiles.data(), nt * sizeof(Tile), hipMemcpyHostToDevice, st));
+    HIPTRY(ctx, hipMemcpyAsync(dctr, hc, sizeof(hc), hipMemcpyHostToDevice, st));
+    RefineArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.R = R->dev();
+    a.S = S->dev();
+    a.items = (const Item *)(base + o_items);
+    a.tiles = (const Tile *)(base + o_tiles);
+    a.ntiles = dctr + 1;
+    a.tile_next = dctr + 10;
+    a.wave_slot = (int32_t *)(base + o_sched);
+    a.tile_cur = a.wave_slot + grid;
+    a.out = (ItemOut *)(base + o_out);
+    a.pairs_done = reinterpret_cast<unsigned long long *>(dctr + 2);
+    a.chunks_culled = reinterpret_cast<unsigned long long *>(dctr + 4);
+    a.tau = -1.0f;
+    a.early = 0;
+    a.cull = ctx->cfg.tile_cull ? 1 : 0;
+    PJTRY(launch_round(ctx, a, dctr, ni, nt, wpc, false, st));
+    std::vector<ItemOut> out(ni);
+    HIPTRY(ctx, hipMemcpyAsync(out.data(), a.out, ni * sizeof(ItemOut), hipMemcpyDeviceToHost, st));
+    HIPTRY(ctx, hipStreamSynchronize(st));
+    for (int k = 0; k < ni; ++k) {
+        const int c = pl.items[k].cand;
+        lb[c] = bits_to_float(out[k].lb);
+        ub[c] = bits_to_float(out[k].ub);
+        hit[c] = (int8_t)out[k].hit;
     }
     return PJ_OK;
 }

@@ -153,6 +153,17 @@ hipError_t launch_mlp_adam(float *params, float *m, float *v, const float *grads
 hipError_t launch_mlp_infer(const float *params, const float *x, int n, const float *cost, int n_lods, float *probs,
                             int32_t *start, hipStream_t st);
 
+// Allocation-free entry point: the device scratch array (one per device,
+// 4 MiB) and its layout limits.
+constexpr size_t kScratchBytes = size_t(4) << 20;
+constexpr int kMaxDevices = 64;
+constexpr int kNoAllocMaxPairs = 4096;    // items
+constexpr int kNoAllocMaxTiles = 65536;   // tiles
+constexpr int kNoAllocMaxGrid = 256 * 64; // persistent workgroups (one slot each)
+// Device address of the scratch array on `device` (looked up once per device
+// with hipGetSymbolAddress, that device current; cached for the process).
+hipError_t scratch_address(int device, void **out);
+
 constexpr int MLP_IN = 16, MLP_H = 64, MLP_OUT = 4;
 constexpr int MLP_NPARAM = MLP_IN * MLP_H + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H * MLP_OUT + MLP_OUT;
 

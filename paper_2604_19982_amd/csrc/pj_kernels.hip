@@ -1,6 +1,8 @@
 // pj_kernels.hip -- HIP kernels for gfx950: ingest (boxes, anchors, hd/ph),
 // MBB filter, FP32 persistent tile refinement, FP64 refinement (tiled and
 // one-workgroup-per-pair), and a facet-pair entry used by tests.
+#include <mutex>
+
 #include "pj_geom.h"
 #include "pj_internal.h"
 
@@ -1725,6 +1727,37 @@ hipError_t launch_facet_pairs(const float *t1, const float *t2, int64_t n, int p
     hipLaunchKernelGGL(k_facet_pairs, dim3((unsigned)std::min<int64_t>((n + 255) / 256, kStrideBlocks)), dim3(256), 0, st,
                        t1, t2, n, prec, d, d_hi, hit);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fixed device scratch of the allocation-free entry point: one array per
+// device, held until the process ends.  Host code never passes the array's
+// name to a kernel (on the host it is a stand-in, not a device address); it
+// uses the address hipGetSymbolAddress returns on each device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(int device, void **out)
+{
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[device] = p;
+    }
+    *out = addr[device];
+    return hipSuccess;
 }
 
 }  // namespace pj
