@@ -69,7 +69,7 @@ def run_step(ctx, gR, gS, taus, verbose=False, k=None):
     import numpy as np
     h = hashlib.sha1()
     tot = dict(pairs=0, pairs64=0, pairsc=0, kms=0.0, launches=0, results=0, band=0, ms=0.0, kms64=0.0,
-               planned=0, items=0, staged=0, chunks=0)
+               planned=0, items=0, staged=0, chunks=0, prep_ms=0.0, refine_ms=0.0, peak=0)
     for tau in (taus if k is None else [None]):
         if k is None:
             res = ctx.join_within(gR, gS, tau)
@@ -101,19 +101,24 @@ def run_step(ctx, gR, gS, taus, verbose=False, k=None):
         tot["items"] += sum(st["lod_items"])
         tot["staged"] += st["staged_bytes"]
         tot["chunks"] += st["chunks"]
+        tot["prep_ms"] += st["t_prep_ms"]
+        tot["refine_ms"] += st["t_refine_ms"]
+        tot["peak"] = max(tot["peak"], st["peak_device_bytes"])
     tot["digest"] = h.hexdigest()
     return tot
 
 
-def train_model(pj, mg, stream, workdir):
+def train_model(pj, mg, stream, workdir, **cfg):
     """LoD model for the learned skip, trained on resolution logs of a
-    held-out workload of the same shape (seed 101, 2k x 400 in 300^3)."""
+    held-out workload of the multi-LoD shape (seed 101, 10k x 2k in 500^3,
+    tau in {0, 2, 5, 10, 20}), written by joins with the given context
+    options (the timed joins')."""
     log = os.path.join(workdir, "resolution.log")
     model = os.path.join(workdir, "lod.model")
     if os.path.exists(log):
         os.remove(log)
-    R, S = mg.config_multilod(seed=101, n_r=2000, n_s=400, box=300.0)
-    c = pj.Context(log_path=log, stream=stream.cuda_stream)
+    R, S = mg.config_multilod(seed=101, n_r=10000, n_s=2000, box=500.0)
+    c = pj.Context(log_path=log, stream=stream.cuda_stream, **cfg)
     gR, gS = c.meshes(R), c.meshes(S)
     for tau in (0.0, 2.0, 5.0, 10.0, 20.0):
         c.join_within(gR, gS, tau)
@@ -121,11 +126,14 @@ def train_model(pj, mg, stream, workdir):
     return model, loss, os.path.getsize(log) // 72
 
 
-def one_step(pj, stream, gR, gS, taus, k=None, **cfg):
-    """One step on another context over the already ingested mesh sets (a
-    mesh set may be shared by contexts on its device)."""
+def one_step(pj, stream, gR, gS, taus, k=None, warmup=1, **cfg):
+    """One timed step on another context over the already ingested mesh sets
+    (a mesh set may be shared by contexts on its device), after `warmup`
+    untimed ones (first-use costs: buffer growth, graph capture, tuning)."""
     import torch
     c = pj.Context(stream=stream.cuda_stream, **cfg)
+    for _ in range(warmup):
+        run_step(c, gR, gS, taus, k=k)
     torch.cuda.synchronize()
     ts = time.time()
     tot = run_step(c, gR, gS, taus, k=k)
@@ -136,8 +144,10 @@ def one_step(pj, stream, gR, gS, taus, k=None, **cfg):
 
 def sample_candidates(oracle, O_R, O_S, gap, max_r=20000, seed=0, block=8192):
     """MBB candidate pairs (box gap <= gap) of up to max_r random R objects
-    (all of R when max_r >= |R|), found by an x-sorted sweep over S with the
-    oracle's FP64 boxes, in (r, s) order."""
+    (all of R when max_r >= |R|), in (r, s) order, with the oracle's FP64
+    boxes: S is binned by box centre in a uniform grid, each r visits the
+    cells its box (widened by gap and S's widest half extent) reaches, and
+    the exact box gap decides."""
     import numpy as np
     bR, _ = oracle.mbbs(O_R)
     bS, _ = oracle.mbbs(O_S)
@@ -145,29 +155,58 @@ def sample_candidates(oracle, O_R, O_S, gap, max_r=20000, seed=0, block=8192):
         rs = np.arange(len(bR))
     else:
         rs = np.sort(np.random.default_rng(seed).permutation(len(bR))[:max_r])
-    order = np.argsort(bS[:, 0], kind="stable")
-    xs = bS[order, 0]
-    wmax = float(np.max(bS[:, 3] - bS[:, 0])) if len(bS) else 0.0
-    cr, cs = [], []
+    if len(bS) == 0 or len(rs) == 0:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64)
+    cen = 0.5 * (bS[:, :3] + bS[:, 3:])
+    half = (0.5 * (bS[:, 3:] - bS[:, :3])).max(0)
+    lo = cen.min(0)
+    ext = np.maximum(cen.max(0) - lo, 1e-9)
+    # cells of about 2 (gap + widest half extent), at most 2^21 of them
+    csz = max(float(2.0 * (gap + half.max())), float(ext.max()) / 128.0, 1e-6)
+    while np.prod(np.floor(ext / csz) + 1) > (1 << 21):
+        csz *= 1.25
+    g = (np.floor(ext / csz) + 1).astype(np.int64)
+    cs = np.minimum(np.floor((cen - lo) / csz).astype(np.int64), g - 1)
+    cid = (cs[:, 2] * g[1] + cs[:, 1]) * g[0] + cs[:, 0]
+    order = np.argsort(cid, kind="stable")
+    beg = np.searchsorted(cid[order], np.arange(np.prod(g) + 1))
+    cr, cso = [], []
     for b0 in range(0, len(rs), block):
         blk = rs[b0:b0 + block]
-        lo = np.searchsorted(xs, bR[blk, 0] - gap - wmax, "left")
-        hi = np.searchsorted(xs, bR[blk, 3] + gap, "right")
-        cnt = np.maximum(hi - lo, 0)
-        if cnt.sum() == 0:
+        a = np.floor((bR[blk, :3] - gap - half - lo) / csz).astype(np.int64) - 1
+        z = np.floor((bR[blk, 3:] + gap + half - lo) / csz).astype(np.int64) + 1
+        a = np.clip(a, 0, g - 1)
+        z = np.clip(z, 0, g - 1)
+        span = z - a + 1
+        rr, ss = [], []
+        for dz in range(int(span[:, 2].max())):
+            for dy in range(int(span[:, 1].max())):
+                m = (dz < span[:, 2]) & (dy < span[:, 1])
+                if not m.any():
+                    continue
+                row = ((a[m, 2] + dz) * g[1] + (a[m, 1] + dy)) * g[0]
+                c0 = beg[row + a[m, 0]]
+                c1 = beg[row + z[m, 0] + 1]
+                cnt = c1 - c0
+                if cnt.sum() == 0:
+                    continue
+                r_rep = np.repeat(blk[m], cnt)
+                first = np.repeat(c0 - np.concatenate([[0], np.cumsum(cnt)[:-1]]), cnt)
+                rr.append(r_rep)
+                ss.append(order[first + np.arange(cnt.sum())])
+        if not rr:
             continue
-        r_rep = np.repeat(blk, cnt)
-        first = np.repeat(lo - np.concatenate([[0], np.cumsum(cnt)[:-1]]), cnt)
-        js = order[first + np.arange(cnt.sum())]
-        g = np.maximum(0.0, np.maximum(bS[js, :3] - bR[r_rep, 3:], bR[r_rep, :3] - bS[js, 3:]))
-        keep = np.sqrt(np.sum(g * g, -1)) <= gap
+        r_rep = np.concatenate(rr)
+        js = np.concatenate(ss)
+        gp = np.maximum(0.0, np.maximum(bS[js, :3] - bR[r_rep, 3:], bR[r_rep, :3] - bS[js, 3:]))
+        keep = np.sqrt(np.sum(gp * gp, -1)) <= gap
         r_k, s_k = r_rep[keep], js[keep]
         o = np.lexsort((s_k, r_k))
         cr.append(r_k[o])
-        cs.append(s_k[o])
+        cso.append(s_k[o])
     if not cr:
         return np.zeros(0, np.int64), np.zeros(0, np.int64)
-    return np.concatenate(cr).astype(np.int64), np.concatenate(cs).astype(np.int64)
+    return np.concatenate(cr).astype(np.int64), np.concatenate(cso).astype(np.int64)
 
 
 def _facets(M, obj, lod):
@@ -309,19 +348,26 @@ def kernel_roofline(steps, workload):
             "single_issue_fma_peak": SINGLE_ISSUE_FP32_TFLOPS}
 
 
-def variants(pj, stream, gR, gS, taus, kk, base_ms, base_digest, tune, wctx, ablations=True, plain=True):
-    """The ablations (no learned skip; no learned skip and no culling) and the
-    plain GPU schedule (FP64, one workgroup per pair and LoD, from LoD 0), one
-    step each on the same ingested sets; each reports whether its results
-    equal the timed run's."""
+def variants(pj, stream, gR, gS, taus, kk, base_ms, base_digest, tune, wctx, timed, ablations=True, plain=True):
+    """The ablations, one change of the timed configuration `timed` at a
+    time (no learned skip; no voxel filter; neither, nor block and facet
+    culling), and the plain GPU schedule (FP64, one workgroup per pair and
+    LoD, from LoD 0, no voxels), one step each on the same ingested sets;
+    each reports whether its results equal the timed run's."""
     abl = {}
     todo = []
     if ablations:
-        todo += [("no_learned_skip", dict(**tune, **wctx)), ("no_learned_no_cull", dict(tile_cull=False, **tune, **wctx))]
+        todo += [("no_learned_skip", dict({k: v for k, v in timed.items() if k not in ("learned_skip", "model_path")},
+                                          **tune, **wctx))]
+        if timed.get("voxels"):
+            todo += [("no_voxels", dict(dict(timed, voxels=False), **tune, **wctx))]
+        todo += [("no_learned_no_voxels_no_cull", dict(tile_cull=False, **tune, **wctx))]
     if plain:
         todo += [("plain_gpu_schedule", dict(schedule="plain", precision="fp64", **wctx))]
     for name, cfg in todo:
-        t = one_step(pj, stream, gR, gS, taus, k=kk, **cfg)
+        # the plain FP64 schedule takes seconds per step and has no first-use
+        # costs to speak of; the others get one warmup step
+        t = one_step(pj, stream, gR, gS, taus, k=kk, warmup=0 if name == "plain_gpu_schedule" else 1, **cfg)
         a = {"ms": t["ms"], "facet_pairs": t["pairs"] + t["pairsc"] + t["pairs64"],
              "planned_facet_pairs": t["planned"], "items": t["items"], "results": t["results"],
              "results_match": t["digest"] == base_digest, "speedup_of_timed_run": t["ms"] / base_ms}
@@ -337,13 +383,13 @@ def variants(pj, stream, gR, gS, taus, kk, base_ms, base_digest, tune, wctx, abl
     return abl
 
 
-def measure_side(pj, stream, name, R, S, gen_s, model, workdir, steps):
+def measure_side(pj, stream, name, R, S, gen_s, timed, workdir, steps):
     """A workload other than the headline: HBM-resident sets, a few timed
     steps, the ablations and the plain schedule."""
     import torch
     wl = WORKLOADS[name]
     tune = dict(autotune=True, autotune_path=os.path.join(workdir, f"shapes_{name}.txt"))
-    ctx = pj.Context(stream=stream.cuda_stream, learned_skip=True, model_path=model, **tune)
+    ctx = pj.Context(stream=stream.cuda_stream, **timed, **tune)
     t0 = time.time()
     gR, gS = ctx.meshes(R), ctx.meshes(S)
     torch.cuda.synchronize()
@@ -351,7 +397,8 @@ def measure_side(pj, stream, name, R, S, gen_s, model, workdir, steps):
     st, wall = timed_steps(ctx, gR, gS, wl["taus"], wl.get("k"), steps, 1, verbose=False)
     ms = wall * 1e3 / steps
     pairs = sum(s["pairs"] + s["pairsc"] + s["pairs64"] for s in st)
-    abl = variants(pj, stream, gR, gS, wl["taus"], wl.get("k"), ms, st[-1]["digest"], tune, {}, ablations=True)
+    abl = variants(pj, stream, gR, gS, wl["taus"], wl.get("k"), ms, st[-1]["digest"], tune, {}, timed,
+                   ablations=True)
     out = {"workload": wl["desc"].format(nr=R.n_objects, ns=S.n_objects), "steps": steps, "ms_per_step": ms,
            "facet_pair_evals_per_s": pairs / wall, "ingest_s": ing, "generate_s": gen_s,
            "results_per_step": st[-1]["results"], "roofline": kernel_roofline(st, name),
@@ -374,6 +421,7 @@ def main():
     ap.add_argument("--side", default="multilod,learned",
                     help="large: other workloads measured in the same run (comma list, or 'none')")
     ap.add_argument("--side-steps", type=int, default=5)
+    ap.add_argument("--voxels", type=int, default=1, help="voxel-pair filtering in the timed configuration")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--n-r", type=int, default=None)
     ap.add_argument("--n-s", type=int, default=None)
@@ -409,12 +457,14 @@ def main():
     import tempfile
     workdir = tempfile.mkdtemp(prefix="pj_bench_")
     t0 = time.time()
-    model, train_loss, n_rec = train_model(pj, mg, stream, workdir)
+    vox = dict(voxels=True) if args.voxels else {}
+    model, train_loss, n_rec = train_model(pj, mg, stream, workdir, **vox)
     log(f"LoD model trained on {n_rec} logged pairs in {time.time() - t0:.1f} s, final loss {train_loss:.3f}")
+    timed = dict(learned_skip=True, model_path=model, **vox)
     # launch shapes come from the autotuner (it times candidates during the
     # warmup step and caches them for the ablation contexts)
     tune = dict(autotune=True, autotune_path=os.path.join(workdir, "shapes.txt"))
-    ctx = pj.Context(stream=stream.cuda_stream, learned_skip=True, model_path=model, **tune, **wl["ctx"])
+    ctx = pj.Context(stream=stream.cuda_stream, **timed, **tune, **wl["ctx"])
     t0 = time.time()
     gR = ctx.meshes(R)
     log(f"ingested R in {time.time() - t0:.1f} s")
@@ -458,7 +508,8 @@ def main():
                    "candidates_last_join": st["candidates"],
                    "generate_s": gen_s,
                    "ingest_s": ingest_s,
-                   "mode": "learned LoD skip + batched persistent tiles + FP32 with FP64 guard band + chunk and "
+                   "mode": ("voxel-pair filtering + " if args.voxels else "") +
+                           "learned LoD skip + batched persistent tiles + FP32 with FP64 guard band + chunk and "
                            "facet culling + hipGraph rounds",
                    "lod_model": {"train_pairs": n_rec, "final_loss": train_loss},
                    "fp32_kernel_facet_pair_evals_per_s": (sum(s["pairs"] for s in steps) /
@@ -467,7 +518,8 @@ def main():
                    "tuned_shapes": [ln for ln in shapes if ln.strip()]},
         "roofline": roof,
     }
-    abl = variants(pj, stream, gR, gS, taus, kk, ms_per_step, digest, tune, wl["ctx"], args.ablations, args.plain)
+    abl = variants(pj, stream, gR, gS, taus, kk, ms_per_step, digest, tune, wl["ctx"], timed, args.ablations,
+                   args.plain)
     if "plain_gpu_schedule" in abl:
         out["config"]["plain_ms_per_step"] = abl["plain_gpu_schedule"]["ms"]
         out["config"]["speedup_vs_plain"] = abl["plain_gpu_schedule"]["ms"] / ms_per_step
@@ -479,7 +531,7 @@ def main():
         del gR, gS
         ctx.close()
         torch.cuda.synchronize()
-        cctx = pj.Context(stream=stream.cuda_stream, learned_skip=True, model_path=model, **tune, **wl["capped"])
+        cctx = pj.Context(stream=stream.cuda_stream, **timed, **tune, **wl["capped"])
         t0 = time.time()
         hR, hS = cctx.meshes(R), cctx.meshes(S)
         torch.cuda.synchronize()
@@ -487,23 +539,36 @@ def main():
         log(f"ingested host-resident in {ing_h:.1f} s")
         cst, cwall = timed_steps(cctx, hR, hS, taus, kk, args.capped_steps, 1)
         cms = cwall * 1e3 / args.capped_steps
-        cab = variants(pj, stream, hR, hS, taus, kk, cms, digest, tune, wl["capped"], ablations=False,
+        cab = variants(pj, stream, hR, hS, taus, kk, cms, digest, tune, wl["capped"], timed, ablations=False,
                        plain=args.plain)
         cst_last = cctx.stats()
+        # streaming overlap: the same capped join with one staging set (gather,
+        # upload, compute and download of each chunk one after another), two
+        # and three sets (the next chunks gathered and uploaded while one
+        # computes)
+        overlap = {}
+        for sets in (1, 2, 3):
+            t = one_step(pj, stream, hR, hS, taus, k=kk, **dict(wl["capped"], stage_sets=sets), **timed, **tune)
+            overlap[f"stage_sets_{sets}"] = {"ms": t["ms"], "refine_ms": t["refine_ms"], "kernel_ms": t["kms"],
+                                             "prep_ms": t["prep_ms"], "chunks": t["chunks"],
+                                             "staged_bytes": t["staged"], "peak_device_bytes": t["peak"],
+                                             "results_match": t["digest"] == digest}
+            log(f"capped, {sets} staging set(s): {t['ms']:.2f} ms, refine {t['refine_ms']:.2f} ms, "
+                f"kernel {t['kms']:.2f} ms, prep {t['prep_ms']:.2f} ms, {t['chunks']} chunks")
         out["config"]["capped_host_resident"] = {
             "mem_cap_bytes": wl["capped"]["mem_cap_bytes"], "steps": args.capped_steps, "ms_per_step": cms,
             "results_match": cst[-1]["digest"] == digest, "ingest_s": ing_h,
             "staged_bytes_per_step": cst[-1]["staged"], "chunks_per_step": cst[-1]["chunks"],
             "peak_device_bytes": cst_last["peak_device_bytes"],
             "speedup_vs_plain": (cab["plain_gpu_schedule"]["ms"] / cms) if "plain_gpu_schedule" in cab else None,
-            "plain_gpu_schedule": cab.get("plain_gpu_schedule")}
+            "plain_gpu_schedule": cab.get("plain_gpu_schedule"), "overlap": overlap}
         log(f"capped host-resident: {cms:.2f} ms per step")
         del hR, hS
         cctx.close()
     if side_sets:
         side = {}
         for name, (sR, sS, sg) in list(side_sets.items()):
-            side[name] = measure_side(pj, stream, name, sR, sS, sg, model, workdir, args.side_steps)
+            side[name] = measure_side(pj, stream, name, sR, sS, sg, timed, workdir, args.side_steps)
             del side_sets[name]
         out["config"]["other_workloads"] = side
     if args.cpu_seconds > 0:

@@ -79,7 +79,8 @@ typedef struct {
                                 round of each work class and keep the fastest (cached in autotune_path);
                                 an explicit tile_s / waves_per_cu always wins */
     int32_t mesh_residency;  /* pj_residency of mesh sets created on this context */
-    int32_t stage_sets;      /* staging buffer sets for streamed chunks, 2 or 3 (0: 2) */
+    int32_t stage_sets;      /* staging buffer sets for streamed chunks, 2 or 3 (0: 2); 1 runs the chunks one
+                                after another with no overlap of gather, copies and compute */
     int32_t filter_mode;     /* MBB filter: 0 auto (x sweep when |R|*|S| > 2^26), 1 all pairs, 2 x sweep.
                                 k-NN candidates: 1 all pairs; otherwise a grid over S's anchors when
                                 k <= 16 (all pairs for larger k) */
@@ -96,6 +97,11 @@ typedef struct {
     void *alloc_user;        /* passed to dev_alloc / dev_free */
     const char *storage_dir; /* PJ_RESIDENT_FILE: directory (on an SSD) for the mesh sets' facet files;
                                 copied at context creation */
+    int32_t voxels;          /* 1: mesh sets created on this context are voxelized (Section 2.1, k-means
+                                over the coarsest facets, at most 64 voxels per object) and the batched
+                                joins run voxel-pair filtering (Section 3.2, Algorithms 1-3) before the LoD
+                                rounds, which then evaluate only facets of surviving voxel pairs */
+    int32_t reserved1;       /* must be 0 */
 } pj_config;
 
 /* Where a mesh set's facet data live.  DEVICE: uploaded once at ingest.
@@ -229,6 +235,15 @@ typedef struct {
     double t_prep_ms;           /* host time gathering streamed chunks' facet data (host/file residency), summed
                                    over chunks; it runs on a prep thread beside the upload and compute of the
                                    chunk before */
+    int64_t vp_pairs;           /* voxel pairs bounded by the voxel filter */
+    int64_t vp_kept;            /* voxel pairs that survived it */
+    int64_t vp_chunks;          /* its chunks */
+    int64_t voxel_decided;      /* object pairs its bounds decided (within: confirmed or pruned; k-NN: by the
+                                   pruning rule on the tightened intervals) */
+    double t_voxel_ms;          /* host wall time of the voxel filter */
+    double planned_sqrt;        /* sum over the (pair, LoD) items visited of sqrt(n_r * n_s): the work measure
+                                   the learned first LoD minimises (with box culling, the facet pairs evaluated
+                                   grow like it); fixed by the schedule's decisions */
 } pj_stats;
 
 pj_status pj_get_stats(const pj_context *ctx, pj_stats *out);

@@ -40,7 +40,8 @@ class Config(ctypes.Structure):
                 ("mem_cap_bytes", ctypes.c_int64),
                 ("model_path", ctypes.c_char_p), ("log_path", ctypes.c_char_p), ("autotune_path", ctypes.c_char_p),
                 ("stream", ctypes.c_void_p), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
-                ("alloc_user", ctypes.c_void_p), ("storage_dir", ctypes.c_char_p)]
+                ("alloc_user", ctypes.c_void_p), ("storage_dir", ctypes.c_char_p),
+                ("voxels", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
 
 
 class MeshDesc(ctypes.Structure):
@@ -77,7 +78,10 @@ class Stats(ctypes.Structure):
                 ("collect_launches", ctypes.c_int64), ("collect_pairs", ctypes.c_int64),
                 ("collect_kernel_ms", ctypes.c_double), ("collected_pairs", ctypes.c_int64),
                 ("collect_overflow", ctypes.c_int64), ("lod_planned_pairs", ctypes.c_int64 * 8),
-                ("knn_grid_cells", ctypes.c_int64), ("t_prune_ms", ctypes.c_double), ("t_prep_ms", ctypes.c_double)]
+                ("knn_grid_cells", ctypes.c_int64), ("t_prune_ms", ctypes.c_double), ("t_prep_ms", ctypes.c_double),
+                ("vp_pairs", ctypes.c_int64), ("vp_kept", ctypes.c_int64), ("vp_chunks", ctypes.c_int64),
+                ("voxel_decided", ctypes.c_int64), ("t_voxel_ms", ctypes.c_double),
+                ("planned_sqrt", ctypes.c_double)]
 
     def to_dict(self):
         d = {}
@@ -201,7 +205,7 @@ class Context:
                  use_graph=True, tile_cull=True, tile_s=0, waves_per_cu=0, mem_cap_bytes=0, model_path=None,
                  log_path=None, stream=None, chunk_tiles=0, autotune=False, autotune_path=None,
                  host_resident=False, stage_sets=0, filter_mode="auto", allocator=None, storage_dir=None,
-                 knn_prune_host=False):
+                 knn_prune_host=False, voxels=False):
         """``allocator``: optional (alloc, free) Python callables for the
         library's device memory: alloc(nbytes) -> device address (int) or
         None, free(address).  They back pj_config.dev_alloc / dev_free.
@@ -226,6 +230,7 @@ class Context:
         c.stage_sets = int(stage_sets)
         c.filter_mode = {"auto": 0, "pairs": 1, "sweep": 2, "grid": 2}[filter_mode]
         c.knn_prune_host = int(bool(knn_prune_host))
+        c.voxels = int(bool(voxels))
         self._paths = [None if p is None else os.fsencode(p) for p in (model_path, log_path, autotune_path)]
         c.model_path, c.log_path, c.autotune_path = self._paths
         self._storage = None if storage_dir is None else os.fsencode(storage_dir)

@@ -156,10 +156,27 @@ struct pj_meshes {
     size_t map_len = 0;
     int fd = -1;
     bool file = false;
+    // voxels (Section 2.1 "Object Voxelization"): up to 64 per object, slot
+    // 64*o + v; labels of every facet of every (object, LoD); per block
+    // record the voxels of its facets.  Boxes, anchors and counts are device
+    // resident for every residency; labels and block masks follow the facets.
+    bool has_vox = false;
+    std::vector<int32_t> h_vcount;
+    std::vector<float> h_vbox, h_vanc;
+    std::vector<uint8_t> h_vlab;
+    std::vector<int64_t> h_lbeg;
+    std::vector<unsigned long long> h_bmask;
+    int32_t *d_vcount = nullptr;
+    float *d_vbox = nullptr, *d_vanc = nullptr;
+    uint8_t *d_vlab = nullptr;
+    int64_t *d_lbeg = nullptr;
+    unsigned long long *d_bmask = nullptr;
     MeshDev dev() const
     {
-        return MeshDev{d_verts, d_tris, d_vbeg, d_tbeg, d_tcnt, d_hpbeg, d_hdph, d_bkbeg, d_blk, n, L};
+        return MeshDev{d_verts, d_tris, d_vbeg, d_tbeg, d_tcnt, d_hpbeg, d_hdph, d_bkbeg, d_blk, n, L,
+                       has_vox ? d_vlab : nullptr, has_vox ? d_lbeg : nullptr, has_vox ? d_bmask : nullptr};
     }
+    VoxSide vox() const { return VoxSide{d_vbox, d_vanc, d_vcount}; }
     int32_t count(int obj, int lod) const { return h_tcnt[(int64_t)obj * L + lod]; }
 };
 
@@ -251,8 +268,13 @@ struct pj_context {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     DevBuf b_items, b_tiles, b_out, b_out64, b_ctr, b_cand_r, b_cand_s, b_cand_lb, b_cand_ub, b_blk, b_blkoff,
         b_total, b_tmp0, b_tmp1, b_tmp2, b_tmp3, b_coll, b_ovf, b_theta, b_koff, b_klb, b_kub, b_kst0, b_kst1,
-        b_kleft, b_gcell, b_gitems, b_gcnt, b_gfill, b_gbeg,
-        b_sched;  // scheduling state of the FP32 rounds: workgroup slots, then A-block cursors
+        b_kleft, b_gcell, b_gitems, b_gcnt, b_gfill, b_gbeg, b_vplb, b_vpub, b_vmask, b_vrow,
+        b_sched;
+    // voxel filter: per set of the double-buffered chunk pipeline, inputs
+    // (pairs, voxel-pair offsets) and outputs (pair bounds, counts, offsets,
+    // survivors), on the device and pinned
+    DevBuf vx_in[2], vx_out[2];
+  // scheduling state of the FP32 rounds: workgroup slots, then A-block cursors
     // chunked streaming: two buffer sets, upload/download streams, pinned staging
     struct PinBuf {
         void *p = nullptr;
@@ -261,6 +283,10 @@ struct pj_context {
     DevBuf sb_items[kMaxSets], sb_tiles[kMaxSets], sb_out[kMaxSets], sb_ctr[kMaxSets], sb_stage[kMaxSets];
     PinBuf pin_items[kMaxSets], pin_tiles[kMaxSets], pin_out[kMaxSets], pin_ctr[kMaxSets], pin_stage[kMaxSets];
     PinBuf pin_cand;  // the filter's candidate count and arrays on their way to the host
+    PinBuf pin_vin[2];
+    hipEvent_t ev_vcomp[2] = {};
+    const unsigned long long *vmask = nullptr;  // surviving voxel pairs of the join's candidates (device)
+    const int32_t *vrow = nullptr;              // per candidate: its block of rows in vmask, -1 for none
     hipStream_t up_stream = nullptr, down_stream = nullptr;
     hipEvent_t ev_h2d[kMaxSets] = {}, ev_comp[kMaxSets] = {}, ev_d2h[kMaxSets] = {}, ev_k0[kMaxSets] = {},
                ev_k1[kMaxSets] = {};
@@ -412,10 +438,11 @@ extern "C" pj_status pj_context_create(const pj_config *cfg, pj_context **out)
     }
     if (ctx->arch.empty()) ctx->arch = "gpu";
     if (c.chunk_tiles < 0 || c.filter_mode < 0 || c.filter_mode > 2 || c.knn_prune_host < 0 || c.knn_prune_host > 1 ||
+        c.voxels < 0 || c.voxels > 1 || c.reserved1 != 0 ||
         (c.mesh_residency != PJ_RESIDENT_DEVICE && c.mesh_residency != PJ_RESIDENT_HOST &&
          c.mesh_residency != PJ_RESIDENT_FILE) ||
         (c.mesh_residency == PJ_RESIDENT_FILE && (!c.storage_dir || !c.storage_dir[0])) ||
-        (c.stage_sets != 0 && c.stage_sets != 2 && c.stage_sets != 3)) {
+        (c.stage_sets < 0 || c.stage_sets > 3)) {
         delete ctx;
         return PJ_ERR_INVALID_ARG;
     }
@@ -456,6 +483,10 @@ extern "C" pj_status pj_context_destroy(pj_context *ctx)
             if (e) (void)hipEventDestroy(e);
     }
     if (ctx->pin_cand.p) (void)hipHostFree(ctx->pin_cand.p);
+    for (int b = 0; b < 2; ++b) {
+        if (ctx->pin_vin[b].p) (void)hipHostFree(ctx->pin_vin[b].p);
+        if (ctx->ev_vcomp[b]) (void)hipEventDestroy(ctx->ev_vcomp[b]);
+    }
     if (ctx->up_stream) (void)hipStreamDestroy(ctx->up_stream);
     if (ctx->down_stream) (void)hipStreamDestroy(ctx->down_stream);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
@@ -486,7 +517,8 @@ void free_meshes(pj_meshes *m)
     for (void *p : {(void *)m->d_verts, (void *)m->d_tris, (void *)m->d_vbeg, (void *)m->d_tbeg, (void *)m->d_hpbeg,
                     (void *)m->d_tcnt, (void *)m->d_hdph, (void *)m->d_box, (void *)m->d_anchor,
                     (void *)m->d_lodmax, (void *)m->d_bkbeg, (void *)m->d_blk, (void *)m->d_xord, (void *)m->d_xbox,
-                    (void *)m->d_xanc, (void *)m->d_xmin})
+                    (void *)m->d_xanc, (void *)m->d_xmin, (void *)m->d_vcount, (void *)m->d_vbox, (void *)m->d_vanc,
+                    (void *)m->d_vlab, (void *)m->d_lbeg, (void *)m->d_bmask})
         if (p) m->al.free(p);
     if (m->map) munmap(m->map, m->map_len);
     if (m->fd >= 0) close(m->fd);
@@ -566,10 +598,181 @@ pj_status validate_desc(pj_context *ctx, const pj_mesh_desc *d)
 
 }  // namespace
 
+namespace {
+void host_for(pj_context *ctx, int64_t n, const std::function<void(int64_t)> &f);
+}  // namespace
+
+// Voxelization (Section 2.1, "Object Voxelization", "Object and Voxel
+// Centers", "Consistent Voxelization across LoDs"), on the host threads at
+// ingest.  Per object: k = 2% of its finest facets, at least 1, at most 64
+// and at most its coarsest facet count; k-means over the centroids of the
+// coarsest facets, the k initial centres being vertices at evenly spaced
+// indices, two update steps, then a final assignment (nearest centre, ties
+// to the lower index; unused centres dropped).  Every facet of a finer LoD
+// takes the voxel of its parent, so the partition is the same at every LoD.
+// A voxel's box and anchor come from its finest facets: the box of their
+// corners, and the corner nearest the box centre (ties: lowest vertex).
+void voxelize(pj_context *ctx, const pj_mesh_desc *d, pj_meshes *m)
+{
+    const int64_t n = m->n, L = m->L;
+    m->has_vox = true;
+    m->h_vcount.assign(n, 1);
+    m->h_vbox.assign((size_t)n * kMaxVox * 6, 0.0f);
+    m->h_vanc.assign((size_t)n * kMaxVox * 3, 0.0f);
+    m->h_lbeg.assign(n * L, 0);
+    int64_t nl = 0;
+    for (int64_t k = 0; k < n * L; ++k) {
+        m->h_lbeg[k] = nl;
+        nl += m->h_tcnt[k];
+    }
+    m->h_vlab.assign(nl, 0);
+    m->h_bmask.assign(m->nblk, 0ull);
+    host_for(ctx, n, [&](int64_t o) {
+        const float *V = d->verts + 3 * m->h_vbeg[o];
+        const int32_t nv = m->h_vcnt[o];
+        auto tri = [&](int64_t l, int32_t f) { return d->tris + 3 * (m->h_tbeg[o * L + l] + f); };
+        const int32_t F0 = m->h_tcnt[o * L], Ff = m->h_tcnt[o * L + L - 1];
+        int k = (int)std::lround(0.02 * (double)Ff);
+        k = std::max(1, std::min(k, std::min(kMaxVox, std::max(F0, 1))));
+        if (L > 1 && !d->parent) k = 1;  // no parent maps: one voxel
+        uint8_t *lab0 = m->h_vlab.data() + m->h_lbeg[o * L];
+        if (k > 1 && nv > 0) {
+            std::vector<double> cen(3 * F0), ctr(3 * k);
+            for (int32_t f = 0; f < F0; ++f) {
+                const int32_t *t = tri(0, f);
+                for (int c = 0; c < 3; ++c)
+                    cen[3 * f + c] = ((double)V[3 * t[0] + c] + V[3 * t[1] + c] + V[3 * t[2] + c]) / 3.0;
+            }
+            for (int i = 0; i < k; ++i) {
+                const int64_t vi = (int64_t)i * nv / k;
+                for (int c = 0; c < 3; ++c) ctr[3 * i + c] = V[3 * vi + c];
+            }
+            std::vector<int> as(F0);
+            auto assign = [&] {
+                for (int32_t f = 0; f < F0; ++f) {
+                    double best = INFINITY;
+                    int bi = 0;
+                    for (int i = 0; i < k; ++i) {
+                        const double dx = cen[3 * f] - ctr[3 * i], dy = cen[3 * f + 1] - ctr[3 * i + 1],
+                                     dz = cen[3 * f + 2] - ctr[3 * i + 2];
+                        const double q = dx * dx + dy * dy + dz * dz;
+                        if (q < best) {
+                            best = q;
+                            bi = i;
+                        }
+                    }
+                    as[f] = bi;
+                }
+            };
+            for (int it = 0; it < 2; ++it) {
+                assign();
+                std::vector<double> sum(3 * k, 0.0);
+                std::vector<int> cnt(k, 0);
+                for (int32_t f = 0; f < F0; ++f) {
+                    cnt[as[f]]++;
+                    for (int c = 0; c < 3; ++c) sum[3 * as[f] + c] += cen[3 * f + c];
+                }
+                for (int i = 0; i < k; ++i)
+                    if (cnt[i])
+                        for (int c = 0; c < 3; ++c) ctr[3 * i + c] = sum[3 * i + c] / cnt[i];
+            }
+            assign();
+            std::vector<int> remap(k, -1);
+            for (int32_t f = 0; f < F0; ++f) remap[as[f]] = 1;
+            int used = 0;
+            for (int i = 0; i < k; ++i)
+                if (remap[i] > 0) remap[i] = used++;
+            for (int32_t f = 0; f < F0; ++f) lab0[f] = (uint8_t)remap[as[f]];
+            k = used;
+        } else {
+            k = 1;
+        }
+        m->h_vcount[o] = k;
+        for (int64_t l = 1; l < L; ++l) {
+            const uint8_t *up = m->h_vlab.data() + m->h_lbeg[o * L + l - 1];
+            uint8_t *lab = m->h_vlab.data() + m->h_lbeg[o * L + l];
+            const int32_t nf = m->h_tcnt[o * L + l];
+            const int32_t *par = d->parent ? d->parent + m->h_tbeg[o * L + l] : nullptr;
+            for (int32_t f = 0; f < nf; ++f) lab[f] = (k > 1 && par) ? up[par[f]] : 0;
+        }
+        for (int64_t l = 0; l < L; ++l) {
+            const uint8_t *lab = m->h_vlab.data() + m->h_lbeg[o * L + l];
+            unsigned long long *bm = m->h_bmask.data() + m->h_bkbeg[o * L + l];
+            for (int32_t f = 0; f < m->h_tcnt[o * L + l]; ++f) bm[f >> 6] |= 1ull << lab[f];
+        }
+        // boxes and anchors from the finest facets
+        float *box = m->h_vbox.data() + (size_t)o * kMaxVox * 6;
+        float *anc = m->h_vanc.data() + (size_t)o * kMaxVox * 3;
+        for (int v = 0; v < kMaxVox; ++v)
+            for (int c = 0; c < 3; ++c) {
+                box[6 * v + c] = INFINITY;
+                box[6 * v + 3 + c] = -INFINITY;
+            }
+        const uint8_t *labf = m->h_vlab.data() + m->h_lbeg[o * L + L - 1];
+        for (int32_t f = 0; f < Ff; ++f) {
+            const int32_t *t = tri(L - 1, f);
+            float *b = box + 6 * labf[f];
+            for (int q = 0; q < 3; ++q)
+                for (int c = 0; c < 3; ++c) {
+                    b[c] = std::min(b[c], V[3 * t[q] + c]);
+                    b[3 + c] = std::max(b[3 + c], V[3 * t[q] + c]);
+                }
+        }
+        std::vector<double> best(k, INFINITY);
+        std::vector<int32_t> bv(k, INT32_MAX);
+        for (int32_t f = 0; f < Ff; ++f) {
+            const int32_t *t = tri(L - 1, f);
+            const int v = labf[f];
+            const float *b = box + 6 * v;
+            for (int q = 0; q < 3; ++q) {
+                double d2 = 0.0;
+                for (int c = 0; c < 3; ++c) {
+                    const double x = (double)V[3 * t[q] + c] - 0.5 * ((double)b[c] + (double)b[3 + c]);
+                    d2 += x * x;
+                }
+                if (d2 < best[v] || (d2 == best[v] && t[q] < bv[v])) {
+                    best[v] = d2;
+                    bv[v] = t[q];
+                }
+            }
+        }
+        for (int v = 0; v < k; ++v)
+            for (int c = 0; c < 3; ++c) anc[3 * v + c] = bv[v] == INT32_MAX ? 0.0f : V[3 * bv[v] + c];
+    });
+}
+
+pj_status upload_voxels(pj_context *ctx, pj_meshes *m, bool with_facets)
+{
+    hipStream_t st = ctx->stream;
+    hipError_t e;
+    const int64_t n = m->n;
+    if ((e = upload(m->al, &m->d_vcount, m->h_vcount.data(), n, st)) != hipSuccess) return hipfail(ctx, e, "voxel counts");
+    if ((e = upload(m->al, &m->d_vbox, m->h_vbox.data(), m->h_vbox.size(), st)) != hipSuccess)
+        return hipfail(ctx, e, "voxel boxes");
+    if ((e = upload(m->al, &m->d_vanc, m->h_vanc.data(), m->h_vanc.size(), st)) != hipSuccess)
+        return hipfail(ctx, e, "voxel anchors");
+    if (with_facets) {
+        if ((e = upload(m->al, &m->d_vlab, m->h_vlab.data(), std::max<size_t>(m->h_vlab.size(), 1), st)) != hipSuccess)
+            return hipfail(ctx, e, "voxel labels");
+        if ((e = upload(m->al, &m->d_lbeg, m->h_lbeg.data(), m->h_lbeg.size(), st)) != hipSuccess)
+            return hipfail(ctx, e, "label offsets");
+        if ((e = upload(m->al, &m->d_bmask, m->h_bmask.data(), std::max<size_t>(m->h_bmask.size(), 1), st)) !=
+            hipSuccess)
+            return hipfail(ctx, e, "block voxel masks");
+    }
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hipfail(ctx, e, "voxel upload");
+    if (with_facets) {
+        // the host copies of facet-aligned arrays are not needed any more
+        std::vector<uint8_t>().swap(m->h_vlab);
+        std::vector<unsigned long long>().swap(m->h_bmask);
+    }
+    return PJ_OK;
+}
+
 // Device-resident ingest of a validated description into m (on failure the
 // caller frees m).  Boxes, anchors, hd/ph, block records and per-LoD maxima
 // are computed on the GPU; host copies of the small per-object arrays stay.
-pj_status ingest_device(pj_context *ctx, const pj_mesh_desc *d, pj_meshes *m)
+pj_status ingest_device(pj_context *ctx, const pj_mesh_desc *d, pj_meshes *m, bool with_voxels = true)
 {
     hipStream_t st = ctx->stream;
     m->device = ctx->cfg.device;
@@ -724,6 +927,10 @@ pj_status ingest_device(pj_context *ctx, const pj_mesh_desc *d, pj_meshes *m)
     md = m->dev();
     if ((e = launch_blocks(md, m->d_blk, m->d_bkbeg, m->nblk, st)) != hipSuccess) return bail(e, "blocks kernel");
     if ((e = launch_lodmax(md, m->d_lodmax, st)) != hipSuccess) return bail(e, "lodmax kernel");
+    if (ctx->cfg.voxels && with_voxels) {
+        voxelize(ctx, d, m);
+        PJTRY(upload_voxels(ctx, m, true));
+    }
     m->h_box.resize(n * 6);
     m->h_anchor.resize(n * 3);
     m->h_lodmax.resize(n * L);
@@ -845,7 +1052,7 @@ pj_status ingest_host(pj_context *ctx, const pj_mesh_desc *d, pj_meshes *m)
         }
         pj_meshes *tmp = new pj_meshes();
         tmp->al = ctx->alloc;
-        pj_status s = ingest_device(ctx, &sub, tmp);
+        pj_status s = ingest_device(ctx, &sub, tmp, false);
         if (s == PJ_OK) {
             std::vector<float2> hp(std::max<int64_t>(tmp->nh, 1));
             std::vector<float4> bk(std::max<int64_t>(2 * tmp->nblk, 1));
@@ -883,6 +1090,10 @@ pj_status ingest_host(pj_context *ctx, const pj_mesh_desc *d, pj_meshes *m)
     if ((e = upload(m->al, &m->d_anchor, m->h_anchor.data(), 3 * n, st)) != hipSuccess) return hipfail(ctx, e, "anchors");
     if ((e = upload(m->al, &m->d_lodmax, m->h_lodmax.data(), n * L, st)) != hipSuccess) return hipfail(ctx, e, "lodmax");
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hipfail(ctx, e, "ingest sync");
+    if (ctx->cfg.voxels) {
+        voxelize(ctx, d, m);
+        PJTRY(upload_voxels(ctx, m, false));
+    }
     m->p_verts = m->h_verts.data();
     m->p_tris = m->h_tris.data();
     m->p_hdph = m->h_hdph.data();
@@ -1085,6 +1296,9 @@ struct PairState {
     int hit64 = 0;
     float thr = INFINITY;   // collect threshold on the FP32 lower distance
     int8_t res_lod = -1;    // LoD round that decided the pair
+    // bounds when the first LoD was chosen (after the box and voxel
+    // filters): the LoD model's gap and upper-bound features
+    double f_lb = 0.0, f_ub = INFINITY;
 };
 
 void pair_frame(const pj_meshes *R, int r, const pj_meshes *S, int s, PairState &ps)
@@ -1216,9 +1430,16 @@ void plan_tiles(const pj_meshes *R, const pj_meshes *S, const std::vector<int> &
 
 // Work of a LoD round as the schedule planned it: the facet pairs of its
 // items before any culling.
-void count_planned(pj_context *ctx, int lod, const TilePlan &pl)
+void count_planned(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, int lod, const TilePlan &pl)
 {
     if (lod >= 0 && lod < 8) ctx->stats.lod_planned_pairs[lod] += pl.pairs;
+    // the LoD model's cost of these items: sqrt(n_r * n_s) each
+    double c = 0.0;
+    for (const Item &it : pl.items) {
+        const bool sw = it.flags & IT_SWAP;
+        c += std::sqrt((double)R->count(sw ? it.b_obj : it.a_obj, lod) * (double)S->count(sw ? it.a_obj : it.b_obj, lod));
+    }
+    ctx->stats.planned_sqrt += c;
 }
 
 // Tile-count hint of the persistent FP32 rounds (any positive value selects
@@ -1402,19 +1623,21 @@ struct SideStage {
     std::vector<int64_t> vdst, tdst, hdst, bdst;  // staged first rows per object
     std::vector<char> tcopy;                    // object copies its triangle range
     int64_t V = 0, T = 0, H = 0, B = 0;
+    std::vector<int64_t> ldst;  // staged first label row per object (voxels)
+    int64_t NL = 0;
     size_t o_verts = 0, o_tris = 0, o_vbeg = 0, o_tbeg = 0, o_tcnt = 0, o_hpbeg = 0, o_hdph = 0, o_bkbeg = 0,
-           o_blk = 0, end = 0;
+           o_blk = 0, o_lbeg = 0, o_vlab = 0, o_bmask = 0, end = 0;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-constexpr int64_t kStageFixed = 10 * 256;
+constexpr int64_t kStageFixed = 13 * 256;
 
 // staged bytes of one object at one LoD (an upper bound: no range sharing)
 int64_t stage_obj_bytes(const pj_meshes *m, int obj, int lod, bool finest)
 {
     const int64_t tc = m->count(obj, lod);
     return 12 * (int64_t)m->h_vcnt[obj] + 12 * tc + (finest ? 0 : 8 * tc) + 32 * ((tc + 63) / 64) + 8 +
-           28 * (int64_t)m->L + 5 * 256 / 64;
+           28 * (int64_t)m->L + 5 * 256 / 64 + (m->has_vox ? tc + 8 * ((tc + 63) / 64) + 8 * (int64_t)m->L + 3 * 256 / 64 : 0);
 }
 
 void stage_plan(const pj_meshes *m, SideStage &s, size_t base)
@@ -1425,6 +1648,8 @@ void stage_plan(const pj_meshes *m, SideStage &s, size_t base)
     s.hdst.resize(n);
     s.bdst.resize(n);
     s.tcopy.assign(n, 0);
+    s.ldst.assign(n, 0);
+    s.NL = 0;
     std::unordered_map<int64_t, std::pair<int32_t, int64_t>> rows;  // source row -> (count, staged row)
     s.V = s.T = s.H = s.B = 0;
     for (int64_t k = 0; k < n; ++k) {
@@ -1447,6 +1672,8 @@ void stage_plan(const pj_meshes *m, SideStage &s, size_t base)
         if (!s.finest) s.H += tc;
         s.bdst[k] = s.B;
         s.B += (tc + 63) / 64;
+        s.ldst[k] = s.NL;
+        if (m->has_vox) s.NL += tc;
     }
     size_t off = base;
     auto put = [&](size_t &o, size_t bytes) {
@@ -1462,6 +1689,11 @@ void stage_plan(const pj_meshes *m, SideStage &s, size_t base)
     put(s.o_hdph, 8 * s.H);
     put(s.o_bkbeg, 8 * (n * L + 1));
     put(s.o_blk, 32 * s.B);
+    if (m->has_vox) {
+        put(s.o_lbeg, 8 * n * L);
+        put(s.o_vlab, (size_t)s.NL);
+        put(s.o_bmask, 8 * s.B);
+    }
     s.end = off;
 }
 
@@ -1505,6 +1737,11 @@ void stage_fill(const pj_meshes *m, const SideStage &s, char *base, int nthreads
         }
     }
     bkbeg[n * L] = s.B;
+    if (m->has_vox) {
+        int64_t *lbeg = reinterpret_cast<int64_t *>(base + s.o_lbeg);
+        for (int64_t k = 0; k < n; ++k)
+            for (int64_t l = 0; l < L; ++l) lbeg[k * L + l] = l == s.lod ? s.ldst[k] : 0;
+    }
     parallel_for(n, nthreads, [&](int64_t k) {
         const int o = s.objs[k];
         const int64_t key = (int64_t)o * L + s.lod;
@@ -1514,6 +1751,12 @@ void stage_fill(const pj_meshes *m, const SideStage &s, char *base, int nthreads
         if (!s.finest && tc) std::memcpy(hdph + s.hdst[k], m->p_hdph + m->h_hpbeg[key], 8 * (size_t)tc);
         const int64_t nb = (tc + 63) / 64;
         if (nb) std::memcpy(blk + 2 * s.bdst[k], m->p_blk + 2 * m->h_bkbeg[key], 32 * (size_t)nb);
+        if (m->has_vox) {
+            if (tc) std::memcpy(base + s.o_vlab + s.ldst[k], m->h_vlab.data() + m->h_lbeg[key], (size_t)tc);
+            if (nb)
+                std::memcpy(reinterpret_cast<unsigned long long *>(base + s.o_bmask) + s.bdst[k],
+                            m->h_bmask.data() + m->h_bkbeg[key], 8 * (size_t)nb);
+        }
     });
 }
 
@@ -1529,7 +1772,10 @@ MeshDev stage_view(const pj_meshes *m, const SideStage &s, char *dbase)
                    reinterpret_cast<const int64_t *>(dbase + s.o_bkbeg),
                    reinterpret_cast<const float4 *>(dbase + s.o_blk),
                    (int32_t)s.objs.size(),
-                   m->L};
+                   m->L,
+                   m->has_vox ? reinterpret_cast<const uint8_t *>(dbase + s.o_vlab) : nullptr,
+                   m->has_vox ? reinterpret_cast<const int64_t *>(dbase + s.o_lbeg) : nullptr,
+                   m->has_vox ? reinterpret_cast<const unsigned long long *>(dbase + s.o_bmask) : nullptr};
 }
 
 int prep_threads(pj_context *ctx)
@@ -1709,7 +1955,10 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
     out.assign(ni, ItemOut{0x7f800000u, 0x7f800000u, 0, 0});
     if (ni == 0 || nt == 0) return PJ_OK;
     PJTRY(ensure_streams(ctx));
-    const int nsets = ctx->cfg.stage_sets == 3 ? 3 : 2;
+    // one set: every chunk is gathered, uploaded, computed and downloaded
+    // before the next is gathered (no overlap; the comparison for the
+    // pipelined two and three sets)
+    const int nsets = ctx->cfg.stage_sets == 3 ? 3 : (ctx->cfg.stage_sets == 1 ? 1 : 2);
     const bool hostR = R->host, hostS = S->host, staged = hostR || hostS;
     const int lod = pl.items[0].lod;
     const bool finest = pl.items[0].flags & IT_FINEST;
@@ -1911,6 +2160,8 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
         a.tau = tau;
         a.early = early ? 1 : 0;
         a.cull = ctx->cfg.tile_cull ? 1 : 0;
+        a.vmask = ctx->vmask;
+        a.vrow = ctx->vrow;
         HIPTRY(ctx, hipStreamWaitEvent(st, ctx->ev_h2d[b], 0));
         HIPTRY(ctx, hipEventRecord(ctx->ev_k0[b], st));
         PJTRY(launch_round(ctx, a, dctr, cni, cnt, wpc, graph, st));
@@ -2136,6 +2387,8 @@ pj_status exact_finest_view(pj_context *ctx, const MeshDev &Rv, const MeshDev &S
     a.collect_cap = cap;
     a.collected = ptr<PairRef>(ctx->b_coll);
     a.overflow = ptr<int32_t>(ctx->b_ovf);
+    a.vmask = ctx->vmask;
+    a.vrow = ctx->vrow;
     HIPTRY(ctx, hipEventRecord(ctx->ev0, st));
     HIPTRY(ctx, launch_collect_f32(a, cgrid, st));
     HIPTRY(ctx, hipEventRecord(ctx->ev1, st));
@@ -2347,8 +2600,12 @@ pj_status mbb_filter(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, do
 int pick_tile_s(pj_context *ctx) { return ctx->cur.tile_s; }
 
 // per-join reset: counters (the ingest time stays) and the launch shape
+pj_status voxel_filter(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, const std::vector<Cand> &cand,
+                       std::vector<PairState> &ps, const std::vector<int> &idx, float tau);
+
 void begin_join(pj_context *ctx)
 {
+    ctx->vmask = nullptr;
     const double ingest = ctx->stats.t_ingest_ms;
     std::memset(&ctx->stats, 0, sizeof(ctx->stats));
     ctx->stats.t_ingest_ms = ingest;
@@ -2382,7 +2639,7 @@ pj_status refine_within(pj_context *ctx, const pj_meshes *R, const pj_meshes *S,
         ctx->stats.rounds++;
         if (fp64) {
             plan_tiles(R, S, act, cand, ps, lod, finest, 64, TS, !plain, pl);
-            count_planned(ctx, lod, pl);
+            count_planned(ctx, R, S, lod, pl);
             std::vector<ItemOut64> out;
             PJTRY(run_f64(ctx, R, S, pl, plain, out));
             for (size_t k = 0; k < pl.items.size(); ++k) {
@@ -2410,7 +2667,7 @@ pj_status refine_within(pj_context *ctx, const pj_meshes *R, const pj_meshes *S,
             PJTRY(choose_shape(ctx, R, S, act, cand, ps, lod, finest, (float)tau, true));
             plan_tiles(R, S, act, cand, ps, lod, finest, 64 * kP, ctx->cur.tile_s, true, pl,
                        tile_target(ctx, ctx->cur.wpc));
-            count_planned(ctx, lod, pl);
+            count_planned(ctx, R, S, lod, pl);
             std::vector<ItemOut> out;
             PJTRY(run_f32(ctx, R, S, pl, (float)tau, true, out, 0));
             for (size_t k = 0; k < pl.items.size(); ++k) {
@@ -2507,8 +2764,8 @@ void append_log(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, double 
     for (size_t i = 0; i < cand.size(); ++i) {
         if (ps[i].res_lod < 0) continue;
         LogRec rec;
-        pair_features(R, cand[i].r, S, cand[i].s, tau_of ? (double)(*tau_of)[cand[i].r] : tau, cand[i].lb0,
-                      cand[i].ub0, rec.f);
+        pair_features(R, cand[i].r, S, cand[i].s, tau_of ? (double)(*tau_of)[cand[i].r] : tau, ps[i].f_lb,
+                      ps[i].f_ub, rec.f);
         rec.label = ps[i].res_lod;
         rec.n_lods = R->L;
         std::fwrite(&rec, sizeof(rec), 1, fp);
@@ -2559,10 +2816,13 @@ pj_status learned_start(pj_context *ctx, const pj_meshes *R, const pj_meshes *S,
     host_for(ctx, n, [&](int64_t q) {
         const Cand &c = cand[idx[q]];
         float f[MLP_IN];
-        pair_features(R, c.r, S, c.s, tau_of ? (double)(*tau_of)[c.r] : tau, c.lb0, c.ub0, f);
+        pair_features(R, c.r, S, c.s, tau_of ? (double)(*tau_of)[c.r] : tau, ps[idx[q]].f_lb, ps[idx[q]].f_ub, f);
         for (int j = 0; j < MLP_IN; ++j) x[(size_t)q * MLP_IN + j] = (f[j] - ctx->feat_mean[j]) / ctx->feat_std[j];
+        // expected work of a LoD: with the box culling of the refinement the
+        // facet pairs evaluated grow with the square root of the planned
+        // n_r * n_s (the facets near the closest approach), not with it
         for (int l = 0; l < MLP_OUT; ++l)
-            cost[(size_t)q * MLP_OUT + l] = (float)((double)R->count(c.r, l) * (double)S->count(c.s, l));
+            cost[(size_t)q * MLP_OUT + l] = (float)std::sqrt((double)R->count(c.r, l) * (double)S->count(c.s, l));
     });
     PJTRY(ensure(ctx, ctx->b_tmp0, (size_t)n * MLP_IN * 4));
     PJTRY(ensure(ctx, ctx->b_tmp1, (size_t)n * MLP_OUT * 4 * 2 + (size_t)n * 4));
@@ -2611,6 +2871,23 @@ extern "C" pj_status pj_join_within(pj_context *ctx, const pj_meshes *R, const p
         else if (cand[i].lb0 > tau) ps[i].status = ST_PRUNED;
     });
     for (int i = 0; i < nc; ++i) ctx->stats.confirmed_filter += ps[i].status == ST_CONF;
+    if (ctx->cfg.voxels && ctx->cfg.schedule == PJ_SCHED_BATCHED) {
+        // voxel-pair filtering of the undecided pairs (Section 3.2)
+        std::vector<int> und;
+        for (int i = 0; i < nc; ++i)
+            if (ps[i].status == ST_UNDEC) und.push_back(i);
+        PJTRY(voxel_filter(ctx, R, S, cand, ps, und, (float)tau));
+        if (ctx->vmask)
+            for (int i : und) {
+                if (ps[i].UB <= tau) ps[i].status = ST_CONF;
+                else if (ps[i].LB > tau) ps[i].status = ST_PRUNED;
+                ctx->stats.voxel_decided += ps[i].status != ST_UNDEC;
+            }
+    }
+    for (int i = 0; i < nc; ++i) {
+        ps[i].f_lb = ps[i].LB;
+        ps[i].f_ub = ps[i].UB;
+    }
     const bool learned = ctx->cfg.learned_skip && ctx->has_model && R->L == MLP_OUT &&
                          ctx->cfg.schedule == PJ_SCHED_BATCHED;
     if (learned) PJTRY(learned_start(ctx, R, S, tau, cand, ps, start));
@@ -2672,6 +2949,152 @@ extern "C" pj_status pj_join_intersect(pj_context *ctx, const pj_meshes *R, cons
 namespace {
 
 // One pruning round of Algorithm 6 (corrected) on the device for every query.
+// Voxel-pair filtering (Section 3.2): Algorithm 1 bounds every voxel pair of
+// the candidates in `idx` and takes the minima as the pairs' bounds;
+// Algorithm 2 keeps the voxel pairs with lb_v <= ub_o (within-tau: also
+// <= tau; a within pair that its voxel bounds decide keeps none) by count,
+// scan and compaction.  The candidates are cut into chunks of at most
+// kVpChunk voxel pairs so that the lb_v buffer has a fixed size (Algorithm
+// 3); the chunks are enqueued back to back on the join stream with two
+// alternating input and output sets.  The survivors stay on the device: a
+// last kernel per chunk turns them into each candidate's 64 rows of 64 bits
+// (R-major), which the refinement kernel reads; only the pairs' bounds
+// return to the host, once.  On return every processed candidate's LB/UB
+// include the voxel bounds and ctx->vmask points at the rows (a candidate
+// that was not processed, or has no survivors because its bounds decided
+// it, keeps every voxel pair).
+constexpr int64_t kVpChunk = int64_t(1) << 26;
+
+pj_status voxel_filter(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, const std::vector<Cand> &cand,
+                       std::vector<PairState> &ps, const std::vector<int> &idx, float tau)
+{
+    ctx->vmask = nullptr;
+    if (!R->has_vox || !S->has_vox || cand.empty()) return PJ_OK;
+    const double t0 = now_ms();
+    hipStream_t st = ctx->stream;
+    for (int b = 0; b < 2; ++b)
+        if (!ctx->ev_vcomp[b]) HIPTRY(ctx, hipEventCreateWithFlags(&ctx->ev_vcomp[b], hipEventDisableTiming));
+    const int64_t nidx = (int64_t)idx.size();
+    // rows of the processed candidates, and each candidate's row index (-1:
+    // every voxel pair); under a cap that cannot hold them (and a chunk of
+    // the smallest size) the filter is skipped and nothing is restricted
+    const int64_t need = align256(nidx * kMaxVox * 8) + align256(cand.size() * 4) +
+                         16 * kMaxVox * kMaxVox + 4 * align256(int64_t(1) << 12) + 64 * 1024;
+    if (ctx->cfg.mem_cap_bytes > 0 && ctx->dev_bytes + need > ctx->cfg.mem_cap_bytes) return PJ_OK;
+    PJTRY(ensure(ctx, ctx->b_vmask, std::max<int64_t>(nidx, 1) * kMaxVox * 8));
+    PJTRY(ensure(ctx, ctx->b_vrow, cand.size() * 4));
+    HIPTRY(ctx, hipMemsetAsync(ctx->b_vmask.p, 0xff, std::max<int64_t>(nidx, 1) * kMaxVox * 8, st));
+    {
+        std::vector<int32_t> vrow(cand.size(), -1);
+        for (int64_t q = 0; q < nidx; ++q) vrow[idx[q]] = (int32_t)q;
+        HIPTRY(ctx, hipMemcpyAsync(ctx->b_vrow.p, vrow.data(), vrow.size() * 4, hipMemcpyHostToDevice, st));
+        HIPTRY(ctx, hipStreamSynchronize(st));
+    }
+    // voxel pairs per chunk: each costs 4 B of lb_v and 4 B of survivors in
+    // each of the two output sets; under a cap, what is left after the pair
+    // bounds and per-pair arrays (with room for one growth step)
+    int64_t budget = kVpChunk;
+    if (ctx->cfg.mem_cap_bytes > 0)
+        budget = std::max<int64_t>(kMaxVox * kMaxVox,
+                                   std::min<int64_t>(budget, (ctx->cfg.mem_cap_bytes - ctx->dev_bytes - 48 * nidx -
+                                                              (int64_t(1) << 18)) / 24));
+    // chunks of candidates (in idx order)
+    std::vector<std::pair<size_t, size_t>> chunks;
+    std::vector<int64_t> nvp(idx.size());
+    {
+        size_t c0 = 0;
+        int64_t acc = 0;
+        for (size_t q = 0; q < idx.size(); ++q) {
+            const Cand &c = cand[idx[q]];
+            nvp[q] = (int64_t)R->h_vcount[c.r] * S->h_vcount[c.s];
+            if (q > c0 && (acc + nvp[q] > budget || q - c0 >= (size_t(1) << 20))) {
+                chunks.push_back({c0, q});
+                c0 = q;
+                acc = 0;
+            }
+            acc += nvp[q];
+        }
+        if (c0 < idx.size()) chunks.push_back({c0, idx.size()});
+    }
+    const int nch = (int)chunks.size();
+    int64_t max_np = 1, max_vp = 1, vp_total = 0;
+    for (auto &ch : chunks) {
+        max_np = std::max<int64_t>(max_np, (int64_t)(ch.second - ch.first));
+        int64_t a = 0;
+        for (size_t q = ch.first; q < ch.second; ++q) a += nvp[q];
+        max_vp = std::max(max_vp, a);
+        vp_total += a;
+    }
+    PJTRY(ensure(ctx, ctx->b_vplb, max_vp * 4));
+    // pair bounds of every processed candidate (float lb, ub), read back once
+    PJTRY(ensure(ctx, ctx->b_vpub, std::max<int64_t>(nidx, 1) * 8 + 256 + 8 * (int64_t)nch));
+    int64_t *dtot = (int64_t *)((char *)ctx->b_vpub.p + align256(std::max<int64_t>(nidx, 1) * 8));  // survivors per chunk
+    // per set: in = cr, cs (int32), vp_off (int64, np + 1); out = count
+    // (int32), blk_off (int64, np + 1), survivors (uint32)
+    const size_t in_bytes = align256(8 * max_np) + align256(8 * (max_np + 1));
+    const size_t out_bytes = align256(4 * max_np) + align256(8 * (max_np + 1)) + align256(4 * max_vp);
+    for (int b = 0; b < std::min(nch, 2); ++b) {
+        PJTRY(ensure(ctx, ctx->vx_in[b], in_bytes));
+        PJTRY(ensure(ctx, ctx->vx_out[b], out_bytes));
+        PJTRY(ensure_pinned(ctx, ctx->pin_vin[b], in_bytes));
+    }
+    const VoxSide vr = R->vox(), vs = S->vox();
+    float *op = ptr<float>(ctx->b_vpub);  // [nidx][2]
+    for (int c = 0; c < nch; ++c) {
+        const int b = c & 1;
+        const size_t q0 = chunks[c].first, q1 = chunks[c].second;
+        const int np = (int)(q1 - q0);
+        // the set's pinned inputs are free once chunk c - 2 has run
+        if (c >= 2) HIPTRY(ctx, hipEventSynchronize(ctx->ev_vcomp[b]));
+        char *hin = (char *)ctx->pin_vin[b].p, *din = (char *)ctx->vx_in[b].p, *dout = (char *)ctx->vx_out[b].p;
+        int32_t *hcr = (int32_t *)hin, *hcs = hcr + max_np;
+        int64_t *hoff = (int64_t *)(hin + align256(8 * max_np));
+        hoff[0] = 0;
+        for (int q = 0; q < np; ++q) {
+            hcr[q] = cand[idx[q0 + q]].r;
+            hcs[q] = cand[idx[q0 + q]].s;
+            hoff[q + 1] = hoff[q] + nvp[q0 + q];
+        }
+        HIPTRY(ctx, hipMemcpyAsync(din, hin, in_bytes, hipMemcpyHostToDevice, st));
+        const int32_t *dcr = (const int32_t *)din, *dcs = dcr + max_np;
+        const int64_t *doff = (const int64_t *)(din + align256(8 * max_np));
+        int32_t *cnt = (int32_t *)dout;
+        int64_t *boff = (int64_t *)(dout + align256(4 * max_np));
+        uint32_t *vpairs = (uint32_t *)(dout + align256(4 * max_np) + align256(8 * (max_np + 1)));
+        float *olb = op + q0, *oub = op + nidx + q0;
+        HIPTRY(ctx, launch_vp_bound(dcr, dcs, doff, np, vr, vs, ptr<float>(ctx->b_vplb), olb, oub, st));
+        HIPTRY(ctx, launch_vp_count(dcr, dcs, doff, np, vr, vs, ptr<float>(ctx->b_vplb), olb, oub, tau, cnt, st));
+        HIPTRY(ctx, launch_scan_i32_to_i64(cnt, boff, boff + np, np, st));
+        HIPTRY(ctx, hipMemcpyAsync(dtot + c, boff + np, 8, hipMemcpyDeviceToDevice, st));
+        HIPTRY(ctx, launch_vp_write(dcr, dcs, doff, np, vr, vs, ptr<float>(ctx->b_vplb), olb, oub, tau, boff, vpairs,
+                                    st));
+        HIPTRY(ctx, launch_vp_rows((int)q0, np, boff, vpairs, ptr<unsigned long long>(ctx->b_vmask), st));
+        HIPTRY(ctx, hipEventRecord(ctx->ev_vcomp[b], st));
+    }
+    std::vector<float> hop(2 * std::max<int64_t>(nidx, 1));
+    std::vector<int64_t> htot(std::max(nch, 1), 0);
+    if (nidx) HIPTRY(ctx, hipMemcpyAsync(hop.data(), op, 8 * nidx, hipMemcpyDeviceToHost, st));
+    if (nch) HIPTRY(ctx, hipMemcpyAsync(htot.data(), dtot, 8 * nch, hipMemcpyDeviceToHost, st));
+    HIPTRY(ctx, hipStreamSynchronize(st));
+    for (int c = 0; c < nch; ++c) ctx->stats.vp_kept += htot[c];
+    for (int64_t q = 0; q < nidx; ++q) {
+        PairState &p = ps[idx[q]];
+        p.LB = std::max(p.LB, (double)hop[q]);
+        p.UB = std::min(p.UB, (double)hop[nidx + q]);
+    }
+    if (ctx->cfg.mem_cap_bytes > 0) {
+        // under a cap the chunk buffers go back before the LoD rounds
+        for (DevBuf *x : {&ctx->b_vplb, &ctx->b_vpub, &ctx->vx_in[0], &ctx->vx_in[1], &ctx->vx_out[0], &ctx->vx_out[1]})
+            x->release();
+    }
+    ctx->vmask = ptr<unsigned long long>(ctx->b_vmask);
+    ctx->vrow = ptr<int32_t>(ctx->b_vrow);
+    ctx->stats.vp_pairs += vp_total;
+    ctx->stats.vp_chunks += nch;
+    ctx->stats.t_voxel_ms += now_ms() - t0;
+    return PJ_OK;
+}
+
 // Grid of the k-NN candidate kernels over S's anchors.  The cell edge is
 // about the distance of an S anchor to its k-th nearest neighbour (from a
 // sample: 128 anchors against up to 4096 others, scaled by the sampling
@@ -2909,6 +3332,18 @@ extern "C" pj_status pj_join_knn(pj_context *ctx, const pj_meshes *R, const pj_m
     const double t1 = now_ms();
     ctx->stats.t_filter_ms = t1 - t0;
     PJTRY(knn_prune_round(ctx, nR, k, off, cand, ps));
+    if (ctx->cfg.voxels && ctx->cfg.schedule == PJ_SCHED_BATCHED) {
+        // voxel-pair filtering of the undecided candidates (Section 3.2), then
+        // the pruning rule on the tightened intervals
+        std::vector<int> und;
+        for (int64_t i = 0; i < total; ++i)
+            if (ps[i].status == ST_UNDEC) und.push_back((int)i);
+        PJTRY(voxel_filter(ctx, R, S, cand, ps, und, -1.0f));
+        if (ctx->vmask) {
+            PJTRY(knn_prune_round(ctx, nR, k, off, cand, ps));
+            for (int i : und) ctx->stats.voxel_decided += ps[i].status != ST_UNDEC;
+        }
+    }
     const int L = R->L;
     // learned first LoD (the threshold feature of a candidate is its query's
     // theta_r, the k-th smallest anchor bound), and resolution logs of the
@@ -2922,6 +3357,10 @@ extern "C" pj_status pj_join_knn(pj_context *ctx, const pj_meshes *R, const pj_m
         HIPTRY(ctx, hipStreamSynchronize(st));
         for (float &x : theta)
             if (!std::isfinite(x)) x = 1e30f;
+    }
+    for (int64_t i = 0; i < total; ++i) {
+        ps[i].f_lb = ps[i].LB;
+        ps[i].f_ub = ps[i].UB;
     }
     if (learned) PJTRY(learned_start(ctx, R, S, 0.0, cand, ps, start, &theta));
     // coarse LoD rounds on the undecided candidates
@@ -2945,7 +3384,7 @@ extern "C" pj_status pj_join_knn(pj_context *ctx, const pj_meshes *R, const pj_m
         ctx->stats.rounds++;
         if (fp64) {
             plan_tiles(R, S, act, cand, ps, lod, 0, 64, TS, !plain, pl);
-            count_planned(ctx, lod, pl);
+            count_planned(ctx, R, S, lod, pl);
             std::vector<ItemOut64> o64;
             PJTRY(run_f64(ctx, R, S, pl, plain, o64));
             for (size_t q = 0; q < pl.items.size(); ++q) {
@@ -2958,7 +3397,7 @@ extern "C" pj_status pj_join_knn(pj_context *ctx, const pj_meshes *R, const pj_m
             PJTRY(choose_shape(ctx, R, S, act, cand, ps, lod, fin_round, -1.0f, false));
             plan_tiles(R, S, act, cand, ps, lod, fin_round, 64 * kP, ctx->cur.tile_s, true, pl,
                        tile_target(ctx, ctx->cur.wpc));
-            count_planned(ctx, lod, pl);
+            count_planned(ctx, R, S, lod, pl);
             std::vector<ItemOut> o32;
             PJTRY(run_f32(ctx, R, S, pl, -1.0f, false, o32, 0));
             for (size_t q = 0; q < pl.items.size(); ++q) {
@@ -3086,6 +3525,7 @@ extern "C" pj_status pj_pair_bounds(pj_context *ctx, const pj_meshes *R, const p
     for (int64_t i = 0; i < n; ++i)
         if (r[i] < 0 || r[i] >= R->n || s[i] < 0 || s[i] >= S->n) return fail(ctx, PJ_ERR_INVALID_ARG, "object id");
     HIPTRY(ctx, hipSetDevice(ctx->cfg.device));
+    ctx->vmask = nullptr;  // every facet pair counts here
     std::vector<Cand> cand(n);
     std::vector<PairState> ps(n);
     std::vector<int> act(n);

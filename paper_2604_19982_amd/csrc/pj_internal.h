@@ -22,7 +22,15 @@ struct MeshDev {
     const int64_t *bkbeg;  // [n*L] first block record of (object, LoD)
     const float4 *blk;     // per block of 64 consecutive facets: (lo.xyz, max hd), (hi.xyz, max ph)
     int32_t n, L;
+    // voxels (null when the set has none): the voxel of every facet of every
+    // (object, LoD), and per block record the set of voxels of its facets
+    const uint8_t *vlab;               // labels, (object, LoD) ranges from lbeg
+    const int64_t *lbeg;               // [n*L]
+    const unsigned long long *bmask;   // [blocks] bit v set if a facet of the block is in voxel v
 };
+
+// Voxels: at most 64 per object, so that a set of voxels is one 64-bit mask.
+constexpr int kMaxVox = 64;
 
 // One refinement work item: an object pair at one LoD.  The facets of the
 // "A" object are held in registers, those of "B" are streamed.
@@ -77,6 +85,11 @@ struct RefineArgs {
     long long collect_cap;   // collect mode: capacity of `collected`
     PairRef *collected;      // collect mode: facet pairs with d_lo <= item.thr
     int32_t *overflow;       // collect mode: per item, 1 if its pairs did not fit
+    // voxel pairs that survived the voxel filter: vrow[item.cand] >= 0 picks a
+    // block of 64 rows of 64 bits in vmask (row i = the S voxels paired with
+    // R voxel i); null, or a negative index: every facet pair counts
+    const unsigned long long *vmask;
+    const int32_t *vrow;
 };
 
 struct Refine64Args {
@@ -135,6 +148,22 @@ hipError_t launch_knn_cand_grid(const float *boxR, const float *ancR, int nR, co
                                 int nS, const float *theta, const KnnGrid &g, const int64_t *beg,
                                 const int32_t *items, int32_t *count, const int64_t *off, int32_t *cs, float *clb,
                                 float *cub, int write_pass, hipStream_t st);
+// Voxel-pair filtering (Algorithms 1-2) over a chunk of candidate pairs.
+struct VoxSide {
+    const float *vbox;      // [n*64][6] voxel boxes (lo, hi); empty voxels have lo > hi
+    const float *vanc;      // [n*64][3] voxel anchors
+    const int32_t *vcount;  // [n] voxels per object
+};
+hipError_t launch_vp_bound(const int32_t *cr, const int32_t *cs, const int64_t *vp_off, int np, VoxSide R, VoxSide S,
+                           float *vp_lb, float *op_lb, float *op_ub, hipStream_t st);
+hipError_t launch_vp_rows(int row0, int np, const int64_t *blk_off, const uint32_t *vpairs, unsigned long long *rows,
+                          hipStream_t st);
+hipError_t launch_vp_count(const int32_t *cr, const int32_t *cs, const int64_t *vp_off, int np, VoxSide R,
+                           VoxSide S, const float *vp_lb, const float *op_lb, const float *op_ub, float tau,
+                           int32_t *count, hipStream_t st);
+hipError_t launch_vp_write(const int32_t *cr, const int32_t *cs, const int64_t *vp_off, int np, VoxSide R,
+                           VoxSide S, const float *vp_lb, const float *op_lb, const float *op_ub, float tau,
+                           const int64_t *blk_off, uint32_t *vpairs, hipStream_t st);
 hipError_t launch_knn_prune(int nR, const int64_t *off, const double *lb, const double *ub, const int32_t *ids,
                             const int8_t *status_in, int8_t *status_out, const int32_t *k_left, hipStream_t st);
 hipError_t launch_refine_f64_tiles(const Refine64Args &a, int64_t ntiles, hipStream_t st);

@@ -696,6 +696,8 @@ struct FacetSrc {
     const float *verts;
     const float2 *hdph;  // nullptr on the finest LoD
     const float4 *blk;   // block records of this (object, LoD)
+    const uint8_t *vlab;               // voxel of each facet (null without voxels)
+    const unsigned long long *bmask;   // voxels of each block record
     int n;
 };
 
@@ -708,8 +710,22 @@ __device__ __forceinline__ FacetSrc facet_src(const MeshDev &M, int obj, int lod
     const int64_t hb = M.hpbeg[k];
     s.hdph = hb >= 0 ? M.hdph + hb : nullptr;
     s.blk = M.blk + 2 * M.bkbeg[k];
+    s.vlab = M.vlab ? M.vlab + M.lbeg[k] : nullptr;
+    s.bmask = M.bmask ? M.bmask + M.bkbeg[k] : nullptr;
     s.n = M.tcnt[k];
     return s;
+}
+
+__device__ __forceinline__ unsigned long long wave_or64(unsigned long long v)
+{
+    unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
+    for (int o = 32; o > 0; o >>= 1) {
+        lo |= (unsigned)__shfl_xor((int)lo, o, 64);
+        hi |= (unsigned)__shfl_xor((int)hi, o, 64);
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    hi = __builtin_amdgcn_readfirstlane(hi);
+    return ((unsigned long long)hi << 32) | lo;
 }
 
 __device__ __forceinline__ Rec load_rec(const FacetSrc &s, int f, V3 o)
@@ -789,6 +805,8 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
     const bool swap = it.flags & IT_SWAP;
     const FacetSrc SA = facet_src(swap ? a.S : a.R, it.a_obj, it.lod);
     const FacetSrc SB = facet_src(swap ? a.R : a.S, it.b_obj, it.lod);
+    const int vrow = (a.vmask && SA.vlab && SB.vlab) ? a.vrow[it.cand] : -1;
+    const unsigned long long *vrows = vrow >= 0 ? a.vmask + (size_t)vrow * kMaxVox : nullptr;
     const V3 org = V3{it.ox, it.oy, it.oz};
     const bool within = a.tau >= 0.0f;
     float lbm = kInf, ubm = kInf;
@@ -824,6 +842,26 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
             ahi = make_float4(fmaxf(ahi.x, h2.x), fmaxf(ahi.y, h2.y), fmaxf(ahi.z, h2.z), fmaxf(ahi.w, h2.w));
         }
         const float aph = ahi.w;
+        // Voxel pairs: the B voxels paired (after the voxel filter) with any
+        // voxel of this A block's facets; B chunks and facets outside them
+        // cannot hold the pair that decides the item and are skipped.
+        unsigned long long bvox = ~0ull;
+        if (vrows) {
+            unsigned long long la = 0ull;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const int fa = a0 + lane + 64 * p;
+                if (fa < SA.n) la |= 1ull << SA.vlab[fa];
+            }
+            la = wave_or64(la);
+            const unsigned long long row = vrows[lane];
+            if (!swap) bvox = wave_or64(((la >> lane) & 1ull) ? row : 0ull);  // rows are A (R) voxels
+            else bvox = __ballot((row & la) != 0ull);                          // rows are B (R) voxels
+            if (bvox == 0ull) {
+                culled += (tl.b1 - tl.b0 + 63) >> 6;
+                continue;
+            }
+        }
         // Surviving B facets wait in an LDS queue (qv: corners, hd, ph and
         // index, as gathered for the facet test) and are evaluated 64 at a
         // time: their records are built by all lanes at once, then every lane
@@ -938,11 +976,17 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
                     gap_l = box_gap32(alo, ahi, blo, bhi) - it.eps;
                     bph_l = bhi.w;
                     live = !chunk_cut<COLLECT>(gap_l, bph_l, aph, cur_lb, cur_ub, lbm, ubm, it, a.tau, within);
+                    if (vrows) live = live && (SB.bmask[c] & bvox) != 0ull;
                 }
                 cmask = __ballot(live);
                 culled += nch - __popcll(cmask);
             } else {
                 cmask = nch == 64 ? ~0ull : ((1ull << nch) - 1ull);
+                if (vrows) {
+                    const bool live = lane < nch && (SB.bmask[(g0 >> 6) + lane] & bvox) != 0ull;
+                    cmask = __ballot(live);
+                    culled += nch - __popcll(cmask);
+                }
             }
             while (cmask != 0ull && !stop) {
                 const int j = __builtin_ctzll(cmask);
@@ -966,6 +1010,7 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
                 // box and ph against the A block; survivors join the LDS queue
                 // with the corners and bounds gathered here.
                 bool keep = lane < nb;
+                if (vrows) keep = keep && ((bvox >> SB.vlab[f]) & 1ull);
                 const int32_t i0 = SB.tris[3 * f], i1 = SB.tris[3 * f + 1], i2 = SB.tris[3 * f + 2];
                 const V3 w0 = ld3f(SB.verts, i0), w1 = ld3f(SB.verts, i1), w2 = ld3f(SB.verts, i2);
                 const float2 bh = SB.hdph ? SB.hdph[f] : make_float2(0.0f, 0.0f);
@@ -1625,6 +1670,177 @@ hipError_t launch_knn_cand_grid(const float *boxR, const float *ancR, int nR, co
     PJ_GRID_CHECK((nR + 255) / 256, 256);
     hipLaunchKernelGGL(k_knn_cand_grid, dim3((nR + 255) / 256), dim3(256), 0, st, boxR, ancR, nR, boxS, ancS, nS,
                        theta, g, beg, items, count, off, cs, clb, cub, write_pass);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Voxel-pair filtering (Section 3.2, Algorithms 1 and 2).  One workgroup per
+// candidate object pair enumerates its voxel pairs (flattened over the
+// workgroup): lb_v = MINDIST of the voxel boxes (FP32, rounded down), ub_v =
+// distance of the voxel anchors (surface vertices, rounded up); the pair's
+// bounds are the minima over its voxel pairs.  Pruning keeps the voxel pairs
+// with lb_v <= ub_o (the object pair's upper bound; for within-tau also
+// <= tau), in three kernels: count per pair, exclusive scan, write.  A
+// within-tau pair that its own bounds decide (ub_o <= tau or lb_o > tau)
+// keeps none.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void vp_bounds(const VoxSide &R, int vr, const VoxSide &S, int vs, float &lb, float &ub)
+{
+    const float *a = R.vbox + 6 * (int64_t)vr, *b = S.vbox + 6 * (int64_t)vs;
+    if (a[0] > a[3] || b[0] > b[3]) {  // an empty voxel (no finest facet)
+        lb = ub = __builtin_inff();
+        return;
+    }
+    const float4 alo = make_float4(a[0], a[1], a[2], 0.0f), ahi = make_float4(a[3], a[4], a[5], 0.0f);
+    const float4 blo = make_float4(b[0], b[1], b[2], 0.0f), bhi = make_float4(b[3], b[4], b[5], 0.0f);
+    lb = box_gap32(alo, ahi, blo, bhi);
+    ub = anchor_ub(R.vanc + 3 * (int64_t)vr, S.vanc + 3 * (int64_t)vs);
+}
+
+__device__ __forceinline__ bool vp_keep(float lb_v, float op_lb, float op_ub, float tau)
+{
+    if (tau >= 0.0f) {
+        if (op_ub <= tau || op_lb > tau) return false;  // decided by the voxel bounds
+        return lb_v <= fminf(op_ub, tau);
+    }
+    return lb_v <= op_ub;
+}
+
+__global__ __launch_bounds__(256) void k_vp_bound(const int32_t *cr, const int32_t *cs, const int64_t *vp_off,
+                                                  VoxSide R, VoxSide S, float *vp_lb, float *op_lb, float *op_ub)
+{
+    __shared__ float sh[8];
+    const int p = blockIdx.x;
+    const int r = cr[p], s = cs[p];
+    const int nr = R.vcount[r], ns = S.vcount[s];
+    const int N = nr * ns;
+    const int64_t off = vp_off[p];
+    float lmin = __builtin_inff(), umin = __builtin_inff();
+    for (int t = threadIdx.x; t < N; t += 256) {
+        const int i = t / ns, j = t - (t / ns) * ns;
+        float lb, ub;
+        vp_bounds(R, kMaxVox * r + i, S, kMaxVox * s + j, lb, ub);
+        vp_lb[off + t] = lb;  // ub_v is only needed as the pair's minimum
+        lmin = fminf(lmin, lb);
+        umin = fminf(umin, ub);
+    }
+    lmin = block_min256(lmin, sh);
+    __syncthreads();
+    umin = block_min256(umin, sh + 4);
+    if (threadIdx.x == 0) {
+        op_lb[p] = lmin;
+        op_ub[p] = umin;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_vp_count(const int32_t *cr, const int32_t *cs, const int64_t *vp_off,
+                                                  VoxSide R, VoxSide S, const float *vp_lb, const float *op_lb,
+                                                  const float *op_ub, float tau, int32_t *count)
+{
+    __shared__ int sh[4];
+    const int p = blockIdx.x;
+    const int N = R.vcount[cr[p]] * S.vcount[cs[p]];
+    const int64_t off = vp_off[p];
+    const float olb = op_lb[p], oub = op_ub[p];
+    int c = 0;
+    for (int t = threadIdx.x; t < N; t += 256) c += vp_keep(vp_lb[off + t], olb, oub, tau) ? 1 : 0;
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) count[p] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// survivors as (pair << 12) | (i << 6) | j, pair-major, (i, j) ascending
+__global__ __launch_bounds__(256) void k_vp_write(const int32_t *cr, const int32_t *cs, const int64_t *vp_off,
+                                                  VoxSide R, VoxSide S, const float *vp_lb, const float *op_lb,
+                                                  const float *op_ub, float tau, const int64_t *blk_off,
+                                                  uint32_t *vpairs)
+{
+    __shared__ int sh[256];
+    const int p = blockIdx.x;
+    const int ns = S.vcount[cs[p]];
+    const int N = R.vcount[cr[p]] * ns;
+    const int64_t off = vp_off[p];
+    const float olb = op_lb[p], oub = op_ub[p];
+    // each thread owns a contiguous run of the flattened voxel pairs, so the
+    // output keeps their order
+    const int per = (N + 255) / 256;
+    const int t0 = min(N, (int)threadIdx.x * per), t1 = min(N, t0 + per);
+    int c = 0;
+    for (int t = t0; t < t1; ++t) c += vp_keep(vp_lb[off + t], olb, oub, tau) ? 1 : 0;
+    // block-wide exclusive scan of the per-thread counts (Hillis-Steele in LDS)
+    sh[threadIdx.x] = c;
+    __syncthreads();
+    for (int st = 1; st < 256; st <<= 1) {
+        const int add = threadIdx.x >= st ? sh[threadIdx.x - st] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int64_t pos = blk_off[p] + sh[threadIdx.x] - c;
+    for (int t = t0; t < t1; ++t)
+        if (vp_keep(vp_lb[off + t], olb, oub, tau)) {
+            const int i = t / ns, j = t - (t / ns) * ns;
+            vpairs[pos++] = ((uint32_t)p << 12) | ((uint32_t)i << 6) | (uint32_t)j;
+        }
+}
+
+hipError_t launch_vp_bound(const int32_t *cr, const int32_t *cs, const int64_t *vp_off, int np, VoxSide R, VoxSide S,
+                           float *vp_lb, float *op_lb, float *op_ub, hipStream_t st)
+{
+    if (np <= 0) return hipSuccess;
+    PJ_GRID_CHECK(np, 256);
+    hipLaunchKernelGGL(k_vp_bound, dim3(np), dim3(256), 0, st, cr, cs, vp_off, R, S, vp_lb, op_lb, op_ub);
+    return hipGetLastError();
+}
+
+// The survivors of each pair of a chunk as 64 rows of 64 bits (row i: the S
+// voxels paired with R voxel i), built in LDS and written over the
+// candidate's rows; a pair without survivors keeps its rows (all pairs).
+__global__ __launch_bounds__(256) void k_vp_rows(int row0, const int64_t *blk_off, const uint32_t *vpairs,
+                                                 unsigned long long *rows)
+{
+    __shared__ unsigned long long sh[kMaxVox];
+    const int p = blockIdx.x;
+    const int64_t b = blk_off[p], e = blk_off[p + 1];
+    if (e == b) return;
+    if (threadIdx.x < kMaxVox) sh[threadIdx.x] = 0ull;
+    __syncthreads();
+    for (int64_t t = b + threadIdx.x; t < e; t += 256) {
+        const uint32_t x = vpairs[t];
+        atomicOr(&sh[(x >> 6) & 63], 1ull << (x & 63));
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxVox) rows[(size_t)(row0 + p) * kMaxVox + threadIdx.x] = sh[threadIdx.x];
+}
+
+hipError_t launch_vp_rows(int row0, int np, const int64_t *blk_off, const uint32_t *vpairs, unsigned long long *rows,
+                          hipStream_t st)
+{
+    if (np <= 0) return hipSuccess;
+    PJ_GRID_CHECK(np, 256);
+    hipLaunchKernelGGL(k_vp_rows, dim3(np), dim3(256), 0, st, row0, blk_off, vpairs, rows);
+    return hipGetLastError();
+}
+
+hipError_t launch_vp_count(const int32_t *cr, const int32_t *cs, const int64_t *vp_off, int np, VoxSide R,
+                           VoxSide S, const float *vp_lb, const float *op_lb, const float *op_ub, float tau,
+                           int32_t *count, hipStream_t st)
+{
+    if (np <= 0) return hipSuccess;
+    PJ_GRID_CHECK(np, 256);
+    hipLaunchKernelGGL(k_vp_count, dim3(np), dim3(256), 0, st, cr, cs, vp_off, R, S, vp_lb, op_lb, op_ub, tau, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_vp_write(const int32_t *cr, const int32_t *cs, const int64_t *vp_off, int np, VoxSide R,
+                           VoxSide S, const float *vp_lb, const float *op_lb, const float *op_ub, float tau,
+                           const int64_t *blk_off, uint32_t *vpairs, hipStream_t st)
+{
+    if (np <= 0) return hipSuccess;
+    PJ_GRID_CHECK(np, 256);
+    hipLaunchKernelGGL(k_vp_write, dim3(np), dim3(256), 0, st, cr, cs, vp_off, R, S, vp_lb, op_lb, op_ub, tau,
+                       blk_off, vpairs);
     return hipGetLastError();
 }
 

@@ -37,10 +37,10 @@ def test_config_default_is_host_only():
 
 def test_struct_sizes_match_header_layout():
     import paper_2604_19982_amd as pj
-    assert ctypes.sizeof(pj.Config) == 4 * 16 + 8 + 8 * 4 + 8 * 3 + 8
+    assert ctypes.sizeof(pj.Config) == 4 * 16 + 8 + 8 * 4 + 8 * 3 + 8 + 8
     assert ctypes.sizeof(pj.MeshDesc) == 8 + 8 + 8 + 8 * 10
     assert ctypes.sizeof(pj.Pairs) == 32
-    assert ctypes.sizeof(pj.Stats) == 7 * 8 + 8 * 8 + 8 * 8 + 16 + 4 * 8 + 8 + 8 + 4 * 64 + 24 + 16 + 64 + 8 + 16
+    assert ctypes.sizeof(pj.Stats) == 7 * 8 + 8 * 8 + 8 * 8 + 16 + 4 * 8 + 8 + 8 + 4 * 64 + 24 + 16 + 64 + 8 + 16 + 40 + 8
 
 
 def test_product_path_does_not_import_oracle():
