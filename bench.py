@@ -149,8 +149,8 @@ def sample_candidates(oracle, O_R, O_S, gap, max_r=20000, seed=0, block=8192):
     cells its box (widened by gap and S's widest half extent) reaches, and
     the exact box gap decides."""
     import numpy as np
-    bR, _ = oracle.mbbs(O_R)
-    bS, _ = oracle.mbbs(O_S)
+    bR, _ = oracle.mbbs(O_R, anchors=False)
+    bS, _ = oracle.mbbs(O_S, anchors=False)
     if max_r >= len(bR):
         rs = np.arange(len(bR))
     else:

@@ -81,7 +81,8 @@ typedef struct {
     int32_t mesh_residency;  /* pj_residency of mesh sets created on this context */
     int32_t stage_sets;      /* staging buffer sets for streamed chunks, 2 or 3 (0: 2); 1 runs the chunks one
                                 after another with no overlap of gather, copies and compute */
-    int32_t filter_mode;     /* MBB filter: 0 auto (x sweep when |R|*|S| > 2^26), 1 all pairs, 2 x sweep.
+    int32_t filter_mode;     /* MBB filter: 0 auto (grid when |R|*|S| > 2^26, else all pairs), 1 all pairs,
+                                2 x sweep, 3 grid over S's anchors (every mode keeps the same candidates).
                                 k-NN candidates: 1 all pairs; otherwise a grid over S's anchors when
                                 k <= 16 (all pairs for larger k) */
     int32_t knn_prune_host;  /* 1: run the k-NN pruning rule on host threads instead of the GPU kernel (the

@@ -196,13 +196,14 @@ def pair_distances_counted(R: OSet, S: OSet, rr, ss, threads: int = 0):
     return d, h.astype(bool), ev
 
 
-def mbbs(S: OSet):
-    """(mbb [n, 6] lo|hi, anchor [n, 3]) in FP64."""
+def mbbs(S: OSet, anchors: bool = True):
+    """(mbb [n, 6] lo|hi, anchor [n, 3]) in FP64 (anchor None when
+    anchors=False)."""
     n = S.ms.n_objects
     box = np.empty((n, 6), np.float64)
-    anc = np.empty((n, 3), np.float64)
+    anc = np.empty((n, 3), np.float64) if anchors else None
     if n:
-        lib().oracle_mbb_all(S.ref, box.ctypes.data, anc.ctypes.data)
+        lib().oracle_mbb_all(S.ref, box.ctypes.data, anc.ctypes.data if anchors else None)
     return box, anc
 
 

@@ -228,7 +228,7 @@ class Context:
         c.autotune = int(bool(autotune))
         c.mesh_residency = 2 if storage_dir is not None else (1 if host_resident else 0)
         c.stage_sets = int(stage_sets)
-        c.filter_mode = {"auto": 0, "pairs": 1, "sweep": 2, "grid": 2}[filter_mode]
+        c.filter_mode = {"auto": 0, "pairs": 1, "sweep": 2, "grid": 3}[filter_mode]
         c.knn_prune_host = int(bool(knn_prune_host))
         c.voxels = int(bool(voxels))
         self._paths = [None if p is None else os.fsencode(p) for p in (model_path, log_path, autotune_path)]

@@ -346,7 +346,10 @@ pj_status ensure(pj_context *ctx, DevBuf &b, size_t bytes)
         nb = bytes;
         after = ctx->dev_bytes - (int64_t)b.cap + (int64_t)nb;
         if (after > ctx->cfg.mem_cap_bytes)
-            return fail(ctx, PJ_ERR_OUT_OF_MEMORY, "work buffers exceed the configured device memory cap");
+            return fail(ctx, PJ_ERR_OUT_OF_MEMORY,
+                        "work buffers exceed the configured device memory cap (" + std::to_string(bytes) +
+                            " bytes requested, " + std::to_string(ctx->dev_bytes) + " in use, cap " +
+                            std::to_string(ctx->cfg.mem_cap_bytes) + ")");
     }
     if (b.p) b.al->free(b.p);
     ctx->dev_bytes -= (int64_t)b.cap;
@@ -437,7 +440,7 @@ extern "C" pj_status pj_context_create(const pj_config *cfg, pj_context **out)
         if (colon != std::string::npos) ctx->arch.resize(colon);
     }
     if (ctx->arch.empty()) ctx->arch = "gpu";
-    if (c.chunk_tiles < 0 || c.filter_mode < 0 || c.filter_mode > 2 || c.knn_prune_host < 0 || c.knn_prune_host > 1 ||
+    if (c.chunk_tiles < 0 || c.filter_mode < 0 || c.filter_mode > 3 || c.knn_prune_host < 0 || c.knn_prune_host > 1 ||
         c.voxels < 0 || c.voxels > 1 || c.reserved1 != 0 ||
         (c.mesh_residency != PJ_RESIDENT_DEVICE && c.mesh_residency != PJ_RESIDENT_HOST &&
          c.mesh_residency != PJ_RESIDENT_FILE) ||
@@ -2564,6 +2567,49 @@ pj_status mbb_filter_sweep(pj_context *ctx, const pj_meshes *R, const pj_meshes 
     return download_cands(ctx, total, cand);
 }
 
+KnnGrid knn_grid_params(const pj_meshes *S, int k);
+
+// Grid filter: the all-pairs test and bounds, applied only to the S objects
+// binned (by anchor) in the grid cells each r's box can reach; candidates in
+// (r, s) order.
+pj_status mbb_filter_grid(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, float tau2, std::vector<Cand> &cand)
+{
+    hipStream_t st = ctx->stream;
+    const int nR = R->n, nS = S->n;
+    const KnnGrid g = knn_grid_params(S, 1);
+    const int64_t ncell = (int64_t)g.gx * g.gy * g.gz;
+    PJTRY(ensure(ctx, ctx->b_gcell, (size_t)nS * 4));
+    PJTRY(ensure(ctx, ctx->b_gitems, (size_t)nS * 4));
+    PJTRY(ensure(ctx, ctx->b_gcnt, (size_t)ncell * 4));
+    PJTRY(ensure(ctx, ctx->b_gfill, (size_t)ncell * 4));
+    PJTRY(ensure(ctx, ctx->b_gbeg, (size_t)(ncell + 3 + ncell / 4096) * 8));
+    PJTRY(ensure(ctx, ctx->b_total, 16));
+    HIPTRY(ctx, launch_grid_build(S->d_anchor, nS, g, ptr<int32_t>(ctx->b_gcell), ptr<int32_t>(ctx->b_gcnt),
+                                  ptr<int64_t>(ctx->b_gbeg), ptr<int64_t>(ctx->b_total) + 1, ptr<int32_t>(ctx->b_gfill),
+                                  ptr<int32_t>(ctx->b_gitems), st));
+    PJTRY(ensure(ctx, ctx->b_blk, (size_t)nR * 4));
+    PJTRY(ensure(ctx, ctx->b_blkoff, (size_t)(nR + 3 + nR / 4096) * 8));
+    // reach: the largest gap the squared test can keep, rounded up
+    const float reach = up_float(std::sqrt((double)tau2) * (1.0 + std::ldexp(1.0, -20)));
+    HIPTRY(ctx, launch_filter_grid(R->d_box, R->d_anchor, nR, S->d_box, S->d_anchor, reach, tau2, g,
+                                   ptr<int64_t>(ctx->b_gbeg), ptr<int32_t>(ctx->b_gitems), ptr<int32_t>(ctx->b_blk),
+                                   nullptr, nullptr, nullptr, nullptr, nullptr, 0, st));
+    HIPTRY(ctx, launch_scan_large(ptr<int32_t>(ctx->b_blk), ptr<int64_t>(ctx->b_blkoff), ptr<int64_t>(ctx->b_total), nR,
+                                  st));
+    int64_t total = 0;
+    PJTRY(read_cand_total(ctx, total));
+    ctx->stats.knn_grid_cells = ncell;
+    if (total == 0) return PJ_OK;
+    if (total > INT32_MAX) return fail(ctx, PJ_ERR_UNSUPPORTED, "more than 2^31 candidate pairs");
+    PJTRY(ensure(ctx, ctx->b_cand_r, total * 16));
+    int32_t *d_cr = ptr<int32_t>(ctx->b_cand_r), *d_cs = d_cr + total;
+    float *d_lb = reinterpret_cast<float *>(d_cs + total), *d_ub = d_lb + total;
+    HIPTRY(ctx, launch_filter_grid(R->d_box, R->d_anchor, nR, S->d_box, S->d_anchor, reach, tau2, g,
+                                   ptr<int64_t>(ctx->b_gbeg), ptr<int32_t>(ctx->b_gitems), nullptr,
+                                   ptr<int64_t>(ctx->b_blkoff), d_cr, d_cs, d_lb, d_ub, 1, st));
+    return download_cands(ctx, total, cand);
+}
+
 // MBB filter on the device: candidates with box gap <= tau.
 pj_status mbb_filter(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, double tau, std::vector<Cand> &cand)
 {
@@ -2572,9 +2618,9 @@ pj_status mbb_filter(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, do
     const int nR = R->n, nS = S->n;
     double t2 = tau * (1.0 + std::ldexp(1.0, -20));
     float tau2 = up_float(t2 * t2);
-    const bool sweep = ctx->cfg.filter_mode == 2 ||
-                       (ctx->cfg.filter_mode == 0 && (double)nR * (double)nS > (double)(int64_t(1) << 26));
-    if (sweep) return mbb_filter_sweep(ctx, R, S, tau2, cand);
+    const bool big = (double)nR * (double)nS > (double)(int64_t(1) << 26);
+    if (ctx->cfg.filter_mode == 2) return mbb_filter_sweep(ctx, R, S, tau2, cand);
+    if (ctx->cfg.filter_mode == 3 || (ctx->cfg.filter_mode == 0 && big)) return mbb_filter_grid(ctx, R, S, tau2, cand);
     const int gx = (nR + 255) / 256, gy = (nS + 511) / 512;
     const int nb = gx * gy;
     PJTRY(ensure(ctx, ctx->b_blk, nb * sizeof(int32_t)));

@@ -1104,10 +1104,33 @@ __device__ __forceinline__ void refine_tiles(const RefineArgs &a, float4 *sh, fl
         refine_tile_f32<P, COLLECT>(a, t, sh, qv, true, pairs_acc, culled_acc);
         t = __builtin_amdgcn_readfirstlane(nxt);
     }
-    // one pass over the slots, starting at this workgroup's own so that the
-    // helpers spread over the tiles in progress
+    // Helping: one pass over the tiles still in progress.  A round with no
+    // more tiles than workgroups scans the tiles themselves (every tile has
+    // been taken by now, and a multi-block tile with blocks left can be
+    // joined); a larger one scans the workgroup slots, starting at this
+    // workgroup's own so that the helpers spread over the tiles in progress.
     const int nslot = gridDim.x;
-    for (int h = 0; h < nslot;) {
+    if (ntiles <= nslot) {
+        for (int h = 0; h < ntiles;) {
+            const int tt = h + (int)threadIdx.x;
+            int c = -1;
+            if (tt < ntiles) {
+                const Tile x = a.tiles[tt];
+                const int nb = (x.a1 - x.a0 + 64 * P - 1) / (64 * P);
+                if (nb > 1 && __hip_atomic_load(a.tile_cur + tt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < nb) c = tt;
+            }
+            const unsigned long long m = __ballot(c >= 0);
+            if (m == 0ull) {
+                h += 64;
+                continue;
+            }
+            const int l = __builtin_ctzll(m);
+            const int tj = __builtin_amdgcn_readlane(c, l);
+            refine_tile_f32<P, COLLECT>(a, tj, sh, qv, false, pairs_acc, culled_acc);
+            h += l + 1;
+        }
+    }
+    for (int h = ntiles <= nslot ? nslot : 0; h < nslot;) {
         const int hw = h + (int)threadIdx.x;
         int w = hw + (int)blockIdx.x;
         if (w >= nslot) w -= nslot;
@@ -1648,6 +1671,89 @@ __global__ __launch_bounds__(256) void k_knn_cand_grid(const float *boxR, const 
         clb[j + 1] = l;
         cub[j + 1] = u;
     }
+}
+
+// Within-tau MBB filter through the same grid: one thread per r visits the
+// cells its box reaches (widened by tau, the widest anchor-to-box extent of S
+// and one cell) and applies the all-pairs kernel's test and bounds to each S
+// object there; count pass, then write pass in s order per r.
+__global__ __launch_bounds__(256) void k_filter_grid(const float *boxR, const float *ancR, int nR, const float *boxS,
+                                                     const float *ancS, float tau, float tau2, KnnGrid g,
+                                                     const int64_t *beg, const int32_t *items, int32_t *count,
+                                                     const int64_t *off, int32_t *cr, int32_t *cs, float *clb,
+                                                     float *cub, int write_pass)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nR) return;
+    float b[6];
+    for (int c = 0; c < 6; ++c) b[c] = boxR[6 * (int64_t)r + c];
+    const float o[3] = {g.ox, g.oy, g.oz}, w[3] = {g.wx, g.wy, g.wz};
+    const int gd[3] = {g.gx, g.gy, g.gz};
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        const float reach = tau + w[a] + g.c;
+        lo[a] = grid_coord(b[a] - reach, o[a], g.inv_c, gd[a]);
+        hi[a] = grid_coord(b[3 + a] + reach, o[a], g.inv_c, gd[a]);
+    }
+    int64_t pos = write_pass ? off[r] : 0;
+    int total = 0;
+    const float ax = ancR[3 * (int64_t)r], ay = ancR[3 * (int64_t)r + 1], az = ancR[3 * (int64_t)r + 2];
+    for (int z = lo[2]; z <= hi[2]; ++z)
+        for (int y = lo[1]; y <= hi[1]; ++y) {
+            const int row = (z * g.gy + y) * g.gx;
+            for (int64_t q = beg[row + lo[0]]; q < beg[row + hi[0] + 1]; ++q) {
+                const int sidx = items[q];
+                const float *x = boxS + 6 * (int64_t)sidx;
+                const float gx = fmaxf(0.0f, fmaxf(x[0] - b[3], b[0] - x[3]));
+                const float gy = fmaxf(0.0f, fmaxf(x[1] - b[4], b[1] - x[4]));
+                const float gz = fmaxf(0.0f, fmaxf(x[2] - b[5], b[2] - x[5]));
+                const float g2 = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
+                if (g2 <= tau2) {
+                    if (write_pass) {
+                        const float *sa = ancS + 3 * (int64_t)sidx;
+                        const float dx = sa[0] - ax, dy = sa[1] - ay, dz = sa[2] - az;
+                        cr[pos] = r;
+                        cs[pos] = sidx;
+                        clb[pos] = __builtin_sqrtf(g2) * (1.0f - 0x1p-20f);
+                        cub[pos] = __builtin_sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx))) * (1.0f + 0x1p-20f);
+                    }
+                    ++pos;
+                    ++total;
+                }
+            }
+        }
+    if (!write_pass) {
+        count[r] = total;
+        return;
+    }
+    // insertion sort of r's candidates by s
+    const int64_t b0 = off[r], e0 = off[r + 1];
+    for (int64_t i = b0 + 1; i < e0; ++i) {
+        const int sv = cs[i];
+        const float l = clb[i], u = cub[i];
+        int64_t j = i - 1;
+        while (j >= b0 && cs[j] > sv) {
+            cs[j + 1] = cs[j];
+            clb[j + 1] = clb[j];
+            cub[j + 1] = cub[j];
+            --j;
+        }
+        cs[j + 1] = sv;
+        clb[j + 1] = l;
+        cub[j + 1] = u;
+    }
+}
+
+hipError_t launch_filter_grid(const float *boxR, const float *ancR, int nR, const float *boxS, const float *ancS,
+                              float tau, float tau2, const KnnGrid &g, const int64_t *beg, const int32_t *items,
+                              int32_t *count, const int64_t *off, int32_t *cr, int32_t *cs, float *clb, float *cub,
+                              int write_pass, hipStream_t st)
+{
+    if (nR == 0) return hipSuccess;
+    PJ_GRID_CHECK((nR + 255) / 256, 256);
+    hipLaunchKernelGGL(k_filter_grid, dim3((nR + 255) / 256), dim3(256), 0, st, boxR, ancR, nR, boxS, ancS, tau, tau2,
+                       g, beg, items, count, off, cr, cs, clb, cub, write_pass);
+    return hipGetLastError();
 }
 
 hipError_t launch_knn_theta_grid(const float *ancR, int nR, const float *ancS, int nS, int k, const KnnGrid &g,

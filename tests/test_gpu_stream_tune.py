@@ -245,18 +245,19 @@ def test_host_resident_pair_bounds(pj, mid):
 # ---------------------------------------------------------------------------
 # MBB filter: x sweep against all pairs
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", ["sweep", "grid"])
 @pytest.mark.parametrize("tau", [0.0, 5.0, 20.0, 400.0])
-def test_sweep_filter_matches_all_pairs(pj, mid, tau):
+def test_sweep_filter_matches_all_pairs(pj, mid, tau, mode):
     R, S = mid
     out = {}
-    for mode in ("pairs", "sweep"):
-        c = pj.Context(filter_mode=mode)
+    for m in ("pairs", mode):
+        c = pj.Context(filter_mode=m)
         res = c.join_within(c.meshes(R), c.meshes(S), tau)
-        out[mode] = (res, c.stats())
-    a, b = out["pairs"][0], out["sweep"][0]
+        out[m] = (res, c.stats())
+    a, b = out["pairs"][0], out[mode][0]
     assert np.array_equal(a["r"], b["r"]) and np.array_equal(a["s"], b["s"])
-    assert out["pairs"][1]["candidates"] == out["sweep"][1]["candidates"] > 0
-    assert out["pairs"][1]["confirmed_filter"] == out["sweep"][1]["confirmed_filter"]
+    assert out["pairs"][1]["candidates"] == out[mode][1]["candidates"] > 0
+    assert out["pairs"][1]["confirmed_filter"] == out[mode][1]["confirmed_filter"]
 
 
 def test_sweep_filter_ties_and_edges(orc, pj):
@@ -267,16 +268,18 @@ def test_sweep_filter_ties_and_edges(orc, pj):
     ref = orc.join_within(orc.OSet(A), orc.OSet(B), 0.0)
     for tau in (0.0, 0.25, 1.0, 3.0):
         got = {}
-        for mode in ("pairs", "sweep"):
+        for mode in ("pairs", "sweep", "grid"):
             c = pj.Context(filter_mode=mode)
             r = c.join_within(c.meshes(A), c.meshes(B), tau)
             got[mode] = set(zip(r["r"].tolist(), r["s"].tolist()))
-        assert got["pairs"] == got["sweep"], tau
+        assert got["pairs"] == got["sweep"] == got["grid"], tau
         if tau == 0.0:
             assert got["sweep"] == set(zip(ref["r"].tolist(), ref["s"].tolist()))
-    c = pj.Context(filter_mode="sweep")
-    gA, gE = c.meshes(A), c.meshes(A.subset([]))
-    assert len(c.join_within(gA, gE, 1.0)["r"]) == 0
+    for mode in ("sweep", "grid"):
+        c = pj.Context(filter_mode=mode)
+        gA, gE = c.meshes(A), c.meshes(A.subset([]))
+        assert len(c.join_within(gA, gE, 1.0)["r"]) == 0
+        assert len(c.join_within(gE, gA, 1.0)["r"]) == 0
     assert len(c.join_within(gE, gA, 1.0)["r"]) == 0
 
 
