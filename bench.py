@@ -394,16 +394,39 @@ def measure_side(pj, stream, name, R, S, gen_s, timed, workdir, steps):
     gR, gS = ctx.meshes(R), ctx.meshes(S)
     torch.cuda.synchronize()
     ing = time.time() - t0
-    st, wall = timed_steps(ctx, gR, gS, wl["taus"], wl.get("k"), steps, 1, verbose=False)
+    kk = wl.get("k")
+    st, wall = timed_steps(ctx, gR, gS, wl["taus"], kk, steps, 1, verbose=False)
     ms = wall * 1e3 / steps
     pairs = sum(s["pairs"] + s["pairsc"] + s["pairs64"] for s in st)
-    abl = variants(pj, stream, gR, gS, wl["taus"], wl.get("k"), ms, st[-1]["digest"], tune, {}, timed,
-                   ablations=True)
+    # the k-NN workload's plain FP64 schedule would evaluate ~1e13 facet pairs:
+    # not run; its comparisons are the candidate generation (grid against all
+    # pairs) and the pruning rule on host threads against the GPU kernel
+    abl = variants(pj, stream, gR, gS, wl["taus"], kk, ms, st[-1]["digest"], tune, {}, timed,
+                   ablations=kk is None, plain=kk is None)
+    if kk is not None:
+        for name_v, cfg in (("all_pairs_candidates", dict(filter_mode="pairs")),
+                            ("pruning_on_host", dict(knn_prune_host=True))):
+            c2 = pj.Context(stream=stream.cuda_stream, **timed, **tune, **cfg)
+            run_step(c2, gR, gS, (), k=kk)
+            torch.cuda.synchronize()
+            ts = time.time()
+            t = run_step(c2, gR, gS, (), k=kk)
+            torch.cuda.synchronize()
+            s2 = c2.stats()
+            abl[name_v] = {"ms": (time.time() - ts) * 1e3, "filter_ms": s2["t_filter_ms"],
+                           "prune_ms": s2["t_prune_ms"], "results_match": t["digest"] == st[-1]["digest"]}
+            log(f"{name}/{name_v}: {abl[name_v]['ms']:.1f} ms (filter {s2['t_filter_ms']:.1f}, "
+                f"pruning {s2['t_prune_ms']:.1f})")
+        s1 = ctx.stats()
+        abl["timed_run_phases"] = {"filter_ms": s1["t_filter_ms"], "prune_ms": s1["t_prune_ms"],
+                                   "grid_cells": s1["knn_grid_cells"], "candidates": s1["candidates"]}
     out = {"workload": wl["desc"].format(nr=R.n_objects, ns=S.n_objects), "steps": steps, "ms_per_step": ms,
            "facet_pair_evals_per_s": pairs / wall, "ingest_s": ing, "generate_s": gen_s,
-           "results_per_step": st[-1]["results"], "roofline": kernel_roofline(st, name),
-           "speedup_vs_plain": abl["plain_gpu_schedule"]["ms"] / ms, "ablations": abl}
-    log(f"{name}: {ms:.2f} ms per step, {out['speedup_vs_plain']:.0f}x vs plain")
+           "results_per_step": st[-1]["results"], "roofline": kernel_roofline(st, name), "ablations": abl}
+    if "plain_gpu_schedule" in abl:
+        out["speedup_vs_plain"] = abl["plain_gpu_schedule"]["ms"] / ms
+    log(f"{name}: {ms:.2f} ms per step" +
+        (f", {out['speedup_vs_plain']:.0f}x vs plain" if "speedup_vs_plain" in out else ""))
     del gR, gS, ctx
     return out
 
@@ -418,9 +441,9 @@ def main():
     ap.add_argument("--ablations", type=int, default=1, help="one step each without the learned skip / culling")
     ap.add_argument("--capped-steps", type=int, default=5,
                     help="large: timed steps on host-resident sets under the 32 GB cap (0: skip)")
-    ap.add_argument("--side", default="multilod,learned",
+    ap.add_argument("--side", default="multilod,learned,knn",
                     help="large: other workloads measured in the same run (comma list, or 'none')")
-    ap.add_argument("--side-steps", type=int, default=5)
+    ap.add_argument("--side-steps", type=int, default=3)
     ap.add_argument("--voxels", type=int, default=1, help="voxel-pair filtering in the timed configuration")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--n-r", type=int, default=None)

@@ -177,6 +177,16 @@ struct pj_meshes {
                        has_vox ? d_vlab : nullptr, has_vox ? d_lbeg : nullptr, has_vox ? d_bmask : nullptr};
     }
     VoxSide vox() const { return VoxSide{d_vbox, d_vanc, d_vcount}; }
+    // grids over the anchors for the filter (k = 1) and the k-NN candidates,
+    // built on first use and kept with the set (sets are immutable)
+    struct Grid {
+        KnnGrid g;
+        int64_t ncell = 0;
+        int64_t *beg = nullptr;   // [ncell + 1 + tile sums] cell starts
+        int32_t *items = nullptr; // [n] object ids by cell
+    };
+    mutable std::mutex grid_mu;
+    mutable std::map<int, Grid> grids;
     int32_t count(int obj, int lod) const { return h_tcnt[(int64_t)obj * L + lod]; }
 };
 
@@ -268,7 +278,7 @@ struct pj_context {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     DevBuf b_items, b_tiles, b_out, b_out64, b_ctr, b_cand_r, b_cand_s, b_cand_lb, b_cand_ub, b_blk, b_blkoff,
         b_total, b_tmp0, b_tmp1, b_tmp2, b_tmp3, b_coll, b_ovf, b_theta, b_koff, b_klb, b_kub, b_kst0, b_kst1,
-        b_kleft, b_gcell, b_gitems, b_gcnt, b_gfill, b_gbeg, b_vplb, b_vpub, b_vmask, b_vrow,
+        b_kleft, b_gcell, b_gcnt, b_gfill, b_vplb, b_vpub, b_vmask, b_vrow,
         b_sched;
     // voxel filter: per set of the double-buffered chunk pipeline, inputs
     // (pairs, voxel-pair offsets) and outputs (pair bounds, counts, offsets,
@@ -336,7 +346,7 @@ pj_status hipfail(pj_context *ctx, hipError_t e, const char *what)
     } while (0)
 
 // grow-only device buffer with the context's memory cap
-pj_status ensure(pj_context *ctx, DevBuf &b, size_t bytes)
+pj_status ensure(pj_context *ctx, DevBuf &b, size_t bytes, int line = __builtin_LINE())
 {
     if (bytes <= b.cap) return PJ_OK;
     size_t nb = std::max(bytes, b.cap + b.cap / 2);
@@ -348,8 +358,9 @@ pj_status ensure(pj_context *ctx, DevBuf &b, size_t bytes)
         if (after > ctx->cfg.mem_cap_bytes)
             return fail(ctx, PJ_ERR_OUT_OF_MEMORY,
                         "work buffers exceed the configured device memory cap (" + std::to_string(bytes) +
-                            " bytes requested, " + std::to_string(ctx->dev_bytes) + " in use, cap " +
-                            std::to_string(ctx->cfg.mem_cap_bytes) + ")");
+                            " bytes requested at pj_api.cpp line " + std::to_string(line) + ", " +
+                            std::to_string(ctx->dev_bytes) + " in use, cap " + std::to_string(ctx->cfg.mem_cap_bytes) +
+                            ")");
     }
     if (b.p) b.al->free(b.p);
     ctx->dev_bytes -= (int64_t)b.cap;
@@ -523,6 +534,10 @@ void free_meshes(pj_meshes *m)
                     (void *)m->d_xanc, (void *)m->d_xmin, (void *)m->d_vcount, (void *)m->d_vbox, (void *)m->d_vanc,
                     (void *)m->d_vlab, (void *)m->d_lbeg, (void *)m->d_bmask})
         if (p) m->al.free(p);
+    for (auto &kv : m->grids) {
+        if (kv.second.beg) m->al.free(kv.second.beg);
+        if (kv.second.items) m->al.free(kv.second.items);
+    }
     if (m->map) munmap(m->map, m->map_len);
     if (m->fd >= 0) close(m->fd);
     delete m;
@@ -2278,10 +2293,23 @@ pj_status run_f64_view(pj_context *ctx, const MeshDev &Rv, const MeshDev &Sv, Ti
     if (plain) {
         HIPTRY(ctx, launch_refine_f64_plain(a, ni, st));
     } else {
-        PJTRY(ensure(ctx, ctx->b_tiles, nt * sizeof(Tile)));
-        HIPTRY(ctx, hipMemcpyAsync(ctx->b_tiles.p, pl.tiles.data(), nt * sizeof(Tile), hipMemcpyHostToDevice, st));
+        // tiles in chunks that fit what a cap leaves (the item results are
+        // minima, so the chunks simply run one after another)
+        int64_t per = nt;
+        if (ctx->cfg.mem_cap_bytes > 0) {
+            HIPTRY(ctx, hipStreamSynchronize(st));
+            ctx->b_tiles.release();
+            per = std::max<int64_t>(1, std::min<int64_t>(nt, (ctx->cfg.mem_cap_bytes - ctx->dev_bytes - 512) /
+                                                                  (int64_t)sizeof(Tile)));
+        }
+        PJTRY(ensure(ctx, ctx->b_tiles, per * sizeof(Tile)));
         a.tiles = ptr<Tile>(ctx->b_tiles);
-        HIPTRY(ctx, launch_refine_f64_tiles(a, nt, st));
+        for (int64_t t0 = 0; t0 < nt; t0 += per) {
+            const int64_t n = std::min<int64_t>(per, nt - t0);
+            HIPTRY(ctx, hipMemcpyAsync(ctx->b_tiles.p, pl.tiles.data() + t0, n * sizeof(Tile), hipMemcpyHostToDevice,
+                                       st));
+            HIPTRY(ctx, launch_refine_f64_tiles(a, n, st));
+        }
     }
     HIPTRY(ctx, hipEventRecord(ctx->ev1, st));
     HIPTRY(ctx, hipMemcpyAsync(out.data(), a.out, ni * sizeof(ItemOut64), hipMemcpyDeviceToHost, st));
@@ -2569,31 +2597,67 @@ pj_status mbb_filter_sweep(pj_context *ctx, const pj_meshes *R, const pj_meshes 
 
 KnnGrid knn_grid_params(const pj_meshes *S, int k);
 
+// The set's grid for k (k = 1: the within filter), built on first use on
+// this context's stream and kept with the set; later joins, on any context,
+// reuse it.
+pj_status set_grid(pj_context *ctx, const pj_meshes *S, int k, const pj_meshes::Grid **out)
+{
+    std::lock_guard<std::mutex> lock(S->grid_mu);
+    auto it = S->grids.find(k);
+    if (it != S->grids.end()) {
+        *out = &it->second;
+        return PJ_OK;
+    }
+    pj_meshes::Grid G;
+    G.g = knn_grid_params(S, k);
+    G.ncell = (int64_t)G.g.gx * G.g.gy * G.g.gz;
+    const int nS = S->n;
+    hipStream_t st = ctx->stream;
+    hipError_t e;
+    if ((e = S->al.alloc((void **)&G.beg, (size_t)(G.ncell + 3 + G.ncell / 4096) * 8)) != hipSuccess)
+        return hipfail(ctx, e, "grid cells");
+    if ((e = S->al.alloc((void **)&G.items, (size_t)std::max(nS, 1) * 4)) != hipSuccess) {
+        S->al.free(G.beg);
+        return hipfail(ctx, e, "grid items");
+    }
+    pj_status ps = ensure(ctx, ctx->b_gcell, (size_t)nS * 4);
+    if (ps == PJ_OK) ps = ensure(ctx, ctx->b_gcnt, (size_t)G.ncell * 4);
+    if (ps == PJ_OK) ps = ensure(ctx, ctx->b_gfill, (size_t)G.ncell * 4);
+    if (ps == PJ_OK) ps = ensure(ctx, ctx->b_total, 16);
+    if (ps == PJ_OK) {
+        e = launch_grid_build(S->d_anchor, nS, G.g, ptr<int32_t>(ctx->b_gcell), ptr<int32_t>(ctx->b_gcnt), G.beg,
+                              ptr<int64_t>(ctx->b_total) + 1, ptr<int32_t>(ctx->b_gfill), G.items, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) ps = hipfail(ctx, e, "grid build");
+    }
+    if (ps != PJ_OK) {
+        S->al.free(G.beg);
+        S->al.free(G.items);
+        return ps;
+    }
+    *out = &S->grids.emplace(k, G).first->second;
+    return PJ_OK;
+}
+
 // Grid filter: the all-pairs test and bounds, applied only to the S objects
 // binned (by anchor) in the grid cells each r's box can reach; candidates in
 // (r, s) order.
 pj_status mbb_filter_grid(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, float tau2, std::vector<Cand> &cand)
 {
     hipStream_t st = ctx->stream;
-    const int nR = R->n, nS = S->n;
-    const KnnGrid g = knn_grid_params(S, 1);
-    const int64_t ncell = (int64_t)g.gx * g.gy * g.gz;
-    PJTRY(ensure(ctx, ctx->b_gcell, (size_t)nS * 4));
-    PJTRY(ensure(ctx, ctx->b_gitems, (size_t)nS * 4));
-    PJTRY(ensure(ctx, ctx->b_gcnt, (size_t)ncell * 4));
-    PJTRY(ensure(ctx, ctx->b_gfill, (size_t)ncell * 4));
-    PJTRY(ensure(ctx, ctx->b_gbeg, (size_t)(ncell + 3 + ncell / 4096) * 8));
+    const int nR = R->n;
+    const pj_meshes::Grid *G = nullptr;
+    PJTRY(set_grid(ctx, S, 1, &G));
+    const KnnGrid g = G->g;
+    const int64_t ncell = G->ncell;
     PJTRY(ensure(ctx, ctx->b_total, 16));
-    HIPTRY(ctx, launch_grid_build(S->d_anchor, nS, g, ptr<int32_t>(ctx->b_gcell), ptr<int32_t>(ctx->b_gcnt),
-                                  ptr<int64_t>(ctx->b_gbeg), ptr<int64_t>(ctx->b_total) + 1, ptr<int32_t>(ctx->b_gfill),
-                                  ptr<int32_t>(ctx->b_gitems), st));
     PJTRY(ensure(ctx, ctx->b_blk, (size_t)nR * 4));
     PJTRY(ensure(ctx, ctx->b_blkoff, (size_t)(nR + 3 + nR / 4096) * 8));
     // reach: the largest gap the squared test can keep, rounded up
     const float reach = up_float(std::sqrt((double)tau2) * (1.0 + std::ldexp(1.0, -20)));
-    HIPTRY(ctx, launch_filter_grid(R->d_box, R->d_anchor, nR, S->d_box, S->d_anchor, reach, tau2, g,
-                                   ptr<int64_t>(ctx->b_gbeg), ptr<int32_t>(ctx->b_gitems), ptr<int32_t>(ctx->b_blk),
-                                   nullptr, nullptr, nullptr, nullptr, nullptr, 0, st));
+    HIPTRY(ctx, launch_filter_grid(R->d_box, R->d_anchor, nR, S->d_box, S->d_anchor, reach, tau2, g, G->beg,
+                                   G->items, ptr<int32_t>(ctx->b_blk), nullptr, nullptr, nullptr, nullptr, nullptr, 0,
+                                   st));
     HIPTRY(ctx, launch_scan_large(ptr<int32_t>(ctx->b_blk), ptr<int64_t>(ctx->b_blkoff), ptr<int64_t>(ctx->b_total), nR,
                                   st));
     int64_t total = 0;
@@ -2604,9 +2668,8 @@ pj_status mbb_filter_grid(pj_context *ctx, const pj_meshes *R, const pj_meshes *
     PJTRY(ensure(ctx, ctx->b_cand_r, total * 16));
     int32_t *d_cr = ptr<int32_t>(ctx->b_cand_r), *d_cs = d_cr + total;
     float *d_lb = reinterpret_cast<float *>(d_cs + total), *d_ub = d_lb + total;
-    HIPTRY(ctx, launch_filter_grid(R->d_box, R->d_anchor, nR, S->d_box, S->d_anchor, reach, tau2, g,
-                                   ptr<int64_t>(ctx->b_gbeg), ptr<int32_t>(ctx->b_gitems), nullptr,
-                                   ptr<int64_t>(ctx->b_blkoff), d_cr, d_cs, d_lb, d_ub, 1, st));
+    HIPTRY(ctx, launch_filter_grid(R->d_box, R->d_anchor, nR, S->d_box, S->d_anchor, reach, tau2, g, G->beg,
+                                   G->items, nullptr, ptr<int64_t>(ctx->b_blkoff), d_cr, d_cs, d_lb, d_ub, 1, st));
     return download_cands(ctx, total, cand);
 }
 
@@ -3313,23 +3376,16 @@ extern "C" pj_status pj_join_knn(pj_context *ctx, const pj_meshes *R, const pj_m
     // (filter_mode 1, or k above what the grid kernel keeps in registers)
     const bool use_grid = ctx->cfg.filter_mode != 1 && k <= kGridMaxK;
     KnnGrid grid;
+    const pj_meshes::Grid *G = nullptr;
     if (use_grid) {
-        grid = knn_grid_params(S, k);
-        const int64_t ncell = (int64_t)grid.gx * grid.gy * grid.gz;
-        PJTRY(ensure(ctx, ctx->b_gcell, (size_t)nS * 4));
-        PJTRY(ensure(ctx, ctx->b_gitems, (size_t)nS * 4));
-        PJTRY(ensure(ctx, ctx->b_gcnt, (size_t)ncell * 4));
-        PJTRY(ensure(ctx, ctx->b_gfill, (size_t)ncell * 4));
-        PJTRY(ensure(ctx, ctx->b_gbeg, (size_t)(ncell + 3 + ncell / 4096) * 8));
-        HIPTRY(ctx, launch_grid_build(S->d_anchor, nS, grid, ptr<int32_t>(ctx->b_gcell), ptr<int32_t>(ctx->b_gcnt),
-                                      ptr<int64_t>(ctx->b_gbeg), ptr<int64_t>(ctx->b_total) + 1,
-                                      ptr<int32_t>(ctx->b_gfill), ptr<int32_t>(ctx->b_gitems), st));
-        HIPTRY(ctx, launch_knn_theta_grid(R->d_anchor, nR, S->d_anchor, nS, k, grid, ptr<int64_t>(ctx->b_gbeg),
-                                          ptr<int32_t>(ctx->b_gitems), ptr<float>(ctx->b_theta), st));
+        PJTRY(set_grid(ctx, S, k, &G));
+        grid = G->g;
+        HIPTRY(ctx, launch_knn_theta_grid(R->d_anchor, nR, S->d_anchor, nS, k, grid, G->beg, G->items,
+                                          ptr<float>(ctx->b_theta), st));
         HIPTRY(ctx, launch_knn_cand_grid(R->d_box, R->d_anchor, nR, S->d_box, S->d_anchor, nS, ptr<float>(ctx->b_theta),
-                                         grid, ptr<int64_t>(ctx->b_gbeg), ptr<int32_t>(ctx->b_gitems),
-                                         ptr<int32_t>(ctx->b_blk), nullptr, nullptr, nullptr, nullptr, 0, st));
-        ctx->stats.knn_grid_cells = ncell;
+                                         grid, G->beg, G->items, ptr<int32_t>(ctx->b_blk), nullptr, nullptr, nullptr,
+                                         nullptr, 0, st));
+        ctx->stats.knn_grid_cells = G->ncell;
     } else {
         HIPTRY(ctx, launch_knn_theta(R->d_anchor, nR, S->d_anchor, nS, k, ptr<float>(ctx->b_theta), st));
         HIPTRY(ctx, launch_knn_cand(R->d_box, R->d_anchor, nR, S->d_box, S->d_anchor, nS, ptr<float>(ctx->b_theta),
@@ -3347,8 +3403,8 @@ extern "C" pj_status pj_join_knn(pj_context *ctx, const pj_meshes *R, const pj_m
     PJTRY(ensure(ctx, ctx->b_cand_ub, std::max<int64_t>(total, 1) * 4));
     if (use_grid)
         HIPTRY(ctx, launch_knn_cand_grid(R->d_box, R->d_anchor, nR, S->d_box, S->d_anchor, nS,
-                                         ptr<float>(ctx->b_theta), grid, ptr<int64_t>(ctx->b_gbeg),
-                                         ptr<int32_t>(ctx->b_gitems), nullptr, ptr<int64_t>(ctx->b_koff),
+                                         ptr<float>(ctx->b_theta), grid, G->beg, G->items, nullptr,
+                                         ptr<int64_t>(ctx->b_koff),
                                          ptr<int32_t>(ctx->b_cand_s), ptr<float>(ctx->b_cand_lb),
                                          ptr<float>(ctx->b_cand_ub), 1, st));
     else

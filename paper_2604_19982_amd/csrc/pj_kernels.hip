@@ -1111,10 +1111,15 @@ __device__ __forceinline__ void refine_tiles(const RefineArgs &a, float4 *sh, fl
     // workgroup's own so that the helpers spread over the tiles in progress.
     const int nslot = gridDim.x;
     if (ntiles <= nslot) {
+        // each helper starts at its own tile (wrapping around), so that they
+        // do not all queue on the cursors of the first tiles
+        const int start = (int)(blockIdx.x % (unsigned)max(ntiles, 1));
         for (int h = 0; h < ntiles;) {
-            const int tt = h + (int)threadIdx.x;
+            const int hw = h + (int)threadIdx.x;
+            int tt = hw + start;
+            if (tt >= ntiles) tt -= ntiles;
             int c = -1;
-            if (tt < ntiles) {
+            if (hw < ntiles) {
                 const Tile x = a.tiles[tt];
                 const int nb = (x.a1 - x.a0 + 64 * P - 1) / (64 * P);
                 if (nb > 1 && __hip_atomic_load(a.tile_cur + tt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < nb) c = tt;
@@ -1484,9 +1489,9 @@ hipError_t launch_knn_cand(const float *boxR, const float *ancR, int nR, const f
 //           to every cell not visited yet (shrunk by one cell and an error
 //           margin, so an anchor binned one cell off is still covered);
 //   cand:   one thread per r tests the S objects of the cells its box can
-//           reach (box widened by theta_r, the widest anchor-to-box extent of
-//           S per axis and one cell), count then write, then sorts its list
-//           by s (the order of the all-pairs kernel).
+//           reach (box widened by theta_r and the widest anchor-to-box extent
+//           of S per axis), count then write, then sorts its list by s (the
+//           order of the all-pairs kernel).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int grid_coord(float x, float o, float inv_c, int g)
 {
@@ -1628,7 +1633,8 @@ __global__ __launch_bounds__(256) void k_knn_cand_grid(const float *boxR, const 
             hi[a] = gd[a] - 1;
             continue;
         }
-        const float reach = th + w[a] + g.c;
+        // (the same monotone cell map as the binning; see k_filter_grid)
+        const float reach = th + w[a] + 0x1p-18f * g.M;
         lo[a] = grid_coord(br[a] - reach, o[a], g.inv_c, gd[a]);
         hi[a] = grid_coord(br[3 + a] + reach, o[a], g.inv_c, gd[a]);
     }
@@ -1690,8 +1696,12 @@ __global__ __launch_bounds__(256) void k_filter_grid(const float *boxR, const fl
     const float o[3] = {g.ox, g.oy, g.oz}, w[3] = {g.wx, g.wy, g.wz};
     const int gd[3] = {g.gx, g.gy, g.gz};
     int lo[3], hi[3];
+    // binning and this range use the same monotone float map from a
+    // coordinate to its cell, so an anchor inside the widened box is inside
+    // the cell range; the small margin covers the rounding of the widening
+    const float margin = 0x1p-18f * g.M;
     for (int a = 0; a < 3; ++a) {
-        const float reach = tau + w[a] + g.c;
+        const float reach = tau + w[a] + margin;
         lo[a] = grid_coord(b[a] - reach, o[a], g.inv_c, gd[a]);
         hi[a] = grid_coord(b[3 + a] + reach, o[a], g.inv_c, gd[a]);
     }
