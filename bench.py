@@ -445,6 +445,9 @@ def main():
                     help="large: other workloads measured in the same run (comma list, or 'none')")
     ap.add_argument("--side-steps", type=int, default=3)
     ap.add_argument("--voxels", type=int, default=1, help="voxel-pair filtering in the timed configuration")
+    ap.add_argument("--storage-dir", default="none",
+                    help="large: also time the capped join with the sets' facet data in files here (out-of-core "
+                         "residency); 'auto' uses the temp directory when it has room, 'none' skips it")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--n-r", type=int, default=None)
     ap.add_argument("--n-s", type=int, default=None)
@@ -588,6 +591,34 @@ def main():
         log(f"capped host-resident: {cms:.2f} ms per step")
         del hR, hS
         cctx.close()
+        # out of core: the same capped join with the facet data in files
+        sdir = args.storage_dir
+        if sdir == "auto":
+            import shutil
+            sdir = tempfile.gettempdir()
+            need = 2 * (R.nbytes() + S.nbytes())
+            if shutil.disk_usage(sdir).free < need:
+                log(f"out-of-core run skipped: {shutil.disk_usage(sdir).free / 1e9:.0f} GB free in {sdir}, "
+                    f"{need / 1e9:.0f} GB wanted")
+                sdir = "none"
+        if sdir != "none":
+            fdir = tempfile.mkdtemp(prefix="pj_facets_", dir=sdir)
+            fctx = pj.Context(stream=stream.cuda_stream, **timed, **tune,
+                              **dict(wl["capped"], host_resident=False, stage_sets=3), storage_dir=fdir)
+            t0 = time.time()
+            fR, fS = fctx.meshes(R), fctx.meshes(S)
+            torch.cuda.synchronize()
+            ing_f = time.time() - t0
+            fst, fwall = timed_steps(fctx, fR, fS, taus, kk, max(1, args.capped_steps), 1, verbose=False)
+            fms = fwall * 1e3 / max(1, args.capped_steps)
+            out["config"]["capped_file_resident"] = {
+                "storage": "files under the temp directory, written once at ingest and read back through a "
+                           "mapping (pages dropped from the page cache after writing)",
+                "ms_per_step": fms, "ingest_s": ing_f, "results_match": fst[-1]["digest"] == digest,
+                "prep_ms_per_step": fst[-1]["prep_ms"], "staged_bytes_per_step": fst[-1]["staged"]}
+            log(f"capped file-resident: {fms:.2f} ms per step, ingest {ing_f:.1f} s")
+            del fR, fS
+            fctx.close()
     if side_sets:
         side = {}
         for name, (sR, sS, sg) in list(side_sets.items()):
