@@ -1855,9 +1855,13 @@ __global__ __launch_bounds__(256) void k_vp_count(const int32_t *cr, const int32
 {
     __shared__ int sh[4];
     const int p = blockIdx.x;
+    const float olb = op_lb[p], oub = op_ub[p];
+    if (tau >= 0.0f && (oub <= tau || olb > tau)) {  // decided by its bounds: nothing kept
+        if (threadIdx.x == 0) count[p] = 0;
+        return;
+    }
     const int N = R.vcount[cr[p]] * S.vcount[cs[p]];
     const int64_t off = vp_off[p];
-    const float olb = op_lb[p], oub = op_ub[p];
     int c = 0;
     for (int t = threadIdx.x; t < N; t += 256) c += vp_keep(vp_lb[off + t], olb, oub, tau) ? 1 : 0;
     for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
@@ -1874,10 +1878,11 @@ __global__ __launch_bounds__(256) void k_vp_write(const int32_t *cr, const int32
 {
     __shared__ int sh[256];
     const int p = blockIdx.x;
+    const float olb = op_lb[p], oub = op_ub[p];
+    if (tau >= 0.0f && (oub <= tau || olb > tau)) return;  // nothing kept (see k_vp_count)
     const int ns = S.vcount[cs[p]];
     const int N = R.vcount[cr[p]] * ns;
     const int64_t off = vp_off[p];
-    const float olb = op_lb[p], oub = op_ub[p];
     // each thread owns a contiguous run of the flattened voxel pairs, so the
     // output keeps their order
     const int per = (N + 255) / 256;
