@@ -126,19 +126,45 @@ def train_model(pj, mg, stream, workdir, **cfg):
     return model, loss, os.path.getsize(log) // 72
 
 
-def one_step(pj, stream, gR, gS, taus, k=None, warmup=1, **cfg):
+_ROCTX = []
+
+
+def roctx():
+    """The roctx marker library (ranges seen by rocprofv3 --marker-trace), or
+    None where it is not installed."""
+    if not _ROCTX:
+        import ctypes
+        lib = None
+        for name in ("librocprofiler-sdk-roctx.so.1", "libroctx64.so.4"):
+            try:
+                lib = ctypes.CDLL(name)
+                lib.roctxRangePushA.argtypes = [ctypes.c_char_p]
+                break
+            except (OSError, AttributeError):
+                lib = None
+        _ROCTX.append(lib)
+    return _ROCTX[0]
+
+
+def one_step(pj, stream, gR, gS, taus, k=None, warmup=1, mark=None, **cfg):
     """One timed step on another context over the already ingested mesh sets
     (a mesh set may be shared by contexts on its device), after `warmup`
-    untimed ones (first-use costs: buffer growth, graph capture, tuning)."""
+    untimed ones (first-use costs: buffer growth, graph capture, tuning).
+    `mark` names a roctx range around the timed step."""
     import torch
     c = pj.Context(stream=stream.cuda_stream, **cfg)
     for _ in range(warmup):
         run_step(c, gR, gS, taus, k=k)
     torch.cuda.synchronize()
+    rt = roctx() if mark else None
+    if rt:
+        rt.roctxRangePushA(mark.encode())
     ts = time.time()
     tot = run_step(c, gR, gS, taus, k=k)
     torch.cuda.synchronize()
     tot["ms"] = (time.time() - ts) * 1e3
+    if rt:
+        rt.roctxRangePop()
     return tot
 
 
@@ -574,7 +600,8 @@ def main():
         # computes)
         overlap = {}
         for sets in (1, 2, 3):
-            t = one_step(pj, stream, hR, hS, taus, k=kk, **dict(wl["capped"], stage_sets=sets), **timed, **tune)
+            t = one_step(pj, stream, hR, hS, taus, k=kk, mark=f"capped stage_sets={sets}",
+                         **dict(wl["capped"], stage_sets=sets), **timed, **tune)
             overlap[f"stage_sets_{sets}"] = {"ms": t["ms"], "refine_ms": t["refine_ms"], "kernel_ms": t["kms"],
                                              "prep_ms": t["prep_ms"], "chunks": t["chunks"],
                                              "staged_bytes": t["staged"], "peak_device_bytes": t["peak"],

@@ -245,6 +245,7 @@ typedef struct {
     double planned_sqrt;        /* sum over the (pair, LoD) items visited of sqrt(n_r * n_s): the work measure
                                    the learned first LoD minimises (with box culling, the facet pairs evaluated
                                    grow like it); fixed by the schedule's decisions */
+    int64_t collect_regrow;     /* collect passes run again with a list sized to what the first offered */
 } pj_stats;
 
 pj_status pj_get_stats(const pj_context *ctx, pj_stats *out);

@@ -81,7 +81,7 @@ class Stats(ctypes.Structure):
                 ("knn_grid_cells", ctypes.c_int64), ("t_prune_ms", ctypes.c_double), ("t_prep_ms", ctypes.c_double),
                 ("vp_pairs", ctypes.c_int64), ("vp_kept", ctypes.c_int64), ("vp_chunks", ctypes.c_int64),
                 ("voxel_decided", ctypes.c_int64), ("t_voxel_ms", ctypes.c_double),
-                ("planned_sqrt", ctypes.c_double)]
+                ("planned_sqrt", ctypes.c_double), ("collect_regrow", ctypes.c_int64)]
 
     def to_dict(self):
         d = {}

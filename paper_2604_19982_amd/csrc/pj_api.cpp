@@ -267,6 +267,7 @@ struct HostPool {
 
 struct pj_context {
     DevAlloc alloc;  // declared first: the work buffers below are freed through it
+    double coll_per_item = 0.0;  // pairs the last collect pass offered per item (sizes the next list)
     std::unique_ptr<HostPool> pool;  // created on first use
     pj_config cfg;
     hipStream_t stream = nullptr;
@@ -279,7 +280,8 @@ struct pj_context {
     DevBuf b_items, b_tiles, b_out, b_out64, b_ctr, b_cand_r, b_cand_s, b_cand_lb, b_cand_ub, b_blk, b_blkoff,
         b_total, b_tmp0, b_tmp1, b_tmp2, b_tmp3, b_coll, b_ovf, b_theta, b_koff, b_klb, b_kub, b_kst0, b_kst1,
         b_kleft, b_gcell, b_gcnt, b_gfill, b_vplb, b_vpub, b_vmask, b_vrow,
-        b_sched;
+        b_sched, b_model;
+    const void *model_dev = nullptr;  // b_model's address when it received the loaded model (weights, feature scales)
     // voxel filter: per set of the double-buffered chunk pipeline, inputs
     // (pairs, voxel-pair offsets) and outputs (pair bounds, counts, offsets,
     // survivors), on the device and pinned
@@ -293,6 +295,7 @@ struct pj_context {
     DevBuf sb_items[kMaxSets], sb_tiles[kMaxSets], sb_out[kMaxSets], sb_ctr[kMaxSets], sb_stage[kMaxSets];
     PinBuf pin_items[kMaxSets], pin_tiles[kMaxSets], pin_out[kMaxSets], pin_ctr[kMaxSets], pin_stage[kMaxSets];
     PinBuf pin_cand;  // the filter's candidate count and arrays on their way to the host
+    PinBuf pin_start; // the learned skip's inputs up, first LoDs down
     PinBuf pin_vin[2];
     hipEvent_t ev_vcomp[2] = {};
     const unsigned long long *vmask = nullptr;  // surviving voxel pairs of the join's candidates (device)
@@ -497,6 +500,7 @@ extern "C" pj_status pj_context_destroy(pj_context *ctx)
             if (e) (void)hipEventDestroy(e);
     }
     if (ctx->pin_cand.p) (void)hipHostFree(ctx->pin_cand.p);
+    if (ctx->pin_start.p) (void)hipHostFree(ctx->pin_start.p);
     for (int b = 0; b < 2; ++b) {
         if (ctx->pin_vin[b].p) (void)hipHostFree(ctx->pin_vin[b].p);
         if (ctx->ev_vcomp[b]) (void)hipEventDestroy(ctx->ev_vcomp[b]);
@@ -1107,6 +1111,8 @@ pj_status ingest_host(pj_context *ctx, const pj_mesh_desc *d, pj_meshes *m)
     if ((e = upload(m->al, &m->d_box, m->h_box.data(), 6 * n, st)) != hipSuccess) return hipfail(ctx, e, "boxes");
     if ((e = upload(m->al, &m->d_anchor, m->h_anchor.data(), 3 * n, st)) != hipSuccess) return hipfail(ctx, e, "anchors");
     if ((e = upload(m->al, &m->d_lodmax, m->h_lodmax.data(), n * L, st)) != hipSuccess) return hipfail(ctx, e, "lodmax");
+    // facet counts stay on the device too (features of the learned skip)
+    if ((e = upload(m->al, &m->d_tcnt, m->h_tcnt.data(), n * L, st)) != hipSuccess) return hipfail(ctx, e, "tri_count");
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hipfail(ctx, e, "ingest sync");
     if (ctx->cfg.voxels) {
         voxelize(ctx, d, m);
@@ -2367,20 +2373,28 @@ pj_status exact_finest_view(pj_context *ctx, const MeshDev &Rv, const MeshDev &S
     const int ni = (int)pl.items.size(), nt = (int)pl.tiles.size();
     if (ni == 0) return PJ_OK;
     const int cgrid = (int)std::min<int64_t>(nt, (int64_t)ctx->num_cu * ctx->cur.wpc);
-    // room for 4096 kept pairs per item (thresholds from a coarse LoD's
-    // bound keep more than those from the finest FP32 minimum), at most 2^28
-    int64_t cap = std::min<int64_t>(std::max<int64_t>(1 << 20, 4096 * (int64_t)ni), int64_t(1) << 28);
+    // The list is sized from what the last collect pass offered per item
+    // (256 before the first), with a quarter more, at least 2^20 pairs and at
+    // most 2^28.  A pass that offers more than the list holds is run once
+    // more with room for what it offered (the thresholds tighten as minima
+    // are published, so the count can differ a little between runs); items
+    // that overflow again are recomputed in full FP64 by the caller.
+    const int64_t kMaxColl = int64_t(1) << 28;
+    auto want = [&](double n) {
+        return std::min<int64_t>(std::max<int64_t>(int64_t(1) << 20, (int64_t)(1.25 * n) + 65536), kMaxColl);
+    };
+    int64_t cap = want((ctx->coll_per_item > 0.0 ? ctx->coll_per_item : 256.0) * ni);
+    int64_t room = kMaxColl;
     if (ctx->cfg.mem_cap_bytes > 0) {
-        // the collect list takes what the cap leaves; items that overflow it
-        // are recomputed in full FP64 below
+        // the collect list takes what the cap leaves
         HIPTRY(ctx, hipStreamSynchronize(st));
         for (DevBuf *x : {&ctx->b_items, &ctx->b_tiles, &ctx->b_out, &ctx->b_out64, &ctx->b_ovf, &ctx->b_coll,
                           &ctx->b_ctr})
             x->release();
         const int64_t fixed = (int64_t)(ni * (sizeof(Item) + sizeof(ItemOut) + sizeof(ItemOut64) + sizeof(int32_t)) +
                                         nt * (sizeof(Tile) + 4) + 64 + 4 * cgrid + 7 * 256);
-        const int64_t room = ctx->cfg.mem_cap_bytes - ctx->dev_bytes - fixed;
-        cap = std::min<int64_t>(cap, room / (int64_t)sizeof(PairRef));
+        room = std::min<int64_t>(room, (ctx->cfg.mem_cap_bytes - ctx->dev_bytes - fixed) / (int64_t)sizeof(PairRef));
+        cap = std::min<int64_t>(cap, room);
         if (cap < 256) return fail(ctx, PJ_ERR_OUT_OF_MEMORY, "the memory cap leaves no room for the FP64 recheck");
     }
     PJTRY(ensure(ctx, ctx->b_items, ni * sizeof(Item)));
@@ -2388,53 +2402,65 @@ pj_status exact_finest_view(pj_context *ctx, const MeshDev &Rv, const MeshDev &S
     PJTRY(ensure(ctx, ctx->b_out, ni * sizeof(ItemOut)));
     PJTRY(ensure(ctx, ctx->b_out64, ni * sizeof(ItemOut64)));
     PJTRY(ensure(ctx, ctx->b_ovf, ni * sizeof(int32_t)));
-    PJTRY(ensure(ctx, ctx->b_coll, cap * sizeof(PairRef)));
     PJTRY(ensure(ctx, ctx->b_ctr, 64 + 4 * (cgrid + nt)));
     HIPTRY(ctx, hipMemcpyAsync(ctx->b_items.p, pl.items.data(), ni * sizeof(Item), hipMemcpyHostToDevice, st));
     HIPTRY(ctx, hipMemcpyAsync(ctx->b_tiles.p, pl.tiles.data(), nt * sizeof(Tile), hipMemcpyHostToDevice, st));
     int32_t *ctr = ptr<int32_t>(ctx->b_ctr);
-    int32_t host_ctr[16] = {0, nt};
-    host_ctr[6] = ni;
-    HIPTRY(ctx, hipMemcpyAsync(ctr, host_ctr, sizeof(host_ctr), hipMemcpyHostToDevice, st));
-    HIPTRY(ctx, hipMemsetAsync(ctx->b_ovf.p, 0, ni * sizeof(int32_t), st));
-    HIPTRY(ctx, launch_init_round(ptr<ItemOut>(ctx->b_out), ctr, ctr + 16, cgrid, ctr + 16 + cgrid, st));
-    HIPTRY(ctx, launch_init_out64(ptr<ItemOut64>(ctx->b_out64), ni, st));
+    int32_t host_ctr[16];
     RefineArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.R = Rv;
-    a.S = Sv;
-    a.items = ptr<Item>(ctx->b_items);
-    a.tiles = ptr<Tile>(ctx->b_tiles);
-    a.ntiles = ctr + 1;
-    a.tile_next = ctr + 10;
-    a.wave_slot = ctr + 16;
-    a.tile_cur = ctr + 16 + cgrid;
-    a.collected_n = reinterpret_cast<unsigned long long *>(ctr + 8);
-    a.out = ptr<ItemOut>(ctx->b_out);
-    a.pairs_done = reinterpret_cast<unsigned long long *>(ctr + 2);
-    a.chunks_culled = reinterpret_cast<unsigned long long *>(ctr + 4);
-    a.tau = -1.0f;
-    a.cull = ctx->cfg.tile_cull ? 1 : 0;
-    a.collect_cap = cap;
-    a.collected = ptr<PairRef>(ctx->b_coll);
-    a.overflow = ptr<int32_t>(ctx->b_ovf);
-    a.vmask = ctx->vmask;
-    a.vrow = ctx->vrow;
-    HIPTRY(ctx, hipEventRecord(ctx->ev0, st));
-    HIPTRY(ctx, launch_collect_f32(a, cgrid, st));
-    HIPTRY(ctx, hipEventRecord(ctx->ev1, st));
-    HIPTRY(ctx, hipMemcpyAsync(host_ctr, ctr, sizeof(host_ctr), hipMemcpyDeviceToHost, st));
-    HIPTRY(ctx, hipStreamSynchronize(st));
-    float ms = 0;
-    HIPTRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-    ctx->stats.collect_kernel_ms += ms;
-    ctx->stats.collect_launches += 1;
-    unsigned long long pairs, offered;
-    std::memcpy(&pairs, host_ctr + 2, 8);
-    std::memcpy(&offered, host_ctr + 8, 8);
-    ctx->stats.collect_pairs += (int64_t)pairs;
+    unsigned long long offered = 0;
+    for (int attempt = 0;; ++attempt) {
+        PJTRY(ensure(ctx, ctx->b_coll, cap * sizeof(PairRef)));
+        std::memset(host_ctr, 0, sizeof(host_ctr));
+        host_ctr[1] = nt;
+        host_ctr[6] = ni;
+        HIPTRY(ctx, hipMemcpyAsync(ctr, host_ctr, sizeof(host_ctr), hipMemcpyHostToDevice, st));
+        HIPTRY(ctx, hipMemsetAsync(ctx->b_ovf.p, 0, ni * sizeof(int32_t), st));
+        HIPTRY(ctx, launch_init_round(ptr<ItemOut>(ctx->b_out), ctr, ctr + 16, cgrid, ctr + 16 + cgrid, st));
+        HIPTRY(ctx, launch_init_out64(ptr<ItemOut64>(ctx->b_out64), ni, st));
+        std::memset(&a, 0, sizeof(a));
+        a.R = Rv;
+        a.S = Sv;
+        a.items = ptr<Item>(ctx->b_items);
+        a.tiles = ptr<Tile>(ctx->b_tiles);
+        a.ntiles = ctr + 1;
+        a.tile_next = ctr + 10;
+        a.wave_slot = ctr + 16;
+        a.tile_cur = ctr + 16 + cgrid;
+        a.collected_n = reinterpret_cast<unsigned long long *>(ctr + 8);
+        a.out = ptr<ItemOut>(ctx->b_out);
+        a.pairs_done = reinterpret_cast<unsigned long long *>(ctr + 2);
+        a.chunks_culled = reinterpret_cast<unsigned long long *>(ctr + 4);
+        a.tau = -1.0f;
+        a.cull = ctx->cfg.tile_cull ? 1 : 0;
+        a.collect_cap = cap;
+        a.collected = ptr<PairRef>(ctx->b_coll);
+        a.overflow = ptr<int32_t>(ctx->b_ovf);
+        a.vmask = ctx->vmask;
+        a.vrow = ctx->vrow;
+        HIPTRY(ctx, hipEventRecord(ctx->ev0, st));
+        HIPTRY(ctx, launch_collect_f32(a, cgrid, st));
+        HIPTRY(ctx, hipEventRecord(ctx->ev1, st));
+        HIPTRY(ctx, hipMemcpyAsync(host_ctr, ctr, sizeof(host_ctr), hipMemcpyDeviceToHost, st));
+        HIPTRY(ctx, hipStreamSynchronize(st));
+        float ms = 0;
+        HIPTRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        ctx->stats.collect_kernel_ms += ms;
+        ctx->stats.collect_launches += 1;
+        unsigned long long pairs;
+        std::memcpy(&pairs, host_ctr + 2, 8);
+        std::memcpy(&offered, host_ctr + 8, 8);
+        ctx->stats.collect_pairs += (int64_t)pairs;
+        ctx->coll_per_item = (double)offered / ni;
+        if (offered <= (unsigned long long)cap || attempt > 0) break;
+        const int64_t grow = std::min<int64_t>(want((double)offered), room);
+        if (grow <= cap) break;
+        cap = grow;
+        ctx->stats.collect_regrow++;
+    }
     const int64_t ncoll = (int64_t)std::min<unsigned long long>(offered, (unsigned long long)cap);
     ctx->stats.collected_pairs += (int64_t)offered;
+    float ms = 0;
     HIPTRY(ctx, hipEventRecord(ctx->ev0, st));
     HIPTRY(ctx, launch_pairs_f64(Rv, Sv, a.items, a.collected, ncoll, ptr<ItemOut64>(ctx->b_out64), st));
     HIPTRY(ctx, hipEventRecord(ctx->ev1, st));
@@ -2905,6 +2931,7 @@ bool load_model(pj_context *ctx, const char *path)
     std::memcpy(ctx->feat_mean, h.mean, sizeof(h.mean));
     std::memcpy(ctx->feat_std, h.stdv, sizeof(h.stdv));
     ctx->has_model = true;
+    ctx->model_dev = nullptr;
     return true;
 }
 
@@ -2920,30 +2947,33 @@ pj_status learned_start(pj_context *ctx, const pj_meshes *R, const pj_meshes *S,
     const int n = (int)idx.size();
     if (n == 0) return PJ_OK;
     hipStream_t st = ctx->stream;
-    std::vector<float> x((size_t)n * MLP_IN), cost((size_t)n * MLP_OUT);
-    // features on the host workers (each candidate writes its own rows)
-    host_for(ctx, n, [&](int64_t q) {
+    // the features, the network and the choice run on the GPU: only the
+    // pairs' ids and bounds go up and the first LoDs come back
+    PJTRY(ensure_pinned(ctx, ctx->pin_start, (size_t)n * sizeof(StartIn)));
+    StartIn *hin = (StartIn *)ctx->pin_start.p;
+    for (int q = 0; q < n; ++q) {
         const Cand &c = cand[idx[q]];
-        float f[MLP_IN];
-        pair_features(R, c.r, S, c.s, tau_of ? (double)(*tau_of)[c.r] : tau, ps[idx[q]].f_lb, ps[idx[q]].f_ub, f);
-        for (int j = 0; j < MLP_IN; ++j) x[(size_t)q * MLP_IN + j] = (f[j] - ctx->feat_mean[j]) / ctx->feat_std[j];
-        // expected work of a LoD: with the box culling of the refinement the
-        // facet pairs evaluated grow with the square root of the planned
-        // n_r * n_s (the facets near the closest approach), not with it
-        for (int l = 0; l < MLP_OUT; ++l)
-            cost[(size_t)q * MLP_OUT + l] = (float)std::sqrt((double)R->count(c.r, l) * (double)S->count(c.s, l));
-    });
-    PJTRY(ensure(ctx, ctx->b_tmp0, (size_t)n * MLP_IN * 4));
-    PJTRY(ensure(ctx, ctx->b_tmp1, (size_t)n * MLP_OUT * 4 * 2 + (size_t)n * 4));
-    PJTRY(ensure(ctx, ctx->b_tmp2, MLP_NPARAM * 4));
-    float *dx = ptr<float>(ctx->b_tmp0), *dcost = ptr<float>(ctx->b_tmp1), *dprob = dcost + (size_t)n * MLP_OUT;
-    int32_t *dstart = reinterpret_cast<int32_t *>(dprob + (size_t)n * MLP_OUT);
-    HIPTRY(ctx, hipMemcpyAsync(dx, x.data(), x.size() * 4, hipMemcpyHostToDevice, st));
-    HIPTRY(ctx, hipMemcpyAsync(dcost, cost.data(), cost.size() * 4, hipMemcpyHostToDevice, st));
-    HIPTRY(ctx, hipMemcpyAsync(ctx->b_tmp2.p, ctx->model.data(), MLP_NPARAM * 4, hipMemcpyHostToDevice, st));
-    HIPTRY(ctx, launch_mlp_infer(ptr<float>(ctx->b_tmp2), dx, n, dcost, R->L, dprob, dstart, st));
-    std::vector<int32_t> s0(n);
-    HIPTRY(ctx, hipMemcpyAsync(s0.data(), dstart, n * 4, hipMemcpyDeviceToHost, st));
+        hin[q] = StartIn{c.r, c.s, ps[idx[q]].f_lb, ps[idx[q]].f_ub, tau_of ? (double)(*tau_of)[c.r] : tau};
+    }
+    PJTRY(ensure(ctx, ctx->b_tmp0, (size_t)n * sizeof(StartIn)));
+    PJTRY(ensure(ctx, ctx->b_tmp1, (size_t)n * 4));
+    PJTRY(ensure(ctx, ctx->b_model, (MLP_NPARAM + 2 * MLP_IN) * 4));
+    float *dpar = ptr<float>(ctx->b_model);
+    int32_t *dstart = ptr<int32_t>(ctx->b_tmp1);
+    HIPTRY(ctx, hipMemcpyAsync(ctx->b_tmp0.p, hin, (size_t)n * sizeof(StartIn), hipMemcpyHostToDevice, st));
+    if (ctx->model_dev != ctx->b_model.p) {  // the weights and feature scales, once per loaded model
+        std::vector<float> hp(MLP_NPARAM + 2 * MLP_IN);
+        std::memcpy(hp.data(), ctx->model.data(), MLP_NPARAM * 4);
+        std::memcpy(hp.data() + MLP_NPARAM, ctx->feat_mean, MLP_IN * 4);
+        std::memcpy(hp.data() + MLP_NPARAM + MLP_IN, ctx->feat_std, MLP_IN * 4);
+        HIPTRY(ctx, hipMemcpyAsync(dpar, hp.data(), hp.size() * 4, hipMemcpyHostToDevice, st));
+        HIPTRY(ctx, hipStreamSynchronize(st));
+        ctx->model_dev = ctx->b_model.p;
+    }
+    const FeatSide fr{R->d_lodmax, R->d_tcnt, R->L}, fs{S->d_lodmax, S->d_tcnt, S->L};
+    HIPTRY(ctx, launch_mlp_start(dpar, dpar + MLP_NPARAM, fr, fs, ptr<StartIn>(ctx->b_tmp0), n, dstart, st));
+    int32_t *s0 = (int32_t *)ctx->pin_start.p;  // the inputs have been read by now (same stream)
+    HIPTRY(ctx, hipMemcpyAsync(s0, dstart, (size_t)n * 4, hipMemcpyDeviceToHost, st));
     HIPTRY(ctx, hipStreamSynchronize(st));
     for (int q = 0; q < n; ++q) start[idx[q]] = std::min(std::max(s0[q], 0), R->L - 1);
     return PJ_OK;
@@ -3915,6 +3945,7 @@ extern "C" pj_status pj_train_lod_model(pj_context *ctx, const char *log_path, c
     std::memcpy(ctx->feat_mean, h.mean, sizeof(h.mean));
     std::memcpy(ctx->feat_std, h.stdv, sizeof(h.stdv));
     ctx->has_model = true;
+    ctx->model_dev = nullptr;
     return PJ_OK;
 }
 

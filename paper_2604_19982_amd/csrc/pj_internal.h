@@ -183,7 +183,20 @@ hipError_t launch_mlp_fwd_bwd(const float *params, const float *x, const int32_t
                               float *loss_per, float *grads, float *scratch, hipStream_t st);
 hipError_t launch_mlp_adam(float *params, float *m, float *v, const float *grads, int step, float lr, float b1,
                            float b2, float eps, hipStream_t st);
-hipError_t launch_mlp_infer(const float *params, const float *x, int n, const float *cost, int n_lods, float *probs,
+// First LoD of each undecided candidate from the network: its 16 features
+// (the bounds below and the two objects' per-LoD facet counts and hd/ph
+// maxima), normalised by the model's mean and deviation, the forward pass,
+// and the start that minimises the expected work.
+struct StartIn {
+    int32_t r, s;
+    double lb, ub, tau;  // the pair's bounds after the filters and its threshold
+};
+struct FeatSide {
+    const float2 *lodmax;  // [n*L] (max hd, max ph) per (object, LoD)
+    const int32_t *tcnt;   // [n*L] facets per (object, LoD)
+    int32_t L;
+};
+hipError_t launch_mlp_start(const float *params, const float *norm, FeatSide R, FeatSide S, const StartIn *in, int n,
                             int32_t *start, hipStream_t st);
 
 // Allocation-free entry point: the device scratch array (one per device,

@@ -792,10 +792,11 @@ __device__ __forceinline__ bool chunk_cut(float g, float bph, float aph, float c
 // used up; the owner (the wave that took the tile from the list) shows the
 // tile in its workgroup slot until the cursor is exhausted.
 template <int P, bool COLLECT>
-__device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t, float4 *sh, float4 *qv, bool owner,
+__device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t, float4 *sh, bool owner,
                                                 unsigned long long &pairs_acc, unsigned long long &culled_acc)
 {
     const int lane = threadIdx.x;
+    float4 *const qv = sh;  // the facet queue shares the record array
     const Tile tl = a.tiles[t];
     const Item it = a.items[tl.item];
     ItemOut *o = a.out + tl.item;
@@ -865,7 +866,10 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
         // Surviving B facets wait in an LDS queue (qv: corners, hd, ph and
         // index, as gathered for the facet test) and are evaluated 64 at a
         // time: their records are built by all lanes at once, then every lane
-        // runs its A facet against each of them.
+        // runs its A facet against each of them.  The queue and the records
+        // share one LDS array: a flush first takes its facets and the queue's
+        // overflow beyond them into registers, writes the records over the
+        // queue, and after the pair loop puts the overflow back at the front.
         int qn = 0;
         auto flush = [&](const int n) {
             if (!built) {
@@ -877,8 +881,20 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
                 }
                 built = true;
             }
+            const int rest = qn - n;  // queued facets beyond this batch (fewer than 64)
+            float4 q0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), q1 = q0, q2 = q0, r0 = q0, r1 = q0, r2 = q0;
             if (lane < n) {
-                const float4 q0 = qv[3 * lane], q1 = qv[3 * lane + 1], q2 = qv[3 * lane + 2];
+                q0 = qv[3 * lane];
+                q1 = qv[3 * lane + 1];
+                q2 = qv[3 * lane + 2];
+            }
+            if (lane < rest) {
+                r0 = qv[3 * (n + lane)];
+                r1 = qv[3 * (n + lane) + 1];
+                r2 = qv[3 * (n + lane) + 2];
+            }
+            __syncthreads();
+            if (lane < n) {
                 const V3 w0{q0.x, q0.y, q0.z}, w1{q0.w, q1.x, q1.y}, w2{q1.z, q1.w, q2.x};
                 Rec rb = make_rec(w0 - org, w1 - org, w2 - org, q2.y, q2.z);
                 rb.pad = q2.w;
@@ -934,6 +950,13 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
             }
             cols += n;
             __syncthreads();
+            if (lane < rest) {
+                qv[3 * lane] = r0;
+                qv[3 * lane + 1] = r1;
+                qv[3 * lane + 2] = r2;
+            }
+            qn = rest;
+            __syncthreads();
             if (a.cull) {  // publish the running minima so that other tiles can cull against them
                 const float wl = wmin_u(lbm), wu = wmin_u(ubm);
                 lbm = wl;
@@ -957,42 +980,63 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
         };
         // Groups of up to 64 streamed chunks: lane j tests chunk j of the group
         // from its block record, a ballot leaves the chunks that may matter, and
-        // the wave walks those in order.  Before a chunk is loaded its test is
-        // repeated with the minima found so far (read back from the testing lane).
-        for (int g0 = tl.b0; g0 < tl.b1 && !stop; g0 += 64 * 64) {
-            const int nch = min(64, (tl.b1 - g0 + 63) >> 6);
-            float cur_lb = kInf, cur_ub = kInf;
-            float gap_l = 0.0f, bph_l = 0.0f;
-            unsigned long long cmask;
-            if (a.cull) {
-                cur_lb = __uint_as_float(__builtin_amdgcn_readfirstlane(
-                    __hip_atomic_load(&o->lb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
-                cur_ub = __uint_as_float(__builtin_amdgcn_readfirstlane(
-                    __hip_atomic_load(&o->ub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
-                bool live = false;
-                if (lane < nch) {
-                    const int c = (g0 >> 6) + lane;
-                    const float4 blo = SB.blk[2 * c], bhi = SB.blk[2 * c + 1];
-                    gap_l = box_gap32(alo, ahi, blo, bhi) - it.eps;
-                    bph_l = bhi.w;
-                    live = !chunk_cut<COLLECT>(gap_l, bph_l, aph, cur_lb, cur_ub, lbm, ubm, it, a.tau, within);
-                    if (vrows) live = live && (SB.bmask[c] & bvox) != 0ull;
+        // the wave walks those nearest first (in order without culling).
+        // Before a chunk is loaded its test is
+        // repeated with the minima found so far (read back from the testing
+        // lane).  One loop takes the surviving chunks of every group and ends
+        // with the flush of what is left in the queue, so the flush and its
+        // pair loop have a single call site.
+        int g0 = tl.b0;  // next group to test
+        int gb = tl.b0;  // group whose survivors are in cmask
+        unsigned long long cmask = 0ull;
+        float cur_lb = kInf, cur_ub = kInf;
+        float gap_l = 0.0f, bph_l = 0.0f;
+        for (;;) {
+            // the next chunk that survives its tests, or -1 at the end of the range
+            int cb = -1;
+            while (!stop) {
+                if (cmask == 0ull) {
+                    if (g0 >= tl.b1) break;
+                    const int nch = min(64, (tl.b1 - g0 + 63) >> 6);
+                    if (a.cull) {
+                        cur_lb = __uint_as_float(__builtin_amdgcn_readfirstlane(
+                            __hip_atomic_load(&o->lb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+                        cur_ub = __uint_as_float(__builtin_amdgcn_readfirstlane(
+                            __hip_atomic_load(&o->ub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+                        bool live = false;
+                        if (lane < nch) {
+                            const int c = (g0 >> 6) + lane;
+                            const float4 blo = SB.blk[2 * c], bhi = SB.blk[2 * c + 1];
+                            gap_l = box_gap32(alo, ahi, blo, bhi) - it.eps;
+                            bph_l = bhi.w;
+                            live = !chunk_cut<COLLECT>(gap_l, bph_l, aph, cur_lb, cur_ub, lbm, ubm, it, a.tau, within);
+                            if (vrows) live = live && (SB.bmask[c] & bvox) != 0ull;
+                        }
+                        cmask = __ballot(live);
+                        culled += nch - __popcll(cmask);
+                    } else {
+                        cmask = nch == 64 ? ~0ull : ((1ull << nch) - 1ull);
+                        if (vrows) {
+                            const bool live = lane < nch && (SB.bmask[(g0 >> 6) + lane] & bvox) != 0ull;
+                            cmask = __ballot(live);
+                            culled += nch - __popcll(cmask);
+                        }
+                    }
+                    gb = g0;
+                    g0 += 64 * 64;
+                    continue;
                 }
-                cmask = __ballot(live);
-                culled += nch - __popcll(cmask);
-            } else {
-                cmask = nch == 64 ? ~0ull : ((1ull << nch) - 1ull);
-                if (vrows) {
-                    const bool live = lane < nch && (SB.bmask[(g0 >> 6) + lane] & bvox) != 0ull;
-                    cmask = __ballot(live);
-                    culled += nch - __popcll(cmask);
+                int j = __builtin_ctzll(cmask);
+                if (a.cull) {
+                    // nearest chunk first (smallest box gap among those left),
+                    // so the running minima tighten early and the chunks after
+                    // it are cut by the retest below
+                    const float gm = ((cmask >> lane) & 1ull) ? gap_l : kInf;
+                    const float mn = wmin_u(gm);
+                    const unsigned long long at = __ballot(gm == mn) & cmask;
+                    if (at != 0ull) j = __builtin_ctzll(at);
                 }
-            }
-            while (cmask != 0ull && !stop) {
-                const int j = __builtin_ctzll(cmask);
-                cmask &= cmask - 1ull;
-                const int cb = g0 + 64 * j;
-                const int nb = min(64, tl.b1 - cb);
+                cmask &= ~(1ull << j);
                 if (a.cull) {
                     const float gj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gap_l), j));
                     const float bj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bph_l), j));
@@ -1004,6 +1048,11 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
                         continue;
                     }
                 }
+                cb = gb + 64 * j;
+                break;
+            }
+            if (cb >= 0) {
+                const int nb = min(64, tl.b1 - cb);
                 int f = cb + lane;
                 if (f >= tl.b1) f = cb;
                 // Facet culling: the same two-sided test with this facet's own
@@ -1025,10 +1074,7 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
                 }
                 const unsigned long long kmask = __ballot(keep);
                 const int nk = __popcll(kmask);
-                if (nk == 0) {
-                    ++culled;
-                    continue;
-                }
+                if (nk == 0) ++culled;
                 if (keep) {
                     const int pos = qn + __builtin_amdgcn_mbcnt_hi((unsigned)(kmask >> 32),
                                                                    __builtin_amdgcn_mbcnt_lo((unsigned)kmask, 0u));
@@ -1038,29 +1084,12 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
                 }
                 qn += nk;
                 __syncthreads();
-                if (qn >= 64) {
-                    flush(64);
-                    // move the rest of the queue to its front
-                    const int rest = qn - 64;
-                    float4 v0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), v1 = v0, v2 = v0;
-                    if (lane < rest) {
-                        v0 = qv[3 * (64 + lane)];
-                        v1 = qv[3 * (64 + lane) + 1];
-                        v2 = qv[3 * (64 + lane) + 2];
-                    }
-                    __syncthreads();
-                    if (lane < rest) {
-                        qv[3 * lane] = v0;
-                        qv[3 * lane + 1] = v1;
-                        qv[3 * lane + 2] = v2;
-                    }
-                    __syncthreads();
-                    qn = rest;
-                }
             }
+            // a full batch (the facets beyond it stay queued), or what is left
+            // at the end of the range
+            if (qn >= 64 || (cb < 0 && qn > 0 && !stop)) flush(min(qn, 64));
+            if (cb < 0) break;
         }
-        if (qn > 0 && !stop) flush(qn);
-        qn = 0;
         npairs += (unsigned long long)min(64 * P, SA.n - a0) * (unsigned long long)cols;
         if (j == nblk - 1) break;  // this wave took the last block: no claim is left to try
     }  // A blocks
@@ -1090,73 +1119,86 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
 // Termination: every fetch raises the list counter; every claim raises a
 // tile cursor; the pass visits each slot at most once.
 template <int P, bool COLLECT>
-__device__ __forceinline__ void refine_tiles(const RefineArgs &a, float4 *sh, float4 *qv)
+__device__ __forceinline__ void refine_tiles(const RefineArgs &a, float4 *sh)
 {
     const int ntiles = *a.ntiles;
+    const int nslot = gridDim.x;
     // launch-wide statistics, published once per wave
     unsigned long long pairs_acc = 0, culled_acc = 0;
-    int t0 = 0;
-    if (threadIdx.x == 0) t0 = atomicAdd(a.tile_next, 1);
-    int t = __builtin_amdgcn_readfirstlane(t0);
-    while (t < ntiles) {
-        int nxt = 0;
-        if (threadIdx.x == 0) nxt = atomicAdd(a.tile_next, 1);
-        refine_tile_f32<P, COLLECT>(a, t, sh, qv, true, pairs_acc, culled_acc);
-        t = __builtin_amdgcn_readfirstlane(nxt);
-    }
-    // Helping: one pass over the tiles still in progress.  A round with no
-    // more tiles than workgroups scans the tiles themselves (every tile has
-    // been taken by now, and a multi-block tile with blocks left can be
-    // joined); a larger one scans the workgroup slots, starting at this
-    // workgroup's own so that the helpers spread over the tiles in progress.
-    const int nslot = gridDim.x;
-    if (ntiles <= nslot) {
-        // each helper starts at its own tile (wrapping around), so that they
-        // do not all queue on the cursors of the first tiles
-        const int start = (int)(blockIdx.x % (unsigned)max(ntiles, 1));
-        for (int h = 0; h < ntiles;) {
-            const int hw = h + (int)threadIdx.x;
-            int tt = hw + start;
-            if (tt >= ntiles) tt -= ntiles;
-            int c = -1;
-            if (hw < ntiles) {
-                const Tile x = a.tiles[tt];
-                const int nb = (x.a1 - x.a0 + 64 * P - 1) / (64 * P);
-                if (nb > 1 && __hip_atomic_load(a.tile_cur + tt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < nb) c = tt;
-            }
-            const unsigned long long m = __ballot(c >= 0);
-            if (m == 0ull) {
-                h += 64;
-                continue;
-            }
-            const int l = __builtin_ctzll(m);
-            const int tj = __builtin_amdgcn_readlane(c, l);
-            refine_tile_f32<P, COLLECT>(a, tj, sh, qv, false, pairs_acc, culled_acc);
-            h += l + 1;
-        }
-    }
-    for (int h = ntiles <= nslot ? nslot : 0; h < nslot;) {
-        const int hw = h + (int)threadIdx.x;
-        int w = hw + (int)blockIdx.x;
-        if (w >= nslot) w -= nslot;
-        int c = -1;
-        if (hw < nslot) {
-            const int tt = __hip_atomic_load(a.wave_slot + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (tt >= 0 && tt < ntiles) {
-                const Tile x = a.tiles[tt];
-                const int nb = (x.a1 - x.a0 + 64 * P - 1) / (64 * P);
-                if (__hip_atomic_load(a.tile_cur + tt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < nb) c = tt;
+    int nxt = 0;  // lane 0: the list index fetched for the next tile
+    if (threadIdx.x == 0) nxt = atomicAdd(a.tile_next, 1);
+    // phase 0 takes tiles from the list; then the helping pass over the tiles
+    // still in progress.  A round with no more tiles than workgroups scans
+    // the tiles themselves (phase 1: every tile has been taken by now, and a
+    // multi-block tile with blocks left can be joined); a larger one scans
+    // the workgroup slots (phase 2), starting at this workgroup's own so
+    // that the helpers spread over the tiles in progress.  In phase 1 each
+    // helper starts at its own tile (wrapping around), so that they do not
+    // all queue on the cursors of the first tiles.  One call site of the
+    // tile body keeps a single copy of it in the kernel.
+    int phase = 0, h = 0;
+    const int start = (int)(blockIdx.x % (unsigned)max(ntiles, 1));
+    for (;;) {
+        int t = -1;
+        bool owner = false;
+        if (phase == 0) {
+            const int c = __builtin_amdgcn_readfirstlane(nxt);
+            if (c < ntiles) {
+                t = c;
+                owner = true;
+                // the fetch for the next tile is issued before this one is processed
+                if (threadIdx.x == 0) nxt = atomicAdd(a.tile_next, 1);
+            } else {
+                phase = ntiles <= nslot ? 1 : 2;
             }
         }
-        const unsigned long long m = __ballot(c >= 0);
-        if (m == 0ull) {
-            h += 64;
-            continue;
+        if (phase == 1) {
+            while (t < 0 && h < ntiles) {
+                const int hw = h + (int)threadIdx.x;
+                int tt = hw + start;
+                if (tt >= ntiles) tt -= ntiles;
+                int c = -1;
+                if (hw < ntiles) {
+                    const Tile x = a.tiles[tt];
+                    const int nb = (x.a1 - x.a0 + 64 * P - 1) / (64 * P);
+                    if (nb > 1 && __hip_atomic_load(a.tile_cur + tt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < nb)
+                        c = tt;
+                }
+                const unsigned long long m = __ballot(c >= 0);
+                if (m == 0ull) {
+                    h += 64;
+                } else {
+                    const int l = __builtin_ctzll(m);
+                    t = __builtin_amdgcn_readlane(c, l);
+                    h += l + 1;
+                }
+            }
+        } else if (phase == 2) {
+            while (t < 0 && h < nslot) {
+                const int hw = h + (int)threadIdx.x;
+                int w = hw + (int)blockIdx.x;
+                if (w >= nslot) w -= nslot;
+                int c = -1;
+                if (hw < nslot) {
+                    const int tt = __hip_atomic_load(a.wave_slot + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (tt >= 0 && tt < ntiles) {
+                        const Tile x = a.tiles[tt];
+                        const int nb = (x.a1 - x.a0 + 64 * P - 1) / (64 * P);
+                        if (__hip_atomic_load(a.tile_cur + tt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < nb) c = tt;
+                    }
+                }
+                const unsigned long long m = __ballot(c >= 0);
+                if (m == 0ull) {
+                    h += 64;
+                } else {
+                    const int l = __builtin_ctzll(m);
+                    t = __builtin_amdgcn_readlane(c, l);
+                    h += l + 1;
+                }
+            }
         }
-        const int l = __builtin_ctzll(m);
-        const int tt = __builtin_amdgcn_readlane(c, l);
-        refine_tile_f32<P, COLLECT>(a, tt, sh, qv, false, pairs_acc, culled_acc);
-        h += l + 1;
+        if (t < 0) break;
+        refine_tile_f32<P, COLLECT>(a, t, sh, owner, pairs_acc, culled_acc);
     }
     if (threadIdx.x == 0) {
         if (pairs_acc) atomicAdd(a.pairs_done, pairs_acc);
@@ -1164,21 +1206,32 @@ __device__ __forceinline__ void refine_tiles(const RefineArgs &a, float4 *sh, fl
     }
 }
 
+// the facet queue (at most 127 entries of 3 float4) lives in the record array
+static_assert(127 * 3 <= 64 * 11, "facet queue fits in the LDS record array");
+
+// Waves per SIMD the refinement kernels are compiled for.  Three (at most
+// 168 VGPRs) fit beside the 11 KB of LDS each single-wave workgroup holds
+// (14 per CU); at that limit the pair loop still keeps every value in
+// registers and only cold per-tile state spills.
+#ifndef PJ_REFINE_WAVES
+#define PJ_REFINE_WAVES 3
+#endif
+
 template <int P>
-__global__ __launch_bounds__(64) void k_refine_f32(RefineArgs a)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PJ_REFINE_WAVES, PJ_REFINE_WAVES))) void
+k_refine_f32(RefineArgs a)
 {
     __shared__ float4 sh[64 * 11];
-    __shared__ float4 qv[128 * 3];
-    refine_tiles<P, false>(a, sh, qv);
+    refine_tiles<P, false>(a, sh);
 }
 
 // Collect pass: the same tiles, keeping every facet pair whose FP32 lower
 // distance is at most the item's threshold (for the FP64 recheck).
-__global__ __launch_bounds__(64) void k_collect_f32(RefineArgs a)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PJ_REFINE_WAVES, PJ_REFINE_WAVES))) void
+k_collect_f32(RefineArgs a)
 {
     __shared__ float4 sh[64 * 11];
-    __shared__ float4 qv[128 * 3];
-    refine_tiles<1, true>(a, sh, qv);
+    refine_tiles<1, true>(a, sh);
 }
 
 hipError_t launch_collect_f32(const RefineArgs &a, int grid, hipStream_t st)

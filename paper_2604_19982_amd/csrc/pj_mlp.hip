@@ -162,18 +162,41 @@ hipError_t launch_mlp_adam(float *params, float *m, float *v, const float *grads
     return hipGetLastError();
 }
 
-// Inference: class probabilities and the first LoD to refine, chosen to
-// minimise the expected facet-pair work  C(s) = c_s + sum_{l>s} c_l P(y >= l)
-// (a pair is assumed to resolve at s when its label is <= s).
-__global__ __launch_bounds__(128) void k_mlp_infer(const float *params, const float *x, const float *cost, int n,
-                                                   int n_lods, float *probs, int32_t *start)
+// Inference.  The 16 features of a candidate pair, computed as the logged
+// ones are (FP64, rounded once): log1p of its lower bound, of tau and of its
+// upper bound, where tau sits between the bounds, and per LoD l log1p of the
+// two objects' max hd and max ph summed and log2(n_r * n_s) / 16.  The first
+// LoD to refine is chosen to minimise the expected facet-pair work
+// C(s) = c_s + sum_{l>s} c_l P(y >= l), c_l = sqrt(n_r n_s) at LoD l (a pair
+// is assumed to resolve at s when its label is <= s).
+__device__ __forceinline__ void pair_features_dev(const FeatSide &R, const FeatSide &S, const StartIn &c, float *f,
+                                                  float *cost)
+{
+    f[0] = (float)log1p(fmax(c.lb, 0.0));
+    f[1] = (float)log1p(c.tau);
+    f[2] = (float)log1p(fmax(c.ub, 0.0));
+    f[3] = (float)fmin(1.0, fmax(0.0, (c.tau - c.lb) / fmax(c.ub - c.lb, 1e-9)));
+    for (int l = 0; l < 4; ++l) {
+        const int lr = min(l, R.L - 1);
+        const float2 a = R.lodmax[(int64_t)c.r * R.L + lr], b = S.lodmax[(int64_t)c.s * S.L + lr];
+        const double nr = R.tcnt[(int64_t)c.r * R.L + lr], ns = S.tcnt[(int64_t)c.s * S.L + lr];
+        f[4 + 3 * l] = (float)log1p((double)a.x + b.x);
+        f[5 + 3 * l] = (float)log1p((double)a.y + b.y);
+        f[6 + 3 * l] = (float)(log2(fmax(nr * ns, 1.0)) / 16.0);
+        cost[l] = (float)sqrt(nr * ns);
+    }
+}
+
+__global__ __launch_bounds__(128) void k_mlp_start(const float *params, const float *norm, FeatSide R, FeatSide S,
+                                                   const StartIn *in, int n, int32_t *start)
 {
     __shared__ float w[MLP_NPARAM];
     stage(params, w);
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= n) return;
-    float xs[MLP_IN], z1[MLP_H], z2[MLP_H], lg[MLP_OUT];
-    for (int i = 0; i < MLP_IN; ++i) xs[i] = x[(int64_t)b * MLP_IN + i];
+    float xs[MLP_IN], cost[MLP_OUT], z1[MLP_H], z2[MLP_H], lg[MLP_OUT];
+    pair_features_dev(R, S, in[b], xs, cost);
+    for (int i = 0; i < MLP_IN; ++i) xs[i] = (xs[i] - norm[i]) / norm[MLP_IN + i];
     forward1(w, xs, z1, z2, lg);
     float m = fmaxf(fmaxf(lg[0], lg[1]), fmaxf(lg[2], lg[3]));
     float e[MLP_OUT], se = 0.0f;
@@ -184,12 +207,12 @@ __global__ __launch_bounds__(128) void k_mlp_infer(const float *params, const fl
     float tail[MLP_OUT + 1];  // tail[l] = P(y >= l)
     tail[MLP_OUT] = 0.0f;
     for (int j = MLP_OUT - 1; j >= 0; --j) tail[j] = tail[j + 1] + e[j] / se;
-    for (int j = 0; j < MLP_OUT; ++j) probs[(int64_t)b * MLP_OUT + j] = e[j] / se;
+    const int nl = min(R.L, MLP_OUT);
     int best = 0;
     float bc = 3.4e38f;
-    for (int s = 0; s < n_lods && s < MLP_OUT; ++s) {
-        float c = cost[(int64_t)b * MLP_OUT + s];
-        for (int l = s + 1; l < n_lods && l < MLP_OUT; ++l) c += cost[(int64_t)b * MLP_OUT + l] * tail[l];
+    for (int s = 0; s < nl; ++s) {
+        float c = cost[s];
+        for (int l = s + 1; l < nl; ++l) c += cost[l] * tail[l];
         if (c < bc) {
             bc = c;
             best = s;
@@ -198,11 +221,11 @@ __global__ __launch_bounds__(128) void k_mlp_infer(const float *params, const fl
     start[b] = best;
 }
 
-hipError_t launch_mlp_infer(const float *params, const float *x, int n, const float *cost, int n_lods, float *probs,
+hipError_t launch_mlp_start(const float *params, const float *norm, FeatSide R, FeatSide S, const StartIn *in, int n,
                             int32_t *start, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mlp_infer, dim3((n + 127) / 128), dim3(128), 0, st, params, x, cost, n, n_lods, probs, start);
+    hipLaunchKernelGGL(k_mlp_start, dim3((n + 127) / 128), dim3(128), 0, st, params, norm, R, S, in, n, start);
     return hipGetLastError();
 }
 

@@ -40,7 +40,7 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(pj.Config) == 4 * 16 + 8 + 8 * 4 + 8 * 3 + 8 + 8
     assert ctypes.sizeof(pj.MeshDesc) == 8 + 8 + 8 + 8 * 10
     assert ctypes.sizeof(pj.Pairs) == 32
-    assert ctypes.sizeof(pj.Stats) == 7 * 8 + 8 * 8 + 8 * 8 + 16 + 4 * 8 + 8 + 8 + 4 * 64 + 24 + 16 + 64 + 8 + 16 + 40 + 8
+    assert ctypes.sizeof(pj.Stats) == 7 * 8 + 8 * 8 + 8 * 8 + 16 + 4 * 8 + 8 + 8 + 4 * 64 + 24 + 16 + 64 + 8 + 16 + 40 + 8 + 8
 
 
 def test_product_path_does_not_import_oracle():
@@ -59,7 +59,7 @@ def test_every_launch_fits_a_dispatch():
     at most 128 per block, and the probes)."""
     import re
     bounded = {"k_scan", "k_init_round", "k_refine_f32", "k_collect_f32", "k_mlp_fwd_bwd", "k_mlp_wgrad",
-               "k_mlp_adam", "k_mlp_infer", "k_fma_probe", "k_copy_probe"}
+               "k_mlp_adam", "k_mlp_start", "k_fma_probe", "k_copy_probe"}
     csrc = os.path.join(ROOT, "paper_2604_19982_amd", "csrc")
     seen = set()
     for f in sorted(os.listdir(csrc)):

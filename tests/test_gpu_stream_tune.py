@@ -200,31 +200,63 @@ def test_host_resident_knn(pj):
     assert h.stats()["staged_bytes"] > 0
 
 
+def parallel_grids(n):
+    """Two n x n unit grids (2 n^2 triangles each), the second one unit above
+    the first: each facet of one lies at distance exactly 1 from the dozen
+    facets of the other that touch its projection, so the k-NN recheck keeps
+    about 12 facet pairs per facet."""
+    g = np.arange(n + 1, dtype=np.float32)
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    v = np.stack([X.ravel(), Y.ravel(), np.zeros(X.size, np.float32)], 1)
+    idx = np.arange((n + 1) ** 2).reshape(n + 1, n + 1)
+    a, b, c, d = idx[:-1, :-1].ravel(), idx[1:, :-1].ravel(), idx[1:, 1:].ravel(), idx[:-1, 1:].ravel()
+    tri = np.concatenate([np.stack([a, b, c], 1), np.stack([a, c, d], 1)])
+    return mg.single_object(v, [tri]), mg.single_object(v + np.float32([0.0, 0.0, 1.0]), [tri])
+
+
 def test_knn_recheck_overflow_redo(pj):
-    """Memory caps small enough that the recheck's collect list overflows:
-    those items are recomputed by the tiled FP64 kernel over all their finest
-    facet pairs, and the lists and distances must equal the uncapped join's
-    (both take the minimum of the same FP64 pair distance over a set holding
-    the minimising pair)."""
-    R, S = mg.config_knn(seed=3, n_r=40, n_s=40, n_clusters=2, box=200.0, sigma=12.0, f_median=2000)
+    """Memory caps small enough that the recheck's collect list overflows
+    (the parallel grids offer about 1.5M pairs for their one item, 24 MB of
+    list): the item is recomputed by the tiled FP64 kernel over all its
+    finest facet pairs, and the list and distance must equal the uncapped
+    join's (both take the minimum of the same FP64 pair distance over a set
+    holding the minimising pair; here exactly 1)."""
+    R, S = parallel_grids(250)
     d = pj.Context()
-    ref = d.join_knn(d.meshes(R), d.meshes(S), 3)
-    assert d.stats()["collect_overflow"] == 0
+    ref = d.join_knn(d.meshes(R), d.meshes(S), 1)
+    assert d.stats()["collect_overflow"] == 0 and ref["dist"][0][0] == 1.0
     overflowed = []
-    for cap in (8 << 20, 6 << 20, 4 << 20, 3 << 20, 2 << 20, 3 << 19, 1 << 20, 3 << 18, 1 << 19):
+    for cap in (32 << 20, 24 << 20, 16 << 20, 12 << 20, 8 << 20):
         h = pj.Context(host_resident=True, mem_cap_bytes=cap, stage_sets=2)
         try:
-            got = h.join_knn(h.meshes(R), h.meshes(S), 3)
+            got = h.join_knn(h.meshes(R), h.meshes(S), 1)
         except pj.PJError as e:  # a cap below what one chunk or the recheck needs
             assert pj.STATUS_NAMES[e.status] == "OUT_OF_MEMORY", (cap, e)
+            print(cap, "out of memory")
             continue
         st = h.stats()
-        print(cap, st["collected_pairs"], st["collect_overflow"])
+        print(cap, st["collected_pairs"], st["collect_regrow"], st["collect_overflow"])
         assert np.array_equal(got["s"], ref["s"]) and np.array_equal(got["count"], ref["count"]), cap
         assert np.array_equal(got["dist"], ref["dist"]), cap
         if st["collect_overflow"] > 0:
             overflowed.append(cap)
     assert overflowed, "no cap made the collect list overflow"
+
+
+def test_knn_recheck_list_grows_to_need(pj):
+    """The parallel grids' recheck offers about 1.5M pairs, more than its
+    first list (2^20 pairs for one item) holds.  The pass runs once more with
+    a list of the offered size: no item falls back to the full FP64 pass,
+    and the distance is exact."""
+    R, S = parallel_grids(250)
+    ctx = pj.Context()
+    res = ctx.join_knn(ctx.meshes(R), ctx.meshes(S), 1)
+    st = ctx.stats()
+    print(st["collected_pairs"], st["collect_regrow"], st["collect_overflow"])
+    assert res["count"][0] == 1 and res["s"][0].tolist()[:1] == [0]
+    assert res["dist"][0][0] == 1.0
+    assert st["collect_regrow"] >= 1 and st["collect_overflow"] == 0
+    assert st["collected_pairs"] > (1 << 20)
 
 
 def test_host_resident_pair_bounds(pj, mid):
