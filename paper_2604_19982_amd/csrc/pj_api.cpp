@@ -1486,7 +1486,9 @@ int64_t tile_target(const pj_context *ctx, int wpc) { return (int64_t)ctx->num_c
 constexpr int kTuneTS[] = {1024, 2048, 4096, 8192, 16384};
 // waves per CU: the refinement kernel holds two waves per SIMD (eight per
 // CU), so a larger grid only queues waves that find the list used up
-constexpr int kTuneWPC[] = {4, 8, 16};
+// waves per CU: at most 12, the refinement kernel's residency (3 per SIMD),
+// so that no wave of the persistent grid starts late
+constexpr int kTuneWPC[] = {4, 8, 12};
 
 void load_tune_cache(pj_context *ctx)
 {
@@ -1518,9 +1520,12 @@ std::string tune_class(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
     for (int i : act) sum += (double)R->count(cand[i].r, lod) * (double)S->count(cand[i].s, lod);
     const double mean = act.empty() ? 0.0 : sum / (double)act.size();
     const int bucket = mean > 1.0 ? (int)std::floor(std::log(mean) / std::log(4.0)) : 0;
+    // and the round's size: a few large items and thousands of them want
+    // different tiles and grids even at the same mean
+    const int nbucket = act.size() > 1 ? (int)std::floor(std::log((double)act.size()) / std::log(4.0)) : 0;
     char buf[160];
-    std::snprintf(buf, sizeof(buf), "%s/%dcu/%s/b%d", ctx->arch.c_str(), ctx->num_cu, tau >= 0.0f ? "within" : "min",
-                  bucket);
+    std::snprintf(buf, sizeof(buf), "%s/%dcu/%s/b%d/n%d", ctx->arch.c_str(), ctx->num_cu,
+                  tau >= 0.0f ? "within" : "min", bucket, nbucket);
     return buf;
 }
 
@@ -1545,13 +1550,17 @@ pj_status choose_shape(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
         sh = it->second;
     } else if (ctx->cfg.autotune && !act.empty()) {
         const double t0 = now_ms();
-        // sample: items spread over the round, up to about 8e9 facet pairs
-        // (large enough that a candidate's time is not launch overhead)
+        // The candidates are timed on the round itself when it plans at most
+        // 2e11 facet pairs (a tenth of that typically survives culling, so a
+        // timing costs milliseconds); a larger round is sampled evenly down
+        // to about that.  A sample of a few items would need more splitting
+        // than the round to fill the GPU and so favour short B ranges.
         std::vector<int> idx(act.begin(), act.end());
         std::vector<int> sample;
-        double pairs = 0.0;
-        const size_t stride = std::max<size_t>(1, idx.size() / 8192);
-        for (size_t i = 0; i < idx.size() && pairs < 8e9; i += stride) {
+        double pairs = 0.0, total = 0.0;
+        for (int i : idx) total += (double)R->count(cand[i].r, lod) * (double)S->count(cand[i].s, lod);
+        const size_t stride = std::max<size_t>(1, (size_t)std::ceil(total / 2e11));
+        for (size_t i = 0; i < idx.size() && pairs < 2e11; i += stride) {
             sample.push_back(idx[i]);
             pairs += (double)R->count(cand[idx[i]].r, lod) * (double)S->count(cand[idx[i]].s, lod);
         }

@@ -790,9 +790,11 @@ __device__ __forceinline__ bool chunk_cut(float g, float bph, float aph, float c
 // The A blocks of a tile with more than one are claimed one at a time from
 // the tile's cursor, so other waves can take part in a tile once the list is
 // used up; the owner (the wave that took the tile from the list) shows the
-// tile in its workgroup slot until the cursor is exhausted.
+// tile in its workgroup slot until the cursor is exhausted.  A helper claims
+// its first block before it comes here (`pre`, -1 for the owner), so a tile
+// whose blocks are all taken costs it one atomic, not the set-up below.
 template <int P, bool COLLECT>
-__device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t, float4 *sh, bool owner,
+__device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t, float4 *sh, bool owner, int pre,
                                                 unsigned long long &pairs_acc, unsigned long long &culled_acc)
 {
     const int lane = threadIdx.x;
@@ -821,7 +823,9 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
     if (owner && nblk > 1 && lane == 0) __hip_atomic_store(a.wave_slot + blockIdx.x, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int k = 0;; ++k) {
         int j = k;
-        if (nblk > 1) {
+        if (k == 0 && pre >= 0) {
+            j = pre;
+        } else if (nblk > 1) {
             int c = 0;
             if (lane == 0) c = atomicAdd(a.tile_cur + t, 1);
             j = __builtin_amdgcn_readfirstlane(c);
@@ -1113,11 +1117,11 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
 // the next tile is issued before the current one is processed.
 //
 // Once the list is used up, the wave makes one pass over the workgroup slots
-// and joins every tile that still has unclaimed A blocks, so a tile whose
-// facets meet over a large area (most of its pairs survive culling) is
-// finished by many waves instead of holding one to the end of the launch.
-// Termination: every fetch raises the list counter; every claim raises a
-// tile cursor; the pass visits each slot at most once.
+// (or the tiles) and joins every tile that still has unclaimed A blocks, so
+// a tile whose facets meet over a large area (most of its pairs survive
+// culling) is finished by many waves instead of holding one to the end of
+// the launch.  Termination: every fetch raises the list counter; every claim
+// raises a tile cursor; the pass visits each slot or tile at most once.
 template <int P, bool COLLECT>
 __device__ __forceinline__ void refine_tiles(const RefineArgs &a, float4 *sh)
 {
@@ -1152,53 +1156,51 @@ __device__ __forceinline__ void refine_tiles(const RefineArgs &a, float4 *sh)
                 phase = ntiles <= nslot ? 1 : 2;
             }
         }
-        if (phase == 1) {
-            while (t < 0 && h < ntiles) {
+        int pre = -1;
+        if (phase == 1 || phase == 2) {
+            // a tile with blocks left (lane l of a 64-wide look), then the
+            // claim of one of them; on a lost race the look goes on
+            const int lim = phase == 1 ? ntiles : nslot;
+            while (t < 0 && h < lim) {
                 const int hw = h + (int)threadIdx.x;
-                int tt = hw + start;
-                if (tt >= ntiles) tt -= ntiles;
-                int c = -1;
-                if (hw < ntiles) {
-                    const Tile x = a.tiles[tt];
-                    const int nb = (x.a1 - x.a0 + 64 * P - 1) / (64 * P);
-                    if (nb > 1 && __hip_atomic_load(a.tile_cur + tt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < nb)
-                        c = tt;
-                }
-                const unsigned long long m = __ballot(c >= 0);
-                if (m == 0ull) {
-                    h += 64;
-                } else {
-                    const int l = __builtin_ctzll(m);
-                    t = __builtin_amdgcn_readlane(c, l);
-                    h += l + 1;
-                }
-            }
-        } else if (phase == 2) {
-            while (t < 0 && h < nslot) {
-                const int hw = h + (int)threadIdx.x;
-                int w = hw + (int)blockIdx.x;
-                if (w >= nslot) w -= nslot;
-                int c = -1;
-                if (hw < nslot) {
-                    const int tt = __hip_atomic_load(a.wave_slot + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                int c = -1, nb = 0;
+                if (hw < lim) {
+                    int tt;
+                    if (phase == 1) {
+                        tt = hw + start;
+                        if (tt >= ntiles) tt -= ntiles;
+                    } else {
+                        int w = hw + (int)blockIdx.x;
+                        if (w >= nslot) w -= nslot;
+                        tt = __hip_atomic_load(a.wave_slot + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
                     if (tt >= 0 && tt < ntiles) {
                         const Tile x = a.tiles[tt];
-                        const int nb = (x.a1 - x.a0 + 64 * P - 1) / (64 * P);
-                        if (__hip_atomic_load(a.tile_cur + tt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < nb) c = tt;
+                        nb = (x.a1 - x.a0 + 64 * P - 1) / (64 * P);
+                        if (nb > 1 && __hip_atomic_load(a.tile_cur + tt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < nb)
+                            c = tt;
                     }
                 }
                 const unsigned long long m = __ballot(c >= 0);
                 if (m == 0ull) {
                     h += 64;
-                } else {
-                    const int l = __builtin_ctzll(m);
-                    t = __builtin_amdgcn_readlane(c, l);
-                    h += l + 1;
+                    continue;
+                }
+                const int l = __builtin_ctzll(m);
+                const int tt = __builtin_amdgcn_readlane(c, l);
+                const int nbt = __builtin_amdgcn_readlane(nb, l);
+                h += l + 1;
+                int got = 0;
+                if (threadIdx.x == 0) got = atomicAdd(a.tile_cur + tt, 1);
+                got = __builtin_amdgcn_readfirstlane(got);
+                if (got < nbt) {
+                    t = tt;
+                    pre = got;
                 }
             }
         }
         if (t < 0) break;
-        refine_tile_f32<P, COLLECT>(a, t, sh, owner, pairs_acc, culled_acc);
+        refine_tile_f32<P, COLLECT>(a, t, sh, owner, pre, pairs_acc, culled_acc);
     }
     if (threadIdx.x == 0) {
         if (pairs_acc) atomicAdd(a.pairs_done, pairs_acc);
