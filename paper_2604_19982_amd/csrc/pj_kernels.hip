@@ -821,6 +821,17 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
     // the tile's A facets, one register block of 64P at a time
     const int nblk = (tl.a1 - tl.a0 + 64 * P - 1) / (64 * P);
     if (owner && nblk > 1 && lane == 0) __hip_atomic_store(a.wave_slot + blockIdx.x, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // Dead A blocks.  Against the union of the B range's chunk records (box,
+    // max ph) a block that passes the chunk cut passes it for every chunk of
+    // the range, each being at least as far and no coarser; such a block
+    // costs only its claim.  The union is formed on the first block the wave
+    // takes, and the blocks are tested 64 at a time (one per lane, the
+    // result a 64-bit mask kept for the batch of the last block taken).
+    const int nbch = (tl.b1 - tl.b0 + 63) >> 6;
+    float4 ulo = make_float4(kInf, kInf, kInf, 0.0f), uhi = make_float4(-kInf, -kInf, -kInf, 0.0f);
+    bool have_u = false;
+    int dead_bt = -1;
+    unsigned long long dead_m = 0ull;
     for (int k = 0;; ++k) {
         int j = k;
         if (k == 0 && pre >= 0) {
@@ -831,6 +842,43 @@ __device__ __forceinline__ void refine_tile_f32(const RefineArgs &a, const int t
             j = __builtin_amdgcn_readfirstlane(c);
         }
         if (j >= nblk || stop) break;
+        if (P == 1 && a.cull && nblk > 1) {
+            if (!have_u) {
+                for (int c0 = 0; c0 < nbch; c0 += 64) {
+                    if (c0 + lane < nbch) {
+                        const int c = (tl.b0 >> 6) + c0 + lane;
+                        const float4 l = SB.blk[2 * c], h = SB.blk[2 * c + 1];
+                        ulo = make_float4(fminf(ulo.x, l.x), fminf(ulo.y, l.y), fminf(ulo.z, l.z), 0.0f);
+                        uhi = make_float4(fmaxf(uhi.x, h.x), fmaxf(uhi.y, h.y), fmaxf(uhi.z, h.z), fmaxf(uhi.w, h.w));
+                    }
+                }
+                ulo = make_float4(wmin_u(ulo.x), wmin_u(ulo.y), wmin_u(ulo.z), 0.0f);
+                uhi = make_float4(-wmin_u(-uhi.x), -wmin_u(-uhi.y), -wmin_u(-uhi.z), -wmin_u(-uhi.w));
+                have_u = true;
+            }
+            const int bt = j >> 6;
+            if (bt != dead_bt) {
+                const float clb = __uint_as_float(__builtin_amdgcn_readfirstlane(
+                    __hip_atomic_load(&o->lb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+                const float cub = __uint_as_float(__builtin_amdgcn_readfirstlane(
+                    __hip_atomic_load(&o->ub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+                bool dead = false;
+                const int jb = (bt << 6) + lane;
+                if (jb < nblk) {
+                    const int rb = (tl.a0 >> 6) + jb;
+                    const float4 bl = SA.blk[2 * rb], bh = SA.blk[2 * rb + 1];
+                    const float g = box_gap32(bl, bh, ulo, uhi) - it.eps;
+                    dead = chunk_cut<COLLECT>(g, uhi.w, bh.w, clb, cub, lbm, ubm, it, a.tau, within);
+                }
+                dead_m = __ballot(dead);
+                dead_bt = bt;
+            }
+            if ((dead_m >> (j & 63)) & 1ull) {
+                culled += nbch;
+                if (j == nblk - 1) break;
+                continue;
+            }
+        }
         const int a0 = tl.a0 + j * 64 * P;
         int cols = 0;
         // the A records are built when the first chunk survives its test, so a
