@@ -31,6 +31,7 @@ from dataclasses import dataclass, field
 import math
 import mmap
 import multiprocessing
+import time
 import os
 
 import numpy as np
@@ -87,14 +88,36 @@ def _gpu_opened() -> bool:
     return False
 
 
-def _run_blocks(fn, args, blocks, workers):
+def _run_blocks(fn, args, blocks, workers, progress=None, label=""):
     """fn(*args, *block) for every block, in forked worker processes (which
-    write their results into shared arrays among ``args``) or serially (one
-    worker, or a process that has opened the GPU)."""
+    write their results into shared arrays among ``args``), or in threads of
+    this process when it has opened the GPU (a profiler can open it before
+    the program starts), or serially for one worker.  The blocks write
+    disjoint slices, so the arrays do not depend on the schedule.  Without
+    forked workers, progress(label done/total) is reported every few
+    seconds."""
     global _FORK_JOB
     if workers <= 1 or len(blocks) <= 1 or _gpu_opened():
-        for b in blocks:
-            fn(*args, *b)
+        from multiprocessing.pool import ThreadPool
+        total = blocks[-1][1] if blocks else 0
+        last = time.time()
+        done = 0
+        if workers <= 1 or len(blocks) <= 1:
+            it = (fn(*args, *b) or b for b in blocks)
+            pool = None
+        else:
+            pool = ThreadPool(min(workers, len(blocks)))
+            it = pool.imap_unordered(lambda b: (fn(*args, *b), b)[1], blocks)
+        try:
+            for b in it:
+                done += b[1] - b[0]
+                if progress is not None and time.time() - last > 5.0:
+                    progress(f"{label} {done}/{total}")
+                    last = time.time()
+        finally:
+            if pool is not None:
+                pool.close()
+                pool.join()
         return
     _FORK_JOB = (fn, args)
     try:
@@ -344,7 +367,7 @@ def make_tubes(rng, centres, n_seg: int, n_lods: int, length_range=(20.0, 80.0),
         # equal tubes: blocks in worker processes, into one shared [n, V, 3]
         out = _shared_array((n, 8 * (n_seg + 1) + 2, 3), np.float32)
         _run_blocks(_tube_block_into, (out, centres, d0, d1, d2, lengths, segs, radius),
-                    [(c0, min(n, c0 + step)) for c0 in range(0, n, step)], workers)
+                    [(c0, min(n, c0 + step)) for c0 in range(0, n, step)], workers, progress, "tubes")
         if progress is not None:
             progress(f"tubes {n}/{n}")
         return out, segs
@@ -445,7 +468,7 @@ def make_blobs(rng, centres, radii, level_min: int, level_max: int, noise=(0.9, 
         v = _shared_array((n, nv, 3), np.float32)
         state = rng.bit_generator.state
         _run_blocks(_blob_block, (v, state, tv[:nv], centres, radii, noise, nv),
-                    [(i0, min(n, i0 + step)) for i0 in range(0, n, step)], workers)
+                    [(i0, min(n, i0 + step)) for i0 in range(0, n, step)], workers, progress, "blobs")
         rng.bit_generator.advance(n * nv)
         if progress is not None:
             progress(f"blobs {n}/{n}")

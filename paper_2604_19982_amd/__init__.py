@@ -297,10 +297,12 @@ class Context:
         lib().pj_knn_free(ctypes.byref(q))
         return dict(count=count, s=s, dist=d)
 
-    def stats(self):
+    def stats(self, raw=False):
+        """The last join's statistics as a dict, or (raw=True) as the ctypes
+        ``Stats`` structure itself (attribute access, no conversion)."""
         st = Stats()
         self._check(lib().pj_get_stats(self.h, ctypes.byref(st)))
-        return st.to_dict()
+        return st if raw else st.to_dict()
 
     def facet_pairs(self, t1, t2, precision="fp32", bounds=False):
         """Facet-pair distances: (d, hit), or (d_lo, d_hi, hit) with bounds=True."""

@@ -292,8 +292,14 @@ struct pj_context {
         void *p = nullptr;
         size_t cap = 0;
     };
-    DevBuf sb_items[kMaxSets], sb_tiles[kMaxSets], sb_out[kMaxSets], sb_ctr[kMaxSets], sb_stage[kMaxSets];
-    PinBuf pin_items[kMaxSets], pin_tiles[kMaxSets], pin_out[kMaxSets], pin_ctr[kMaxSets], pin_stage[kMaxSets];
+    // A chunk's round data live in one buffer per set, on the device and
+    // pinned alike: [results: ci x ItemOut][counters: 256 B][items: ci x Item]
+    // [tiles: ct x Tile] for capacities ci and ct, so that a round takes one
+    // upload (counters, items, tiles) and one download (results, counters),
+    // and the addresses stay fixed while the capacities do (graph keys).
+    DevBuf sb_rnd[kMaxSets], sb_stage[kMaxSets];
+    PinBuf pin_rnd[kMaxSets], pin_stage[kMaxSets];
+    int64_t rcap_i[kMaxSets] = {}, rcap_t[kMaxSets] = {};
     PinBuf pin_cand;  // the filter's candidate count and arrays on their way to the host
     PinBuf pin_start; // the learned skip's inputs up, first LoDs down
     PinBuf pin_vin[2];
@@ -494,7 +500,7 @@ extern "C" pj_status pj_context_destroy(pj_context *ctx)
     for (auto &g : ctx->graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     for (int b = 0; b < kMaxSets; ++b) {
-        for (auto *pb : {&ctx->pin_items[b], &ctx->pin_tiles[b], &ctx->pin_out[b], &ctx->pin_ctr[b], &ctx->pin_stage[b]})
+        for (auto *pb : {&ctx->pin_rnd[b], &ctx->pin_stage[b]})
             if (pb->p) (void)hipHostFree(pb->p);
         for (hipEvent_t e : {ctx->ev_h2d[b], ctx->ev_comp[b], ctx->ev_d2h[b], ctx->ev_k0[b], ctx->ev_k1[b]})
             if (e) (void)hipEventDestroy(e);
@@ -1969,6 +1975,11 @@ pj_status launch_round(pj_context *ctx, const RefineArgs &a, int32_t *ctr, int n
     return PJ_OK;
 }
 
+// Offsets in a set's round buffer for an item capacity ci (see pj_context).
+size_t rnd_ctr_off(int64_t ci) { return (size_t)ci * sizeof(ItemOut); }
+size_t rnd_items_off(int64_t ci) { return rnd_ctr_off(ci) + 256; }
+size_t rnd_tiles_off(int64_t ci) { return rnd_items_off(ci) + (size_t)ci * sizeof(Item); }
+
 // FP32 bulk pass over a plan, streamed in chunks (the refinement pipeline of
 // Section 3.3, Algorithm 5, on HIP streams).  A prep thread gathers chunk
 // c+1 (items, tiles and, for host-resident sets, the chunk's facet data)
@@ -2005,8 +2016,9 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
         // given back (the join stream is idle between rounds)
         HIPTRY(ctx, hipStreamSynchronize(st));
         for (int b = 0; b < kMaxSets; ++b)
-            for (DevBuf *x : {&ctx->sb_items[b], &ctx->sb_tiles[b], &ctx->sb_out[b], &ctx->sb_ctr[b], &ctx->sb_stage[b]})
+            for (DevBuf *x : {&ctx->sb_rnd[b], &ctx->sb_stage[b]})
                 x->release();
+        for (int b = 0; b < kMaxSets; ++b) ctx->rcap_i[b] = ctx->rcap_t[b] = 0;
         ctx->b_sched.release();
         // the shared scheduling buffer: a slot per workgroup (reserved here)
         // and a cursor per tile of a chunk (charged with each tile below)
@@ -2106,15 +2118,20 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
     auto alloc = [&](int j) -> pj_status {
         const int b = j % nsets;
         const Chunk &c = chunks[j];
-        const size_t cni = c.items.size(), cnt = (size_t)(c.t1 - c.t0);
-        PJTRY(ensure(ctx, ctx->sb_items[b], cni * sizeof(Item)));
-        PJTRY(ensure(ctx, ctx->sb_tiles[b], cnt * sizeof(Tile)));
-        PJTRY(ensure(ctx, ctx->sb_out[b], cni * sizeof(ItemOut)));
-        PJTRY(ensure(ctx, ctx->sb_ctr[b], 64));
-        PJTRY(ensure_pinned(ctx, ctx->pin_items[b], cni * sizeof(Item)));
-        PJTRY(ensure_pinned(ctx, ctx->pin_tiles[b], cnt * sizeof(Tile)));
-        PJTRY(ensure_pinned(ctx, ctx->pin_out[b], cni * sizeof(ItemOut)));
-        PJTRY(ensure_pinned(ctx, ctx->pin_ctr[b], 64));
+        const int64_t cni = (int64_t)c.items.size(), cnt = c.t1 - c.t0;
+        if (cni > ctx->rcap_i[b] || cnt > ctx->rcap_t[b]) {
+            // grow by half at least (new addresses mean a new graph); under a
+            // memory cap exactly (the chunks were sized to what it leaves)
+            const bool exact = ctx->cfg.mem_cap_bytes > 0;
+            auto grow = [exact](int64_t need, int64_t have) {
+                return exact ? need : std::max(need, have + have / 2 + 64) / 64 * 64 + 64;
+            };
+            if (cni > ctx->rcap_i[b]) ctx->rcap_i[b] = grow(cni, ctx->rcap_i[b]);
+            if (cnt > ctx->rcap_t[b]) ctx->rcap_t[b] = grow(cnt, ctx->rcap_t[b]);
+        }
+        const size_t bytes = rnd_tiles_off(ctx->rcap_i[b]) + (size_t)ctx->rcap_t[b] * sizeof(Tile);
+        PJTRY(ensure(ctx, ctx->sb_rnd[b], bytes));
+        PJTRY(ensure_pinned(ctx, ctx->pin_rnd[b], bytes));
         if (staged) {
             PJTRY(ensure(ctx, ctx->sb_stage[b], c.stage_bytes));
             PJTRY(ensure_pinned(ctx, ctx->pin_stage[b], c.stage_bytes));
@@ -2127,8 +2144,9 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
         const int b = j % nsets;
         const Chunk &c = chunks[j];
         const int cni = (int)c.items.size();
-        Item *hi = (Item *)ctx->pin_items[b].p;
-        Tile *ht = (Tile *)ctx->pin_tiles[b].p;
+        char *hb = (char *)ctx->pin_rnd[b].p;
+        Item *hi = (Item *)(hb + rnd_items_off(ctx->rcap_i[b]));
+        Tile *ht = (Tile *)(hb + rnd_tiles_off(ctx->rcap_i[b]));
         for (int q = 0; q < cni; ++q) {
             Item x = pl.items[c.items[q]];
             const bool sw = x.flags & IT_SWAP;
@@ -2141,7 +2159,7 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
             x.item = tile_local[t];
             ht[t - c.t0] = x;
         }
-        int32_t *hc = (int32_t *)ctx->pin_ctr[b].p;
+        int32_t *hc = (int32_t *)(hb + rnd_ctr_off(ctx->rcap_i[b]));
         // counter block: [1] tiles, [2..3] pairs evaluated, [4..5] chunks
         // culled, [6] items, [10] next tile to take (all others 0)
         std::memset(hc, 0, 64);
@@ -2158,36 +2176,42 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
         if (hostS) stage_fill(S, c.sS, hs, nthreads);
         prep_ms[j] = now_ms() - tp;
     };
+    // A round of one chunk on device-resident sets has nothing to overlap:
+    // its copies go on the join stream, which saves two hand-offs between
+    // hardware queues per round.
+    const bool one = nch == 1 && !staged;
+    hipStream_t ups = one ? st : ctx->up_stream, downs = one ? st : ctx->down_stream;
     auto enqueue = [&](int j) -> pj_status {
         const int b = j % nsets;
         const Chunk &c = chunks[j];
         const int cni = (int)c.items.size(), cnt = (int)(c.t1 - c.t0);
-        int32_t *dctr = ptr<int32_t>(ctx->sb_ctr[b]);
+        const int64_t ci = ctx->rcap_i[b];
+        char *db = (char *)ctx->sb_rnd[b].p, *hb = (char *)ctx->pin_rnd[b].p;
+        int32_t *dctr = (int32_t *)(db + rnd_ctr_off(ci));
         if (staged) {
             HIPTRY(ctx, hipMemcpyAsync(ctx->sb_stage[b].p, ctx->pin_stage[b].p, c.stage_bytes, hipMemcpyHostToDevice,
                                        ctx->up_stream));
             ctx->stats.staged_bytes += (int64_t)c.stage_bytes;
         }
-        HIPTRY(ctx, hipMemcpyAsync(ctx->sb_items[b].p, ctx->pin_items[b].p, cni * sizeof(Item), hipMemcpyHostToDevice,
-                                   ctx->up_stream));
-        HIPTRY(ctx, hipMemcpyAsync(ctx->sb_tiles[b].p, ctx->pin_tiles[b].p, cnt * sizeof(Tile), hipMemcpyHostToDevice,
-                                   ctx->up_stream));
-        HIPTRY(ctx, hipMemcpyAsync(dctr, ctx->pin_ctr[b].p, 64, hipMemcpyHostToDevice, ctx->up_stream));
-        HIPTRY(ctx, hipEventRecord(ctx->ev_h2d[b], ctx->up_stream));
+        // counters, items and tiles in one copy
+        HIPTRY(ctx, hipMemcpyAsync(db + rnd_ctr_off(ci), hb + rnd_ctr_off(ci),
+                                   rnd_tiles_off(ci) - rnd_ctr_off(ci) + (size_t)cnt * sizeof(Tile),
+                                   hipMemcpyHostToDevice, ups));
+        if (!one) HIPTRY(ctx, hipEventRecord(ctx->ev_h2d[b], ups));
         RefineArgs a;
         std::memset(&a, 0, sizeof(a));
         char *ds = (char *)ctx->sb_stage[b].p;
         a.R = hostR ? stage_view(R, c.sR, ds) : R->dev();
         a.S = hostS ? stage_view(S, c.sS, ds) : S->dev();
-        a.items = ptr<Item>(ctx->sb_items[b]);
-        a.tiles = ptr<Tile>(ctx->sb_tiles[b]);
+        a.items = (Item *)(db + rnd_items_off(ci));
+        a.tiles = (Tile *)(db + rnd_tiles_off(ci));
         a.ntiles = dctr + 1;
         a.tile_next = dctr + 10;
         // rounds run one after another on the join stream, so all chunks
         // share one set of slots and cursors (reset by the round's init kernel)
         a.wave_slot = ptr<int32_t>(ctx->b_sched);
         a.tile_cur = ptr<int32_t>(ctx->b_sched) + grid;
-        a.out = ptr<ItemOut>(ctx->sb_out[b]);
+        a.out = (ItemOut *)db;
         a.pairs_done = reinterpret_cast<unsigned long long *>(dctr + 2);
         a.chunks_culled = reinterpret_cast<unsigned long long *>(dctr + 4);
         a.tau = tau;
@@ -2195,16 +2219,17 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
         a.cull = ctx->cfg.tile_cull ? 1 : 0;
         a.vmask = ctx->vmask;
         a.vrow = ctx->vrow;
-        HIPTRY(ctx, hipStreamWaitEvent(st, ctx->ev_h2d[b], 0));
+        if (!one) HIPTRY(ctx, hipStreamWaitEvent(st, ctx->ev_h2d[b], 0));
         HIPTRY(ctx, hipEventRecord(ctx->ev_k0[b], st));
         PJTRY(launch_round(ctx, a, dctr, cni, cnt, wpc, graph, st));
         HIPTRY(ctx, hipEventRecord(ctx->ev_k1[b], st));
-        HIPTRY(ctx, hipEventRecord(ctx->ev_comp[b], st));
-        HIPTRY(ctx, hipStreamWaitEvent(ctx->down_stream, ctx->ev_comp[b], 0));
-        HIPTRY(ctx, hipMemcpyAsync(ctx->pin_out[b].p, a.out, cni * sizeof(ItemOut), hipMemcpyDeviceToHost,
-                                   ctx->down_stream));
-        HIPTRY(ctx, hipMemcpyAsync(ctx->pin_ctr[b].p, dctr, 64, hipMemcpyDeviceToHost, ctx->down_stream));
-        HIPTRY(ctx, hipEventRecord(ctx->ev_d2h[b], ctx->down_stream));
+        if (!one) {
+            HIPTRY(ctx, hipEventRecord(ctx->ev_comp[b], st));
+            HIPTRY(ctx, hipStreamWaitEvent(downs, ctx->ev_comp[b], 0));
+        }
+        // results and counters in one copy
+        HIPTRY(ctx, hipMemcpyAsync(hb, db, rnd_ctr_off(ci) + 64, hipMemcpyDeviceToHost, downs));
+        HIPTRY(ctx, hipEventRecord(ctx->ev_d2h[b], downs));
         ctx->stats.chunks++;
         return PJ_OK;
     };
@@ -2214,14 +2239,14 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
         const int b = j % nsets;
         HIPTRY(ctx, hipEventSynchronize(ctx->ev_d2h[b]));
         const Chunk &c = chunks[j];
-        const ItemOut *o = (const ItemOut *)ctx->pin_out[b].p;
+        const ItemOut *o = (const ItemOut *)ctx->pin_rnd[b].p;
         for (size_t q = 0; q < c.items.size(); ++q) {
             ItemOut &d = out[c.items[q]];
             d.lb = std::min(d.lb, o[q].lb);
             d.ub = std::min(d.ub, o[q].ub);
             d.hit |= o[q].hit;
         }
-        const int32_t *hc = (const int32_t *)ctx->pin_ctr[b].p;
+        const int32_t *hc = (const int32_t *)((const char *)ctx->pin_rnd[b].p + rnd_ctr_off(ctx->rcap_i[b]));
         unsigned long long pairs, culled;
         std::memcpy(&pairs, hc + 2, 8);
         std::memcpy(&culled, hc + 4, 8);
@@ -2267,7 +2292,7 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
     for (int j = 0; j < nch; ++j) PJTRY(merge(j));
     for (double x : prep_ms) ctx->stats.t_prep_ms += x;
     // the join stream must not run ahead of the downloads
-    HIPTRY(ctx, hipStreamWaitEvent(st, ctx->ev_d2h[(nch - 1) % nsets], 0));
+    if (!one) HIPTRY(ctx, hipStreamWaitEvent(st, ctx->ev_d2h[(nch - 1) % nsets], 0));
     ctx->stats.tiles += nt;
     if (lod < 8) {
         ctx->stats.lod_items[lod] += ni;
@@ -2280,8 +2305,9 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
         // give them back so that the next phase has the same room
         HIPTRY(ctx, hipStreamSynchronize(st));
         for (int b = 0; b < kMaxSets; ++b)
-            for (DevBuf *x : {&ctx->sb_items[b], &ctx->sb_tiles[b], &ctx->sb_out[b], &ctx->sb_ctr[b], &ctx->sb_stage[b]})
+            for (DevBuf *x : {&ctx->sb_rnd[b], &ctx->sb_stage[b]})
                 x->release();
+        for (int b = 0; b < kMaxSets; ++b) ctx->rcap_i[b] = ctx->rcap_t[b] = 0;
         ctx->b_sched.release();
     }
     return PJ_OK;

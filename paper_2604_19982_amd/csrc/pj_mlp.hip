@@ -169,63 +169,104 @@ hipError_t launch_mlp_adam(float *params, float *m, float *v, const float *grads
 // LoD to refine is chosen to minimise the expected facet-pair work
 // C(s) = c_s + sum_{l>s} c_l P(y >= l), c_l = sqrt(n_r n_s) at LoD l (a pair
 // is assumed to resolve at s when its label is <= s).
-__device__ __forceinline__ void pair_features_dev(const FeatSide &R, const FeatSide &S, const StartIn &c, float *f,
-                                                  float *cost)
+// Feature q of a candidate (computed by lane q of its wave): the same
+// expressions as the logged features, in FP64 rounded once.
+__device__ __forceinline__ float pair_feature(const FeatSide &R, const FeatSide &S, const StartIn &c, int q)
 {
-    f[0] = (float)log1p(fmax(c.lb, 0.0));
-    f[1] = (float)log1p(c.tau);
-    f[2] = (float)log1p(fmax(c.ub, 0.0));
-    f[3] = (float)fmin(1.0, fmax(0.0, (c.tau - c.lb) / fmax(c.ub - c.lb, 1e-9)));
-    for (int l = 0; l < 4; ++l) {
-        const int lr = min(l, R.L - 1);
-        const float2 a = R.lodmax[(int64_t)c.r * R.L + lr], b = S.lodmax[(int64_t)c.s * S.L + lr];
-        const double nr = R.tcnt[(int64_t)c.r * R.L + lr], ns = S.tcnt[(int64_t)c.s * S.L + lr];
-        f[4 + 3 * l] = (float)log1p((double)a.x + b.x);
-        f[5 + 3 * l] = (float)log1p((double)a.y + b.y);
-        f[6 + 3 * l] = (float)(log2(fmax(nr * ns, 1.0)) / 16.0);
-        cost[l] = (float)sqrt(nr * ns);
-    }
+    if (q == 0) return (float)log1p(fmax(c.lb, 0.0));
+    if (q == 1) return (float)log1p(c.tau);
+    if (q == 2) return (float)log1p(fmax(c.ub, 0.0));
+    if (q == 3) return (float)fmin(1.0, fmax(0.0, (c.tau - c.lb) / fmax(c.ub - c.lb, 1e-9)));
+    const int l = (q - 4) / 3, m = (q - 4) % 3;
+    const int lr = min(l, R.L - 1);
+    const float2 a = R.lodmax[(int64_t)c.r * R.L + lr], b = S.lodmax[(int64_t)c.s * S.L + lr];
+    if (m == 0) return (float)log1p((double)a.x + b.x);
+    if (m == 1) return (float)log1p((double)a.y + b.y);
+    const double nr = R.tcnt[(int64_t)c.r * R.L + lr], ns = S.tcnt[(int64_t)c.s * S.L + lr];
+    return (float)(log2(fmax(nr * ns, 1.0)) / 16.0);
 }
 
-__global__ __launch_bounds__(128) void k_mlp_start(const float *params, const float *norm, FeatSide R, FeatSide S,
+// One wave per candidate (a workgroup's four waves stride over them, the
+// BF16 weights staged once per workgroup): lane q < 16 computes feature q,
+// lane j of 64 hidden unit j of each layer (its inputs broadcast from LDS,
+// summed in the same order as the training kernels), lanes 0..3 the logits,
+// lane 0 the choice.
+__global__ __launch_bounds__(256) void k_mlp_start(const float *params, const float *norm, FeatSide R, FeatSide S,
                                                    const StartIn *in, int n, int32_t *start)
 {
     __shared__ float w[MLP_NPARAM];
+    __shared__ float act[4][MLP_H + MLP_IN];
     stage(params, w);
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= n) return;
-    float xs[MLP_IN], cost[MLP_OUT], z1[MLP_H], z2[MLP_H], lg[MLP_OUT];
-    pair_features_dev(R, S, in[b], xs, cost);
-    for (int i = 0; i < MLP_IN; ++i) xs[i] = (xs[i] - norm[i]) / norm[MLP_IN + i];
-    forward1(w, xs, z1, z2, lg);
-    float m = fmaxf(fmaxf(lg[0], lg[1]), fmaxf(lg[2], lg[3]));
-    float e[MLP_OUT], se = 0.0f;
-    for (int j = 0; j < MLP_OUT; ++j) {
-        e[j] = expf(lg[j] - m);
-        se += e[j];
-    }
-    float tail[MLP_OUT + 1];  // tail[l] = P(y >= l)
-    tail[MLP_OUT] = 0.0f;
-    for (int j = MLP_OUT - 1; j >= 0; --j) tail[j] = tail[j + 1] + e[j] / se;
-    const int nl = min(R.L, MLP_OUT);
-    int best = 0;
-    float bc = 3.4e38f;
-    for (int s = 0; s < nl; ++s) {
-        float c = cost[s];
-        for (int l = s + 1; l < nl; ++l) c += cost[l] * tail[l];
-        if (c < bc) {
-            bc = c;
-            best = s;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    float *xs = act[wv] + MLP_H;  // features, then the hidden activations in act[wv][0..63]
+    float *hs = act[wv];
+    // every wave runs the same iterations (the barriers are workgroup-wide);
+    // a wave past the end computes on a copy of the last candidate and stores
+    // nothing
+    for (int b0 = blockIdx.x * 4; b0 < n; b0 += gridDim.x * 4) {
+        const int b = b0 + wv;
+        const StartIn c = in[min(b, n - 1)];
+        if (lane < MLP_IN) xs[lane] = (pair_feature(R, S, c, lane) - norm[lane]) / norm[MLP_IN + lane];
+        float cost = 0.0f;  // lane l < 4: the work of LoD l
+        if (lane < MLP_OUT) {
+            const int lr = min(lane, R.L - 1);
+            cost = (float)sqrt((double)R.tcnt[(int64_t)c.r * R.L + lr] * (double)S.tcnt[(int64_t)c.s * S.L + lr]);
         }
+        __syncthreads();
+        float a = w[OFF_B1 + lane];
+        for (int i = 0; i < MLP_IN; ++i) a = fmaf(xs[i], w[OFF_W1 + i * MLP_H + lane], a);
+        __syncthreads();
+        hs[lane] = fmaxf(a, 0.0f);
+        __syncthreads();
+        a = w[OFF_B2 + lane];
+        for (int i = 0; i < MLP_H; ++i) a = fmaf(hs[i], w[OFF_W2 + i * MLP_H + lane], a);
+        __syncthreads();
+        hs[lane] = fmaxf(a, 0.0f);
+        __syncthreads();
+        float lg = 0.0f;
+        if (lane < MLP_OUT) {
+            lg = w[OFF_B3 + lane];
+            for (int i = 0; i < MLP_H; ++i) lg = fmaf(hs[i], w[OFF_W3 + i * MLP_OUT + lane], lg);
+        }
+        // logits and costs to lane 0
+        float L4[MLP_OUT], C4[MLP_OUT];
+        for (int j = 0; j < MLP_OUT; ++j) {
+            L4[j] = __shfl(lg, j, 64);
+            C4[j] = __shfl(cost, j, 64);
+        }
+        if (lane == 0 && b < n) {
+            const float m = fmaxf(fmaxf(L4[0], L4[1]), fmaxf(L4[2], L4[3]));
+            float e[MLP_OUT], se = 0.0f;
+            for (int j = 0; j < MLP_OUT; ++j) {
+                e[j] = expf(L4[j] - m);
+                se += e[j];
+            }
+            float tail[MLP_OUT + 1];  // tail[l] = P(y >= l)
+            tail[MLP_OUT] = 0.0f;
+            for (int j = MLP_OUT - 1; j >= 0; --j) tail[j] = tail[j + 1] + e[j] / se;
+            const int nl = min(R.L, MLP_OUT);
+            int best = 0;
+            float bc = 3.4e38f;
+            for (int s0 = 0; s0 < nl; ++s0) {
+                float cc = C4[s0];
+                for (int l = s0 + 1; l < nl; ++l) cc += C4[l] * tail[l];
+                if (cc < bc) {
+                    bc = cc;
+                    best = s0;
+                }
+            }
+            start[b] = best;
+        }
+        __syncthreads();
     }
-    start[b] = best;
 }
 
 hipError_t launch_mlp_start(const float *params, const float *norm, FeatSide R, FeatSide S, const StartIn *in, int n,
                             int32_t *start, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mlp_start, dim3((n + 127) / 128), dim3(128), 0, st, params, norm, R, S, in, n, start);
+    const int blocks = (int)std::min<int64_t>(((int64_t)n + 3) / 4, 4096);
+    hipLaunchKernelGGL(k_mlp_start, dim3(blocks), dim3(256), 0, st, params, norm, R, S, in, n, start);
     return hipGetLastError();
 }
 
