@@ -332,10 +332,10 @@ WORKLOADS = {
                   desc="large intersection join: {nr} blobs (80..5120 triangles) x {ns} tubes (336..20496 "
                        "triangles), 20000^3 box, tau = 0; timed on HBM-resident mesh sets, with the same join on "
                        "host-resident sets under a 32 GB device cap reported beside it"),
-    # capped: host-resident sets under a 64 MB device cap, so that every LoD
+    # capped: host-resident sets under a 256 MB device cap, so that every LoD
     # round streams in many chunks (the overlap study of the chunk pipeline)
     "multilod": dict(builder="config_multilod", taus=TAUS, ctx={}, cpu_gap=5.0,
-                     capped=dict(host_resident=True, mem_cap_bytes=64 << 20),
+                     capped=dict(host_resident=True, mem_cap_bytes=256 << 20),
                      desc="multilod within-tau join: {nr} blobs (80/320/1280/5120 triangles) x {ns} tubes "
                           "(336..20496 triangles), 500^3 box, tau in {{0, 5, 20}} per step"),
     "learned": dict(builder="config_learned", taus=(10.0,), ctx={}, cpu_gap=10.0,
@@ -472,7 +472,7 @@ def main():
     ap.add_argument("--ablations", type=int, default=1, help="one step each without the learned skip / culling")
     ap.add_argument("--capped-steps", type=int, default=5,
                     help="timed steps on host-resident sets under the workload's device cap (large: 32 GB, "
-                         "multilod: 64 MB), then the overlap study (0: skip)")
+                         "multilod: 256 MB), then the overlap study (0: skip)")
     ap.add_argument("--side", default="multilod,learned,knn",
                     help="large: other workloads measured in the same run (comma list, or 'none')")
     ap.add_argument("--side-steps", type=int, default=3)
@@ -603,12 +603,16 @@ def main():
         # streaming overlap: the same capped join with one staging set (gather,
         # upload, compute and download of each chunk one after another), two
         # and three sets (the next chunks gathered and uploaded while one
-        # computes)
+        # computes).  Each set gets the room one set has under the
+        # configuration's cap with its two sets (the cap scales with the
+        # sets), so the chunks are the same and only the overlap differs.
         overlap = {}
         for sets in (1, 2, 3):
+            cap = wl["capped"]["mem_cap_bytes"] * sets // 2
             t = one_step(pj, stream, hR, hS, taus, k=kk, mark=f"capped stage_sets={sets}",
-                         **dict(wl["capped"], stage_sets=sets), **timed, **tune)
-            overlap[f"stage_sets_{sets}"] = {"ms": t["ms"], "refine_ms": t["refine_ms"], "kernel_ms": t["kms"],
+                         **dict(wl["capped"], stage_sets=sets, mem_cap_bytes=cap), **timed, **tune)
+            overlap[f"stage_sets_{sets}"] = {"mem_cap_bytes": cap, "ms": t["ms"], "refine_ms": t["refine_ms"],
+                                             "kernel_ms": t["kms"],
                                              "prep_ms": t["prep_ms"], "chunks": t["chunks"],
                                              "staged_bytes": t["staged"], "peak_device_bytes": t["peak"],
                                              "results_match": t["digest"] == digest}

@@ -2114,11 +2114,17 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
         c.stage_bytes = std::max(hostR ? c.sR.end : 0, hostS ? c.sS.end : 0);
     }
     const int nthreads = prep_threads(ctx);
+    // the largest chunk of the round sizes every set's buffers once
+    int64_t rnd_ni = 0, rnd_nt = 0, rnd_stage = 0;
+    for (const Chunk &c : chunks) {
+        rnd_ni = std::max<int64_t>(rnd_ni, (int64_t)c.items.size());
+        rnd_nt = std::max<int64_t>(rnd_nt, c.t1 - c.t0);
+        rnd_stage = std::max<int64_t>(rnd_stage, (int64_t)c.stage_bytes);
+    }
     // buffers of chunk j's set (main thread: HIP allocation calls stay here)
     auto alloc = [&](int j) -> pj_status {
         const int b = j % nsets;
-        const Chunk &c = chunks[j];
-        const int64_t cni = (int64_t)c.items.size(), cnt = c.t1 - c.t0;
+        const int64_t cni = rnd_ni, cnt = rnd_nt;
         if (cni > ctx->rcap_i[b] || cnt > ctx->rcap_t[b]) {
             // grow by half at least (new addresses mean a new graph); under a
             // memory cap exactly (the chunks were sized to what it leaves)
@@ -2133,8 +2139,8 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
         PJTRY(ensure(ctx, ctx->sb_rnd[b], bytes));
         PJTRY(ensure_pinned(ctx, ctx->pin_rnd[b], bytes));
         if (staged) {
-            PJTRY(ensure(ctx, ctx->sb_stage[b], c.stage_bytes));
-            PJTRY(ensure_pinned(ctx, ctx->pin_stage[b], c.stage_bytes));
+            PJTRY(ensure(ctx, ctx->sb_stage[b], (size_t)rnd_stage));
+            PJTRY(ensure_pinned(ctx, ctx->pin_stage[b], (size_t)rnd_stage));
         }
         return PJ_OK;
     };
