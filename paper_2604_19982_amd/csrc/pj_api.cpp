@@ -1935,15 +1935,20 @@ pj_status for_staged(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, Ti
     return PJ_OK;
 }
 
-// Launch one chunk's refinement on `st` (from a cached hipGraph or directly).
+// Launch one chunk's refinement on `st`: the round's init kernel, then the
+// refinement kernel (from a cached hipGraph of that one launch, or directly),
+// with the events `e0`, `e1` (if given) around the latter only, so that they
+// time the refinement kernel.
 pj_status launch_round(pj_context *ctx, const RefineArgs &a, int32_t *ctr, int ni, int nt, int wpc, bool graph,
-                       hipStream_t st)
+                       hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
 {
     // persistent grid: fixed size, the kernel reads the tile count from memory
     const int grid = ctx->num_cu * wpc;
+    HIPTRY(ctx, launch_init_round(a.out, ctr, a.wave_slot, grid, a.tile_cur, st));
+    if (e0) HIPTRY(ctx, hipEventRecord(e0, st));
     if (!graph) {
-        HIPTRY(ctx, launch_init_round(a.out, ctr, a.wave_slot, grid, a.tile_cur, st));
         HIPTRY(ctx, launch_refine_f32(a, std::min<int64_t>(nt, grid), kP, st));
+        if (e1) HIPTRY(ctx, hipEventRecord(e1, st));
         return PJ_OK;
     }
     std::vector<char> key(sizeof(a) + sizeof(int));
@@ -1956,8 +1961,7 @@ pj_status launch_round(pj_context *ctx, const RefineArgs &a, int32_t *ctr, int n
         if (!ctx->cap_stream) HIPTRY(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
         hipGraph_t graph = nullptr;
         HIPTRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e1 = launch_init_round(a.out, ctr, a.wave_slot, grid, a.tile_cur, ctx->cap_stream);
-        hipError_t e2 = e1 == hipSuccess ? launch_refine_f32(a, grid, kP, ctx->cap_stream) : e1;
+        hipError_t e2 = launch_refine_f32(a, grid, kP, ctx->cap_stream);
         hipError_t e3 = hipStreamEndCapture(ctx->cap_stream, &graph);
         if (e2 != hipSuccess) return hipfail(ctx, e2, "capture of the refinement round");
         if (e3 != hipSuccess) return hipfail(ctx, e3, "hipStreamEndCapture");
@@ -1971,6 +1975,7 @@ pj_status launch_round(pj_context *ctx, const RefineArgs &a, int32_t *ctr, int n
         ctx->graphs.push_back(pj_context::GraphEntry{key, exec});
     }
     HIPTRY(ctx, hipGraphLaunch(exec, st));
+    if (e1) HIPTRY(ctx, hipEventRecord(e1, st));
     ctx->stats.graph_replays++;
     return PJ_OK;
 }
@@ -2226,9 +2231,7 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
         a.vmask = ctx->vmask;
         a.vrow = ctx->vrow;
         if (!one) HIPTRY(ctx, hipStreamWaitEvent(st, ctx->ev_h2d[b], 0));
-        HIPTRY(ctx, hipEventRecord(ctx->ev_k0[b], st));
-        PJTRY(launch_round(ctx, a, dctr, cni, cnt, wpc, graph, st));
-        HIPTRY(ctx, hipEventRecord(ctx->ev_k1[b], st));
+        PJTRY(launch_round(ctx, a, dctr, cni, cnt, wpc, graph, st, ctx->ev_k0[b], ctx->ev_k1[b]));
         if (!one) {
             HIPTRY(ctx, hipEventRecord(ctx->ev_comp[b], st));
             HIPTRY(ctx, hipStreamWaitEvent(downs, ctx->ev_comp[b], 0));
