@@ -23,6 +23,22 @@ def test_tube_blocks_do_not_change_arrays(monkeypatch):
     assert all(np.array_equal(x, y) for x, y in zip(_arrays(a), _arrays(b)))
 
 
+def test_worker_processes_and_threads_give_one_pass_arrays(monkeypatch):
+    """Large sets are built in blocks by forked workers, or by threads of the
+    process once it has opened the GPU; both write the same arrays as one
+    serial pass."""
+    monkeypatch.setattr(mg, "BLOB_BLOCK_VALUES", 3 * 642)
+    monkeypatch.setattr(mg, "TUBE_BLOCK", 5)
+    ref_b = mg.blob_set(mg.rng_for(9, 0), 37, (0.0, 50.0), 1, 3, radius_sigma=0.3, workers=1)
+    ref_t = mg.tube_set(mg.rng_for(9, 1), 23, (0.0, 50.0), 64, 3, workers=1)
+    for opened in (False, True):
+        monkeypatch.setattr(mg, "_gpu_opened", lambda: opened)
+        b = mg.blob_set(mg.rng_for(9, 0), 37, (0.0, 50.0), 1, 3, radius_sigma=0.3, workers=4)
+        t = mg.tube_set(mg.rng_for(9, 1), 23, (0.0, 50.0), 64, 3, workers=4)
+        assert all(np.array_equal(x, y) for x, y in zip(_arrays(ref_b), _arrays(b))), opened
+        assert all(np.array_equal(x, y) for x, y in zip(_arrays(ref_t), _arrays(t))), opened
+
+
 def test_multilod_structure():
     R, S = mg.config_multilod(seed=1, n_r=7, n_s=3, box=50.0, n_seg=64)
     assert R.n_lods == S.n_lods == 4
