@@ -113,6 +113,28 @@ struct TmpDev {
 
 enum Status : int8_t { ST_UNDEC = 0, ST_CONF = 1, ST_PRUNED = 2, ST_BAND = 3 };
 
+struct Cand {
+    int32_t r, s;
+    float lb0, ub0;  // filter bounds
+};
+
+struct PairState {  // 80 bytes
+    int8_t status = ST_UNDEC;
+    int8_t lod_done = -1;
+    int8_t res_lod = -1;    // LoD round that decided the pair
+    int hit64 = 0;
+    float eps = 0.0f;
+    float ox = 0, oy = 0, oz = 0;
+    float thr = INFINITY;   // collect threshold on the FP32 lower distance
+    double LB = 0.0, UB = INFINITY;
+    double M = 0.0;
+    double d64 = INFINITY;  // FP64 finest distance once known
+    // bounds when the first LoD was chosen (after the box and voxel
+    // filters): the LoD model's gap and upper-bound features
+    double f_lb = 0.0, f_ub = INFINITY;
+};
+static_assert(sizeof(PairState) == 80, "PairState layout");
+
 }  // namespace
 
 struct pj_meshes {
@@ -303,6 +325,11 @@ struct pj_context {
     PinBuf pin_cand;  // the filter's candidate count and arrays on their way to the host
     PinBuf pin_start; // the learned skip's inputs up, first LoDs down
     PinBuf pin_vin[2];
+    PinBuf pin_vrow;  // the voxel filter's row map up, its pair bounds and survivor counts down
+    // a within join's candidates and their states, kept between joins so
+    // that their host memory is reused
+    std::vector<Cand> j_cand;
+    std::vector<PairState> j_ps;
     hipEvent_t ev_vcomp[2] = {};
     const unsigned long long *vmask = nullptr;  // surviving voxel pairs of the join's candidates (device)
     const int32_t *vrow = nullptr;              // per candidate: its block of rows in vmask, -1 for none
@@ -507,6 +534,7 @@ extern "C" pj_status pj_context_destroy(pj_context *ctx)
     }
     if (ctx->pin_cand.p) (void)hipHostFree(ctx->pin_cand.p);
     if (ctx->pin_start.p) (void)hipHostFree(ctx->pin_start.p);
+    if (ctx->pin_vrow.p) (void)hipHostFree(ctx->pin_vrow.p);
     for (int b = 0; b < 2; ++b) {
         if (ctx->pin_vin[b].p) (void)hipHostFree(ctx->pin_vin[b].p);
         if (ctx->ev_vcomp[b]) (void)hipEventDestroy(ctx->ev_vcomp[b]);
@@ -1309,27 +1337,6 @@ extern "C" pj_status pj_meshes_hdph(const pj_meshes *m, int32_t obj, int32_t lod
 namespace {
 
 constexpr int kP = 1;  // A facets per lane in the FP32 kernel
-
-struct Cand {
-    int32_t r, s;
-    float lb0, ub0;  // filter bounds
-};
-
-struct PairState {
-    int8_t status = ST_UNDEC;
-    int8_t lod_done = -1;
-    double LB = 0.0, UB = INFINITY;
-    float eps = 0.0f;
-    double M = 0.0;
-    float ox = 0, oy = 0, oz = 0;
-    double d64 = INFINITY;  // FP64 finest distance once known
-    int hit64 = 0;
-    float thr = INFINITY;   // collect threshold on the FP32 lower distance
-    int8_t res_lod = -1;    // LoD round that decided the pair
-    // bounds when the first LoD was chosen (after the box and voxel
-    // filters): the LoD model's gap and upper-bound features
-    double f_lb = 0.0, f_ub = INFINITY;
-};
 
 void pair_frame(const pj_meshes *R, int r, const pj_meshes *S, int s, PairState &ps)
 {
@@ -2794,27 +2801,30 @@ void begin_join(pj_context *ctx)
     ctx->peak_bytes = ctx->dev_bytes;
 }
 
-// Progressive refinement of within-tau candidates (Section 3.1): returns the
-// confirmed candidate indices.
+// Progressive refinement of within-tau candidates (Section 3.1).  `live`
+// holds the undecided candidates in index order; each round refines those
+// whose first LoD has come and drops the decided ones from the list.
 pj_status refine_within(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, double tau, std::vector<Cand> &cand,
-                        std::vector<PairState> &ps, std::vector<int> &start_lod)
+                        std::vector<PairState> &ps, std::vector<int> &start_lod, std::vector<int> &live)
 {
     const int L = R->L;
     const bool plain = ctx->cfg.schedule == PJ_SCHED_PLAIN;
     const bool fp64 = plain || ctx->cfg.precision == PJ_PREC_FP64;
     const int TS = pick_tile_s(ctx);
     TilePlan pl;
+    std::vector<int> act;
     for (int lod = 0; lod < L; ++lod) {
         const bool finest = lod == L - 1;
-        std::vector<int> act;
-        for (int i = 0; i < (int)cand.size(); ++i)
-            if (ps[i].status == ST_UNDEC && start_lod[i] <= lod) act.push_back(i);
-        if (act.empty()) {
-            bool any = false;
-            for (int i = 0; i < (int)cand.size(); ++i) any |= ps[i].status == ST_UNDEC;
-            if (!any) break;
-            continue;
-        }
+        act.clear();
+        size_t nl = 0;
+        for (int i : live)
+            if (ps[i].status == ST_UNDEC) {
+                live[nl++] = i;
+                if (start_lod[i] <= lod) act.push_back(i);
+            }
+        live.resize(nl);
+        if (live.empty()) break;
+        if (act.empty()) continue;
         ctx->stats.rounds++;
         if (fp64) {
             plan_tiles(R, S, act, cand, ps, lod, finest, 64, TS, !plain, pl);
@@ -2873,9 +2883,10 @@ pj_status refine_within(pj_context *ctx, const pj_meshes *R, const pj_meshes *S,
         }
     }
     // guard band: FP64 with the exact meet test on the facet pairs that can
-    // still decide (FP32 lower distance <= tau + eps)
+    // still decide (FP32 lower distance <= tau + eps); they were undecided
+    // when the finest round began
     std::vector<int> band;
-    for (int i = 0; i < (int)cand.size(); ++i)
+    for (int i : act)
         if (ps[i].status == ST_BAND) {
             band.push_back(i);
             ps[i].thr = (float)tau + ps[i].eps;
@@ -2983,11 +2994,15 @@ bool load_model(pj_context *ctx, const char *path)
 // pairs have no prediction.
 pj_status learned_start(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, double tau, const std::vector<Cand> &cand,
                         const std::vector<PairState> &ps, std::vector<int> &start,
-                        const std::vector<float> *tau_of = nullptr)
+                        const std::vector<float> *tau_of = nullptr, const std::vector<int> *live = nullptr)
 {
+    // the undecided candidates (all of them in `live` when it is given)
     std::vector<int> idx;
-    for (size_t i = 0; i < cand.size(); ++i)
-        if (ps[i].status == ST_UNDEC) idx.push_back((int)i);
+    if (live)
+        idx = *live;
+    else
+        for (size_t i = 0; i < cand.size(); ++i)
+            if (ps[i].status == ST_UNDEC) idx.push_back((int)i);
     const int n = (int)idx.size();
     if (n == 0) return PJ_OK;
     hipStream_t st = ctx->stream;
@@ -3039,11 +3054,12 @@ extern "C" pj_status pj_join_within(pj_context *ctx, const pj_meshes *R, const p
         ctx->stats.t_total_ms = now_ms() - t0;
         return PJ_OK;
     }
-    std::vector<Cand> cand;
+    std::vector<Cand> &cand = ctx->j_cand;
     PJTRY(mbb_filter(ctx, R, S, tau, cand));
     const int nc = (int)cand.size();
     ctx->stats.candidates = nc;
-    std::vector<PairState> ps(nc);
+    std::vector<PairState> &ps = ctx->j_ps;
+    ps.assign(nc, PairState{});
     std::vector<int> start(nc, 0);
     host_for(ctx, nc, [&](int64_t i) {
         pair_frame(R, cand[i].r, S, cand[i].s, ps[i]);
@@ -3053,30 +3069,37 @@ extern "C" pj_status pj_join_within(pj_context *ctx, const pj_meshes *R, const p
         if (cand[i].ub0 <= tau) ps[i].status = ST_CONF;
         else if (cand[i].lb0 > tau) ps[i].status = ST_PRUNED;
     });
-    for (int i = 0; i < nc; ++i) ctx->stats.confirmed_filter += ps[i].status == ST_CONF;
+    // the undecided candidates in index order: the later passes visit only
+    // these (most candidates are decided by their box bounds)
+    std::vector<int> live;
+    for (int i = 0; i < nc; ++i) {
+        ctx->stats.confirmed_filter += ps[i].status == ST_CONF;
+        if (ps[i].status == ST_UNDEC) live.push_back(i);
+    }
     if (ctx->cfg.voxels && ctx->cfg.schedule == PJ_SCHED_BATCHED) {
         // voxel-pair filtering of the undecided pairs (Section 3.2)
-        std::vector<int> und;
-        for (int i = 0; i < nc; ++i)
-            if (ps[i].status == ST_UNDEC) und.push_back(i);
-        PJTRY(voxel_filter(ctx, R, S, cand, ps, und, (float)tau));
-        if (ctx->vmask)
-            for (int i : und) {
+        PJTRY(voxel_filter(ctx, R, S, cand, ps, live, (float)tau));
+        if (ctx->vmask) {
+            size_t nl = 0;
+            for (int i : live) {
                 if (ps[i].UB <= tau) ps[i].status = ST_CONF;
                 else if (ps[i].LB > tau) ps[i].status = ST_PRUNED;
                 ctx->stats.voxel_decided += ps[i].status != ST_UNDEC;
+                if (ps[i].status == ST_UNDEC) live[nl++] = i;
             }
+            live.resize(nl);
+        }
     }
-    for (int i = 0; i < nc; ++i) {
+    for (int i : live) {
         ps[i].f_lb = ps[i].LB;
         ps[i].f_ub = ps[i].UB;
     }
     const bool learned = ctx->cfg.learned_skip && ctx->has_model && R->L == MLP_OUT &&
                          ctx->cfg.schedule == PJ_SCHED_BATCHED;
-    if (learned) PJTRY(learned_start(ctx, R, S, tau, cand, ps, start));
+    if (learned) PJTRY(learned_start(ctx, R, S, tau, cand, ps, start, nullptr, &live));
     double t1 = now_ms();
     ctx->stats.t_filter_ms = t1 - t0;
-    PJTRY(refine_within(ctx, R, S, tau, cand, ps, start));
+    PJTRY(refine_within(ctx, R, S, tau, cand, ps, start, live));
     if (!learned) append_log(ctx, R, S, tau, cand, ps);
     ctx->stats.t_refine_ms = now_ms() - t1 - ctx->stats.t_band_ms;
     std::vector<int> res;
@@ -3120,6 +3143,10 @@ extern "C" pj_status pj_join_within(pj_context *ctx, const pj_meshes *R, const p
         if (out->dist) out->dist[k] = ps[res[k]].hit64 ? 0.0 : ps[res[k]].d64;
     }
     ctx->stats.peak_device_bytes = ctx->peak_bytes;
+    if (ps.capacity() > (size_t(1) << 20)) {  // hold at most about 100 MB between joins
+        std::vector<Cand>().swap(cand);
+        std::vector<PairState>().swap(ps);
+    }
     ctx->stats.t_total_ms = now_ms() - t0;
     return PJ_OK;
 }
@@ -3167,11 +3194,15 @@ pj_status voxel_filter(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
     PJTRY(ensure(ctx, ctx->b_vmask, std::max<int64_t>(nidx, 1) * kMaxVox * 8));
     PJTRY(ensure(ctx, ctx->b_vrow, cand.size() * 4));
     HIPTRY(ctx, hipMemsetAsync(ctx->b_vmask.p, 0xff, std::max<int64_t>(nidx, 1) * kMaxVox * 8, st));
+    // the row map goes up from pinned memory, which the bounds come back
+    // through at the end (the join stream is synchronised before that)
+    const size_t tot_off = align256(std::max<int64_t>(nidx, 1) * 8);  // survivors per chunk after the bounds
+    PJTRY(ensure_pinned(ctx, ctx->pin_vrow, std::max<size_t>(cand.size() * 4, tot_off + 8 * (size_t)(1 + cand.size()))));
     {
-        std::vector<int32_t> vrow(cand.size(), -1);
+        int32_t *vrow = (int32_t *)ctx->pin_vrow.p;
+        std::fill(vrow, vrow + cand.size(), -1);
         for (int64_t q = 0; q < nidx; ++q) vrow[idx[q]] = (int32_t)q;
-        HIPTRY(ctx, hipMemcpyAsync(ctx->b_vrow.p, vrow.data(), vrow.size() * 4, hipMemcpyHostToDevice, st));
-        HIPTRY(ctx, hipStreamSynchronize(st));
+        HIPTRY(ctx, hipMemcpyAsync(ctx->b_vrow.p, vrow, cand.size() * 4, hipMemcpyHostToDevice, st));
     }
     // voxel pairs per chunk: each costs 4 B of lb_v and 4 B of survivors in
     // each of the two output sets; under a cap, what is left after the pair
@@ -3210,8 +3241,8 @@ pj_status voxel_filter(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
     }
     PJTRY(ensure(ctx, ctx->b_vplb, max_vp * 4));
     // pair bounds of every processed candidate (float lb, ub), read back once
-    PJTRY(ensure(ctx, ctx->b_vpub, std::max<int64_t>(nidx, 1) * 8 + 256 + 8 * (int64_t)nch));
-    int64_t *dtot = (int64_t *)((char *)ctx->b_vpub.p + align256(std::max<int64_t>(nidx, 1) * 8));  // survivors per chunk
+    PJTRY(ensure(ctx, ctx->b_vpub, tot_off + 8 * (int64_t)nch));
+    int64_t *dtot = (int64_t *)((char *)ctx->b_vpub.p + tot_off);  // survivors per chunk
     // per set: in = cr, cs (int32), vp_off (int64, np + 1); out = count
     // (int32), blk_off (int64, np + 1), survivors (uint32)
     const size_t in_bytes = align256(8 * max_np) + align256(8 * (max_np + 1));
@@ -3254,11 +3285,12 @@ pj_status voxel_filter(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
         HIPTRY(ctx, launch_vp_rows((int)q0, np, boff, vpairs, ptr<unsigned long long>(ctx->b_vmask), st));
         HIPTRY(ctx, hipEventRecord(ctx->ev_vcomp[b], st));
     }
-    std::vector<float> hop(2 * std::max<int64_t>(nidx, 1));
-    std::vector<int64_t> htot(std::max(nch, 1), 0);
-    if (nidx) HIPTRY(ctx, hipMemcpyAsync(hop.data(), op, 8 * nidx, hipMemcpyDeviceToHost, st));
-    if (nch) HIPTRY(ctx, hipMemcpyAsync(htot.data(), dtot, 8 * nch, hipMemcpyDeviceToHost, st));
+    // bounds and survivor counts in one copy (the row map upload, ahead on
+    // the same stream, has read the pinned buffer by then)
+    HIPTRY(ctx, hipMemcpyAsync(ctx->pin_vrow.p, op, tot_off + 8 * (size_t)nch, hipMemcpyDeviceToHost, st));
     HIPTRY(ctx, hipStreamSynchronize(st));
+    const float *hop = (const float *)ctx->pin_vrow.p;
+    const int64_t *htot = (const int64_t *)((const char *)ctx->pin_vrow.p + tot_off);
     for (int c = 0; c < nch; ++c) ctx->stats.vp_kept += htot[c];
     for (int64_t q = 0; q < nidx; ++q) {
         PairState &p = ps[idx[q]];
