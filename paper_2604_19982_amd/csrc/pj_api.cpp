@@ -299,6 +299,7 @@ struct pj_context {
     int num_cu = 256;
     int64_t dev_bytes = 0, peak_bytes = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    DevBuf b_fslot;  // the grid filter's per-r slots
     DevBuf b_items, b_tiles, b_out, b_out64, b_ctr, b_cand_r, b_cand_s, b_cand_lb, b_cand_ub, b_blk, b_blkoff,
         b_total, b_tmp0, b_tmp1, b_tmp2, b_tmp3, b_coll, b_ovf, b_theta, b_koff, b_klb, b_kub, b_kst0, b_kst1,
         b_kleft, b_gcell, b_gcnt, b_gfill, b_vplb, b_vpub, b_vmask, b_vrow,
@@ -2730,11 +2731,13 @@ pj_status mbb_filter_grid(pj_context *ctx, const pj_meshes *R, const pj_meshes *
     PJTRY(ensure(ctx, ctx->b_total, 16));
     PJTRY(ensure(ctx, ctx->b_blk, (size_t)nR * 4));
     PJTRY(ensure(ctx, ctx->b_blkoff, (size_t)(nR + 3 + nR / 4096) * 8));
+    PJTRY(ensure(ctx, ctx->b_fslot, (size_t)nR * kFilterSlots * 4));
+    int32_t *slot = ptr<int32_t>(ctx->b_fslot);
     // reach: the largest gap the squared test can keep, rounded up
     const float reach = up_float(std::sqrt((double)tau2) * (1.0 + std::ldexp(1.0, -20)));
     HIPTRY(ctx, launch_filter_grid(R->d_box, R->d_anchor, nR, S->d_box, S->d_anchor, reach, tau2, g, G->beg,
-                                   G->items, ptr<int32_t>(ctx->b_blk), nullptr, nullptr, nullptr, nullptr, nullptr, 0,
-                                   st));
+                                   G->items, ptr<int32_t>(ctx->b_blk), slot, nullptr, nullptr, nullptr, nullptr,
+                                   nullptr, 0, st));
     HIPTRY(ctx, launch_scan_large(ptr<int32_t>(ctx->b_blk), ptr<int64_t>(ctx->b_blkoff), ptr<int64_t>(ctx->b_total), nR,
                                   st));
     int64_t total = 0;
@@ -2746,7 +2749,8 @@ pj_status mbb_filter_grid(pj_context *ctx, const pj_meshes *R, const pj_meshes *
     int32_t *d_cr = ptr<int32_t>(ctx->b_cand_r), *d_cs = d_cr + total;
     float *d_lb = reinterpret_cast<float *>(d_cs + total), *d_ub = d_lb + total;
     HIPTRY(ctx, launch_filter_grid(R->d_box, R->d_anchor, nR, S->d_box, S->d_anchor, reach, tau2, g, G->beg,
-                                   G->items, nullptr, ptr<int64_t>(ctx->b_blkoff), d_cr, d_cs, d_lb, d_ub, 1, st));
+                                   G->items, ptr<int32_t>(ctx->b_blk), slot, ptr<int64_t>(ctx->b_blkoff), d_cr, d_cs,
+                                   d_lb, d_ub, 1, st));
     return download_cands(ctx, total, cand);
 }
 

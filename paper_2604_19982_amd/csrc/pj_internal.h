@@ -142,10 +142,14 @@ constexpr int kGridMaxK = 16;  // k of the grid theta kernel (registers); larger
 hipError_t launch_scan_large(const int32_t *in, int64_t *out, int64_t *total, int64_t n, hipStream_t st);
 hipError_t launch_grid_build(const float *ancS, int nS, const KnnGrid &g, int32_t *cell_of, int32_t *count,
                              int64_t *beg, int64_t *total, int32_t *fill, int32_t *items, hipStream_t st);
+// Grid filter passes.  count: per r (written by the count pass, read by the
+// write pass); slot: kFilterSlots per r, the objects the count pass found
+// for an r with at most that many.
+constexpr int kFilterSlots = 2;
 hipError_t launch_filter_grid(const float *boxR, const float *ancR, int nR, const float *boxS, const float *ancS,
                               float tau, float tau2, const KnnGrid &g, const int64_t *beg, const int32_t *items,
-                              int32_t *count, const int64_t *off, int32_t *cr, int32_t *cs, float *clb, float *cub,
-                              int write_pass, hipStream_t st);
+                              int32_t *count, int32_t *slot, const int64_t *off, int32_t *cr, int32_t *cs, float *clb,
+                              float *cub, int write_pass, hipStream_t st);
 hipError_t launch_knn_theta_grid(const float *ancR, int nR, const float *ancS, int nS, int k, const KnnGrid &g,
                                  const int64_t *beg, const int32_t *items, float *theta, hipStream_t st);
 hipError_t launch_knn_cand_grid(const float *boxR, const float *ancR, int nR, const float *boxS, const float *ancS,

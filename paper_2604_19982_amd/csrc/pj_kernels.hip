@@ -1785,15 +1785,24 @@ __global__ __launch_bounds__(256) void k_knn_cand_grid(const float *boxR, const 
 // Within-tau MBB filter through the same grid: one thread per r visits the
 // cells its box reaches (widened by tau, the widest anchor-to-box extent of S
 // and one cell) and applies the all-pairs kernel's test and bounds to each S
-// object there; count pass, then write pass in s order per r.
+// object there; count pass, then write pass in s order per r.  The count
+// pass keeps the first kFilterSlots objects it finds for r; the write pass
+// skips an r without candidates and takes an r with at most that many from
+// its slots (recomputing their bounds), so only busier r revisit the cells.
 __global__ __launch_bounds__(256) void k_filter_grid(const float *boxR, const float *ancR, int nR, const float *boxS,
                                                      const float *ancS, float tau, float tau2, KnnGrid g,
                                                      const int64_t *beg, const int32_t *items, int32_t *count,
-                                                     const int64_t *off, int32_t *cr, int32_t *cs, float *clb,
-                                                     float *cub, int write_pass)
+                                                     int32_t *slot, const int64_t *off, int32_t *cr, int32_t *cs,
+                                                     float *clb, float *cub, int write_pass)
 {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nR) return;
+    int kept = 0;  // write pass: candidates of r held in its slots (0: visit the cells)
+    if (write_pass) {
+        const int c = count[r];
+        if (c == 0) return;
+        if (c <= kFilterSlots) kept = c;
+    }
     float b[6];
     for (int c = 0; c < 6; ++c) b[c] = boxR[6 * (int64_t)r + c];
     const float o[3] = {g.ox, g.oy, g.oz}, w[3] = {g.wx, g.wy, g.wz};
@@ -1810,33 +1819,43 @@ __global__ __launch_bounds__(256) void k_filter_grid(const float *boxR, const fl
     }
     int64_t pos = write_pass ? off[r] : 0;
     int total = 0;
+    int found[kFilterSlots];
     const float ax = ancR[3 * (int64_t)r], ay = ancR[3 * (int64_t)r + 1], az = ancR[3 * (int64_t)r + 2];
-    for (int z = lo[2]; z <= hi[2]; ++z)
-        for (int y = lo[1]; y <= hi[1]; ++y) {
-            const int row = (z * g.gy + y) * g.gx;
-            for (int64_t q = beg[row + lo[0]]; q < beg[row + hi[0] + 1]; ++q) {
-                const int sidx = items[q];
-                const float *x = boxS + 6 * (int64_t)sidx;
-                const float gx = fmaxf(0.0f, fmaxf(x[0] - b[3], b[0] - x[3]));
-                const float gy = fmaxf(0.0f, fmaxf(x[1] - b[4], b[1] - x[4]));
-                const float gz = fmaxf(0.0f, fmaxf(x[2] - b[5], b[2] - x[5]));
-                const float g2 = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
-                if (g2 <= tau2) {
-                    if (write_pass) {
-                        const float *sa = ancS + 3 * (int64_t)sidx;
-                        const float dx = sa[0] - ax, dy = sa[1] - ay, dz = sa[2] - az;
-                        cr[pos] = r;
-                        cs[pos] = sidx;
-                        clb[pos] = __builtin_sqrtf(g2) * (1.0f - 0x1p-20f);
-                        cub[pos] = __builtin_sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx))) * (1.0f + 0x1p-20f);
-                    }
-                    ++pos;
-                    ++total;
-                }
+    // the box test and, in the write pass, the candidate's bounds
+    auto test = [&](const int sidx) {
+        const float *x = boxS + 6 * (int64_t)sidx;
+        const float gx = fmaxf(0.0f, fmaxf(x[0] - b[3], b[0] - x[3]));
+        const float gy = fmaxf(0.0f, fmaxf(x[1] - b[4], b[1] - x[4]));
+        const float gz = fmaxf(0.0f, fmaxf(x[2] - b[5], b[2] - x[5]));
+        const float g2 = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
+        if (g2 <= tau2) {
+            if (write_pass) {
+                const float *sa = ancS + 3 * (int64_t)sidx;
+                const float dx = sa[0] - ax, dy = sa[1] - ay, dz = sa[2] - az;
+                cr[pos] = r;
+                cs[pos] = sidx;
+                clb[pos] = __builtin_sqrtf(g2) * (1.0f - 0x1p-20f);
+                cub[pos] = __builtin_sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx))) * (1.0f + 0x1p-20f);
+            } else if (total < kFilterSlots) {
+                found[total] = sidx;
             }
+            ++pos;
+            ++total;
         }
+    };
+    if (kept > 0) {
+        for (int k = 0; k < kept; ++k) test(slot[(int64_t)kFilterSlots * r + k]);
+    } else {
+        for (int z = lo[2]; z <= hi[2]; ++z)
+            for (int y = lo[1]; y <= hi[1]; ++y) {
+                const int row = (z * g.gy + y) * g.gx;
+                for (int64_t q = beg[row + lo[0]]; q < beg[row + hi[0] + 1]; ++q) test(items[q]);
+            }
+    }
     if (!write_pass) {
         count[r] = total;
+        if (total <= kFilterSlots)
+            for (int k = 0; k < total; ++k) slot[(int64_t)kFilterSlots * r + k] = found[k];
         return;
     }
     // insertion sort of r's candidates by s
@@ -1859,13 +1878,13 @@ __global__ __launch_bounds__(256) void k_filter_grid(const float *boxR, const fl
 
 hipError_t launch_filter_grid(const float *boxR, const float *ancR, int nR, const float *boxS, const float *ancS,
                               float tau, float tau2, const KnnGrid &g, const int64_t *beg, const int32_t *items,
-                              int32_t *count, const int64_t *off, int32_t *cr, int32_t *cs, float *clb, float *cub,
-                              int write_pass, hipStream_t st)
+                              int32_t *count, int32_t *slot, const int64_t *off, int32_t *cr, int32_t *cs, float *clb,
+                              float *cub, int write_pass, hipStream_t st)
 {
     if (nR == 0) return hipSuccess;
     PJ_GRID_CHECK((nR + 255) / 256, 256);
     hipLaunchKernelGGL(k_filter_grid, dim3((nR + 255) / 256), dim3(256), 0, st, boxR, ancR, nR, boxS, ancS, tau, tau2,
-                       g, beg, items, count, off, cr, cs, clb, cub, write_pass);
+                       g, beg, items, count, slot, off, cr, cs, clb, cub, write_pass);
     return hipGetLastError();
 }
 
