@@ -2765,7 +2765,7 @@ pj_status mbb_filter(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, do
     const bool big = (double)nR * (double)nS > (double)(int64_t(1) << 26);
     if (ctx->cfg.filter_mode == 2) return mbb_filter_sweep(ctx, R, S, tau2, cand);
     if (ctx->cfg.filter_mode == 3 || (ctx->cfg.filter_mode == 0 && big)) return mbb_filter_grid(ctx, R, S, tau2, cand);
-    const int gx = (nR + 255) / 256, gy = (nS + 511) / 512;
+    const int gx = (nR + kFiltR - 1) / kFiltR, gy = (nS + kFiltS - 1) / kFiltS;
     const int nb = gx * gy;
     PJTRY(ensure(ctx, ctx->b_blk, nb * sizeof(int32_t)));
     PJTRY(ensure(ctx, ctx->b_blkoff, (nb + 1) * sizeof(int64_t)));

@@ -142,6 +142,10 @@ constexpr int kGridMaxK = 16;  // k of the grid theta kernel (registers); larger
 hipError_t launch_scan_large(const int32_t *in, int64_t *out, int64_t *total, int64_t n, hipStream_t st);
 hipError_t launch_grid_build(const float *ancS, int nS, const KnnGrid &g, int32_t *cell_of, int32_t *count,
                              int64_t *beg, int64_t *total, int32_t *fill, int32_t *items, hipStream_t st);
+// All-pairs MBB filter: a workgroup tests kFiltR objects of R (one per
+// thread) against kFiltS objects of S staged in LDS.
+constexpr int kFiltR = 256, kFiltS = 128;
+
 // Grid filter passes.  count: per r (written by the count pass, read by the
 // write pass); slot: kFilterSlots per r, the objects the count pass found
 // for an r with at most that many.

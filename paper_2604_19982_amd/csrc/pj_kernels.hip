@@ -356,7 +356,7 @@ hipError_t launch_lodmax(const MeshDev &m, float2 *lodmax, hipStream_t st)
 // Count pass -> exclusive scan of block counts -> write pass (each block
 // writes its survivors contiguously, in (thread, s) order).
 // ---------------------------------------------------------------------------
-constexpr int FILT_R = 256, FILT_S = 512;
+constexpr int FILT_R = kFiltR, FILT_S = kFiltS;
 
 __global__ __launch_bounds__(256) void k_filter(const float *boxR, const float *ancR, int nR, const float *boxS,
                                                  const float *ancS, int nS, float tau2, int32_t *blk_count,
