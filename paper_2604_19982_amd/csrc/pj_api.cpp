@@ -1947,15 +1947,30 @@ pj_status for_staged(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, Ti
 // refinement kernel (from a cached hipGraph of that one launch, or directly),
 // with the events `e0`, `e1` (if given) around the latter only, so that they
 // time the refinement kernel.
-pj_status launch_round(pj_context *ctx, const RefineArgs &a, int32_t *ctr, int ni, int nt, int wpc, bool graph,
-                       hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
+// Waves of a round's persistent launch: wpc per CU, or, for a round of fewer
+// claimable units (A blocks x B ranges), the next power of two (at least 64)
+// above their count.  More waves than units would only contend for the
+// tile counters; the power-of-two steps keep few graph variants.
+int round_grid(const pj_context *ctx, int wpc, int64_t units)
 {
-    // persistent grid: fixed size, the kernel reads the tile count from memory
-    const int grid = ctx->num_cu * wpc;
-    HIPTRY(ctx, launch_init_round(a.out, ctr, a.wave_slot, grid, a.tile_cur, st));
+    const int full = ctx->num_cu * wpc;
+    if (units <= 0 || units >= full) return full;
+    int g = 64;
+    while (g < units) g *= 2;
+    return std::min(g, full);
+}
+
+pj_status launch_round(pj_context *ctx, const RefineArgs &a, int32_t *ctr, int ni, int nt, int wpc, bool graph,
+                       hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, int64_t units = 0)
+{
+    // persistent grid of a fixed size per shape: the kernel reads the tile
+    // count from memory; the slots of the full grid are reset
+    const int full = ctx->num_cu * wpc;
+    const int grid = round_grid(ctx, wpc, units);
+    HIPTRY(ctx, launch_init_round(a.out, ctr, a.wave_slot, full, a.tile_cur, st));
     if (e0) HIPTRY(ctx, hipEventRecord(e0, st));
     if (!graph) {
-        HIPTRY(ctx, launch_refine_f32(a, std::min<int64_t>(nt, grid), kP, st));
+        HIPTRY(ctx, launch_refine_f32(a, units > 0 ? grid : std::min<int64_t>(nt, grid), kP, st));
         if (e1) HIPTRY(ctx, hipEventRecord(e1, st));
         return PJ_OK;
     }
@@ -1976,7 +1991,7 @@ pj_status launch_round(pj_context *ctx, const RefineArgs &a, int32_t *ctr, int n
         hipError_t e4 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (e4 != hipSuccess) return hipfail(ctx, e4, "hipGraphInstantiate");
-        if (ctx->graphs.size() >= 16) {
+        if (ctx->graphs.size() >= 32) {
             (void)hipGraphExecDestroy(ctx->graphs.front().exec);
             ctx->graphs.erase(ctx->graphs.begin());
         }
@@ -2239,7 +2254,10 @@ pj_status run_f32(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, TileP
         a.vmask = ctx->vmask;
         a.vrow = ctx->vrow;
         if (!one) HIPTRY(ctx, hipStreamWaitEvent(st, ctx->ev_h2d[b], 0));
-        PJTRY(launch_round(ctx, a, dctr, cni, cnt, wpc, graph, st, ctx->ev_k0[b], ctx->ev_k1[b]));
+        int64_t units = 0;  // claimable (A block, B range) units of the chunk
+        for (int64_t t = c.t0; t < c.t1; ++t)
+            units += (pl.tiles[t].a1 - pl.tiles[t].a0 + 64 * kP - 1) / (64 * kP);
+        PJTRY(launch_round(ctx, a, dctr, cni, cnt, wpc, graph, st, ctx->ev_k0[b], ctx->ev_k1[b], units));
         if (!one) {
             HIPTRY(ctx, hipEventRecord(ctx->ev_comp[b], st));
             HIPTRY(ctx, hipStreamWaitEvent(downs, ctx->ev_comp[b], 0));
