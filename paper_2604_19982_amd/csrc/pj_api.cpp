@@ -1483,6 +1483,9 @@ void count_planned(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, int 
 // Tile-count hint of the persistent FP32 rounds (any positive value selects
 // their whole-A-side tiles; 16 per resident wave).
 int64_t tile_target(const pj_context *ctx, int wpc) { return (int64_t)ctx->num_cu * wpc * 16; }
+// Rounds are planned for the largest grid the tuner tries, whatever waves
+// per CU it picks: the plan a round runs is the plan its shape was timed on.
+constexpr int kPlanWPC = 12;
 
 // ---------------------------------------------------------------------------
 // Launch-shape autotuner.  Work is classed by (device, mode, size bucket of
@@ -1590,9 +1593,18 @@ pj_status choose_shape(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
             // counts as much as the kernel when items have many tiles)
             const double tp = now_ms();
             TilePlan pl;
-            plan_tiles(R, S, sample, cand, ps, lod, finest, 64 * kP, ts, true, pl, tile_target(ctx, 12));
+            plan_tiles(R, S, sample, cand, ps, lod, finest, 64 * kP, ts, true, pl, tile_target(ctx, kPlanWPC));
             const double plan_ms = now_ms() - tp;
-            for (int wpc : wpc_list) {
+            // waves per CU from the most down: a smaller count must be 3%
+            // faster to be taken.  A round of fewer units than the smaller
+            // grids launches the same waves for every count (the grid per
+            // round), so its timings tie, and the larger count keeps the
+            // class's bigger rounds (and its tile plan) from running short
+            // of waves.
+            double best_ts = INFINITY;
+            int wpc_ts = 0;
+            for (auto w = wpc_list.rbegin(); w != wpc_list.rend(); ++w) {
+                const int wpc = *w;
                 double t = INFINITY;
                 for (int rep = 0; rep < 3; ++rep) {
                     std::vector<ItemOut> out;
@@ -1601,11 +1613,15 @@ pj_status choose_shape(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
                     PJTRY(run_f32(ctx, R, S, pl, tau, early, out, wpc));
                     t = std::min(t, plan_ms + (now_ms() - tr));
                 }
-                if (t < best) {
-                    best = t;
-                    bs = pj_context::Shape{ts, wpc};
+                if (t < (wpc_ts ? 0.97 * best_ts : INFINITY)) {
+                    best_ts = t;
+                    wpc_ts = wpc;
                 }
                 if (ts == def.tile_s && wpc == def.wpc) t_default = t;
+            }
+            if (best_ts < best) {
+                best = best_ts;
+                bs = pj_context::Shape{ts, wpc_ts};
             }
         }
         // within 3% the default wins: run-to-run timing noise should not
@@ -2578,7 +2594,7 @@ pj_status exact_finest(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
     }
     if (!open.empty()) {
         TilePlan po;
-        plan_tiles(R, S, open, cand, ps, L - 1, 1, 64 * kP, ctx->cur.tile_s, true, po, tile_target(ctx, ctx->cur.wpc));
+        plan_tiles(R, S, open, cand, ps, L - 1, 1, 64 * kP, ctx->cur.tile_s, true, po, tile_target(ctx, kPlanWPC));
         std::vector<ItemOut> o32;
         PJTRY(run_f32(ctx, R, S, po, -1.0f, false, o32, 0));
         for (size_t k = 0; k < po.items.size(); ++k) {
@@ -2588,7 +2604,7 @@ pj_status exact_finest(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
         }
     }
     TilePlan pl;
-    plan_tiles(R, S, which, cand, ps, L - 1, 1, 64, ctx->cur.tile_s, true, pl, tile_target(ctx, ctx->cur.wpc));
+    plan_tiles(R, S, which, cand, ps, L - 1, 1, 64, ctx->cur.tile_s, true, pl, tile_target(ctx, kPlanWPC));
     std::vector<int> redo;
     PJTRY(for_staged(ctx, R, S, pl,
                      [&](TilePlan &sp, const MeshDev &Rv, const MeshDev &Sv, const std::vector<int> &) {
@@ -2877,7 +2893,7 @@ pj_status refine_within(pj_context *ctx, const pj_meshes *R, const pj_meshes *S,
         } else {
             PJTRY(choose_shape(ctx, R, S, act, cand, ps, lod, finest, (float)tau, true));
             plan_tiles(R, S, act, cand, ps, lod, finest, 64 * kP, ctx->cur.tile_s, true, pl,
-                       tile_target(ctx, ctx->cur.wpc));
+                       tile_target(ctx, kPlanWPC));
             count_planned(ctx, R, S, lod, pl);
             std::vector<ItemOut> out;
             PJTRY(run_f32(ctx, R, S, pl, (float)tau, true, out, 0));
@@ -3626,7 +3642,7 @@ extern "C" pj_status pj_join_knn(pj_context *ctx, const pj_meshes *R, const pj_m
         } else {
             PJTRY(choose_shape(ctx, R, S, act, cand, ps, lod, fin_round, -1.0f, false));
             plan_tiles(R, S, act, cand, ps, lod, fin_round, 64 * kP, ctx->cur.tile_s, true, pl,
-                       tile_target(ctx, ctx->cur.wpc));
+                       tile_target(ctx, kPlanWPC));
             count_planned(ctx, R, S, lod, pl);
             std::vector<ItemOut> o32;
             PJTRY(run_f32(ctx, R, S, pl, -1.0f, false, o32, 0));
@@ -3785,7 +3801,7 @@ extern "C" pj_status pj_pair_bounds(pj_context *ctx, const pj_meshes *R, const p
         }
     } else {
         plan_tiles(R, S, act, cand, ps, lod, finest, 64 * kP, pick_tile_s(ctx), true, pl,
-                   tile_target(ctx, ctx->cur.wpc));
+                   tile_target(ctx, kPlanWPC));
         std::vector<ItemOut> out;
         PJTRY(run_f32(ctx, R, S, pl, -1.0f, false, out, 0));
         for (size_t k = 0; k < pl.items.size(); ++k) {
