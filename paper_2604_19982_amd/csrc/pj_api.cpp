@@ -1489,7 +1489,8 @@ constexpr int kPlanWPC = 12;
 
 // ---------------------------------------------------------------------------
 // Launch-shape autotuner.  Work is classed by (device, mode, size bucket of
-// the mean facet pairs per item); the first bulk round of a class without a
+// the mean facet pairs per item, item-count bucket, chunk culling on or
+// off); the first bulk round of a class without a
 // cached shape times every (tile_s, waves_per_cu) candidate on a sample of
 // its items (eager launches; wall time of planning plus the streamed round,
 // best of two) and keeps the fastest.  Results never depend on the shape: the per-item minima are
@@ -1540,9 +1541,10 @@ std::string tune_class(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
     // and the round's size: a few large items and thousands of them want
     // different tiles and grids even at the same mean
     const int nbucket = act.size() > 1 ? (int)std::floor(std::log((double)act.size()) / std::log(4.0)) : 0;
+    // rounds without chunk culling evaluate every planned pair: their own class
     char buf[160];
-    std::snprintf(buf, sizeof(buf), "%s/%dcu/%s/b%d/n%d", ctx->arch.c_str(), ctx->num_cu,
-                  tau >= 0.0f ? "within" : "min", bucket, nbucket);
+    std::snprintf(buf, sizeof(buf), "%s/%dcu/%s/b%d/n%d%s", ctx->arch.c_str(), ctx->num_cu,
+                  tau >= 0.0f ? "within" : "min", bucket, nbucket, ctx->cfg.tile_cull ? "" : "/nocull");
     return buf;
 }
 
