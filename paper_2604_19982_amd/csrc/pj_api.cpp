@@ -1578,8 +1578,10 @@ pj_status choose_shape(pj_context *ctx, const pj_meshes *R, const pj_meshes *S, 
         std::vector<int> sample;
         double pairs = 0.0, total = 0.0;
         for (int i : idx) total += (double)R->count(cand[i].r, lod) * (double)S->count(cand[i].s, lod);
-        const size_t stride = std::max<size_t>(1, (size_t)std::ceil(total / 2e11));
-        for (size_t i = 0; i < idx.size() && pairs < 2e11; i += stride) {
+        // without culling every planned pair is evaluated: a tenth of the sample
+        const double budget = ctx->cfg.tile_cull ? 2e11 : 2e10;
+        const size_t stride = std::max<size_t>(1, (size_t)std::ceil(total / budget));
+        for (size_t i = 0; i < idx.size() && pairs < budget; i += stride) {
             sample.push_back(idx[i]);
             pairs += (double)R->count(cand[idx[i]].r, lod) * (double)S->count(cand[idx[i]].s, lod);
         }
